@@ -1,0 +1,200 @@
+"""Seeded synthetic inputs shared by the HIP path, the oracle and the benchmark.
+
+This module only produces input data: meshes (node coordinates, CCW triangles,
+Dirichlet flags), analytic velocity fields and sweep parameters.  It performs
+none of the coarse-grid-projection arithmetic (no refinement, no assembly, no
+transfer operators, no solves), so both sides of every parity test can consume
+the same arrays without sharing method code.
+
+The workloads stand in for the paper's cylinder-wake runs (Section 3): the
+paper's Gmsh meshes and flow fields are not available, so nested P1 meshes of a
+jittered rectangle and divergence-free Fourier stream-function flows are used.
+
+Recipes (all RNG = numpy PCG64 via ``numpy.random.default_rng(seed)``):
+
+* ``jittered_rect(nx, ny, seed)``: node (i, j) has id ``j*nx + i`` and sits at
+  ``(lx*i/(nx-1), ly*j/(ny-1))``; every interior coordinate is displaced by an
+  independent ``U(-0.2 h, 0.2 h)`` draw (h = the grid spacing along that axis).
+  Cell (i, j) is split along its SW-NE diagonal into the CCW triangles
+  ``(n00, n10, n11)`` and ``(n00, n11, n01)`` with ids ``2*(j*(nx-1)+i) + {0,1}``.
+  Boundary nodes are Dirichlet nodes.
+* ``fourier_modes(seed)``: 8 modes with wavevector ``pi*(p, q)``,
+  ``p, q ~ U{1..4}``, amplitude ``N(0,1)/|k|^2``, phase ``U[0, 2 pi)`` and angular
+  frequency ``U(0.5, 2)``.
+* ``stream_velocity``: ``psi = sum_m c_m cos(k_m . x + theta_m + omega_m t)``,
+  ``u = d psi / dy``, ``v = -d psi / dx`` evaluated analytically at given points.
+* ``potential_velocity``: ``grad chi`` for a second mode set (adds a divergent
+  part, used for the pressure-equation source).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "Mesh",
+    "jittered_rect",
+    "rect_with_hole",
+    "permuted",
+    "fourier_modes",
+    "stream_velocity",
+    "potential_velocity",
+    "stuart_numbers",
+    "batch_sizes",
+    "DT",
+]
+
+#: time step of the paper's runs (Section 3), used to advance the synthetic phases
+DT = 0.05
+
+
+class Mesh:
+    """Plain container: ``xy`` float64 (N,2), ``tri`` int32 (T,3) CCW, ``dirichlet`` uint8 (N,)."""
+
+    def __init__(self, xy, tri, dirichlet, nx=None, ny=None):
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self.dirichlet = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        self.nx, self.ny = nx, ny
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xy.shape[0])
+
+    @property
+    def n_tris(self) -> int:
+        return int(self.tri.shape[0])
+
+
+def _grid_triangles(nx: int, ny: int) -> np.ndarray:
+    i, j = np.meshgrid(np.arange(nx - 1), np.arange(ny - 1), indexing="xy")
+    i = i.ravel()
+    j = j.ravel()
+    n00 = j * nx + i
+    n10 = n00 + 1
+    n01 = n00 + nx
+    n11 = n01 + 1
+    tri = np.empty((2 * i.size, 3), dtype=np.int32)
+    tri[0::2] = np.stack([n00, n10, n11], axis=1)
+    tri[1::2] = np.stack([n00, n11, n01], axis=1)
+    return tri
+
+
+def jittered_rect(nx: int, ny: int, seed: int | None, jitter: float = 0.2,
+                  lx: float = 2.0, ly: float = 1.0) -> Mesh:
+    """Jittered structured P1 mesh of ``[0,lx] x [0,ly]`` (``seed=None`` or ``jitter=0`` = no jitter)."""
+    if nx < 2 or ny < 2:
+        raise ValueError("need at least 2x2 nodes")
+    i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    i = i.ravel()
+    j = j.ravel()
+    x = lx * i / (nx - 1)
+    y = ly * j / (ny - 1)
+    boundary = (i == 0) | (i == nx - 1) | (j == 0) | (j == ny - 1)
+    if seed is not None and jitter != 0.0:
+        rng = np.random.default_rng(seed)
+        d = rng.uniform(-1.0, 1.0, size=(nx * ny, 2))
+        hx = lx / (nx - 1)
+        hy = ly / (ny - 1)
+        x = x + np.where(boundary, 0.0, jitter * hx * d[:, 0])
+        y = y + np.where(boundary, 0.0, jitter * hy * d[:, 1])
+    xy = np.stack([x, y], axis=1)
+    return Mesh(xy, _grid_triangles(nx, ny), boundary.astype(np.uint8), nx, ny)
+
+
+def rect_with_hole(nx: int, ny: int, hole: tuple[int, int, int, int], seed: int | None = None,
+                   jitter: float = 0.2) -> Mesh:
+    """Jittered rectangle with the cells ``i0 <= i < i1, j0 <= j < j1`` removed (a one-hole domain).
+
+    Nodes strictly inside the hole are dropped and the rest renumbered in
+    ascending order; nodes on the hole's rim are Dirichlet nodes, like the
+    outer boundary.  A stand-in for the paper's domain with a cylinder cut out.
+    """
+    i0, i1, j0, j1 = hole
+    if not (0 < i0 < i1 < nx - 1 and 0 < j0 < j1 < ny - 1):
+        raise ValueError("hole must be strictly inside the grid")
+    base = jittered_rect(nx, ny, seed, jitter)
+    ci, cj = np.meshgrid(np.arange(nx - 1), np.arange(ny - 1), indexing="xy")
+    cell_in_hole = ((ci >= i0) & (ci < i1) & (cj >= j0) & (cj < j1)).ravel()
+    keep_tri = ~np.repeat(cell_in_hole, 2)
+    tri = base.tri[keep_tri]
+    ni, nj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    ni = ni.ravel()
+    nj = nj.ravel()
+    inside = (ni > i0) & (ni < i1) & (nj > j0) & (nj < j1)
+    rim = (ni >= i0) & (ni <= i1) & (nj >= j0) & (nj <= j1) & ~inside
+    # the rim may have been jittered as an interior node: put it back on the rim
+    xy = base.xy.copy()
+    gx = 2.0 * ni / (nx - 1)
+    gy = 1.0 * nj / (ny - 1)
+    xy[rim, 0] = gx[rim]
+    xy[rim, 1] = gy[rim]
+    dirichlet = (base.dirichlet.astype(bool) | rim)
+    new_id = np.cumsum(~inside) - 1
+    tri = new_id[tri].astype(np.int32)
+    return Mesh(xy[~inside], tri, dirichlet[~inside].astype(np.uint8))
+
+
+def permuted(mesh: Mesh, seed: int) -> Mesh:
+    """Same mesh with node ids, triangle order and each triangle's starting vertex shuffled (still CCW)."""
+    rng = np.random.default_rng(seed)
+    n = mesh.n_nodes
+    perm = rng.permutation(n)          # new id of old node
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    xy = mesh.xy[inv]
+    dirichlet = mesh.dirichlet[inv]
+    tri = perm[mesh.tri][rng.permutation(mesh.n_tris)]
+    rot = rng.integers(0, 3, size=tri.shape[0])
+    rows = np.arange(tri.shape[0])[:, None]
+    cols = (np.arange(3)[None, :] + rot[:, None]) % 3
+    tri = tri[rows, cols]
+    return Mesh(xy, tri.astype(np.int32), dirichlet)
+
+
+def fourier_modes(seed: int, n_modes: int = 8, kmax: int = 4) -> dict:
+    """Random Fourier mode set (wavevectors, amplitudes, phases, angular frequencies)."""
+    rng = np.random.default_rng(seed)
+    p = rng.integers(1, kmax + 1, size=n_modes)
+    q = rng.integers(1, kmax + 1, size=n_modes)
+    kx = np.pi * p
+    ky = np.pi * q
+    k2 = kx * kx + ky * ky
+    c = rng.standard_normal(n_modes) / k2
+    theta = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    omega = rng.uniform(0.5, 2.0, size=n_modes)
+    return {"kx": kx, "ky": ky, "c": c, "theta": theta, "omega": omega}
+
+
+def _phase(xy: np.ndarray, modes: dict, t: float) -> np.ndarray:
+    return (xy[:, 0:1] * modes["kx"][None, :] + xy[:, 1:2] * modes["ky"][None, :]
+            + modes["theta"][None, :] + modes["omega"][None, :] * t)
+
+
+def stream_velocity(xy: np.ndarray, modes: dict, t: float = 0.0) -> tuple[np.ndarray, np.ndarray]:
+    """Divergence-free velocity ``(d psi/dy, -d psi/dx)`` of the Fourier stream function at points ``xy``."""
+    s = np.sin(_phase(xy, modes, t))
+    u = -(s * (modes["c"] * modes["ky"])[None, :]).sum(axis=1)
+    v = (s * (modes["c"] * modes["kx"])[None, :]).sum(axis=1)
+    return np.ascontiguousarray(u), np.ascontiguousarray(v)
+
+
+def potential_velocity(xy: np.ndarray, modes: dict, t: float = 0.0) -> tuple[np.ndarray, np.ndarray]:
+    """Curl-free velocity ``grad chi`` of a Fourier potential ``chi`` at points ``xy``."""
+    s = np.sin(_phase(xy, modes, t))
+    u = -(s * (modes["c"] * modes["kx"])[None, :]).sum(axis=1)
+    v = -(s * (modes["c"] * modes["ky"])[None, :]).sum(axis=1)
+    return np.ascontiguousarray(u), np.ascontiguousarray(v)
+
+
+def stuart_numbers(count: int) -> np.ndarray:
+    """Stuart numbers log-spaced over [0.1, 10]."""
+    if count == 1:
+        return np.array([1.0])
+    return 10.0 ** (-1.0 + 2.0 * np.arange(count) / (count - 1))
+
+
+def batch_sizes(count: int, seed: int, mmin: int = 32, mmax: int = 256) -> list[tuple[int, int]]:
+    """Uneven coarse grids for a batched sweep: ``nx = 2m+1``, ``ny = m+1``, ``m ~ U{mmin..mmax}``."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(mmin, mmax + 1, size=count)
+    return [(int(2 * mi + 1), int(mi + 1)) for mi in m]

@@ -1,0 +1,19 @@
+"""CPU oracle for the coarse-grid-projection hot path -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, fp64 implementation of what the HIP library computes, written
+from the paper (Kashefi, "A coarse-grid projection method for accelerating
+incompressible MHD flow simulations", arXiv 2003.00082):
+
+* ``oracle.mesh``   nested 4-way refinement (Section 2.3, Eq. 18), injection
+                    (Eq. 19) and P1 prolongation (Eq. 20);
+* ``oracle.fem``    Galerkin P1 stiffness (Section 2.3), the coarse sources of
+                    Eqs. 12 and 15, and the Lorentz-force source of Eqs. 13-14;
+* ``oracle.solve``  the exact coarse solution (sparse/dense direct factorisation)
+                    and Jacobi-preconditioned CG in fp64 and in fp32 with fp64
+                    iterative refinement (plain C, ``oracle/pcg_oracle.c``);
+* ``oracle.gnn``    the learned initial-guess network, forward and analytic
+                    backward in fp64 with bf16 rounding emulated.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP path.
+"""
