@@ -1,0 +1,236 @@
+/*
+ * cgp.h -- C ABI of the MI355X (gfx950) coarse-grid-projection library.
+ *
+ * The library implements the per-time-step elliptic work that coarse grid
+ * projection (CGP; Kashefi, arXiv 2003.00082) moves onto a coarsened mesh, on
+ * a fine P1 space V_j and a coarse space V_{j-k} built by k uniform 4-way
+ * subdivisions (Section 2.3, Eq. 18):
+ *
+ *   cgp_restrict       inject the fine velocity onto the coarse nodes (Eq. 19)
+ *                      and assemble the coarse source of Eq. 12 or Eq. 15;
+ *   cgp_poisson_solve  solve the coarse Poisson system (Eqs. 12, 15);
+ *   cgp_prolong        P1 prolongation back to the finest level (Eq. 20);
+ *   cgp_lorentz_force  grad(phi_f) and the Lorentz source of Eqs. 13-14.
+ *
+ * Conventions for every call:
+ *   - Return value: CGP_OK (0) or a negative cgp_status.  No C++ exception
+ *     crosses the ABI.  cgp_last_error() gives a message for the last failing
+ *     call of the calling thread.
+ *   - h_* arguments are host pointers, read during the call and never retained.
+ *   - d_* arguments are device pointers owned by the caller (e.g. torch tensors
+ *     on the context's device).  They must stay valid until the work enqueued on
+ *     the context's stream has completed.
+ *   - Meshes, matrices, maps, solver workspaces and models are owned by the
+ *     library and released by cgp_mesh_free / cgp_model_free / cgp_destroy.
+ *   - Unless stated otherwise a call only enqueues work on the context's stream
+ *     and returns; device-side failures surface at cgp_sync().
+ *   - Arguments are validated before anything is enqueued: null pointers, sizes
+ *     out of range or unknown handles give CGP_E_INVALID and enqueue nothing.
+ *   - A context is used by one host thread at a time.  A mesh's solver
+ *     workspace is shared by all solves on that mesh, so two solves on the same
+ *     mesh must not run concurrently (they are serialised on one stream anyway).
+ *   - Floating-point data are IEEE fp64 unless stated; indices are int32.
+ */
+#ifndef CGP_H
+#define CGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cgp_ctx_s *cgp_ctx;
+typedef int32_t cgp_mesh;   /* handle of an uploaded mesh hierarchy (>= 0) */
+typedef int32_t cgp_model;  /* handle of a learned initial-guess network (>= 0) */
+typedef int32_t cgp_graph;  /* handle of a captured HIP graph (>= 0) */
+typedef int32_t cgp_status;
+
+enum {
+    CGP_OK = 0,
+    CGP_E_INVALID = -1,     /* bad argument; nothing was enqueued */
+    CGP_E_NOMEM = -2,       /* device or host allocation failed */
+    CGP_E_HIP = -3,         /* a HIP runtime call failed (message in cgp_last_error) */
+    CGP_E_MESH = -4,        /* mesh rejected: index out of range or triangle not CCW */
+    CGP_E_NOCONV = -5,      /* returned by cgp_solve_check: an instance hit max_iter */
+    CGP_E_BREAKDOWN = -6,   /* returned by cgp_solve_check: p.Kp <= 0 or non-finite */
+    CGP_E_UNSUPPORTED = -7, /* valid request the library does not implement */
+    CGP_E_ABORTED = -8      /* returned by cgp_solve_check: the solve kernel timed out */
+};
+
+/* sources of cgp_restrict */
+enum { CGP_SRC_CURL = 0, CGP_SRC_DIV = 1 };
+/* arithmetic of cgp_poisson_solve */
+enum { CGP_FP64 = 0, CGP_FP32_IR = 1 };
+/* initial guess of cgp_poisson_solve */
+enum { CGP_GUESS_ZERO = 0, CGP_GUESS_GIVEN = 1, CGP_GUESS_EXTRAP = 2, CGP_GUESS_LEARNED = 3 };
+/* per-instance solve status (cgp_solve_stats.status) */
+enum { CGP_SOLVE_OK = 0, CGP_SOLVE_NOCONV = 1, CGP_SOLVE_BREAKDOWN = 2, CGP_SOLVE_ABORTED = 3 };
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the null stream.
+ * Synchronous. */
+cgp_status cgp_create(cgp_ctx *out, int32_t device, void *hip_stream);
+/* Free the context and everything it owns (meshes, models, graphs).  Synchronous. */
+cgp_status cgp_destroy(cgp_ctx ctx);
+/* Replace the stream on which later calls enqueue their work. */
+cgp_status cgp_set_stream(cgp_ctx ctx, void *hip_stream);
+/* Wait for the context's stream; reports asynchronous HIP errors. */
+cgp_status cgp_sync(cgp_ctx ctx);
+/* Message of the last failing call made by this thread ("" if none). */
+const char *cgp_last_error(void);
+/* Number of compute units of the context's device (for sizing launches). */
+int32_t cgp_device_cus(cgp_ctx ctx);
+
+/* ------------------------------------------------------------------ meshes */
+
+/* Upload a coarse P1 mesh and build k uniform 4-way refinements on the device
+ * (Section 2.3, Eq. 18: each level has 4x the triangles of the one below).
+ *   h_xy        [2*n_nodes]  node coordinates, (x0, y0, x1, y1, ...)
+ *   h_tri       [3*n_tris]   triangles, counter-clockwise vertex ids
+ *   h_dirichlet [n_nodes]    1 = homogeneous Dirichlet node, 0 = free
+ *   k_levels    >= 0         number of refinements (the finest level is k)
+ * Numbering of the hierarchy: level l+1 keeps the ids of level l; its other
+ * nodes are the midpoints of the level-l edges, edge e (edges = sorted unique
+ * (min id, max id) pairs in lexicographic order) getting id N_l + e.
+ * Triangle t = (a,b,c) has children 4t..4t+3 = (a,mab,mca), (mab,b,mbc),
+ * (mca,mbc,c), (mab,mbc,mca).  A midpoint is a Dirichlet node iff its edge has
+ * exactly one adjacent triangle and both end points are Dirichlet nodes.
+ * Level 0 also gets the Galerkin P1 stiffness matrix of the coarse Poisson
+ * problems in CSR form (ascending columns), with Dirichlet rows replaced by
+ * identity rows and Dirichlet columns removed, plus its Jacobi inverse
+ * diagonal and fp32 copies.
+ * Returns CGP_E_MESH if a vertex id is out of range, a triangle repeats a
+ * vertex or has non-positive signed area.  Synchronous (setup call). */
+cgp_status cgp_mesh_upload(cgp_ctx ctx, const double *h_xy, int64_t n_nodes,
+                           const int32_t *h_tri, int64_t n_tris,
+                           const uint8_t *h_dirichlet, int32_t k_levels, cgp_mesh *out);
+/* Sizes of level `level` (0 = coarse .. k = finest).  n_edges is the edge
+ * count of that level (0 for the finest level, whose edges are not built);
+ * nnz is the stiffness nonzero count (level 0 only, else 0).  Any output may
+ * be NULL.  Synchronous. */
+cgp_status cgp_mesh_info(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t *n_nodes,
+                         int64_t *n_tris, int64_t *n_edges, int64_t *nnz);
+/* Number of refinement levels k of the mesh. */
+cgp_status cgp_mesh_levels(cgp_ctx ctx, cgp_mesh mesh, int32_t *k_levels);
+/* Copy level `level` back to the host: h_xy [2N], h_tri [3T], h_dirichlet [N],
+ * h_edge_ends [2E] (edge e = (h_edge_ends[2e], h_edge_ends[2e+1]), min first).
+ * Any output may be NULL.  Synchronous. */
+cgp_status cgp_mesh_download(cgp_ctx ctx, cgp_mesh mesh, int32_t level, double *h_xy,
+                             int32_t *h_tri, uint8_t *h_dirichlet, int32_t *h_edge_ends);
+/* Copy the level-0 system matrix back: h_rowptr [N+1], h_col [nnz], h_val
+ * [nnz], h_dinv [N] (any may be NULL).  Synchronous. */
+cgp_status cgp_mesh_matrix(cgp_ctx ctx, cgp_mesh mesh, int32_t *h_rowptr, int32_t *h_col,
+                           double *h_val, double *h_dinv);
+/* Release a mesh and its workspaces.  Synchronous. */
+cgp_status cgp_mesh_free(cgp_ctx ctx, cgp_mesh mesh);
+
+/* ------------------------------------------------------------------ CGP steps 1 and 5 */
+
+/* Restrict the finest-level velocity (d_uf, d_vf: [N_k]) to the coarse nodes by
+ * injection (Eq. 19; under the hierarchical numbering coarse node i is fine
+ * node i) and assemble the coarse right-hand side d_b [N_0] of K phi = b:
+ *   kind = CGP_SRC_CURL: Eq. 12, b_i = -scale * int (dv/dx - du/dy) psi_i  (scale = B0)
+ *   kind = CGP_SRC_DIV : Eq. 15, b_i = -scale * int (du/dx + dv/dy) psi_i  (scale = rho/dt)
+ * with the element-constant derivatives of the P1 interpolant of the injected
+ * velocity; b_i = 0 on Dirichlet rows.  (K is the positive stiffness matrix, so
+ * this is the paper's Laplace equation multiplied by -1.)  d_uc, d_vc [N_0]
+ * optionally receive the injected velocity (NULL to skip). */
+cgp_status cgp_restrict(cgp_ctx ctx, cgp_mesh mesh, const double *d_uf, const double *d_vf,
+                        int32_t kind, double scale, double *d_b, double *d_uc, double *d_vc);
+
+/* ------------------------------------------------------------------ CGP steps 2 and 6 */
+
+typedef struct {
+    int32_t precision;    /* CGP_FP64 or CGP_FP32_IR                                    */
+    int32_t guess;        /* CGP_GUESS_*                                                */
+    double tol;           /* stop when ||b - K phi||_2 <= tol ||b||_2 (true fp64 residual) */
+    double refine_delta;  /* CGP_FP32_IR: refine when the fp32 residual fell by this factor
+                             since the last refinement (0 = default 0.1)                 */
+    int32_t max_iter;     /* cap on CG iterations per instance (0 = default 100000)      */
+    cgp_model model;      /* network for CGP_GUESS_LEARNED                               */
+    int32_t spmv_lanes;   /* lanes per matrix row: 0 = autotuned/default, else 1,2,4,8   */
+    int32_t blocks;       /* persistent workgroups: 0 = one per compute unit             */
+} cgp_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* CG iterations                                          */
+    int32_t refinements;  /* fp64 residual refinements (CGP_FP32_IR)                */
+    int32_t status;       /* CGP_SOLVE_*                                            */
+    int32_t guess_used;   /* CGP_GUESS_* actually used (LEARNED may fall back to GIVEN) */
+    double rel_res;       /* final true ||b - K phi|| / ||b||                        */
+    double rel_res_guess; /* ||b - K phi0|| / ||b|| of the initial guess used         */
+} cgp_solve_stats;
+
+/* Solve K phi = b on the level-0 mesh of each of n_inst instances with
+ * Jacobi-preconditioned conjugate gradients, all instances in one persistent
+ * launch (Eqs. 12, 15; the paper used GMRES(m)+ILU(0) for the same systems).
+ *   h_meshes[i]  mesh of instance i (distinct meshes; one instance per mesh)
+ *   h_d_b[i]     device pointer, right-hand side [N_0]
+ *   h_d_phi[i]   device pointer [N_0]: the guess on entry for GUESS_GIVEN, the
+ *                solution on exit
+ *   h_d_prev1[i], h_d_prev2[i]  previous two solutions phi^{n-1}, phi^{n-2}
+ *                (device pointers; required for GUESS_EXTRAP, which starts from
+ *                2 phi^{n-1} - phi^{n-2}, and GUESS_LEARNED, whose network
+ *                guess is kept only if its residual is below that of
+ *                phi^{n-1}); may be NULL otherwise.  They must not alias phi.
+ *   d_stats      device array [n_inst], written when the solve completes.
+ * CGP_FP64: every vector and product in fp64.  CGP_FP32_IR: fp32 matrix,
+ * vectors and products with fp64 dot-product accumulation, refined by true
+ * fp64 residuals b - K phi and fp64 solution updates.  ||b|| = 0 gives phi = 0.
+ * Asynchronous; numerical failures are reported in d_stats (see
+ * cgp_solve_check). */
+cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_meshes,
+                             const double *const *h_d_b, double *const *h_d_phi,
+                             const double *const *h_d_prev1, const double *const *h_d_prev2,
+                             const cgp_solve_opts *h_opts, cgp_solve_stats *d_stats);
+/* Synchronise and read n_inst stats back into h_stats (may be NULL); returns
+ * CGP_OK, or CGP_E_NOCONV / CGP_E_BREAKDOWN / CGP_E_ABORTED for the first
+ * failing instance. */
+cgp_status cgp_solve_check(cgp_ctx ctx, int32_t n_inst, const cgp_solve_stats *d_stats,
+                           cgp_solve_stats *h_stats);
+/* Pick spmv_lanes per mesh by timing the solver's matrix-vector stage on the
+ * device (one entry per mesh in h_lanes_out, also remembered by the mesh and
+ * used when cgp_solve_opts.spmv_lanes == 0).  Synchronous. */
+cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_t precision,
+                        int32_t *h_lanes_out);
+
+/* ------------------------------------------------------------------ CGP steps 3, 7 and 4 */
+
+/* Prolong a coarse nodal field d_qc [N_0] to the finest level d_qf [N_k] with
+ * the P1 shape functions, one level at a time (Eq. 20): nodes kept from the
+ * coarser level copy their value, the midpoint of edge (a, b) gets
+ * (q_a + q_b) * 0.5.  k = 0 copies. */
+cgp_status cgp_prolong(cgp_ctx ctx, cgp_mesh mesh, const double *d_qc, double *d_qf);
+
+/* Lorentz-force source of Eqs. 13-14 on the finest level from the prolonged
+ * potential d_phif [N_k] and velocity d_uf, d_vf [N_k]:
+ *   F_x = sigma B0 (-G_y - B0 u),  F_y = sigma B0 (G_x - B0 v)
+ * where G is the nodal gradient of phi: the area-weighted mean of the
+ * element-constant gradients of the triangles around the node (Eqs. 4, 7, 11;
+ * sigma = the Stuart number N when rho = d = u_inf = B0 = 1, Eq. 24).
+ * d_fx, d_fy [N_k] receive the force; d_grad_elem [2 T_k] optionally receives
+ * the element gradients (gx, gy per triangle; NULL to skip). */
+cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif,
+                             const double *d_uf, const double *d_vf, double sigma, double B0,
+                             double *d_fx, double *d_fy, double *d_grad_elem);
+
+/* ------------------------------------------------------------------ HIP graphs */
+
+/* Begin capturing the context's stream; library calls made until
+ * cgp_graph_end are recorded instead of executed (they must be the
+ * asynchronous calls above).  The stream must not be the null stream. */
+cgp_status cgp_graph_begin(cgp_ctx ctx);
+/* End the capture and instantiate it. */
+cgp_status cgp_graph_end(cgp_ctx ctx, cgp_graph *out);
+/* Launch a captured graph on the context's stream. */
+cgp_status cgp_graph_launch(cgp_ctx ctx, cgp_graph graph);
+cgp_status cgp_graph_free(cgp_ctx ctx, cgp_graph graph);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGP_H */

@@ -1,0 +1,171 @@
+// Two-grid transfer work of a CGP step (Section 2.2, steps 1, 3, 5, 7 and the
+// source of step 4):
+//   k_restrict_source  injection of the fine velocity (Eq. 19) fused with the
+//                      assembly of the coarse right-hand side of Eq. 12 / Eq. 15
+//   k_prolong_level    P1 prolongation from one level to the next (Eq. 20)
+//   k_lorentz          nodal grad(phi_f) and the Lorentz source of Eqs. 13-14
+//
+// All three are per-node gathers over the node->triangle incidence lists
+// (ascending triangle id), one thread per node: no atomics, deterministic.
+// They are HBM-bound streaming kernels (coordinates, connectivity and fields
+// read once per incident triangle from L2).
+#include "cgp_internal.hpp"
+
+namespace cgp {
+namespace {
+
+constexpr int TPB = 256;
+
+// b_i = -scale/3 * sum_{e ni i} q_e A_e with q_e the element-constant curl or
+// divergence of the P1 interpolant.  With beta_a = (y_b - y_c, x_c - x_b)
+// (cyclic) and D_e = 2 A_e, grad(psi_a) = beta_a / D_e, so
+//   curl_e A_e = 1/2 sum_a (v_a beta_a.x - u_a beta_a.y)
+//   div_e  A_e = 1/2 sum_a (u_a beta_a.x + v_a beta_a.y)
+// and the element area cancels.
+__global__ __launch_bounds__(TPB) void k_restrict_source(
+    int64_t n, const int32_t *__restrict__ ne_ptr, const int32_t *__restrict__ ne_idx,
+    const int32_t *__restrict__ tri, const double *__restrict__ xy, const uint8_t *__restrict__ dir,
+    const double *__restrict__ uf, const double *__restrict__ vf, int kind, double scale,
+    double *__restrict__ b, double *__restrict__ uc, double *__restrict__ vc) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (uc) uc[i] = uf[i];   // coarse node i is fine node i (hierarchical numbering)
+    if (vc) vc[i] = vf[i];
+    if (dir[i]) {
+        b[i] = 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int32_t k = ne_ptr[i]; k < ne_ptr[i + 1]; ++k) {
+        const int64_t e = ne_idx[k];
+        const int32_t a0 = tri[3 * e], a1 = tri[3 * e + 1], a2 = tri[3 * e + 2];
+        const double x0 = xy[2 * a0], y0 = xy[2 * a0 + 1];
+        const double x1 = xy[2 * a1], y1 = xy[2 * a1 + 1];
+        const double x2 = xy[2 * a2], y2 = xy[2 * a2 + 1];
+        const double bx0 = y1 - y2, bx1 = y2 - y0, bx2 = y0 - y1;
+        const double by0 = x2 - x1, by1 = x0 - x2, by2 = x1 - x0;
+        const double u0 = uf[a0], u1 = uf[a1], u2 = uf[a2];
+        const double v0 = vf[a0], v1 = vf[a1], v2 = vf[a2];
+        double qa;
+        if (kind == CGP_SRC_CURL)
+            qa = (v0 * bx0 + v1 * bx1 + v2 * bx2) - (u0 * by0 + u1 * by1 + u2 * by2);
+        else
+            qa = (u0 * bx0 + u1 * bx1 + u2 * bx2) + (v0 * by0 + v1 * by1 + v2 * by2);
+        acc += 0.5 * qa;
+    }
+    b[i] = -scale * acc / 3.0;
+}
+
+// level l -> l+1: kept nodes copy, midpoint N_l + e of edge (a, b) = (q_a + q_b) * 0.5
+__global__ __launch_bounds__(TPB) void k_prolong_level(int64_t n, int64_t E, const int32_t *__restrict__ ends,
+                                                       const double *__restrict__ q, double *__restrict__ qf) {
+    const int64_t id = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id < n) {
+        qf[id] = q[id];
+    } else if (id < n + E) {
+        const int64_t e = id - n;
+        qf[id] = (q[ends[2 * e]] + q[ends[2 * e + 1]]) * 0.5;
+    }
+}
+
+// G_i = sum_e A_e g_e / sum_e A_e over the triangles around i, with
+// A_e g_e = 1/2 sum_a phi_a beta_a; F = sigma B0 (-G_y - B0 u, G_x - B0 v)
+__global__ __launch_bounds__(TPB) void k_lorentz(
+    int64_t n, const int32_t *__restrict__ ne_ptr, const int32_t *__restrict__ ne_idx,
+    const int32_t *__restrict__ tri, const double *__restrict__ xy, const double *__restrict__ phi,
+    const double *__restrict__ u, const double *__restrict__ v, double sigma, double b0,
+    double *__restrict__ fx, double *__restrict__ fy) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double gx = 0.0, gy = 0.0, area = 0.0;
+    for (int32_t k = ne_ptr[i]; k < ne_ptr[i + 1]; ++k) {
+        const int64_t e = ne_idx[k];
+        const int32_t a0 = tri[3 * e], a1 = tri[3 * e + 1], a2 = tri[3 * e + 2];
+        const double x0 = xy[2 * a0], y0 = xy[2 * a0 + 1];
+        const double x1 = xy[2 * a1], y1 = xy[2 * a1 + 1];
+        const double x2 = xy[2 * a2], y2 = xy[2 * a2 + 1];
+        const double p0 = phi[a0], p1 = phi[a1], p2 = phi[a2];
+        gx += 0.5 * (p0 * (y1 - y2) + p1 * (y2 - y0) + p2 * (y0 - y1));
+        gy += 0.5 * (p0 * (x2 - x1) + p1 * (x0 - x2) + p2 * (x1 - x0));
+        area += 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+    }
+    gx /= area;
+    gy /= area;
+    fx[i] = sigma * b0 * (-gy - b0 * u[i]);
+    fy[i] = sigma * b0 * (gx - b0 * v[i]);
+}
+
+// element gradient g_e = sum_a phi_a beta_a / D_e
+__global__ __launch_bounds__(TPB) void k_elem_grad(int64_t T, const int32_t *__restrict__ tri,
+                                                   const double *__restrict__ xy, const double *__restrict__ phi,
+                                                   double *__restrict__ g) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    const int32_t a0 = tri[3 * e], a1 = tri[3 * e + 1], a2 = tri[3 * e + 2];
+    const double x0 = xy[2 * a0], y0 = xy[2 * a0 + 1];
+    const double x1 = xy[2 * a1], y1 = xy[2 * a1 + 1];
+    const double x2 = xy[2 * a2], y2 = xy[2 * a2 + 1];
+    const double p0 = phi[a0], p1 = phi[a1], p2 = phi[a2];
+    const double d = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+    g[2 * e] = (p0 * (y1 - y2) + p1 * (y2 - y0) + p2 * (y0 - y1)) / d;
+    g[2 * e + 1] = (p0 * (x2 - x1) + p1 * (x0 - x2) + p2 * (x1 - x0)) / d;
+}
+
+__global__ __launch_bounds__(TPB) void k_guess(int64_t n, int guess, double *__restrict__ x,
+                                               const double *__restrict__ p1, const double *__restrict__ p2) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (guess == CGP_GUESS_ZERO)
+        x[i] = 0.0;
+    else if (guess == CGP_GUESS_EXTRAP)
+        x[i] = 2.0 * p1[i] - p2[i];
+    else
+        x[i] = p1[i];
+}
+
+}  // namespace
+
+void launch_restrict(hipStream_t s, const Mesh &m, const double *uf, const double *vf, int kind,
+                     double scale, double *b, double *uc, double *vc) {
+    const Level &L = m.lv[0];
+    hipLaunchKernelGGL(k_restrict_source, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p,
+                       L.ne_idx.p, L.tri.p, L.xy.p, L.dir.p, uf, vf, kind, scale, b, uc, vc);
+    CGP_HIP(hipGetLastError());
+}
+
+void launch_prolong(hipStream_t s, Mesh &m, const double *qc, double *qf) {
+    if (m.k == 0) {
+        CGP_HIP(hipMemcpyAsync(qf, qc, m.lv[0].n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    const double *src = qc;
+    for (int32_t l = 0; l < m.k; ++l) {
+        const Level &L = m.lv[l];
+        double *dst = (l + 1 == m.k) ? qf : m.lv[l + 1].tmp.p;
+        hipLaunchKernelGGL(k_prolong_level, dim3(blocks_for(L.n + L.E, TPB)), dim3(TPB), 0, s, L.n, L.E,
+                           L.ends.p, src, dst);
+        CGP_HIP(hipGetLastError());
+        src = dst;
+    }
+}
+
+void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const double *uf, const double *vf,
+                    double sigma, double b0, double *fx, double *fy, double *grad_elem) {
+    const Level &L = m.lv[m.k];
+    hipLaunchKernelGGL(k_lorentz, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
+                       L.tri.p, L.xy.p, phif, uf, vf, sigma, b0, fx, fy);
+    CGP_HIP(hipGetLastError());
+    if (grad_elem) {
+        hipLaunchKernelGGL(k_elem_grad, dim3(blocks_for(L.T, TPB)), dim3(TPB), 0, s, L.T, L.tri.p, L.xy.p,
+                           phif, grad_elem);
+        CGP_HIP(hipGetLastError());
+    }
+}
+
+void launch_guess_prep(hipStream_t s, int guess, int64_t n, double *x, const double *prev1,
+                       const double *prev2) {
+    hipLaunchKernelGGL(k_guess, dim3(blocks_for(n, TPB)), dim3(TPB), 0, s, n, guess, x, prev1, prev2);
+    CGP_HIP(hipGetLastError());
+}
+
+}  // namespace cgp
