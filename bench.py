@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the CGP hot path on one MI355X.
+
+Workload (default): coarse 513x257 jittered P1 mesh of [0,2]x[0,1] (131841
+nodes, 262144 triangles), refined once to the 1025x513 fine mesh (525825
+nodes); a drifting 8-mode Fourier flow gives the fine velocity of each time
+step.  One *step* is one pass of the whole hot path:
+
+    restrict (Eq. 19) + curl source (Eq. 12) -> solve phi -> prolong phi (Eq. 20)
+    -> Lorentz force (Eqs. 13-14) -> restrict + divergence source (Eq. 15)
+    -> solve p -> prolong p
+
+with both Poisson solves to a true relative residual of 1e-8.  Two forms run on
+the same inputs:
+
+    A  plain fp64 Jacobi-PCG from the previous solution
+    B  fp32 Jacobi-PCG with fp64 residual refinement from the predicted guess
+       (the learned network when a trained model is given, else the
+       extrapolation 2 phi^{n-1} - phi^{n-2})
+
+``value`` is form B's whole-job Poisson solves per second (2 solves per step)
+over the timed steps, inputs resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Poisson solves/s at 1e-8 rel. residual: learned+FP32-refined vs plain FP64 PCG"
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-8
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed CGP time steps")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed steps before the timed ones")
+    ap.add_argument("--nx", type=int, default=513)
+    ap.add_argument("--ny", type=int, default=257)
+    ap.add_argument("--stuart", type=float, default=1.0, help="Stuart number N (sigma of the Lorentz force)")
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample: steps (2 solves each)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="AB")
+    return ap.parse_args()
+
+
+def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extrap: bool) -> float:
+    """Algorithmic HBM bytes of one solve (matrix and vectors read/written once per pass)."""
+    if mixed:
+        per_it = 8 * nnz + 52 * n            # fp32 CSR values + int32 cols, fp32 vectors
+        init = 12 * nnz + 4 * n + 16 * n + 20 * n
+        refine = 24 * n + 12 * nnz + 4 * n + 16 * n + 12 * n
+        total = init + iters * per_it + refinements * refine
+    else:
+        per_it = 12 * nnz + 100 * n          # fp64 CSR + int32 cols, fp64 vectors
+        resid = 12 * nnz + 4 * n + 16 * n + 24 * n
+        total = 2 * resid + iters * per_it
+    if extrap:
+        total += 24 * n
+    return float(total)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances of a batch or "
+              "mesh partitions would shard across GPUs, which this build does not do.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import cgp_inputs as ci
+    import paper_2003_00082_amd as cgp
+
+    dev = torch.device("cuda:0")
+    nx, ny = args.nx, args.ny
+    coarse = ci.jittered_rect(nx, ny, 2000)
+    ctx = cgp.Context(0)
+    h = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+    info0, info1 = ctx.mesh_info(h, 0), ctx.mesh_info(h, 1)
+    nc, nnz, nf = info0["n_nodes"], info0["nnz"], info1["n_nodes"]
+    fine_xy = ctx.mesh_download(h, 1)[0]
+    seq = ci.FourierSequence(fine_xy, ci.fourier_modes(2500), ci.fourier_modes(2700))
+    W, K = args.warmup, args.steps
+    steps = list(range(-W, K))
+    vel = {}
+    for n in steps:                                   # inputs resident in HBM before timing
+        vel[n] = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in seq.at(n))
+    torch.cuda.synchronize()
+
+    f64 = dict(dtype=torch.float64, device=dev)
+    b_phi, b_p = torch.empty(nc, **f64), torch.empty(nc, **f64)
+    phif, pf, fx, fy = (torch.empty(nf, **f64) for _ in range(4))
+    sigma, rho_dt = args.stuart, 1.0 / ci.DT
+    stats = cgp.stats_buffer(2 * len(steps))
+    stream = torch.cuda.current_stream()
+
+    def run(form: str):
+        mixed = form == "B"
+        bufs = {"phi": [torch.zeros(nc, **f64) for _ in range(3)], "p": [torch.zeros(nc, **f64) for _ in range(3)]}
+        ev = []
+        keep = {}
+
+        def solve(eq, bvec, n, slot, timed):
+            B = bufs[eq]
+            if mixed:
+                cur, p1, p2 = B[n % 3], B[(n - 1) % 3], B[(n - 2) % 3]
+                kw = dict(prev1=[p1], prev2=[p2], guess=cgp.CGP_GUESS_EXTRAP, precision=cgp.CGP_FP32_IR)
+            else:
+                cur = B[0]
+                kw = dict(guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64)
+            st = stats[slot * cgp.STATS_BYTES:(slot + 1) * cgp.STATS_BYTES]
+            if timed:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            ctx.poisson_solve([h], [bvec], [cur], st, tol=TOL, **kw)
+            if timed:
+                e1.record(stream)
+                ev.append((e0, e1))
+            return cur
+
+        def step(n, timed):
+            u, v, ut, vt = vel[n]
+            slot = 2 * (n + W)
+            ctx.restrict(h, u, v, cgp.CGP_SRC_CURL, 1.0, b_phi)
+            phi = solve("phi", b_phi, n, slot, timed)
+            ctx.prolong(h, phi, phif)
+            ctx.lorentz_force(h, phif, u, v, sigma, 1.0, fx, fy)
+            ctx.restrict(h, ut, vt, cgp.CGP_SRC_DIV, rho_dt, b_p)
+            p = solve("p", b_p, n, slot + 1, timed)
+            ctx.prolong(h, p, pf)
+            if n == 0:
+                keep["phi"], keep["p"] = phi.clone(), p.clone()
+
+        for n in steps[:W]:
+            step(n, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in steps[W:]:
+            step(n, True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        host = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=np.dtype(
+            [("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"), ("rel0", "f8")]))
+        timed = host[2 * W:]
+        ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
+        solve_ms = np.array([a.elapsed_time(b) for a, b in ev])
+        nbytes = np.array([pcg_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed, mixed) for r in timed])
+        return {
+            "solves_per_s": 2 * K / elapsed,
+            "ms_per_step": 1e3 * elapsed / K,
+            "mean_iters": float(timed["iters"].mean()),
+            "mean_refinements": float(timed["ref"].mean()),
+            "max_rel_res": float(timed["rel"].max()),
+            "mean_guess_rel_res": float(timed["rel0"].mean()),
+            "all_converged": ok,
+            "solve_ms_mean": float(solve_ms.mean()),
+            "solve_share": float(solve_ms.sum() / (1e3 * elapsed)),
+            "achieved_GBs": float(nbytes.sum() / (solve_ms.sum() * 1e-3) / 1e9),
+            "bytes_per_solve": float(nbytes.mean()),
+            "step0": {k: v.cpu().numpy() for k, v in keep.items()},
+        }
+
+    res = {f: run(f) for f in args.forms}
+    main_form = "B" if "B" in res else args.forms[0]
+    R = res[main_form]
+
+    # error of the step-0 solutions against the oracle's exact coarse solution
+    cpu = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        from oracle import fem, mesh, solve
+        hier = mesh.Hierarchy(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+        oseq = ci.FourierSequence(hier.xy[1], ci.fourier_modes(2500), ci.fourier_modes(2700))
+        a = fem.system_matrix(coarse.xy, coarse.tri, coarse.dirichlet)
+
+        def rhs(n):
+            u, v, ut, vt = oseq.at(n)
+            return (fem.source(coarse.xy, coarse.tri, coarse.dirichlet, u[:nc], v[:nc], fem.CURL, 1.0),
+                    fem.source(coarse.xy, coarse.tri, coarse.dirichlet, ut[:nc], vt[:nc], fem.DIV, rho_dt))
+
+        b0 = rhs(0)
+        exact = {"phi": solve.direct(a, b0[0]), "p": solve.direct(a, b0[1])}
+        for f, r in res.items():
+            errs[f] = {eq: float(np.linalg.norm(r["step0"][eq] - exact[eq]) / np.linalg.norm(exact[eq]))
+                       for eq in ("phi", "p")}
+        # timed sample: fp64 Jacobi-PCG from the previous solution (form A's algorithm), steps 0..S-1
+        prev = {"phi": solve.direct(a, rhs(-1)[0]), "p": solve.direct(a, rhs(-1)[1])}
+        S = max(1, args.cpu_steps)
+        rhs_s = [rhs(n) for n in range(S)]
+        t0 = time.perf_counter()
+        its = []
+        for n in range(S):
+            for k, eq in enumerate(("phi", "p")):
+                x, inf = solve.pcg(a, rhs_s[n][k], prev[eq], tol=TOL)
+                prev[eq] = x
+                its.append(inf["iters"])
+        cpu_t = time.perf_counter() - t0
+        cpu = {"value": 2 * S / cpu_t, "unit": "solves/s", "cores": solve.threads(), "kind": "oracle",
+               "sample": f"fp64 Jacobi-PCG (C, OpenMP) from the previous solution, steps 0..{S - 1} of the same "
+                         f"sequence, phi and p ({2 * S} solves, mean {np.mean(its):.0f} iterations, "
+                         f"{cpu_t:.1f} s)"}
+
+    bpi = (8 * nnz + 52 * nc) if main_form == "B" else (12 * nnz + 100 * nc)
+    out = {
+        "metric": METRIC,
+        "value": R["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": R["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if main_form == "B" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"CGP step, coarse {nx}x{ny} jittered P1 ({nc} nodes, nnz {nnz}), fine k=1 "
+                               f"({nf} nodes), {K}-step drifting 8-mode Fourier flow, phi and p solves to "
+                               f"{TOL:g} true relative residual",
+                   "coarse_nodes": nc, "fine_nodes": nf, "nnz": nnz, "tol": TOL, "stuart": sigma},
+        "forms": {f: {k: v for k, v in r.items() if k != "step0"} | {"err_vs_oracle_step0": errs.get(f)}
+                  for f, r in res.items()},
+        "speedup_B_over_A": (res["B"]["solves_per_s"] / res["A"]["solves_per_s"]) if {"A", "B"} <= set(res) else None,
+        "roofline": {"bound": "hbm", "achieved": R["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": R["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_pcg (persistent solve)", "bytes_per_iter": bpi},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

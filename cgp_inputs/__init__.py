@@ -38,6 +38,7 @@ __all__ = [
     "fourier_modes",
     "stream_velocity",
     "potential_velocity",
+    "FourierSequence",
     "stuart_numbers",
     "batch_sizes",
     "DT",
@@ -184,6 +185,41 @@ def potential_velocity(xy: np.ndarray, modes: dict, t: float = 0.0) -> tuple[np.
     u = -(s * (modes["c"] * modes["kx"])[None, :]).sum(axis=1)
     v = -(s * (modes["c"] * modes["ky"])[None, :]).sum(axis=1)
     return np.ascontiguousarray(u), np.ascontiguousarray(v)
+
+
+class FourierSequence:
+    """Velocity fields of a drifting Fourier flow at fixed points, step after step.
+
+    ``at(n)`` returns the stream-function velocity ``(u, v)`` and the velocity
+    with an added gradient part ``(u + chi_x, v + chi_y)`` at time ``n * DT``
+    (phases advance by ``omega_m * DT`` per step).  The sines of the mode phases
+    are expanded once (sin(a + w t) = sin a cos w t + cos a sin w t), so a step
+    costs two small matrix-vector products per field.
+    """
+
+    def __init__(self, xy: np.ndarray, modes: dict, chi_modes: dict):
+        self.modes, self.chi = modes, chi_modes
+        self._tabs = []
+        for md in (modes, chi_modes):
+            ph = _phase(xy, md, 0.0)
+            self._tabs.append((np.sin(ph), np.cos(ph)))
+
+    def _sin(self, which: int, t: float) -> np.ndarray:
+        s, c = self._tabs[which]
+        md = (self.modes, self.chi)[which]
+        return s * np.cos(md["omega"] * t)[None, :] + c * np.sin(md["omega"] * t)[None, :]
+
+    def at(self, n: int):
+        t = n * DT
+        s = self._sin(0, t)
+        m = self.modes
+        u = -(s @ (m["c"] * m["ky"]))
+        v = s @ (m["c"] * m["kx"])
+        s2 = self._sin(1, t)
+        c2 = self.chi
+        ut = u - s2 @ (c2["c"] * c2["kx"])
+        vt = v - s2 @ (c2["c"] * c2["ky"])
+        return u, v, ut, vt
 
 
 def stuart_numbers(count: int) -> np.ndarray:

@@ -65,6 +65,14 @@ enum { CGP_SRC_CURL = 0, CGP_SRC_DIV = 1 };
 enum { CGP_FP64 = 0, CGP_FP32_IR = 1 };
 /* initial guess of cgp_poisson_solve */
 enum { CGP_GUESS_ZERO = 0, CGP_GUESS_GIVEN = 1, CGP_GUESS_EXTRAP = 2, CGP_GUESS_LEARNED = 3 };
+/* how cgp_poisson_solve synchronises its workgroups between CG stages:
+ *   STAGED      one kernel launch per stage (one per CG iteration), launched from
+ *               replayed HIP graphs; the call returns once the host has seen every
+ *               instance finish (it waits on the device, it does not enqueue only)
+ *   PERSISTENT  one co-resident launch with a grid-wide barrier between stages;
+ *               fully asynchronous, so it can be captured in a caller's graph
+ *   AUTO        STAGED, or PERSISTENT while the context's stream is being captured */
+enum { CGP_ENGINE_AUTO = 0, CGP_ENGINE_STAGED = 1, CGP_ENGINE_PERSISTENT = 2 };
 /* per-instance solve status (cgp_solve_stats.status) */
 enum { CGP_SOLVE_OK = 0, CGP_SOLVE_NOCONV = 1, CGP_SOLVE_BREAKDOWN = 2, CGP_SOLVE_ABORTED = 3 };
 
@@ -153,7 +161,9 @@ typedef struct {
     int32_t max_iter;     /* cap on CG iterations per instance (0 = default 100000)      */
     cgp_model model;      /* network for CGP_GUESS_LEARNED                               */
     int32_t spmv_lanes;   /* lanes per matrix row: 0 = autotuned/default, else 1,2,4,8   */
-    int32_t blocks;       /* persistent workgroups: 0 = one per compute unit             */
+    int32_t blocks;       /* workgroups of the solve: 0 = one per compute unit           */
+    int32_t engine;       /* CGP_ENGINE_*                                                */
+    int32_t launches_per_graph; /* CGP_ENGINE_STAGED: stages per replayed graph (0 = 32; even) */
 } cgp_solve_opts;
 
 typedef struct {
@@ -181,8 +191,10 @@ typedef struct {
  * CGP_FP64: every vector and product in fp64.  CGP_FP32_IR: fp32 matrix,
  * vectors and products with fp64 dot-product accumulation, refined by true
  * fp64 residuals b - K phi and fp64 solution updates.  ||b|| = 0 gives phi = 0.
- * Asynchronous; numerical failures are reported in d_stats (see
- * cgp_solve_check). */
+ * With CGP_ENGINE_STAGED the call waits until every instance has finished
+ * (results are complete once the stream reaches the enqueued work); with
+ * CGP_ENGINE_PERSISTENT it only enqueues.  Numerical failures are reported in
+ * d_stats (see cgp_solve_check). */
 cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_meshes,
                              const double *const *h_d_b, double *const *h_d_phi,
                              const double *const *h_d_prev1, const double *const *h_d_prev2,

@@ -13,6 +13,7 @@
  * so every product and sum is rounded as written).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -34,6 +35,9 @@ static double dot64(int n, const double *a, const double *b) {
     for (int i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
 }
+
+/* threads an OpenMP region of this library runs with */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 void oracle_spmv_f64(int n, const int *rowptr, const int *col, const double *val,
                      const double *x, double *y) {

@@ -41,6 +41,8 @@ def _load():
         lib.oracle_pcg_mixed.restype = ctypes.c_int
         lib.oracle_spmv_f64.argtypes = [ctypes.c_int, ip, ip, dp, dp, dp]
         lib.oracle_spmv_f64.restype = None
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -103,6 +105,11 @@ def pcg_mixed(a: sp.csr_matrix, b: np.ndarray, x0: np.ndarray | None = None, tol
                               _p(dinv, ctypes.c_double), _p(b, ctypes.c_double), _p(x, ctypes.c_double),
                               tol, delta, max_iter, ctypes.byref(it), ctypes.byref(upd), ctypes.byref(rel))
     return x, {"status": STATUS[st], "iters": it.value, "updates": upd.value, "rel_res": rel.value}
+
+
+def threads() -> int:
+    """OpenMP threads the C solvers run with."""
+    return int(_load().oracle_threads())
 
 
 def spmv(a: sp.csr_matrix, x: np.ndarray) -> np.ndarray:

@@ -24,8 +24,20 @@ struct Plan {
     DBuf<uint8_t> buf;
     InstDesc *d_insts = nullptr;
     int32_t *d_block_inst = nullptr;
-    int32_t *d_done_at = nullptr;
+    RowRange *d_ranges = nullptr;
+    int32_t *d_done_at = nullptr;    // persistent driver: stage at which each instance finished
+    int32_t *d_done = nullptr;       // staged driver: finished-instance counter
+    SolveParams *d_prm = nullptr;    // staged driver: parameters of the current call
     int grid = 0;
+    int n_inst = 0;
+    int halo = 0;                    // widest column range of a workgroup
+    hipGraph_t graph = nullptr;      // staged driver: `launches` stage launches
+    hipGraphExec_t exec = nullptr;
+    int launches = 0;
+    ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
 };
 
 struct GraphRec {
@@ -48,6 +60,10 @@ struct cgp_ctx_s {
     std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
     std::map<int32_t, GraphRec> graphs;
     DBuf<GridSync> sync;
+    int32_t *host_flag = nullptr;     // pinned, mapped: set by the device when a staged solve is done
+    int32_t *host_flag_dev = nullptr;
+    hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+    uint64_t timeout_ticks = 0;
     bool capturing = false;
 };
 
@@ -85,17 +101,15 @@ void ensure_work(Mesh &m) {
     const int64_t n = m.lv[0].n;
     SolveWork &w = m.work;
     if (w.n == n) return;
-    w.r.alloc(n);
-    w.z.alloc(n);
-    w.p0.alloc(n);
-    w.p1.alloc(n);
-    w.q.alloc(n);
+    w.r.alloc(2 * n);
+    w.w.alloc(2 * n);
+    w.s.alloc(2 * n);
+    w.p.alloc(n);
+    w.r32.alloc(2 * n);
+    w.w32.alloc(2 * n);
+    w.s32.alloc(2 * n);
+    w.p32.alloc(n);
     w.c32.alloc(n);
-    w.r32.alloc(n);
-    w.z32.alloc(n);
-    w.p32a.alloc(n);
-    w.p32b.alloc(n);
-    w.q32.alloc(n);
     w.n = n;
 }
 
@@ -152,6 +166,15 @@ cgp_status cgp_create(cgp_ctx *out, int32_t device, void *hip_stream) {
         ctx->max_blocks_per_cu = std::max(1, pcg_max_blocks_per_cu());
         ctx->sync.alloc(1);
         CGP_HIP(hipMemset(ctx->sync.p, 0, sizeof(GridSync)));
+        CGP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->host_flag), sizeof(int32_t), hipHostMallocMapped));
+        *ctx->host_flag = 0;
+        CGP_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->host_flag_dev), ctx->host_flag, 0));
+        CGP_HIP(hipEventCreateWithFlags(&ctx->chunk_ev[0], hipEventDisableTiming));
+        CGP_HIP(hipEventCreateWithFlags(&ctx->chunk_ev[1], hipEventDisableTiming));
+        int khz = 0;
+        CGP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
+        if (khz <= 0) khz = 100000;
+        ctx->timeout_ticks = static_cast<uint64_t>(khz) * 1000ull * 4ull;   // 4 s per barrier wait
         CGP_HIP(hipDeviceSynchronize());
         *out = ctx.release();
     });
@@ -166,7 +189,11 @@ cgp_status cgp_destroy(cgp_ctx ctx) {
             if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
             if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
         }
+        ctx->plans.clear();
         if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+        for (auto &e : ctx->chunk_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
         delete ctx;
     });
 }
@@ -321,11 +348,14 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         CGP_REQUIRE(o.guess >= CGP_GUESS_ZERO && o.guess <= CGP_GUESS_LEARNED, "unknown guess mode");
         CGP_REQUIRE(o.tol > 0.0 && std::isfinite(o.tol), "tol must be positive");
         CGP_REQUIRE(o.refine_delta >= 0.0 && o.refine_delta < 1.0, "refine_delta must be in [0, 1)");
-        CGP_REQUIRE(o.max_iter >= 0, "max_iter must be >= 0");
+        CGP_REQUIRE(o.max_iter >= 0 && o.max_iter <= 10000000, "max_iter must be in [0, 1e7]");
         CGP_REQUIRE(o.spmv_lanes == 0 || o.spmv_lanes == 1 || o.spmv_lanes == 2 || o.spmv_lanes == 4 ||
                         o.spmv_lanes == 8,
                     "spmv_lanes must be 0, 1, 2, 4 or 8");
         CGP_REQUIRE(o.blocks >= 0, "blocks must be >= 0");
+        CGP_REQUIRE(o.engine >= CGP_ENGINE_AUTO && o.engine <= CGP_ENGINE_PERSISTENT, "unknown engine");
+        CGP_REQUIRE(o.launches_per_graph >= 0 && o.launches_per_graph % 2 == 0 && o.launches_per_graph <= 4096,
+                    "launches_per_graph must be even and <= 4096");
         if (o.guess == CGP_GUESS_LEARNED)
             throw Error{CGP_E_UNSUPPORTED, "learned guess requires a model (not loaded)"};
         const bool need_prev = o.guess == CGP_GUESS_EXTRAP || o.guess == CGP_GUESS_LEARNED;
@@ -344,11 +374,14 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                             "prev1/prev2 must not alias phi");
             }
         }
+        const bool persistent = o.engine == CGP_ENGINE_PERSISTENT || (o.engine == CGP_ENGINE_AUTO && ctx->capturing);
+        CGP_REQUIRE(persistent || !ctx->capturing, "the staged engine cannot be captured; use CGP_ENGINE_PERSISTENT");
         SolveParams prm{};
         prm.tol = o.tol;
         prm.delta = o.refine_delta > 0.0 ? o.refine_delta : 0.1;
         prm.max_iter = o.max_iter > 0 ? o.max_iter : 100000;
         prm.precision = o.precision;
+        const int launches = o.launches_per_graph > 0 ? o.launches_per_graph : 32;
 
         const int max_grid = ctx->cus * ctx->max_blocks_per_cu;
         int grid = o.blocks > 0 ? o.blocks : ctx->cus;
@@ -356,24 +389,32 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         for (int i = 0; i < n_inst; ++i) ensure_work(*ms[i]);
 
         // instances in groups of at most `grid` (one workgroup minimum each)
-        for (int g0 = 0; g0 < n_inst; g0 += grid) {
-            const int gn = std::min(grid, n_inst - g0);
+        for (int g0 = 0; g0 < n_inst; g0 += (persistent ? grid : n_inst)) {
+            const int gn = persistent ? std::min(grid, n_inst - g0) : n_inst;
             std::vector<int64_t> rows(gn);
             for (int i = 0; i < gn; ++i) rows[i] = ms[g0 + i]->lv[0].n;
-            std::vector<int32_t> nb = split_blocks(rows, grid);
+            // staged: one row per thread, so ceil(n / block) workgroups per instance;
+            // persistent: the co-resident grid split between the instances
+            std::vector<int32_t> nb;
+            if (persistent) {
+                nb = split_blocks(rows, grid);
+            } else {
+                for (int64_t r : rows) nb.push_back(static_cast<int32_t>((r + pcg_block_size() - 1) / pcg_block_size()));
+            }
             int used = 0;
             for (int v : nb) used += v;
+            auto lanes_of = [&](Mesh &m) {
+                return o.spmv_lanes ? o.spmv_lanes : (m.tuned_lanes[o.precision] ? m.tuned_lanes[o.precision] : 4);
+            };
             // cache key: everything the launch records depend on
             std::ostringstream key;
-            key << o.precision << ':' << o.guess << ':' << used << ':';
+            key << o.precision << ':' << o.guess << ':' << used << ':' << launches << ':' << persistent << ':';
             for (int i = 0; i < gn; ++i) {
                 const int ii = g0 + i;
-                const int lanes = o.spmv_lanes ? o.spmv_lanes
-                                               : (ms[ii]->tuned_lanes[o.precision] ? ms[ii]->tuned_lanes[o.precision] : 4);
-                key << h_meshes[ii] << ',' << lanes << ',' << nb[i] << ',' << (const void *)h_d_b[ii] << ','
-                    << (const void *)h_d_phi[ii] << ',' << (const void *)(need_prev ? h_d_prev1[ii] : nullptr)
-                    << ',' << (const void *)(need_prev ? h_d_prev2[ii] : nullptr) << ','
-                    << (const void *)(d_stats + ii) << ';';
+                key << h_meshes[ii] << ',' << lanes_of(*ms[ii]) << ',' << nb[i] << ',' << (const void *)h_d_b[ii]
+                    << ',' << (const void *)h_d_phi[ii] << ','
+                    << (const void *)(need_prev ? h_d_prev1[ii] : nullptr) << ','
+                    << (const void *)(need_prev ? h_d_prev2[ii] : nullptr) << ';';
             }
             auto it = ctx->plans.find(key.str());
             Plan *plan = nullptr;
@@ -383,15 +424,21 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 auto p = std::make_unique<Plan>();
                 size_t npart = 0;
                 for (int v : nb) npart += static_cast<size_t>(2) * NPART * v;
-                const size_t off_bi = sizeof(InstDesc) * gn;
-                const size_t off_done = off_bi + sizeof(int32_t) * used;
-                const size_t off_part = ((off_done + sizeof(int32_t) * gn) + 255) / 256 * 256;
+                auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+                const size_t off_bi = align(sizeof(InstDesc) * gn);
+                const size_t off_rng = align(off_bi + sizeof(int32_t) * used);
+                const size_t off_ctl = align(off_rng + sizeof(RowRange) * used);
+                const size_t off_done_at = align(off_ctl + sizeof(Ctl) * 2 * gn);
+                const size_t off_done = align(off_done_at + sizeof(int32_t) * gn);
+                const size_t off_prm = align(off_done + sizeof(int32_t));
+                const size_t off_part = align(off_prm + sizeof(SolveParams));
                 const size_t total = off_part + sizeof(double) * npart;
                 p->buf.alloc(total);
-                std::vector<uint8_t> host(total, 0);
+                std::vector<uint8_t> host(off_ctl, 0);
                 InstDesc *hd = reinterpret_cast<InstDesc *>(host.data());
                 int32_t *hbi = reinterpret_cast<int32_t *>(host.data() + off_bi);
                 double *dpart = reinterpret_cast<double *>(p->buf.p + off_part);
+                Ctl *dctl = reinterpret_cast<Ctl *>(p->buf.p + off_ctl);
                 int blk = 0;
                 size_t poff = 0;
                 for (int i = 0; i < gn; ++i) {
@@ -401,8 +448,15 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     d.n = static_cast<int32_t>(m.lv[0].n);
                     d.blk0 = blk;
                     d.nblk = nb[i];
-                    d.lanes = o.spmv_lanes ? o.spmv_lanes : (m.tuned_lanes[o.precision] ? m.tuned_lanes[o.precision] : 4);
+                    d.lanes = lanes_of(m);
                     d.guess = o.guess;
+                    d.stats_index = i;
+                    d.chunk = static_cast<int32_t>((m.lv[0].n + nb[i] - 1) / nb[i]);
+                    d.fast = (!persistent && m.max_row <= pcg_sell_max_width()) ? 1 : 0;
+                    d.sell_ptr = m.sell_ptr.p;
+                    d.sell_col = m.sell_col.p;
+                    d.sell_val = m.sell_val.p;
+                    d.sell_val32 = m.sell_val32.p;
                     d.rowptr = m.rowptr.p;
                     d.col = m.col.p;
                     d.val = m.val.p;
@@ -414,36 +468,89 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     d.prev1 = need_prev ? h_d_prev1[ii] : nullptr;
                     d.prev2 = need_prev ? h_d_prev2[ii] : nullptr;
                     d.r = m.work.r.p;
-                    d.z = m.work.z.p;
-                    d.p0 = m.work.p0.p;
-                    d.p1 = m.work.p1.p;
-                    d.q = m.work.q.p;
-                    d.c32 = m.work.c32.p;
+                    d.w = m.work.w.p;
+                    d.s = m.work.s.p;
+                    d.p = m.work.p.p;
                     d.r32 = m.work.r32.p;
-                    d.z32 = m.work.z32.p;
-                    d.p32a = m.work.p32a.p;
-                    d.p32b = m.work.p32b.p;
-                    d.q32 = m.work.q32.p;
+                    d.w32 = m.work.w32.p;
+                    d.s32 = m.work.s32.p;
+                    d.p32 = m.work.p32.p;
+                    d.c32 = m.work.c32.p;
                     d.partials = dpart + poff;
-                    d.stats = d_stats + ii;
+                    d.ctl = dctl + 2 * i;
                     hd[i] = d;
                     for (int v = 0; v < nb[i]; ++v) hbi[blk + v] = i;
                     blk += nb[i];
                     poff += static_cast<size_t>(2) * NPART * nb[i];
                 }
-                CGP_HIP(hipMemcpyAsync(p->buf.p, host.data(), off_part, hipMemcpyHostToDevice, ctx->aux));
-                CGP_HIP(hipStreamSynchronize(ctx->aux));
+                CGP_HIP(hipMemcpyAsync(p->buf.p, host.data(), off_rng, hipMemcpyHostToDevice, ctx->aux));
                 p->d_insts = reinterpret_cast<InstDesc *>(p->buf.p);
                 p->d_block_inst = reinterpret_cast<int32_t *>(p->buf.p + off_bi);
-                p->d_done_at = reinterpret_cast<int32_t *>(p->buf.p + off_done);
+                p->d_ranges = reinterpret_cast<RowRange *>(p->buf.p + off_rng);
+                p->d_done_at = reinterpret_cast<int32_t *>(p->buf.p + off_done_at);
+                p->d_done = reinterpret_cast<int32_t *>(p->buf.p + off_done);
+                p->d_prm = reinterpret_cast<SolveParams *>(p->buf.p + off_prm);
                 p->grid = used;
+                p->n_inst = gn;
+                launch_ranges(ctx->aux, p->d_insts, p->d_block_inst, used, p->d_ranges);
+                std::vector<RowRange> hr(used);
+                CGP_HIP(hipMemcpyAsync(hr.data(), p->d_ranges, sizeof(RowRange) * used, hipMemcpyDeviceToHost,
+                                       ctx->aux));
+                CGP_HIP(hipStreamSynchronize(ctx->aux));
+                for (const RowRange &r : hr) p->halo = std::max(p->halo, r.c1 - r.c0 + 1);
                 plan = p.get();
                 ctx->plans[key.str()] = std::move(p);
             }
             SolveParams gp = prm;
             gp.n_inst = gn;
-            launch_pcg(ctx->stream, plan->d_insts, gn, plan->d_block_inst, plan->grid, pcg_block_size(), gp,
-                       ctx->sync.p, plan->d_done_at, pcg_lds_bytes());
+            gp.stats = d_stats + g0;
+            if (persistent) {
+                launch_cg_persistent(ctx->stream, plan->d_insts, gn, plan->d_block_inst, plan->d_ranges, plan->grid,
+                                     gp, ctx->sync.p, plan->d_done_at, ctx->timeout_ticks);
+                continue;
+            }
+            // staged: a graph of `launches` stage launches, replayed until every instance is done
+            if (!plan->exec) {
+                // the launch template is recorded on the private stream (the caller's may be the null stream)
+                CGP_HIP(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeRelaxed));
+                for (int l = 0; l < launches; ++l)
+                    launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, plan->d_insts, plan->d_block_inst,
+                                   plan->d_ranges, plan->grid, plan->d_prm, l & 1, plan->d_done,
+                                   ctx->host_flag_dev);
+                CGP_HIP(hipStreamEndCapture(ctx->aux, &plan->graph));
+                CGP_HIP(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+                plan->launches = launches;
+            }
+            volatile int32_t *flag = ctx->host_flag;
+            *flag = 0;
+            launch_cg_boot(ctx->stream, plan->d_insts, gn, gp, plan->d_prm, plan->d_done);
+            // each instance needs at most max_iter iterations plus three stages per
+            // refinement (at most one per iteration) plus a few set-up stages
+            const int64_t max_stages = 4 * static_cast<int64_t>(prm.max_iter) + 16;
+            const int64_t max_chunks = max_stages / plan->launches + 2;
+            int64_t chunk = 0;
+            bool finished = false;
+            while (!finished) {
+                if (chunk >= 2) {
+                    // wait for the older chunk in flight (or for the device to report completion)
+                    hipEvent_t old = ctx->chunk_ev[chunk & 1];
+                    for (;;) {
+                        if (*flag) {
+                            finished = true;
+                            break;
+                        }
+                        const hipError_t q = hipEventQuery(old);
+                        if (q == hipSuccess) break;
+                        if (q != hipErrorNotReady) CGP_HIP(q);
+                    }
+                    if (finished) break;
+                    if (*flag) break;
+                }
+                if (chunk >= max_chunks) throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
+                CGP_HIP(hipGraphLaunch(plan->exec, ctx->stream));
+                CGP_HIP(hipEventRecord(ctx->chunk_ev[chunk & 1], ctx->stream));
+                ++chunk;
+            }
         }
     });
 }

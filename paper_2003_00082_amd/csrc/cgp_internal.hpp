@@ -78,11 +78,11 @@ struct Level {
     DBuf<double> tmp;       // [n] prolongation staging (levels 1..k-1)
 };
 
-// per-instance solver workspace, owned by the mesh
+// per-instance solver workspace, owned by the mesh (r, w, s double-buffered)
 struct SolveWork {
     int64_t n = 0;
-    DBuf<double> r, z, p0, p1, q;                   // fp64 recurrences
-    DBuf<float> c32, r32, z32, p32a, p32b, q32;     // fp32 inner recurrences
+    DBuf<double> r, w, s, p;
+    DBuf<float> r32, w32, s32, p32, c32;
 };
 
 struct Mesh {
@@ -97,20 +97,40 @@ struct Mesh {
     DBuf<int32_t> rowptr, col;
     DBuf<double> val, dinv;
     DBuf<float> val32, dinv32;
+    // sliced ELL copy (64-row slices): slice s holds entries [sell_ptr[s], sell_ptr[s+1])
+    int64_t sell_nnz = 0;
+    DBuf<int32_t> sell_ptr, sell_col;
+    DBuf<double> sell_val;
+    DBuf<float> sell_val32;
     SolveWork work;
     int32_t tuned_lanes[2] = {0, 0};   // autotuned SpMV lanes per precision (0 = not tuned)
 };
 
 // ------------------------------------------------------------------ solver launch records
 
-// device-side description of one instance of a (batched) persistent solve
+// per-instance control state of the CG stage machine
+struct Ctl {
+    int32_t state, it, refinements, status, guess_used, pad_, restart, first;
+    double gamma, alpha, beta, pap, bnorm, rmax, rel_res, rel_res_guess;
+};
+
+// rows [r0, r1) of one workgroup and the column range [c0, c1] they touch
+struct RowRange {
+    int32_t r0, r1, c0, c1;
+};
+
+constexpr int NPART = 4;
+
+// device-side description of one instance of a (batched) solve
 struct InstDesc {
-    int32_t n;          // rows
-    int32_t blk0;       // first persistent workgroup of this instance
-    int32_t nblk;       // workgroups of this instance
-    int32_t lanes;      // SpMV lanes per row (1, 2, 4, 8)
-    int32_t guess;      // CGP_GUESS_*
-    int32_t pad_;
+    int32_t n;            // rows
+    int32_t blk0;         // first workgroup of this instance
+    int32_t nblk;         // workgroups of this instance
+    int32_t lanes;        // SpMV lanes per row (1, 2, 4, 8)
+    int32_t guess;        // CGP_GUESS_*
+    int32_t stats_index;  // record of this instance in SolveParams::stats
+    int32_t chunk;        // rows per workgroup
+    int32_t fast;         // every row fits the one-row-per-thread iteration (sliced ELL width)
     const int32_t *rowptr;
     const int32_t *col;
     const double *val;
@@ -121,13 +141,15 @@ struct InstDesc {
     double *x;
     const double *prev1;
     const double *prev2;
-    double *r, *z, *p0, *p1, *q;
-    float *c32, *r32, *z32, *p32a, *p32b, *q32;
-    double *partials;   // [2][NPART][nblk]
-    cgp_solve_stats *stats;
+    double *r, *w, *s, *p;               // fp64 recurrences (r, w, s: 2n each)
+    float *r32, *w32, *s32, *p32, *c32;  // fp32 recurrences and correction
+    double *partials;                    // [2][NPART][nblk]
+    Ctl *ctl;                            // [2]
+    const int32_t *sell_ptr;             // sliced ELL copy of the matrix
+    const int32_t *sell_col;
+    const double *sell_val;
+    const float *sell_val32;
 };
-
-constexpr int NPART = 4;
 
 struct SolveParams {
     double tol;
@@ -136,9 +158,10 @@ struct SolveParams {
     int32_t precision;
     int32_t n_inst;
     int32_t pad_;
+    cgp_solve_stats *stats;   // caller's stats array (per call, not part of the cached plan)
 };
 
-// grid-wide barrier state (one per context, zeroed at creation)
+// grid-wide barrier state of the persistent driver (one per context, zeroed at creation)
 struct GridSync {
     uint32_t arrive;
     uint32_t gen;
@@ -146,12 +169,20 @@ struct GridSync {
     int32_t pad_;
 };
 
-// launch the persistent solver (pcg.hip)
-void launch_pcg(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
-                int grid, int block, const SolveParams &prm, GridSync *d_sync, int32_t *d_done_at,
-                size_t lds_bytes);
+// solver launches (pcg.hip)
 int pcg_block_size();
-size_t pcg_lds_bytes();
+int pcg_max_blocks_per_cu();
+void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_block_inst, int grid,
+                   RowRange *d_ranges);
+void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
+                    int32_t *d_done);
+void launch_cg_step(hipStream_t s, bool mixed, int halo, const InstDesc *d_insts, const int32_t *d_block_inst,
+                    const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par, int32_t *d_done,
+                    int32_t *d_host_flag);
+int pcg_sell_max_width();
+void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
+                          const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,
+                          int32_t *d_done_at, uint64_t timeout_ticks);
 
 // mesh build (mesh_build.hip)
 void build_hierarchy(hipStream_t s, Mesh &m, const double *h_xy, int64_t n, const int32_t *h_tri,
@@ -164,8 +195,6 @@ void launch_prolong(hipStream_t s, Mesh &m, const double *qc, double *qf);
 void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const double *uf,
                     const double *vf, double sigma, double b0, double *fx, double *fy,
                     double *grad_elem);
-void launch_guess_prep(hipStream_t s, int guess, int64_t n, double *x, const double *prev1,
-                       const double *prev2);
 
 // scan (mesh_build.hip): out[0..n] exclusive prefix sums of in[0..n-1]; returns total
 int64_t exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t n);

@@ -1,28 +1,43 @@
-// Persistent Jacobi-preconditioned CG for the coarse Poisson systems K phi = b
-// of Eqs. 12 and 15 (the paper solves them with GMRES(m)+ILU(0), Section 2.3;
-// K is symmetric positive definite, so CG applies).
+// Jacobi-preconditioned conjugate gradients for the coarse Poisson systems
+// K phi = b of Eqs. 12 and 15 (the paper solves them with GMRES(m)+ILU(0),
+// Section 2.3; after Dirichlet elimination K is symmetric positive definite,
+// so CG applies).
 //
-// One launch solves a batch of independent instances.  The grid is co-resident
-// (one or two workgroups per compute unit) and split statically between the
-// instances; each workgroup owns a contiguous range of rows of one instance.
-// The solve is a sequence of stages separated by grid-wide barriers; after each
-// barrier every workgroup of an instance reduces that instance's per-workgroup
-// partial sums in the same fixed order, so all of them take the same decision
-// (bitwise) without a further barrier.
+// Single-reduction form: one grid-wide synchronisation per iteration.  With
+// u = M^-1 r, w = K u and s = K p carried by recurrences,
+//   p_i = u_i + beta_i p_{i-1},   s_i = w_i + beta_i s_{i-1}
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i
+//   u_{i+1} = M^-1 r_{i+1},       w_{i+1} = K u_{i+1}
+//   gamma = r.u, delta = w.u, sigma = u.s_i   (one fused reduction)
+//   beta_{i+1}  = gamma_{i+1} / gamma_i
+//   alpha_{i+1} = gamma_{i+1} / (delta + 2 beta sigma + beta^2 gamma_i / alpha_i)
+// The denominator is p_{i+1}.K p_{i+1} expanded exactly, so it stays valid when
+// the residual is replaced by a true residual (mixed precision, below).
 //
-// Iteration (2 barriers): with p double-buffered,
-//   stage A: p_new = z + beta p_old ; q = K p_new ; partial p_new.q
-//   stage B: x += alpha p_new ; r -= alpha q ; z = D^-1 r ; partials r.r, r.z
-// Stage A gathers p_new at neighbouring rows by recomputing z_j + beta p_old_j
-// (both stable during the stage), staged once per stage into LDS when the
-// workgroup's column range fits, so the product reads LDS instead of scattered
-// global memory.
+// Halo: the product w_{i+1} = K u_{i+1} needs u_{i+1} at neighbouring rows owned
+// by other workgroups.  Those values are recomputed from r_i, w_i, s_{i-1}
+// (written by the previous stage, hence stable) into LDS over the workgroup's
+// column range, so neither a second synchronisation nor a global gather of a
+// freshly written vector is needed.  r, w, s are double-buffered by stage
+// parity: every stage reads buffer par^1 and writes buffer par (copying what it
+// does not change), so the buffers a stage reads are known before its state is.
 //
-// Mixed mode (CGP_FP32_IR): the same recurrences in fp32 (matrix, vectors,
-// products) with fp64 dot accumulation; the fp32 residual is replaced by the
-// true fp64 residual b - K x after folding the fp32 correction into the fp64
-// iterate whenever the fp32 residual has dropped by `delta` since the last
-// replacement.  Convergence is only decided on a true fp64 residual.
+// Mixed precision (CGP_FP32_IR): matrix, recurrences and products in fp32, dot
+// products accumulated in fp64; the fp32 correction c is folded into the fp64
+// iterate and the residual replaced by fl32(b - K x) computed in fp64 whenever
+// ||r|| has dropped by `delta` since the last replacement.  Convergence is
+// decided on true fp64 residuals only.
+//
+// Two drivers run the same stages:
+//   k_cg_step       one stage per launch, one row per thread; the host replays
+//                   a captured graph of launches until the instances are done
+//                   (kernel boundaries are the cheapest grid-wide
+//                   synchronisation on this GPU).  Every global load an
+//                   iteration needs (sliced-ELL row, vectors over the halo range)
+//                   is issued at kernel start, before the stage is decoded, so an
+//                   iteration costs about one memory round trip.
+//   k_cg_persistent all stages in one co-resident launch with a grid barrier
+//                   (fits inside a caller's graph capture of a whole step)
 #include "cgp_internal.hpp"
 
 namespace cgp {
@@ -30,30 +45,22 @@ namespace {
 
 constexpr int BLOCK = 512;
 constexpr int NWAVE = BLOCK / 64;
-constexpr int LDS_DOUBLES = 8192;          // 64 KB staging buffer
+constexpr int LDS_DOUBLES = 8192;   // 64 KB staging buffer
 constexpr int LDS_FLOATS = 2 * LDS_DOUBLES;
+constexpr int KMAX = 12;            // longest row the one-row-per-thread iteration holds in registers
+constexpr int HMAX = 8;             // most staged entries per thread in that iteration (4096 per workgroup)
 
 enum State : int32_t {
-    ST_PREP = 0,   // x = initial guess (ZERO / EXTRAP)
-    ST_JUDGE,      // LEARNED: residual norms of the network guess and of prev1
-    ST_PICK,       // LEARNED rejected: x = prev1
-    ST_INIT,       // fp64: r = b - K x, z = D^-1 r, p_old = 0
-    ST_A,          // fp64: p_new = z + beta p_old, q = K p_new
-    ST_B,          // fp64: x += alpha p_new, r -= alpha q, z = D^-1 r
-    ST_VERIFY,     // fp64: true residual when the recurrence says converged
-    MX_INIT,       // mixed: r64 = b - K x, r32 = fl32(r64), c32 = 0, z32, p_old32 = 0
-    MX_A,          // mixed: p_new32 = z32 + beta p_old32, q32 = K32 p_new32
-    MX_B,          // mixed: c32 += alpha p_new32, r32 -= alpha q32, z32 = D32^-1 r32
-    MX_FOLD,       // mixed: x += c32, c32 = 0
-    MX_RES,        // mixed: r64 = b - K x, r32 = fl32(r64), z32
-    ST_ZEROX,      // ||b|| = 0: x = 0
+    ST_BOOT = 0,  // before the first stage
+    ST_PREP,      // x = initial guess (ZERO / EXTRAP)
+    ST_JUDGE,     // LEARNED: residual norms of the network guess and of prev1
+    ST_PICK,      // LEARNED rejected: x = prev1
+    ST_RES,       // r = b - K x (fp64)
+    ST_START,     // u = M^-1 r, w = K u, reductions gamma, delta, sigma
+    ST_ITER,      // one CG iteration
+    ST_FOLD,      // mixed: x += c, c = 0
+    ST_ZEROX,     // ||b|| = 0: x = 0
     ST_DONE
-};
-
-struct Ctl {
-    int32_t state, it, refinements, status, guess_used, par, done;
-    int32_t pad_;
-    double rho, alpha, beta, bnorm, rmax, rel_res, rel_res_guess;
 };
 
 __device__ inline double wave_sum(double v) {
@@ -62,7 +69,7 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// block-wide sums of NPART values; result valid in every thread after return
+// block-wide sums of NPART values into out[] (valid for every thread after return)
 __device__ inline void block_sums(double (&v)[NPART], double (*red)[NPART], double *out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -72,23 +79,636 @@ __device__ inline void block_sums(double (&v)[NPART], double (*red)[NPART], doub
         for (int s = 0; s < NPART; ++s) red[wave][s] = v[s];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int s = 0; s < NPART; ++s) {
-            double t = 0.0;
-            for (int w = 0; w < NWAVE; ++w) t += red[w][s];
-            out[s] = t;
-        }
+    if (threadIdx.x < NPART) {
+        double t = 0.0;
+        for (int w = 0; w < NWAVE; ++w) t += red[w][threadIdx.x];
+        out[threadIdx.x] = t;
     }
     __syncthreads();
 }
 
-// Grid barrier: arrive counter + generation.  The wait is bounded: past
-// `timeout` ticks of the constant-rate wall clock the workgroup raises the
-// abort flag, and every waiter leaves once it sees the flag.  Returns false
-// when the solve was aborted.
-__device__ inline bool grid_barrier(GridSync *gs, uint32_t nblocks, uint32_t &my_gen, uint64_t timeout,
-                                    int *s_ok) {
+// sum of an instance's per-workgroup partials (same order in every workgroup)
+__device__ inline void reduce_partials(const double *part, int nblk, double (*red)[NPART], double *out) {
+    double t[NPART] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < nblk; j += BLOCK) {
+#pragma unroll
+        for (int s = 0; s < NPART; ++s) t[s] += part[s * nblk + j];
+    }
+    block_sums(t, red, out);
+}
+
+// ------------------------------------------------------------------ state transitions
+
+// Decide the next stage from the stage just executed and its reductions S.
+// Executed by one thread; every workgroup of the instance computes the same result.
+__device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm, int guess) {
+    const bool mixed = prm.precision == CGP_FP32_IR;
+    const double tol = prm.tol;
+    switch (c.state) {
+    case ST_BOOT:
+        c.it = c.refinements = 0;
+        c.status = CGP_SOLVE_OK;
+        c.guess_used = guess;
+        c.restart = 1;
+        c.first = 1;
+        c.gamma = c.alpha = c.beta = c.pap = 0.0;
+        c.bnorm = c.rmax = c.rel_res = c.rel_res_guess = 0.0;
+        c.state = guess == CGP_GUESS_LEARNED ? ST_JUDGE : (guess == CGP_GUESS_GIVEN ? ST_RES : ST_PREP);
+        break;
+    case ST_PREP:
+    case ST_PICK:
+        c.state = ST_RES;
+        break;
+    case ST_JUDGE: {
+        const double rl = S[0], rp = S[1];
+        const double bn = sqrt(S[2]) > 0.0 ? sqrt(S[2]) : 1.0;
+        if (rl <= rp && isfinite(rl)) {   // a non-finite network output is rejected
+            c.guess_used = CGP_GUESS_LEARNED;
+            c.rel_res_guess = sqrt(rl) / bn;
+            c.state = ST_RES;
+        } else {
+            c.guess_used = CGP_GUESS_GIVEN;
+            c.rel_res_guess = sqrt(rp) / bn;
+            c.state = ST_PICK;
+        }
+        break;
+    }
+    case ST_RES: {
+        const double rr = S[0];
+        if (c.first) {
+            c.bnorm = sqrt(S[1]);
+            if (S[1] == 0.0) {
+                c.state = ST_ZEROX;
+                break;
+            }
+            if (!isfinite(S[1])) {
+                c.status = CGP_SOLVE_BREAKDOWN;
+                c.state = ST_DONE;
+                break;
+            }
+        }
+        if (!isfinite(rr)) {
+            c.status = CGP_SOLVE_BREAKDOWN;
+            c.state = ST_DONE;
+            break;
+        }
+        const double rn = sqrt(rr);
+        c.rel_res = rn / c.bnorm;
+        if (c.first && guess != CGP_GUESS_LEARNED) c.rel_res_guess = c.rel_res;
+        if (!c.first) ++c.refinements;
+        if (rn <= tol * c.bnorm) {
+            c.status = CGP_SOLVE_OK;
+            c.state = ST_DONE;
+            break;
+        }
+        if (c.it >= prm.max_iter) {
+            c.status = CGP_SOLVE_NOCONV;
+            c.state = ST_DONE;
+            break;
+        }
+        // fp64: a failed verification restarts CG; mixed: a replaced residual keeps p and s
+        c.restart = (c.first || !mixed) ? 1 : 0;
+        c.first = 0;
+        c.rmax = rn;
+        c.state = ST_START;
+        break;
+    }
+    case ST_START: {
+        const double g = S[0], dl = S[1], sg = S[2];
+        double denom;
+        if (c.restart) {
+            c.beta = 0.0;
+            denom = dl;
+        } else {
+            c.beta = g / c.gamma;
+            denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap;
+        }
+        if (!(denom > 0.0) || !isfinite(denom) || !isfinite(g)) {
+            c.status = CGP_SOLVE_BREAKDOWN;
+            c.state = ST_DONE;
+            break;
+        }
+        c.alpha = g / denom;
+        c.gamma = g;
+        c.state = ST_ITER;
+        break;
+    }
+    case ST_ITER: {
+        const double g = S[0], dl = S[1], sg = S[2], rr = S[3];
+        ++c.it;
+        if (!isfinite(rr) || !isfinite(g)) {
+            c.status = CGP_SOLVE_BREAKDOWN;
+            c.state = ST_DONE;
+            break;
+        }
+        const double rn = sqrt(rr);
+        const bool stop = rn <= tol * c.bnorm || c.it >= prm.max_iter;
+        c.pap = c.gamma / c.alpha;   // p.Kp of the direction just used
+        if (!mixed && stop) {
+            c.state = ST_RES;   // verify on the true residual
+            break;
+        }
+        if (mixed && (stop || rn <= prm.delta * c.rmax)) {
+            c.state = ST_FOLD;   // refine: the direction p (and s = K p) is kept
+            break;
+        }
+        c.beta = g / c.gamma;
+        const double denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap;
+        if (!(denom > 0.0) || !isfinite(denom)) {
+            c.status = CGP_SOLVE_BREAKDOWN;
+            c.state = ST_DONE;
+            break;
+        }
+        c.alpha = g / denom;
+        c.gamma = g;
+        c.restart = 0;
+        break;
+    }
+    case ST_FOLD:
+        c.state = ST_RES;
+        break;
+    case ST_ZEROX:
+        c.rel_res = c.rel_res_guess = 0.0;
+        c.status = CGP_SOLVE_OK;
+        c.state = ST_DONE;
+        break;
+    default:
+        break;
+    }
+    return c;
+}
+
+// ------------------------------------------------------------------ stage work
+
+// y_i = sum_k val[k] * g(col[k]) for the workgroup's rows, `lanes` threads per row;
+// emit(i, y_i) from each row's first lane.
+template <class V, class Gather, class Emit>
+__device__ inline void spmv_rows(const RowRange &R, int lanes, const int32_t *__restrict__ rowptr,
+                                 const int32_t *__restrict__ col, const V *__restrict__ val, Gather g,
+                                 Emit emit) {
+    const int per_pass = BLOCK / lanes;
+    const int sub = threadIdx.x % lanes;
+    for (int32_t base = R.r0; base < R.r1; base += per_pass) {
+        const int32_t i = base + threadIdx.x / lanes;
+        V acc = V(0);
+        if (i < R.r1) {
+            const int32_t k1 = rowptr[i + 1];
+            for (int32_t k = rowptr[i] + sub; k < k1; k += lanes) acc += val[k] * g(col[k]);
+        }
+        for (int m = lanes >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+        if (i < R.r1 && sub == 0) emit(i, acc);
+    }
+}
+
+// Fill LDS with src(j) over the column range (calling own(j, v) for the
+// workgroup's own rows) and multiply from LDS; without room in LDS, own(j, v)
+// runs over the own rows and the product gathers src(col) directly.
+template <class V, class Src, class Own, class Emit>
+__device__ inline void staged_product(const RowRange &R, bool staged, int lanes, const int32_t *rowptr,
+                                      const int32_t *col, const V *val, V *lds, Src src, Own own, Emit emit) {
+    if (staged) {
+        for (int32_t j = R.c0 + threadIdx.x; j <= R.c1; j += BLOCK) {
+            const V v = src(j);
+            lds[j - R.c0] = v;
+            if (j >= R.r0 && j < R.r1) own(j, v);
+        }
+        __syncthreads();
+        spmv_rows<V>(R, lanes, rowptr, col, val, [&](int32_t j) { return lds[j - R.c0]; },
+                     [&](int32_t i, V y) { emit(i, y, lds[i - R.c0]); });
+        __syncthreads();
+    } else {
+        for (int32_t j = R.r0 + threadIdx.x; j < R.r1; j += BLOCK) own(j, src(j));
+        spmv_rows<V>(R, lanes, rowptr, col, val, src, [&](int32_t i, V y) { emit(i, y, src(i)); });
+    }
+}
+
+struct Shared {
+    double lds[LDS_DOUBLES];
+    double red[NWAVE][NPART];
+    double sums[NPART];
+    Ctl ctl;
+};
+
+// One stage of instance D over the workgroup's rows (any number of rows per
+// thread); reads buffers rd = par^1, writes buffers wr = par; partial sums into v[].
+__device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRange &R,
+                                        const SolveParams &prm, Shared &sh, int par, double (&v)[NPART]) {
+    const bool mixed = prm.precision == CGP_FP32_IR;
+    const int lanes = D.lanes;
+    const double *__restrict__ b = D.b;
+    double *__restrict__ x = D.x;
+    const int64_t n = D.n;
+    const int rd = par ^ 1, wr = par;
+    const bool staged64 = R.c1 >= R.c0 && R.c1 - R.c0 + 1 <= LDS_DOUBLES;
+    const bool staged32 = R.c1 >= R.c0 && R.c1 - R.c0 + 1 <= LDS_FLOATS;
+    double *lds64 = sh.lds;
+    float *lds32 = reinterpret_cast<float *>(sh.lds);
+    auto nop = [](int32_t, auto) {};
+    // carry the recurrence vectors of untouched rows into the write buffers
+    auto carry = [&](bool cr, bool cw, bool cs) {
+        for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) {
+            if (mixed) {
+                if (cr) D.r32[wr * n + i] = D.r32[rd * n + i];
+                if (cw) D.w32[wr * n + i] = D.w32[rd * n + i];
+                if (cs) D.s32[wr * n + i] = D.s32[rd * n + i];
+            } else {
+                if (cr) D.r[wr * n + i] = D.r[rd * n + i];
+                if (cw) D.w[wr * n + i] = D.w[rd * n + i];
+                if (cs) D.s[wr * n + i] = D.s[rd * n + i];
+            }
+        }
+    };
+
+    switch (c.state) {
+    case ST_PREP:
+        for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK)
+            x[i] = (D.guess == CGP_GUESS_EXTRAP) ? 2.0 * D.prev1[i] - D.prev2[i] : 0.0;
+        break;
+    case ST_PICK:
+        for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) x[i] = D.prev1[i];
+        break;
+    case ST_ZEROX:
+        for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) x[i] = 0.0;
+        break;
+    case ST_FOLD:
+        for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) {
+            x[i] += static_cast<double>(D.c32[i]);
+            D.c32[i] = 0.0f;
+        }
+        carry(false, false, true);   // RES recomputes r and START rebuilds w; s = K p is kept
+        break;
+    case ST_JUDGE: {
+        const double *p1 = D.prev1;
+        staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return x[j]; },
+                               nop, [&](int32_t i, double y, double) {
+                                   const double r = b[i] - y;
+                                   v[0] += r * r;
+                                   v[2] += b[i] * b[i];
+                               });
+        staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return p1[j]; },
+                               nop, [&](int32_t i, double y, double) {
+                                   const double r = b[i] - y;
+                                   v[1] += r * r;
+                               });
+        break;
+    }
+    case ST_RES: {
+        const bool first = c.first;
+        if (mixed) {
+            float *r32 = D.r32 + wr * n;
+            float *c32 = D.c32;
+            staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
+                                   [&](int32_t j) { return x[j]; }, nop, [&](int32_t i, double y, double) {
+                                       const double ri = b[i] - y;
+                                       r32[i] = static_cast<float>(ri);
+                                       if (first) c32[i] = 0.0f;
+                                       v[0] += ri * ri;
+                                       if (first) v[1] += b[i] * b[i];
+                                   });
+        } else {
+            double *r = D.r + wr * n;
+            staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
+                                   [&](int32_t j) { return x[j]; }, nop, [&](int32_t i, double y, double) {
+                                       const double ri = b[i] - y;
+                                       r[i] = ri;
+                                       v[0] += ri * ri;
+                                       if (first) v[1] += b[i] * b[i];
+                                   });
+        }
+        if (!first && mixed) carry(false, false, true);   // START keeps the direction: it needs s
+        break;
+    }
+    case ST_START: {
+        const bool keep = !c.restart;
+        if (mixed) {
+            const float *r = D.r32 + rd * n, *s = D.s32 + rd * n, *dv = D.dinv32;
+            float *w = D.w32 + wr * n;
+            staged_product<float>(R, staged32, lanes, D.rowptr, D.col, D.val32, lds32,
+                                  [&](int32_t j) { return dv[j] * r[j]; },
+                                  [&](int32_t j, float u) {
+                                      v[0] += static_cast<double>(r[j]) * static_cast<double>(u);
+                                      if (keep) v[2] += static_cast<double>(u) * static_cast<double>(s[j]);
+                                  },
+                                  [&](int32_t i, float y, float u) {
+                                      w[i] = y;
+                                      v[1] += static_cast<double>(y) * static_cast<double>(u);
+                                  });
+        } else {
+            const double *r = D.r + rd * n, *s = D.s + rd * n, *dv = D.dinv;
+            double *w = D.w + wr * n;
+            staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
+                                   [&](int32_t j) { return dv[j] * r[j]; },
+                                   [&](int32_t j, double u) {
+                                       v[0] += r[j] * u;
+                                       if (keep) v[2] += u * s[j];
+                                   },
+                                   [&](int32_t i, double y, double u) {
+                                       w[i] = y;
+                                       v[1] += y * u;
+                                   });
+        }
+        carry(true, false, keep);
+        break;
+    }
+    case ST_ITER: {
+        const bool rs = c.restart;
+        if (mixed) {
+            const float al = static_cast<float>(c.alpha), be = static_cast<float>(c.beta);
+            const float *r = D.r32 + rd * n, *w = D.w32 + rd * n, *so = D.s32 + rd * n, *dv = D.dinv32;
+            float *rn = D.r32 + wr * n, *wn = D.w32 + wr * n, *sn = D.s32 + wr * n;
+            float *p = D.p32, *cc = D.c32;
+            // u_{i+1} at row j from the stable r_i, w_i, s_{i-1}
+            auto s_new = [&](int32_t j) { return rs ? w[j] : w[j] + be * so[j]; };
+            staged_product<float>(R, staged32, lanes, D.rowptr, D.col, D.val32, lds32,
+                                  [&](int32_t j) { return dv[j] * (r[j] - al * s_new(j)); },
+                                  [&](int32_t j, float u1) {
+                                      const float sj = s_new(j);
+                                      const float u0 = dv[j] * r[j];
+                                      const float pj = rs ? u0 : u0 + be * p[j];
+                                      const float rj = r[j] - al * sj;
+                                      p[j] = pj;
+                                      sn[j] = sj;
+                                      rn[j] = rj;
+                                      cc[j] += al * pj;
+                                      v[0] += static_cast<double>(rj) * static_cast<double>(u1);
+                                      v[2] += static_cast<double>(u1) * static_cast<double>(sj);
+                                      v[3] += static_cast<double>(rj) * static_cast<double>(rj);
+                                  },
+                                  [&](int32_t i, float y, float u1) {
+                                      wn[i] = y;
+                                      v[1] += static_cast<double>(y) * static_cast<double>(u1);
+                                  });
+        } else {
+            const double al = c.alpha, be = c.beta;
+            const double *r = D.r + rd * n, *w = D.w + rd * n, *so = D.s + rd * n, *dv = D.dinv;
+            double *rn = D.r + wr * n, *wn = D.w + wr * n, *sn = D.s + wr * n;
+            double *p = D.p;
+            auto s_new = [&](int32_t j) { return rs ? w[j] : w[j] + be * so[j]; };
+            staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
+                                   [&](int32_t j) { return dv[j] * (r[j] - al * s_new(j)); },
+                                   [&](int32_t j, double u1) {
+                                       const double sj = s_new(j);
+                                       const double u0 = dv[j] * r[j];
+                                       const double pj = rs ? u0 : u0 + be * p[j];
+                                       const double rj = r[j] - al * sj;
+                                       p[j] = pj;
+                                       sn[j] = sj;
+                                       rn[j] = rj;
+                                       x[j] += al * pj;
+                                       v[0] += rj * u1;
+                                       v[2] += u1 * sj;
+                                       v[3] += rj * rj;
+                                   },
+                                   [&](int32_t i, double y, double u1) {
+                                       wn[i] = y;
+                                       v[1] += y * u1;
+                                   });
+        }
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+// ------------------------------------------------------------------ one-row-per-thread iteration
+
+// Values an iteration needs, loaded before the stage is decoded: the sliced-ELL
+// row of the thread's row and r, w, s, D^-1 over the staged halo range.
+template <class T, int H>
+struct IterPrefetch {
+    T hd[H], hr[H], hw[H], hs[H];                // staged entries c0 + tid + h*BLOCK
+    T od, orr, ow, os, op, ox;                   // own row: D^-1, r, w, s, p, c (mixed) or x (fp64)
+    T sv[KMAX];
+    int32_t sc[KMAX];
+    int32_t width;
+};
+
+template <class T>
+__device__ inline const T *vec_of(const InstDesc &D, int which);   // 0 r, 1 w, 2 s, 3 dinv, 4 p
+template <>
+__device__ inline const double *vec_of<double>(const InstDesc &D, int which) {
+    return which == 0 ? D.r : which == 1 ? D.w : which == 2 ? D.s : which == 3 ? D.dinv : D.p;
+}
+template <>
+__device__ inline const float *vec_of<float>(const InstDesc &D, int which) {
+    return which == 0 ? D.r32 : which == 1 ? D.w32 : which == 2 ? D.s32 : which == 3 ? D.dinv32 : D.p32;
+}
+
+template <class T, int H>
+__device__ inline void iter_prefetch(IterPrefetch<T, H> &f, const InstDesc &D, const RowRange &R, int rd) {
+    const int64_t n = D.n;
+    const T *r = vec_of<T>(D, 0) + rd * n, *w = vec_of<T>(D, 1) + rd * n, *s = vec_of<T>(D, 2) + rd * n;
+    const T *dv = vec_of<T>(D, 3), *p = vec_of<T>(D, 4);
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int32_t j = R.c0 + threadIdx.x + h * BLOCK;
+        if (j <= R.c1) {
+            f.hd[h] = dv[j];
+            f.hr[h] = r[j];
+            f.hw[h] = w[j];
+            f.hs[h] = s[j];
+        }
+    }
+    const int32_t i = R.r0 + threadIdx.x;
+    f.width = 0;
+    if (i < R.r1) {
+        f.od = dv[i];
+        f.orr = r[i];
+        f.ow = w[i];
+        f.os = s[i];
+        f.op = p[i];
+        if constexpr (sizeof(T) == 4)
+            f.ox = D.c32[i];
+        else
+            f.ox = D.x[i];
+        const int32_t sl = i >> 6;
+        const int32_t base = D.sell_ptr[sl] + (i & 63);
+        f.width = (D.sell_ptr[sl + 1] - D.sell_ptr[sl]) >> 6;
+        const T *sv = sizeof(T) == 4 ? reinterpret_cast<const T *>(D.sell_val32) : reinterpret_cast<const T *>(D.sell_val);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k < f.width) {
+                f.sv[k] = sv[base + 64 * k];
+                f.sc[k] = D.sell_col[base + 64 * k];
+            }
+        }
+    }
+}
+
+// one CG iteration for the workgroup's rows (at most BLOCK of them) from prefetched values
+template <class T, int H>
+__device__ inline void iter_fast(const IterPrefetch<T, H> &f, const Ctl &c, const InstDesc &D, const RowRange &R,
+                                 int wr, T *lds, double (&v)[NPART]) {
+    const int64_t n = D.n;
+    const T al = static_cast<T>(c.alpha), be = static_cast<T>(c.beta);
+    const bool rs = c.restart;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int32_t j = R.c0 + threadIdx.x + h * BLOCK;
+        if (j <= R.c1) {
+            const T sj = rs ? f.hw[h] : f.hw[h] + be * f.hs[h];
+            lds[j - R.c0] = f.hd[h] * (f.hr[h] - al * sj);
+        }
+    }
+    __syncthreads();
+    const int32_t i = R.r0 + threadIdx.x;
+    if (i < R.r1) {
+        const T sj = rs ? f.ow : f.ow + be * f.os;
+        const T rj = f.orr - al * sj;
+        const T u1 = lds[i - R.c0];
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < f.width) acc += f.sv[k] * lds[f.sc[k] - R.c0];
+        const T u0 = f.od * f.orr;
+        const T pj = rs ? u0 : u0 + be * f.op;
+        T *rn = const_cast<T *>(vec_of<T>(D, 0)) + wr * n;
+        T *wn = const_cast<T *>(vec_of<T>(D, 1)) + wr * n;
+        T *sn = const_cast<T *>(vec_of<T>(D, 2)) + wr * n;
+        T *p = const_cast<T *>(vec_of<T>(D, 4));
+        p[i] = pj;
+        sn[i] = sj;
+        rn[i] = rj;
+        wn[i] = acc;
+        if constexpr (sizeof(T) == 4)
+            D.c32[i] = f.ox + al * pj;
+        else
+            D.x[i] = f.ox + al * pj;
+        const double r64 = static_cast<double>(rj), u64 = static_cast<double>(u1);
+        v[0] += r64 * u64;
+        v[1] += static_cast<double>(acc) * u64;
+        v[2] += u64 * static_cast<double>(sj);
+        v[3] += r64 * r64;
+    }
+}
+
+__device__ inline void write_stats(const Ctl &c, const SolveParams &prm, int idx) {
+    cgp_solve_stats o;
+    o.iters = c.it;
+    o.refinements = c.refinements;
+    o.status = c.status;
+    o.guess_used = c.guess_used;
+    o.rel_res = c.rel_res;
+    o.rel_res_guess = c.rel_res_guess;
+    prm.stats[idx] = o;
+}
+
+// sums of an instance's per-workgroup partials by one wavefront (fixed order)
+__device__ inline void wave_reduce_partials(const double *part, int nblk, double (&S)[NPART]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < NPART; ++s) S[s] = 0.0;
+    for (int j = lane; j < nblk; j += 64) {
+#pragma unroll
+        for (int s = 0; s < NPART; ++s) S[s] += part[s * nblk + j];
+    }
+#pragma unroll
+    for (int s = 0; s < NPART; ++s) S[s] = wave_sum(S[s]);
+}
+
+// The common transition, an iteration followed by another one, kept short and
+// inline; every other case goes through transition().  Same arithmetic.
+__device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolveParams &prm, int guess) {
+    if (prev.state == ST_ITER) {
+        const double g = S[0], dl = S[1], sg = S[2], rr = S[3];
+        const double rn = sqrt(rr);
+        const bool mixed = prm.precision == CGP_FP32_IR;
+        const bool go_on = isfinite(rr) && isfinite(g) && !(rn <= prm.tol * prev.bnorm) &&
+                           prev.it + 1 < prm.max_iter && !(mixed && rn <= prm.delta * prev.rmax);
+        if (go_on) {
+            Ctl c = prev;
+            ++c.it;
+            c.pap = c.gamma / c.alpha;
+            c.beta = g / c.gamma;
+            const double denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap;
+            if (denom > 0.0 && isfinite(denom)) {
+                c.alpha = g / denom;
+                c.gamma = g;
+                c.restart = 0;
+                return c;
+            }
+        }
+    }
+    return transition(prev, S, prm, guess);
+}
+
+// ------------------------------------------------------------------ driver 1: one stage per launch
+
+template <class T, int H>
+__global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ insts,
+                                                   const int32_t *__restrict__ block_inst,
+                                                   const RowRange *__restrict__ ranges,
+                                                   const SolveParams *__restrict__ prm_dev, int par,
+                                                   int32_t *done_count, int32_t *host_flag) {
+    __shared__ Shared sh;
+    const int inst = block_inst[blockIdx.x];
+    const InstDesc D = insts[inst];
+    const int lb = blockIdx.x - D.blk0;
+    const RowRange R = ranges[blockIdx.x];
+    const int rd = par ^ 1;
+    const bool fast = D.fast && R.r1 - R.r0 <= BLOCK && R.c1 >= R.c0 && R.c1 - R.c0 + 1 <= H * BLOCK;
+    // speculative loads for an iteration, in flight while the state is decoded
+    IterPrefetch<T, H> f;
+    if (fast) iter_prefetch<T, H>(f, D, R, rd);
+    // decode the stage: wavefront 0 reduces the previous stage's partials and
+    // applies the transition; the other wavefronts wait at the barrier
+    if (threadIdx.x < 64) {
+        const SolveParams prm = *prm_dev;
+        const Ctl prev = D.ctl[rd];
+        Ctl c = prev;
+        if (prev.state != ST_DONE) {
+            double S[NPART];
+            wave_reduce_partials(D.partials + static_cast<size_t>(rd) * NPART * D.nblk, D.nblk, S);
+            if (threadIdx.x == 0) c = next_state(prev, S, prm, D.guess);
+        }
+        if (threadIdx.x == 0) {
+            sh.ctl = c;
+            if (lb == 0) {
+                D.ctl[par] = c;   // carried forward every launch, DONE included
+                if (c.state == ST_DONE && prev.state != ST_DONE) {
+                    write_stats(c, prm, D.stats_index);
+                    if (atomicAdd(done_count, 1) == prm.n_inst - 1)
+                        __hip_atomic_store(host_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const Ctl c = sh.ctl;
+    if (c.state == ST_DONE) return;
+    double v[NPART] = {0.0, 0.0, 0.0, 0.0};
+    if (fast && c.state == ST_ITER) {
+        iter_fast<T, H>(f, c, D, R, par, reinterpret_cast<T *>(sh.lds), v);
+    } else {
+        const SolveParams prm = *prm_dev;
+        stage_work(c, D, R, prm, sh, par, v);
+    }
+    block_sums(v, sh.red, sh.sums);
+    if (threadIdx.x < NPART) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
+        sh.sums[threadIdx.x];
+}
+
+__global__ void k_cg_boot(InstDesc *insts, int n_inst, const SolveParams prm, SolveParams *prm_dev,
+                          int32_t *done_count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *prm_dev = prm;
+        *done_count = 0;
+    }
+    if (i < n_inst) {
+        Ctl c{};
+        c.state = ST_BOOT;
+        insts[i].ctl[1] = c;   // read by the first launch (par = 0)
+    }
+}
+
+// ------------------------------------------------------------------ driver 2: persistent launch
+
+// Grid barrier (arrive counter + generation) with a bounded wait: past `timeout`
+// ticks of the constant-rate clock the workgroup raises the abort flag and
+// every waiter leaves once it sees it.  Returns false when aborted.
+__device__ inline bool grid_barrier(GridSync *gs, uint32_t nblocks, uint32_t &my_gen, uint64_t timeout, int *s_ok) {
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
@@ -122,477 +742,62 @@ __device__ inline bool grid_barrier(GridSync *gs, uint32_t nblocks, uint32_t &my
     return *s_ok != 0;
 }
 
-// ------------------------------------------------------------------ row kernels of the stages
-
-struct Rows {
-    int32_t r0, r1;       // rows of this workgroup
-    int32_t c0, c1;       // column range [c0, c1] touched by those rows
-    bool staged;          // gathers go through LDS
-};
-
-// y_i = sum_k val[k] * src(col[k]) for the workgroup's rows, `lanes` threads per
-// row; calls emit(i, y_i) once per row (from the row's first lane).
-template <class V, class Src, class Emit>
-__device__ inline void spmv_rows(const Rows &R, int lanes, const int32_t *__restrict__ rowptr,
-                                 const int32_t *__restrict__ col, const V *__restrict__ val, V *lds,
-                                 Src src, Emit emit) {
-    if (R.staged) {
-        for (int32_t j = R.c0 + threadIdx.x; j <= R.c1; j += BLOCK) lds[j - R.c0] = src(j);
-        __syncthreads();
-    }
-    const int per_pass = BLOCK / lanes;
-    const int sub = threadIdx.x % lanes;
-    for (int32_t base = R.r0; base < R.r1; base += per_pass) {
-        const int32_t i = base + threadIdx.x / lanes;
-        V acc = V(0);
-        if (i < R.r1) {
-            const int32_t k1 = rowptr[i + 1];
-            if (R.staged) {
-                for (int32_t k = rowptr[i] + sub; k < k1; k += lanes) acc += val[k] * lds[col[k] - R.c0];
-            } else {
-                for (int32_t k = rowptr[i] + sub; k < k1; k += lanes) acc += val[k] * src(col[k]);
-            }
-        }
-        for (int m = lanes >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-        if (i < R.r1 && sub == 0) emit(i, acc);
-    }
-    if (R.staged) __syncthreads();   // LDS is reused by the next product
-}
-
-// ------------------------------------------------------------------ the persistent kernel
-
-__global__ __launch_bounds__(BLOCK) void k_pcg(const InstDesc *__restrict__ insts,
-                                               const int32_t *__restrict__ block_inst, SolveParams prm,
-                                               GridSync *gs, int32_t *done_at, uint64_t timeout) {
-    __shared__ double lds_raw[LDS_DOUBLES];
-    __shared__ double red[NWAVE][NPART];
-    __shared__ double sums[NPART];
-    __shared__ Ctl ctl;
-    __shared__ int s_ok, s_cmin, s_cmax, s_exit;
-
+__global__ __launch_bounds__(BLOCK) void k_cg_persistent(const InstDesc *__restrict__ insts,
+                                                         const int32_t *__restrict__ block_inst,
+                                                         const RowRange *__restrict__ ranges, SolveParams prm,
+                                                         GridSync *gs, int32_t *done_at, uint64_t timeout) {
+    __shared__ Shared sh;
+    __shared__ int s_ok, s_exit;
     const int inst = block_inst[blockIdx.x];
-    const InstDesc D = insts[inst];
+    const InstDesc &D = insts[inst];
     const int lb = blockIdx.x - D.blk0;
-    const int32_t chunk = (D.n + D.nblk - 1) / D.nblk;
-    Rows R;
-    R.r0 = min(D.n, lb * chunk);
-    R.r1 = min(D.n, R.r0 + chunk);
-    const bool mixed = prm.precision == CGP_FP32_IR;
-    const int lanes = D.lanes;
-
-    // column range of the workgroup's rows (columns are sorted within a row)
-    if (threadIdx.x == 0) {
-        s_cmin = INT32_MAX;
-        s_cmax = -1;
-    }
-    __syncthreads();
-    {
-        int32_t lo = INT32_MAX, hi = -1;
-        for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) {
-            const int32_t k0 = D.rowptr[i], k1 = D.rowptr[i + 1];
-            if (k1 > k0) {
-                lo = min(lo, D.col[k0]);
-                hi = max(hi, D.col[k1 - 1]);
-            }
-        }
-        if (hi >= 0) {
-            atomicMin(&s_cmin, lo);
-            atomicMax(&s_cmax, hi);
-        }
-    }
-    __syncthreads();
-    R.c0 = s_cmin;
-    R.c1 = s_cmax;
-    const int cap = mixed ? LDS_FLOATS : LDS_DOUBLES;
-    R.staged = (R.c1 >= R.c0) && (R.c1 - R.c0 + 1 <= cap);
-    double *lds64 = lds_raw;
-    float *lds32 = reinterpret_cast<float *>(lds_raw);
-
+    const RowRange R = ranges[blockIdx.x];
     uint32_t my_gen = 0;
     if (threadIdx.x == 0) {
         my_gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ctl.it = 0;
-        ctl.refinements = 0;
-        ctl.status = CGP_SOLVE_OK;
-        ctl.par = 0;
-        ctl.done = 0;
-        ctl.rho = ctl.alpha = ctl.beta = 0.0;
-        ctl.bnorm = ctl.rmax = 0.0;
-        ctl.rel_res = ctl.rel_res_guess = 0.0;
-        ctl.guess_used = D.guess;
-        if (D.guess == CGP_GUESS_LEARNED)
-            ctl.state = ST_JUDGE;
-        else if (D.guess == CGP_GUESS_GIVEN)
-            ctl.state = mixed ? MX_INIT : ST_INIT;
-        else
-            ctl.state = ST_PREP;
+        Ctl c{};
+        c.state = ST_BOOT;
+        sh.ctl = transition(c, sh.sums, prm, D.guess);
     }
     __syncthreads();
-
-    const double *__restrict__ b = D.b;
-    double *__restrict__ x = D.x;
-    const double *__restrict__ dinv = D.dinv;
-    const float *__restrict__ dinv32 = D.dinv32;
-
     for (int32_t stage = 0;; ++stage) {
         const int par = stage & 1;
         double *part = D.partials + static_cast<size_t>(par) * NPART * D.nblk;
+        const Ctl c = sh.ctl;
         double v[NPART] = {0.0, 0.0, 0.0, 0.0};
-        const int32_t st = ctl.state;
-        const double alpha = ctl.alpha, beta = ctl.beta;
-        double *pold = ctl.par ? D.p1 : D.p0;
-        double *pnew = ctl.par ? D.p0 : D.p1;
-        float *pold32 = ctl.par ? D.p32b : D.p32a;
-        float *pnew32 = ctl.par ? D.p32a : D.p32b;
-
-        // ---------------------------------------------------------- row work
-        switch (st) {
-        case ST_PREP:
-            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK)
-                x[i] = (D.guess == CGP_GUESS_EXTRAP) ? 2.0 * D.prev1[i] - D.prev2[i] : 0.0;
-            break;
-        case ST_JUDGE: {
-            // |b - K x|^2 (network guess) in v[0], |b - K prev1|^2 in v[1], |b|^2 in v[2]
-            spmv_rows<double>(R, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return x[j]; },
-                              [&](int32_t i, double y) {
-                                  const double r = b[i] - y;
-                                  v[0] += r * r;
-                                  v[2] += b[i] * b[i];
-                              });
-            const double *p1v = D.prev1;
-            spmv_rows<double>(R, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return p1v[j]; },
-                              [&](int32_t i, double y) {
-                                  const double r = b[i] - y;
-                                  v[1] += r * r;
-                              });
-            break;
-        }
-        case ST_PICK:
-            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) x[i] = D.prev1[i];
-            break;
-        case ST_INIT:
-        case ST_VERIFY: {
-            double *r = D.r, *z = D.z;
-            const bool init = st == ST_INIT;
-            spmv_rows<double>(R, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return x[j]; },
-                              [&](int32_t i, double y) {
-                                  const double ri = b[i] - y;
-                                  const double zi = dinv[i] * ri;
-                                  r[i] = ri;
-                                  z[i] = zi;
-                                  pold[i] = 0.0;
-                                  v[0] += ri * ri;
-                                  v[1] += ri * zi;
-                                  if (init) v[2] += b[i] * b[i];
-                              });
-            break;
-        }
-        case ST_A: {
-            const double *z = D.z;
-            double *q = D.q;
-            const double *po = pold;
-            spmv_rows<double>(R, lanes, D.rowptr, D.col, D.val, lds64,
-                              [&](int32_t j) { return z[j] + beta * po[j]; },
-                              [&](int32_t i, double y) {
-                                  q[i] = y;
-                                  v[0] += (z[i] + beta * po[i]) * y;
-                              });
-            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) pnew[i] = z[i] + beta * po[i];
-            break;
-        }
-        case ST_B: {
-            double *r = D.r, *z = D.z;
-            const double *q = D.q;
-            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) {
-                x[i] += alpha * pnew[i];
-                const double ri = r[i] - alpha * q[i];
-                const double zi = dinv[i] * ri;
-                r[i] = ri;
-                z[i] = zi;
-                v[0] += ri * ri;
-                v[1] += ri * zi;
-            }
-            break;
-        }
-        case MX_INIT:
-        case MX_RES: {
-            float *r32 = D.r32, *z32 = D.z32, *c32 = D.c32;
-            const bool init = st == MX_INIT;
-            spmv_rows<double>(R, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return x[j]; },
-                              [&](int32_t i, double y) {
-                                  const double ri = b[i] - y;
-                                  const float r32i = static_cast<float>(ri);
-                                  const float z32i = dinv32[i] * r32i;
-                                  r32[i] = r32i;
-                                  z32[i] = z32i;
-                                  v[0] += ri * ri;
-                                  v[1] += static_cast<double>(r32i) * static_cast<double>(z32i);
-                                  if (init) {
-                                      c32[i] = 0.0f;
-                                      pold32[i] = 0.0f;
-                                      v[2] += b[i] * b[i];
-                                  }
-                              });
-            break;
-        }
-        case MX_A: {
-            const float *z32 = D.z32;
-            float *q32 = D.q32;
-            const float *po = pold32;
-            const float bf = static_cast<float>(beta);
-            spmv_rows<float>(R, lanes, D.rowptr, D.col, D.val32, lds32,
-                             [&](int32_t j) { return z32[j] + bf * po[j]; },
-                             [&](int32_t i, float y) {
-                                 q32[i] = y;
-                                 const float pi = z32[i] + bf * po[i];
-                                 v[0] += static_cast<double>(pi) * static_cast<double>(y);
-                             });
-            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) pnew32[i] = z32[i] + bf * po[i];
-            break;
-        }
-        case MX_B: {
-            float *r32 = D.r32, *z32 = D.z32, *c32 = D.c32;
-            const float *q32 = D.q32;
-            const float af = static_cast<float>(alpha);
-            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) {
-                c32[i] += af * pnew32[i];
-                const float ri = r32[i] - af * q32[i];
-                const float zi = dinv32[i] * ri;
-                r32[i] = ri;
-                z32[i] = zi;
-                v[0] += static_cast<double>(ri) * static_cast<double>(ri);
-                v[1] += static_cast<double>(ri) * static_cast<double>(zi);
-            }
-            break;
-        }
-        case MX_FOLD: {
-            float *c32 = D.c32;
-            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) {
-                x[i] += static_cast<double>(c32[i]);
-                c32[i] = 0.0f;
-            }
-            break;
-        }
-        case ST_ZEROX:
-            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) x[i] = 0.0;
-            break;
-        default:
-            break;
-        }
-
-        // ---------------------------------------------------------- partial sums of this workgroup
-        block_sums(v, red, sums);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int s = 0; s < NPART; ++s) part[s * D.nblk + lb] = sums[s];
-        }
-
+        if (c.state != ST_DONE) stage_work(c, D, R, prm, sh, par, v);
+        block_sums(v, sh.red, sh.sums);
+        if (threadIdx.x < NPART) part[threadIdx.x * D.nblk + lb] = sh.sums[threadIdx.x];
         if (!grid_barrier(gs, gridDim.x, my_gen, timeout, &s_ok)) {
-            if (lb == 0 && threadIdx.x == 0 && !ctl.done) {
-                cgp_solve_stats o;
-                o.iters = ctl.it;
-                o.refinements = ctl.refinements;
-                o.status = CGP_SOLVE_ABORTED;
-                o.guess_used = ctl.guess_used;
-                o.rel_res = ctl.rel_res;
-                o.rel_res_guess = ctl.rel_res_guess;
-                *D.stats = o;
+            if (lb == 0 && threadIdx.x == 0 && c.state != ST_DONE) {
+                Ctl a = c;
+                a.status = CGP_SOLVE_ABORTED;
+                write_stats(a, prm, D.stats_index);
             }
             return;
         }
-
-        // ---------------------------------------------------------- instance decision
-        if (!ctl.done) {
-            double t[NPART] = {0.0, 0.0, 0.0, 0.0};
-            for (int j = threadIdx.x; j < D.nblk; j += BLOCK) {
-#pragma unroll
-                for (int s = 0; s < NPART; ++s) t[s] += part[s * D.nblk + j];
-            }
-            block_sums(t, red, sums);
+        if (c.state != ST_DONE) {
+            reduce_partials(part, D.nblk, sh.red, sh.sums);
             if (threadIdx.x == 0) {
-                Ctl &c = ctl;
-                const double tol = prm.tol;
-                auto finish = [&](int status) {
-                    c.status = status;
-                    c.done = 1;
-                    c.state = ST_DONE;
-                };
-                switch (st) {
-                case ST_PREP:
-                    c.state = mixed ? MX_INIT : ST_INIT;
-                    break;
-                case ST_JUDGE: {
-                    c.bnorm = sqrt(sums[2]);
-                    const double rl = sums[0], rp = sums[1];
-                    const double bn = c.bnorm > 0.0 ? c.bnorm : 1.0;
-                    if (rl <= rp && isfinite(rl)) {   // NaN/Inf network output is rejected
-                        c.guess_used = CGP_GUESS_LEARNED;
-                        c.rel_res_guess = sqrt(rl) / bn;
-                        c.state = mixed ? MX_INIT : ST_INIT;
-                    } else {
-                        c.guess_used = CGP_GUESS_GIVEN;
-                        c.rel_res_guess = sqrt(rp) / bn;
-                        c.state = ST_PICK;
-                    }
-                    break;
-                }
-                case ST_PICK:
-                    c.state = mixed ? MX_INIT : ST_INIT;
-                    break;
-                case ST_INIT:
-                case MX_INIT: {
-                    const double rr = sums[0], rz = sums[1], bb = sums[2];
-                    c.bnorm = sqrt(bb);
-                    if (bb == 0.0) {
-                        c.state = ST_ZEROX;
-                        break;
-                    }
-                    if (!isfinite(rr) || !isfinite(bb)) {
-                        finish(CGP_SOLVE_BREAKDOWN);
-                        break;
-                    }
-                    const double rn = sqrt(rr);
-                    c.rel_res = rn / c.bnorm;
-                    if (D.guess != CGP_GUESS_LEARNED) c.rel_res_guess = c.rel_res;
-                    if (rn <= tol * c.bnorm) {
-                        finish(CGP_SOLVE_OK);
-                        break;
-                    }
-                    c.rmax = rn;
-                    c.rho = rz;
-                    c.beta = 0.0;
-                    c.state = (st == ST_INIT) ? ST_A : MX_A;
-                    break;
-                }
-                case ST_A:
-                case MX_A: {
-                    const double pq = sums[0];
-                    if (!(pq > 0.0) || !isfinite(pq)) {
-                        finish(CGP_SOLVE_BREAKDOWN);
-                        break;
-                    }
-                    c.alpha = c.rho / pq;
-                    c.state = (st == ST_A) ? ST_B : MX_B;
-                    break;
-                }
-                case ST_B: {
-                    const double rr = sums[0], rz = sums[1];
-                    ++c.it;
-                    if (!isfinite(rr)) {
-                        finish(CGP_SOLVE_BREAKDOWN);
-                        break;
-                    }
-                    if (sqrt(rr) <= tol * c.bnorm || c.it >= prm.max_iter) {
-                        c.state = ST_VERIFY;
-                        c.par ^= 1;   // p_new becomes p_old (zeroed by VERIFY)
-                        break;
-                    }
-                    c.beta = rz / c.rho;
-                    c.rho = rz;
-                    c.par ^= 1;
-                    c.state = ST_A;
-                    break;
-                }
-                case ST_VERIFY: {
-                    const double rr = sums[0], rz = sums[1];
-                    const double rn = sqrt(rr);
-                    c.rel_res = rn / c.bnorm;
-                    if (!isfinite(rr)) {
-                        finish(CGP_SOLVE_BREAKDOWN);
-                        break;
-                    }
-                    if (rn <= tol * c.bnorm) {
-                        finish(CGP_SOLVE_OK);
-                        break;
-                    }
-                    if (c.it >= prm.max_iter) {
-                        finish(CGP_SOLVE_NOCONV);
-                        break;
-                    }
-                    c.rho = rz;   // restart from the current iterate
-                    c.beta = 0.0;
-                    c.state = ST_A;
-                    break;
-                }
-                case MX_B: {
-                    const double rr = sums[0], rz = sums[1];
-                    ++c.it;
-                    const double rn = sqrt(rr);
-                    if (!isfinite(rr)) {
-                        finish(CGP_SOLVE_BREAKDOWN);
-                        break;
-                    }
-                    if (rn <= prm.delta * c.rmax || rn <= tol * c.bnorm || c.it >= prm.max_iter) {
-                        c.state = MX_FOLD;
-                        break;
-                    }
-                    c.beta = rz / c.rho;
-                    c.rho = rz;
-                    c.par ^= 1;
-                    c.state = MX_A;
-                    break;
-                }
-                case MX_FOLD:
-                    c.state = MX_RES;
-                    break;
-                case MX_RES: {
-                    const double rr = sums[0], rz = sums[1];
-                    ++c.refinements;
-                    const double rn = sqrt(rr);
-                    c.rel_res = rn / c.bnorm;
-                    if (!isfinite(rr)) {
-                        finish(CGP_SOLVE_BREAKDOWN);
-                        break;
-                    }
-                    if (rn <= tol * c.bnorm) {
-                        finish(CGP_SOLVE_OK);
-                        break;
-                    }
-                    if (c.it >= prm.max_iter) {
-                        finish(CGP_SOLVE_NOCONV);
-                        break;
-                    }
-                    c.rmax = rn;
-                    c.beta = rz / c.rho;   // keep the search direction
-                    c.rho = rz;
-                    c.par ^= 1;
-                    c.state = MX_A;
-                    break;
-                }
-                case ST_ZEROX:
-                    c.rel_res = 0.0;
-                    c.rel_res_guess = 0.0;
-                    finish(CGP_SOLVE_OK);
-                    break;
-                default:
-                    break;
-                }
-                if (c.done && lb == 0) {
-                    cgp_solve_stats o;
-                    o.iters = c.it;
-                    o.refinements = c.refinements;
-                    o.status = c.status;
-                    o.guess_used = c.guess_used;
-                    o.rel_res = c.rel_res;
-                    o.rel_res_guess = c.rel_res_guess;
-                    *D.stats = o;
+                sh.ctl = transition(c, sh.sums, prm, D.guess);
+                if (sh.ctl.state == ST_DONE && lb == 0) {
+                    write_stats(sh.ctl, prm, D.stats_index);
                     done_at[inst] = stage;
                 }
             }
         }
-        // ---------------------------------------------------------- global exit: every instance
-        // finished at an earlier stage (values written after this barrier are not counted)
+        // leave once every instance finished at an earlier stage (values written
+        // after this barrier are not counted, so all workgroups agree)
         if (threadIdx.x == 0) s_exit = 1;
         __syncthreads();
         for (int i = threadIdx.x; i < prm.n_inst; i += BLOCK)
-            if (__hip_atomic_load(&done_at[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > stage - 1)
-                s_exit = 0;
+            if (__hip_atomic_load(&done_at[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > stage - 1) s_exit = 0;
         __syncthreads();
         if (s_exit) return;
     }
 }
 
-__global__ void k_pcg_setup(GridSync *gs, int32_t *done_at, int n_inst) {
+__global__ void k_persistent_setup(GridSync *gs, int32_t *done_at, int n_inst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         gs->arrive = 0u;
@@ -601,30 +806,93 @@ __global__ void k_pcg_setup(GridSync *gs, int32_t *done_at, int n_inst) {
     if (i < n_inst) done_at[i] = INT32_MAX;
 }
 
+// ------------------------------------------------------------------ plan set-up
+
+// rows [r0, r1) of each workgroup and the column range they touch
+__global__ void k_ranges(const InstDesc *insts, const int32_t *block_inst, int grid, RowRange *ranges) {
+    const int blk = blockIdx.x;
+    if (blk >= grid) return;
+    __shared__ int s_lo, s_hi;
+    const InstDesc &D = insts[block_inst[blk]];
+    const int lb = blk - D.blk0;
+    const int32_t r0 = min(D.n, lb * D.chunk), r1 = min(D.n, r0 + D.chunk);
+    if (threadIdx.x == 0) {
+        s_lo = INT32_MAX;
+        s_hi = -1;
+    }
+    __syncthreads();
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const int32_t k0 = D.rowptr[i], k1 = D.rowptr[i + 1];
+        if (k1 > k0) {
+            lo = min(lo, D.col[k0]);
+            hi = max(hi, D.col[k1 - 1]);
+        }
+    }
+    if (hi >= 0) {
+        atomicMin(&s_lo, lo);
+        atomicMax(&s_hi, hi);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        RowRange R;
+        R.r0 = r0;
+        R.r1 = r1;
+        R.c0 = s_lo;
+        R.c1 = s_hi;
+        ranges[blk] = R;
+    }
+}
+
 }  // namespace
 
 int pcg_block_size() { return BLOCK; }
-size_t pcg_lds_bytes() { return sizeof(double) * LDS_DOUBLES; }
 
 int pcg_max_blocks_per_cu() {
-    int nb = 0;
-    CGP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pcg, BLOCK, 0));
-    return nb;
+    int a = 0;
+    CGP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_cg_persistent, BLOCK, 0));
+    return a;
 }
 
-void launch_pcg(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst, int grid,
-                int block, const SolveParams &prm, GridSync *d_sync, int32_t *d_done_at, size_t) {
-    (void)block;
-    int dev = 0;
-    CGP_HIP(hipGetDevice(&dev));
-    int khz = 0;
-    CGP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-    if (khz <= 0) khz = 100000;
-    const uint64_t timeout = static_cast<uint64_t>(khz) * 1000ull * 4ull;   // 4 s per barrier wait
-    hipLaunchKernelGGL(k_pcg_setup, dim3((n_inst + 255) / 256), dim3(256), 0, s, d_sync, d_done_at, n_inst);
+int pcg_sell_max_width() { return KMAX; }
+
+void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_block_inst, int grid, RowRange *d_ranges) {
+    hipLaunchKernelGGL(k_ranges, dim3(grid), dim3(256), 0, s, d_insts, d_block_inst, grid, d_ranges);
     CGP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_pcg, dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, prm, d_sync, d_done_at,
-                       timeout);
+}
+
+void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
+                    int32_t *d_done) {
+    hipLaunchKernelGGL(k_cg_boot, dim3((n_inst + 255) / 256), dim3(256), 0, s, d_insts, n_inst, prm, d_prm, d_done);
+    CGP_HIP(hipGetLastError());
+}
+
+void launch_cg_step(hipStream_t s, bool mixed, int halo, const InstDesc *d_insts, const int32_t *d_block_inst,
+                    const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par, int32_t *d_done,
+                    int32_t *d_host_flag) {
+    // staged entries per thread: 4 covers workgroups whose column range spans <= 2048 rows
+    const bool small = halo <= 4 * BLOCK;
+#define CGP_STEP(T, H)                                                                                             \
+    hipLaunchKernelGGL((k_cg_step<T, H>), dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, d_ranges, d_prm, par, \
+                       d_done, d_host_flag)
+    if (mixed) {
+        if (small) CGP_STEP(float, 4);
+        else CGP_STEP(float, HMAX);
+    } else {
+        if (small) CGP_STEP(double, 4);
+        else CGP_STEP(double, HMAX);
+    }
+#undef CGP_STEP
+    CGP_HIP(hipGetLastError());
+}
+
+void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
+                          const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,
+                          int32_t *d_done_at, uint64_t timeout_ticks) {
+    hipLaunchKernelGGL(k_persistent_setup, dim3((n_inst + 255) / 256), dim3(256), 0, s, d_sync, d_done_at, n_inst);
+    CGP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cg_persistent, dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, d_ranges, prm, d_sync,
+                       d_done_at, timeout_ticks);
     CGP_HIP(hipGetLastError());
 }
 

@@ -111,18 +111,6 @@ __global__ __launch_bounds__(TPB) void k_elem_grad(int64_t T, const int32_t *__r
     g[2 * e + 1] = (p0 * (x2 - x1) + p1 * (x0 - x2) + p2 * (x1 - x0)) / d;
 }
 
-__global__ __launch_bounds__(TPB) void k_guess(int64_t n, int guess, double *__restrict__ x,
-                                               const double *__restrict__ p1, const double *__restrict__ p2) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (guess == CGP_GUESS_ZERO)
-        x[i] = 0.0;
-    else if (guess == CGP_GUESS_EXTRAP)
-        x[i] = 2.0 * p1[i] - p2[i];
-    else
-        x[i] = p1[i];
-}
-
 }  // namespace
 
 void launch_restrict(hipStream_t s, const Mesh &m, const double *uf, const double *vf, int kind,
@@ -160,12 +148,6 @@ void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const doub
                            phif, grad_elem);
         CGP_HIP(hipGetLastError());
     }
-}
-
-void launch_guess_prep(hipStream_t s, int guess, int64_t n, double *x, const double *prev1,
-                       const double *prev2) {
-    hipLaunchKernelGGL(k_guess, dim3(blocks_for(n, TPB)), dim3(TPB), 0, s, n, guess, x, prev1, prev2);
-    CGP_HIP(hipGetLastError());
 }
 
 }  // namespace cgp

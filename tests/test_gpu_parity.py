@@ -179,11 +179,15 @@ def _solve(ctx, cgp, handle, b, x0=None, guess=None, precision=0, tol=1e-10, **k
     return phi.cpu().numpy(), st
 
 
+ENGINES = [1, 2]   # CGP_ENGINE_STAGED, CGP_ENGINE_PERSISTENT
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8])
-def test_fp64_solve_matches_direct_and_oracle_pcg(ctx, cgp, c1, lanes):
+def test_fp64_solve_matches_direct_and_oracle_pcg(ctx, cgp, c1, lanes, engine):
     for b in (c1.b_phi, c1.b_p):
         xs = solve.direct(c1.a, b)
-        x, st = _solve(ctx, cgp, c1.handle, b, tol=1e-10, spmv_lanes=lanes)
+        x, st = _solve(ctx, cgp, c1.handle, b, tol=1e-10, spmv_lanes=lanes, engine=engine)
         assert st["status"] == "ok" and st["rel_res"] <= 1e-10
         assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-8
         xo, info = solve.pcg(c1.a, b, tol=1e-10)
@@ -191,48 +195,52 @@ def test_fp64_solve_matches_direct_and_oracle_pcg(ctx, cgp, c1, lanes):
         assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-9
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("lanes", [1, 4])
-def test_mixed_solve_matches_direct(ctx, cgp, c1, lanes):
+def test_mixed_solve_matches_direct(ctx, cgp, c1, lanes, engine):
     for b in (c1.b_phi, c1.b_p):
         xs = solve.direct(c1.a, b)
-        x, st = _solve(ctx, cgp, c1.handle, b, precision=cgp.CGP_FP32_IR, tol=1e-8, spmv_lanes=lanes)
+        x, st = _solve(ctx, cgp, c1.handle, b, precision=cgp.CGP_FP32_IR, tol=1e-8, spmv_lanes=lanes,
+                       engine=engine)
         assert st["status"] == "ok" and st["rel_res"] <= 1e-8 and st["refinements"] >= 1
         assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-6
         _, info = solve.pcg_mixed(c1.a, b, tol=1e-8)
         assert abs(st["iters"] - info["iters"]) <= max(3, info["iters"] // 20), (st, info)
 
 
-def test_guess_modes(ctx, cgp, c1):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_guess_modes(ctx, cgp, c1, engine):
     b = c1.b_phi
     xs = solve.direct(c1.a, b)
     for prec in (cgp.CGP_FP64, cgp.CGP_FP32_IR):
-        _, st = _solve(ctx, cgp, c1.handle, b, x0=xs, precision=prec, tol=1e-8)
+        _, st = _solve(ctx, cgp, c1.handle, b, x0=xs, precision=prec, tol=1e-8, engine=engine)
         assert st["iters"] == 0 and st["status"] == "ok"          # exact guess: nothing to do
         # extrapolation 2 p1 - p2 with p1 = p2 = x* is x*
         n = b.shape[0]
         phi = torch.zeros(n, dtype=torch.float64, device=DEV)
         stats = cgp.stats_buffer(1)
         ctx.poisson_solve([c1.handle], [dt(b)], [phi], stats, prev1=[dt(xs)], prev2=[dt(xs)],
-                          precision=prec, guess=cgp.CGP_GUESS_EXTRAP, tol=1e-8)
+                          precision=prec, guess=cgp.CGP_GUESS_EXTRAP, tol=1e-8, engine=engine)
         st = ctx.solve_check(1, stats)[0]
         assert st["iters"] == 0 and st["rel_res_guess"] <= 1e-8
 
 
-def test_edge_cases(ctx, cgp, c1):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_edge_cases(ctx, cgp, c1, engine):
     n = c1.m.n_nodes
     # zero right-hand side: phi = 0 whatever the guess
-    x, st = _solve(ctx, cgp, c1.handle, np.zeros(n), x0=np.ones(n))
+    x, st = _solve(ctx, cgp, c1.handle, np.zeros(n), x0=np.ones(n), engine=engine)
     assert st["status"] == "ok" and st["iters"] == 0 and not x.any()
     # iteration cap
-    _, st = _solve(ctx, cgp, c1.handle, c1.b_phi, max_iter=1)
+    _, st = _solve(ctx, cgp, c1.handle, c1.b_phi, max_iter=1, engine=engine)
     assert st["status"] == "noconv" and st["iters"] == 1
-    _, st = _solve(ctx, cgp, c1.handle, c1.b_phi, precision=cgp.CGP_FP32_IR, tol=1e-8, max_iter=3)
+    _, st = _solve(ctx, cgp, c1.handle, c1.b_phi, precision=cgp.CGP_FP32_IR, tol=1e-8, max_iter=3, engine=engine)
     assert st["status"] == "noconv"
     # non-finite input
     bad = c1.b_phi.copy()
     bad[100] = np.nan
     for prec in (cgp.CGP_FP64, cgp.CGP_FP32_IR):
-        _, st = _solve(ctx, cgp, c1.handle, bad, precision=prec)
+        _, st = _solve(ctx, cgp, c1.handle, bad, precision=prec, engine=engine)
         assert st["status"] == "breakdown"
     # argument validation: nothing enqueued, error code returned
     with pytest.raises(cgp.CGPError) as e:
@@ -240,16 +248,19 @@ def test_edge_cases(ctx, cgp, c1):
     assert e.value.code == cgp.CGP_E_INVALID
     with pytest.raises(cgp.CGPError):
         _solve(ctx, cgp, c1.handle, c1.b_phi, spmv_lanes=3)
+    with pytest.raises(cgp.CGPError):
+        _solve(ctx, cgp, c1.handle, c1.b_phi, launches_per_graph=3)
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("nx,ny", [(3, 3), (2, 2), (4, 3)])
-def test_degenerate_meshes(ctx, cgp, nx, ny):
+def test_degenerate_meshes(ctx, cgp, nx, ny, engine):
     m = ci.jittered_rect(nx, ny, 9)
     h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 1)
     try:
         a = fem.system_matrix(m.xy, m.tri, m.dirichlet)
         b = np.where(m.dirichlet.astype(bool), 0.0, 1.0)
-        x, st = _solve(ctx, cgp, h, b, tol=1e-12)
+        x, st = _solve(ctx, cgp, h, b, tol=1e-12, engine=engine)
         assert st["status"] == "ok"
         if b.any():
             np.testing.assert_allclose(x, solve.direct(a, b), rtol=1e-10)
@@ -259,14 +270,16 @@ def test_degenerate_meshes(ctx, cgp, nx, ny):
         ctx.mesh_free(h)
 
 
-def test_solves_are_bitwise_reproducible(ctx, cgp, c1):
-    x1, s1 = _solve(ctx, cgp, c1.handle, c1.b_phi)
-    x2, s2 = _solve(ctx, cgp, c1.handle, c1.b_phi)
+@pytest.mark.parametrize("engine", ENGINES)
+def test_solves_are_bitwise_reproducible(ctx, cgp, c1, engine):
+    x1, s1 = _solve(ctx, cgp, c1.handle, c1.b_phi, engine=engine)
+    x2, s2 = _solve(ctx, cgp, c1.handle, c1.b_phi, engine=engine)
     np.testing.assert_array_equal(x1, x2)
     assert s1 == s2
 
 
-def test_batched_instances_match_single_solves(ctx, cgp):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_batched_instances_match_single_solves(ctx, cgp, engine):
     sizes = [(17, 9), (33, 17), (9, 5), (65, 33), (25, 13)]
     steps = [Step(nx, ny, 3000 + i) for i, (nx, ny) in enumerate(sizes)]
     hs = [ctx.mesh_upload(s.m.xy, s.m.tri, s.m.dirichlet, 1) for s in steps]
@@ -275,13 +288,13 @@ def test_batched_instances_match_single_solves(ctx, cgp):
             bs = [dt(s.b_phi) for s in steps]
             xs = [torch.zeros_like(b) for b in bs]
             stats = cgp.stats_buffer(len(steps))
-            ctx.poisson_solve(hs, bs, xs, stats, precision=prec, guess=cgp.CGP_GUESS_ZERO, tol=tol)
+            ctx.poisson_solve(hs, bs, xs, stats, precision=prec, guess=cgp.CGP_GUESS_ZERO, tol=tol, engine=engine)
             sts = ctx.solve_check(len(steps), stats)
             for s, h, x, st in zip(steps, hs, xs, sts):
                 assert st["status"] == "ok" and st["rel_res"] <= tol
                 ref = solve.direct(s.a, s.b_phi)
                 assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) <= bound
-                alone, st1 = _solve(ctx, cgp, h, s.b_phi, precision=prec, tol=tol)
+                alone, st1 = _solve(ctx, cgp, h, s.b_phi, precision=prec, tol=tol, engine=engine)
                 assert abs(st1["iters"] - st["iters"]) <= 2
                 assert np.linalg.norm(x.cpu().numpy() - alone) / np.linalg.norm(ref) <= bound
     finally:
@@ -304,13 +317,16 @@ def test_graph_replay_matches_eager(ctx, cgp, c1):
 
     def step():
         gctx.restrict(h, uf, vf, cgp.CGP_SRC_CURL, 1.0, b)
-        gctx.poisson_solve([h], [b], [phi], stats, precision=cgp.CGP_FP32_IR, guess=cgp.CGP_GUESS_ZERO, tol=1e-8)
+        gctx.poisson_solve([h], [b], [phi], stats, precision=cgp.CGP_FP32_IR, guess=cgp.CGP_GUESS_ZERO, tol=1e-8,
+                           engine=cgp.CGP_ENGINE_PERSISTENT)
         gctx.prolong(h, phi, phif)
         gctx.lorentz_force(h, phif, uf, vf, 0.5, 1.0, fx, fy)
 
     step()
     gctx.sync()
     eager = [t.cpu().numpy().copy() for t in (b, phi, phif, fx, fy)]
+    xs = solve.direct(c1.a, c1.b_phi)
+    assert np.linalg.norm(eager[1] - xs) / np.linalg.norm(xs) <= 1e-6
     gctx.graph_begin()
     step()
     g = gctx.graph_end()
@@ -324,5 +340,11 @@ def test_graph_replay_matches_eager(ctx, cgp, c1):
             np.testing.assert_array_equal(t.cpu().numpy(), e)
         assert gctx.solve_check(1, stats)[0]["status"] == "ok"
     gctx.graph_free(g)
+    # the staged engine refuses capture instead of recording a host-driven loop
+    gctx.graph_begin()
+    with pytest.raises(cgp.CGPError):
+        gctx.poisson_solve([h], [b], [phi], stats, precision=cgp.CGP_FP32_IR, guess=cgp.CGP_GUESS_ZERO, tol=1e-8,
+                           engine=cgp.CGP_ENGINE_STAGED)
+    gctx.graph_free(gctx.graph_end())
     gctx.mesh_free(h)
     gctx.close()
