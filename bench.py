@@ -53,16 +53,24 @@ def parse():
 
 
 def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extrap: bool) -> float:
-    """Algorithmic HBM bytes of one solve (matrix and vectors read/written once per pass)."""
+    """Algorithmic HBM bytes of one solve: every matrix entry (value + int32 column) and
+    every vector element each stage reads or writes, counted once (halo re-reads and
+    padding are not counted).
+
+    fp32 iteration: matrix 8 nnz; reads r, w, s, D^-1, p, c and writes p, s, r, w, c
+    (4 B each): 8 nnz + 44 n.  fp64 iteration: 12 nnz + 88 n.  A refinement (mixed)
+    is FOLD (32 n) + true residual in fp64 (12 nnz + 32 n) + restart of the
+    recurrences in fp32 (8 nnz + 28 n)."""
     if mixed:
-        per_it = 8 * nnz + 52 * n            # fp32 CSR values + int32 cols, fp32 vectors
-        init = 12 * nnz + 4 * n + 16 * n + 20 * n
-        refine = 24 * n + 12 * nnz + 4 * n + 16 * n + 12 * n
-        total = init + iters * per_it + refinements * refine
+        it = 8 * nnz + 44 * n
+        res = 12 * nnz + 32 * n
+        start = 8 * nnz + 28 * n
+        total = res + start + iters * it + refinements * (32 * n + res + start)
     else:
-        per_it = 12 * nnz + 100 * n          # fp64 CSR + int32 cols, fp64 vectors
-        resid = 12 * nnz + 4 * n + 16 * n + 24 * n
-        total = 2 * resid + iters * per_it
+        it = 12 * nnz + 88 * n
+        res = 12 * nnz + 28 * n
+        start = 12 * nnz + 36 * n
+        total = res + start + iters * it + refinements * res
     if extrap:
         total += 24 * n
     return float(total)
@@ -143,11 +151,13 @@ def main():
         for n in steps[:W]:
             step(n, False)
         torch.cuda.synchronize()
+        launches0 = ctx.stage_launches
         t0 = time.perf_counter()
         for n in steps[W:]:
             step(n, True)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        launches = ctx.stage_launches - launches0
         host = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=np.dtype(
             [("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"), ("rel0", "f8")]))
         timed = host[2 * W:]
@@ -165,6 +175,8 @@ def main():
             "solve_ms_mean": float(solve_ms.mean()),
             "solve_share": float(solve_ms.sum() / (1e3 * elapsed)),
             "achieved_GBs": float(nbytes.sum() / (solve_ms.sum() * 1e-3) / 1e9),
+            "stage_launches": int(launches),
+            "kernel_avg_us": float(solve_ms.sum() * 1e3 / max(launches, 1)),
             "bytes_per_solve": float(nbytes.mean()),
             "step0": {k: v.cpu().numpy() for k, v in keep.items()},
         }
@@ -209,7 +221,7 @@ def main():
                          f"sequence, phi and p ({2 * S} solves, mean {np.mean(its):.0f} iterations, "
                          f"{cpu_t:.1f} s)"}
 
-    bpi = (8 * nnz + 52 * nc) if main_form == "B" else (12 * nnz + 100 * nc)
+    bpi = (8 * nnz + 44 * nc) if main_form == "B" else (12 * nnz + 88 * nc)
     out = {
         "metric": METRIC,
         "value": R["solves_per_s"],
@@ -232,7 +244,8 @@ def main():
         "speedup_B_over_A": (res["B"]["solves_per_s"] / res["A"]["solves_per_s"]) if {"A", "B"} <= set(res) else None,
         "roofline": {"bound": "hbm", "achieved": R["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": R["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_pcg (persistent solve)", "bytes_per_iter": bpi},
+                     "kernel": "k_cg_step (one CG stage per launch)", "bytes_per_iter": bpi,
+                     "kernel_avg_us": R["kernel_avg_us"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

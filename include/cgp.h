@@ -204,6 +204,10 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
  * failing instance. */
 cgp_status cgp_solve_check(cgp_ctx ctx, int32_t n_inst, const cgp_solve_stats *d_stats,
                            cgp_solve_stats *h_stats);
+/* Total number of stage kernels the staged engine has enqueued on this context
+ * (including the launches of the last replayed graph that found every instance
+ * already finished); for averaging per-launch time. */
+int64_t cgp_stage_launches(cgp_ctx ctx);
 /* Pick spmv_lanes per mesh by timing the solver's matrix-vector stage on the
  * device (one entry per mesh in h_lanes_out, also remembered by the mesh and
  * used when cgp_solve_opts.spmv_lanes == 0).  Synchronous. */

@@ -75,6 +75,7 @@ _SIGS = {
     "cgp_sync": ([_vp], _i32),
     "cgp_last_error": ([], ctypes.c_char_p),
     "cgp_device_cus": ([_vp], _i32),
+    "cgp_stage_launches": ([_vp], _i64),
     "cgp_mesh_upload": ([_vp, _vp, _i64, _vp, _i64, _vp, _i32, ctypes.POINTER(_i32)], _i32),
     "cgp_mesh_info": ([_vp, _i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                        ctypes.POINTER(_i64)], _i32),
@@ -165,6 +166,10 @@ class Context:
     @property
     def cus(self) -> int:
         return int(load().cgp_device_cus(self.handle))
+
+    @property
+    def stage_launches(self) -> int:
+        return int(load().cgp_stage_launches(self.handle))
 
     # ---------------------------------------------------------------- meshes
     def mesh_upload(self, xy, tri, dirichlet, k_levels: int) -> int:

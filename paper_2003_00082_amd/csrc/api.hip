@@ -64,6 +64,7 @@ struct cgp_ctx_s {
     int32_t *host_flag_dev = nullptr;
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     uint64_t timeout_ticks = 0;
+    int64_t stage_launches = 0;
     bool capturing = false;
 };
 
@@ -215,6 +216,8 @@ cgp_status cgp_sync(cgp_ctx ctx) {
 }
 
 int32_t cgp_device_cus(cgp_ctx ctx) { return ctx ? ctx->cus : 0; }
+
+int64_t cgp_stage_launches(cgp_ctx ctx) { return ctx ? ctx->stage_launches : 0; }
 
 // ------------------------------------------------------------------ meshes
 
@@ -452,11 +455,11 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     d.guess = o.guess;
                     d.stats_index = i;
                     d.chunk = static_cast<int32_t>((m.lv[0].n + nb[i] - 1) / nb[i]);
-                    d.fast = (!persistent && m.max_row <= pcg_sell_max_width()) ? 1 : 0;
-                    d.sell_ptr = m.sell_ptr.p;
-                    d.sell_col = m.sell_col.p;
-                    d.sell_val = m.sell_val.p;
-                    d.sell_val32 = m.sell_val32.p;
+                    d.fast = (!persistent && m.max_row <= pcg_ell_max_width()) ? 1 : 0;
+                    d.ell_w = m.max_row;
+                    d.ell_col = m.ell_col.p;
+                    d.ell_val = m.ell_val.p;
+                    d.ell_val32 = m.ell_val32.p;
                     d.rowptr = m.rowptr.p;
                     d.col = m.col.p;
                     d.val = m.val.p;
@@ -514,7 +517,8 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 // the launch template is recorded on the private stream (the caller's may be the null stream)
                 CGP_HIP(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeRelaxed));
                 for (int l = 0; l < launches; ++l)
-                    launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, plan->d_insts, plan->d_block_inst,
+                    launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
+                                   plan->d_block_inst,
                                    plan->d_ranges, plan->grid, plan->d_prm, l & 1, plan->d_done,
                                    ctx->host_flag_dev);
                 CGP_HIP(hipStreamEndCapture(ctx->aux, &plan->graph));
@@ -549,6 +553,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 if (chunk >= max_chunks) throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
                 CGP_HIP(hipGraphLaunch(plan->exec, ctx->stream));
                 CGP_HIP(hipEventRecord(ctx->chunk_ev[chunk & 1], ctx->stream));
+                ctx->stage_launches += plan->launches;
                 ++chunk;
             }
         }

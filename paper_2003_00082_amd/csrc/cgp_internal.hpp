@@ -97,11 +97,10 @@ struct Mesh {
     DBuf<int32_t> rowptr, col;
     DBuf<double> val, dinv;
     DBuf<float> val32, dinv32;
-    // sliced ELL copy (64-row slices): slice s holds entries [sell_ptr[s], sell_ptr[s+1])
-    int64_t sell_nnz = 0;
-    DBuf<int32_t> sell_ptr, sell_col;
-    DBuf<double> sell_val;
-    DBuf<float> sell_val32;
+    // column-major ELL copy, width max_row: entry k of row i at k * n + i
+    DBuf<int32_t> ell_col;
+    DBuf<double> ell_val;
+    DBuf<float> ell_val32;
     SolveWork work;
     int32_t tuned_lanes[2] = {0, 0};   // autotuned SpMV lanes per precision (0 = not tuned)
 };
@@ -130,7 +129,9 @@ struct InstDesc {
     int32_t guess;        // CGP_GUESS_*
     int32_t stats_index;  // record of this instance in SolveParams::stats
     int32_t chunk;        // rows per workgroup
-    int32_t fast;         // every row fits the one-row-per-thread iteration (sliced ELL width)
+    int32_t fast;         // every row fits the one-row-per-thread iteration (ELL width <= its limit)
+    int32_t ell_w;        // ELL width
+    int32_t pad2_;
     const int32_t *rowptr;
     const int32_t *col;
     const double *val;
@@ -145,10 +146,9 @@ struct InstDesc {
     float *r32, *w32, *s32, *p32, *c32;  // fp32 recurrences and correction
     double *partials;                    // [2][NPART][nblk]
     Ctl *ctl;                            // [2]
-    const int32_t *sell_ptr;             // sliced ELL copy of the matrix
-    const int32_t *sell_col;
-    const double *sell_val;
-    const float *sell_val32;
+    const int32_t *ell_col;              // column-major ELL copy of the matrix
+    const double *ell_val;
+    const float *ell_val32;
 };
 
 struct SolveParams {
@@ -176,10 +176,10 @@ void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_bloc
                    RowRange *d_ranges);
 void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
                     int32_t *d_done);
-void launch_cg_step(hipStream_t s, bool mixed, int halo, const InstDesc *d_insts, const int32_t *d_block_inst,
+void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts, const int32_t *d_block_inst,
                     const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par, int32_t *d_done,
                     int32_t *d_host_flag);
-int pcg_sell_max_width();
+int pcg_ell_max_width();
 void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
                           const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,
                           int32_t *d_done_at, uint64_t timeout_ticks);

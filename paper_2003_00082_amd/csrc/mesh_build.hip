@@ -358,39 +358,27 @@ __global__ void k_max_row(int64_t n, const int32_t *rowptr, int32_t *out) {
     if (i < n) atomicMax(out, rowptr[i + 1] - rowptr[i]);
 }
 
-// ------------------------------------------------------------------ sliced ELL copy of K
+// ------------------------------------------------------------------ ELL copy of K
 
-// Slices of 64 consecutive rows (one wavefront); within a slice the k-th entry of
-// every row is stored contiguously, so a wavefront reads entry k of its 64 rows
-// with one coalesced load.  Slice width = longest row of the slice; shorter rows
-// are padded with (column = the row itself, value = 0).
-__global__ void k_sell_width(int64_t n, const int32_t *rowptr, int32_t *width64) {
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t nsl = (n + 63) / 64;
-    if (s >= nsl) return;
-    int32_t w = 0;
-    for (int64_t i = 64 * s; i < min(n, 64 * s + 64); ++i) w = max(w, rowptr[i + 1] - rowptr[i]);
-    width64[s] = 64 * w;
-}
-
-__global__ void k_sell_fill(int64_t n, const int32_t *rowptr, const int32_t *col, const double *val,
-                            const float *val32, const int32_t *sell_ptr, int32_t *scol, double *sval,
-                            float *sval32) {
+// Column-major ELL: entry k of row i at k * n + i, width = the longest row.  A
+// wavefront reads entry k of 64 consecutive rows with one coalesced load and the
+// address needs no per-row lookup.  Shorter rows are padded with (column = the
+// row itself, value = 0).
+__global__ void k_ell_fill(int64_t n, int32_t width, const int32_t *rowptr, const int32_t *col, const double *val,
+                           const float *val32, int32_t *ecol, double *eval, float *eval32) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t s = i / 64, lane = i % 64;
-    const int32_t w = (sell_ptr[s + 1] - sell_ptr[s]) / 64;
     const int32_t k0 = rowptr[i], len = rowptr[i + 1] - k0;
-    for (int32_t k = 0; k < w; ++k) {
-        const int64_t o = sell_ptr[s] + static_cast<int64_t>(k) * 64 + lane;
+    for (int32_t k = 0; k < width; ++k) {
+        const int64_t o = static_cast<int64_t>(k) * n + i;
         if (k < len) {
-            scol[o] = col[k0 + k];
-            sval[o] = val[k0 + k];
-            sval32[o] = val32[k0 + k];
+            ecol[o] = col[k0 + k];
+            eval[o] = val[k0 + k];
+            eval32[o] = val32[k0 + k];
         } else {
-            scol[o] = static_cast<int32_t>(i);
-            sval[o] = 0.0;
-            sval32[o] = 0.0f;
+            ecol[o] = static_cast<int32_t>(i);
+            eval[o] = 0.0;
+            eval32[o] = 0.0f;
         }
     }
 }
@@ -513,19 +501,12 @@ void build_hierarchy(hipStream_t s, Mesh &m, const double *h_xy, int64_t n, cons
             hipLaunchKernelGGL(k_max_row, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.rowptr.p, mr.p);
             CGP_HIP(hipGetLastError());
             m.max_row = read_i32(s, mr.p);
-            // sliced ELL copy
-            const int64_t nsl = (L.n + 63) / 64;
-            DBuf<int32_t> w64;
-            w64.alloc(nsl);
-            hipLaunchKernelGGL(k_sell_width, dim3(blocks_for(nsl, TPB)), dim3(TPB), 0, s, L.n, m.rowptr.p, w64.p);
-            CGP_HIP(hipGetLastError());
-            m.sell_ptr.alloc(nsl + 1);
-            m.sell_nnz = exclusive_scan(s, w64.p, m.sell_ptr.p, nsl);
-            m.sell_col.alloc(m.sell_nnz);
-            m.sell_val.alloc(m.sell_nnz);
-            m.sell_val32.alloc(m.sell_nnz);
-            hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.rowptr.p, m.col.p,
-                               m.val.p, m.val32.p, m.sell_ptr.p, m.sell_col.p, m.sell_val.p, m.sell_val32.p);
+            // ELL copy
+            m.ell_col.alloc(static_cast<size_t>(m.max_row) * L.n);
+            m.ell_val.alloc(static_cast<size_t>(m.max_row) * L.n);
+            m.ell_val32.alloc(static_cast<size_t>(m.max_row) * L.n);
+            hipLaunchKernelGGL(k_ell_fill, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.max_row, m.rowptr.p,
+                               m.col.p, m.val.p, m.val32.p, m.ell_col.p, m.ell_val.p, m.ell_val32.p);
             CGP_HIP(hipGetLastError());
             CGP_HIP(hipStreamSynchronize(s));
         }

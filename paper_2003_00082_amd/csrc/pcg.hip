@@ -47,8 +47,20 @@ constexpr int BLOCK = 512;
 constexpr int NWAVE = BLOCK / 64;
 constexpr int LDS_DOUBLES = 8192;   // 64 KB staging buffer
 constexpr int LDS_FLOATS = 2 * LDS_DOUBLES;
-constexpr int KMAX = 12;            // longest row the one-row-per-thread iteration holds in registers
+constexpr int KMAX = 12;            // widest ELL row the one-row-per-thread iteration holds in registers
 constexpr int HMAX = 8;             // most staged entries per thread in that iteration (4096 per workgroup)
+
+// Pointers read from a launch record are generic (flat) to the compiler; these
+// casts let it emit global-memory loads and stores, which it can keep in flight.
+#define CGP_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const CGP_GLOBAL T *gld(const T *p) {
+    return (const CGP_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ CGP_GLOBAL T *gst(T *p) {
+    return (CGP_GLOBAL T *)p;
+}
 
 enum State : int32_t {
     ST_BOOT = 0,  // before the first stage
@@ -473,15 +485,14 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
 
 // ------------------------------------------------------------------ one-row-per-thread iteration
 
-// Values an iteration needs, loaded before the stage is decoded: the sliced-ELL
-// row of the thread's row and r, w, s, D^-1 over the staged halo range.
+// Values an iteration needs, loaded before the stage is decoded: the ELL row of
+// the thread's row and r, w, s, D^-1 over the staged halo range.
 template <class T, int H>
 struct IterPrefetch {
     T hd[H], hr[H], hw[H], hs[H];                // staged entries c0 + tid + h*BLOCK
     T od, orr, ow, os, op, ox;                   // own row: D^-1, r, w, s, p, c (mixed) or x (fp64)
     T sv[KMAX];
     int32_t sc[KMAX];
-    int32_t width;
 };
 
 template <class T>
@@ -498,8 +509,9 @@ __device__ inline const float *vec_of<float>(const InstDesc &D, int which) {
 template <class T, int H>
 __device__ inline void iter_prefetch(IterPrefetch<T, H> &f, const InstDesc &D, const RowRange &R, int rd) {
     const int64_t n = D.n;
-    const T *r = vec_of<T>(D, 0) + rd * n, *w = vec_of<T>(D, 1) + rd * n, *s = vec_of<T>(D, 2) + rd * n;
-    const T *dv = vec_of<T>(D, 3), *p = vec_of<T>(D, 4);
+    const CGP_GLOBAL T *r = gld(vec_of<T>(D, 0) + rd * n), *w = gld(vec_of<T>(D, 1) + rd * n);
+    const CGP_GLOBAL T *s = gld(vec_of<T>(D, 2) + rd * n);
+    const CGP_GLOBAL T *dv = gld(vec_of<T>(D, 3)), *p = gld(vec_of<T>(D, 4));
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         const int32_t j = R.c0 + threadIdx.x + h * BLOCK;
@@ -511,7 +523,6 @@ __device__ inline void iter_prefetch(IterPrefetch<T, H> &f, const InstDesc &D, c
         }
     }
     const int32_t i = R.r0 + threadIdx.x;
-    f.width = 0;
     if (i < R.r1) {
         f.od = dv[i];
         f.orr = r[i];
@@ -519,18 +530,17 @@ __device__ inline void iter_prefetch(IterPrefetch<T, H> &f, const InstDesc &D, c
         f.os = s[i];
         f.op = p[i];
         if constexpr (sizeof(T) == 4)
-            f.ox = D.c32[i];
+            f.ox = gld(D.c32)[i];
         else
-            f.ox = D.x[i];
-        const int32_t sl = i >> 6;
-        const int32_t base = D.sell_ptr[sl] + (i & 63);
-        f.width = (D.sell_ptr[sl + 1] - D.sell_ptr[sl]) >> 6;
-        const T *sv = sizeof(T) == 4 ? reinterpret_cast<const T *>(D.sell_val32) : reinterpret_cast<const T *>(D.sell_val);
+            f.ox = gld(D.x)[i];
+        const CGP_GLOBAL T *ev = gld(sizeof(T) == 4 ? reinterpret_cast<const T *>(D.ell_val32)
+                                                     : reinterpret_cast<const T *>(D.ell_val));
+        const CGP_GLOBAL int32_t *ec = gld(D.ell_col);
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            if (k < f.width) {
-                f.sv[k] = sv[base + 64 * k];
-                f.sc[k] = D.sell_col[base + 64 * k];
+            if (k < D.ell_w) {
+                f.sv[k] = ev[k * n + i];
+                f.sc[k] = ec[k * n + i];
             }
         }
     }
@@ -560,21 +570,17 @@ __device__ inline void iter_fast(const IterPrefetch<T, H> &f, const Ctl &c, cons
         T acc = T(0);
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
-            if (k < f.width) acc += f.sv[k] * lds[f.sc[k] - R.c0];
+            if (k < D.ell_w) acc += f.sv[k] * lds[f.sc[k] - R.c0];
         const T u0 = f.od * f.orr;
         const T pj = rs ? u0 : u0 + be * f.op;
-        T *rn = const_cast<T *>(vec_of<T>(D, 0)) + wr * n;
-        T *wn = const_cast<T *>(vec_of<T>(D, 1)) + wr * n;
-        T *sn = const_cast<T *>(vec_of<T>(D, 2)) + wr * n;
-        T *p = const_cast<T *>(vec_of<T>(D, 4));
-        p[i] = pj;
-        sn[i] = sj;
-        rn[i] = rj;
-        wn[i] = acc;
+        gst(const_cast<T *>(vec_of<T>(D, 4)))[i] = pj;
+        gst(const_cast<T *>(vec_of<T>(D, 2)) + wr * n)[i] = sj;
+        gst(const_cast<T *>(vec_of<T>(D, 0)) + wr * n)[i] = rj;
+        gst(const_cast<T *>(vec_of<T>(D, 1)) + wr * n)[i] = acc;
         if constexpr (sizeof(T) == 4)
-            D.c32[i] = f.ox + al * pj;
+            gst(D.c32)[i] = f.ox + al * pj;
         else
-            D.x[i] = f.ox + al * pj;
+            gst(D.x)[i] = f.ox + al * pj;
         const double r64 = static_cast<double>(rj), u64 = static_cast<double>(u1);
         v[0] += r64 * u64;
         v[1] += static_cast<double>(acc) * u64;
@@ -594,14 +600,26 @@ __device__ inline void write_stats(const Ctl &c, const SolveParams &prm, int idx
     prm.stats[idx] = o;
 }
 
-// sums of an instance's per-workgroup partials by one wavefront (fixed order)
+// sums of an instance's per-workgroup partials by one wavefront (fixed order);
+// loads are issued four rows of 64 at a time so they are in flight together
 __device__ inline void wave_reduce_partials(const double *part, int nblk, double (&S)[NPART]) {
     const int lane = threadIdx.x & 63;
+    const CGP_GLOBAL double *pg = gld(part);
 #pragma unroll
     for (int s = 0; s < NPART; ++s) S[s] = 0.0;
-    for (int j = lane; j < nblk; j += 64) {
+    for (int base = 0; base < nblk; base += 256) {
+        double t[4][NPART];
 #pragma unroll
-        for (int s = 0; s < NPART; ++s) S[s] += part[s * nblk + j];
+        for (int u = 0; u < 4; ++u) {
+            const int j = base + lane + 64 * u;
+#pragma unroll
+            for (int s = 0; s < NPART; ++s) t[u][s] = j < nblk ? pg[s * nblk + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int s = 0; s < NPART; ++s) S[s] += t[u][s];
+        }
     }
 #pragma unroll
     for (int s = 0; s < NPART; ++s) S[s] = wave_sum(S[s]);
@@ -612,10 +630,11 @@ __device__ inline void wave_reduce_partials(const double *part, int nblk, double
 __device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolveParams &prm, int guess) {
     if (prev.state == ST_ITER) {
         const double g = S[0], dl = S[1], sg = S[2], rr = S[3];
-        const double rn = sqrt(rr);
+        // the stopping tests of transition() on squares: rn <= t  <=>  rr <= t^2 (t >= 0)
+        const double t_conv = prm.tol * prev.bnorm, t_ref = prm.delta * prev.rmax;
         const bool mixed = prm.precision == CGP_FP32_IR;
-        const bool go_on = isfinite(rr) && isfinite(g) && !(rn <= prm.tol * prev.bnorm) &&
-                           prev.it + 1 < prm.max_iter && !(mixed && rn <= prm.delta * prev.rmax);
+        const bool go_on = isfinite(rr) && isfinite(g) && !(rr <= t_conv * t_conv) &&
+                           prev.it + 1 < prm.max_iter && !(mixed && rr <= t_ref * t_ref);
         if (go_on) {
             Ctl c = prev;
             ++c.it;
@@ -637,12 +656,12 @@ __device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolvePa
 
 template <class T, int H>
 __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ insts,
-                                                   const int32_t *__restrict__ block_inst,
+                                                   const int32_t *__restrict__ block_inst, int n_inst,
                                                    const RowRange *__restrict__ ranges,
                                                    const SolveParams *__restrict__ prm_dev, int par,
                                                    int32_t *done_count, int32_t *host_flag) {
     __shared__ Shared sh;
-    const int inst = block_inst[blockIdx.x];
+    const int inst = n_inst == 1 ? 0 : block_inst[blockIdx.x];
     const InstDesc D = insts[inst];
     const int lb = blockIdx.x - D.blk0;
     const RowRange R = ranges[blockIdx.x];
@@ -654,14 +673,12 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
     // decode the stage: wavefront 0 reduces the previous stage's partials and
     // applies the transition; the other wavefronts wait at the barrier
     if (threadIdx.x < 64) {
-        const SolveParams prm = *prm_dev;
         const Ctl prev = D.ctl[rd];
+        double S[NPART];   // loaded whatever the state, so the loads overlap the control read
+        wave_reduce_partials(D.partials + static_cast<size_t>(rd) * NPART * D.nblk, D.nblk, S);
+        const SolveParams prm = *prm_dev;
         Ctl c = prev;
-        if (prev.state != ST_DONE) {
-            double S[NPART];
-            wave_reduce_partials(D.partials + static_cast<size_t>(rd) * NPART * D.nblk, D.nblk, S);
-            if (threadIdx.x == 0) c = next_state(prev, S, prm, D.guess);
-        }
+        if (prev.state != ST_DONE && threadIdx.x == 0) c = next_state(prev, S, prm, D.guess);
         if (threadIdx.x == 0) {
             sh.ctl = c;
             if (lb == 0) {
@@ -854,7 +871,7 @@ int pcg_max_blocks_per_cu() {
     return a;
 }
 
-int pcg_sell_max_width() { return KMAX; }
+int pcg_ell_max_width() { return KMAX; }
 
 void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_block_inst, int grid, RowRange *d_ranges) {
     hipLaunchKernelGGL(k_ranges, dim3(grid), dim3(256), 0, s, d_insts, d_block_inst, grid, d_ranges);
@@ -867,14 +884,14 @@ void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolvePar
     CGP_HIP(hipGetLastError());
 }
 
-void launch_cg_step(hipStream_t s, bool mixed, int halo, const InstDesc *d_insts, const int32_t *d_block_inst,
-                    const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par, int32_t *d_done,
-                    int32_t *d_host_flag) {
+void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts,
+                    const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
+                    int32_t *d_done, int32_t *d_host_flag) {
     // staged entries per thread: 4 covers workgroups whose column range spans <= 2048 rows
     const bool small = halo <= 4 * BLOCK;
 #define CGP_STEP(T, H)                                                                                             \
-    hipLaunchKernelGGL((k_cg_step<T, H>), dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, d_ranges, d_prm, par, \
-                       d_done, d_host_flag)
+    hipLaunchKernelGGL((k_cg_step<T, H>), dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, n_inst, d_ranges, \
+                       d_prm, par, d_done, d_host_flag)
     if (mixed) {
         if (small) CGP_STEP(float, 4);
         else CGP_STEP(float, HMAX);
