@@ -10,16 +10,19 @@ step.  One *step* is one pass of the whole hot path:
     -> Lorentz force (Eqs. 13-14) -> restrict + divergence source (Eq. 15)
     -> solve p -> prolong p
 
-with both Poisson solves to a true relative residual of 1e-8.  Two forms run on
-the same inputs:
+with both Poisson solves to a true relative residual of 1e-8.  Three forms run
+on the same inputs:
 
     A  plain fp64 Jacobi-PCG from the previous solution
-    B  fp32 Jacobi-PCG with fp64 residual refinement from the predicted guess
-       (the learned network when a trained model is given, else the
-       extrapolation 2 phi^{n-1} - phi^{n-2})
+    B  fp32 Jacobi-PCG with fp64 residual refinement from the learned guess (one
+       network per equation, trained on the GPU beforehand on the solutions of
+       the steps that precede the warm-up; each guess is judged against the
+       previous solution by the solver)
+    C  as B with the extrapolation 2 phi^{n-1} - phi^{n-2} instead of the network
 
 ``value`` is form B's whole-job Poisson solves per second (2 solves per step)
-over the timed steps, inputs resident in HBM.  Prints one JSON line.
+over the timed steps, inputs resident in HBM.  Training is a one-off set-up
+cost, reported beside it.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -48,7 +51,10 @@ def parse():
     ap.add_argument("--stuart", type=float, default=1.0, help="Stuart number N (sigma of the Lorentz force)")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample: steps (2 solves each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="AB")
+    ap.add_argument("--forms", default="ABC")
+    ap.add_argument("--train-steps", type=int, default=48, help="steps solved (fp64) to train the networks")
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--lr", type=float, default=2e-3)
     return ap.parse_args()
 
 
@@ -98,9 +104,10 @@ def main():
     fine_xy = ctx.mesh_download(h, 1)[0]
     seq = ci.FourierSequence(fine_xy, ci.fourier_modes(2500), ci.fourier_modes(2700))
     W, K = args.warmup, args.steps
+    TR = args.train_steps if "B" in args.forms else 0
     steps = list(range(-W, K))
     vel = {}
-    for n in steps:                                   # inputs resident in HBM before timing
+    for n in range(-W - TR, K):                       # inputs resident in HBM before timing
         vel[n] = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in seq.at(n))
     torch.cuda.synchronize()
 
@@ -111,8 +118,44 @@ def main():
     stats = cgp.stats_buffer(2 * len(steps))
     stream = torch.cuda.current_stream()
 
+    # ---- training data and networks for form B: the steps before the warm-up, solved in fp64
+    models, train_info = {}, None
+    if TR > 0:
+        t0 = time.perf_counter()
+        sols = {"phi": [], "p": []}
+        rhs_t = {"phi": [], "p": []}
+        x = {"phi": torch.zeros(nc, **f64), "p": torch.zeros(nc, **f64)}
+        st1 = cgp.stats_buffer(1)
+        for n in range(-W - TR, -W):
+            u, v, ut, vt = vel[n]
+            for eq, kind, uu, vv, sc in (("phi", cgp.CGP_SRC_CURL, u, v, 1.0),
+                                         ("p", cgp.CGP_SRC_DIV, ut, vt, rho_dt)):
+                bb = torch.empty(nc, **f64)
+                ctx.restrict(h, uu, vv, kind, sc, bb)
+                ctx.poisson_solve([h], [bb], [x[eq]], st1, guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64,
+                                  tol=1e-10)
+                rhs_t[eq].append(bb)
+                sols[eq].append(x[eq].clone())
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        hist = {}
+        for i, eq in enumerate(("phi", "p")):
+            md = ctx.model_create(seed=11 + i)
+            S, B = sols[eq], rhs_t[eq]
+            idx = range(2, len(S))
+            hist[eq] = ctx.model_train(md, h, [B[j] for j in idx], [S[j - 1] for j in idx], [S[j - 2] for j in idx],
+                                       [S[j] for j in idx], epochs=args.epochs, lr=args.lr, seed=5 + i)
+            models[eq] = md
+        torch.cuda.synchronize()
+        train_info = {"train_steps": TR, "samples_per_network": TR - 2, "epochs": args.epochs, "lr": args.lr,
+                      "data_s": t_data, "train_s": time.perf_counter() - t0,
+                      "loss_first_epoch": {k: float(v[0]) for k, v in hist.items()},
+                      "loss_last_epoch": {k: float(v[-1]) for k, v in hist.items()}}
+        del sols, rhs_t
+
     def run(form: str):
-        mixed = form == "B"
+        mixed = form in "BC"
         bufs = {"phi": [torch.zeros(nc, **f64) for _ in range(3)], "p": [torch.zeros(nc, **f64) for _ in range(3)]}
         ev = []
         keep = {}
@@ -121,7 +164,11 @@ def main():
             B = bufs[eq]
             if mixed:
                 cur, p1, p2 = B[n % 3], B[(n - 1) % 3], B[(n - 2) % 3]
-                kw = dict(prev1=[p1], prev2=[p2], guess=cgp.CGP_GUESS_EXTRAP, precision=cgp.CGP_FP32_IR)
+                kw = dict(prev1=[p1], prev2=[p2], precision=cgp.CGP_FP32_IR)
+                if form == "B":
+                    kw.update(guess=cgp.CGP_GUESS_LEARNED, model=models[eq])
+                else:
+                    kw.update(guess=cgp.CGP_GUESS_EXTRAP)
             else:
                 cur = B[0]
                 kw = dict(guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64)
@@ -158,11 +205,25 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         launches = ctx.stage_launches - launches0
+        # the network's share of the solve time, timed live on the same stream and inputs
+        gnn_us = 0.0
+        if form == "B":
+            g = torch.empty(nc, **f64)
+            B = bufs["phi"]
+            reps = 20
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                ctx.model_predict(models["phi"], h, b_phi, B[0], B[1], g)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gnn_us = 1e3 * e0.elapsed_time(e1) / reps
         host = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=np.dtype(
             [("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"), ("rel0", "f8")]))
         timed = host[2 * W:]
         ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
         solve_ms = np.array([a.elapsed_time(b) for a, b in ev])
+        pcg_ms = solve_ms.sum() - 1e-3 * gnn_us * len(solve_ms)
         nbytes = np.array([pcg_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed, mixed) for r in timed])
         return {
             "solves_per_s": 2 * K / elapsed,
@@ -171,12 +232,14 @@ def main():
             "mean_refinements": float(timed["ref"].mean()),
             "max_rel_res": float(timed["rel"].max()),
             "mean_guess_rel_res": float(timed["rel0"].mean()),
+            "learned_guess_kept": float(np.mean(timed["guess"] == cgp.CGP_GUESS_LEARNED)) if form == "B" else None,
             "all_converged": ok,
             "solve_ms_mean": float(solve_ms.mean()),
             "solve_share": float(solve_ms.sum() / (1e3 * elapsed)),
-            "achieved_GBs": float(nbytes.sum() / (solve_ms.sum() * 1e-3) / 1e9),
+            "gnn_predict_us": gnn_us if form == "B" else None,
+            "achieved_GBs": float(nbytes.sum() / (pcg_ms * 1e-3) / 1e9),
             "stage_launches": int(launches),
-            "kernel_avg_us": float(solve_ms.sum() * 1e3 / max(launches, 1)),
+            "kernel_avg_us": float(pcg_ms * 1e3 / max(launches, 1)),
             "bytes_per_solve": float(nbytes.mean()),
             "step0": {k: v.cpu().numpy() for k, v in keep.items()},
         }
@@ -221,7 +284,7 @@ def main():
                          f"sequence, phi and p ({2 * S} solves, mean {np.mean(its):.0f} iterations, "
                          f"{cpu_t:.1f} s)"}
 
-    bpi = (8 * nnz + 44 * nc) if main_form == "B" else (12 * nnz + 88 * nc)
+    bpi = (8 * nnz + 44 * nc) if main_form in "BC" else (12 * nnz + 88 * nc)
     out = {
         "metric": METRIC,
         "value": R["solves_per_s"],
@@ -233,7 +296,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if main_form == "B" else "f64",
+        "dtype": "f32+f64 (network bf16)" if main_form == "B" else ("f32+f64" if main_form == "C" else "f64"),
         "data": "synthetic",
         "config": {"workload": f"CGP step, coarse {nx}x{ny} jittered P1 ({nc} nodes, nnz {nnz}), fine k=1 "
                                f"({nf} nodes), {K}-step drifting 8-mode Fourier flow, phi and p solves to "
@@ -242,6 +305,8 @@ def main():
         "forms": {f: {k: v for k, v in r.items() if k != "step0"} | {"err_vs_oracle_step0": errs.get(f)}
                   for f, r in res.items()},
         "speedup_B_over_A": (res["B"]["solves_per_s"] / res["A"]["solves_per_s"]) if {"A", "B"} <= set(res) else None,
+        "speedup_C_over_A": (res["C"]["solves_per_s"] / res["A"]["solves_per_s"]) if {"A", "C"} <= set(res) else None,
+        "training": train_info,
         "roofline": {"bound": "hbm", "achieved": R["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": R["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_cg_step (one CG stage per launch)", "bytes_per_iter": bpi,

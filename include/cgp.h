@@ -184,9 +184,12 @@ typedef struct {
  *                solution on exit
  *   h_d_prev1[i], h_d_prev2[i]  previous two solutions phi^{n-1}, phi^{n-2}
  *                (device pointers; required for GUESS_EXTRAP, which starts from
- *                2 phi^{n-1} - phi^{n-2}, and GUESS_LEARNED, whose network
- *                guess is kept only if its residual is below that of
- *                phi^{n-1}); may be NULL otherwise.  They must not alias phi.
+ *                2 phi^{n-1} - phi^{n-2}, and GUESS_LEARNED, whose network guess
+ *                (h_opts->model, see cgp_model_predict) is kept only if its
+ *                error in the energy norm |x - x*|_K, which CG minimises, is not
+ *                above that of phi^{n-1}, else phi^{n-1} is used; the two are
+ *                compared exactly through J(x) = x.Kx/2 - b.x = |x - x*|_K^2/2 + const);
+ *                may be NULL otherwise.  They must not alias phi.
  *   d_stats      device array [n_inst], written when the solve completes.
  * CGP_FP64: every vector and product in fp64.  CGP_FP32_IR: fp32 matrix,
  * vectors and products with fp64 dot-product accumulation, refined by true
@@ -233,6 +236,51 @@ cgp_status cgp_prolong(cgp_ctx ctx, cgp_mesh mesh, const double *d_qc, double *d
 cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif,
                              const double *d_uf, const double *d_vf, double sigma, double B0,
                              double *d_fx, double *d_fy, double *d_grad_elem);
+
+/* ------------------------------------------------------------------ learned initial guess */
+
+/* A graph network on the coarse mesh that predicts the initial guess of a
+ * solve from the current right-hand side b and the previous two solutions p1,
+ * p2 (an extension of the paper's method; Section 2.2's sequence of solves
+ * supplies the training data):
+ *   features  [b/s_b, p1/s_p, p2/s_p, r_e/s_r, K d/s_r, d/s_d, dirichlet, 1] with
+ *             e = 2 p1 - p2, d = p1 - p2, r_e = b - K e, s_* = RMS over the nodes
+ *   encoder   h = relu(X W0 + c0) (8 -> 64); three layers
+ *             h <- relu([h, mean of the neighbours' h] W_l + c_l) + h (128 -> 64)
+ *   decoder   y = h w_d + c_d;  guess = e + s_d y on free nodes, 0 on Dirichlet nodes
+ * Dense products use bfloat16 operands on the matrix cores with fp32
+ * accumulation.  Parameters: cgp_model_param_count() floats, in the order
+ * W0 [16x64] (rows 8..15 multiply zero padding), c0 [64], then W_l [128x64],
+ * c_l [64] for l = 1..3, then w_d [64], c_d [1] (row-major).
+ * Training minimises the energy norm (delta^T K delta) / N_free of delta =
+ * (y - (target - e) / s_d) on free nodes with Adam (beta 0.9 / 0.999, eps 1e-8). */
+int64_t cgp_model_param_count(void);
+/* New model with seeded He-normal weights (splitmix64 stream) and zero biases. */
+cgp_status cgp_model_create(cgp_ctx ctx, uint64_t seed, cgp_model *out);
+cgp_status cgp_model_free(cgp_ctx ctx, cgp_model model);
+/* Copy the fp32 parameters out / in (h_params: cgp_model_param_count() floats).
+ * Setting parameters resets the optimiser state.  Synchronous. */
+cgp_status cgp_model_get_params(cgp_ctx ctx, cgp_model model, float *h_params);
+cgp_status cgp_model_set_params(cgp_ctx ctx, cgp_model model, const float *h_params);
+/* Enqueue one prediction: d_guess [N_0] receives the network's guess. */
+cgp_status cgp_model_predict(cgp_ctx ctx, cgp_model model, cgp_mesh mesh, const double *d_b,
+                             const double *d_prev1, const double *d_prev2, double *d_guess);
+/* Loss and gradient for one sample with d_target = the solution.  h_loss (1)
+ * and h_grad (cgp_model_param_count()) may be NULL.  Synchronous. */
+cgp_status cgp_model_grad(cgp_ctx ctx, cgp_model model, cgp_mesh mesh, const double *d_b,
+                          const double *d_prev1, const double *d_prev2, const double *d_target,
+                          double *h_loss, float *h_grad);
+/* Train on n_samples samples (device pointers, all on `mesh`) for `epochs`
+ * epochs, one Adam step per sample, samples in a seeded shuffled order per
+ * epoch.  h_loss_history [epochs] receives the mean loss of each epoch (may be
+ * NULL).  Synchronous. */
+cgp_status cgp_model_train(cgp_ctx ctx, cgp_model model, cgp_mesh mesh, int32_t n_samples,
+                           const double *const *h_d_b, const double *const *h_d_prev1,
+                           const double *const *h_d_prev2, const double *const *h_d_target,
+                           int32_t epochs, double lr, uint64_t seed, double *h_loss_history);
+/* Parameters to / from a file (8-byte tag, int64 count, float32 values). */
+cgp_status cgp_model_save(cgp_ctx ctx, cgp_model model, const char *path);
+cgp_status cgp_model_load(cgp_ctx ctx, const char *path, cgp_model *out);
 
 /* ------------------------------------------------------------------ HIP graphs */
 

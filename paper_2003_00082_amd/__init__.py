@@ -89,6 +89,16 @@ _SIGS = {
     "cgp_autotune": ([_vp, _i32, _vp, _i32, _vp], _i32),
     "cgp_prolong": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_lorentz_force": ([_vp, _i32, _vp, _vp, _vp, _f64, _f64, _vp, _vp, _vp], _i32),
+    "cgp_model_param_count": ([], _i64),
+    "cgp_model_create": ([_vp, ctypes.c_uint64, ctypes.POINTER(_i32)], _i32),
+    "cgp_model_free": ([_vp, _i32], _i32),
+    "cgp_model_get_params": ([_vp, _i32, _vp], _i32),
+    "cgp_model_set_params": ([_vp, _i32, _vp], _i32),
+    "cgp_model_predict": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp], _i32),
+    "cgp_model_grad": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "cgp_model_train": ([_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _f64, ctypes.c_uint64, _vp], _i32),
+    "cgp_model_save": ([_vp, _i32, ctypes.c_char_p], _i32),
+    "cgp_model_load": ([_vp, ctypes.c_char_p, ctypes.POINTER(_i32)], _i32),
     "cgp_graph_begin": ([_vp], _i32),
     "cgp_graph_end": ([_vp, ctypes.POINTER(_i32)], _i32),
     "cgp_graph_launch": ([_vp, _i32], _i32),
@@ -259,6 +269,61 @@ class Context:
         out = (_i32 * k)()
         _check(load().cgp_autotune(self.handle, k, arr_m, precision, out))
         return list(out)
+
+    # ---------------------------------------------------------------- learned guess
+    @staticmethod
+    def model_param_count() -> int:
+        return int(load().cgp_model_param_count())
+
+    def model_create(self, seed: int = 0) -> int:
+        out = _i32()
+        _check(load().cgp_model_create(self.handle, int(seed), ctypes.byref(out)))
+        return int(out.value)
+
+    def model_free(self, model: int):
+        _check(load().cgp_model_free(self.handle, model))
+
+    def model_get_params(self, model: int) -> np.ndarray:
+        h = np.empty(self.model_param_count(), dtype=np.float32)
+        _check(load().cgp_model_get_params(self.handle, model, h.ctypes.data))
+        return h
+
+    def model_set_params(self, model: int, params):
+        h = _np(params, np.float32)
+        if h.size != self.model_param_count():
+            raise ValueError(f"expected {self.model_param_count()} parameters, got {h.size}")
+        _check(load().cgp_model_set_params(self.handle, model, h.ctypes.data))
+
+    def model_predict(self, model: int, mesh: int, b, prev1, prev2, guess):
+        _check(load().cgp_model_predict(self.handle, model, mesh, _ptr(b), _ptr(prev1), _ptr(prev2), _ptr(guess)))
+
+    def model_grad(self, model: int, mesh: int, b, prev1, prev2, target):
+        """(loss, gradient as float32 numpy array) for one sample."""
+        loss = _f64()
+        g = np.empty(self.model_param_count(), dtype=np.float32)
+        _check(load().cgp_model_grad(self.handle, model, mesh, _ptr(b), _ptr(prev1), _ptr(prev2), _ptr(target),
+                                     ctypes.byref(loss), g.ctypes.data))
+        return float(loss.value), g
+
+    def model_train(self, model: int, mesh: int, b, prev1, prev2, target, *, epochs: int, lr: float,
+                    seed: int = 0) -> np.ndarray:
+        """Train on the samples (sequences of device tensors); returns the mean loss per epoch."""
+        k = len(b)
+        if not (len(prev1) == len(prev2) == len(target) == k):
+            raise ValueError("sample sequences differ in length")
+        arrs = [(_vp * k)(*[_ptr(t) for t in seq]) for seq in (b, prev1, prev2, target)]
+        hist = np.empty(int(epochs), dtype=np.float64)
+        _check(load().cgp_model_train(self.handle, model, mesh, k, *arrs, int(epochs), float(lr), int(seed),
+                                      hist.ctypes.data))
+        return hist
+
+    def model_save(self, model: int, path: str):
+        _check(load().cgp_model_save(self.handle, model, os.fsencode(path)))
+
+    def model_load(self, path: str) -> int:
+        out = _i32()
+        _check(load().cgp_model_load(self.handle, os.fsencode(path), ctypes.byref(out)))
+        return int(out.value)
 
     # ---------------------------------------------------------------- graphs
     def graph_begin(self):

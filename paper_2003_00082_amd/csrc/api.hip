@@ -3,6 +3,7 @@
 // HIP graph capture, and argument validation.  No C++ exception crosses the ABI.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <sstream>
@@ -59,6 +60,11 @@ struct cgp_ctx_s {
     std::map<int32_t, std::unique_ptr<Mesh>> meshes;
     std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
     std::map<int32_t, GraphRec> graphs;
+    struct ModelDel {
+        void operator()(Model *m) const { gnn_destroy(m); }
+    };
+    std::map<int32_t, std::unique_ptr<Model, ModelDel>> models;
+    int32_t next_model = 0;
     DBuf<GridSync> sync;
     int32_t *host_flag = nullptr;     // pinned, mapped: set by the device when a staged solve is done
     int32_t *host_flag_dev = nullptr;
@@ -145,6 +151,12 @@ std::vector<int32_t> split_blocks(const std::vector<int64_t> &rows, int grid) {
     return nb;
 }
 
+Model &get_model(cgp_ctx ctx, cgp_model h) {
+    auto it = ctx->models.find(h);
+    if (it == ctx->models.end()) throw Error{CGP_E_INVALID, "unknown model handle"};
+    return *it->second;
+}
+
 }  // namespace
 
 extern "C" {
@@ -191,6 +203,7 @@ cgp_status cgp_destroy(cgp_ctx ctx) {
             if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
         }
         ctx->plans.clear();
+        ctx->models.clear();
         if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
         for (auto &e : ctx->chunk_ev)
             if (e) (void)hipEventDestroy(e);
@@ -298,6 +311,7 @@ cgp_status cgp_mesh_free(cgp_ctx ctx, cgp_mesh mesh) {
         CGP_HIP(hipStreamSynchronize(ctx->stream));
         // launch plans that reference this mesh's buffers become stale
         ctx->plans.clear();
+        for (auto &md : ctx->models) gnn_release_mesh(*md.second, ctx->meshes[mesh].get());
         ctx->meshes.erase(mesh);
     });
 }
@@ -359,8 +373,12 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         CGP_REQUIRE(o.engine >= CGP_ENGINE_AUTO && o.engine <= CGP_ENGINE_PERSISTENT, "unknown engine");
         CGP_REQUIRE(o.launches_per_graph >= 0 && o.launches_per_graph % 2 == 0 && o.launches_per_graph <= 4096,
                     "launches_per_graph must be even and <= 4096");
-        if (o.guess == CGP_GUESS_LEARNED)
-            throw Error{CGP_E_UNSUPPORTED, "learned guess requires a model (not loaded)"};
+        Model *model = nullptr;
+        if (o.guess == CGP_GUESS_LEARNED) {
+            auto mit = ctx->models.find(o.model);
+            CGP_REQUIRE(mit != ctx->models.end(), "CGP_GUESS_LEARNED needs a valid model handle");
+            model = mit->second.get();
+        }
         const bool need_prev = o.guess == CGP_GUESS_EXTRAP || o.guess == CGP_GUESS_LEARNED;
         std::vector<Mesh *> ms(n_inst);
         for (int i = 0; i < n_inst; ++i) {
@@ -507,6 +525,10 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             SolveParams gp = prm;
             gp.n_inst = gn;
             gp.stats = d_stats + g0;
+            if (model)   // the network's guess goes into phi; the solver judges it against prev1
+                for (int i = 0; i < gn; ++i)
+                    gnn_predict(ctx->stream, *model, *ms[g0 + i], h_d_b[g0 + i], h_d_prev1[g0 + i],
+                                h_d_prev2[g0 + i], h_d_phi[g0 + i]);
             if (persistent) {
                 launch_cg_persistent(ctx->stream, plan->d_insts, gn, plan->d_block_inst, plan->d_ranges, plan->grid,
                                      gp, ctx->sync.p, plan->d_done_at, ctx->timeout_ticks);
@@ -638,6 +660,123 @@ cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_
         CGP_HIP(hipEventDestroy(e0));
         CGP_HIP(hipEventDestroy(e1));
         ctx->plans.clear();
+    });
+}
+
+// ------------------------------------------------------------------ learned guess
+
+int64_t cgp_model_param_count(void) { return gnn_param_count(); }
+
+cgp_status cgp_model_create(cgp_ctx ctx, uint64_t seed, cgp_model *out) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(out != nullptr, "null output pointer");
+        CGP_REQUIRE(!ctx->capturing, "cgp_model_create cannot be captured");
+        std::unique_ptr<Model, cgp_ctx_s::ModelDel> md(gnn_create(ctx->stream, seed));
+        const int32_t h = ctx->next_model++;
+        ctx->models[h] = std::move(md);
+        *out = h;
+    });
+}
+
+cgp_status cgp_model_free(cgp_ctx ctx, cgp_model model) {
+    return guarded([&] {
+        use_device(ctx);
+        (void)get_model(ctx, model);
+        CGP_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->models.erase(model);
+    });
+}
+
+cgp_status cgp_model_get_params(cgp_ctx ctx, cgp_model model, float *h_params) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(h_params != nullptr, "null output pointer");
+        gnn_get_params(ctx->stream, get_model(ctx, model), h_params);
+    });
+}
+
+cgp_status cgp_model_set_params(cgp_ctx ctx, cgp_model model, const float *h_params) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(h_params != nullptr, "null input pointer");
+        gnn_set_params(ctx->stream, get_model(ctx, model), h_params);
+    });
+}
+
+cgp_status cgp_model_predict(cgp_ctx ctx, cgp_model model, cgp_mesh mesh, const double *d_b, const double *d_prev1,
+                             const double *d_prev2, double *d_guess) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(d_b && d_prev1 && d_prev2 && d_guess, "null device pointer");
+        gnn_predict(ctx->stream, get_model(ctx, model), get_mesh(ctx, mesh), d_b, d_prev1, d_prev2, d_guess);
+    });
+}
+
+cgp_status cgp_model_grad(cgp_ctx ctx, cgp_model model, cgp_mesh mesh, const double *d_b, const double *d_prev1,
+                          const double *d_prev2, const double *d_target, double *h_loss, float *h_grad) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(d_b && d_prev1 && d_prev2 && d_target, "null device pointer");
+        CGP_REQUIRE(!ctx->capturing, "cgp_model_grad cannot be captured");
+        gnn_grad(ctx->stream, get_model(ctx, model), get_mesh(ctx, mesh), d_b, d_prev1, d_prev2, d_target, h_loss,
+                 h_grad);
+    });
+}
+
+cgp_status cgp_model_train(cgp_ctx ctx, cgp_model model, cgp_mesh mesh, int32_t n_samples,
+                           const double *const *h_d_b, const double *const *h_d_prev1,
+                           const double *const *h_d_prev2, const double *const *h_d_target, int32_t epochs, double lr,
+                           uint64_t seed, double *h_loss_history) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(n_samples >= 1 && epochs >= 1, "need at least one sample and one epoch");
+        CGP_REQUIRE(h_d_b && h_d_prev1 && h_d_prev2 && h_d_target, "null sample arrays");
+        for (int i = 0; i < n_samples; ++i)
+            CGP_REQUIRE(h_d_b[i] && h_d_prev1[i] && h_d_prev2[i] && h_d_target[i], "null sample pointer");
+        CGP_REQUIRE(lr > 0.0 && std::isfinite(lr), "lr must be positive");
+        CGP_REQUIRE(!ctx->capturing, "cgp_model_train cannot be captured");
+        gnn_train(ctx->stream, get_model(ctx, model), get_mesh(ctx, mesh), n_samples, h_d_b, h_d_prev1, h_d_prev2,
+                  h_d_target, epochs, lr, seed, h_loss_history);
+    });
+}
+
+cgp_status cgp_model_save(cgp_ctx ctx, cgp_model model, const char *path) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(path != nullptr, "null path");
+        std::vector<float> h(gnn_param_count());
+        gnn_get_params(ctx->stream, get_model(ctx, model), h.data());
+        FILE *f = std::fopen(path, "wb");
+        if (!f) throw Error{CGP_E_INVALID, std::string("cannot open ") + path};
+        const char tag[8] = {'C', 'G', 'P', 'G', 'N', 'N', '1', 0};
+        const int64_t cnt = static_cast<int64_t>(h.size());
+        bool ok = std::fwrite(tag, 1, 8, f) == 8 && std::fwrite(&cnt, sizeof cnt, 1, f) == 1 &&
+                  std::fwrite(h.data(), sizeof(float), h.size(), f) == h.size();
+        ok = (std::fclose(f) == 0) && ok;
+        if (!ok) throw Error{CGP_E_INVALID, std::string("cannot write ") + path};
+    });
+}
+
+cgp_status cgp_model_load(cgp_ctx ctx, const char *path, cgp_model *out) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(path != nullptr && out != nullptr, "null argument");
+        FILE *f = std::fopen(path, "rb");
+        if (!f) throw Error{CGP_E_INVALID, std::string("cannot open ") + path};
+        char tag[8] = {0};
+        int64_t cnt = 0;
+        std::vector<float> h(gnn_param_count());
+        bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, "CGPGNN1", 8) == 0 &&
+                  std::fread(&cnt, sizeof cnt, 1, f) == 1 && cnt == gnn_param_count() &&
+                  std::fread(h.data(), sizeof(float), h.size(), f) == h.size();
+        std::fclose(f);
+        if (!ok) throw Error{CGP_E_INVALID, std::string("not a model file: ") + path};
+        std::unique_ptr<Model, cgp_ctx_s::ModelDel> md(gnn_create(ctx->stream, 0));
+        gnn_set_params(ctx->stream, *md, h.data());
+        const int32_t hd = ctx->next_model++;
+        ctx->models[hd] = std::move(md);
+        *out = hd;
     });
 }
 

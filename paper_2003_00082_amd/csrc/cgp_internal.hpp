@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -195,6 +196,22 @@ void launch_prolong(hipStream_t s, Mesh &m, const double *qc, double *qf);
 void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const double *uf,
                     const double *vf, double sigma, double b0, double *fx, double *fy,
                     double *grad_elem);
+
+// learned initial guess (gnn.hip)
+struct Model;
+int64_t gnn_param_count();
+Model *gnn_create(hipStream_t s, uint64_t seed);   // owned by the caller, freed by gnn_destroy
+void gnn_set_params(hipStream_t s, Model &md, const float *h);
+void gnn_get_params(hipStream_t s, Model &md, float *h);
+void gnn_predict(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
+                 double *guess);
+void gnn_grad(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
+              const double *target, double *h_loss, float *h_grad);
+void gnn_train(hipStream_t s, Model &md, const Mesh &m, int n_samples, const double *const *b,
+               const double *const *p1, const double *const *p2, const double *const *target, int epochs,
+               double lr, uint64_t seed, double *h_loss);
+void gnn_release_mesh(Model &md, const Mesh *m);
+void gnn_destroy(Model *md);
 
 // scan (mesh_build.hip): out[0..n] exclusive prefix sums of in[0..n-1]; returns total
 int64_t exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t n);

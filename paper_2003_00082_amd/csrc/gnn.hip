@@ -1,0 +1,700 @@
+// Learned initial guess of the coarse Poisson solve: a small graph network on the
+// coarse mesh that corrects the extrapolation 2 phi^{n-1} - phi^{n-2} (the guess
+// is then judged against phi^{n-1} by the solver; see pcg.hip).
+//
+//   features  X = [b/s_b, p1/s_p, p2/s_p, r_e/s_r, K d/s_r, d/s_d, dirichlet, 1]
+//             e = 2 p1 - p2, d = p1 - p2, r_e = b - K e, s_* = RMS over all nodes
+//   encoder   h0 = relu(X W0 + c0)                          8 (padded to 16) -> 64
+//   layers    h <- relu([h, mean_nbr(h)] W_l + c_l) + h      128 -> 64, l = 1..3
+//   decoder   y = h w_d + c_d;  guess = (e + s_d y) on free nodes
+//
+// Dense products run on the matrix cores (v_mfma_f32_32x32x16_bf16): bfloat16
+// operands (features, weights, stored activations, neighbour means, and the
+// activation gradients of the backward pass), fp32 accumulation; biases,
+// decoder, reductions and master weights in fp32.  Training minimises the
+// energy norm (delta^T K delta)/N_free of the scaled output error with Adam.
+// Every reduction is a per-workgroup partial followed by a fixed-order sum: no
+// floating-point atomics, bitwise reproducible.
+#include <cmath>
+#include <fstream>
+#include <map>
+#include <memory>
+
+#include "cgp_internal.hpp"
+
+namespace cgp {
+
+constexpr int GH = 64;                 // hidden width
+constexpr int GF = 8;                  // input features
+constexpr int GFP = 16;                // padded to the MFMA K step
+constexpr int GL = 3;                  // message-passing layers
+constexpr int P_W0 = 0;
+constexpr int P_C0 = P_W0 + GFP * GH;
+constexpr int P_L0 = P_C0 + GH;                       // layer l: W at P_L0 + (l-1)*(2GH*GH+GH), c after it
+constexpr int P_LSTRIDE = 2 * GH * GH + GH;
+constexpr int P_WD = P_L0 + GL * P_LSTRIDE;
+constexpr int P_CD = P_WD + GH;
+constexpr int P_COUNT = P_CD + 1;
+constexpr int Q_W0 = 0;                               // bf16 copies: W0 then W1..W3
+constexpr int Q_COUNT = GFP * GH + GL * 2 * GH * GH;
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct GnnWork {
+    int64_t n = 0;
+    DBuf<double> e, d, re, kd, part, scales, delta;
+    DBuf<bf16> x;                 // [n, 16]
+    DBuf<bf16> h[GL + 1];         // [n, 64]
+    DBuf<float> a[GL + 1];        // pre-activations [n, 64] (training)
+    DBuf<float> y;                // [n]
+    DBuf<float> dy, dh, dhp, dm;  // training
+    DBuf<float> gpart;            // per-workgroup gradient partials
+    DBuf<float> grad;             // [P_COUNT]
+    DBuf<double> lpart;
+};
+
+struct Model {
+    DBuf<float> theta, m1, m2;
+    DBuf<bf16> wq;
+    int64_t step = 0;
+    std::map<const Mesh *, std::unique_ptr<GnnWork>> work;
+};
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int TM = 64;                 // rows per forward workgroup
+constexpr int BW_SUB = 4;              // 64-row sub-tiles per backward workgroup
+
+__device__ inline bf16 to_bf16(float v) { return static_cast<bf16>(v); }
+__device__ inline float from_bf16(bf16 v) { return static_cast<float>(v); }
+
+// acc[32x32] += A[32 x K] B[K x 32], A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (LDS)
+__device__ inline void mfma_tile(f32x16 &acc, const bf16 *A, int sam, int sak, const bf16 *B, int sbk, int sbn,
+                                 int K) {
+    const int l = threadIdx.x & 63;
+    const int mi = l & 31, kh = (l >> 5) * 8;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            a[i] = A[mi * sam + (k0 + kh + i) * sak];
+            b[i] = B[(k0 + kh + i) * sbk + mi * sbn];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+}
+// element v of lane l of a 32x32 accumulator tile
+__device__ inline int acc_row(int v) { return (v >> 2) * 8 + ((threadIdx.x & 63) >> 5) * 4 + (v & 3); }
+__device__ inline int acc_col() { return threadIdx.x & 31; }
+
+// ------------------------------------------------------------------ features
+
+// e, d, r_e = b - K e, K d per row; per-block partial sums of b^2, p1^2, r_e^2, d^2
+__global__ __launch_bounds__(TPB) void k_gnn_prep(int64_t n, const int32_t *rowptr, const int32_t *col,
+                                                  const double *val, const double *b, const double *p1,
+                                                  const double *p2, double *e, double *d, double *re, double *kd,
+                                                  double *part) {
+    __shared__ double red[TPB / 64][4];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < n) {
+        double ke = 0.0, kdd = 0.0;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            ke += val[k] * (2.0 * p1[j] - p2[j]);
+            kdd += val[k] * (p1[j] - p2[j]);
+        }
+        const double ei = 2.0 * p1[i] - p2[i], di = p1[i] - p2[i], ri = b[i] - ke;
+        e[i] = ei;
+        d[i] = di;
+        re[i] = ri;
+        kd[i] = kdd;
+        s[0] = b[i] * b[i];
+        s[1] = p1[i] * p1[i];
+        s[2] = ri * ri;
+        s[3] = di * di;
+    }
+    for (int q = 0; q < 4; ++q) {
+        double v = s[q];
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < TPB / 64; ++w) t += red[w][threadIdx.x];
+        part[static_cast<int64_t>(threadIdx.x) * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// scales[q] = sqrt(sum / n) (1 when zero), q = b, p1, r_e, d; one workgroup
+__global__ __launch_bounds__(TPB) void k_gnn_scales(int64_t n, const double *part, int nblk, double *scales) {
+    __shared__ double red[TPB / 64][4];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < nblk; j += TPB)
+        for (int q = 0; q < 4; ++q) s[q] += part[static_cast<int64_t>(q) * nblk + j];
+    for (int q = 0; q < 4; ++q) {
+        double v = s[q];
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < TPB / 64; ++w) t += red[w][threadIdx.x];
+        const double r = sqrt(t / static_cast<double>(n));
+        scales[threadIdx.x] = r > 0.0 ? r : 1.0;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_gnn_features(int64_t n, const double *b, const double *p1, const double *p2,
+                                                      const double *re, const double *kd, const double *d,
+                                                      const uint8_t *dir, const double *scales, bf16 *x) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    if (i >= n) return;
+    const double sb = scales[0], sp = scales[1], sr = scales[2], sd = scales[3];
+    const double f[GF] = {b[i] / sb, p1[i] / sp, p2[i] / sp, re[i] / sr, kd[i] / sr, d[i] / sd,
+                          static_cast<double>(dir[i]), 1.0};
+    bf16 *o = x + i * GFP;
+#pragma unroll
+    for (int q = 0; q < GF; ++q) o[q] = to_bf16(static_cast<float>(f[q]));
+#pragma unroll
+    for (int q = GF; q < GFP; ++q) o[q] = to_bf16(0.0f);
+}
+
+// ------------------------------------------------------------------ forward layers
+
+// Z tile [TM x 128] in LDS: own h row and the mean of the neighbours' h rows
+__device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const bf16 *h, const int32_t *adj_ptr,
+                               const int32_t *adj_col) {
+    for (int task = threadIdx.x; task < TM * (GH / 8); task += blockDim.x) {
+        const int r = task / (GH / 8), c = (task % (GH / 8)) * 8;
+        const int64_t i = r0 + r;
+        float self[8], acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) self[q] = acc[q] = 0.0f;
+        if (i < n) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) self[q] = from_bf16(h[i * GH + c + q]);
+            int deg = 0;
+            for (int32_t k = adj_ptr[i]; k < adj_ptr[i + 1]; ++k) {
+                const int32_t j = adj_col[k];
+                if (j == i) continue;
+                ++deg;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += from_bf16(h[static_cast<int64_t>(j) * GH + c + q]);
+            }
+            const float inv = deg > 0 ? 1.0f / static_cast<float>(deg) : 0.0f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] *= inv;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            Z[r * (2 * GH) + c + q] = to_bf16(self[q]);
+            Z[r * (2 * GH) + GH + c + q] = to_bf16(acc[q]);
+        }
+    }
+}
+
+// one layer for TM rows: ENC: h = relu(X W0 + c0); else h = relu([h,m] W + c) + h
+template <bool ENC>
+__global__ __launch_bounds__(TPB) void k_gnn_layer(int64_t n, const bf16 *hin, const bf16 *xin, const int32_t *adj_ptr,
+                                                   const int32_t *adj_col, const bf16 *W, const float *c, bf16 *hout,
+                                                   float *aout) {
+    constexpr int K = ENC ? GFP : 2 * GH;
+    __shared__ bf16 Z[TM * K];
+    __shared__ bf16 Ws[K * GH];
+    __shared__ bf16 O[TM * GH];
+    __shared__ float A[TM * GH];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * TM;
+    for (int t = threadIdx.x; t < K * GH; t += TPB) Ws[t] = W[t];
+    if (ENC) {
+        for (int t = threadIdx.x; t < TM * GFP; t += TPB) {
+            const int64_t i = r0 + t / GFP;
+            Z[t] = i < n ? xin[r0 * GFP + t] : to_bf16(0.0f);
+        }
+    } else {
+        build_z(Z, r0, n, hin, adj_ptr, adj_col);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int tr = (wave >> 1) * 32, tc = (wave & 1) * 32;
+    f32x16 acc = {};
+    mfma_tile(acc, Z + tr * K, K, 1, Ws + tc, GH, 1, K);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = tr + acc_row(v), colx = tc + acc_col();
+        const float a = acc[v] + c[colx];
+        float hv = fmaxf(a, 0.0f);
+        if (!ENC) hv += from_bf16(Z[row * K + colx]);
+        O[row * GH + colx] = to_bf16(hv);
+        A[row * GH + colx] = a;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TM * GH; t += TPB) {
+        const int64_t i = r0 + t / GH;
+        if (i < n) {
+            hout[r0 * GH + t] = O[t];
+            if (aout) aout[r0 * GH + t] = A[t];
+        }
+    }
+}
+
+// y = h w_d + c_d; guess = (e + s_d y) on free nodes (optional)
+__global__ __launch_bounds__(TPB) void k_gnn_decode(int64_t n, const bf16 *h, const float *theta, const double *e,
+                                                    const double *scales, const uint8_t *dir, float *y,
+                                                    double *guess) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int q = 0; q < GH; ++q) s += from_bf16(h[i * GH + q]) * theta[P_WD + q];
+    s += theta[P_CD];
+    y[i] = s;
+    if (guess) guess[i] = dir[i] ? 0.0 : e[i] + scales[3] * static_cast<double>(s);
+}
+
+// ------------------------------------------------------------------ training
+
+// delta = (y - (target - e)/s_d) on free nodes
+__global__ __launch_bounds__(TPB) void k_gnn_delta(int64_t n, const float *y, const double *target, const double *e,
+                                                   const double *scales, const uint8_t *dir, double *delta) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    if (i >= n) return;
+    delta[i] = dir[i] ? 0.0 : static_cast<double>(y[i]) - (target[i] - e[i]) / scales[3];
+}
+
+// dy = 2 K delta / N_free on free nodes; per-block partial of delta.K delta
+__global__ __launch_bounds__(TPB) void k_gnn_dy(int64_t n, const int32_t *rowptr, const int32_t *col,
+                                                const double *val, const double *delta, const uint8_t *dir,
+                                                double nfree, float *dy, double *lpart) {
+    __shared__ double red[TPB / 64];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    double l = 0.0;
+    if (i < n) {
+        double kd = 0.0;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) kd += val[k] * delta[col[k]];
+        dy[i] = dir[i] ? 0.0f : static_cast<float>(2.0 * kd / nfree);
+        l = delta[i] * kd;
+    }
+    for (int m = 32; m >= 1; m >>= 1) l += __shfl_xor(l, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < TPB / 64; ++w) t += red[w];
+        lpart[blockIdx.x] = t;
+    }
+}
+
+// loss = sum(lpart) / N_free, added to *out
+__global__ void k_gnn_loss(const double *lpart, int nblk, double nfree, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double t = 0.0;
+    for (int j = 0; j < nblk; ++j) t += lpart[j];
+    *out += t / nfree;
+}
+
+// dh3 = dy w_d^T; partials of h3^T dy (64) and sum(dy) (1) per block: gpart[blk][65]
+__global__ __launch_bounds__(TPB) void k_gnn_dec_bwd(int64_t n, const float *dy, const bf16 *h, const float *theta,
+                                                     float *dh, float *gpart) {
+    __shared__ float red[TPB / 64][GH + 1];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    const float g = i < n ? dy[i] : 0.0f;
+    for (int q = 0; q <= GH; ++q) {
+        float v;
+        if (q < GH) {
+            if (i < n) dh[i * GH + q] = g * theta[P_WD + q];
+            v = i < n ? from_bf16(h[i * GH + q]) * g : 0.0f;
+        } else {
+            v = g;
+        }
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x <= GH) {
+        float t = 0.0f;
+        for (int w = 0; w < TPB / 64; ++w) t += red[w][threadIdx.x];
+        gpart[static_cast<int64_t>(blockIdx.x) * (GH + 1) + threadIdx.x] = t;
+    }
+}
+
+// message layer backward for BW_SUB*TM rows: da = dh * (a > 0);
+// dW partial = Z^T bf16(da), dc partial = colsum(da); dZ = bf16(da) W^T ->
+// dhp = dh + dZ[:, :64], dm = dZ[:, 64:] / deg
+__global__ __launch_bounds__(TPB) void k_gnn_layer_bwd(int64_t n, const bf16 *hin, const int32_t *adj_ptr,
+                                                       const int32_t *adj_col, const bf16 *W, const float *a,
+                                                       const float *dh, float *dhp, float *dm, float *gpart) {
+    constexpr int K = 2 * GH;
+    __shared__ bf16 Z[TM * K];
+    __shared__ bf16 Ws[K * GH];
+    __shared__ bf16 Dq[TM * GH];
+    __shared__ float Df[TM * GH];
+    __shared__ int deg_s[TM];
+    for (int t = threadIdx.x; t < K * GH; t += TPB) Ws[t] = W[t];
+    const int wave = threadIdx.x >> 6;
+    f32x16 gw0 = {}, gw1 = {};         // dW tiles (rows wave*32.., cols 0..31 / 32..63)
+    float dc = 0.0f;                   // column threadIdx.x (< 64) sum of da
+    for (int sub = 0; sub < BW_SUB; ++sub) {
+        const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * BW_SUB + sub) * TM;
+        build_z(Z, r0, n, hin, adj_ptr, adj_col);
+        for (int t = threadIdx.x; t < TM * GH; t += TPB) {
+            const int64_t i = r0 + t / GH;
+            const float v = (i < n && a[r0 * GH + t] > 0.0f) ? dh[r0 * GH + t] : 0.0f;
+            Df[t] = v;
+            Dq[t] = to_bf16(v);
+        }
+        for (int r = threadIdx.x; r < TM; r += TPB) {
+            const int64_t i = r0 + r;
+            int dg = 0;
+            if (i < n)
+                for (int32_t k = adj_ptr[i]; k < adj_ptr[i + 1]; ++k) dg += adj_col[k] != i;
+            deg_s[r] = dg;
+        }
+        __syncthreads();
+        if (threadIdx.x < GH)
+            for (int r = 0; r < TM; ++r) dc += Df[r * GH + threadIdx.x];
+        // dW += Z^T Dq  (K = rows of the sub-tile)
+        mfma_tile(gw0, Z + wave * 32, 1, K, Dq, GH, 1, TM);
+        mfma_tile(gw1, Z + wave * 32, 1, K, Dq + 32, GH, 1, TM);
+        // dZ = Dq W^T: output [TM x 128]; wave: row tile (wave>>1)*32, column tiles 2*(wave&1), +1
+        const int tr = (wave >> 1) * 32;
+        for (int ct = 0; ct < 2; ++ct) {
+            const int tc = (2 * (wave & 1) + ct) * 32;
+            f32x16 acc = {};
+            mfma_tile(acc, Dq + tr * GH, GH, 1, Ws + tc * GH, 1, GH, GH);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = tr + acc_row(v), colx = tc + acc_col();
+                const int64_t i = r0 + row;
+                if (i >= n) continue;
+                if (colx < GH)
+                    dhp[i * GH + colx] = dh[i * GH + colx] + acc[v];
+                else
+                    dm[i * GH + colx - GH] = deg_s[row] > 0 ? acc[v] / static_cast<float>(deg_s[row]) : 0.0f;
+            }
+        }
+        __syncthreads();
+    }
+    float *g = gpart + static_cast<int64_t>(blockIdx.x) * (K * GH + GH);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = wave * 32 + acc_row(v), colx = acc_col();
+        g[row * GH + colx] = gw0[v];
+        g[row * GH + 32 + colx] = gw1[v];
+    }
+    if (threadIdx.x < GH) g[K * GH + threadIdx.x] = dc;
+}
+
+// dh_prev_j = dhp_j + sum over neighbours i of dm_i (the mean's transpose; adjacency is symmetric)
+__global__ __launch_bounds__(TPB) void k_gnn_agg_bwd(int64_t n, const int32_t *adj_ptr, const int32_t *adj_col,
+                                                     const float *dhp, const float *dm, float *dh) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    const int64_t j = t / (GH / 8);
+    if (j >= n) return;
+    const int c = static_cast<int>(t % (GH / 8)) * 8;
+    float s[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] = dhp[j * GH + c + q];
+    for (int32_t k = adj_ptr[j]; k < adj_ptr[j + 1]; ++k) {
+        const int32_t i = adj_col[k];
+        if (i == j) continue;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s[q] += dm[static_cast<int64_t>(i) * GH + c + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dh[j * GH + c + q] = s[q];
+}
+
+// encoder backward for BW_SUB*TM rows: partials of X^T bf16(da0) (16x64) and colsum(da0)
+__global__ __launch_bounds__(TPB) void k_gnn_enc_bwd(int64_t n, const bf16 *x, const float *a, const float *dh,
+                                                     float *gpart) {
+    __shared__ float Xs[TM * GFP];
+    __shared__ float Dq[TM * GH];
+    __shared__ float Df[TM * GH];
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // outputs threadIdx.x + 256 q of the 16x64 block
+    float dc = 0.0f;
+    for (int sub = 0; sub < BW_SUB; ++sub) {
+        const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * BW_SUB + sub) * TM;
+        for (int t = threadIdx.x; t < TM * GFP; t += TPB) {
+            const int64_t i = r0 + t / GFP;
+            Xs[t] = i < n ? from_bf16(x[r0 * GFP + t]) : 0.0f;
+        }
+        for (int t = threadIdx.x; t < TM * GH; t += TPB) {
+            const int64_t i = r0 + t / GH;
+            const float v = (i < n && a[r0 * GH + t] > 0.0f) ? dh[r0 * GH + t] : 0.0f;
+            Df[t] = v;
+            Dq[t] = from_bf16(to_bf16(v));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = threadIdx.x + TPB * q, k = o / GH, c = o % GH;
+            for (int r = 0; r < TM; ++r) acc[q] += Xs[r * GFP + k] * Dq[r * GH + c];
+        }
+        if (threadIdx.x < GH)
+            for (int r = 0; r < TM; ++r) dc += Df[r * GH + threadIdx.x];
+        __syncthreads();
+    }
+    float *g = gpart + static_cast<int64_t>(blockIdx.x) * (GFP * GH + GH);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g[threadIdx.x + TPB * q] = acc[q];
+    if (threadIdx.x < GH) g[GFP * GH + threadIdx.x] = dc;
+}
+
+// grad[off + p] = sum over blocks of gpart[blk * stride + p], p < count (fixed order)
+__global__ __launch_bounds__(TPB) void k_gnn_reduce(const float *gpart, int nblk, int stride, int count, float *grad,
+                                                    int off) {
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= count) return;
+    float t = 0.0f;
+    for (int b = 0; b < nblk; ++b) t += gpart[static_cast<int64_t>(b) * stride + p];
+    grad[off + p] = t;
+}
+
+// Adam on the fp32 master weights, then the bf16 copies of the matrices
+__global__ __launch_bounds__(TPB) void k_gnn_adam(float *theta, float *m1, float *m2, const float *grad, float lr,
+                                                  float b1, float b2, float c1, float c2, float eps) {
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= P_COUNT) return;
+    const float g = grad[p];
+    const float m = b1 * m1[p] + (1.0f - b1) * g;
+    const float v = b2 * m2[p] + (1.0f - b2) * g * g;
+    m1[p] = m;
+    m2[p] = v;
+    theta[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+__global__ __launch_bounds__(TPB) void k_gnn_quantize(const float *theta, bf16 *wq) {
+    const int q = blockIdx.x * TPB + threadIdx.x;
+    if (q >= Q_COUNT) return;
+    int src;
+    if (q < GFP * GH) {
+        src = P_W0 + q;
+    } else {
+        const int l = (q - GFP * GH) / (2 * GH * GH), o = (q - GFP * GH) % (2 * GH * GH);
+        src = P_L0 + l * P_LSTRIDE + o;
+    }
+    wq[q] = to_bf16(theta[src]);
+}
+
+// ------------------------------------------------------------------ host side
+
+GnnWork &work_for(Model &md, const Mesh &m, bool training) {
+    auto &slot = md.work[&m];
+    if (!slot) slot = std::make_unique<GnnWork>();
+    GnnWork &w = *slot;
+    const int64_t n = m.lv[0].n;
+    if (w.n != n) {
+        w = GnnWork();
+        w.n = n;
+        w.e.alloc(n);
+        w.d.alloc(n);
+        w.re.alloc(n);
+        w.kd.alloc(n);
+        w.part.alloc(4 * blocks_for(n, TPB));
+        w.scales.alloc(4);
+        w.x.alloc(n * GFP);
+        for (auto &h : w.h) h.alloc(n * GH);
+        w.y.alloc(n);
+    }
+    if (training && w.dy.n == 0) {
+        for (auto &a : w.a) a.alloc(n * GH);
+        w.delta.alloc(n);
+        w.dy.alloc(n);
+        w.dh.alloc(n * GH);
+        w.dhp.alloc(n * GH);
+        w.dm.alloc(n * GH);
+        const int64_t nbw = (n + BW_SUB * TM - 1) / (BW_SUB * TM);
+        w.gpart.alloc(std::max<int64_t>(nbw * (2 * GH * GH + GH), blocks_for(n, TPB) * (GH + 1)));
+        w.grad.alloc(P_COUNT);
+        w.lpart.alloc(blocks_for(n, TPB));
+    }
+    return w;
+}
+
+// features + forward; a[] saved when training; guess written when non-null
+void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *b, const double *p1,
+             const double *p2, double *guess, bool training) {
+    const int64_t n = m.lv[0].n;
+    const unsigned nb = blocks_for(n, TPB);
+    hipLaunchKernelGGL(k_gnn_prep, dim3(nb), dim3(TPB), 0, s, n, m.rowptr.p, m.col.p, m.val.p, b, p1, p2, w.e.p,
+                       w.d.p, w.re.p, w.kd.p, w.part.p);
+    hipLaunchKernelGGL(k_gnn_scales, dim3(1), dim3(TPB), 0, s, n, w.part.p, static_cast<int>(nb), w.scales.p);
+    hipLaunchKernelGGL(k_gnn_features, dim3(nb), dim3(TPB), 0, s, n, b, p1, p2, w.re.p, w.kd.p, w.d.p,
+                       m.lv[0].dir.p, w.scales.p, w.x.p);
+    const unsigned nt = static_cast<unsigned>((n + TM - 1) / TM);
+    const float *th = md.theta.p;
+    hipLaunchKernelGGL((k_gnn_layer<true>), dim3(nt), dim3(TPB), 0, s, n, nullptr, w.x.p, nullptr, nullptr,
+                       md.wq.p + Q_W0, th + P_C0, w.h[0].p, training ? w.a[0].p : nullptr);
+    for (int l = 1; l <= GL; ++l)
+        hipLaunchKernelGGL((k_gnn_layer<false>), dim3(nt), dim3(TPB), 0, s, n, w.h[l - 1].p, nullptr,
+                           m.adj_ptr.p, m.adj_col.p, md.wq.p + GFP * GH + (l - 1) * 2 * GH * GH,
+                           th + P_L0 + (l - 1) * P_LSTRIDE + 2 * GH * GH, w.h[l].p,
+                           training ? w.a[l].p : nullptr);
+    hipLaunchKernelGGL(k_gnn_decode, dim3(nb), dim3(TPB), 0, s, n, w.h[GL].p, th, w.e.p, w.scales.p,
+                       m.lv[0].dir.p, w.y.p, guess);
+    CGP_HIP(hipGetLastError());
+}
+
+double count_free(hipStream_t s, const Mesh &m) {
+    std::vector<uint8_t> d(m.lv[0].n);
+    CGP_HIP(hipMemcpyAsync(d.data(), m.lv[0].dir.p, d.size(), hipMemcpyDeviceToHost, s));
+    CGP_HIP(hipStreamSynchronize(s));
+    double f = 0.0;
+    for (uint8_t v : d) f += v ? 0.0 : 1.0;
+    return f > 0.0 ? f : 1.0;
+}
+
+// one sample: forward, loss (added to *loss_dev), gradient into w.grad
+void loss_grad(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *b, const double *p1,
+               const double *p2, const double *target, double nfree, double *loss_dev) {
+    const int64_t n = m.lv[0].n;
+    const unsigned nb = blocks_for(n, TPB);
+    forward(s, md, m, w, b, p1, p2, nullptr, true);
+    hipLaunchKernelGGL(k_gnn_delta, dim3(nb), dim3(TPB), 0, s, n, w.y.p, target, w.e.p, w.scales.p,
+                       m.lv[0].dir.p, w.delta.p);
+    hipLaunchKernelGGL(k_gnn_dy, dim3(nb), dim3(TPB), 0, s, n, m.rowptr.p, m.col.p, m.val.p, w.delta.p,
+                       m.lv[0].dir.p, nfree, w.dy.p, w.lpart.p);
+    hipLaunchKernelGGL(k_gnn_loss, dim3(1), dim3(64), 0, s, w.lpart.p, static_cast<int>(nb), nfree, loss_dev);
+    // decoder
+    hipLaunchKernelGGL(k_gnn_dec_bwd, dim3(nb), dim3(TPB), 0, s, n, w.dy.p, w.h[GL].p, md.theta.p, w.dh.p,
+                       w.gpart.p);
+    hipLaunchKernelGGL(k_gnn_reduce, dim3(1), dim3(TPB), 0, s, w.gpart.p, static_cast<int>(nb), GH + 1, GH + 1,
+                       w.grad.p, P_WD);
+    const unsigned nbw = static_cast<unsigned>((n + BW_SUB * TM - 1) / (BW_SUB * TM));
+    const int lstride = 2 * GH * GH + GH;
+    for (int l = GL; l >= 1; --l) {
+        hipLaunchKernelGGL(k_gnn_layer_bwd, dim3(nbw), dim3(TPB), 0, s, n, w.h[l - 1].p, m.adj_ptr.p, m.adj_col.p,
+                           md.wq.p + GFP * GH + (l - 1) * 2 * GH * GH, w.a[l].p, w.dh.p, w.dhp.p, w.dm.p,
+                           w.gpart.p);
+        hipLaunchKernelGGL(k_gnn_reduce, dim3(blocks_for(lstride, TPB)), dim3(TPB), 0, s, w.gpart.p,
+                           static_cast<int>(nbw), lstride, lstride, w.grad.p, P_L0 + (l - 1) * P_LSTRIDE);
+        hipLaunchKernelGGL(k_gnn_agg_bwd, dim3(blocks_for(n * (GH / 8), TPB)), dim3(TPB), 0, s, n, m.adj_ptr.p,
+                           m.adj_col.p, w.dhp.p, w.dm.p, w.dh.p);
+    }
+    hipLaunchKernelGGL(k_gnn_enc_bwd, dim3(nbw), dim3(TPB), 0, s, n, w.x.p, w.a[0].p, w.dh.p, w.gpart.p);
+    hipLaunchKernelGGL(k_gnn_reduce, dim3(blocks_for(GFP * GH + GH, TPB)), dim3(TPB), 0, s, w.gpart.p,
+                       static_cast<int>(nbw), GFP * GH + GH, GFP * GH + GH, w.grad.p, P_W0);
+    CGP_HIP(hipGetLastError());
+}
+
+uint64_t splitmix64(uint64_t &x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double gauss(uint64_t &st) {
+    const double u1 = (static_cast<double>(splitmix64(st) >> 11) + 0.5) / 9007199254740992.0;
+    const double u2 = (static_cast<double>(splitmix64(st) >> 11) + 0.5) / 9007199254740992.0;
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+void upload_params(hipStream_t s, Model &md, const float *h) {
+    CGP_HIP(hipMemcpyAsync(md.theta.p, h, P_COUNT * sizeof(float), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_gnn_quantize, dim3(blocks_for(Q_COUNT, TPB)), dim3(TPB), 0, s, md.theta.p, md.wq.p);
+    CGP_HIP(hipGetLastError());
+    CGP_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+int64_t gnn_param_count() { return P_COUNT; }
+
+Model *gnn_create(hipStream_t s, uint64_t seed) {
+    auto md = std::make_unique<Model>();
+    md->theta.alloc(P_COUNT);
+    md->m1.alloc(P_COUNT);
+    md->m2.alloc(P_COUNT);
+    md->wq.alloc(Q_COUNT);
+    CGP_HIP(hipMemsetAsync(md->m1.p, 0, P_COUNT * sizeof(float), s));
+    CGP_HIP(hipMemsetAsync(md->m2.p, 0, P_COUNT * sizeof(float), s));
+    // He-normal weights (std sqrt(2 / fan_in)) from a splitmix64 stream; zero biases;
+    // a small decoder so the first guesses stay close to the extrapolation
+    std::vector<float> h(P_COUNT, 0.0f);
+    uint64_t st = seed;
+    for (int k = 0; k < GF; ++k)
+        for (int c = 0; c < GH; ++c) h[P_W0 + k * GH + c] = static_cast<float>(gauss(st) * std::sqrt(2.0 / GF));
+    for (int l = 0; l < GL; ++l)
+        for (int q = 0; q < 2 * GH * GH; ++q)
+            h[P_L0 + l * P_LSTRIDE + q] = static_cast<float>(gauss(st) * std::sqrt(2.0 / (2 * GH)) * 0.5);
+    for (int q = 0; q < GH; ++q) h[P_WD + q] = static_cast<float>(gauss(st) * 0.01);
+    upload_params(s, *md, h.data());
+    return md.release();
+}
+
+void gnn_set_params(hipStream_t s, Model &md, const float *h) {
+    upload_params(s, md, h);
+    CGP_HIP(hipMemsetAsync(md.m1.p, 0, P_COUNT * sizeof(float), s));
+    CGP_HIP(hipMemsetAsync(md.m2.p, 0, P_COUNT * sizeof(float), s));
+    md.step = 0;
+}
+
+void gnn_get_params(hipStream_t s, Model &md, float *h) {
+    CGP_HIP(hipMemcpyAsync(h, md.theta.p, P_COUNT * sizeof(float), hipMemcpyDeviceToHost, s));
+    CGP_HIP(hipStreamSynchronize(s));
+}
+
+void gnn_predict(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
+                 double *guess) {
+    GnnWork &w = work_for(md, m, false);
+    forward(s, md, m, w, b, p1, p2, guess, false);
+}
+
+void gnn_grad(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
+              const double *target, double *h_loss, float *h_grad) {
+    GnnWork &w = work_for(md, m, true);
+    const double nfree = count_free(s, m);
+    DBuf<double> loss;
+    loss.alloc(1);
+    CGP_HIP(hipMemsetAsync(loss.p, 0, sizeof(double), s));
+    loss_grad(s, md, m, w, b, p1, p2, target, nfree, loss.p);
+    if (h_loss) CGP_HIP(hipMemcpyAsync(h_loss, loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (h_grad) CGP_HIP(hipMemcpyAsync(h_grad, w.grad.p, P_COUNT * sizeof(float), hipMemcpyDeviceToHost, s));
+    CGP_HIP(hipStreamSynchronize(s));
+}
+
+void gnn_train(hipStream_t s, Model &md, const Mesh &m, int n_samples, const double *const *b,
+               const double *const *p1, const double *const *p2, const double *const *target, int epochs,
+               double lr, uint64_t seed, double *h_loss) {
+    GnnWork &w = work_for(md, m, true);
+    const double nfree = count_free(s, m);
+    DBuf<double> losses;
+    losses.alloc(epochs);
+    CGP_HIP(hipMemsetAsync(losses.p, 0, epochs * sizeof(double), s));
+    std::vector<int> order(n_samples);
+    for (int i = 0; i < n_samples; ++i) order[i] = i;
+    uint64_t st = seed;
+    const float b1 = 0.9f, b2 = 0.999f;
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int i = n_samples - 1; i > 0; --i) std::swap(order[i], order[splitmix64(st) % (i + 1)]);
+        for (int k = 0; k < n_samples; ++k) {
+            const int q = order[k];
+            loss_grad(s, md, m, w, b[q], p1[q], p2[q], target[q], nfree, losses.p + ep);
+            ++md.step;
+            const float c1 = 1.0f - std::pow(b1, static_cast<float>(md.step));
+            const float c2 = 1.0f - std::pow(b2, static_cast<float>(md.step));
+            hipLaunchKernelGGL(k_gnn_adam, dim3(blocks_for(P_COUNT, TPB)), dim3(TPB), 0, s, md.theta.p, md.m1.p,
+                               md.m2.p, w.grad.p, static_cast<float>(lr), b1, b2, c1, c2, 1e-8f);
+            hipLaunchKernelGGL(k_gnn_quantize, dim3(blocks_for(Q_COUNT, TPB)), dim3(TPB), 0, s, md.theta.p,
+                               md.wq.p);
+            CGP_HIP(hipGetLastError());
+        }
+    }
+    std::vector<double> hl(epochs);
+    CGP_HIP(hipMemcpyAsync(hl.data(), losses.p, epochs * sizeof(double), hipMemcpyDeviceToHost, s));
+    CGP_HIP(hipStreamSynchronize(s));
+    if (h_loss)
+        for (int e = 0; e < epochs; ++e) h_loss[e] = hl[e] / n_samples;
+}
+
+void gnn_release_mesh(Model &md, const Mesh *m) { md.work.erase(m); }
+
+void gnn_destroy(Model *md) { delete md; }
+
+}  // namespace cgp

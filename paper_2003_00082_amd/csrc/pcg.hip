@@ -65,7 +65,7 @@ __device__ __forceinline__ CGP_GLOBAL T *gst(T *p) {
 enum State : int32_t {
     ST_BOOT = 0,  // before the first stage
     ST_PREP,      // x = initial guess (ZERO / EXTRAP)
-    ST_JUDGE,     // LEARNED: residual norms of the network guess and of prev1
+    ST_JUDGE,     // LEARNED: energy-norm comparison of the network guess with prev1
     ST_PICK,      // LEARNED rejected: x = prev1
     ST_RES,       // r = b - K x (fp64)
     ST_START,     // u = M^-1 r, w = K u, reductions gamma, delta, sigma
@@ -132,9 +132,9 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
         c.state = ST_RES;
         break;
     case ST_JUDGE: {
-        const double rl = S[0], rp = S[1];
+        const double rl = S[0], rp = S[1], gain = S[3];
         const double bn = sqrt(S[2]) > 0.0 ? sqrt(S[2]) : 1.0;
-        if (rl <= rp && isfinite(rl)) {   // a non-finite network output is rejected
+        if (gain >= 0.0 && isfinite(rl) && isfinite(gain)) {   // a non-finite network output is rejected
             c.guess_used = CGP_GUESS_LEARNED;
             c.rel_res_guess = sqrt(rl) / bn;
             c.state = ST_RES;
@@ -351,16 +351,21 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
         break;
     case ST_JUDGE: {
         const double *p1 = D.prev1;
+        // J(x) = x.Kx / 2 - b.x = -x.(b + r) / 2 differs from the energy-norm error
+        // |x - x*|_K^2 / 2 by a constant, so v[3] = J(prev1) - J(guess) (times 2) > 0
+        // says the network's guess is the closer one in the norm CG minimises
         staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return x[j]; },
                                nop, [&](int32_t i, double y, double) {
                                    const double r = b[i] - y;
                                    v[0] += r * r;
                                    v[2] += b[i] * b[i];
+                                   v[3] += x[i] * (b[i] + r);
                                });
         staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return p1[j]; },
                                nop, [&](int32_t i, double y, double) {
                                    const double r = b[i] - y;
                                    v[1] += r * r;
+                                   v[3] -= p1[i] * (b[i] + r);
                                });
         break;
     }

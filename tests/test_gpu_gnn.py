@@ -1,0 +1,257 @@
+"""Learned initial guess on the GPU (through the C ABI) against the network oracle.
+
+The device computes the dense products with bfloat16 operands and fp32
+accumulation, the oracle with the same bfloat16 roundings and fp64 sums.  The
+two round the same values; they differ only where an fp32 sum and its fp64
+counterpart fall on opposite sides of a bfloat16 rounding boundary, which moves
+that one value by one bfloat16 step (2^-8 relative).  Measured on 777 nodes the
+network output then differs by at most 1.2e-4 and every gradient block by at
+most 2e-4 (norm-wise, relative); the tolerances below (1e-3, 2e-3) sit well
+above that and well below the 2.5e-3 .. 3e-2 gap between the bfloat16-emulating
+oracle and plain fp64, so a device that skipped a rounding the oracle makes, or
+made one the oracle does not, fails them.
+"""
+import numpy as np
+import pytest
+
+import cgp_inputs as ci
+from oracle import fem, gnn, solve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+def dt(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def cgp():
+    import paper_2003_00082_amd as lib
+    lib.load()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def ctx(cgp):
+    c = cgp.Context(0)
+    yield c
+    c.close()
+
+
+class Seq:
+    """Coarse right-hand sides and exact solutions of the phi equation over time steps."""
+
+    def __init__(self, nx, ny, seed, steps):
+        self.m = ci.jittered_rect(nx, ny, seed)
+        m = self.m
+        self.a = fem.system_matrix(m.xy, m.tri, m.dirichlet)
+        self.mo = gnn.neighbour_mean_operator(gnn.triangle_adjacency(m.n_nodes, m.tri))
+        sq = ci.FourierSequence(m.xy, ci.fourier_modes(seed + 1), ci.fourier_modes(seed + 2))
+        self.b, self.x = [], []
+        for n in range(steps):
+            u, v, _, _ = sq.at(n)
+            b = fem.source(m.xy, m.tri, m.dirichlet, u, v, fem.CURL, 1.0)
+            self.b.append(b)
+            self.x.append(solve.direct(self.a, b))
+
+    def sample(self, n):
+        """(b, prev1, prev2, target) of step n >= 2."""
+        return self.b[n], self.x[n - 1], self.x[n - 2], self.x[n]
+
+
+@pytest.fixture(scope="module")
+def seq(ctx):
+    s = Seq(37, 21, 4100, 40)        # 777 nodes: 12 full 64-row tiles and a ragged tail of 9
+    s.handle = ctx.mesh_upload(s.m.xy, s.m.tri, s.m.dirichlet, 1)
+    yield s
+    ctx.mesh_free(s.handle)
+
+
+def random_theta(seed):
+    """He-scaled random parameters (float32 values) with non-zero biases."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shape in gnn.param_shapes():
+        fan = shape[0] if len(shape) == 2 else 64
+        p[name] = rng.standard_normal(shape) * (np.sqrt(2.0 / fan) if len(shape) == 2 else 0.1)
+    p["W0"][8:] = 0.0
+    p["wd"] = rng.standard_normal(64) * 0.2
+    return gnn.pack(p).astype(np.float32)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_param_count_matches_oracle(cgp):
+    assert cgp.Context.model_param_count() == gnn.param_count()
+
+
+def test_params_roundtrip_and_file(ctx, cgp, tmp_path):
+    md = ctx.model_create(seed=9)
+    try:
+        th = random_theta(1)
+        ctx.model_set_params(md, th)
+        np.testing.assert_array_equal(ctx.model_get_params(md), th)
+        path = str(tmp_path / "m.bin")
+        ctx.model_save(md, path)
+        m2 = ctx.model_load(path)
+        np.testing.assert_array_equal(ctx.model_get_params(m2), th)
+        ctx.model_free(m2)
+        bad = tmp_path / "bad.bin"
+        bad.write_bytes(b"not a model")
+        with pytest.raises(cgp.CGPError):
+            ctx.model_load(str(bad))
+    finally:
+        ctx.model_free(md)
+    with pytest.raises(cgp.CGPError):
+        ctx.model_free(md)
+
+
+def test_created_models_are_seeded(ctx):
+    a, b, c = ctx.model_create(seed=5), ctx.model_create(seed=5), ctx.model_create(seed=6)
+    pa, pb, pc = (ctx.model_get_params(h) for h in (a, b, c))
+    for h in (a, b, c):
+        ctx.model_free(h)
+    np.testing.assert_array_equal(pa, pb)
+    assert not np.array_equal(pa, pc)
+    assert np.all(pa[8 * 64:16 * 64] == 0)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_predict_matches_oracle(ctx, seq, seed):
+    th = random_theta(seed)
+    md = ctx.model_create()
+    try:
+        ctx.model_set_params(md, th)
+        for n in (2, 17):
+            b, p1, p2, _ = seq.sample(n)
+            g = torch.full((seq.m.n_nodes,), np.nan, dtype=torch.float64, device=DEV)
+            ctx.model_predict(md, seq.handle, dt(b), dt(p1), dt(p2), g)
+            ctx.sync()
+            got = g.cpu().numpy()
+            x, e, sd = gnn.features(seq.a, seq.m.dirichlet, b, p1, p2)
+            y_ref, _ = gnn.forward(th.astype(np.float64), x, seq.mo, emulate=True)
+            free = seq.m.dirichlet == 0
+            np.testing.assert_array_equal(got[~free], 0.0)
+            y_got = (got[free] - e[free]) / sd
+            assert rel(y_got, y_ref[free]) <= 1e-3
+    finally:
+        ctx.model_free(md)
+
+
+def test_grad_matches_oracle(ctx, seq):
+    th = random_theta(3)
+    md = ctx.model_create()
+    try:
+        ctx.model_set_params(md, th)
+        b, p1, p2, tgt = seq.sample(9)
+        loss, g = ctx.model_grad(md, seq.handle, dt(b), dt(p1), dt(p2), dt(tgt))
+        lref, gref = gnn.loss_and_grad(th.astype(np.float64), seq.a, seq.m.dirichlet, b, p1, p2, tgt, seq.mo,
+                                       emulate=True)
+        assert loss == pytest.approx(lref, rel=5e-4)
+        offs = np.cumsum([0] + [int(np.prod(s)) for _, s in gnn.param_shapes()])
+        for q, (name, _) in enumerate(gnn.param_shapes()):
+            gs, rs = g[offs[q]:offs[q + 1]], gref[offs[q]:offs[q + 1]]
+            assert rel(gs.astype(np.float64), rs) <= 2e-3, name
+        np.testing.assert_array_equal(g[8 * 64:16 * 64], 0.0)
+    finally:
+        ctx.model_free(md)
+
+
+def _train(ctx, seq, steps, epochs, lr=2e-3, seed=0, model_seed=1):
+    md = ctx.model_create(seed=model_seed)
+    smp = [seq.sample(n) for n in steps]
+    cols = [[dt(s[i]) for s in smp] for i in range(4)]
+    hist = ctx.model_train(md, seq.handle, *cols, epochs=epochs, lr=lr, seed=seed)
+    return md, hist
+
+
+def test_training_reduces_loss_and_is_reproducible(ctx, seq):
+    md1, h1 = _train(ctx, seq, range(2, 14), 30)
+    md2, h2 = _train(ctx, seq, range(2, 14), 30)
+    try:
+        assert np.all(np.isfinite(h1))
+        np.testing.assert_array_equal(h1, h2)                       # fixed-order sums: bitwise
+        np.testing.assert_array_equal(ctx.model_get_params(md1), ctx.model_get_params(md2))
+        assert h1[-1] < 1e-2 * h1[0], h1
+    finally:
+        ctx.model_free(md1)
+        ctx.model_free(md2)
+
+
+def _energy(a, e):
+    return float(e @ (a @ e))
+
+
+def test_learned_guess_beats_extrapolation_on_held_out_steps(ctx, cgp, seq):
+    md, _ = _train(ctx, seq, range(2, 26), 40)
+    try:
+        gain = []
+        for n in range(26, 40):
+            b, p1, p2, tgt = seq.sample(n)
+            g = torch.empty(seq.m.n_nodes, dtype=torch.float64, device=DEV)
+            ctx.model_predict(md, seq.handle, dt(b), dt(p1), dt(p2), g)
+            ctx.sync()
+            el = _energy(seq.a, g.cpu().numpy() - tgt)
+            ee = _energy(seq.a, (2 * p1 - p2) * (seq.m.dirichlet == 0) - tgt)
+            ep = _energy(seq.a, p1 - tgt)
+            gain.append(el / ee)
+            # inside the solver the guess is kept exactly when its energy-norm error is the smaller
+            phi = torch.zeros(seq.m.n_nodes, dtype=torch.float64, device=DEV)
+            stats = cgp.stats_buffer(1)
+            ctx.poisson_solve([seq.handle], [dt(b)], [phi], stats, prev1=[dt(p1)], prev2=[dt(p2)],
+                              precision=cgp.CGP_FP32_IR, guess=cgp.CGP_GUESS_LEARNED, model=md, tol=1e-8)
+            st = ctx.solve_check(1, stats)[0]
+            assert st["status"] == "ok"
+            if abs(el - ep) > 1e-9 * ep:
+                assert st["guess_used"] == (cgp.CGP_GUESS_LEARNED if el < ep else cgp.CGP_GUESS_GIVEN)
+        # energy-norm error of the learned guess relative to the extrapolation's
+        assert np.mean(gain) < 0.1, gain
+    finally:
+        ctx.model_free(md)
+
+
+@pytest.mark.parametrize("engine", [1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_learned_solve(ctx, cgp, seq, engine, precision):
+    md = ctx.model_create(seed=2)
+    bad = ctx.model_create(seed=3)
+    try:
+        p = gnn.unpack(ctx.model_get_params(md).astype(np.float64))
+        p["wd"][:] = 0.0
+        p["cd"][:] = 0.0                      # network output 0: the guess is the extrapolation
+        ctx.model_set_params(md, gnn.pack(p).astype(np.float32))
+        p["cd"][:] = 1e6                      # a far-off guess the solver must reject
+        ctx.model_set_params(bad, gnn.pack(p).astype(np.float32))
+        b, p1, p2, tgt = seq.sample(20)
+        tol = 1e-8
+        for model, want in ((md, cgp.CGP_GUESS_LEARNED), (bad, cgp.CGP_GUESS_GIVEN)):
+            phi = torch.zeros(seq.m.n_nodes, dtype=torch.float64, device=DEV)
+            stats = cgp.stats_buffer(1)
+            ctx.poisson_solve([seq.handle], [dt(b)], [phi], stats, prev1=[dt(p1)], prev2=[dt(p2)],
+                              precision=precision, guess=cgp.CGP_GUESS_LEARNED, model=model, tol=tol, engine=engine)
+            st = ctx.solve_check(1, stats)[0]
+            assert st["status"] == "ok" and st["rel_res"] <= tol
+            assert st["guess_used"] == want
+            x = phi.cpu().numpy()
+            assert rel(x, tgt) <= (1e-6 if precision else 1e-7)
+            start = (2 * p1 - p2) * (seq.m.dirichlet == 0) if want == cgp.CGP_GUESS_LEARNED else p1
+            r0 = solve.relative_residual(seq.a, b, start)
+            assert st["rel_res_guess"] == pytest.approx(r0, rel=1e-6)
+    finally:
+        ctx.model_free(md)
+        ctx.model_free(bad)
+
+
+def test_learned_solve_needs_a_model(ctx, cgp, seq):
+    b, p1, p2, _ = seq.sample(5)
+    phi = torch.zeros(seq.m.n_nodes, dtype=torch.float64, device=DEV)
+    stats = cgp.stats_buffer(1)
+    with pytest.raises(cgp.CGPError):
+        ctx.poisson_solve([seq.handle], [dt(b)], [phi], stats, prev1=[dt(p1)], prev2=[dt(p2)],
+                          guess=cgp.CGP_GUESS_LEARNED, model=12345, tol=1e-8)
