@@ -57,7 +57,7 @@ struct GnnWork {
 
 struct Model {
     DBuf<float> theta, m1, m2;
-    DBuf<bf16> wq;
+    DBuf<bf16> wq, wqT;       // bf16 weight matrices, row-major and transposed
     int64_t step = 0;
     std::map<const Mesh *, std::unique_ptr<GnnWork>> work;
 };
@@ -150,21 +150,6 @@ __global__ __launch_bounds__(TPB) void k_gnn_scales(int64_t n, const double *par
     }
 }
 
-__global__ __launch_bounds__(TPB) void k_gnn_features(int64_t n, const double *b, const double *p1, const double *p2,
-                                                      const double *re, const double *kd, const double *d,
-                                                      const uint8_t *dir, const double *scales, bf16 *x) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
-    if (i >= n) return;
-    const double sb = scales[0], sp = scales[1], sr = scales[2], sd = scales[3];
-    const double f[GF] = {b[i] / sb, p1[i] / sp, p2[i] / sp, re[i] / sr, kd[i] / sr, d[i] / sd,
-                          static_cast<double>(dir[i]), 1.0};
-    bf16 *o = x + i * GFP;
-#pragma unroll
-    for (int q = 0; q < GF; ++q) o[q] = to_bf16(static_cast<float>(f[q]));
-#pragma unroll
-    for (int q = GF; q < GFP; ++q) o[q] = to_bf16(0.0f);
-}
-
 // ------------------------------------------------------------------ forward layers
 
 // Z tile [TM x 128] in LDS: own h row and the mean of the neighbours' h rows
@@ -199,61 +184,153 @@ __device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const bf16 *h, co
     }
 }
 
-// one layer for TM rows: ENC: h = relu(X W0 + c0); else h = relu([h,m] W + c) + h
-template <bool ENC>
-__global__ __launch_bounds__(TPB) void k_gnn_layer(int64_t n, const bf16 *hin, const bf16 *xin, const int32_t *adj_ptr,
-                                                   const int32_t *adj_col, const bf16 *W, const float *c, bf16 *hout,
-                                                   float *aout) {
-    constexpr int K = ENC ? GFP : 2 * GH;
-    __shared__ bf16 Z[TM * K];
-    __shared__ bf16 Ws[K * GH];
-    __shared__ bf16 O[TM * GH];
-    __shared__ float A[TM * GH];
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * TM;
-    for (int t = threadIdx.x; t < K * GH; t += TPB) Ws[t] = W[t];
-    if (ENC) {
-        for (int t = threadIdx.x; t < TM * GFP; t += TPB) {
-            const int64_t i = r0 + t / GFP;
-            Z[t] = i < n ? xin[r0 * GFP + t] : to_bf16(0.0f);
-        }
-    } else {
-        build_z(Z, r0, n, hin, adj_ptr, adj_col);
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6;
-    const int tr = (wave >> 1) * 32, tc = (wave & 1) * 32;
-    f32x16 acc = {};
-    mfma_tile(acc, Z + tr * K, K, 1, Ws + tc, GH, 1, K);
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int row = tr + acc_row(v), colx = tc + acc_col();
-        const float a = acc[v] + c[colx];
-        float hv = fmaxf(a, 0.0f);
-        if (!ENC) hv += from_bf16(Z[row * K + colx]);
-        O[row * GH + colx] = to_bf16(hv);
-        A[row * GH + colx] = a;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < TM * GH; t += TPB) {
-        const int64_t i = r0 + t / GH;
-        if (i < n) {
-            hout[r0 * GH + t] = O[t];
-            if (aout) aout[r0 * GH + t] = A[t];
-        }
-    }
-}
+// Forward layer, one wavefront per 32-row tile; a workgroup takes groups of four
+// consecutive tiles (grid-stride, the same trip count for all its wavefronts).  The
+// MFMA A operand of lane l is row l%32, columns 8(l/32)..+7 of each 16-wide k step,
+// i.e. the 16-byte chunks 2s + l/32 of the row: the lane gathers exactly those chunks
+// of its own row and of its neighbours straight into registers.  Weights arrive
+// transposed ([64 x K] bf16) and are shared through LDS rows padded by 16 bytes; the
+// accumulator tile goes back through LDS so that each lane finishes its own row's
+// chunks (residual from the registers it gathered, 16-byte stores).
+//   MODE 0  encoder: features of the row computed here from b, p1, p2, r_e, K d, d
+//   MODE 1  message layer: h' = relu([h, mean_nbr h] W + c) + h
+//   MODE 2  message layer + decoder: y = h' w_d + c_d, guess = e + s_d y on free nodes
+struct FwdArgs {
+    int64_t n;
+    const int32_t *adj_ptr, *adj_col;
+    const bf16 *hin;
+    const double *b, *p1, *p2, *re, *kd, *d, *e, *scales;
+    const uint8_t *dir;
+    const bf16 *wT;
+    const float *bias;
+    const float *wd;      // w_d [64] then c_d
+    bf16 *hout;
+    float *aout;          // pre-activations (training) or null
+    bf16 *xout;           // encoder: features (training) or null
+    float *yout;          // decoder: network output or null
+    double *guess;        // decoder: guess or null
+};
 
-// y = h w_d + c_d; guess = (e + s_d y) on free nodes (optional)
-__global__ __launch_bounds__(TPB) void k_gnn_decode(int64_t n, const bf16 *h, const float *theta, const double *e,
-                                                    const double *scales, const uint8_t *dir, float *y,
-                                                    double *guess) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.0f;
-    for (int q = 0; q < GH; ++q) s += from_bf16(h[i * GH + q]) * theta[P_WD + q];
-    s += theta[P_CD];
-    y[i] = s;
-    if (guess) guess[i] = dir[i] ? 0.0 : e[i] + scales[3] * static_cast<double>(s);
+constexpr int FWD_WAVES = TPB / 64;
+constexpr int FWD_MAX_BLOCKS = 2048;
+constexpr int CTS = 36;   // padded row of the 32x32 accumulator tile in LDS (floats)
+
+__device__ inline bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+template <int MODE>
+__global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
+    constexpr int K = MODE == 0 ? GFP : 2 * GH;
+    constexpr int KS = K / 16;
+    constexpr int KP = K + 8;
+    __shared__ __align__(16) bf16 Wl[GH * KP];
+    __shared__ __align__(16) float Ct[FWD_WAVES][32 * CTS];
+    for (int t = threadIdx.x; t < GH * (K / 8); t += TPB) {
+        const int row = t / (K / 8), ch = t % (K / 8);
+        *reinterpret_cast<bf16x8 *>(Wl + row * KP + ch * 8) = ld8(A.wT + row * K + ch * 8);
+    }
+    __syncthreads();
+    const int l = threadIdx.x & 63, r = l & 31, half = l >> 5, wave = threadIdx.x >> 6;
+    float *C = Ct[wave];
+    const int64_t n = A.n, ntiles = (n + 31) / 32, ngroups = (ntiles + FWD_WAVES - 1) / FWD_WAVES;
+    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int64_t row0 = (g * FWD_WAVES + wave) * 32, i = row0 + r;
+        const bool valid = i < n;
+        bf16x8 af[KS];
+        if constexpr (MODE == 0) {
+            float f[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            if (valid && half == 0) {
+                const double sb = A.scales[0], sp = A.scales[1], sr = A.scales[2], sd = A.scales[3];
+                f[0] = static_cast<float>(A.b[i] / sb);
+                f[1] = static_cast<float>(A.p1[i] / sp);
+                f[2] = static_cast<float>(A.p2[i] / sp);
+                f[3] = static_cast<float>(A.re[i] / sr);
+                f[4] = static_cast<float>(A.kd[i] / sr);
+                f[5] = static_cast<float>(A.d[i] / sd);
+                f[6] = static_cast<float>(A.dir[i]);
+                f[7] = 1.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) af[0][q] = to_bf16(f[q]);
+            if (A.xout && valid) *reinterpret_cast<bf16x8 *>(A.xout + i * GFP + 8 * half) = af[0];
+        } else {
+            const bf16 *h = A.hin;
+            float acc[4][8];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                af[j] = valid ? ld8(h + i * GH + (2 * j + half) * 8) : bf16x8{};
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[j][q] = 0.0f;
+            }
+            int deg = 0;
+            if (valid) {
+                const int32_t k0 = A.adj_ptr[i], k1 = A.adj_ptr[i + 1];
+                for (int32_t k = k0; k < k1; k += 8) {
+                    int32_t nb[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) nb[u] = k + u < k1 ? A.adj_col[k + u] : -1;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (nb[u] < 0 || nb[u] == i) continue;
+                        ++deg;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const bf16x8 c = ld8(h + static_cast<int64_t>(nb[u]) * GH + (2 * j + half) * 8);
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) acc[j][q] += from_bf16(c[q]);
+                        }
+                    }
+                }
+            }
+            const float inv = deg > 0 ? 1.0f / static_cast<float>(deg) : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) af[4 + j][q] = to_bf16(acc[j][q] * inv);
+        }
+        float ypart = 0.0f;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            f32x16 c = {};
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[s], ld8(Wl + (ct * 32 + r) * KP + 16 * s + 8 * half),
+                                                            c, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) C[((v >> 2) * 8 + half * 4 + (v & 3)) * CTS + r] = c[v];
+            __syncthreads();
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) {
+                const int cb = (2 * jj + half) * 8, col = ct * 32 + cb;
+                if (valid) {
+                    float pre[8];
+                    bf16x8 hb;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        pre[q] = C[r * CTS + cb + q] + A.bias[col + q];
+                        float hv = fmaxf(pre[q], 0.0f);
+                        if constexpr (MODE != 0) hv += from_bf16(af[2 * ct + jj][q]);
+                        hb[q] = to_bf16(hv);
+                        if (MODE == 2) ypart += from_bf16(hb[q]) * A.wd[col + q];
+                    }
+                    *reinterpret_cast<bf16x8 *>(A.hout + i * GH + col) = hb;
+                    if (A.aout) {
+                        float4 *o = reinterpret_cast<float4 *>(A.aout + i * GH + col);
+                        o[0] = make_float4(pre[0], pre[1], pre[2], pre[3]);
+                        o[1] = make_float4(pre[4], pre[5], pre[6], pre[7]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (MODE == 2) {
+            ypart += __shfl_xor(ypart, 32, 64);
+            if (valid && half == 0) {
+                const float y = ypart + A.wd[GH];
+                if (A.yout) A.yout[i] = y;
+                if (A.guess) A.guess[i] = A.dir[i] ? 0.0 : A.e[i] + A.scales[3] * static_cast<double>(y);
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ training
@@ -468,17 +545,21 @@ __global__ __launch_bounds__(TPB) void k_gnn_adam(float *theta, float *m1, float
     theta[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-__global__ __launch_bounds__(TPB) void k_gnn_quantize(const float *theta, bf16 *wq) {
+// bf16 copies of the weight matrices: row-major (backward) and transposed (forward)
+__global__ __launch_bounds__(TPB) void k_gnn_quantize(const float *theta, bf16 *wq, bf16 *wqT) {
     const int q = blockIdx.x * TPB + threadIdx.x;
     if (q >= Q_COUNT) return;
-    int src;
+    int src, srcT;
     if (q < GFP * GH) {
         src = P_W0 + q;
+        srcT = P_W0 + (q % GFP) * GH + q / GFP;
     } else {
         const int l = (q - GFP * GH) / (2 * GH * GH), o = (q - GFP * GH) % (2 * GH * GH);
         src = P_L0 + l * P_LSTRIDE + o;
+        srcT = P_L0 + l * P_LSTRIDE + (o % (2 * GH)) * GH + o / (2 * GH);
     }
     wq[q] = to_bf16(theta[src]);
+    wqT[q] = to_bf16(theta[srcT]);
 }
 
 // ------------------------------------------------------------------ host side
@@ -516,7 +597,7 @@ GnnWork &work_for(Model &md, const Mesh &m, bool training) {
     return w;
 }
 
-// features + forward; a[] saved when training; guess written when non-null
+// features + forward; x, a[] and y saved when training; guess written when non-null
 void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *b, const double *p1,
              const double *p2, double *guess, bool training) {
     const int64_t n = m.lv[0].n;
@@ -524,19 +605,44 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     hipLaunchKernelGGL(k_gnn_prep, dim3(nb), dim3(TPB), 0, s, n, m.rowptr.p, m.col.p, m.val.p, b, p1, p2, w.e.p,
                        w.d.p, w.re.p, w.kd.p, w.part.p);
     hipLaunchKernelGGL(k_gnn_scales, dim3(1), dim3(TPB), 0, s, n, w.part.p, static_cast<int>(nb), w.scales.p);
-    hipLaunchKernelGGL(k_gnn_features, dim3(nb), dim3(TPB), 0, s, n, b, p1, p2, w.re.p, w.kd.p, w.d.p,
-                       m.lv[0].dir.p, w.scales.p, w.x.p);
-    const unsigned nt = static_cast<unsigned>((n + TM - 1) / TM);
+    const int64_t ngroups = ((n + 31) / 32 + FWD_WAVES - 1) / FWD_WAVES;
+    const unsigned nf = static_cast<unsigned>(std::min<int64_t>(ngroups, FWD_MAX_BLOCKS));
     const float *th = md.theta.p;
-    hipLaunchKernelGGL((k_gnn_layer<true>), dim3(nt), dim3(TPB), 0, s, n, nullptr, w.x.p, nullptr, nullptr,
-                       md.wq.p + Q_W0, th + P_C0, w.h[0].p, training ? w.a[0].p : nullptr);
-    for (int l = 1; l <= GL; ++l)
-        hipLaunchKernelGGL((k_gnn_layer<false>), dim3(nt), dim3(TPB), 0, s, n, w.h[l - 1].p, nullptr,
-                           m.adj_ptr.p, m.adj_col.p, md.wq.p + GFP * GH + (l - 1) * 2 * GH * GH,
-                           th + P_L0 + (l - 1) * P_LSTRIDE + 2 * GH * GH, w.h[l].p,
-                           training ? w.a[l].p : nullptr);
-    hipLaunchKernelGGL(k_gnn_decode, dim3(nb), dim3(TPB), 0, s, n, w.h[GL].p, th, w.e.p, w.scales.p,
-                       m.lv[0].dir.p, w.y.p, guess);
+    FwdArgs A{};
+    A.n = n;
+    A.adj_ptr = m.adj_ptr.p;
+    A.adj_col = m.adj_col.p;
+    A.b = b;
+    A.p1 = p1;
+    A.p2 = p2;
+    A.re = w.re.p;
+    A.kd = w.kd.p;
+    A.d = w.d.p;
+    A.e = w.e.p;
+    A.scales = w.scales.p;
+    A.dir = m.lv[0].dir.p;
+    A.wd = th + P_WD;
+    A.wT = md.wqT.p + Q_W0;
+    A.bias = th + P_C0;
+    A.hout = w.h[0].p;
+    A.aout = training ? w.a[0].p : nullptr;
+    A.xout = training ? w.x.p : nullptr;
+    hipLaunchKernelGGL(k_gnn_fwd<0>, dim3(nf), dim3(TPB), 0, s, A);
+    A.xout = nullptr;
+    for (int l = 1; l <= GL; ++l) {
+        A.hin = w.h[l - 1].p;
+        A.hout = w.h[l].p;
+        A.aout = training ? w.a[l].p : nullptr;
+        A.wT = md.wqT.p + GFP * GH + (l - 1) * 2 * GH * GH;
+        A.bias = th + P_L0 + (l - 1) * P_LSTRIDE + 2 * GH * GH;
+        if (l < GL) {
+            hipLaunchKernelGGL(k_gnn_fwd<1>, dim3(nf), dim3(TPB), 0, s, A);
+        } else {
+            A.yout = w.y.p;
+            A.guess = guess;
+            hipLaunchKernelGGL(k_gnn_fwd<2>, dim3(nf), dim3(TPB), 0, s, A);
+        }
+    }
     CGP_HIP(hipGetLastError());
 }
 
@@ -597,7 +703,8 @@ double gauss(uint64_t &st) {
 
 void upload_params(hipStream_t s, Model &md, const float *h) {
     CGP_HIP(hipMemcpyAsync(md.theta.p, h, P_COUNT * sizeof(float), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_gnn_quantize, dim3(blocks_for(Q_COUNT, TPB)), dim3(TPB), 0, s, md.theta.p, md.wq.p);
+    hipLaunchKernelGGL(k_gnn_quantize, dim3(blocks_for(Q_COUNT, TPB)), dim3(TPB), 0, s, md.theta.p, md.wq.p,
+                       md.wqT.p);
     CGP_HIP(hipGetLastError());
     CGP_HIP(hipStreamSynchronize(s));
 }
@@ -612,6 +719,7 @@ Model *gnn_create(hipStream_t s, uint64_t seed) {
     md->m1.alloc(P_COUNT);
     md->m2.alloc(P_COUNT);
     md->wq.alloc(Q_COUNT);
+    md->wqT.alloc(Q_COUNT);
     CGP_HIP(hipMemsetAsync(md->m1.p, 0, P_COUNT * sizeof(float), s));
     CGP_HIP(hipMemsetAsync(md->m2.p, 0, P_COUNT * sizeof(float), s));
     // He-normal weights (std sqrt(2 / fan_in)) from a splitmix64 stream; zero biases;
@@ -682,7 +790,7 @@ void gnn_train(hipStream_t s, Model &md, const Mesh &m, int n_samples, const dou
             hipLaunchKernelGGL(k_gnn_adam, dim3(blocks_for(P_COUNT, TPB)), dim3(TPB), 0, s, md.theta.p, md.m1.p,
                                md.m2.p, w.grad.p, static_cast<float>(lr), b1, b2, c1, c2, 1e-8f);
             hipLaunchKernelGGL(k_gnn_quantize, dim3(blocks_for(Q_COUNT, TPB)), dim3(TPB), 0, s, md.theta.p,
-                               md.wq.p);
+                               md.wq.p, md.wqT.p);
             CGP_HIP(hipGetLastError());
         }
     }
