@@ -39,6 +39,20 @@ if ROOT not in sys.path:
 METRIC = "Poisson solves/s at 1e-8 rel. residual: learned+FP32-refined vs plain FP64 PCG"
 HBM_PEAK_GBS = 8000.0
 TOL = 1e-8
+# HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
+# scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
+# fingerprint is recorded with them; reported as null for any other source.
+MEASURED_TRAFFIC = {"fingerprint": "46f274b451f7be2c", "float": 18.38e6, "double": 31.81e6,
+                    "profile": "profiles/k_cg_step_traffic_513x257.md"}
+
+
+def kernel_fingerprint() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pcg.hip", "cgp_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2003_00082_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -55,6 +69,11 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=48, help="steps solved (fp64) to train the networks")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch"],
+                    help="sequence: one 513x257 CGP sequence (default); batch: 64-instance Stuart sweep")
+    ap.add_argument("--instances", type=int, default=64, help="batch: number of instances")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -82,12 +101,161 @@ def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extra
     return float(total)
 
 
+def batch_main(args):
+    """Batched Stuart sweep: `instances` independent CGP instances (coarse nx = 2m+1,
+    ny = m+1, m ~ U{32..256}, each refined once; own Fourier flow; Stuart numbers
+    log-spaced over [0.1, 10]).  Each step solves phi for every instance in ONE batched
+    call, then p in one.  Two engines on the same inputs: staged (one graph-replayed
+    launch per CG stage for the whole batch) and persistent (one co-resident launch
+    per batched solve with grid barriers, captured in HIP graphs, SpMV lanes per
+    instance from the autotuner).  fp32 CG with fp64 refinement from the extrapolated
+    guess, to 1e-8."""
+    import numpy as np
+    import torch
+
+    import cgp_inputs as ci
+    import paper_2003_00082_amd as cgp
+
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    M = args.instances
+    sizes = ci.batch_sizes(M, 3000)
+    sig = ci.stuart_numbers(M)
+    stream = torch.cuda.Stream(dev)        # graph capture needs a non-default stream
+    torch.cuda.set_stream(stream)
+    ctx = cgp.Context(0, stream)
+    H, nc, nnz, nf = [], [], [], []
+    W, K = max(args.warmup, 3), args.steps
+    vel = [dict() for _ in range(M)]
+    for i, (nx, ny) in enumerate(sizes):
+        m = ci.jittered_rect(nx, ny, 3000 + i)
+        h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 1)
+        H.append(h)
+        i0, i1 = ctx.mesh_info(h, 0), ctx.mesh_info(h, 1)
+        nc.append(i0["n_nodes"])
+        nnz.append(i0["nnz"])
+        nf.append(i1["n_nodes"])
+        seq = ci.FourierSequence(ctx.mesh_download(h, 1)[0], ci.fourier_modes(3500 + i), ci.fourier_modes(3700 + i))
+        for n in range(-W, K):
+            vel[i][n] = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in seq.at(n))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lanes = ctx.autotune(H, cgp.CGP_FP32_IR)
+    tune_s = time.perf_counter() - t0
+    rho_dt = 1.0 / ci.DT
+    bphi = [torch.empty(n, **f64) for n in nc]
+    bp = [torch.empty(n, **f64) for n in nc]
+    phif = [torch.empty(n, **f64) for n in nf]
+    pf = [torch.empty(n, **f64) for n in nf]
+    fx = [torch.empty(n, **f64) for n in nf]
+    fy = [torch.empty(n, **f64) for n in nf]
+    nsteps = W + K
+    stats_all = torch.zeros(2 * nsteps * M * cgp.STATS_BYTES, dtype=torch.uint8, device=dev)
+
+    def run(engine: str):
+        bufs = {eq: [[torch.zeros(n, **f64) for n in nc] for _ in range(3)] for eq in ("phi", "p")}
+        st = {eq: cgp.stats_buffer(M) for eq in ("phi", "p")}
+        graphs = {}
+
+        def solve(eq, bvecs, n):
+            cur, p1, p2 = (bufs[eq][(n - k) % 3] for k in range(3))
+            kw = dict(prev1=p1, prev2=p2, guess=cgp.CGP_GUESS_EXTRAP, precision=cgp.CGP_FP32_IR, tol=TOL)
+            if engine == "staged":
+                ctx.poisson_solve(H, bvecs, cur, st[eq], engine=cgp.CGP_ENGINE_STAGED, **kw)
+            else:
+                key = (eq, n % 3)
+                if key not in graphs:
+                    ctx.graph_begin()
+                    ctx.poisson_solve(H, bvecs, cur, st[eq], engine=cgp.CGP_ENGINE_PERSISTENT, **kw)
+                    graphs[key] = ctx.graph_end()
+                ctx.graph_launch(graphs[key])
+            slot = (2 * (n + W) + (eq == "p")) * M * cgp.STATS_BYTES
+            stats_all[slot:slot + M * cgp.STATS_BYTES].copy_(st[eq])
+            return cur
+
+        def step(n):
+            for i in range(M):
+                u, v, _, _ = vel[i][n]
+                ctx.restrict(H[i], u, v, cgp.CGP_SRC_CURL, 1.0, bphi[i])
+            phi = solve("phi", bphi, n)
+            for i in range(M):
+                u, v, ut, vt = vel[i][n]
+                ctx.prolong(H[i], phi[i], phif[i])
+                ctx.lorentz_force(H[i], phif[i], u, v, float(sig[i]), 1.0, fx[i], fy[i])
+                ctx.restrict(H[i], ut, vt, cgp.CGP_SRC_DIV, rho_dt, bp[i])
+            p = solve("p", bp, n)
+            for i in range(M):
+                ctx.prolong(H[i], p[i], pf[i])
+
+        for n in range(-W, 0):
+            step(n)
+        torch.cuda.synchronize()
+        l0 = ctx.stage_launches
+        t0 = time.perf_counter()
+        ev = []
+        for n in range(K):
+            step(n)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        launches = ctx.stage_launches - l0
+        host = np.frombuffer(stats_all.cpu().numpy().tobytes(), dtype=np.dtype(
+            [("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"), ("rel0", "f8")]))
+        timed = host[2 * W * M:].reshape(K, 2, M)
+        ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
+        nbytes = sum(pcg_bytes(nc[i], nnz[i], int(timed["iters"][k, e, i]), int(timed["ref"][k, e, i]), True, True)
+                     for k in range(K) for e in range(2) for i in range(M))
+        for g in graphs.values():
+            ctx.graph_free(g)
+        return {"solves_per_s": 2 * M * K / elapsed, "ms_per_step": 1e3 * elapsed / K,
+                "mean_iters": float(timed["iters"].mean()), "max_iters": int(timed["iters"].max()),
+                "all_converged": ok, "max_rel_res": float(timed["rel"].max()),
+                "bytes_per_step": nbytes / K, "stage_launches_per_step": launches / K,
+                "achieved_GBs_step": nbytes / elapsed / 1e9}
+
+    res = {e: run(e) for e in ("staged", "persistent")}
+    best = max(res, key=lambda e: res[e]["solves_per_s"])
+    R = res[best]
+    out = {
+        "metric": METRIC,
+        "value": R["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": R["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched Stuart sweep: {M} CGP instances, coarse nx=2m+1, ny=m+1, m~U{{32..256}} "
+                               f"({sum(nc)} coarse rows in all, nnz {sum(nnz)}), each refined once "
+                               f"({sum(nf)} fine nodes), Stuart numbers log-spaced over [0.1, 10], phi and p "
+                               f"solves of all instances batched, fp32 PCG with fp64 refinement from the "
+                               f"extrapolated guess to {TOL:g}",
+                   "instances": M, "coarse_rows": int(sum(nc)), "nnz": int(sum(nnz)), "engine": best},
+        "engines": res,
+        "autotune": {"lanes": lanes, "seconds": tune_s},
+        "roofline": {"bound": "hbm", "achieved": R["achieved_GBs_step"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": R["achieved_GBs_step"] / HBM_PEAK_GBS, "traffic": None,
+                     "note": "algorithmic PCG bytes of all solves / whole step time (restrict, prolong and "
+                             "force launches included in the time, not in the bytes)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances of a batch or "
               "mesh partitions would shard across GPUs, which this build does not do.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        if args.steps == 200:
+            args.steps = 6
+        return batch_main(args)
     import numpy as np
     import torch
 
@@ -285,6 +453,9 @@ def main():
                          f"{cpu_t:.1f} s)"}
 
     bpi = (8 * nnz + 44 * nc) if main_form in "BC" else (12 * nnz + 88 * nc)
+    traffic = None
+    if kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"] and (nx, ny) == (513, 257):
+        traffic = MEASURED_TRAFFIC["float" if main_form in "BC" else "double"]
     out = {
         "metric": METRIC,
         "value": R["solves_per_s"],
@@ -308,13 +479,31 @@ def main():
         "speedup_C_over_A": (res["C"]["solves_per_s"] / res["A"]["solves_per_s"]) if {"A", "C"} <= set(res) else None,
         "training": train_info,
         "roofline": {"bound": "hbm", "achieved": R["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": R["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_cg_step (one CG stage per launch)", "bytes_per_iter": bpi,
+                     "frac": R["achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "kernel": f"k_cg_step<{'float' if main_form in 'BC' else 'double'}, 4> (one CG stage per launch)",
+                     "algorithmic_bytes_per_iter": bpi,
+                     "algorithmic_bytes_per_launch": R["achieved_GBs"] * 1e3 * R["kernel_avg_us"],
                      "kernel_avg_us": R["kernel_avg_us"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
     ctx.close()
+    if args.calibrate_copy:
+        calibrate_copy()
+
+
+def calibrate_copy():
+    """One plain copy of 2^30 bytes: it reads and writes exactly 1 GiB of HBM, so the
+    profiler's FETCH_SIZE / WRITE_SIZE for this dispatch give the counters' scale."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": src.numel() * 8}), file=sys.stderr)
 
 
 if __name__ == "__main__":
