@@ -10,15 +10,17 @@ step.  One *step* is one pass of the whole hot path:
     -> Lorentz force (Eqs. 13-14) -> restrict + divergence source (Eq. 15)
     -> solve p -> prolong p
 
-with both Poisson solves to a true relative residual of 1e-8.  Three forms run
-on the same inputs:
+with both Poisson solves to a true relative residual of 1e-8.  Forms on the
+same inputs (d = --degree, the Chebyshev polynomial preconditioner's degree):
 
-    A  plain fp64 Jacobi-PCG from the previous solution
-    B  fp32 Jacobi-PCG with fp64 residual refinement from the learned guess (one
-       network per equation, trained on the GPU beforehand on the solutions of
-       the steps that precede the warm-up; each guess is judged against the
-       previous solution by the solver)
-    C  as B with the extrapolation 2 phi^{n-1} - phi^{n-2} instead of the network
+    A  plain fp64 Jacobi-PCG from the previous solution (the baseline)
+    B  fp32 PCG with fp64 residual refinement, Chebyshev degree d, from the
+       learned guess (one network per equation, trained on the GPU beforehand on
+       the solutions of the steps that precede the warm-up; each guess is judged
+       against the previous solution by the solver)
+    C  as B from the extrapolation 2 phi^{n-1} - phi^{n-2} instead of the network
+    D  fp64 PCG, Chebyshev degree d, from the previous solution
+    E  fp32 Jacobi-PCG with fp64 refinement from the extrapolation
 
 ``value`` is form B's whole-job Poisson solves per second (2 solves per step)
 over the timed steps, inputs resident in HBM.  Training is a one-off set-up
@@ -42,8 +44,7 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "46f274b451f7be2c", "float": 18.38e6, "double": 31.81e6,
-                    "profile": "profiles/k_cg_step_traffic_513x257.md"}
+MEASURED_TRAFFIC = {"fingerprint": None, "profile": "profiles/cg_traffic_513x257.md"}
 
 
 def kernel_fingerprint() -> str:
@@ -65,7 +66,8 @@ def parse():
     ap.add_argument("--stuart", type=float, default=1.0, help="Stuart number N (sigma of the Lorentz force)")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample: steps (2 solves each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="ABC")
+    ap.add_argument("--forms", default="ABCDE")
+    ap.add_argument("--degree", type=int, default=8, help="Chebyshev preconditioner degree of forms B, C, D")
     ap.add_argument("--train-steps", type=int, default=48, help="steps solved (fp64) to train the networks")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -77,16 +79,30 @@ def parse():
     return ap.parse_args()
 
 
-def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extrap: bool) -> float:
-    """Algorithmic HBM bytes of one solve: every matrix entry (value + int32 column) and
-    every vector element each stage reads or writes, counted once (halo re-reads and
-    padding are not counted).
+def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extrap: bool,
+              degree: int = 0) -> float:
+    """Algorithmic HBM bytes of one solve: every matrix entry (value + int32 column) each
+    product with K reads and every vector element each stage reads or writes, counted
+    once per stage (halo re-reads, region copies and padding are not counted).
 
-    fp32 iteration: matrix 8 nnz; reads r, w, s, D^-1, p, c and writes p, s, r, w, c
-    (4 B each): 8 nnz + 44 n.  fp64 iteration: 12 nnz + 88 n.  A refinement (mixed)
-    is FOLD (32 n) + true residual in fp64 (12 nnz + 32 n) + restart of the
-    recurrences in fp32 (8 nnz + 28 n)."""
-    if mixed:
+    Jacobi (degree 0, row-range kernel): fp32 iteration 8 nnz + 44 n (matrix; reads r, w,
+    s, D^-1, p, c, writes p, s, r, w, c); fp64 iteration 12 nnz + 88 n.  A refinement
+    (mixed) is FOLD (32 n) + true residual in fp64 (12 nnz + 32 n) + restart of the
+    recurrences in fp32 (8 nnz + 28 n).
+    Chebyshev degree d >= 1 (tiled kernel): an iteration or restart performs d products
+    with K, d (8 nnz + 8 n) in fp32, plus the recurrences of the own rows (reads r, w, s,
+    u, p, c, D^-1, writes r, w, s, u, p, c: 52 n); fp64 doubles the vector and value
+    bytes (12 nnz + 16 n per product, 104 n).  The initial guess adds 24 n (extrapolation)."""
+    if degree >= 1:
+        if mixed:
+            it = degree * (8 * nnz + 8 * n) + 52 * n
+            res = 12 * nnz + 32 * n
+            total = res + it + iters * it + refinements * (32 * n + res + it)
+        else:
+            it = degree * (12 * nnz + 16 * n) + 104 * n
+            res = 12 * nnz + 28 * n
+            total = res + it + iters * it + refinements * (res + it)
+    elif mixed:
         it = 8 * nnz + 44 * n
         res = 12 * nnz + 32 * n
         start = 8 * nnz + 28 * n
@@ -105,11 +121,12 @@ def batch_main(args):
     """Batched Stuart sweep: `instances` independent CGP instances (coarse nx = 2m+1,
     ny = m+1, m ~ U{32..256}, each refined once; own Fourier flow; Stuart numbers
     log-spaced over [0.1, 10]).  Each step solves phi for every instance in ONE batched
-    call, then p in one.  Two engines on the same inputs: staged (one graph-replayed
-    launch per CG stage for the whole batch) and persistent (one co-resident launch
-    per batched solve with grid barriers, captured in HIP graphs, SpMV lanes per
-    instance from the autotuner).  fp32 CG with fp64 refinement from the extrapolated
-    guess, to 1e-8."""
+    call, then p in one.  Three variants on the same inputs: staged with the
+    Chebyshev preconditioner of degree --degree (one graph-replayed launch per CG
+    stage for the whole batch, tiled), staged Jacobi (row ranges), and persistent
+    Jacobi (one co-resident launch per batched solve with grid barriers, captured in
+    HIP graphs, SpMV lanes per instance from the autotuner).  fp32 CG with fp64
+    refinement from the extrapolated guess, to 1e-8."""
     import numpy as np
     import torch
 
@@ -153,15 +170,19 @@ def batch_main(args):
     stats_all = torch.zeros(2 * nsteps * M * cgp.STATS_BYTES, dtype=torch.uint8, device=dev)
 
     def run(engine: str):
+        fdeg = args.degree if engine == "staged_chebyshev" else 0
         bufs = {eq: [[torch.zeros(n, **f64) for n in nc] for _ in range(3)] for eq in ("phi", "p")}
         st = {eq: cgp.stats_buffer(M) for eq in ("phi", "p")}
         graphs = {}
 
         def solve(eq, bvecs, n):
             cur, p1, p2 = (bufs[eq][(n - k) % 3] for k in range(3))
-            kw = dict(prev1=p1, prev2=p2, guess=cgp.CGP_GUESS_EXTRAP, precision=cgp.CGP_FP32_IR, tol=TOL)
-            if engine == "staged":
+            kw = dict(prev1=p1, prev2=p2, guess=cgp.CGP_GUESS_EXTRAP, precision=cgp.CGP_FP32_IR, tol=TOL,
+                      precond_degree=fdeg)
+            if engine == "staged_chebyshev":
                 ctx.poisson_solve(H, bvecs, cur, st[eq], engine=cgp.CGP_ENGINE_STAGED, **kw)
+            elif engine == "staged_jacobi":
+                ctx.poisson_solve(H, bvecs, cur, st[eq], engine=cgp.CGP_ENGINE_STAGED_ROWS, **kw)
             else:
                 key = (eq, n % 3)
                 if key not in graphs:
@@ -202,7 +223,8 @@ def batch_main(args):
             [("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"), ("rel0", "f8")]))
         timed = host[2 * W * M:].reshape(K, 2, M)
         ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
-        nbytes = sum(pcg_bytes(nc[i], nnz[i], int(timed["iters"][k, e, i]), int(timed["ref"][k, e, i]), True, True)
+        nbytes = sum(pcg_bytes(nc[i], nnz[i], int(timed["iters"][k, e, i]), int(timed["ref"][k, e, i]), True, True,
+                               fdeg)
                      for k in range(K) for e in range(2) for i in range(M))
         for g in graphs.values():
             ctx.graph_free(g)
@@ -212,7 +234,7 @@ def batch_main(args):
                 "bytes_per_step": nbytes / K, "stage_launches_per_step": launches / K,
                 "achieved_GBs_step": nbytes / elapsed / 1e9}
 
-    res = {e: run(e) for e in ("staged", "persistent")}
+    res = {e: run(e) for e in ("staged_chebyshev", "staged_jacobi", "persistent")}
     best = max(res, key=lambda e: res[e]["solves_per_s"])
     R = res[best]
     out = {
@@ -301,7 +323,7 @@ def main():
                 bb = torch.empty(nc, **f64)
                 ctx.restrict(h, uu, vv, kind, sc, bb)
                 ctx.poisson_solve([h], [bb], [x[eq]], st1, guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64,
-                                  tol=1e-10)
+                                  tol=1e-10, precond_degree=args.degree)
                 rhs_t[eq].append(bb)
                 sols[eq].append(x[eq].clone())
         torch.cuda.synchronize()
@@ -322,24 +344,33 @@ def main():
                       "loss_last_epoch": {k: float(v[-1]) for k, v in hist.items()}}
         del sols, rhs_t
 
+    deg = args.degree
+    forms = {   # precision, guess, preconditioner degree (0 = Jacobi, row-range kernel)
+        "A": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, 0),
+        "B": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, deg),
+        "C": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, deg),
+        "D": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, deg),
+        "E": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, 0),
+    }
+
     def run(form: str):
-        mixed = form in "BC"
+        prec, guess, fdeg = forms[form]
+        mixed = prec == cgp.CGP_FP32_IR
+        rotating = guess in (cgp.CGP_GUESS_EXTRAP, cgp.CGP_GUESS_LEARNED)
         bufs = {"phi": [torch.zeros(nc, **f64) for _ in range(3)], "p": [torch.zeros(nc, **f64) for _ in range(3)]}
         ev = []
         keep = {}
 
         def solve(eq, bvec, n, slot, timed):
             B = bufs[eq]
-            if mixed:
+            kw = dict(precision=prec, guess=guess, precond_degree=fdeg)
+            if rotating:
                 cur, p1, p2 = B[n % 3], B[(n - 1) % 3], B[(n - 2) % 3]
-                kw = dict(prev1=[p1], prev2=[p2], precision=cgp.CGP_FP32_IR)
-                if form == "B":
-                    kw.update(guess=cgp.CGP_GUESS_LEARNED, model=models[eq])
-                else:
-                    kw.update(guess=cgp.CGP_GUESS_EXTRAP)
+                kw.update(prev1=[p1], prev2=[p2])
+                if guess == cgp.CGP_GUESS_LEARNED:
+                    kw.update(model=models[eq])
             else:
                 cur = B[0]
-                kw = dict(guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64)
             st = stats[slot * cgp.STATS_BYTES:(slot + 1) * cgp.STATS_BYTES]
             if timed:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -375,7 +406,7 @@ def main():
         launches = ctx.stage_launches - launches0
         # the network's share of the solve time, timed live on the same stream and inputs
         gnn_us = 0.0
-        if form == "B":
+        if guess == cgp.CGP_GUESS_LEARNED:
             g = torch.empty(nc, **f64)
             B = bufs["phi"]
             reps = 20
@@ -392,7 +423,8 @@ def main():
         ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
         solve_ms = np.array([a.elapsed_time(b) for a, b in ev])
         pcg_ms = solve_ms.sum() - 1e-3 * gnn_us * len(solve_ms)
-        nbytes = np.array([pcg_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed, mixed) for r in timed])
+        nbytes = np.array([pcg_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed, rotating, fdeg)
+                           for r in timed])
         return {
             "solves_per_s": 2 * K / elapsed,
             "ms_per_step": 1e3 * elapsed / K,
@@ -400,11 +432,16 @@ def main():
             "mean_refinements": float(timed["ref"].mean()),
             "max_rel_res": float(timed["rel"].max()),
             "mean_guess_rel_res": float(timed["rel0"].mean()),
-            "learned_guess_kept": float(np.mean(timed["guess"] == cgp.CGP_GUESS_LEARNED)) if form == "B" else None,
+            "learned_guess_kept": (float(np.mean(timed["guess"] == cgp.CGP_GUESS_LEARNED))
+                                   if guess == cgp.CGP_GUESS_LEARNED else None),
+            "precision": "fp32+fp64 refinement" if mixed else "fp64",
+            "preconditioner": f"Chebyshev degree {fdeg}" if fdeg >= 2 else "Jacobi",
+            "guess": {cgp.CGP_GUESS_GIVEN: "previous solution", cgp.CGP_GUESS_EXTRAP: "extrapolation",
+                      cgp.CGP_GUESS_LEARNED: "learned"}[guess],
             "all_converged": ok,
             "solve_ms_mean": float(solve_ms.mean()),
             "solve_share": float(solve_ms.sum() / (1e3 * elapsed)),
-            "gnn_predict_us": gnn_us if form == "B" else None,
+            "gnn_predict_us": gnn_us if guess == cgp.CGP_GUESS_LEARNED else None,
             "achieved_GBs": float(nbytes.sum() / (pcg_ms * 1e-3) / 1e9),
             "stage_launches": int(launches),
             "kernel_avg_us": float(pcg_ms * 1e3 / max(launches, 1)),
@@ -452,10 +489,18 @@ def main():
                          f"sequence, phi and p ({2 * S} solves, mean {np.mean(its):.0f} iterations, "
                          f"{cpu_t:.1f} s)"}
 
-    bpi = (8 * nnz + 44 * nc) if main_form in "BC" else (12 * nnz + 88 * nc)
+    mprec, _, mdeg = forms[main_form]
+    mixed_main = mprec == cgp.CGP_FP32_IR
+    tname = "float" if mixed_main else "double"
+    if mdeg >= 1:
+        kname = f"k_cg_tile<{tname}, 8>"
+        bpi = (mdeg * (8 * nnz + 8 * nc) + 52 * nc) if mixed_main else (mdeg * (12 * nnz + 16 * nc) + 104 * nc)
+    else:
+        kname = f"k_cg_step<{tname}, 4>"
+        bpi = (8 * nnz + 44 * nc) if mixed_main else (12 * nnz + 88 * nc)
     traffic = None
     if kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"] and (nx, ny) == (513, 257):
-        traffic = MEASURED_TRAFFIC["float" if main_form in "BC" else "double"]
+        traffic = MEASURED_TRAFFIC.get(f"{kname} degree {mdeg}")
     out = {
         "metric": METRIC,
         "value": R["solves_per_s"],
@@ -467,7 +512,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64 (network bf16)" if main_form == "B" else ("f32+f64" if main_form == "C" else "f64"),
+        "dtype": ("f32+f64" if mixed_main else "f64") + (" (network bf16)" if main_form == "B" else ""),
         "data": "synthetic",
         "config": {"workload": f"CGP step, coarse {nx}x{ny} jittered P1 ({nc} nodes, nnz {nnz}), fine k=1 "
                                f"({nf} nodes), {K}-step drifting 8-mode Fourier flow, phi and p solves to "
@@ -475,15 +520,18 @@ def main():
                    "coarse_nodes": nc, "fine_nodes": nf, "nnz": nnz, "tol": TOL, "stuart": sigma},
         "forms": {f: {k: v for k, v in r.items() if k != "step0"} | {"err_vs_oracle_step0": errs.get(f)}
                   for f, r in res.items()},
-        "speedup_B_over_A": (res["B"]["solves_per_s"] / res["A"]["solves_per_s"]) if {"A", "B"} <= set(res) else None,
-        "speedup_C_over_A": (res["C"]["solves_per_s"] / res["A"]["solves_per_s"]) if {"A", "C"} <= set(res) else None,
+        "speedup_over_A": ({f: res[f]["solves_per_s"] / res["A"]["solves_per_s"] for f in res}
+                           if "A" in res else None),
+        "preconditioner_degree": deg,
         "training": train_info,
         "roofline": {"bound": "hbm", "achieved": R["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": R["achieved_GBs"] / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": f"k_cg_step<{'float' if main_form in 'BC' else 'double'}, 4> (one CG stage per launch)",
+                     "kernel": f"{kname} (one CG stage per launch)",
                      "algorithmic_bytes_per_iter": bpi,
+                     "bytes_model": "d products with K (matrix read once each) + own-row recurrence vectors; "
+                                    "see pcg_bytes",
                      "algorithmic_bytes_per_launch": R["achieved_GBs"] * 1e3 * R["kernel_avg_us"],
                      "kernel_avg_us": R["kernel_avg_us"]},
         "cpu_baseline": cpu,

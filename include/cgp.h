@@ -68,11 +68,18 @@ enum { CGP_GUESS_ZERO = 0, CGP_GUESS_GIVEN = 1, CGP_GUESS_EXTRAP = 2, CGP_GUESS_
 /* how cgp_poisson_solve synchronises its workgroups between CG stages:
  *   STAGED      one kernel launch per stage (one per CG iteration), launched from
  *               replayed HIP graphs; the call returns once the host has seen every
- *               instance finish (it waits on the device, it does not enqueue only)
+ *               instance finish (it waits on the device, it does not enqueue only).
+ *               Each workgroup owns a compact tile of at most 512 rows (recursive
+ *               coordinate bisection) and works on the rows within graph distance
+ *               d of it; meshes whose rows are wider than 12 entries or whose
+ *               regions do not fit use STAGED_ROWS instead (Jacobi only)
+ *   STAGED_ROWS as STAGED with workgroups owning consecutive row ranges (Jacobi only)
  *   PERSISTENT  one co-resident launch with a grid-wide barrier between stages;
  *               fully asynchronous, so it can be captured in a caller's graph
- *   AUTO        STAGED, or PERSISTENT while the context's stream is being captured */
-enum { CGP_ENGINE_AUTO = 0, CGP_ENGINE_STAGED = 1, CGP_ENGINE_PERSISTENT = 2 };
+ *               (Jacobi only)
+ *   AUTO        PERSISTENT while the context's stream is being captured; otherwise
+ *               STAGED for the Chebyshev preconditioner and STAGED_ROWS for Jacobi */
+enum { CGP_ENGINE_AUTO = 0, CGP_ENGINE_STAGED = 1, CGP_ENGINE_PERSISTENT = 2, CGP_ENGINE_STAGED_ROWS = 3 };
 /* per-instance solve status (cgp_solve_stats.status) */
 enum { CGP_SOLVE_OK = 0, CGP_SOLVE_NOCONV = 1, CGP_SOLVE_BREAKDOWN = 2, CGP_SOLVE_ABORTED = 3 };
 
@@ -164,6 +171,11 @@ typedef struct {
     int32_t blocks;       /* workgroups of the solve: 0 = one per compute unit           */
     int32_t engine;       /* CGP_ENGINE_*                                                */
     int32_t launches_per_graph; /* CGP_ENGINE_STAGED: stages per replayed graph (0 = 32; even) */
+    int32_t precond_degree; /* 0 or 1: Jacobi M = diag(K); 2..8: Chebyshev polynomial of this
+                             degree in D^-1 K over [hi/1000, hi], hi = max_i sum_j |K_ij|/K_ii
+                             (Gershgorin), applied as that many steps of Chebyshev
+                             iteration for K z = r from z = 0 (CGP_ENGINE_STAGED only)  */
+    int32_t reserved_;    /* must be 0                                                   */
 } cgp_solve_opts;
 
 typedef struct {
@@ -176,8 +188,9 @@ typedef struct {
 } cgp_solve_stats;
 
 /* Solve K phi = b on the level-0 mesh of each of n_inst instances with
- * Jacobi-preconditioned conjugate gradients, all instances in one persistent
- * launch (Eqs. 12, 15; the paper used GMRES(m)+ILU(0) for the same systems).
+ * preconditioned conjugate gradients (Jacobi or a Chebyshev polynomial, see
+ * cgp_solve_opts.precond_degree), all instances in the same launches (Eqs. 12, 15;
+ * the paper used GMRES(m)+ILU(0) for the same systems).
  *   h_meshes[i]  mesh of instance i (distinct meshes; one instance per mesh)
  *   h_d_b[i]     device pointer, right-hand side [N_0]
  *   h_d_phi[i]   device pointer [N_0]: the guess on entry for GUESS_GIVEN, the

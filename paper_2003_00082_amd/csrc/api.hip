@@ -117,6 +117,8 @@ void ensure_work(Mesh &m) {
     w.s32.alloc(2 * n);
     w.p32.alloc(n);
     w.c32.alloc(n);
+    w.u.alloc(n);
+    w.u32.alloc(n);
     w.n = n;
 }
 
@@ -370,7 +372,10 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                         o.spmv_lanes == 8,
                     "spmv_lanes must be 0, 1, 2, 4 or 8");
         CGP_REQUIRE(o.blocks >= 0, "blocks must be >= 0");
-        CGP_REQUIRE(o.engine >= CGP_ENGINE_AUTO && o.engine <= CGP_ENGINE_PERSISTENT, "unknown engine");
+        CGP_REQUIRE(o.engine >= CGP_ENGINE_AUTO && o.engine <= CGP_ENGINE_STAGED_ROWS, "unknown engine");
+        CGP_REQUIRE(o.precond_degree >= 0 && o.precond_degree <= TILE_MAX_DEGREE,
+                    "precond_degree must be in [0, 8]");
+        CGP_REQUIRE(o.reserved_ == 0, "reserved field must be 0");
         CGP_REQUIRE(o.launches_per_graph >= 0 && o.launches_per_graph % 2 == 0 && o.launches_per_graph <= 4096,
                     "launches_per_graph must be even and <= 4096");
         Model *model = nullptr;
@@ -397,6 +402,20 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         }
         const bool persistent = o.engine == CGP_ENGINE_PERSISTENT || (o.engine == CGP_ENGINE_AUTO && ctx->capturing);
         CGP_REQUIRE(persistent || !ctx->capturing, "the staged engine cannot be captured; use CGP_ENGINE_PERSISTENT");
+        const int degree = std::max(1, o.precond_degree);
+        if (degree >= 2 && (persistent || o.engine == CGP_ENGINE_STAGED_ROWS))
+            throw Error{CGP_E_UNSUPPORTED, "the Chebyshev preconditioner needs CGP_ENGINE_STAGED"};
+        // tiled iteration when every instance's mesh fits it with one matrix width (AUTO: only
+        // for the Chebyshev preconditioner; the row-range kernel is the faster Jacobi iteration)
+        std::vector<TilePlan *> tp(n_inst, nullptr);
+        bool tiled = !persistent && o.engine != CGP_ENGINE_STAGED_ROWS &&
+                     (o.engine == CGP_ENGINE_STAGED || degree >= 2);
+        for (int i = 0; i < n_inst && tiled; ++i) {
+            tp[i] = tile_plan(ctx->aux, *ms[i], degree);
+            tiled = tp[i] != nullptr && tp[i]->width == tp[0]->width;
+        }
+        if (degree >= 2 && !tiled)
+            throw Error{CGP_E_UNSUPPORTED, "a mesh does not fit the tiled iteration the Chebyshev preconditioner needs"};
         SolveParams prm{};
         prm.tol = o.tol;
         prm.delta = o.refine_delta > 0.0 ? o.refine_delta : 0.1;
@@ -419,6 +438,8 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             std::vector<int32_t> nb;
             if (persistent) {
                 nb = split_blocks(rows, grid);
+            } else if (tiled) {
+                for (int i = 0; i < gn; ++i) nb.push_back(tp[g0 + i]->nparts);
             } else {
                 for (int64_t r : rows) nb.push_back(static_cast<int32_t>((r + pcg_block_size() - 1) / pcg_block_size()));
             }
@@ -429,7 +450,8 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             };
             // cache key: everything the launch records depend on
             std::ostringstream key;
-            key << o.precision << ':' << o.guess << ':' << used << ':' << launches << ':' << persistent << ':';
+            key << o.precision << ':' << o.guess << ':' << used << ':' << launches << ':' << persistent << ':'
+                << tiled << ':' << degree << ':';
             for (int i = 0; i < gn; ++i) {
                 const int ii = g0 + i;
                 key << h_meshes[ii] << ',' << lanes_of(*ms[ii]) << ',' << nb[i] << ',' << (const void *)h_d_b[ii]
@@ -499,6 +521,33 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     d.c32 = m.work.c32.p;
                     d.partials = dpart + poff;
                     d.ctl = dctl + 2 * i;
+                    d.u = m.work.u.p;
+                    d.u32 = m.work.u32.p;
+                    if (tiled) {
+                        const TilePlan &T = *tp[ii];
+                        d.degree = degree;
+                        d.tblk = T.blk.p;
+                        d.treg = T.reg.p;
+                        d.tcol = T.ecol.p;
+                        d.tval32 = T.eval32.p;
+                        d.tval = T.eval64.p;
+                        if (degree == 1) {
+                            d.cheb[0] = 1.0;   // Jacobi: z = D^-1 r
+                        } else {
+                            // Chebyshev iteration over [hi/1000, hi]: the first step scales D^-1 r by
+                            // 1/c, step k updates dz <- a1 dz + a2 D^-1 res
+                            const double hi = mesh_gershgorin(ctx->aux, m), lo = hi / 1000.0;
+                            const double c = 0.5 * (hi + lo), e = 0.5 * (hi - lo), sig = c / e;
+                            double rho = 1.0 / sig;
+                            d.cheb[0] = 1.0 / c;
+                            for (int k = 1; k < degree; ++k) {
+                                const double rn = 1.0 / (2.0 * sig - rho);
+                                d.cheb[2 * k - 1] = rn * rho;
+                                d.cheb[2 * k] = 2.0 * rn / e;
+                                rho = rn;
+                            }
+                        }
+                    }
                     hd[i] = d;
                     for (int v = 0; v < nb[i]; ++v) hbi[blk + v] = i;
                     blk += nb[i];
@@ -538,11 +587,16 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             if (!plan->exec) {
                 // the launch template is recorded on the private stream (the caller's may be the null stream)
                 CGP_HIP(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeRelaxed));
-                for (int l = 0; l < launches; ++l)
-                    launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
-                                   plan->d_block_inst,
-                                   plan->d_ranges, plan->grid, plan->d_prm, l & 1, plan->d_done,
-                                   ctx->host_flag_dev);
+                for (int l = 0; l < launches; ++l) {
+                    if (tiled)
+                        launch_cg_tile(ctx->aux, o.precision == CGP_FP32_IR, tp[g0]->width, gn, plan->d_insts,
+                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
+                                       plan->d_done, ctx->host_flag_dev);
+                    else
+                        launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
+                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
+                                       plan->d_done, ctx->host_flag_dev);
+                }
                 CGP_HIP(hipStreamEndCapture(ctx->aux, &plan->graph));
                 CGP_HIP(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
                 plan->launches = launches;

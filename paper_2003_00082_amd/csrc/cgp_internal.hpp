@@ -79,11 +79,42 @@ struct Level {
     DBuf<double> tmp;       // [n] prolongation staging (levels 1..k-1)
 };
 
-// per-instance solver workspace, owned by the mesh (r, w, s double-buffered)
+// per-instance solver workspace, owned by the mesh (r, w, s double-buffered;
+// u = M^-1 r of the tiled iteration single-buffered: only its own row reads it)
 struct SolveWork {
     int64_t n = 0;
-    DBuf<double> r, w, s, p;
-    DBuf<float> r32, w32, s32, p32, c32;
+    DBuf<double> r, w, s, p, u;
+    DBuf<float> r32, w32, s32, p32, c32, u32;
+};
+
+// ------------------------------------------------------------------ tiled iteration
+
+constexpr int TILE_ROWS = 512;        // own rows per workgroup (one per thread)
+constexpr int TILE_REGION = 2048;     // region rows per workgroup (own rows + halo to distance d)
+constexpr int TILE_SPMV = 1536;       // region rows that carry a local matrix row
+constexpr int TILE_MAX_DEGREE = 8;
+
+// One workgroup of the tiled iteration: a compact tile of own rows (recursive
+// coordinate bisection of the node coordinates) and its region, the rows within
+// graph distance d of the tile, listed own rows first and then by distance.
+struct TileBlk {
+    int32_t reg_off;                  // first entry of the region in TilePlan::reg
+    int32_t ell_off;                  // first entry of the local ELL block
+    int32_t nreg;                     // region rows (= nt[degree])
+    int32_t nspmv;                    // rows with a local matrix row (= nt[max(degree - 1, 0)])
+    int32_t nt[TILE_MAX_DEGREE + 2];  // nt[t]: region rows at distance <= t
+};
+
+// Partition and local matrices of one mesh for one preconditioner degree.  Local
+// ELL: entry k of local row t at ell_off + k * nspmv + t, column = region index.
+struct TilePlan {
+    int32_t degree = 0, width = 0, nparts = 0;
+    std::vector<TileBlk> hblk;
+    DBuf<TileBlk> blk;
+    DBuf<int32_t> reg;
+    DBuf<uint16_t> ecol;
+    DBuf<float> eval32;
+    DBuf<double> eval64;
 };
 
 struct Mesh {
@@ -104,7 +135,14 @@ struct Mesh {
     DBuf<float> ell_val32;
     SolveWork work;
     int32_t tuned_lanes[2] = {0, 0};   // autotuned SpMV lanes per precision (0 = not tuned)
+    double gershgorin = 0.0;           // max_i sum_j |K_ij| / K_ii (0 = not computed)
+    std::unique_ptr<TilePlan> tiles[TILE_MAX_DEGREE + 1];   // per preconditioner degree
 };
+
+// builds (or returns) the tiled plan of a mesh for degree d; nullptr when the
+// mesh does not fit the tiled iteration (rows wider than 12, regions too large)
+TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree);
+double mesh_gershgorin(hipStream_t s, Mesh &m);
 
 // ------------------------------------------------------------------ solver launch records
 
@@ -150,6 +188,17 @@ struct InstDesc {
     const int32_t *ell_col;              // column-major ELL copy of the matrix
     const double *ell_val;
     const float *ell_val32;
+    // tiled iteration (degree >= 1; 0 = not tiled)
+    int32_t degree;
+    int32_t pad3_;
+    const TileBlk *tblk;                 // [nblk]
+    const int32_t *treg;
+    const uint16_t *tcol;
+    const float *tval32;
+    const double *tval;
+    double *u;                           // M^-1 r (own rows)
+    float *u32;
+    double cheb[2 * TILE_MAX_DEGREE];    // [0]: scale of the first step; [2k-1], [2k]: step k coefficients
 };
 
 struct SolveParams {
@@ -180,6 +229,9 @@ void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolvePar
 void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts, const int32_t *d_block_inst,
                     const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par, int32_t *d_done,
                     int32_t *d_host_flag);
+void launch_cg_tile(hipStream_t s, bool mixed, int width, int n_inst, const InstDesc *d_insts,
+                    const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
+                    int32_t *d_done, int32_t *d_host_flag);
 int pcg_ell_max_width();
 void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
                           const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,

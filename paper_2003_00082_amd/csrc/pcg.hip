@@ -657,26 +657,11 @@ __device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolvePa
     return transition(prev, S, prm, guess);
 }
 
-// ------------------------------------------------------------------ driver 1: one stage per launch
-
-template <class T, int H>
-__global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ insts,
-                                                   const int32_t *__restrict__ block_inst, int n_inst,
-                                                   const RowRange *__restrict__ ranges,
-                                                   const SolveParams *__restrict__ prm_dev, int par,
-                                                   int32_t *done_count, int32_t *host_flag) {
-    __shared__ Shared sh;
-    const int inst = n_inst == 1 ? 0 : block_inst[blockIdx.x];
-    const InstDesc D = insts[inst];
-    const int lb = blockIdx.x - D.blk0;
-    const RowRange R = ranges[blockIdx.x];
-    const int rd = par ^ 1;
-    const bool fast = D.fast && R.r1 - R.r0 <= BLOCK && R.c1 >= R.c0 && R.c1 - R.c0 + 1 <= H * BLOCK;
-    // speculative loads for an iteration, in flight while the state is decoded
-    IterPrefetch<T, H> f;
-    if (fast) iter_prefetch<T, H>(f, D, R, rd);
-    // decode the stage: wavefront 0 reduces the previous stage's partials and
-    // applies the transition; the other wavefronts wait at the barrier
+// Decode the stage: wavefront 0 reduces the previous stage's partials and applies
+// the transition into sh.ctl (workgroup 0 of the instance also carries the state
+// forward and reports completion); the other wavefronts wait at the barrier.
+__device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, const SolveParams *prm_dev,
+                                    Shared &sh, int32_t *done_count, int32_t *host_flag) {
     if (threadIdx.x < 64) {
         const Ctl prev = D.ctl[rd];
         double S[NPART];   // loaded whatever the state, so the loads overlap the control read
@@ -697,6 +682,27 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
         }
     }
     __syncthreads();
+}
+
+// ------------------------------------------------------------------ driver 1: one stage per launch
+
+template <class T, int H>
+__global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ insts,
+                                                   const int32_t *__restrict__ block_inst, int n_inst,
+                                                   const RowRange *__restrict__ ranges,
+                                                   const SolveParams *__restrict__ prm_dev, int par,
+                                                   int32_t *done_count, int32_t *host_flag) {
+    __shared__ Shared sh;
+    const int inst = n_inst == 1 ? 0 : block_inst[blockIdx.x];
+    const InstDesc D = insts[inst];
+    const int lb = blockIdx.x - D.blk0;
+    const RowRange R = ranges[blockIdx.x];
+    const int rd = par ^ 1;
+    const bool fast = D.fast && R.r1 - R.r0 <= BLOCK && R.c1 >= R.c0 && R.c1 - R.c0 + 1 <= H * BLOCK;
+    // speculative loads for an iteration, in flight while the state is decoded
+    IterPrefetch<T, H> f;
+    if (fast) iter_prefetch<T, H>(f, D, R, rd);
+    decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
     const Ctl c = sh.ctl;
     if (c.state == ST_DONE) return;
     double v[NPART] = {0.0, 0.0, 0.0, 0.0};
@@ -704,6 +710,223 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
         iter_fast<T, H>(f, c, D, R, par, reinterpret_cast<T *>(sh.lds), v);
     } else {
         const SolveParams prm = *prm_dev;
+        stage_work(c, D, R, prm, sh, par, v);
+    }
+    block_sums(v, sh.red, sh.sums);
+    if (threadIdx.x < NPART) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
+        sh.sums[threadIdx.x];
+}
+
+// ------------------------------------------------------------------ tiled iteration
+
+// One CG stage (iteration or restart of the recurrences) for a workgroup's tile,
+// with the preconditioner M^-1 = Jacobi (degree 1) or a Chebyshev polynomial of
+// degree d in D^-1 K: the workgroup gathers r, w, s and D^-1 over its region
+// (distance <= d), updates r there, runs the d-step Chebyshev iteration for
+// K z = r' on shrinking prefixes of the region (each product with K loses one
+// distance level) and ends with u' = z and w' = K u' on its own rows — one
+// global reduction per iteration however large d is.
+constexpr int TH = TILE_REGION / BLOCK;   // region rows per thread
+constexpr int TS = TILE_SPMV / BLOCK;     // local matrix rows per thread
+static_assert(BLOCK == TILE_ROWS, "one own row per thread");
+static_assert(3 * TILE_REGION * sizeof(double) <= LDS_DOUBLES * sizeof(double), "three region vectors in LDS");
+
+template <class T, int W>
+struct TilePrefetch {
+    int32_t g[TH];                 // region rows t = tid + h * BLOCK (global ids, -1 past the end)
+    T r[TH], w[TH], s[TH], dv[TH];
+    T ou, op, ox;                  // own row: u = M^-1 r, p, c (mixed) or x (fp64)
+    T ev[TS][W];                   // local matrix rows t = tid + h * BLOCK
+    uint32_t ec[TS][W / 2];        // their region columns, two 16-bit indices per register
+};
+
+template <class T>
+__device__ inline const T *tile_val(const InstDesc &D);
+template <>
+__device__ inline const double *tile_val<double>(const InstDesc &D) { return D.tval; }
+template <>
+__device__ inline const float *tile_val<float>(const InstDesc &D) { return D.tval32; }
+
+template <class T, int W>
+__device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, const TileBlk &B, int rd) {
+    const int64_t n = D.n;
+    const CGP_GLOBAL uint16_t *ec = gld(D.tcol + B.ell_off);
+    const CGP_GLOBAL T *ev = gld(tile_val<T>(D) + B.ell_off);
+#pragma unroll
+    for (int h = 0; h < TS; ++h) {
+        const int t = threadIdx.x + h * BLOCK;
+        if (t < B.nspmv) {
+#pragma unroll
+            for (int k = 0; k < W; k += 2)
+                f.ec[h][k / 2] = static_cast<uint32_t>(ec[k * B.nspmv + t]) |
+                                 (static_cast<uint32_t>(ec[(k + 1) * B.nspmv + t]) << 16);
+#pragma unroll
+            for (int k = 0; k < W; ++k) f.ev[h][k] = ev[k * B.nspmv + t];
+        }
+    }
+    const CGP_GLOBAL int32_t *reg = gld(D.treg + B.reg_off);
+#pragma unroll
+    for (int h = 0; h < TH; ++h) {
+        const int t = threadIdx.x + h * BLOCK;
+        f.g[h] = t < B.nreg ? reg[t] : -1;
+    }
+    const CGP_GLOBAL T *r = gld(vec_of<T>(D, 0) + rd * n), *w = gld(vec_of<T>(D, 1) + rd * n);
+    const CGP_GLOBAL T *s = gld(vec_of<T>(D, 2) + rd * n), *dv = gld(vec_of<T>(D, 3));
+#pragma unroll
+    for (int h = 0; h < TH; ++h) {
+        const int32_t j = f.g[h];
+        if (j >= 0) {
+            f.r[h] = r[j];
+            f.w[h] = w[j];
+            f.s[h] = s[j];
+            f.dv[h] = dv[j];
+        }
+    }
+    if (static_cast<int>(threadIdx.x) < B.nt[0]) {
+        const int32_t j = f.g[0];
+        if constexpr (sizeof(T) == 4) {
+            f.ou = gld(D.u32)[j];
+            f.op = gld(D.p32)[j];
+            f.ox = gld(D.c32)[j];
+        } else {
+            f.ou = gld(D.u)[j];
+            f.op = gld(D.p)[j];
+            f.ox = gld(D.x)[j];
+        }
+    }
+}
+
+// y_t = sum_k ev[h][k] * x[ec[h][k]] for the thread's local matrix row h
+template <class T, int W>
+__device__ inline T tile_row(const TilePrefetch<T, W> &f, int h, const T *x) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc += f.ev[h][k] * x[(f.ec[h][k / 2] >> (16 * (k & 1))) & 0xffffu];
+    return acc;
+}
+
+// nt: the tile's distance prefix counts, cheb: the Chebyshev coefficients (both in LDS).
+// Each Chebyshev step is one pass over the rows that still need it: the step's
+// residual update (one product with K, reading the previous step's dz of the
+// neighbours from LDS) and its dz and z updates; r', the residual and z of a row
+// stay in the thread's registers (no other row reads them), dz alternates
+// between two LDS buffers, and the last step leaves the final z there for w = K z.
+template <class T, int W>
+__device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, const InstDesc &D, const TileBlk &B,
+                                 const int32_t *nt, const double *cheb, int wr, T *lds, double (&v)[NPART]) {
+    const int64_t n = D.n;
+    const bool start = c.state == ST_START;
+    const bool rs = c.restart;
+    const T al = start ? T(0) : static_cast<T>(c.alpha), be = static_cast<T>(c.beta);
+    T *Zl = lds, *Da = lds + TILE_REGION, *Db = Da + TILE_REGION;
+    const int deg = D.degree;
+    const T c0 = static_cast<T>(cheb[0]);
+    T s_own = T(0), r_own = T(0);
+    T rr[TS], zz[TS], qq[TS], dd[TS];
+    // r' = r - alpha (w + beta s) over the region; first Chebyshev step z = c0 D^-1 r'
+#pragma unroll
+    for (int h = 0; h < TH; ++h) {
+        const int t = threadIdx.x + h * BLOCK;
+        if (t < B.nreg) {
+            const T sj = start ? f.s[h] : (rs ? f.w[h] : f.w[h] + be * f.s[h]);
+            const T rj = start ? f.r[h] : f.r[h] - al * sj;
+            if (h == 0) {
+                s_own = sj;
+                r_own = rj;
+            }
+            const T z = f.dv[h] * rj * c0;
+            Zl[t] = z;
+            if (h < TS) {
+                rr[h] = rj;
+                zz[h] = z;
+                dd[h] = z;
+            }
+        }
+    }
+    __syncthreads();
+    const T *Uz = Zl;   // where the final z ends up
+    for (int k = 1; k < deg; ++k) {
+        // step k on rows at distance <= d-k: res_k = res_{k-1} - K dz_{k-1} (res_1 = r' - K z_1),
+        // dz_k = a1 dz_{k-1} + a2 D^-1 res_k, z += dz_k
+        const T a1 = static_cast<T>(cheb[2 * k - 1]), a2 = static_cast<T>(cheb[2 * k]);
+        const int lim = nt[deg - k];
+        const T *src = k == 1 ? Zl : ((k & 1) ? Db : Da);
+        T *dst = (k & 1) ? Da : Db;
+        const bool last = k + 1 == deg;
+#pragma unroll
+        for (int h = 0; h < TS; ++h) {
+            const int t = threadIdx.x + h * BLOCK;
+            if (t < lim) {
+                const T kx = tile_row(f, h, src);
+                qq[h] = k == 1 ? rr[h] - kx : qq[h] - kx;
+                const T dz = a1 * dd[h] + a2 * (f.dv[h] * qq[h]);
+                dd[h] = dz;
+                zz[h] += dz;
+                dst[t] = last ? zz[h] : dz;
+            }
+        }
+        __syncthreads();
+        Uz = dst;
+    }
+    // own rows: u' = z, w' = K u', the recurrences and the reductions
+    if (static_cast<int>(threadIdx.x) < nt[0]) {
+        const int32_t j = f.g[0];
+        const T u1 = zz[0];
+        const T wn = tile_row(f, 0, Uz);
+        gst(const_cast<T *>(vec_of<T>(D, 0)) + wr * n)[j] = r_own;
+        gst(const_cast<T *>(vec_of<T>(D, 1)) + wr * n)[j] = wn;
+        gst(const_cast<T *>(vec_of<T>(D, 2)) + wr * n)[j] = s_own;
+        if constexpr (sizeof(T) == 4)
+            gst(D.u32)[j] = u1;
+        else
+            gst(D.u)[j] = u1;
+        if (!start) {
+            const T pj = rs ? f.ou : f.ou + be * f.op;
+            gst(const_cast<T *>(vec_of<T>(D, 4)))[j] = pj;
+            if constexpr (sizeof(T) == 4)
+                gst(D.c32)[j] = f.ox + al * pj;
+            else
+                gst(D.x)[j] = f.ox + al * pj;
+        }
+        const double r64 = static_cast<double>(r_own), u64 = static_cast<double>(u1);
+        v[0] += r64 * u64;
+        v[1] += static_cast<double>(wn) * u64;
+        v[2] += u64 * static_cast<double>(s_own);
+        v[3] += r64 * r64;
+    }
+}
+
+// fp32: at most 128 VGPRs, so that two workgroups share a compute unit and a grid of
+// up to twice the compute units (a 131841-row mesh cuts into 258 tiles) runs at once
+template <class T, int W>
+__global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const InstDesc *__restrict__ insts,
+                                                   const int32_t *__restrict__ block_inst, int n_inst,
+                                                   const RowRange *__restrict__ ranges,
+                                                   const SolveParams *__restrict__ prm_dev, int par,
+                                                   int32_t *done_count, int32_t *host_flag) {
+    __shared__ Shared sh;
+    __shared__ int32_t s_nt[TILE_MAX_DEGREE + 2];
+    __shared__ double s_cheb[2 * TILE_MAX_DEGREE];
+    const int inst = n_inst == 1 ? 0 : block_inst[blockIdx.x];
+    const InstDesc D = insts[inst];
+    const int lb = blockIdx.x - D.blk0;
+    const TileBlk B = D.tblk[lb];
+    const int rd = par ^ 1;
+    // per-distance row counts and coefficients, indexed by a run-time degree: LDS
+    if (threadIdx.x < TILE_MAX_DEGREE + 2) s_nt[threadIdx.x] = D.tblk[lb].nt[threadIdx.x];
+    if (threadIdx.x < 2 * TILE_MAX_DEGREE) s_cheb[threadIdx.x] = insts[inst].cheb[threadIdx.x];
+    // speculative loads for an iteration, in flight while the state is decoded
+    TilePrefetch<T, W> f;
+    tile_prefetch<T, W>(f, D, B, rd);
+    decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
+    const Ctl c = sh.ctl;
+    if (c.state == ST_DONE) return;
+    double v[NPART] = {0.0, 0.0, 0.0, 0.0};
+    if (c.state == ST_ITER || c.state == ST_START) {
+        tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), v);
+    } else {
+        const SolveParams prm = *prm_dev;
+        const RowRange R = ranges[blockIdx.x];
         stage_work(c, D, R, prm, sh, par, v);
     }
     block_sums(v, sh.red, sh.sums);
@@ -886,6 +1109,21 @@ void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_bloc
 void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
                     int32_t *d_done) {
     hipLaunchKernelGGL(k_cg_boot, dim3((n_inst + 255) / 256), dim3(256), 0, s, d_insts, n_inst, prm, d_prm, d_done);
+    CGP_HIP(hipGetLastError());
+}
+
+void launch_cg_tile(hipStream_t s, bool mixed, int width, int n_inst, const InstDesc *d_insts,
+                    const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
+                    int32_t *d_done, int32_t *d_host_flag) {
+#define CGP_TILE(T, W)                                                                                          \
+    hipLaunchKernelGGL((k_cg_tile<T, W>), dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, n_inst, d_ranges, \
+                       d_prm, par, d_done, d_host_flag)
+    if (mixed) {
+        if (width <= 8) CGP_TILE(float, 8); else CGP_TILE(float, 12);
+    } else {
+        if (width <= 8) CGP_TILE(double, 8); else CGP_TILE(double, 12);
+    }
+#undef CGP_TILE
     CGP_HIP(hipGetLastError());
 }
 

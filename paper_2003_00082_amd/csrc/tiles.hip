@@ -1,0 +1,213 @@
+// Tiles of the coarse mesh for the tiled CG iteration (host side).
+//
+// Each workgroup of the tiled iteration owns a compact tile of at most 512 rows,
+// cut by recursive coordinate bisection of the node coordinates, and works on
+// the tile's region: the rows within graph distance d of the tile in the matrix
+// graph (d = degree of the polynomial preconditioner, 1 for Jacobi), listed own
+// rows first and then by distance, so that "distance <= t" is a prefix of the
+// list.  A local ELL copy of the matrix rows at distance <= d - 1, with columns
+// given as region indices, lets the workgroup apply the preconditioner and the
+// matrix to its own rows from the region's values alone.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "cgp_internal.hpp"
+
+namespace cgp {
+namespace {
+
+template <class T>
+std::vector<T> d2h(hipStream_t s, const T *p, size_t n) {
+    std::vector<T> h(n);
+    if (n) CGP_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    CGP_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+template <class T>
+void h2d(hipStream_t s, DBuf<T> &d, const std::vector<T> &h) {
+    d.alloc(h.size());
+    if (!h.empty()) CGP_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// split ids[lo, hi) into `parts` pieces of nearly equal size, each cut across the
+// longer side of the piece's bounding box; appends the end of every piece to cuts
+void bisect(std::vector<int32_t> &ids, size_t lo, size_t hi, int parts, const std::vector<double> &xy,
+            std::vector<size_t> &cuts) {
+    if (parts <= 1) {
+        cuts.push_back(hi);
+        return;
+    }
+    double mn[2] = {std::numeric_limits<double>::infinity(), std::numeric_limits<double>::infinity()};
+    double mx[2] = {-mn[0], -mn[1]};
+    for (size_t q = lo; q < hi; ++q)
+        for (int a = 0; a < 2; ++a) {
+            const double v = xy[2 * static_cast<size_t>(ids[q]) + a];
+            mn[a] = std::min(mn[a], v);
+            mx[a] = std::max(mx[a], v);
+        }
+    const int ax = (mx[0] - mn[0] >= mx[1] - mn[1]) ? 0 : 1;
+    const int pl = parts / 2;
+    const size_t nl = (hi - lo) * static_cast<size_t>(pl) / static_cast<size_t>(parts);
+    std::nth_element(ids.begin() + lo, ids.begin() + lo + nl, ids.begin() + hi, [&](int32_t a, int32_t b) {
+        const double xa = xy[2 * static_cast<size_t>(a) + ax], xb = xy[2 * static_cast<size_t>(b) + ax];
+        return xa < xb || (xa == xb && a < b);
+    });
+    bisect(ids, lo, lo + nl, pl, xy, cuts);
+    bisect(ids, lo + nl, hi, parts - pl, xy, cuts);
+}
+
+// the tiles for `parts` pieces, or an empty plan when a region or its matrix rows
+// exceed the workgroup's capacity
+bool build_tiles(int64_t n, int parts, int degree, int width, const std::vector<int32_t> &rowptr,
+                 const std::vector<int32_t> &col, const std::vector<double> &val, const std::vector<double> &xy,
+                 std::vector<TileBlk> &blk, std::vector<int32_t> &reg, std::vector<uint16_t> &ecol,
+                 std::vector<double> &eval) {
+    std::vector<int32_t> ids(n);
+    for (int64_t i = 0; i < n; ++i) ids[i] = static_cast<int32_t>(i);
+    std::vector<size_t> cuts;
+    bisect(ids, 0, static_cast<size_t>(n), parts, xy, cuts);
+    std::vector<int32_t> mark(n, -1), loc(n, -1);
+    blk.assign(parts, TileBlk{});
+    reg.clear();
+    ecol.clear();
+    eval.clear();
+    size_t b0 = 0;
+    for (int p = 0; p < parts; ++p) {
+        const size_t b1 = cuts[p];
+        if (b1 - b0 > static_cast<size_t>(TILE_ROWS)) return false;
+        TileBlk &B = blk[p];
+        B.reg_off = static_cast<int32_t>(reg.size());
+        B.ell_off = static_cast<int32_t>(ecol.size());
+        std::vector<int32_t> list(ids.begin() + b0, ids.begin() + b1);
+        std::sort(list.begin(), list.end());
+        for (int32_t g : list) mark[g] = p;
+        B.nt[0] = static_cast<int32_t>(list.size());
+        size_t f0 = 0;
+        for (int t = 1; t <= degree; ++t) {
+            const size_t f1 = list.size();
+            std::vector<int32_t> next;
+            for (size_t q = f0; q < f1; ++q) {
+                const int32_t g = list[q];
+                for (int32_t k = rowptr[g]; k < rowptr[g + 1]; ++k) {
+                    const int32_t j = col[k];
+                    if (mark[j] != p) {
+                        mark[j] = p;
+                        next.push_back(j);
+                    }
+                }
+            }
+            std::sort(next.begin(), next.end());
+            list.insert(list.end(), next.begin(), next.end());
+            B.nt[t] = static_cast<int32_t>(list.size());
+            f0 = f1;
+        }
+        for (int t = degree + 1; t < TILE_MAX_DEGREE + 2; ++t) B.nt[t] = B.nt[degree];
+        B.nreg = B.nt[degree];
+        B.nspmv = B.nt[std::max(degree - 1, 0)];
+        if (B.nreg > TILE_REGION || B.nspmv > TILE_SPMV) return false;
+        for (int32_t t = 0; t < B.nreg; ++t) loc[list[t]] = t;
+        ecol.resize(ecol.size() + static_cast<size_t>(width) * B.nspmv);
+        eval.resize(eval.size() + static_cast<size_t>(width) * B.nspmv);
+        for (int32_t t = 0; t < B.nspmv; ++t) {
+            const int32_t g = list[t];
+            const int32_t len = rowptr[g + 1] - rowptr[g];
+            for (int k = 0; k < width; ++k) {
+                const size_t o = static_cast<size_t>(B.ell_off) + static_cast<size_t>(k) * B.nspmv + t;
+                if (k < len) {
+                    const int32_t lc = loc[col[rowptr[g] + k]];
+                    if (lc < 0) throw Error{CGP_E_HIP, "tile region misses a matrix neighbour"};
+                    ecol[o] = static_cast<uint16_t>(lc);
+                    eval[o] = val[rowptr[g] + k];
+                } else {
+                    ecol[o] = static_cast<uint16_t>(t);
+                    eval[o] = 0.0;
+                }
+            }
+        }
+        for (int32_t g : list) loc[g] = -1;
+        reg.insert(reg.end(), list.begin(), list.end());
+        b0 = b1;
+    }
+    // every row owned by exactly one tile; every index inside its array
+    std::vector<int32_t> owned(n, 0);
+    for (const TileBlk &B : blk) {
+        for (int32_t t = 0; t < B.nt[0]; ++t) ++owned[reg[static_cast<size_t>(B.reg_off) + t]];
+        for (int32_t t = 0; t < B.nreg; ++t) {
+            const int32_t g = reg[static_cast<size_t>(B.reg_off) + t];
+            if (g < 0 || g >= n) throw Error{CGP_E_HIP, "tile region row out of range"};
+        }
+        for (size_t q = 0; q < static_cast<size_t>(width) * B.nspmv; ++q)
+            if (ecol[B.ell_off + q] >= B.nreg) throw Error{CGP_E_HIP, "tile matrix column out of range"};
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (owned[i] != 1) throw Error{CGP_E_HIP, "tiles do not partition the rows"};
+    return true;
+}
+
+}  // namespace
+
+double mesh_gershgorin(hipStream_t s, Mesh &m) {
+    if (m.gershgorin > 0.0) return m.gershgorin;
+    const int64_t n = m.lv[0].n;
+    const auto rowptr = d2h(s, m.rowptr.p, n + 1);
+    const auto val = d2h(s, m.val.p, m.nnz);
+    const auto col = d2h(s, m.col.p, m.nnz);
+    double hi = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double sum = 0.0, diag = 0.0;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            sum += std::fabs(val[k]);
+            if (col[k] == i) diag = val[k];
+        }
+        if (diag > 0.0) hi = std::max(hi, sum / diag);
+    }
+    m.gershgorin = hi;
+    return hi;
+}
+
+TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
+    CGP_REQUIRE(degree >= 1 && degree <= TILE_MAX_DEGREE, "preconditioner degree out of range");
+    if (m.tiles[degree]) return m.tiles[degree]->nparts > 0 ? m.tiles[degree].get() : nullptr;
+    auto plan = std::make_unique<TilePlan>();
+    TilePlan *out = nullptr;
+    const int width = m.max_row <= 8 ? 8 : (m.max_row <= 12 ? 12 : 0);
+    if (width > 0) {
+        const int64_t n = m.lv[0].n;
+        const auto rowptr = d2h(s, m.rowptr.p, n + 1);
+        const auto col = d2h(s, m.col.p, m.nnz);
+        const auto val = d2h(s, m.val.p, m.nnz);
+        const auto xy = d2h(s, m.lv[0].xy.p, 2 * n);
+        std::vector<TileBlk> blk;
+        std::vector<int32_t> reg;
+        std::vector<uint16_t> ecol;
+        std::vector<double> eval;
+        // more, smaller tiles until every region fits (tiles of at least 64 rows)
+        int parts = static_cast<int>((n + TILE_ROWS - 1) / TILE_ROWS);
+        const int max_parts = static_cast<int>((n + 63) / 64);
+        bool ok = false;
+        while (!ok && parts <= max_parts) {
+            ok = build_tiles(n, parts, degree, width, rowptr, col, val, xy, blk, reg, ecol, eval);
+            if (!ok) parts = parts + std::max(1, parts / 8);
+        }
+        if (ok) {
+            plan->degree = degree;
+            plan->width = width;
+            plan->nparts = parts;
+            plan->hblk = blk;
+            h2d(s, plan->blk, blk);
+            h2d(s, plan->reg, reg);
+            h2d(s, plan->ecol, ecol);
+            h2d(s, plan->eval64, eval);
+            std::vector<float> e32(eval.begin(), eval.end());
+            h2d(s, plan->eval32, e32);
+            CGP_HIP(hipStreamSynchronize(s));
+            out = plan.get();
+        }
+    }
+    m.tiles[degree] = std::move(plan);
+    return out;
+}
+
+}  // namespace cgp

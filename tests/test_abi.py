@@ -45,4 +45,4 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
 def test_struct_layouts_match_the_header():
     import paper_2003_00082_amd as cgp
     assert ctypes.sizeof(cgp.SolveStats) == 32
-    assert ctypes.sizeof(cgp.SolveOpts) == 48
+    assert ctypes.sizeof(cgp.SolveOpts) == 56

@@ -179,7 +179,7 @@ def _solve(ctx, cgp, handle, b, x0=None, guess=None, precision=0, tol=1e-10, **k
     return phi.cpu().numpy(), st
 
 
-ENGINES = [1, 2]   # CGP_ENGINE_STAGED, CGP_ENGINE_PERSISTENT
+ENGINES = [1, 2, 3]   # CGP_ENGINE_STAGED (tiled), CGP_ENGINE_PERSISTENT, CGP_ENGINE_STAGED_ROWS
 
 
 @pytest.mark.parametrize("engine", ENGINES)
@@ -348,3 +348,94 @@ def test_graph_replay_matches_eager(ctx, cgp, c1):
     gctx.graph_free(gctx.graph_end())
     gctx.mesh_free(h)
     gctx.close()
+
+
+# ---------------------------------------------------------------- Chebyshev polynomial preconditioner
+
+def cheb_meshes():
+    return {
+        "rect_33x17": ci.jittered_rect(33, 17, 1001),
+        "rect_129x65": ci.jittered_rect(129, 65, 1002),      # 17 tiles, regions several rows deep
+        "hole_41x21": ci.rect_with_hole(41, 21, (12, 28, 6, 14), seed=5),
+        "permuted_40x21": ci.permuted(ci.jittered_rect(40, 21, 6), seed=7),
+        "ragged_7x4": ci.jittered_rect(7, 4, 5),
+    }
+
+
+@pytest.fixture(scope="module")
+def cheb_cases(ctx):
+    out = {}
+    for name, m in cheb_meshes().items():
+        a = fem.system_matrix(m.xy, m.tri, m.dirichlet)
+        u, v = ci.stream_velocity(m.xy, ci.fourier_modes(77), 0.0)
+        b = fem.source(m.xy, m.tri, m.dirichlet, u, v, fem.CURL, 1.0)
+        out[name] = (m, a, b, ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 1))
+    yield out
+    for m, a, b, h in out.values():
+        ctx.mesh_free(h)
+
+
+@pytest.mark.parametrize("name", list(cheb_meshes()))
+@pytest.mark.parametrize("degree", [1, 2, 3, 5, 8])
+def test_chebyshev_fp64_matches_direct_and_oracle(ctx, cgp, cheb_cases, name, degree):
+    m, a, b, h = cheb_cases[name]
+    xs = solve.direct(a, b)
+    x, st = _solve(ctx, cgp, h, b, tol=1e-10, precond_degree=degree)
+    assert st["status"] == "ok" and st["rel_res"] <= 1e-10
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-8
+    _, info = solve.pcg(a, b, tol=1e-10, degree=degree)
+    assert abs(st["iters"] - info["iters"]) <= 2, (st, info)
+
+
+@pytest.mark.parametrize("name", ["rect_129x65", "hole_41x21", "permuted_40x21"])
+@pytest.mark.parametrize("degree", [2, 4, 8])
+def test_chebyshev_mixed_matches_direct_and_oracle(ctx, cgp, cheb_cases, name, degree):
+    m, a, b, h = cheb_cases[name]
+    xs = solve.direct(a, b)
+    x, st = _solve(ctx, cgp, h, b, precision=cgp.CGP_FP32_IR, tol=1e-8, precond_degree=degree)
+    assert st["status"] == "ok" and st["rel_res"] <= 1e-8
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-6
+    _, info = solve.pcg_mixed(a, b, tol=1e-8, degree=degree)
+    assert abs(st["iters"] - info["iters"]) <= max(3, info["iters"] // 10), (st, info)
+
+
+def test_chebyshev_guess_modes_and_batches(ctx, cgp, cheb_cases):
+    names = ["rect_33x17", "rect_129x65", "hole_41x21"]
+    hs = [cheb_cases[k][3] for k in names]
+    bs = [dt(cheb_cases[k][2]) for k in names]
+    refs = [solve.direct(cheb_cases[k][1], cheb_cases[k][2]) for k in names]
+    for prec, tol, bound in ((cgp.CGP_FP64, 1e-10, 1e-8), (cgp.CGP_FP32_IR, 1e-8, 1e-6)):
+        xs = [torch.zeros_like(b) for b in bs]
+        stats = cgp.stats_buffer(len(hs))
+        ctx.poisson_solve(hs, bs, xs, stats, precision=prec, guess=cgp.CGP_GUESS_ZERO, tol=tol, precond_degree=4)
+        for x, ref, st in zip(xs, refs, ctx.solve_check(len(hs), stats)):
+            assert st["status"] == "ok"
+            assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) <= bound
+        # exact previous solutions: the extrapolation is exact, nothing to iterate
+        xs = [torch.zeros_like(b) for b in bs]
+        ctx.poisson_solve(hs, bs, xs, stats, prev1=[dt(r) for r in refs], prev2=[dt(r) for r in refs],
+                          precision=prec, guess=cgp.CGP_GUESS_EXTRAP, tol=1e-8, precond_degree=4)
+        assert all(st["iters"] == 0 for st in ctx.solve_check(len(hs), stats))
+
+
+def test_chebyshev_edge_cases(ctx, cgp, c1):
+    n = c1.m.n_nodes
+    x, st = _solve(ctx, cgp, c1.handle, np.zeros(n), x0=np.ones(n), precond_degree=5)
+    assert st["status"] == "ok" and st["iters"] == 0 and not x.any()
+    _, st = _solve(ctx, cgp, c1.handle, c1.b_phi, max_iter=2, precond_degree=5)
+    assert st["status"] == "noconv" and st["iters"] == 2
+    bad = c1.b_phi.copy()
+    bad[7] = np.inf
+    _, st = _solve(ctx, cgp, c1.handle, bad, precond_degree=3)
+    assert st["status"] == "breakdown"
+    x1, s1 = _solve(ctx, cgp, c1.handle, c1.b_phi, precision=cgp.CGP_FP32_IR, tol=1e-8, precond_degree=6)
+    x2, s2 = _solve(ctx, cgp, c1.handle, c1.b_phi, precision=cgp.CGP_FP32_IR, tol=1e-8, precond_degree=6)
+    np.testing.assert_array_equal(x1, x2)
+    assert s1 == s2
+    for kw in (dict(engine=cgp.CGP_ENGINE_PERSISTENT), dict(engine=cgp.CGP_ENGINE_STAGED_ROWS)):
+        with pytest.raises(cgp.CGPError) as e:
+            _solve(ctx, cgp, c1.handle, c1.b_phi, precond_degree=4, **kw)
+        assert e.value.code == cgp.CGP_E_UNSUPPORTED
+    with pytest.raises(cgp.CGPError) as e:
+        _solve(ctx, cgp, c1.handle, c1.b_phi, precond_degree=9)
+    assert e.value.code == cgp.CGP_E_INVALID
