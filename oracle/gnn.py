@@ -16,11 +16,15 @@ Training minimises the energy norm of the guess error measured in the scaled
 output: L = (delta^T K delta) / N_free with delta = (y - y*) on free nodes and
 y* = (phi* - e) / s_d, because the energy norm is what CG reduces.
 
-``emulate=True`` rounds, as the device does, every matrix-product operand to
-bfloat16 (round to nearest even): features, weights, stored activations, the
-neighbour mean, and in the backward pass the activation gradients; biases, the
-decoder and all accumulations stay in high precision.  ``emulate=False`` is
-plain fp64 (used for the finite-difference pin of the backward pass).
+``emulate=True`` rounds, as the device does, to bfloat16 (round to nearest
+even): the weights of every matrix product, forward and backward, and in the
+backward pass the other operands of the gradient products (layer inputs,
+features and activation gradients).  Forward activations, features and the
+neighbour mean are not rounded: the device carries them in fp32 and feeds the
+matrix cores their bfloat16 high and low parts, which represent them to about
+2^-17.  Biases, the decoder and all accumulations stay in high precision.
+``emulate=False`` is plain fp64 (used for the finite-difference pin of the
+backward pass).
 
 Parameter vector (float32 on the device, float64 here), in this order:
 W0 [16 x 64] (rows 8..15 multiply zero padding), c0 [64], then for l = 1..3
@@ -112,15 +116,15 @@ def forward(theta, x, mean_op, emulate: bool = True):
     """Network output y and the saved intermediates."""
     p = unpack(theta)
     r = bf16 if emulate else (lambda v: np.asarray(v, dtype=np.float64))
-    xq = r(x)
+    xq = np.asarray(x, dtype=np.float64)
     a0 = xq @ r(p["W0"][:F_IN]) + p["c0"]
-    h = r(np.maximum(a0, 0.0))
+    h = np.maximum(a0, 0.0)
     cache = {"xq": xq, "a": [a0], "h": [h], "z": []}
     for l in range(1, LAYERS + 1):
-        m = r(mean_op @ h)
+        m = mean_op @ h
         z = np.concatenate([h, m], axis=1)
         a = z @ r(p[f"W{l}"]) + p[f"c{l}"]
-        h = r(np.maximum(a, 0.0) + h)
+        h = np.maximum(a, 0.0) + h
         cache["z"].append(z)
         cache["a"].append(a)
         cache["h"].append(h)
@@ -157,12 +161,12 @@ def loss_and_grad(theta, k, dirichlet, b, p1, p2, target, mean_op, emulate=True)
         a = c["a"][l]
         da = dh * (a > 0.0)
         daq = r(da)
-        g[f"W{l}"] = c["z"][l - 1].T @ daq
+        g[f"W{l}"] = r(c["z"][l - 1]).T @ daq
         g[f"c{l}"] = da.sum(axis=0)
         dz = daq @ r(p[f"W{l}"]).T
         dh = dh + dz[:, :HIDDEN] + mean_op.T @ dz[:, HIDDEN:]
     da0 = dh * (c["a"][0] > 0.0)
     da0q = r(da0)
-    g["W0"][:F_IN] = c["xq"].T @ da0q
+    g["W0"][:F_IN] = r(c["xq"]).T @ da0q
     g["c0"] = da0.sum(axis=0)
     return loss, pack(g)
