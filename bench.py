@@ -68,8 +68,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="ABCDE")
     ap.add_argument("--degree", type=int, default=8, help="Chebyshev preconditioner degree of forms B, C, D")
-    ap.add_argument("--train-steps", type=int, default=48, help="steps solved (fp64) to train the networks")
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--train-steps", type=int, default=200, help="steps solved (fp64) to train the networks")
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workload", default="sequence", choices=["sequence", "batch"],
                     help="sequence: one 513x257 CGP sequence (default); batch: 64-instance Stuart sweep")

@@ -8,10 +8,13 @@
 //   layers    h <- relu([h, mean_nbr(h)] W_l + c_l) + h      128 -> 64, l = 1..3
 //   decoder   y = h w_d + c_d;  guess = (e + s_d y) on free nodes
 //
-// Dense products run on the matrix cores (v_mfma_f32_32x32x16_bf16): bfloat16
-// operands (features, weights, stored activations, neighbour means, and the
-// activation gradients of the backward pass), fp32 accumulation; biases,
-// decoder, reductions and master weights in fp32.  Training minimises the
+// Dense products run on the matrix cores (v_mfma_f32_32x32x16_bf16) with
+// bfloat16 weights and fp32 accumulation.  Activations, features and neighbour
+// means are fp32; the forward pass feeds each as two bfloat16 operands, its high
+// part and the remainder (a + b with a = bf16(v), b = bf16(v - a) carries v to
+// about 2^-17), so the network's output carries no per-node bfloat16 noise.  The
+// gradient products take single bfloat16 operands (layer inputs, features,
+// activation gradients).  Biases, decoder, reductions and master weights in fp32.  Training minimises the
 // energy norm (delta^T K delta)/N_free of the scaled output error with Adam.
 // Every reduction is a per-workgroup partial followed by a fixed-order sum: no
 // floating-point atomics, bitwise reproducible.
@@ -45,8 +48,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 struct GnnWork {
     int64_t n = 0;
     DBuf<double> e, d, re, kd, part, scales, delta;
-    DBuf<bf16> x;                 // [n, 16]
-    DBuf<bf16> h[GL + 1];         // [n, 64]
+    DBuf<float> x;                // [n, 16] features (training)
+    DBuf<float> h[GL + 1];        // [n, 64] activations
     DBuf<float> a[GL + 1];        // pre-activations [n, 64] (training)
     DBuf<float> y;                // [n]
     DBuf<float> dy, dh, dhp, dm;  // training
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_scales(int64_t n, const double *par
 // ------------------------------------------------------------------ forward layers
 
 // Z tile [TM x 128] in LDS: own h row and the mean of the neighbours' h rows
-__device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const bf16 *h, const int32_t *adj_ptr,
+__device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const float *h, const int32_t *adj_ptr,
                                const int32_t *adj_col) {
     for (int task = threadIdx.x; task < TM * (GH / 8); task += blockDim.x) {
         const int r = task / (GH / 8), c = (task % (GH / 8)) * 8;
@@ -163,14 +166,14 @@ __device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const bf16 *h, co
         for (int q = 0; q < 8; ++q) self[q] = acc[q] = 0.0f;
         if (i < n) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) self[q] = from_bf16(h[i * GH + c + q]);
+            for (int q = 0; q < 8; ++q) self[q] = h[i * GH + c + q];
             int deg = 0;
             for (int32_t k = adj_ptr[i]; k < adj_ptr[i + 1]; ++k) {
                 const int32_t j = adj_col[k];
                 if (j == i) continue;
                 ++deg;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) acc[q] += from_bf16(h[static_cast<int64_t>(j) * GH + c + q]);
+                for (int q = 0; q < 8; ++q) acc[q] += h[static_cast<int64_t>(j) * GH + c + q];
             }
             const float inv = deg > 0 ? 1.0f / static_cast<float>(deg) : 0.0f;
 #pragma unroll
@@ -187,26 +190,27 @@ __device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const bf16 *h, co
 // Forward layer, one wavefront per 32-row tile; a workgroup takes groups of four
 // consecutive tiles (grid-stride, the same trip count for all its wavefronts).  The
 // MFMA A operand of lane l is row l%32, columns 8(l/32)..+7 of each 16-wide k step,
-// i.e. the 16-byte chunks 2s + l/32 of the row: the lane gathers exactly those chunks
-// of its own row and of its neighbours straight into registers.  Weights arrive
-// transposed ([64 x K] bf16) and are shared through LDS rows padded by 16 bytes; the
-// accumulator tile goes back through LDS so that each lane finishes its own row's
-// chunks (residual from the registers it gathered, 16-byte stores).
+// i.e. the 8-value chunks 2s + l/32 of the row: the lane gathers exactly those
+// chunks of its own row and of its neighbours (fp32) straight into registers and
+// feeds each as its bfloat16 high part and remainder (two MFMAs per k step).
+// Weights arrive transposed ([64 x K] bf16) and are shared through LDS rows padded
+// by 16 bytes; the accumulator tile goes back through LDS so that each lane
+// finishes its own row's chunks (residual from the registers it gathered).
 //   MODE 0  encoder: features of the row computed here from b, p1, p2, r_e, K d, d
 //   MODE 1  message layer: h' = relu([h, mean_nbr h] W + c) + h
 //   MODE 2  message layer + decoder: y = h' w_d + c_d, guess = e + s_d y on free nodes
 struct FwdArgs {
     int64_t n;
     const int32_t *adj_ptr, *adj_col;
-    const bf16 *hin;
+    const float *hin;
     const double *b, *p1, *p2, *re, *kd, *d, *e, *scales;
     const uint8_t *dir;
     const bf16 *wT;
     const float *bias;
     const float *wd;      // w_d [64] then c_d
-    bf16 *hout;
+    float *hout;
     float *aout;          // pre-activations (training) or null
-    bf16 *xout;           // encoder: features (training) or null
+    float *xout;          // encoder: features (training) or null
     float *yout;          // decoder: network output or null
     double *guess;        // decoder: guess or null
 };
@@ -216,6 +220,26 @@ constexpr int FWD_MAX_BLOCKS = 2048;
 constexpr int CTS = 36;   // padded row of the 32x32 accumulator tile in LDS (floats)
 
 __device__ inline bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+struct F8 {
+    float v[8];
+};
+__device__ inline F8 ldf8(const float *p) {
+    const float4 a = reinterpret_cast<const float4 *>(p)[0], b = reinterpret_cast<const float4 *>(p)[1];
+    return F8{{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}};
+}
+__device__ inline void stf8(float *p, const float (&v)[8]) {
+    reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+    reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+// v = hi + lo with hi = bf16(v), lo = bf16(v - hi)
+__device__ inline void split8(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        hi[q] = to_bf16(v[q]);
+        lo[q] = to_bf16(v[q] - from_bf16(hi[q]));
+    }
+}
 
 template <int MODE>
 __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
@@ -235,7 +259,8 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
     for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int64_t row0 = (g * FWD_WAVES + wave) * 32, i = row0 + r;
         const bool valid = i < n;
-        bf16x8 af[KS];
+        bf16x8 ah[KS], al[KS];
+        float self[MODE == 0 ? 1 : 4][8];
         if constexpr (MODE == 0) {
             float f[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             if (valid && half == 0) {
@@ -249,15 +274,21 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
                 f[6] = static_cast<float>(A.dir[i]);
                 f[7] = 1.0f;
             }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) af[0][q] = to_bf16(f[q]);
-            if (A.xout && valid) *reinterpret_cast<bf16x8 *>(A.xout + i * GFP + 8 * half) = af[0];
+            split8(f, ah[0], al[0]);
+            if (A.xout && valid) stf8(A.xout + i * GFP + 8 * half, f);
         } else {
-            const bf16 *h = A.hin;
+            const float *h = A.hin;
             float acc[4][8];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                af[j] = valid ? ld8(h + i * GH + (2 * j + half) * 8) : bf16x8{};
+                if (valid) {
+                    const F8 c = ldf8(h + i * GH + (2 * j + half) * 8);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) self[j][q] = c.v[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) self[j][q] = 0.0f;
+                }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) acc[j][q] = 0.0f;
             }
@@ -274,27 +305,32 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
                         ++deg;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
-                            const bf16x8 c = ld8(h + static_cast<int64_t>(nb[u]) * GH + (2 * j + half) * 8);
+                            const F8 c = ldf8(h + static_cast<int64_t>(nb[u]) * GH + (2 * j + half) * 8);
 #pragma unroll
-                            for (int q = 0; q < 8; ++q) acc[j][q] += from_bf16(c[q]);
+                            for (int q = 0; q < 8; ++q) acc[j][q] += c.v[q];
                         }
                     }
                 }
             }
             const float inv = deg > 0 ? 1.0f / static_cast<float>(deg) : 0.0f;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) af[4 + j][q] = to_bf16(acc[j][q] * inv);
+                for (int q = 0; q < 8; ++q) acc[j][q] *= inv;
+                split8(self[j], ah[j], al[j]);
+                split8(acc[j], ah[4 + j], al[4 + j]);
+            }
         }
         float ypart = 0.0f;
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
             f32x16 c = {};
 #pragma unroll
-            for (int s = 0; s < KS; ++s)
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[s], ld8(Wl + (ct * 32 + r) * KP + 16 * s + 8 * half),
-                                                            c, 0, 0, 0);
+            for (int s = 0; s < KS; ++s) {
+                const bf16x8 w = ld8(Wl + (ct * 32 + r) * KP + 16 * s + 8 * half);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], w, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], w, c, 0, 0, 0);
+            }
 #pragma unroll
             for (int v = 0; v < 16; ++v) C[((v >> 2) * 8 + half * 4 + (v & 3)) * CTS + r] = c[v];
             __syncthreads();
@@ -302,22 +338,16 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
             for (int jj = 0; jj < 2; ++jj) {
                 const int cb = (2 * jj + half) * 8, col = ct * 32 + cb;
                 if (valid) {
-                    float pre[8];
-                    bf16x8 hb;
+                    float pre[8], hv[8];
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         pre[q] = C[r * CTS + cb + q] + A.bias[col + q];
-                        float hv = fmaxf(pre[q], 0.0f);
-                        if constexpr (MODE != 0) hv += from_bf16(af[2 * ct + jj][q]);
-                        hb[q] = to_bf16(hv);
-                        if (MODE == 2) ypart += from_bf16(hb[q]) * A.wd[col + q];
+                        hv[q] = fmaxf(pre[q], 0.0f);
+                        if constexpr (MODE != 0) hv[q] += self[2 * ct + jj][q];
+                        if (MODE == 2) ypart += hv[q] * A.wd[col + q];
                     }
-                    *reinterpret_cast<bf16x8 *>(A.hout + i * GH + col) = hb;
-                    if (A.aout) {
-                        float4 *o = reinterpret_cast<float4 *>(A.aout + i * GH + col);
-                        o[0] = make_float4(pre[0], pre[1], pre[2], pre[3]);
-                        o[1] = make_float4(pre[4], pre[5], pre[6], pre[7]);
-                    }
+                    stf8(A.hout + i * GH + col, hv);
+                    if (A.aout) stf8(A.aout + i * GH + col, pre);
                 }
             }
             __syncthreads();
@@ -375,7 +405,7 @@ __global__ void k_gnn_loss(const double *lpart, int nblk, double nfree, double *
 }
 
 // dh3 = dy w_d^T; partials of h3^T dy (64) and sum(dy) (1) per block: gpart[blk][65]
-__global__ __launch_bounds__(TPB) void k_gnn_dec_bwd(int64_t n, const float *dy, const bf16 *h, const float *theta,
+__global__ __launch_bounds__(TPB) void k_gnn_dec_bwd(int64_t n, const float *dy, const float *h, const float *theta,
                                                      float *dh, float *gpart) {
     __shared__ float red[TPB / 64][GH + 1];
     const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
@@ -384,7 +414,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_dec_bwd(int64_t n, const float *dy,
         float v;
         if (q < GH) {
             if (i < n) dh[i * GH + q] = g * theta[P_WD + q];
-            v = i < n ? from_bf16(h[i * GH + q]) * g : 0.0f;
+            v = i < n ? h[i * GH + q] * g : 0.0f;
         } else {
             v = g;
         }
@@ -402,7 +432,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_dec_bwd(int64_t n, const float *dy,
 // message layer backward for BW_SUB*TM rows: da = dh * (a > 0);
 // dW partial = Z^T bf16(da), dc partial = colsum(da); dZ = bf16(da) W^T ->
 // dhp = dh + dZ[:, :64], dm = dZ[:, 64:] / deg
-__global__ __launch_bounds__(TPB) void k_gnn_layer_bwd(int64_t n, const bf16 *hin, const int32_t *adj_ptr,
+__global__ __launch_bounds__(TPB) void k_gnn_layer_bwd(int64_t n, const float *hin, const int32_t *adj_ptr,
                                                        const int32_t *adj_col, const bf16 *W, const float *a,
                                                        const float *dh, float *dhp, float *dm, float *gpart) {
     constexpr int K = 2 * GH;
@@ -487,7 +517,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_agg_bwd(int64_t n, const int32_t *a
 }
 
 // encoder backward for BW_SUB*TM rows: partials of X^T bf16(da0) (16x64) and colsum(da0)
-__global__ __launch_bounds__(TPB) void k_gnn_enc_bwd(int64_t n, const bf16 *x, const float *a, const float *dh,
+__global__ __launch_bounds__(TPB) void k_gnn_enc_bwd(int64_t n, const float *x, const float *a, const float *dh,
                                                      float *gpart) {
     __shared__ float Xs[TM * GFP];
     __shared__ float Dq[TM * GH];
@@ -498,7 +528,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_enc_bwd(int64_t n, const bf16 *x, c
         const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * BW_SUB + sub) * TM;
         for (int t = threadIdx.x; t < TM * GFP; t += TPB) {
             const int64_t i = r0 + t / GFP;
-            Xs[t] = i < n ? from_bf16(x[r0 * GFP + t]) : 0.0f;
+            Xs[t] = i < n ? from_bf16(to_bf16(x[r0 * GFP + t])) : 0.0f;
         }
         for (int t = threadIdx.x; t < TM * GH; t += TPB) {
             const int64_t i = r0 + t / GH;

@@ -1,15 +1,17 @@
 """Learned initial guess on the GPU (through the C ABI) against the network oracle.
 
-The device computes the dense products with bfloat16 operands and fp32
-accumulation, the oracle with the same bfloat16 roundings and fp64 sums.  The
-two round the same values; they differ only where an fp32 sum and its fp64
-counterpart fall on opposite sides of a bfloat16 rounding boundary, which moves
-that one value by one bfloat16 step (2^-8 relative).  Measured on 777 nodes the
-network output then differs by at most 1.2e-4 and every gradient block by at
-most 2e-4 (norm-wise, relative); the tolerances below (1e-3, 2e-3) sit well
-above that and well below the 2.5e-3 .. 3e-2 gap between the bfloat16-emulating
-oracle and plain fp64, so a device that skipped a rounding the oracle makes, or
-made one the oracle does not, fails them.
+The device computes the dense products with bfloat16 weights and fp32
+accumulation; forward activations are fp32, fed to the matrix cores as their
+bfloat16 high part and remainder (about 2^-17 relative); the gradient products
+take single bfloat16 operands.  The oracle rounds the same operands (weights;
+in the backward pass also layer inputs, features and activation gradients) and
+sums in fp64.  Forward outputs then agree to the fp32 level: 7e-6 at most
+measured on 777 nodes, against 1.2e-3 .. 1.9e-3 between the bfloat16-emulating
+oracle and plain fp64, so the 1e-4 tolerance below catches a device that does
+not round the weights.  Gradients differ where an fp32 operand and its fp64
+counterpart round to different bfloat16 values (one step, 2^-8 relative): at
+most 1.9e-3 per block measured, tolerance 4e-3, against a 7e-3 .. 2.6e-2 gap
+to unrounded fp64.
 """
 import numpy as np
 import pytest
@@ -139,7 +141,7 @@ def test_predict_matches_oracle(ctx, seq, seed):
             free = seq.m.dirichlet == 0
             np.testing.assert_array_equal(got[~free], 0.0)
             y_got = (got[free] - e[free]) / sd
-            assert rel(y_got, y_ref[free]) <= 1e-3
+            assert rel(y_got, y_ref[free]) <= 1e-4
     finally:
         ctx.model_free(md)
 
@@ -153,11 +155,11 @@ def test_grad_matches_oracle(ctx, seq):
         loss, g = ctx.model_grad(md, seq.handle, dt(b), dt(p1), dt(p2), dt(tgt))
         lref, gref = gnn.loss_and_grad(th.astype(np.float64), seq.a, seq.m.dirichlet, b, p1, p2, tgt, seq.mo,
                                        emulate=True)
-        assert loss == pytest.approx(lref, rel=5e-4)
+        assert loss == pytest.approx(lref, rel=5e-5)
         offs = np.cumsum([0] + [int(np.prod(s)) for _, s in gnn.param_shapes()])
         for q, (name, _) in enumerate(gnn.param_shapes()):
             gs, rs = g[offs[q]:offs[q + 1]], gref[offs[q]:offs[q + 1]]
-            assert rel(gs.astype(np.float64), rs) <= 2e-3, name
+            assert rel(gs.astype(np.float64), rs) <= 4e-3, name
         np.testing.assert_array_equal(g[8 * 64:16 * 64], 0.0)
     finally:
         ctx.model_free(md)
