@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="ABCDE")
     ap.add_argument("--degree", type=int, default=8, help="Chebyshev preconditioner degree of forms B, C, D")
+    ap.add_argument("--refine-delta", type=float, default=1e-3,
+                    help="fp32 Chebyshev forms: refine when the fp32 residual fell by this factor since the last "
+                         "refinement (the Jacobi forms keep the library's default, 0.1)")
     ap.add_argument("--train-steps", type=int, default=200, help="steps solved (fp64) to train the networks")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -178,7 +181,7 @@ def batch_main(args):
         def solve(eq, bvecs, n):
             cur, p1, p2 = (bufs[eq][(n - k) % 3] for k in range(3))
             kw = dict(prev1=p1, prev2=p2, guess=cgp.CGP_GUESS_EXTRAP, precision=cgp.CGP_FP32_IR, tol=TOL,
-                      precond_degree=fdeg)
+                      precond_degree=fdeg, refine_delta=args.refine_delta if fdeg >= 2 else 0.0)
             if engine == "staged_chebyshev":
                 ctx.poisson_solve(H, bvecs, cur, st[eq], engine=cgp.CGP_ENGINE_STAGED, **kw)
             elif engine == "staged_jacobi":
@@ -363,7 +366,8 @@ def main():
 
         def solve(eq, bvec, n, slot, timed):
             B = bufs[eq]
-            kw = dict(precision=prec, guess=guess, precond_degree=fdeg)
+            kw = dict(precision=prec, guess=guess, precond_degree=fdeg,
+                      refine_delta=args.refine_delta if fdeg >= 2 else 0.0)
             if rotating:
                 cur, p1, p2 = B[n % 3], B[(n - 1) % 3], B[(n - 2) % 3]
                 kw.update(prev1=[p1], prev2=[p2])

@@ -164,13 +164,14 @@ typedef struct {
     int32_t guess;        /* CGP_GUESS_*                                                */
     double tol;           /* stop when ||b - K phi||_2 <= tol ||b||_2 (true fp64 residual) */
     double refine_delta;  /* CGP_FP32_IR: refine when the fp32 residual fell by this factor
-                             since the last refinement (0 = default 0.1)                 */
+                             since the last refinement (0 = default: 0.1 with Jacobi,
+                             0.01 with the Chebyshev preconditioner)                    */
     int32_t max_iter;     /* cap on CG iterations per instance (0 = default 100000)      */
     cgp_model model;      /* network for CGP_GUESS_LEARNED                               */
     int32_t spmv_lanes;   /* lanes per matrix row: 0 = autotuned/default, else 1,2,4,8   */
     int32_t blocks;       /* workgroups of the solve: 0 = one per compute unit           */
     int32_t engine;       /* CGP_ENGINE_*                                                */
-    int32_t launches_per_graph; /* CGP_ENGINE_STAGED: stages per replayed graph (0 = 32; even) */
+    int32_t launches_per_graph; /* CGP_ENGINE_STAGED: stages per replayed graph (0 = 16; even) */
     int32_t precond_degree; /* 0 or 1: Jacobi M = diag(K); 2..8: Chebyshev polynomial of this
                              degree in D^-1 K over [hi/1000, hi], hi = max_i sum_j |K_ij|/K_ii
                              (Gershgorin), applied as that many steps of Chebyshev

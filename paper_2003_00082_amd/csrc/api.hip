@@ -418,10 +418,11 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             throw Error{CGP_E_UNSUPPORTED, "a mesh does not fit the tiled iteration the Chebyshev preconditioner needs"};
         SolveParams prm{};
         prm.tol = o.tol;
-        prm.delta = o.refine_delta > 0.0 ? o.refine_delta : 0.1;
+        // fewer iterations between refinements with the Chebyshev preconditioner: longer fp32 runs
+        prm.delta = o.refine_delta > 0.0 ? o.refine_delta : (o.precond_degree >= 2 ? 0.01 : 0.1);
         prm.max_iter = o.max_iter > 0 ? o.max_iter : 100000;
         prm.precision = o.precision;
-        const int launches = o.launches_per_graph > 0 ? o.launches_per_graph : 32;
+        const int launches = o.launches_per_graph > 0 ? o.launches_per_graph : 16;
 
         const int max_grid = ctx->cus * ctx->max_blocks_per_cu;
         int grid = o.blocks > 0 ? o.blocks : ctx->cus;

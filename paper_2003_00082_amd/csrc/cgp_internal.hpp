@@ -99,14 +99,18 @@ constexpr int TILE_MAX_DEGREE = 8;
 // graph distance d of the tile, listed own rows first and then by distance.
 struct TileBlk {
     int32_t reg_off;                  // first entry of the region in TilePlan::reg
-    int32_t ell_off;                  // first entry of the local ELL block
+    int32_t ell_off;                  // first local matrix row record of the tile
     int32_t nreg;                     // region rows (= nt[degree])
     int32_t nspmv;                    // rows with a local matrix row (= nt[max(degree - 1, 0)])
     int32_t nt[TILE_MAX_DEGREE + 2];  // nt[t]: region rows at distance <= t
 };
 
+// 16-bit column entries per local matrix row record (a multiple of 8: 16-byte loads)
+constexpr int tile_col_stride(int width) { return width <= 8 ? 8 : 16; }
+
 // Partition and local matrices of one mesh for one preconditioner degree.  Local
-// ELL: entry k of local row t at ell_off + k * nspmv + t, column = region index.
+// matrix row t of a tile: columns (region indices) at (ell_off + t) * tile_col_stride,
+// values at (ell_off + t) * width.
 struct TilePlan {
     int32_t degree = 0, width = 0, nparts = 0;
     std::vector<TileBlk> hblk;

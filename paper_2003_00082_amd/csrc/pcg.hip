@@ -747,21 +747,48 @@ __device__ inline const double *tile_val<double>(const InstDesc &D) { return D.t
 template <>
 __device__ inline const float *tile_val<float>(const InstDesc &D) { return D.tval32; }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <class T, int W>
 __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, const TileBlk &B, int rd) {
     const int64_t n = D.n;
-    const CGP_GLOBAL uint16_t *ec = gld(D.tcol + B.ell_off);
-    const CGP_GLOBAL T *ev = gld(tile_val<T>(D) + B.ell_off);
+    constexpr int CW = tile_col_stride(W);   // 16-bit columns per record
+    constexpr int VP = 16 / sizeof(T);        // values per 16-byte load
+    static_assert(W % VP == 0, "value records are whole 16-byte loads");
 #pragma unroll
     for (int h = 0; h < TS; ++h) {
         const int t = threadIdx.x + h * BLOCK;
+#pragma unroll
+        for (int k = 0; k < W / 2; ++k) f.ec[h][k] = 0u;   // rows past nspmv gather entry 0 times 0
+#pragma unroll
+        for (int k = 0; k < W; ++k) f.ev[h][k] = T(0);
         if (t < B.nspmv) {
+            const size_t row = static_cast<size_t>(B.ell_off) + t;
+            const CGP_GLOBAL u32x4 *ec = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(D.tcol) + row * CW);
+            const u32x4 c0 = ec[0];
+            f.ec[h][0] = c0.x;
+            f.ec[h][1] = c0.y;
+            f.ec[h][2] = c0.z;
+            f.ec[h][3] = c0.w;
+            if constexpr (W > 8) {
+                const u32x4 c1 = ec[1];
+                f.ec[h][4] = c1.x;
+                f.ec[h][5] = c1.y;
+            }
+            const CGP_GLOBAL u32x4 *ev = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(tile_val<T>(D)) + row * W);
 #pragma unroll
-            for (int k = 0; k < W; k += 2)
-                f.ec[h][k / 2] = static_cast<uint32_t>(ec[k * B.nspmv + t]) |
-                                 (static_cast<uint32_t>(ec[(k + 1) * B.nspmv + t]) << 16);
-#pragma unroll
-            for (int k = 0; k < W; ++k) f.ev[h][k] = ev[k * B.nspmv + t];
+            for (int q = 0; q < W / VP; ++q) {
+                const u32x4 u = ev[q];
+                if constexpr (sizeof(T) == 4) {
+                    f.ev[h][4 * q] = __uint_as_float(u.x);
+                    f.ev[h][4 * q + 1] = __uint_as_float(u.y);
+                    f.ev[h][4 * q + 2] = __uint_as_float(u.z);
+                    f.ev[h][4 * q + 3] = __uint_as_float(u.w);
+                } else {
+                    f.ev[h][2 * q] = __hiloint2double(static_cast<int>(u.y), static_cast<int>(u.x));
+                    f.ev[h][2 * q + 1] = __hiloint2double(static_cast<int>(u.w), static_cast<int>(u.z));
+                }
+            }
         }
     }
     const CGP_GLOBAL int32_t *reg = gld(D.treg + B.reg_off);
@@ -853,12 +880,15 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
         const T *src = k == 1 ? Zl : ((k & 1) ? Db : Da);
         T *dst = (k & 1) ? Da : Db;
         const bool last = k + 1 == deg;
+        // the gathers of all of the thread's rows first (in flight together), then the updates
+        T kx[TS];
+#pragma unroll
+        for (int h = 0; h < TS; ++h) kx[h] = tile_row(f, h, src);
 #pragma unroll
         for (int h = 0; h < TS; ++h) {
             const int t = threadIdx.x + h * BLOCK;
             if (t < lim) {
-                const T kx = tile_row(f, h, src);
-                qq[h] = k == 1 ? rr[h] - kx : qq[h] - kx;
+                qq[h] = k == 1 ? rr[h] - kx[h] : qq[h] - kx[h];
                 const T dz = a1 * dd[h] + a2 * (f.dv[h] * qq[h]);
                 dd[h] = dz;
                 zz[h] += dz;

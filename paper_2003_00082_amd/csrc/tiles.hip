@@ -7,7 +7,10 @@
 // rows first and then by distance, so that "distance <= t" is a prefix of the
 // list.  A local ELL copy of the matrix rows at distance <= d - 1, with columns
 // given as region indices, lets the workgroup apply the preconditioner and the
-// matrix to its own rows from the region's values alone.
+// matrix to its own rows from the region's values alone.  Its rows are records:
+// the columns of local row t (16-bit, padded to 8 or 16 entries) at
+// (ell_off + t) * cols_per_row, its values (width entries) at (ell_off + t) * width,
+// so that a thread reads a row with a few 16-byte loads.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -79,7 +82,7 @@ bool build_tiles(int64_t n, int parts, int degree, int width, const std::vector<
         if (b1 - b0 > static_cast<size_t>(TILE_ROWS)) return false;
         TileBlk &B = blk[p];
         B.reg_off = static_cast<int32_t>(reg.size());
-        B.ell_off = static_cast<int32_t>(ecol.size());
+        B.ell_off = static_cast<int32_t>(eval.size() / width);
         std::vector<int32_t> list(ids.begin() + b0, ids.begin() + b1);
         std::sort(list.begin(), list.end());
         for (int32_t g : list) mark[g] = p;
@@ -108,21 +111,22 @@ bool build_tiles(int64_t n, int parts, int degree, int width, const std::vector<
         B.nspmv = B.nt[std::max(degree - 1, 0)];
         if (B.nreg > TILE_REGION || B.nspmv > TILE_SPMV) return false;
         for (int32_t t = 0; t < B.nreg; ++t) loc[list[t]] = t;
-        ecol.resize(ecol.size() + static_cast<size_t>(width) * B.nspmv);
+        const int cw = tile_col_stride(width);
+        ecol.resize(ecol.size() + static_cast<size_t>(cw) * B.nspmv);
         eval.resize(eval.size() + static_cast<size_t>(width) * B.nspmv);
         for (int32_t t = 0; t < B.nspmv; ++t) {
             const int32_t g = list[t];
             const int32_t len = rowptr[g + 1] - rowptr[g];
-            for (int k = 0; k < width; ++k) {
-                const size_t o = static_cast<size_t>(B.ell_off) + static_cast<size_t>(k) * B.nspmv + t;
+            const size_t oc = (static_cast<size_t>(B.ell_off) + t) * cw, ov = (static_cast<size_t>(B.ell_off) + t) * width;
+            for (int k = 0; k < cw; ++k) {
                 if (k < len) {
                     const int32_t lc = loc[col[rowptr[g] + k]];
                     if (lc < 0) throw Error{CGP_E_HIP, "tile region misses a matrix neighbour"};
-                    ecol[o] = static_cast<uint16_t>(lc);
-                    eval[o] = val[rowptr[g] + k];
+                    ecol[oc + k] = static_cast<uint16_t>(lc);
+                    if (k < width) eval[ov + k] = val[rowptr[g] + k];
                 } else {
-                    ecol[o] = static_cast<uint16_t>(t);
-                    eval[o] = 0.0;
+                    ecol[oc + k] = static_cast<uint16_t>(t);
+                    if (k < width) eval[ov + k] = 0.0;
                 }
             }
         }
@@ -138,8 +142,10 @@ bool build_tiles(int64_t n, int parts, int degree, int width, const std::vector<
             const int32_t g = reg[static_cast<size_t>(B.reg_off) + t];
             if (g < 0 || g >= n) throw Error{CGP_E_HIP, "tile region row out of range"};
         }
-        for (size_t q = 0; q < static_cast<size_t>(width) * B.nspmv; ++q)
-            if (ecol[B.ell_off + q] >= B.nreg) throw Error{CGP_E_HIP, "tile matrix column out of range"};
+        const size_t cw = static_cast<size_t>(tile_col_stride(width));
+        for (size_t q = 0; q < cw * B.nspmv; ++q)
+            if (ecol[static_cast<size_t>(B.ell_off) * cw + q] >= B.nreg)
+                throw Error{CGP_E_HIP, "tile matrix column out of range"};
     }
     for (int64_t i = 0; i < n; ++i)
         if (owned[i] != 1) throw Error{CGP_E_HIP, "tiles do not partition the rows"};

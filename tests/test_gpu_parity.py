@@ -201,7 +201,7 @@ def test_mixed_solve_matches_direct(ctx, cgp, c1, lanes, engine):
     for b in (c1.b_phi, c1.b_p):
         xs = solve.direct(c1.a, b)
         x, st = _solve(ctx, cgp, c1.handle, b, precision=cgp.CGP_FP32_IR, tol=1e-8, spmv_lanes=lanes,
-                       engine=engine)
+                       engine=engine, refine_delta=0.1)
         assert st["status"] == "ok" and st["rel_res"] <= 1e-8 and st["refinements"] >= 1
         assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-6
         _, info = solve.pcg_mixed(c1.a, b, tol=1e-8)
@@ -392,7 +392,7 @@ def test_chebyshev_fp64_matches_direct_and_oracle(ctx, cgp, cheb_cases, name, de
 def test_chebyshev_mixed_matches_direct_and_oracle(ctx, cgp, cheb_cases, name, degree):
     m, a, b, h = cheb_cases[name]
     xs = solve.direct(a, b)
-    x, st = _solve(ctx, cgp, h, b, precision=cgp.CGP_FP32_IR, tol=1e-8, precond_degree=degree)
+    x, st = _solve(ctx, cgp, h, b, precision=cgp.CGP_FP32_IR, tol=1e-8, precond_degree=degree, refine_delta=0.1)
     assert st["status"] == "ok" and st["rel_res"] <= 1e-8
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-6
     _, info = solve.pcg_mixed(a, b, tol=1e-8, degree=degree)
