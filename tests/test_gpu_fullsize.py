@@ -1,0 +1,175 @@
+"""Parity at the workloads' full sizes, in the launch configuration the benchmark times.
+
+* 513x257 coarse / 1025x513 fine (the sequence workload): one CGP step through
+  the C ABI — restriction and source, the fp32 Chebyshev-8 solve with fp64
+  refinement from the extrapolation, prolongation, Lorentz force — against the
+  oracle on every output (the oracle's SuperLU gives phi*).
+* 1025x513 coarse refined twice (8394753 fine nodes): hierarchy counts (Euler),
+  the system matrix against the oracle's assembly, prolongation exact for a
+  linear field and the force of a linear potential in closed form at every fine
+  node, and a batch of 8 solves checked by the true fp64 residual the oracle
+  recomputes (properties that hold at any size).
+* The 64-instance batch of uneven meshes: every instance's true residual, and
+  four sampled instances against SuperLU.
+"""
+import numpy as np
+import pytest
+
+import cgp_inputs as ci
+from oracle import fem, mesh, solve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+TOL = 1e-8
+
+
+def dt(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def cgp():
+    import paper_2003_00082_amd as lib
+    lib.load()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def ctx(cgp):
+    c = cgp.Context(0)
+    yield c
+    c.close()
+
+
+def _bench_solve(ctx, cgp, hs, bs, xs, p1, p2):
+    stats = cgp.stats_buffer(len(hs))
+    ctx.poisson_solve(hs, bs, xs, stats, prev1=p1, prev2=p2, precision=cgp.CGP_FP32_IR,
+                      guess=cgp.CGP_GUESS_EXTRAP, tol=TOL, precond_degree=8, refine_delta=1e-3)
+    return ctx.solve_check(len(hs), stats)
+
+
+def test_sequence_step_513x257(ctx, cgp):
+    coarse = ci.jittered_rect(513, 257, 2000)
+    h = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+    try:
+        hier = mesh.Hierarchy(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+        nc, nf = coarse.n_nodes, hier.n_nodes(1)
+        seq = ci.FourierSequence(hier.xy[1], ci.fourier_modes(2500), ci.fourier_modes(2700))
+        a = fem.system_matrix(coarse.xy, coarse.tri, coarse.dirichlet)
+        rhs = {}
+        for n in (-2, -1, 0):
+            u, v, _, _ = seq.at(n)
+            rhs[n] = (u, v, fem.source(coarse.xy, coarse.tri, coarse.dirichlet, u[:nc], v[:nc], fem.CURL, 1.0))
+        sol = {n: solve.direct(a, rhs[n][2]) for n in (-2, -1, 0)}   # SuperLU at this size
+        u, v, b_ref = rhs[0]
+        b = torch.empty(nc, dtype=torch.float64, device=DEV)
+        ctx.restrict(h, dt(u), dt(v), cgp.CGP_SRC_CURL, 1.0, b)
+        ctx.sync()
+        np.testing.assert_allclose(b.cpu().numpy(), b_ref, rtol=0, atol=1e-12 * np.abs(b_ref).max())
+        phi = torch.zeros(nc, dtype=torch.float64, device=DEV)
+        st = _bench_solve(ctx, cgp, [h], [b], [phi], [dt(sol[-1])], [dt(sol[-2])])[0]
+        assert st["status"] == "ok" and st["rel_res"] <= TOL
+        x = phi.cpu().numpy()
+        assert np.linalg.norm(x - sol[0]) / np.linalg.norm(sol[0]) <= 1e-6
+        assert solve.relative_residual(a, b_ref, x) <= 1.01 * TOL
+        # the plain fp64 baseline of the same step
+        phi64 = dt(sol[-1])
+        stats = cgp.stats_buffer(1)
+        ctx.poisson_solve([h], [b], [phi64], stats, precision=cgp.CGP_FP64, guess=cgp.CGP_GUESS_GIVEN, tol=TOL)
+        assert ctx.solve_check(1, stats)[0]["status"] == "ok"
+        assert np.linalg.norm(phi64.cpu().numpy() - sol[0]) / np.linalg.norm(sol[0]) <= 1e-7
+        # prolongation (bit-exact) and the Lorentz force of the solved potential
+        phif = torch.empty(nf, dtype=torch.float64, device=DEV)
+        ctx.prolong(h, phi, phif)
+        fx, fy = (torch.empty(nf, dtype=torch.float64, device=DEV) for _ in range(2))
+        ctx.lorentz_force(h, phif, dt(u), dt(v), 1.0, 1.0, fx, fy)
+        ctx.sync()
+        pf = mesh.prolong(x, hier)
+        np.testing.assert_array_equal(phif.cpu().numpy(), pf)
+        fxr, fyr, _ = fem.lorentz_force(hier.xy[1], hier.tri[1], pf, u, v, 1.0, 1.0)
+        scale = max(np.abs(fxr).max(), np.abs(fyr).max())
+        np.testing.assert_allclose(fx.cpu().numpy(), fxr, rtol=0, atol=1e-11 * scale)
+        np.testing.assert_allclose(fy.cpu().numpy(), fyr, rtol=0, atol=1e-11 * scale)
+    finally:
+        ctx.mesh_free(h)
+
+
+def test_two_level_1025x513(ctx, cgp):
+    coarse = ci.jittered_rect(1025, 513, 5000)
+    n0, t0 = coarse.n_nodes, coarse.n_tris
+    handles = [ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 2)]
+    try:
+        i1, i2 = ctx.mesh_info(handles[0], 1), ctx.mesh_info(handles[0], 2)
+        n1 = 2 * n0 + t0 - 1                      # Euler: one boundary loop
+        assert (i1["n_nodes"], i1["n_tris"]) == (n1, 4 * t0)
+        assert (i2["n_nodes"], i2["n_tris"]) == (2 * n1 + 4 * t0 - 1, 16 * t0)
+        # the system matrix against the oracle's assembly
+        rowptr, col, val, _ = ctx.mesh_matrix(handles[0])
+        a = fem.system_matrix(coarse.xy, coarse.tri, coarse.dirichlet)
+        np.testing.assert_array_equal(rowptr, a.indptr)
+        np.testing.assert_array_equal(col, a.indices)
+        np.testing.assert_allclose(val, a.data, rtol=0, atol=1e-14 * np.abs(a.data).max())
+        # prolongation of a linear field is exact; its force is known in closed form
+        xyf = ctx.mesh_download(handles[0], 2)[0]
+        cx, cy, c0 = 0.7, -1.3, 0.25
+        lin = lambda xy: cx * xy[:, 0] + cy * xy[:, 1] + c0
+        nf = xyf.shape[0]
+        phif = torch.empty(nf, dtype=torch.float64, device=DEV)
+        ctx.prolong(handles[0], dt(lin(coarse.xy)), phif)
+        uf = np.sin(xyf[:, 0]) * np.cos(xyf[:, 1])
+        vf = np.cos(3 * xyf[:, 0])
+        fx, fy = (torch.empty(nf, dtype=torch.float64, device=DEV) for _ in range(2))
+        sig, b0 = 2.5, 1.5
+        ctx.lorentz_force(handles[0], phif, dt(uf), dt(vf), sig, b0, fx, fy)
+        ctx.sync()
+        np.testing.assert_allclose(phif.cpu().numpy(), lin(xyf), rtol=0, atol=1e-13)
+        np.testing.assert_allclose(fx.cpu().numpy(), sig * b0 * (-cy - b0 * uf), rtol=0, atol=1e-10)
+        np.testing.assert_allclose(fy.cpu().numpy(), sig * b0 * (cx - b0 * vf), rtol=0, atol=1e-10)
+        # a batch of 8 instances (own meshes and flows), solved together
+        for i in range(1, 8):
+            m = ci.jittered_rect(1025, 513, 5000 + i)
+            handles.append(ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 0))
+        bs, refs = [], []
+        for i, hh in enumerate(handles):
+            m = ci.jittered_rect(1025, 513, 5000 + i)
+            u, v = ci.stream_velocity(m.xy, ci.fourier_modes(5500 + i), 0.0)
+            bref = fem.source(m.xy, m.tri, m.dirichlet, u, v, fem.CURL, 1.0)
+            bs.append(dt(bref))
+            refs.append((fem.system_matrix(m.xy, m.tri, m.dirichlet), bref))
+        xs = [torch.zeros_like(b) for b in bs]
+        zeros = [torch.zeros_like(b) for b in bs]
+        sts = _bench_solve(ctx, cgp, handles, bs, xs, zeros, zeros)
+        for (ai, bi), x, st in zip(refs, xs, sts):
+            assert st["status"] == "ok"
+            assert solve.relative_residual(ai, bi, x.cpu().numpy()) <= 1.01 * TOL
+    finally:
+        for hh in handles:
+            ctx.mesh_free(hh)
+
+
+def test_batch_of_64_uneven_meshes(ctx, cgp):
+    sizes = ci.batch_sizes(64, 3000)
+    meshes = [ci.jittered_rect(nx, ny, 3000 + i) for i, (nx, ny) in enumerate(sizes)]
+    handles = [ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 1) for m in meshes]
+    try:
+        bs, mats = [], []
+        for i, m in enumerate(meshes):
+            u, v = ci.stream_velocity(m.xy, ci.fourier_modes(3500 + i), 0.0)
+            b = fem.source(m.xy, m.tri, m.dirichlet, u, v, fem.CURL, 1.0)
+            bs.append(b)
+            mats.append(fem.system_matrix(m.xy, m.tri, m.dirichlet))
+        xs = [torch.zeros(m.n_nodes, dtype=torch.float64, device=DEV) for m in meshes]
+        zeros = [torch.zeros_like(x) for x in xs]
+        sts = _bench_solve(ctx, cgp, handles, [dt(b) for b in bs], xs, zeros, zeros)
+        for a, b, x, st in zip(mats, bs, xs, sts):
+            assert st["status"] == "ok"
+            assert solve.relative_residual(a, b, x.cpu().numpy()) <= 1.01 * TOL
+        for i in (0, 17, 40, 63):
+            ref = solve.direct(mats[i], bs[i])
+            assert np.linalg.norm(xs[i].cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-6
+    finally:
+        for hh in handles:
+            ctx.mesh_free(hh)
