@@ -10,7 +10,10 @@ previous solutions to a correction of the extrapolated guess 2 phi^{n-1} - phi^{
   layers    m = mean over mesh neighbours (self excluded) of h
             h <- relu([h, m] W_l + c_l) + h,  l = 1, 2, 3          (128 -> 64)
   decoder   y = h w_d + c_d                                        (64 -> 1)
-  guess     phi0 = (e + s_d y) on free nodes, 0 on Dirichlet nodes
+  guess     phi0 = (e + s_d y) on free nodes, 0 on Dirichlet nodes, then SMOOTH_SWEEPS
+            damped Jacobi sweeps phi0 <- phi0 + (2/3) D^-1 (b - K phi0), which remove the
+            high-frequency part of the network's error (cheap for a smoother, costly for
+            a residual-based stopping rule) while keeping the smooth part it predicts
 
 Training minimises the energy norm of the guess error measured in the scaled
 output: L = (delta^T K delta) / N_free with delta = (y - y*) on free nodes and
@@ -36,6 +39,8 @@ import numpy as np
 import scipy.sparse as sp
 
 HIDDEN = 64
+SMOOTH_SWEEPS = 4
+SMOOTH_OMEGA = 2.0 / 3.0
 F_IN = 8
 F_PAD = 16
 LAYERS = 3
@@ -132,11 +137,20 @@ def forward(theta, x, mean_op, emulate: bool = True):
     return y, cache
 
 
-def guess(theta, k, dirichlet, b, p1, p2, mean_op, emulate=True):
+def smooth(k: sp.csr_matrix, b, x, sweeps: int = SMOOTH_SWEEPS, omega: float = SMOOTH_OMEGA):
+    """Damped Jacobi sweeps x <- x + omega D^-1 (b - K x), D = diag(K)."""
+    dinv = 1.0 / k.diagonal()
+    x = np.array(x, dtype=np.float64, copy=True)
+    for _ in range(sweeps):
+        x = x + omega * dinv * (b - k @ x)
+    return x
+
+
+def guess(theta, k, dirichlet, b, p1, p2, mean_op, emulate=True, sweeps: int = SMOOTH_SWEEPS):
     x, e, sd = features(k, dirichlet, b, p1, p2)
     y, _ = forward(theta, x, mean_op, emulate)
     free = 1.0 - np.asarray(dirichlet, dtype=np.float64)
-    return (e + sd * y) * free
+    return smooth(k, b, (e + sd * y) * free, sweeps)
 
 
 def loss_and_grad(theta, k, dirichlet, b, p1, p2, target, mean_op, emulate=True):

@@ -92,7 +92,7 @@ def test_loss_is_energy_norm_of_guess_error():
     th = _theta()
     for emulate in (False, True):
         loss, _ = gnn.loss_and_grad(th, k, m.dirichlet, b, p1, p2, tgt, mo, emulate=emulate)
-        g = gnn.guess(th, k, m.dirichlet, b, p1, p2, mo, emulate=emulate)
+        g = gnn.guess(th, k, m.dirichlet, b, p1, p2, mo, emulate=emulate, sweeps=0)
         d = p1 - p2
         sd = np.sqrt(np.mean(d * d))
         err = g - tgt
@@ -105,17 +105,41 @@ def test_zero_decoder_gives_extrapolation():
     p = gnn.unpack(_theta())
     p["wd"][:] = 0.0
     p["cd"][:] = 0.0
-    g = gnn.guess(gnn.pack(p), k, m.dirichlet, b, p1, p2, mo, emulate=True)
+    g = gnn.guess(gnn.pack(p), k, m.dirichlet, b, p1, p2, mo, emulate=True, sweeps=0)
     free = m.dirichlet == 0
     np.testing.assert_array_equal(g[free], (2 * p1 - p2)[free])
     np.testing.assert_array_equal(g[~free], 0.0)
+    # with the smoothing sweeps: the extrapolation, smoothed
+    g4 = gnn.guess(gnn.pack(p), k, m.dirichlet, b, p1, p2, mo, emulate=True)
+    np.testing.assert_array_equal(g4, gnn.smooth(k, b, (2 * p1 - p2) * free))
+
+
+def test_smoothing_damps_sine_modes_by_the_jacobi_factor():
+    # unjittered grid: K = 5-point stencil (D = 4 on free rows); with b = K x* the error
+    # of a sine mode is multiplied by (1 - omega lam / 4) per sweep
+    nx, ny = 33, 17
+    m = ci.jittered_rect(nx, ny, None)
+    k = fem.system_matrix(m.xy, m.tri, m.dirichlet)
+    i = np.arange(m.n_nodes) % nx
+    j = np.arange(m.n_nodes) // nx
+    xs = np.sin(np.pi * i / (nx - 1)) * np.sin(2 * np.pi * j / (ny - 1))
+    b = k @ xs
+    err = np.zeros(m.n_nodes)
+    expect = np.zeros(m.n_nodes)
+    for p, q, c in ((1, 1, 1.0), (20, 10, 0.5), (31, 15, -0.25)):
+        v = np.sin(p * np.pi * i / (nx - 1)) * np.sin(q * np.pi * j / (ny - 1))
+        lam = 4 - 2 * np.cos(p * np.pi / (nx - 1)) - 2 * np.cos(q * np.pi / (ny - 1))
+        err += c * v
+        expect += c * v * (1 - gnn.SMOOTH_OMEGA * lam / 4) ** 3
+    x = gnn.smooth(k, b, xs + err, sweeps=3)
+    np.testing.assert_allclose(x - xs, expect, rtol=0, atol=1e-13)
 
 
 def test_guess_is_homogeneous_of_degree_one():
     m, k, b, p1, p2, tgt, mo = _problem()
     th = _theta()
     g1 = gnn.guess(th, k, m.dirichlet, b, p1, p2, mo, emulate=False)
-    g2 = gnn.guess(th, k, m.dirichlet, 4.0 * b, 4.0 * p1, 4.0 * p2, mo, emulate=False)
+    g2 = gnn.guess(th, k, m.dirichlet, 4.0 * b, 4.0 * p1, 4.0 * p2, mo, emulate=False)   # smoothing is linear
     np.testing.assert_allclose(g2, 4.0 * g1, rtol=1e-12, atol=1e-14 * np.abs(g1).max())
 
 
