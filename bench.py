@@ -8,7 +8,7 @@ step.  One *step* is one pass of the whole hot path:
 
     restrict (Eq. 19) + curl source (Eq. 12) -> solve phi -> prolong phi (Eq. 20)
     -> Lorentz force (Eqs. 13-14) -> restrict + divergence source (Eq. 15)
-    -> solve p -> prolong p
+    -> solve p -> prolong p -> velocity correction (Eqs. 16-17)
 
 with both Poisson solves to a true relative residual of 1e-8.  Forms on the
 same inputs (d = --degree, the Chebyshev polynomial preconditioner's degree):
@@ -169,6 +169,8 @@ def batch_main(args):
     phif = [torch.empty(n, **f64) for n in nf]
     pf = [torch.empty(n, **f64) for n in nf]
     fx = [torch.empty(n, **f64) for n in nf]
+    un = [torch.empty(n, **f64) for n in nf]
+    vn = [torch.empty(n, **f64) for n in nf]
     fy = [torch.empty(n, **f64) for n in nf]
     nsteps = W + K
     stats_all = torch.zeros(2 * nsteps * M * cgp.STATS_BYTES, dtype=torch.uint8, device=dev)
@@ -210,7 +212,9 @@ def batch_main(args):
                 ctx.restrict(H[i], ut, vt, cgp.CGP_SRC_DIV, rho_dt, bp[i])
             p = solve("p", bp, n)
             for i in range(M):
+                _, _, ut, vt = vel[i][n]
                 ctx.prolong(H[i], p[i], pf[i])
+                ctx.velocity_correct(H[i], pf[i], ut, vt, 1.0 / rho_dt, un[i], vn[i])
 
         for n in range(-W, 0):
             step(n)
@@ -307,7 +311,7 @@ def main():
 
     f64 = dict(dtype=torch.float64, device=dev)
     b_phi, b_p = torch.empty(nc, **f64), torch.empty(nc, **f64)
-    phif, pf, fx, fy = (torch.empty(nf, **f64) for _ in range(4))
+    phif, pf, fx, fy, un, vn = (torch.empty(nf, **f64) for _ in range(6))
     sigma, rho_dt = args.stuart, 1.0 / ci.DT
     stats = cgp.stats_buffer(2 * len(steps))
     stream = torch.cuda.current_stream()
@@ -396,6 +400,7 @@ def main():
             ctx.restrict(h, ut, vt, cgp.CGP_SRC_DIV, rho_dt, b_p)
             p = solve("p", b_p, n, slot + 1, timed)
             ctx.prolong(h, p, pf)
+            ctx.velocity_correct(h, pf, ut, vt, 1.0 / rho_dt, un, vn)
             if n == 0:
                 keep["phi"], keep["p"] = phi.clone(), p.clone()
 

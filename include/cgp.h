@@ -10,7 +10,8 @@
  *                      and assemble the coarse source of Eq. 12 or Eq. 15;
  *   cgp_poisson_solve  solve the coarse Poisson system (Eqs. 12, 15);
  *   cgp_prolong        P1 prolongation back to the finest level (Eq. 20);
- *   cgp_lorentz_force  grad(phi_f) and the Lorentz source of Eqs. 13-14.
+ *   cgp_lorentz_force  grad(phi_f) and the Lorentz source of Eqs. 13-14;
+ *   cgp_velocity_correct  grad(p_f) and the projection of Eqs. 16-17.
  *
  * Conventions for every call:
  *   - Return value: CGP_OK (0) or a negative cgp_status.  No C++ exception
@@ -251,6 +252,17 @@ cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif,
                              const double *d_uf, const double *d_vf, double sigma, double B0,
                              double *d_fx, double *d_fy, double *d_grad_elem);
 
+/* Velocity correction of Eqs. 16-17 (step 8 of Section 2.2) on the finest level:
+ *   u = ut - scale G_x,  v = vt - scale G_y,  scale = dt / rho,
+ * with G the nodal gradient of the prolonged pressure d_pf [N_k] (the same
+ * area-weighted mean of element gradients as cgp_lorentz_force).  d_ut, d_vt
+ * [N_k] hold the intermediate velocity of Eqs. 13-14; d_u, d_v [N_k] receive
+ * the corrected velocity at every node (velocity boundary values belong to the
+ * momentum step and are re-imposed by the caller).  In place is allowed
+ * (d_u == d_ut, d_v == d_vt); d_u != d_v and neither is d_pf (CGP_E_INVALID). */
+cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, const double *d_ut,
+                                const double *d_vt, double scale, double *d_u, double *d_v);
+
 /* ------------------------------------------------------------------ learned initial guess */
 
 /* A graph network on the coarse mesh that predicts the initial guess of a
@@ -261,7 +273,9 @@ cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif,
  *             e = 2 p1 - p2, d = p1 - p2, r_e = b - K e, s_* = RMS over the nodes
  *   encoder   h = relu(X W0 + c0) (8 -> 64); three layers
  *             h <- relu([h, mean of the neighbours' h] W_l + c_l) + h (128 -> 64)
- *   decoder   y = h w_d + c_d;  guess = e + s_d y on free nodes, 0 on Dirichlet nodes
+ *   decoder   y = h w_d + c_d;  g = e + s_d y on free nodes, 0 on Dirichlet nodes
+ *   smoother  guess = g after 4 damped Jacobi sweeps g <- g + (2/3) D^-1 (b - K g),
+ *             which damp the high-frequency part of the network's error
  * Dense products use bfloat16 operands on the matrix cores with fp32
  * accumulation.  Parameters: cgp_model_param_count() floats, in the order
  * W0 [16x64] (rows 8..15 multiply zero padding), c0 [64], then W_l [128x64],

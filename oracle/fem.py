@@ -6,7 +6,8 @@
 * ``source``             the weak right-hand side of the coarse Poisson problems:
                           Eq. 12 (electric potential, curl of the restricted velocity
                           times B0) and Eq. 15 (pressure, divergence times rho/dt);
-* ``gradient_lorentz``   grad(phi_f) and the Lorentz force of Eqs. 13-14.
+* ``gradient_lorentz``   grad(phi_f) and the Lorentz force of Eqs. 13-14;
+* ``velocity_correction`` the projection of Eqs. 16-17 with grad(p_f).
 
 Sign convention (Eq. 12 / Eq. 15 are Delta(phi) = f): multiplying by a test
 function and integrating by parts gives K phi = b with b_i = -int f psi_i, so K is
@@ -130,3 +131,13 @@ def lorentz_force(xy, tri, phi_f, u_f, v_f, sigma: float, b0: float):
     fx = sigma * b0 * (-g[:, 1] - b0 * u_f)
     fy = sigma * b0 * (g[:, 0] - b0 * v_f)
     return fx, fy, element_gradient(xy, tri, phi_f)
+
+
+def velocity_correction(xy, tri, p_f, ut, vt, scale: float):
+    """Eqs. 16-17: u = ut - scale dp/dx, v = vt - scale dp/dy with scale = dt/rho.
+
+    The derivatives of the prolonged pressure are its nodal gradient (the same
+    area-weighted mean of element gradients as the Lorentz source uses).
+    """
+    g = nodal_gradient(xy, tri, p_f)
+    return ut - scale * g[:, 0], vt - scale * g[:, 1]

@@ -91,6 +91,7 @@ _SIGS = {
     "cgp_autotune": ([_vp, _i32, _vp, _i32, _vp], _i32),
     "cgp_prolong": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_lorentz_force": ([_vp, _i32, _vp, _vp, _vp, _f64, _f64, _vp, _vp, _vp], _i32),
+    "cgp_velocity_correct": ([_vp, _i32, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
     "cgp_model_param_count": ([], _i64),
     "cgp_model_create": ([_vp, ctypes.c_uint64, ctypes.POINTER(_i32)], _i32),
     "cgp_model_free": ([_vp, _i32], _i32),
@@ -239,6 +240,10 @@ class Context:
     def lorentz_force(self, mesh: int, phif, uf, vf, sigma: float, b0: float, fx, fy, grad_elem=None):
         _check(load().cgp_lorentz_force(self.handle, mesh, _ptr(phif), _ptr(uf), _ptr(vf), float(sigma), float(b0),
                                         _ptr(fx), _ptr(fy), _ptr(grad_elem)))
+
+    def velocity_correct(self, mesh: int, pf, ut, vt, scale: float, u, v):
+        _check(load().cgp_velocity_correct(self.handle, mesh, _ptr(pf), _ptr(ut), _ptr(vt), float(scale), _ptr(u),
+                                           _ptr(v)))
 
     def poisson_solve(self, meshes, b, phi, stats, *, prev1=None, prev2=None, precision=CGP_FP64,
                       guess=CGP_GUESS_GIVEN, tol=1e-8, refine_delta=0.0, max_iter=0, model=-1, spmv_lanes=0,

@@ -354,6 +354,19 @@ cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif, c
     });
 }
 
+cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, const double *d_ut,
+                                const double *d_vt, double scale, double *d_u, double *d_v) {
+    return guarded([&] {
+        use_device(ctx);
+        Mesh &m = get_mesh(ctx, mesh);
+        CGP_REQUIRE(d_pf && d_ut && d_vt && d_u && d_v, "null device pointer");
+        CGP_REQUIRE(std::isfinite(scale), "scale must be finite");
+        CGP_REQUIRE(d_u != d_v, "d_u and d_v must differ");
+        CGP_REQUIRE(d_u != d_pf && d_v != d_pf, "the output must not overwrite d_pf");
+        launch_velocity(ctx->stream, m, d_pf, d_ut, d_vt, scale, d_u, d_v);
+    });
+}
+
 cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_meshes, const double *const *h_d_b,
                              double *const *h_d_phi, const double *const *h_d_prev1,
                              const double *const *h_d_prev2, const cgp_solve_opts *h_opts,

@@ -252,6 +252,8 @@ void launch_prolong(hipStream_t s, Mesh &m, const double *qc, double *qf);
 void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const double *uf,
                     const double *vf, double sigma, double b0, double *fx, double *fy,
                     double *grad_elem);
+void launch_velocity(hipStream_t s, const Mesh &m, const double *pf, const double *ut, const double *vt,
+                     double scale, double *u, double *v);
 
 // learned initial guess (gnn.hip)
 struct Model;

@@ -69,6 +69,8 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int TM = 64;                 // rows per forward workgroup
+constexpr int SMOOTH_SWEEPS = 4;       // damped Jacobi sweeps applied to the network's guess
+constexpr double SMOOTH_OMEGA = 2.0 / 3.0;
 constexpr int BW_SUB = 4;              // 64-row sub-tiles per backward workgroup
 
 __device__ inline bf16 to_bf16(float v) { return static_cast<bf16>(v); }
@@ -260,7 +262,6 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
         const int64_t row0 = (g * FWD_WAVES + wave) * 32, i = row0 + r;
         const bool valid = i < n;
         bf16x8 ah[KS], al[KS];
-        float self[MODE == 0 ? 1 : 4][8];
         if constexpr (MODE == 0) {
             float f[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             if (valid && half == 0) {
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
             if (A.xout && valid) stf8(A.xout + i * GFP + 8 * half, f);
         } else {
             const float *h = A.hin;
-            float acc[4][8];
+            float self[4][8], acc[4][8];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (valid) {
@@ -338,12 +339,16 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
             for (int jj = 0; jj < 2; ++jj) {
                 const int cb = (2 * jj + half) * 8, col = ct * 32 + cb;
                 if (valid) {
+                    // the residual input is read again (a cache hit) rather than kept in registers
+                    // across the products
+                    F8 res{};
+                    if constexpr (MODE != 0) res = ldf8(A.hin + i * GH + col);
                     float pre[8], hv[8];
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         pre[q] = C[r * CTS + cb + q] + A.bias[col + q];
                         hv[q] = fmaxf(pre[q], 0.0f);
-                        if constexpr (MODE != 0) hv[q] += self[2 * ct + jj][q];
+                        if constexpr (MODE != 0) hv[q] += res.v[q];
                         if (MODE == 2) ypart += hv[q] * A.wd[col + q];
                     }
                     stf8(A.hout + i * GH + col, hv);
@@ -361,6 +366,18 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
             }
         }
     }
+}
+
+// one damped Jacobi sweep xout = xin + omega D^-1 (b - K xin); Dirichlet rows (identity, b = 0)
+// keep their zero
+__global__ __launch_bounds__(TPB) void k_gnn_smooth(int64_t n, const int32_t *rowptr, const int32_t *col,
+                                                    const double *val, const double *dinv, const double *b,
+                                                    const double *xin, double *xout, double omega) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    if (i >= n) return;
+    double kx = 0.0;
+    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) kx += val[k] * xin[col[k]];
+    xout[i] = xin[i] + omega * dinv[i] * (b[i] - kx);
 }
 
 // ------------------------------------------------------------------ training
@@ -672,6 +689,15 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
             A.guess = guess;
             hipLaunchKernelGGL(k_gnn_fwd<2>, dim3(nf), dim3(TPB), 0, s, A);
         }
+    }
+    // smoothing of the guess, ping-pong through re (no longer needed): an even number of
+    // sweeps ends in guess
+    static_assert(SMOOTH_SWEEPS % 2 == 0, "sweeps must end in the guess buffer");
+    for (int q = 0; guess && q < SMOOTH_SWEEPS; ++q) {
+        const double *xin = (q & 1) ? w.re.p : guess;
+        double *xout = (q & 1) ? guess : w.re.p;
+        hipLaunchKernelGGL(k_gnn_smooth, dim3(nb), dim3(TPB), 0, s, n, m.rowptr.p, m.col.p, m.val.p, m.dinv.p, b,
+                           xin, xout, SMOOTH_OMEGA);
     }
     CGP_HIP(hipGetLastError());
 }

@@ -4,8 +4,9 @@
 //                      assembly of the coarse right-hand side of Eq. 12 / Eq. 15
 //   k_prolong_level    P1 prolongation from one level to the next (Eq. 20)
 //   k_lorentz          nodal grad(phi_f) and the Lorentz source of Eqs. 13-14
+//   k_velocity         nodal grad(p_f) and the velocity correction of Eqs. 16-17
 //
-// All three are per-node gathers over the node->triangle incidence lists
+// All four are per-node gathers over the node->triangle incidence lists
 // (ascending triangle id), one thread per node: no atomics, deterministic.
 // They are HBM-bound streaming kernels (coordinates, connectivity and fields
 // read once per incident triangle from L2).
@@ -68,15 +69,12 @@ __global__ __launch_bounds__(TPB) void k_prolong_level(int64_t n, int64_t E, con
     }
 }
 
-// G_i = sum_e A_e g_e / sum_e A_e over the triangles around i, with
-// A_e g_e = 1/2 sum_a phi_a beta_a; F = sigma B0 (-G_y - B0 u, G_x - B0 v)
-__global__ __launch_bounds__(TPB) void k_lorentz(
-    int64_t n, const int32_t *__restrict__ ne_ptr, const int32_t *__restrict__ ne_idx,
-    const int32_t *__restrict__ tri, const double *__restrict__ xy, const double *__restrict__ phi,
-    const double *__restrict__ u, const double *__restrict__ v, double sigma, double b0,
-    double *__restrict__ fx, double *__restrict__ fy) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// nodal gradient G_i = sum_e A_e g_e / sum_e A_e over the triangles around i, with
+// A_e g_e = 1/2 sum_a phi_a beta_a
+__device__ inline void nodal_gradient(int64_t i, const int32_t *__restrict__ ne_ptr,
+                                      const int32_t *__restrict__ ne_idx, const int32_t *__restrict__ tri,
+                                      const double *__restrict__ xy, const double *__restrict__ phi, double &Gx,
+                                      double &Gy) {
     double gx = 0.0, gy = 0.0, area = 0.0;
     for (int32_t k = ne_ptr[i]; k < ne_ptr[i + 1]; ++k) {
         const int64_t e = ne_idx[k];
@@ -89,10 +87,37 @@ __global__ __launch_bounds__(TPB) void k_lorentz(
         gy += 0.5 * (p0 * (x2 - x1) + p1 * (x0 - x2) + p2 * (x1 - x0));
         area += 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
     }
-    gx /= area;
-    gy /= area;
+    Gx = gx / area;
+    Gy = gy / area;
+}
+
+// F = sigma B0 (-G_y - B0 u, G_x - B0 v)
+__global__ __launch_bounds__(TPB) void k_lorentz(
+    int64_t n, const int32_t *__restrict__ ne_ptr, const int32_t *__restrict__ ne_idx,
+    const int32_t *__restrict__ tri, const double *__restrict__ xy, const double *__restrict__ phi,
+    const double *__restrict__ u, const double *__restrict__ v, double sigma, double b0,
+    double *__restrict__ fx, double *__restrict__ fy) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double gx, gy;
+    nodal_gradient(i, ne_ptr, ne_idx, tri, xy, phi, gx, gy);
     fx[i] = sigma * b0 * (-gy - b0 * u[i]);
     fy[i] = sigma * b0 * (gx - b0 * v[i]);
+}
+
+// u = ut - scale G_x, v = vt - scale G_y (scale = dt / rho); u may alias ut and v vt,
+// since thread i reads and writes only entry i of them
+__global__ __launch_bounds__(TPB) void k_velocity(
+    int64_t n, const int32_t *__restrict__ ne_ptr, const int32_t *__restrict__ ne_idx,
+    const int32_t *__restrict__ tri, const double *__restrict__ xy, const double *__restrict__ p,
+    const double *ut, const double *vt, double scale, double *u, double *v) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double gx, gy;
+    nodal_gradient(i, ne_ptr, ne_idx, tri, xy, p, gx, gy);
+    const double a = ut[i], b = vt[i];
+    u[i] = a - scale * gx;
+    v[i] = b - scale * gy;
 }
 
 // element gradient g_e = sum_a phi_a beta_a / D_e
@@ -148,6 +173,14 @@ void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const doub
                            phif, grad_elem);
         CGP_HIP(hipGetLastError());
     }
+}
+
+void launch_velocity(hipStream_t s, const Mesh &m, const double *pf, const double *ut, const double *vt,
+                     double scale, double *u, double *v) {
+    const Level &L = m.lv[m.k];
+    hipLaunchKernelGGL(k_velocity, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
+                       L.tri.p, L.xy.p, pf, ut, vt, scale, u, v);
+    CGP_HIP(hipGetLastError());
 }
 
 }  // namespace cgp

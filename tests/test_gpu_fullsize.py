@@ -93,6 +93,13 @@ def test_sequence_step_513x257(ctx, cgp):
         scale = max(np.abs(fxr).max(), np.abs(fyr).max())
         np.testing.assert_allclose(fx.cpu().numpy(), fxr, rtol=0, atol=1e-11 * scale)
         np.testing.assert_allclose(fy.cpu().numpy(), fyr, rtol=0, atol=1e-11 * scale)
+        # velocity correction (Eqs. 16-17) with the prolonged field in the role of the pressure
+        un, vn = (torch.empty(nf, dtype=torch.float64, device=DEV) for _ in range(2))
+        ctx.velocity_correct(h, phif, dt(u), dt(v), 0.01, un, vn)
+        ctx.sync()
+        ur, vr = fem.velocity_correction(hier.xy[1], hier.tri[1], pf, u, v, 0.01)
+        np.testing.assert_allclose(un.cpu().numpy(), ur, rtol=0, atol=1e-12 * (scale + np.abs(u).max()))
+        np.testing.assert_allclose(vn.cpu().numpy(), vr, rtol=0, atol=1e-12 * (scale + np.abs(v).max()))
     finally:
         ctx.mesh_free(h)
 

@@ -140,8 +140,13 @@ def test_predict_matches_oracle(ctx, seq, seed):
             y_ref, _ = gnn.forward(th.astype(np.float64), x, seq.mo, emulate=True)
             free = seq.m.dirichlet == 0
             np.testing.assert_array_equal(got[~free], 0.0)
-            y_got = (got[free] - e[free]) / sd
-            assert rel(y_got, y_ref[free]) <= 1e-4
+            # the smoother is affine: guess = S(e) + S0(s_d y) with S0 the sweeps at b = 0, so the
+            # network's part is compared after subtracting the smoothed extrapolation
+            part_ref = gnn.smooth(seq.a, np.zeros_like(b), sd * y_ref * free)
+            part_got = got - gnn.smooth(seq.a, b, e * free)
+            assert rel(part_got, part_ref) <= 1e-4
+            want = gnn.guess(th.astype(np.float64), seq.a, seq.m.dirichlet, b, p1, p2, seq.mo, emulate=True)
+            assert np.linalg.norm(got - want) <= 1e-4 * np.linalg.norm(part_ref) + 1e-13 * np.linalg.norm(want)
     finally:
         ctx.model_free(md)
 
@@ -226,7 +231,7 @@ def test_learned_solve(ctx, cgp, seq, engine, precision):
     try:
         p = gnn.unpack(ctx.model_get_params(md).astype(np.float64))
         p["wd"][:] = 0.0
-        p["cd"][:] = 0.0                      # network output 0: the guess is the extrapolation
+        p["cd"][:] = 0.0                      # network output 0: the guess is the smoothed extrapolation
         ctx.model_set_params(md, gnn.pack(p).astype(np.float32))
         p["cd"][:] = 1e6                      # a far-off guess the solver must reject
         ctx.model_set_params(bad, gnn.pack(p).astype(np.float32))
@@ -242,7 +247,8 @@ def test_learned_solve(ctx, cgp, seq, engine, precision):
             assert st["guess_used"] == want
             x = phi.cpu().numpy()
             assert rel(x, tgt) <= (1e-6 if precision else 1e-7)
-            start = (2 * p1 - p2) * (seq.m.dirichlet == 0) if want == cgp.CGP_GUESS_LEARNED else p1
+            extrap = (2 * p1 - p2) * (seq.m.dirichlet == 0)
+            start = gnn.smooth(seq.a, b, extrap) if want == cgp.CGP_GUESS_LEARNED else p1
             r0 = solve.relative_residual(seq.a, b, start)
             assert st["rel_res_guess"] == pytest.approx(r0, rel=1e-6)
     finally:

@@ -168,6 +168,36 @@ def test_lorentz_force_matches_oracle(ctx, k):
         ctx.mesh_free(h)
 
 
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_velocity_correction_matches_oracle(ctx, cgp, k):
+    m = ci.jittered_rect(21, 11, 79)
+    h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, k)
+    ref = mesh.Hierarchy(m.xy, m.tri, m.dirichlet, k)
+    try:
+        rng = np.random.default_rng(5)
+        nf = ref.n_nodes(k)
+        p, ut, vt = rng.standard_normal(nf), rng.standard_normal(nf), rng.standard_normal(nf)
+        ur, vr = fem.velocity_correction(ref.xy[k], ref.tri[k], p, ut, vt, 0.05)
+        gscale = np.abs(fem.nodal_gradient(ref.xy[k], ref.tri[k], p)).max() * 0.05
+        u, v = (torch.empty(nf, dtype=torch.float64, device=DEV) for _ in range(2))
+        ctx.velocity_correct(h, dt(p), dt(ut), dt(vt), 0.05, u, v)
+        # in place: the outputs overwrite the intermediate velocity
+        ui, vi = dt(ut), dt(vt)
+        ctx.velocity_correct(h, dt(p), ui, vi, 0.05, ui, vi)
+        ctx.sync()
+        for a, r in ((u, ur), (v, vr), (ui, ur), (vi, vr)):
+            np.testing.assert_allclose(a.cpu().numpy(), r, rtol=0, atol=1e-12 * (gscale + 1.0))
+        pf = dt(p)
+        with pytest.raises(cgp.CGPError):
+            ctx.velocity_correct(h, pf, dt(ut), dt(vt), 0.05, pf, v)
+        with pytest.raises(cgp.CGPError):
+            ctx.velocity_correct(h, pf, dt(ut), dt(vt), 0.05, u, u)
+        with pytest.raises(cgp.CGPError):
+            ctx.velocity_correct(h, pf, dt(ut), dt(vt), float("nan"), u, v)
+    finally:
+        ctx.mesh_free(h)
+
+
 def _solve(ctx, cgp, handle, b, x0=None, guess=None, precision=0, tol=1e-10, **kw):
     n = b.shape[0]
     phi = dt(x0) if x0 is not None else torch.zeros(n, dtype=torch.float64, device=DEV)

@@ -340,6 +340,60 @@ def test_lorentz_force_closed_forms():
     np.testing.assert_allclose(f3[1], 3.0 * f1[1], rtol=1e-14)
 
 
+def test_velocity_correction_of_a_linear_pressure():
+    m = _grid(12, 7, 43)
+    rng = np.random.default_rng(5)
+    ut, vt = rng.standard_normal(m.n_nodes), rng.standard_normal(m.n_nodes)
+    p = -0.75 + 2.5 * m.xy[:, 0] + 0.25 * m.xy[:, 1]
+    u, v = fem.velocity_correction(m.xy, m.tri, p, ut, vt, 0.2)
+    np.testing.assert_allclose(u, ut - 0.2 * 2.5, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(v, vt - 0.2 * 0.25, rtol=0, atol=1e-13)
+
+
+def test_gradient_of_a_quadratic_is_exact_on_point_symmetric_patches():
+    # unjittered grid: the six equal triangles around an interior node are point-symmetric
+    # about it, so the averaged gradient of the interpolated quadratic is the exact gradient
+    m = _grid(9, 6, None)
+    x, y = m.xy[:, 0], m.xy[:, 1]
+    p = x * x + 3.0 * x * y - 2.0 * y * y
+    g = fem.nodal_gradient(m.xy, m.tri, p)
+    inner = m.dirichlet == 0
+    np.testing.assert_allclose(g[inner, 0], (2 * x + 3 * y)[inner], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g[inner, 1], (3 * x - 4 * y)[inner], rtol=0, atol=1e-12)
+
+
+def _projection_residual(coarse, rho_dt=4.0):
+    """One CGP pressure projection (steps 5-8) of ut = grad(chi) + curl(psi) on the fine mesh.
+
+    chi and psi vanish on the boundary, so Eq. 15 gives p = (rho/dt) chi and Eqs. 16-17
+    return the divergence-free part curl(psi) = (psi_y, -psi_x)."""
+    h = mesh.Hierarchy(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+    x, y = h.xy[1][:, 0], h.xy[1][:, 1]
+    sx, cx = np.sin(np.pi * x / 2), np.cos(np.pi * x / 2)
+    sy, cy = np.sin(np.pi * y), np.cos(np.pi * y)
+    chi_x, chi_y = np.pi / 2 * cx * sy, np.pi * sx * cy           # chi = sin(pi x/2) sin(pi y)
+    s2x, c2x = np.sin(np.pi * x), np.cos(np.pi * x)
+    psi_x, psi_y = np.pi * c2x * sy * sy, 2 * np.pi * s2x * sy * cy   # psi = sin(pi x) sin(pi y)^2
+    ut, vt = chi_x + psi_y, chi_y - psi_x
+    n = coarse.n_nodes
+    a = fem.system_matrix(coarse.xy, coarse.tri, coarse.dirichlet)
+    b = fem.source(coarse.xy, coarse.tri, coarse.dirichlet, mesh.restrict_inject(ut, n),
+                   mesh.restrict_inject(vt, n), fem.DIV, rho_dt)
+    p_f = mesh.prolong(solve.direct(a, b), h)
+    u, v = fem.velocity_correction(h.xy[1], h.tri[1], p_f, ut, vt, 1.0 / rho_dt)
+    return _rms(np.hypot(u - psi_y, v + psi_x)), _rms(np.hypot(chi_x, chi_y))
+
+
+def test_projection_removes_the_gradient_part():
+    base = _grid(17, 9, 5)
+    h = mesh.Hierarchy(base.xy, base.tri, base.dirichlet, 2)
+    res = [_projection_residual(ci.Mesh(h.xy[l], h.tri[l], h.dirichlet[l])) for l in range(3)]
+    err = [r for r, _ in res]
+    assert err[-1] < 0.05 * res[-1][1], res
+    order = _orders(err)
+    assert np.all(order > 0.9), (err, order)
+
+
 def test_prolonged_field_has_the_parent_gradient_on_every_child():
     m = _grid(10, 6, 41)
     h = mesh.Hierarchy(m.xy, m.tri, m.dirichlet, 2)
