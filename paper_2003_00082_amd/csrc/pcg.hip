@@ -686,6 +686,16 @@ __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, 
 
 // ------------------------------------------------------------------ driver 1: one stage per launch
 
+// Workgroups are dealt to the eight XCDs round-robin (workgroup v to XCD v % 8), each
+// XCD with its own L2.  The staged kernels renumber an instance's workgroups so that
+// every XCD takes a contiguous range of row blocks or tiles: neighbouring blocks share
+// halo rows, which are then read through one L2 rather than fetched by several.  A
+// bijection of [0, G), so every block and partial-sum slot is still covered once.
+__device__ inline int xcd_block(int v, int G) {
+    const int x = v % 8, k = v / 8, q = G / 8, rm = G % 8;
+    return x * q + (x < rm ? x : rm) + k;
+}
+
 template <class T, int H>
 __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ insts,
                                                    const int32_t *__restrict__ block_inst, int n_inst,
@@ -695,8 +705,8 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
     __shared__ Shared sh;
     const int inst = n_inst == 1 ? 0 : block_inst[blockIdx.x];
     const InstDesc D = insts[inst];
-    const int lb = blockIdx.x - D.blk0;
-    const RowRange R = ranges[blockIdx.x];
+    const int lb = xcd_block(blockIdx.x - D.blk0, D.nblk);
+    const RowRange R = ranges[D.blk0 + lb];
     const int rd = par ^ 1;
     const bool fast = D.fast && R.r1 - R.r0 <= BLOCK && R.c1 >= R.c0 && R.c1 - R.c0 + 1 <= H * BLOCK;
     // speculative loads for an iteration, in flight while the state is decoded
@@ -939,7 +949,7 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     __shared__ double s_cheb[2 * TILE_MAX_DEGREE];
     const int inst = n_inst == 1 ? 0 : block_inst[blockIdx.x];
     const InstDesc D = insts[inst];
-    const int lb = blockIdx.x - D.blk0;
+    const int lb = xcd_block(blockIdx.x - D.blk0, D.nblk);
     const TileBlk B = D.tblk[lb];
     const int rd = par ^ 1;
     // per-distance row counts and coefficients, indexed by a run-time degree: LDS
@@ -956,7 +966,7 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
         tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), v);
     } else {
         const SolveParams prm = *prm_dev;
-        const RowRange R = ranges[blockIdx.x];
+        const RowRange R = ranges[D.blk0 + lb];
         stage_work(c, D, R, prm, sh, par, v);
     }
     block_sums(v, sh.red, sh.sums);
