@@ -79,7 +79,8 @@ enum { CGP_GUESS_ZERO = 0, CGP_GUESS_GIVEN = 1, CGP_GUESS_EXTRAP = 2, CGP_GUESS_
  *               fully asynchronous, so it can be captured in a caller's graph
  *               (Jacobi only)
  *   AUTO        PERSISTENT while the context's stream is being captured; otherwise
- *               STAGED for the Chebyshev preconditioner and STAGED_ROWS for Jacobi */
+ *               STAGED for the Chebyshev preconditioner or deflation and
+ *               STAGED_ROWS for plain Jacobi */
 enum { CGP_ENGINE_AUTO = 0, CGP_ENGINE_STAGED = 1, CGP_ENGINE_PERSISTENT = 2, CGP_ENGINE_STAGED_ROWS = 3 };
 /* per-instance solve status (cgp_solve_stats.status) */
 enum { CGP_SOLVE_OK = 0, CGP_SOLVE_NOCONV = 1, CGP_SOLVE_BREAKDOWN = 2, CGP_SOLVE_ABORTED = 3 };
@@ -174,10 +175,19 @@ typedef struct {
     int32_t engine;       /* CGP_ENGINE_*                                                */
     int32_t launches_per_graph; /* CGP_ENGINE_STAGED: stages per replayed graph (0 = 16; even) */
     int32_t precond_degree; /* 0 or 1: Jacobi M = diag(K); 2..8: Chebyshev polynomial of this
-                             degree in D^-1 K over [hi/1000, hi], hi = max_i sum_j |K_ij|/K_ii
-                             (Gershgorin), applied as that many steps of Chebyshev
-                             iteration for K z = r from z = 0 (CGP_ENGINE_STAGED only)  */
-    int32_t reserved_;    /* must be 0                                                   */
+                             degree in D^-1 K over [hi/1000, hi] ([hi/100, hi] with
+                             deflation), hi = max_i sum_j |K_ij|/K_ii (Gershgorin),
+                             applied as that many steps of Chebyshev iteration for
+                             K z = r from z = 0 (CGP_ENGINE_STAGED only)                */
+    int32_t deflation;    /* 0: off.  1: subdomain deflation (an extension): CG runs on the
+                             complement of the coarse space Z of the tiled iteration's
+                             tiles (free-row indicators; recursive coordinate bisection,
+                             <= 512 rows each), x0 is corrected so that Z^T r = 0 and each
+                             direction is made K-orthogonal to range(Z) (Nicolaides;
+                             Saad, Yeung, Erhel, Guyomarc'h).  Needs the tiled iteration
+                             (CGP_ENGINE_STAGED or AUTO), at most 1024 tiles per mesh,
+                             rows coupled to at most 4 tiles: CGP_E_UNSUPPORTED otherwise.
+                             E = Z^T K Z is factorised on the host on first use per mesh. */
 } cgp_solve_opts;
 
 typedef struct {

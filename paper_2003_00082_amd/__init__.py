@@ -54,7 +54,7 @@ class SolveOpts(ctypes.Structure):
                 ("refine_delta", ctypes.c_double), ("max_iter", ctypes.c_int32), ("model", ctypes.c_int32),
                 ("spmv_lanes", ctypes.c_int32), ("blocks", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("launches_per_graph", ctypes.c_int32), ("precond_degree", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32)]
+                ("deflation", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -247,7 +247,7 @@ class Context:
 
     def poisson_solve(self, meshes, b, phi, stats, *, prev1=None, prev2=None, precision=CGP_FP64,
                       guess=CGP_GUESS_GIVEN, tol=1e-8, refine_delta=0.0, max_iter=0, model=-1, spmv_lanes=0,
-                      blocks=0, engine=CGP_ENGINE_AUTO, launches_per_graph=0, precond_degree=0):
+                      blocks=0, engine=CGP_ENGINE_AUTO, launches_per_graph=0, precond_degree=0, deflation=0):
         """Enqueue one (batched) solve.  ``meshes``/``b``/``phi``/``prev*`` are sequences (one per
         instance); ``stats`` is a device uint8 tensor of n_inst * 32 bytes."""
         k = len(meshes)
@@ -257,7 +257,7 @@ class Context:
         arr_p1 = (_vp * k)(*[_ptr(t) for t in prev1]) if prev1 is not None else None
         arr_p2 = (_vp * k)(*[_ptr(t) for t in prev2]) if prev2 is not None else None
         opts = SolveOpts(precision, guess, tol, refine_delta, max_iter, model, spmv_lanes, blocks, engine,
-                         launches_per_graph, precond_degree, 0)
+                         launches_per_graph, precond_degree, deflation)
         _check(load().cgp_poisson_solve(self.handle, k, arr_m, arr_b, arr_x, arr_p1, arr_p2, ctypes.byref(opts),
                                         _ptr(stats)))
 

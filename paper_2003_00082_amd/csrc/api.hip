@@ -29,6 +29,8 @@ struct Plan {
     int32_t *d_done_at = nullptr;    // persistent driver: stage at which each instance finished
     int32_t *d_done = nullptr;       // staged driver: finished-instance counter
     SolveParams *d_prm = nullptr;    // staged driver: parameters of the current call
+    int32_t *d_cblk_inst = nullptr;  // deflation: instance of each coarse-kernel workgroup
+    int cgrid = 0;                   // deflation: coarse-kernel workgroups
     int grid = 0;
     int n_inst = 0;
     int halo = 0;                    // widest column range of a workgroup
@@ -388,7 +390,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         CGP_REQUIRE(o.engine >= CGP_ENGINE_AUTO && o.engine <= CGP_ENGINE_STAGED_ROWS, "unknown engine");
         CGP_REQUIRE(o.precond_degree >= 0 && o.precond_degree <= TILE_MAX_DEGREE,
                     "precond_degree must be in [0, 8]");
-        CGP_REQUIRE(o.reserved_ == 0, "reserved field must be 0");
+        CGP_REQUIRE(o.deflation == 0 || o.deflation == 1, "deflation must be 0 or 1");
         CGP_REQUIRE(o.launches_per_graph >= 0 && o.launches_per_graph % 2 == 0 && o.launches_per_graph <= 4096,
                     "launches_per_graph must be even and <= 4096");
         Model *model = nullptr;
@@ -422,13 +424,20 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         // for the Chebyshev preconditioner; the row-range kernel is the faster Jacobi iteration)
         std::vector<TilePlan *> tp(n_inst, nullptr);
         bool tiled = !persistent && o.engine != CGP_ENGINE_STAGED_ROWS &&
-                     (o.engine == CGP_ENGINE_STAGED || degree >= 2);
+                     (o.engine == CGP_ENGINE_STAGED || degree >= 2 || o.deflation == 1);
         for (int i = 0; i < n_inst && tiled; ++i) {
             tp[i] = tile_plan(ctx->aux, *ms[i], degree);
             tiled = tp[i] != nullptr && tp[i]->width == tp[0]->width;
         }
         if (degree >= 2 && !tiled)
             throw Error{CGP_E_UNSUPPORTED, "a mesh does not fit the tiled iteration the Chebyshev preconditioner needs"};
+        const bool defl = o.deflation == 1;
+        if (defl) {
+            if (!tiled) throw Error{CGP_E_UNSUPPORTED, "deflation needs the tiled iteration (CGP_ENGINE_STAGED)"};
+            for (int i = 0; i < n_inst; ++i)
+                if (!tile_deflation(ctx->aux, *ms[i], *tp[i]))
+                    throw Error{CGP_E_UNSUPPORTED, "a mesh does not fit deflation (tiles or couplings)"};
+        }
         SolveParams prm{};
         prm.tol = o.tol;
         // fewer iterations between refinements with the Chebyshev preconditioner: longer fp32 runs
@@ -465,7 +474,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             // cache key: everything the launch records depend on
             std::ostringstream key;
             key << o.precision << ':' << o.guess << ':' << used << ':' << launches << ':' << persistent << ':'
-                << tiled << ':' << degree << ':';
+                << tiled << ':' << degree << ':' << defl << ':';
             for (int i = 0; i < gn; ++i) {
                 const int ii = g0 + i;
                 key << h_meshes[ii] << ',' << lanes_of(*ms[ii]) << ',' << nb[i] << ',' << (const void *)h_d_b[ii]
@@ -479,8 +488,13 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 plan = it->second.get();
             } else {
                 auto p = std::make_unique<Plan>();
-                size_t npart = 0;
-                for (int v : nb) npart += static_cast<size_t>(2) * NPART * v;
+                size_t npart = 0, nmu = 0, ncb_total = 0;
+                for (int v : nb) {
+                    npart += static_cast<size_t>(2) * NPART * v;
+                    nmu += v;
+                    ncb_total += (v + COARSE_ROWS - 1) / COARSE_ROWS;
+                }
+                if (!defl) nmu = ncb_total = 0;
                 auto align = [](size_t x) { return (x + 255) / 256 * 256; };
                 const size_t off_bi = align(sizeof(InstDesc) * gn);
                 const size_t off_rng = align(off_bi + sizeof(int32_t) * used);
@@ -489,15 +503,21 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 const size_t off_done = align(off_done_at + sizeof(int32_t) * gn);
                 const size_t off_prm = align(off_done + sizeof(int32_t));
                 const size_t off_part = align(off_prm + sizeof(SolveParams));
-                const size_t total = off_part + sizeof(double) * npart;
+                const size_t off_mu = align(off_part + sizeof(double) * npart);
+                const size_t off_cpart = align(off_mu + sizeof(double) * nmu);
+                const size_t off_cbi = align(off_cpart + sizeof(double) * ncb_total);
+                const size_t total = off_cbi + sizeof(int32_t) * ncb_total;
                 p->buf.alloc(total);
                 std::vector<uint8_t> host(off_ctl, 0);
                 InstDesc *hd = reinterpret_cast<InstDesc *>(host.data());
                 int32_t *hbi = reinterpret_cast<int32_t *>(host.data() + off_bi);
                 double *dpart = reinterpret_cast<double *>(p->buf.p + off_part);
                 Ctl *dctl = reinterpret_cast<Ctl *>(p->buf.p + off_ctl);
-                int blk = 0;
+                int blk = 0, cblk = 0;
                 size_t poff = 0;
+                double *dmu = reinterpret_cast<double *>(p->buf.p + off_mu);
+                double *dcpart = reinterpret_cast<double *>(p->buf.p + off_cpart);
+                std::vector<int32_t> hcbi;
                 for (int i = 0; i < gn; ++i) {
                     const int ii = g0 + i;
                     Mesh &m = *ms[ii];
@@ -545,12 +565,30 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                         d.tcol = T.ecol.p;
                         d.tval32 = T.eval32.p;
                         d.tval = T.eval64.p;
+                        if (defl) {
+                            d.defl = 1;
+                            d.ncb = (nb[i] + COARSE_ROWS - 1) / COARSE_ROWS;
+                            d.cblk0 = cblk;
+                            d.kzr = T.kzr.p;
+                            d.kzg = T.kzg.p;
+                            d.kzv32 = T.kzv32.p;
+                            d.kzv = T.kzv64.p;
+                            d.einv = T.einv.p;
+                            d.mu = dmu;
+                            d.cpart = dcpart;
+                            d.dir = m.lv[0].dir.p;
+                            dmu += nb[i];
+                            dcpart += d.ncb;
+                            for (int v = 0; v < d.ncb; ++v) hcbi.push_back(i);
+                            cblk += d.ncb;
+                        }
                         if (degree == 1) {
                             d.cheb[0] = 1.0;   // Jacobi: z = D^-1 r
                         } else {
-                            // Chebyshev iteration over [hi/1000, hi]: the first step scales D^-1 r by
-                            // 1/c, step k updates dz <- a1 dz + a2 D^-1 res
-                            const double hi = mesh_gershgorin(ctx->aux, m), lo = hi / 1000.0;
+                            // Chebyshev iteration over [hi/1000, hi] ([hi/100, hi] with deflation, whose
+                            // coarse space takes over the smooth end of the spectrum): the first step
+                            // scales D^-1 r by 1/c, step k updates dz <- a1 dz + a2 D^-1 res
+                            const double hi = mesh_gershgorin(ctx->aux, m), lo = hi / (defl ? 100.0 : 1000.0);
                             const double c = 0.5 * (hi + lo), e = 0.5 * (hi - lo), sig = c / e;
                             double rho = 1.0 / sig;
                             d.cheb[0] = 1.0 / c;
@@ -568,6 +606,15 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     poff += static_cast<size_t>(2) * NPART * nb[i];
                 }
                 CGP_HIP(hipMemcpyAsync(p->buf.p, host.data(), off_rng, hipMemcpyHostToDevice, ctx->aux));
+                if (defl) {
+                    // mu and the coarse partials start at zero: the first stages read them before
+                    // any coarse step has produced values for them
+                    CGP_HIP(hipMemsetAsync(p->buf.p + off_mu, 0, off_cbi - off_mu, ctx->aux));
+                    CGP_HIP(hipMemcpyAsync(p->buf.p + off_cbi, hcbi.data(), sizeof(int32_t) * hcbi.size(),
+                                           hipMemcpyHostToDevice, ctx->aux));
+                    p->d_cblk_inst = reinterpret_cast<int32_t *>(p->buf.p + off_cbi);
+                    p->cgrid = cblk;
+                }
                 p->d_insts = reinterpret_cast<InstDesc *>(p->buf.p);
                 p->d_block_inst = reinterpret_cast<int32_t *>(p->buf.p + off_bi);
                 p->d_ranges = reinterpret_cast<RowRange *>(p->buf.p + off_rng);
@@ -602,11 +649,12 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 // the launch template is recorded on the private stream (the caller's may be the null stream)
                 CGP_HIP(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeRelaxed));
                 for (int l = 0; l < launches; ++l) {
-                    if (tiled)
+                    if (tiled) {
                         launch_cg_tile(ctx->aux, o.precision == CGP_FP32_IR, tp[g0]->width, gn, plan->d_insts,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
                                        plan->d_done, ctx->host_flag_dev);
-                    else
+                        if (defl) launch_cg_coarse(ctx->aux, plan->d_insts, plan->d_cblk_inst, plan->cgrid, l & 1);
+                    } else
                         launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
                                        plan->d_done, ctx->host_flag_dev);

@@ -103,6 +103,8 @@ struct TileBlk {
     int32_t nreg;                     // region rows (= nt[degree])
     int32_t nspmv;                    // rows with a local matrix row (= nt[max(degree - 1, 0)])
     int32_t nt[TILE_MAX_DEGREE + 2];  // nt[t]: region rows at distance <= t
+    int32_t kz_off;                   // deflation: first coupling record of the tile
+    int32_t nkz;                      // deflation: coupling records (<= TILE_ROWS)
 };
 
 // 16-bit column entries per local matrix row record (a multiple of 8: 16-byte loads)
@@ -114,12 +116,24 @@ constexpr int tile_col_stride(int width) { return width <= 8 ? 8 : 16; }
 struct TilePlan {
     int32_t degree = 0, width = 0, nparts = 0;
     std::vector<TileBlk> hblk;
+    std::vector<int32_t> hreg;
     DBuf<TileBlk> blk;
     DBuf<int32_t> reg;
     DBuf<uint16_t> ecol;
     DBuf<float> eval32;
     DBuf<double> eval64;
+    // subdomain deflation with the tiles as aggregates (built on first use; defl_state
+    // 0 = not built, 1 = built, -1 = not supported for this mesh)
+    int32_t defl_state = 0;
+    DBuf<int32_t> kzr;        // coupling record: region index of the row
+    DBuf<int32_t> kzg;        // [4] per record: aggregates (tiles) the row couples to
+    DBuf<float> kzv32;        // [4] per record: (K Z)_{row, aggregate}
+    DBuf<double> kzv64;
+    DBuf<double> einv;        // [nparts x nparts] (Z^T K Z)^-1, row-major
 };
+
+constexpr int KZ_PER_ROW = 4;            // aggregates one row may couple to
+constexpr int MAX_DEFL_AGGREGATES = 1024;
 
 struct Mesh {
     int32_t k = 0;
@@ -147,6 +161,10 @@ struct Mesh {
 // mesh does not fit the tiled iteration (rows wider than 12, regions too large)
 TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree);
 double mesh_gershgorin(hipStream_t s, Mesh &m);
+// builds (or reports) the deflation data of a tile plan; false when the mesh does not fit
+// it (too many aggregates, a row coupled to more than KZ_PER_ROW aggregates, more
+// coupled rows in a region than a workgroup has threads)
+bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P);
 
 // ------------------------------------------------------------------ solver launch records
 
@@ -161,7 +179,11 @@ struct RowRange {
     int32_t r0, r1, c0, c1;
 };
 
-constexpr int NPART = 4;
+// per-workgroup partial sums of a stage: gamma, delta, sigma, r.r and (deflation) the
+// aggregate sum of w or r over the workgroup's free rows; the first NRED are reduced over
+// the instance by the next stage, which puts the coarse term c in place of the fifth
+constexpr int NPART = 5;
+constexpr int NRED = 4;
 
 // device-side description of one instance of a (batched) solve
 struct InstDesc {
@@ -203,6 +225,19 @@ struct InstDesc {
     double *u;                           // M^-1 r (own rows)
     float *u32;
     double cheb[2 * TILE_MAX_DEGREE];    // [0]: scale of the first step; [2k-1], [2k]: step k coefficients
+    // subdomain deflation (tiled iteration only; aggregates = the instance's tiles)
+    int32_t defl;                        // 0 off, 1 on
+    int32_t ncb;                         // workgroups of the coarse kernel for this instance
+    int32_t cblk0;                       // first of them
+    int32_t pad4_;
+    const int32_t *kzr;
+    const int32_t *kzg;
+    const float *kzv32;
+    const double *kzv;
+    const double *einv;                  // [nblk x nblk]
+    double *mu;                          // [nblk] E^-1 Z^T v of the last stage
+    double *cpart;                       // [ncb] partial sums of mu . Z^T v
+    const uint8_t *dir;                  // Dirichlet flags of the rows
 };
 
 struct SolveParams {
@@ -236,6 +271,9 @@ void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstD
 void launch_cg_tile(hipStream_t s, bool mixed, int width, int n_inst, const InstDesc *d_insts,
                     const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
                     int32_t *d_done, int32_t *d_host_flag);
+// the coarse step of deflation after a tiled stage launch: mu = E^-1 (aggregate sums), c partials
+constexpr int COARSE_ROWS = 4;   // aggregates per coarse workgroup (one wavefront each)
+void launch_cg_coarse(hipStream_t s, const InstDesc *d_insts, const int32_t *d_cblk_inst, int grid, int par);
 int pcg_ell_max_width();
 void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
                           const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,

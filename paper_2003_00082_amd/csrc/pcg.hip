@@ -101,7 +101,7 @@ __device__ inline void block_sums(double (&v)[NPART], double (*red)[NPART], doub
 
 // sum of an instance's per-workgroup partials (same order in every workgroup)
 __device__ inline void reduce_partials(const double *part, int nblk, double (*red)[NPART], double *out) {
-    double t[NPART] = {0.0, 0.0, 0.0, 0.0};
+    double t[NPART] = {};
     for (int j = threadIdx.x; j < nblk; j += BLOCK) {
 #pragma unroll
         for (int s = 0; s < NPART; ++s) t[s] += part[s * nblk + j];
@@ -188,12 +188,13 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
     case ST_START: {
         const double g = S[0], dl = S[1], sg = S[2];
         double denom;
+        // with deflation S[NRED] = mu . Z^T K u: p = u + beta p - Z mu stays K-orthogonal to range(Z)
         if (c.restart) {
             c.beta = 0.0;
-            denom = dl;
+            denom = dl - S[NRED];
         } else {
             c.beta = g / c.gamma;
-            denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap;
+            denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap - S[NRED];
         }
         if (!(denom > 0.0) || !isfinite(denom) || !isfinite(g)) {
             c.status = CGP_SOLVE_BREAKDOWN;
@@ -225,7 +226,7 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
             break;
         }
         c.beta = g / c.gamma;
-        const double denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap;
+        const double denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap - S[NRED];
         if (!(denom > 0.0) || !isfinite(denom)) {
             c.status = CGP_SOLVE_BREAKDOWN;
             c.state = ST_DONE;
@@ -605,29 +606,38 @@ __device__ inline void write_stats(const Ctl &c, const SolveParams &prm, int idx
     prm.stats[idx] = o;
 }
 
-// sums of an instance's per-workgroup partials by one wavefront (fixed order);
-// loads are issued four rows of 64 at a time so they are in flight together
+// sums of the first NRED of an instance's per-workgroup partials by one wavefront
+// (fixed order); loads are issued four rows of 64 at a time so they are in flight together
 __device__ inline void wave_reduce_partials(const double *part, int nblk, double (&S)[NPART]) {
     const int lane = threadIdx.x & 63;
     const CGP_GLOBAL double *pg = gld(part);
 #pragma unroll
     for (int s = 0; s < NPART; ++s) S[s] = 0.0;
     for (int base = 0; base < nblk; base += 256) {
-        double t[4][NPART];
+        double t[4][NRED];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int j = base + lane + 64 * u;
 #pragma unroll
-            for (int s = 0; s < NPART; ++s) t[u][s] = j < nblk ? pg[s * nblk + j] : 0.0;
+            for (int s = 0; s < NRED; ++s) t[u][s] = j < nblk ? pg[s * nblk + j] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
 #pragma unroll
-            for (int s = 0; s < NPART; ++s) S[s] += t[u][s];
+            for (int s = 0; s < NRED; ++s) S[s] += t[u][s];
         }
     }
 #pragma unroll
-    for (int s = 0; s < NPART; ++s) S[s] = wave_sum(S[s]);
+    for (int s = 0; s < NRED; ++s) S[s] = wave_sum(S[s]);
+}
+
+// the coarse term c = mu . Z^T v of deflation: the sum of the coarse kernel's partials
+__device__ inline double wave_coarse_term(const double *cpart, int ncb) {
+    const int lane = threadIdx.x & 63;
+    const CGP_GLOBAL double *pg = gld(cpart);
+    double t = 0.0;
+    for (int j = lane; j < ncb; j += 64) t += pg[j];
+    return wave_sum(t);
 }
 
 // The common transition, an iteration followed by another one, kept short and
@@ -645,7 +655,7 @@ __device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolvePa
             ++c.it;
             c.pap = c.gamma / c.alpha;
             c.beta = g / c.gamma;
-            const double denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap;
+            const double denom = dl + 2.0 * c.beta * sg + c.beta * c.beta * c.pap - S[NRED];
             if (denom > 0.0 && isfinite(denom)) {
                 c.alpha = g / denom;
                 c.gamma = g;
@@ -666,6 +676,7 @@ __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, 
         const Ctl prev = D.ctl[rd];
         double S[NPART];   // loaded whatever the state, so the loads overlap the control read
         wave_reduce_partials(D.partials + static_cast<size_t>(rd) * NPART * D.nblk, D.nblk, S);
+        if (D.defl) S[NRED] = wave_coarse_term(D.cpart, D.ncb);
         const SolveParams prm = *prm_dev;
         Ctl c = prev;
         if (prev.state != ST_DONE && threadIdx.x == 0) c = next_state(prev, S, prm, D.guess);
@@ -715,7 +726,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
     decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
     const Ctl c = sh.ctl;
     if (c.state == ST_DONE) return;
-    double v[NPART] = {0.0, 0.0, 0.0, 0.0};
+    double v[NPART] = {};
     if (fast && c.state == ST_ITER) {
         iter_fast<T, H>(f, c, D, R, par, reinterpret_cast<T *>(sh.lds), v);
     } else {
@@ -739,7 +750,8 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
 constexpr int TH = TILE_REGION / BLOCK;   // region rows per thread
 constexpr int TS = TILE_SPMV / BLOCK;     // local matrix rows per thread
 static_assert(BLOCK == TILE_ROWS, "one own row per thread");
-static_assert(3 * TILE_REGION * sizeof(double) <= LDS_DOUBLES * sizeof(double), "three region vectors in LDS");
+static_assert(4 * TILE_REGION * sizeof(double) <= LDS_DOUBLES * sizeof(double),
+              "three region vectors and the deflation term in LDS");
 
 template <class T, int W>
 struct TilePrefetch {
@@ -833,6 +845,51 @@ __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, c
     }
 }
 
+// Deflation (aggregates = the tiles, Z their free-row indicators): the coarse
+// coefficients mu = E^-1 Z^T v written by the coarse kernel after the previous stage,
+// the thread's coupling record (a region row and its (K Z) entries) with the mu of the
+// aggregates it names, and the own row's aggregate coefficient and Dirichlet flag.
+template <class T>
+struct DeflPrefetch {
+    int32_t kr;                // region index of the record, -1 for none
+    T kv[KZ_PER_ROW];          // (K Z)_{row, a}
+    T km[KZ_PER_ROW];          // mu_a (rounded to the iteration's precision)
+    T mown;                    // mu of the tile's own aggregate
+    bool ofree;                // the own row is not a Dirichlet row
+};
+
+template <class T>
+__device__ inline const T *kz_val(const InstDesc &D);
+template <>
+__device__ inline const double *kz_val<double>(const InstDesc &D) { return D.kzv; }
+template <>
+__device__ inline const float *kz_val<float>(const InstDesc &D) { return D.kzv32; }
+
+template <class T>
+__device__ inline void defl_prefetch(DeflPrefetch<T> &f, const InstDesc &D, const TileBlk &B, int lb, int32_t own) {
+    const CGP_GLOBAL double *mu = gld(D.mu);
+    f.kr = -1;
+    f.mown = static_cast<T>(mu[lb]);
+    f.ofree = own >= 0 ? gld(D.dir)[own] == 0 : false;
+#pragma unroll
+    for (int e = 0; e < KZ_PER_ROW; ++e) {
+        f.kv[e] = T(0);
+        f.km[e] = T(0);
+    }
+    if (static_cast<int>(threadIdx.x) < B.nkz) {
+        const size_t q = static_cast<size_t>(B.kz_off) + threadIdx.x;
+        f.kr = gld(D.kzr)[q];
+        const u32x4 g = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(D.kzg))[q];
+        const CGP_GLOBAL T *kv = gld(kz_val<T>(D)) + q * KZ_PER_ROW;
+#pragma unroll
+        for (int e = 0; e < KZ_PER_ROW; ++e) f.kv[e] = kv[e];
+        f.km[0] = static_cast<T>(mu[g.x]);
+        f.km[1] = static_cast<T>(mu[g.y]);
+        f.km[2] = static_cast<T>(mu[g.z]);
+        f.km[3] = static_cast<T>(mu[g.w]);
+    }
+}
+
 // y_t = sum_k ev[h][k] * x[ec[h][k]] for the thread's local matrix row h
 template <class T, int W>
 __device__ inline T tile_row(const TilePrefetch<T, W> &f, int h, const T *x) {
@@ -848,9 +905,14 @@ __device__ inline T tile_row(const TilePrefetch<T, W> &f, int h, const T *x) {
 // neighbours from LDS) and its dz and z updates; r', the residual and z of a row
 // stay in the thread's registers (no other row reads them), dz alternates
 // between two LDS buffers, and the last step leaves the final z there for w = K z.
+// With deflation, kzm holds (K Z mu) over the region and mown, ofree describe the own
+// row: ITER takes p = u + beta p - Z mu, s = w + beta s - K Z mu (mu = E^-1 Z^T w of the
+// previous stage); START applies the coarse correction x += Z mu, r -= K Z mu (mu =
+// E^-1 Z^T r of the residual stage before it).  Both emit Z^T w' as the fifth partial.
 template <class T, int W>
 __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, const InstDesc &D, const TileBlk &B,
-                                 const int32_t *nt, const double *cheb, int wr, T *lds, double (&v)[NPART]) {
+                                 const int32_t *nt, const double *cheb, int wr, T *lds, const T *kzm, bool defl,
+                                 T mown, bool ofree, double (&v)[NPART]) {
     const int64_t n = D.n;
     const bool start = c.state == ST_START;
     const bool rs = c.restart;
@@ -865,8 +927,9 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
     for (int h = 0; h < TH; ++h) {
         const int t = threadIdx.x + h * BLOCK;
         if (t < B.nreg) {
-            const T sj = start ? f.s[h] : (rs ? f.w[h] : f.w[h] + be * f.s[h]);
-            const T rj = start ? f.r[h] : f.r[h] - al * sj;
+            const T kz = defl ? kzm[t] : T(0);
+            const T sj = start ? f.s[h] : (rs ? f.w[h] : f.w[h] + be * f.s[h]) - kz;
+            const T rj = start ? f.r[h] - kz : f.r[h] - al * sj;
             if (h == 0) {
                 s_own = sj;
                 r_own = rj;
@@ -920,20 +983,54 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
             gst(D.u32)[j] = u1;
         else
             gst(D.u)[j] = u1;
+        const T zm = (defl && ofree) ? mown : T(0);   // (Z mu) at the own row
         if (!start) {
-            const T pj = rs ? f.ou : f.ou + be * f.op;
+            const T pj = (rs ? f.ou : f.ou + be * f.op) - zm;
             gst(const_cast<T *>(vec_of<T>(D, 4)))[j] = pj;
             if constexpr (sizeof(T) == 4)
                 gst(D.c32)[j] = f.ox + al * pj;
             else
                 gst(D.x)[j] = f.ox + al * pj;
+        } else if (defl) {
+            // the correction is exact in fp64; in mixed precision it starts the fp32 correction
+            if constexpr (sizeof(T) == 4)
+                gst(D.c32)[j] = f.ox + zm;
+            else
+                gst(D.x)[j] = f.ox + zm;
         }
         const double r64 = static_cast<double>(r_own), u64 = static_cast<double>(u1);
         v[0] += r64 * u64;
         v[1] += static_cast<double>(wn) * u64;
         v[2] += u64 * static_cast<double>(s_own);
         v[3] += r64 * r64;
+        if (defl && ofree) v[4] += static_cast<double>(wn);
     }
+}
+
+// The residual stage of a deflated solve, over the tile's own rows (so that the fifth
+// partial is the tile's aggregate sum Z^T r): r = b - K x in fp64 from the CSR matrix.
+__device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &B, int32_t own, bool ofree,
+                                bool mixed, int par, double (&v)[NPART]) {
+    if (static_cast<int>(threadIdx.x) >= B.nt[0]) return;
+    const int64_t n = D.n;
+    const int wr = par, rd = par ^ 1;
+    const CGP_GLOBAL int32_t *rowptr = gld(D.rowptr), *col = gld(D.col);
+    const CGP_GLOBAL double *val = gld(D.val), *x = gld(D.x);
+    double kx = 0.0;
+    for (int32_t k = rowptr[own]; k < rowptr[own + 1]; ++k) kx += val[k] * x[col[k]];
+    const double bi = gld(D.b)[own], ri = bi - kx;
+    if (mixed) {
+        gst(D.r32)[wr * n + own] = static_cast<float>(ri);
+        if (c.first)
+            gst(D.c32)[own] = 0.0f;
+        else
+            gst(D.s32)[wr * n + own] = gld(D.s32)[rd * n + own];   // START keeps the direction: it needs s
+    } else {
+        gst(D.r)[wr * n + own] = ri;
+    }
+    v[0] += ri * ri;
+    if (c.first) v[1] += bi * bi;
+    if (ofree) v[4] += ri;
 }
 
 // fp32: at most 128 VGPRs, so that two workgroups share a compute unit and a grid of
@@ -958,12 +1055,39 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     // speculative loads for an iteration, in flight while the state is decoded
     TilePrefetch<T, W> f;
     tile_prefetch<T, W>(f, D, B, rd);
+    const bool defl = D.defl != 0;
+    DeflPrefetch<T> df;
+    T *kzm = reinterpret_cast<T *>(sh.lds) + 3 * TILE_REGION;
+    df.kr = -1;
+    df.mown = T(0);
+    df.ofree = false;
+    if (defl) {
+        defl_prefetch<T>(df, D, B, lb, static_cast<int>(threadIdx.x) < B.nt[0] ? f.g[0] : -1);
+#pragma unroll
+        for (int h = 0; h < TH; ++h) {
+            const int t = threadIdx.x + h * BLOCK;
+            if (t < B.nreg) kzm[t] = T(0);
+        }
+    }
     decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
     const Ctl c = sh.ctl;
     if (c.state == ST_DONE) return;
-    double v[NPART] = {0.0, 0.0, 0.0, 0.0};
+    double v[NPART] = {};
     if (c.state == ST_ITER || c.state == ST_START) {
-        tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), v);
+        if (defl) {
+            // K Z mu over the region: one coupling record per thread, zero elsewhere
+            if (df.kr >= 0) {
+                T a = T(0);
+#pragma unroll
+                for (int e = 0; e < KZ_PER_ROW; ++e) a += df.kv[e] * df.km[e];
+                kzm[df.kr] = a;
+            }
+            __syncthreads();
+        }
+        tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), kzm, defl, df.mown,
+                        df.ofree, v);
+    } else if (c.state == ST_RES && defl) {
+        tile_res(c, D, B, static_cast<int>(threadIdx.x) < B.nt[0] ? f.g[0] : -1, df.ofree, sizeof(T) == 4, par, v);
     } else {
         const SolveParams prm = *prm_dev;
         const RowRange R = ranges[D.blk0 + lb];
@@ -972,6 +1096,36 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     block_sums(v, sh.red, sh.sums);
     if (threadIdx.x < NPART) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
         sh.sums[threadIdx.x];
+}
+
+// Coarse step of deflation after a tiled stage: mu = E^-1 q with q the stage's aggregate
+// sums (the fifth partial of its workgroups), one wavefront per aggregate, and per
+// workgroup the partial sum of mu_a q_a (fixed order); the next stage reads both.
+__global__ __launch_bounds__(64 * COARSE_ROWS) void k_cg_coarse(const InstDesc *__restrict__ insts,
+                                                               const int32_t *__restrict__ cblk_inst, int par) {
+    __shared__ double red[COARSE_ROWS];
+    const InstDesc &D = insts[cblk_inst[blockIdx.x]];
+    const int cb = blockIdx.x - D.cblk0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = D.nblk;
+    const int a = cb * COARSE_ROWS + wave;
+    const CGP_GLOBAL double *q = gld(D.partials) + static_cast<size_t>(par) * NPART * m + static_cast<size_t>(NRED) * m;
+    double acc = 0.0;
+    if (a < m) {
+        const CGP_GLOBAL double *e = gld(D.einv) + static_cast<size_t>(a) * m;
+        for (int b = lane; b < m; b += 64) acc += e[b] * q[b];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        red[wave] = a < m ? acc * q[a] : 0.0;
+        if (a < m) gst(D.mu)[a] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < COARSE_ROWS; ++w) t += red[w];
+        gst(D.cpart)[cb] = t;
+    }
 }
 
 __global__ void k_cg_boot(InstDesc *insts, int n_inst, const SolveParams prm, SolveParams *prm_dev,
@@ -1049,7 +1203,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_persistent(const InstDesc *__restr
         const int par = stage & 1;
         double *part = D.partials + static_cast<size_t>(par) * NPART * D.nblk;
         const Ctl c = sh.ctl;
-        double v[NPART] = {0.0, 0.0, 0.0, 0.0};
+        double v[NPART] = {};
         if (c.state != ST_DONE) stage_work(c, D, R, prm, sh, par, v);
         block_sums(v, sh.red, sh.sums);
         if (threadIdx.x < NPART) part[threadIdx.x * D.nblk + lb] = sh.sums[threadIdx.x];
@@ -1164,6 +1318,11 @@ void launch_cg_tile(hipStream_t s, bool mixed, int width, int n_inst, const Inst
         if (width <= 8) CGP_TILE(double, 8); else CGP_TILE(double, 12);
     }
 #undef CGP_TILE
+    CGP_HIP(hipGetLastError());
+}
+
+void launch_cg_coarse(hipStream_t s, const InstDesc *d_insts, const int32_t *d_cblk_inst, int grid, int par) {
+    hipLaunchKernelGGL(k_cg_coarse, dim3(grid), dim3(64 * COARSE_ROWS), 0, s, d_insts, d_cblk_inst, par);
     CGP_HIP(hipGetLastError());
 }
 

@@ -107,6 +107,8 @@ bool build_tiles(int64_t n, int parts, int degree, int width, const std::vector<
             f0 = f1;
         }
         for (int t = degree + 1; t < TILE_MAX_DEGREE + 2; ++t) B.nt[t] = B.nt[degree];
+        B.kz_off = 0;
+        B.nkz = 0;
         B.nreg = B.nt[degree];
         B.nspmv = B.nt[std::max(degree - 1, 0)];
         if (B.nreg > TILE_REGION || B.nspmv > TILE_SPMV) return false;
@@ -202,6 +204,7 @@ TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
             plan->width = width;
             plan->nparts = parts;
             plan->hblk = blk;
+            plan->hreg = reg;
             h2d(s, plan->blk, blk);
             h2d(s, plan->reg, reg);
             h2d(s, plan->ecol, ecol);
@@ -214,6 +217,135 @@ TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
     }
     m.tiles[degree] = std::move(plan);
     return out;
+}
+
+// Deflation data of the tiled iteration, with the tiles as aggregates (Z: free-row
+// indicators of the tiles).  For every region row that couples to an aggregate through
+// K, a record (region index, up to KZ_PER_ROW aggregates, (K Z)_{row, a}); a row whose
+// couplings cancel (an interior row: zero row sum) gets none.  E = Z^T K Z is inverted
+// on the host (Cholesky), an aggregate without free rows getting E_aa = 1.
+bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
+    if (P.defl_state != 0) return P.defl_state > 0;
+    P.defl_state = -1;
+    const int na = P.nparts;
+    if (na > MAX_DEFL_AGGREGATES) return false;
+    const int64_t n = m.lv[0].n;
+    const auto rowptr = d2h(s, m.rowptr.p, n + 1);
+    const auto col = d2h(s, m.col.p, m.nnz);
+    const auto val = d2h(s, m.val.p, m.nnz);
+    const auto dir = d2h(s, m.lv[0].dir.p, n);
+    std::vector<int32_t> agg(n, -1);
+    for (int t = 0; t < na; ++t) {
+        const TileBlk &B = P.hblk[t];
+        for (int32_t q = 0; q < B.nt[0]; ++q) {
+            const int32_t j = P.hreg[static_cast<size_t>(B.reg_off) + q];
+            if (!dir[j]) agg[j] = t;
+        }
+    }
+    // coupling records
+    std::vector<TileBlk> blk = P.hblk;
+    std::vector<int32_t> kzr, kzg;
+    std::vector<double> kzv;
+    for (int t = 0; t < na; ++t) {
+        const TileBlk &B = P.hblk[t];
+        blk[t].kz_off = static_cast<int32_t>(kzr.size());
+        for (int32_t q = 0; q < B.nreg; ++q) {
+            const int32_t j = P.hreg[static_cast<size_t>(B.reg_off) + q];
+            int32_t ids[16];
+            double sums[16];
+            int cnt = 0;
+            double scale = 0.0;
+            for (int32_t k = rowptr[j]; k < rowptr[j + 1]; ++k) {
+                scale += std::fabs(val[k]);
+                const int32_t a = agg[col[k]];
+                if (a < 0) continue;
+                int e = 0;
+                while (e < cnt && ids[e] != a) ++e;
+                if (e == cnt) {
+                    if (cnt == 16) return false;
+                    ids[cnt] = a;
+                    sums[cnt] = 0.0;
+                    ++cnt;
+                }
+                sums[e] += val[k];
+            }
+            // drop couplings that cancel to rounding (row sums of interior rows)
+            int keep = 0;
+            for (int e = 0; e < cnt; ++e)
+                if (std::fabs(sums[e]) > 1e-13 * scale) {
+                    ids[keep] = ids[e];
+                    sums[keep] = sums[e];
+                    ++keep;
+                }
+            if (keep == 0) continue;
+            if (keep > KZ_PER_ROW) return false;
+            kzr.push_back(q);
+            for (int e = 0; e < KZ_PER_ROW; ++e) {
+                kzg.push_back(e < keep ? ids[e] : t);
+                kzv.push_back(e < keep ? sums[e] : 0.0);
+            }
+        }
+        blk[t].nkz = static_cast<int32_t>(kzr.size()) - blk[t].kz_off;
+        if (blk[t].nkz > TILE_ROWS) return false;   // one record per thread
+    }
+    // E = Z^T K Z and its inverse
+    std::vector<double> E(static_cast<size_t>(na) * na, 0.0);
+    std::vector<int32_t> nfree(na, 0);
+    for (int64_t j = 0; j < n; ++j) {
+        const int32_t a = agg[j];
+        if (a < 0) continue;
+        ++nfree[a];
+        for (int32_t k = rowptr[j]; k < rowptr[j + 1]; ++k) {
+            const int32_t b = agg[col[k]];
+            if (b >= 0) E[static_cast<size_t>(a) * na + b] += val[k];
+        }
+    }
+    for (int a = 0; a < na; ++a)
+        if (nfree[a] == 0) E[static_cast<size_t>(a) * na + a] = 1.0;
+    // Cholesky E = L L^T (lower triangle in place), then E^-1 = L^-T L^-1
+    std::vector<double> L = E;
+    for (int j = 0; j < na; ++j) {
+        double d = L[static_cast<size_t>(j) * na + j];
+        for (int k = 0; k < j; ++k) d -= L[static_cast<size_t>(j) * na + k] * L[static_cast<size_t>(j) * na + k];
+        if (!(d > 0.0)) return false;
+        d = std::sqrt(d);
+        L[static_cast<size_t>(j) * na + j] = d;
+        for (int i = j + 1; i < na; ++i) {
+            double v = L[static_cast<size_t>(i) * na + j];
+            for (int k = 0; k < j; ++k) v -= L[static_cast<size_t>(i) * na + k] * L[static_cast<size_t>(j) * na + k];
+            L[static_cast<size_t>(i) * na + j] = v / d;
+        }
+    }
+    // Li = L^-1 (lower triangular), by columns
+    std::vector<double> Li(static_cast<size_t>(na) * na, 0.0);
+    for (int c = 0; c < na; ++c) {
+        Li[static_cast<size_t>(c) * na + c] = 1.0 / L[static_cast<size_t>(c) * na + c];
+        for (int i = c + 1; i < na; ++i) {
+            double v = 0.0;
+            for (int k = c; k < i; ++k) v -= L[static_cast<size_t>(i) * na + k] * Li[static_cast<size_t>(k) * na + c];
+            Li[static_cast<size_t>(i) * na + c] = v / L[static_cast<size_t>(i) * na + i];
+        }
+    }
+    std::vector<double> Ei(static_cast<size_t>(na) * na, 0.0);
+    for (int a = 0; a < na; ++a)
+        for (int b = 0; b <= a; ++b) {
+            double v = 0.0;
+            for (int k = a; k < na; ++k) v += Li[static_cast<size_t>(k) * na + a] * Li[static_cast<size_t>(k) * na + b];
+            Ei[static_cast<size_t>(a) * na + b] = v;
+            Ei[static_cast<size_t>(b) * na + a] = v;
+        }
+    // in place: cached launch records of earlier solves point at this buffer
+    P.hblk = blk;
+    CGP_HIP(hipMemcpyAsync(P.blk.p, blk.data(), blk.size() * sizeof(TileBlk), hipMemcpyHostToDevice, s));
+    h2d(s, P.kzr, kzr);
+    h2d(s, P.kzg, kzg);
+    h2d(s, P.kzv64, kzv);
+    std::vector<float> kzv32(kzv.begin(), kzv.end());
+    h2d(s, P.kzv32, kzv32);
+    h2d(s, P.einv, Ei);
+    CGP_HIP(hipStreamSynchronize(s));
+    P.defl_state = 1;
+    return true;
 }
 
 }  // namespace cgp
