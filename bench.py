@@ -11,16 +11,19 @@ step.  One *step* is one pass of the whole hot path:
     -> solve p -> prolong p -> velocity correction (Eqs. 16-17)
 
 with both Poisson solves to a true relative residual of 1e-8.  Forms on the
-same inputs (d = --degree, the Chebyshev polynomial preconditioner's degree):
+same inputs (d = --degree, the Chebyshev polynomial preconditioner's degree;
+"deflated" = subdomain deflation with the solver's tiles as aggregates, on
+unless --deflation 0):
 
     A  plain fp64 Jacobi-PCG from the previous solution (the baseline)
-    B  fp32 PCG with fp64 residual refinement, Chebyshev degree d, from the
-       learned guess (one network per equation, trained on the GPU beforehand on
-       the solutions of the steps that precede the warm-up; each guess is judged
-       against the previous solution by the solver)
+    B  fp32 PCG with fp64 residual refinement, Chebyshev degree d, deflated, from
+       the learned guess (one network per equation, trained on the GPU beforehand
+       on the solutions of the steps that precede the warm-up; each guess is
+       judged against the previous solution by the solver)
     C  as B from the extrapolation 2 phi^{n-1} - phi^{n-2} instead of the network
-    D  fp64 PCG, Chebyshev degree d, from the previous solution
+    D  fp64 PCG, Chebyshev degree d, deflated, from the previous solution
     E  fp32 Jacobi-PCG with fp64 refinement from the extrapolation
+    F  as B without deflation
 
 ``value`` is form B's whole-job Poisson solves per second (2 solves per step)
 over the timed steps, inputs resident in HBM.  Training is a one-off set-up
@@ -67,7 +70,8 @@ def parse():
     ap.add_argument("--stuart", type=float, default=1.0, help="Stuart number N (sigma of the Lorentz force)")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample: steps (2 solves each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="ABCDE")
+    ap.add_argument("--forms", default="ABCDEF")
+    ap.add_argument("--deflation", type=int, default=1, choices=[0, 1], help="deflation in forms B, C, D")
     ap.add_argument("--degree", type=int, default=8, help="Chebyshev preconditioner degree of forms B, C, D")
     ap.add_argument("--refine-delta", type=float, default=1e-3,
                     help="fp32 Chebyshev forms: refine when the fp32 residual fell by this factor since the last "
@@ -84,7 +88,7 @@ def parse():
 
 
 def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extrap: bool,
-              degree: int = 0) -> float:
+              degree: int = 0, aggregates: int = 0) -> float:
     """Algorithmic HBM bytes of one solve: every matrix entry (value + int32 column) each
     product with K reads and every vector element each stage reads or writes, counted
     once per stage (halo re-reads, region copies and padding are not counted).
@@ -96,14 +100,17 @@ def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extra
     Chebyshev degree d >= 1 (tiled kernel): an iteration or restart performs d products
     with K, d (8 nnz + 8 n) in fp32, plus the recurrences of the own rows (reads r, w, s,
     u, p, c, D^-1, writes r, w, s, u, p, c: 52 n); fp64 doubles the vector and value
-    bytes (12 nnz + 16 n per product, 104 n).  The initial guess adds 24 n (extrapolation)."""
+    bytes (12 nnz + 16 n per product, 104 n).  The initial guess adds 24 n (extrapolation).
+    Deflation with m aggregates adds the coarse step of every stage, 8 m^2 (E^-1) + 16 m
+    (aggregate sums in, coefficients out); its per-row coupling records (a few percent) are
+    not counted."""
     if degree >= 1:
         if mixed:
-            it = degree * (8 * nnz + 8 * n) + 52 * n
+            it = degree * (8 * nnz + 8 * n) + 52 * n + 8 * aggregates * aggregates + 16 * aggregates
             res = 12 * nnz + 32 * n
             total = res + it + iters * it + refinements * (32 * n + res + it)
         else:
-            it = degree * (12 * nnz + 16 * n) + 104 * n
+            it = degree * (12 * nnz + 16 * n) + 104 * n + 8 * aggregates * aggregates + 16 * aggregates
             res = 12 * nnz + 28 * n
             total = res + it + iters * it + refinements * (res + it)
     elif mixed:
@@ -184,7 +191,8 @@ def batch_main(args):
         def solve(eq, bvecs, n):
             cur, p1, p2 = (bufs[eq][(n - k) % 3] for k in range(3))
             kw = dict(prev1=p1, prev2=p2, guess=cgp.CGP_GUESS_EXTRAP, precision=cgp.CGP_FP32_IR, tol=TOL,
-                      precond_degree=fdeg, refine_delta=args.refine_delta if fdeg >= 2 else 0.0)
+                      precond_degree=fdeg, refine_delta=args.refine_delta if fdeg >= 2 else 0.0,
+                      deflation=args.deflation if engine == "staged_chebyshev" else 0)
             if engine == "staged_chebyshev":
                 ctx.poisson_solve(H, bvecs, cur, st[eq], engine=cgp.CGP_ENGINE_STAGED, **kw)
             elif engine == "staged_jacobi":
@@ -353,16 +361,19 @@ def main():
         del sols, rhs_t
 
     deg = args.degree
-    forms = {   # precision, guess, preconditioner degree (0 = Jacobi, row-range kernel)
-        "A": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, 0),
-        "B": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, deg),
-        "C": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, deg),
-        "D": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, deg),
-        "E": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, 0),
+    dfl = args.deflation
+    forms = {   # precision, guess, preconditioner degree (0 = Jacobi, row-range kernel), deflation
+        "A": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, 0, 0),
+        "B": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, deg, dfl),
+        "C": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, deg, dfl),
+        "D": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, deg, dfl),
+        "E": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, 0, 0),
+        "F": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, deg, 0),
     }
+    tiles = -(-nc // 512)   # aggregates of the deflated forms (the first tile count fits this mesh)
 
     def run(form: str):
-        prec, guess, fdeg = forms[form]
+        prec, guess, fdeg, fdefl = forms[form]
         mixed = prec == cgp.CGP_FP32_IR
         rotating = guess in (cgp.CGP_GUESS_EXTRAP, cgp.CGP_GUESS_LEARNED)
         bufs = {"phi": [torch.zeros(nc, **f64) for _ in range(3)], "p": [torch.zeros(nc, **f64) for _ in range(3)]}
@@ -371,7 +382,7 @@ def main():
 
         def solve(eq, bvec, n, slot, timed):
             B = bufs[eq]
-            kw = dict(precision=prec, guess=guess, precond_degree=fdeg,
+            kw = dict(precision=prec, guess=guess, precond_degree=fdeg, deflation=fdefl,
                       refine_delta=args.refine_delta if fdeg >= 2 else 0.0)
             if rotating:
                 cur, p1, p2 = B[n % 3], B[(n - 1) % 3], B[(n - 2) % 3]
@@ -433,8 +444,8 @@ def main():
         ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
         solve_ms = np.array([a.elapsed_time(b) for a, b in ev])
         pcg_ms = solve_ms.sum() - 1e-3 * gnn_us * len(solve_ms)
-        nbytes = np.array([pcg_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed, rotating, fdeg)
-                           for r in timed])
+        nbytes = np.array([pcg_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed, rotating, fdeg,
+                                     tiles if fdefl else 0) for r in timed])
         return {
             "solves_per_s": 2 * K / elapsed,
             "ms_per_step": 1e3 * elapsed / K,
@@ -445,7 +456,8 @@ def main():
             "learned_guess_kept": (float(np.mean(timed["guess"] == cgp.CGP_GUESS_LEARNED))
                                    if guess == cgp.CGP_GUESS_LEARNED else None),
             "precision": "fp32+fp64 refinement" if mixed else "fp64",
-            "preconditioner": f"Chebyshev degree {fdeg}" if fdeg >= 2 else "Jacobi",
+            "preconditioner": (f"Chebyshev degree {fdeg}" if fdeg >= 2 else "Jacobi") +
+                              (f", deflated ({tiles} aggregates)" if fdefl else ""),
             "guess": {cgp.CGP_GUESS_GIVEN: "previous solution", cgp.CGP_GUESS_EXTRAP: "extrapolation",
                       cgp.CGP_GUESS_LEARNED: "learned"}[guess],
             "all_converged": ok,
@@ -499,18 +511,19 @@ def main():
                          f"sequence, phi and p ({2 * S} solves, mean {np.mean(its):.0f} iterations, "
                          f"{cpu_t:.1f} s)"}
 
-    mprec, _, mdeg = forms[main_form]
+    mprec, _, mdeg, mdefl = forms[main_form]
     mixed_main = mprec == cgp.CGP_FP32_IR
     tname = "float" if mixed_main else "double"
     if mdeg >= 1:
         kname = f"k_cg_tile<{tname}, 8>"
-        bpi = (mdeg * (8 * nnz + 8 * nc) + 52 * nc) if mixed_main else (mdeg * (12 * nnz + 16 * nc) + 104 * nc)
+        bpi = pcg_bytes(nc, nnz, 1, 0, mixed_main, False, mdeg, tiles if mdefl else 0) - \
+            pcg_bytes(nc, nnz, 0, 0, mixed_main, False, mdeg, tiles if mdefl else 0)
     else:
         kname = f"k_cg_step<{tname}, 4>"
         bpi = (8 * nnz + 44 * nc) if mixed_main else (12 * nnz + 88 * nc)
     traffic = None
     if kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"] and (nx, ny) == (513, 257):
-        traffic = MEASURED_TRAFFIC.get(f"{kname} degree {mdeg}")
+        traffic = MEASURED_TRAFFIC.get(f"{kname} degree {mdeg}" + (" deflated" if mdefl else ""))
     out = {
         "metric": METRIC,
         "value": R["solves_per_s"],
@@ -538,7 +551,8 @@ def main():
                      "frac": R["achieved_GBs"] / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": f"{kname} (one CG stage per launch)",
+                     "kernel": f"{kname} (one CG stage per launch" +
+                               (", followed by the coarse kernel k_cg_coarse)" if mdefl else ")"),
                      "algorithmic_bytes_per_iter": bpi,
                      "bytes_model": "d products with K (matrix read once each) + own-row recurrence vectors; "
                                     "see pcg_bytes",

@@ -30,6 +30,8 @@ struct Plan {
     int32_t *d_done = nullptr;       // staged driver: finished-instance counter
     SolveParams *d_prm = nullptr;    // staged driver: parameters of the current call
     int32_t *d_cblk_inst = nullptr;  // deflation: instance of each coarse-kernel workgroup
+    CoarseRec *d_crecs = nullptr;    // deflation: per-instance coarse-step records (device)
+    std::vector<CoarseRec> crecs;    // the same on the host (a single instance's goes by value)
     int cgrid = 0;                   // deflation: coarse-kernel workgroups
     int grid = 0;
     int n_inst = 0;
@@ -37,11 +39,18 @@ struct Plan {
     hipGraph_t graph = nullptr;      // staged driver: `launches` stage launches
     hipGraphExec_t exec = nullptr;
     int launches = 0;
+    hipGraph_t tail_graph = nullptr; // staged driver: TAIL_LAUNCHES stage launches for the end of a solve
+    hipGraphExec_t tail_exec = nullptr;
+    int32_t last_stages = 0;         // launches the previous solve of this plan needed (0 = unknown)
     ~Plan() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (tail_exec) (void)hipGraphExecDestroy(tail_exec);
+        if (tail_graph) (void)hipGraphDestroy(tail_graph);
     }
 };
+
+constexpr int TAIL_LAUNCHES = 4;   // stage launches per graph near the predicted end of a solve
 
 struct GraphRec {
     hipGraph_t graph = nullptr;
@@ -68,7 +77,8 @@ struct cgp_ctx_s {
     std::map<int32_t, std::unique_ptr<Model, ModelDel>> models;
     int32_t next_model = 0;
     DBuf<GridSync> sync;
-    int32_t *host_flag = nullptr;     // pinned, mapped: set by the device when a staged solve is done
+    int32_t *host_flag = nullptr;     // pinned, mapped: [0] set by the device when a staged solve is
+                                      // done, [1] the launches its last instance needed
     int32_t *host_flag_dev = nullptr;
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     uint64_t timeout_ticks = 0;
@@ -183,8 +193,8 @@ cgp_status cgp_create(cgp_ctx *out, int32_t device, void *hip_stream) {
         ctx->max_blocks_per_cu = std::max(1, pcg_max_blocks_per_cu());
         ctx->sync.alloc(1);
         CGP_HIP(hipMemset(ctx->sync.p, 0, sizeof(GridSync)));
-        CGP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->host_flag), sizeof(int32_t), hipHostMallocMapped));
-        *ctx->host_flag = 0;
+        CGP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->host_flag), 2 * sizeof(int32_t), hipHostMallocMapped));
+        ctx->host_flag[0] = ctx->host_flag[1] = 0;
         CGP_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->host_flag_dev), ctx->host_flag, 0));
         CGP_HIP(hipEventCreateWithFlags(&ctx->chunk_ev[0], hipEventDisableTiming));
         CGP_HIP(hipEventCreateWithFlags(&ctx->chunk_ev[1], hipEventDisableTiming));
@@ -506,7 +516,8 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 const size_t off_mu = align(off_part + sizeof(double) * npart);
                 const size_t off_cpart = align(off_mu + sizeof(double) * nmu);
                 const size_t off_cbi = align(off_cpart + sizeof(double) * ncb_total);
-                const size_t total = off_cbi + sizeof(int32_t) * ncb_total;
+                const size_t off_crec = align(off_cbi + sizeof(int32_t) * ncb_total);
+                const size_t total = off_crec + (defl ? sizeof(CoarseRec) * gn : 0);
                 p->buf.alloc(total);
                 std::vector<uint8_t> host(off_ctl, 0);
                 InstDesc *hd = reinterpret_cast<InstDesc *>(host.data());
@@ -580,6 +591,14 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                             dmu += nb[i];
                             dcpart += d.ncb;
                             for (int v = 0; v < d.ncb; ++v) hcbi.push_back(i);
+                            CoarseRec cr{};
+                            cr.einv = d.einv;
+                            cr.partials = d.partials;
+                            cr.mu = d.mu;
+                            cr.cpart = d.cpart;
+                            cr.m = nb[i];
+                            cr.cblk0 = cblk;
+                            p->crecs.push_back(cr);
                             cblk += d.ncb;
                         }
                         if (degree == 1) {
@@ -613,6 +632,9 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     CGP_HIP(hipMemcpyAsync(p->buf.p + off_cbi, hcbi.data(), sizeof(int32_t) * hcbi.size(),
                                            hipMemcpyHostToDevice, ctx->aux));
                     p->d_cblk_inst = reinterpret_cast<int32_t *>(p->buf.p + off_cbi);
+                    p->d_crecs = reinterpret_cast<CoarseRec *>(p->buf.p + off_crec);
+                    CGP_HIP(hipMemcpyAsync(p->d_crecs, p->crecs.data(), sizeof(CoarseRec) * p->crecs.size(),
+                                           hipMemcpyHostToDevice, ctx->aux));
                     p->cgrid = cblk;
                 }
                 p->d_insts = reinterpret_cast<InstDesc *>(p->buf.p);
@@ -644,32 +666,43 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                                      gp, ctx->sync.p, plan->d_done_at, ctx->timeout_ticks);
                 continue;
             }
-            // staged: a graph of `launches` stage launches, replayed until every instance is done
-            if (!plan->exec) {
+            // staged: graphs of stage launches (an even count each, so that the buffer parity runs
+            // on from one graph to the next), replayed until every instance is done
+            auto capture = [&](int count, hipGraph_t &graph, hipGraphExec_t &exec) {
                 // the launch template is recorded on the private stream (the caller's may be the null stream)
                 CGP_HIP(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeRelaxed));
-                for (int l = 0; l < launches; ++l) {
+                for (int l = 0; l < count; ++l) {
                     if (tiled) {
-                        launch_cg_tile(ctx->aux, o.precision == CGP_FP32_IR, tp[g0]->width, gn, plan->d_insts,
+                        launch_cg_tile(ctx->aux, o.precision == CGP_FP32_IR, tp[g0]->width, defl, gn, plan->d_insts,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
                                        plan->d_done, ctx->host_flag_dev);
-                        if (defl) launch_cg_coarse(ctx->aux, plan->d_insts, plan->d_cblk_inst, plan->cgrid, l & 1);
-                    } else
+                        if (defl)
+                            launch_cg_coarse(ctx->aux, gn == 1 ? plan->crecs.data() : nullptr, plan->d_crecs,
+                                             plan->d_cblk_inst, plan->cgrid, l & 1);
+                    } else {
                         launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
                                        plan->d_done, ctx->host_flag_dev);
+                    }
                 }
-                CGP_HIP(hipStreamEndCapture(ctx->aux, &plan->graph));
-                CGP_HIP(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+                CGP_HIP(hipStreamEndCapture(ctx->aux, &graph));
+                CGP_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            };
+            if (!plan->exec) {
+                capture(launches, plan->graph, plan->exec);
                 plan->launches = launches;
+                if (launches > TAIL_LAUNCHES) capture(TAIL_LAUNCHES, plan->tail_graph, plan->tail_exec);
             }
             volatile int32_t *flag = ctx->host_flag;
-            *flag = 0;
+            flag[0] = 0;
             launch_cg_boot(ctx->stream, plan->d_insts, gn, gp, plan->d_prm, plan->d_done);
             // each instance needs at most max_iter iterations plus three stages per
             // refinement (at most one per iteration) plus a few set-up stages
             const int64_t max_stages = 4 * static_cast<int64_t>(prm.max_iter) + 16;
-            const int64_t max_chunks = max_stages / plan->launches + 2;
+            // full graphs while they end before the launch count the previous solve of this plan
+            // needed, then short ones, so that little runs past the end
+            const int64_t predicted = plan->last_stages;
+            int64_t issued = 0;
             int64_t chunk = 0;
             bool finished = false;
             while (!finished) {
@@ -688,12 +721,17 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     if (finished) break;
                     if (*flag) break;
                 }
-                if (chunk >= max_chunks) throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
-                CGP_HIP(hipGraphLaunch(plan->exec, ctx->stream));
+                if (issued >= max_stages + 2 * plan->launches)
+                    throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
+                const bool tail = plan->tail_exec && predicted > 0 && issued + plan->launches > predicted;
+                CGP_HIP(hipGraphLaunch(tail ? plan->tail_exec : plan->exec, ctx->stream));
                 CGP_HIP(hipEventRecord(ctx->chunk_ev[chunk & 1], ctx->stream));
-                ctx->stage_launches += plan->launches;
+                const int count = tail ? TAIL_LAUNCHES : plan->launches;
+                ctx->stage_launches += count;
+                issued += count;
                 ++chunk;
             }
+            plan->last_stages = flag[1];
         }
     });
 }

@@ -170,7 +170,7 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P);
 
 // per-instance control state of the CG stage machine
 struct Ctl {
-    int32_t state, it, refinements, status, guess_used, pad_, restart, first;
+    int32_t state, it, refinements, status, guess_used, stages, restart, first;   // stages: launches decoded
     double gamma, alpha, beta, pap, bnorm, rmax, rel_res, rel_res_guess;
 };
 
@@ -268,12 +268,22 @@ void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolvePar
 void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts, const int32_t *d_block_inst,
                     const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par, int32_t *d_done,
                     int32_t *d_host_flag);
-void launch_cg_tile(hipStream_t s, bool mixed, int width, int n_inst, const InstDesc *d_insts,
+void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst, const InstDesc *d_insts,
                     const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
                     int32_t *d_done, int32_t *d_host_flag);
 // the coarse step of deflation after a tiled stage launch: mu = E^-1 (aggregate sums), c partials
 constexpr int COARSE_ROWS = 4;   // aggregates per coarse workgroup (one wavefront each)
-void launch_cg_coarse(hipStream_t s, const InstDesc *d_insts, const int32_t *d_cblk_inst, int grid, int par);
+struct CoarseRec {               // what the coarse step of one instance touches
+    const double *einv;          // [m x m]
+    const double *partials;      // the instance's [2][NPART][m] stage partials
+    double *mu;                  // [m]
+    double *cpart;               // [ceil(m / COARSE_ROWS)]
+    int32_t m;                   // aggregates (= tiles = workgroups of the tiled stage)
+    int32_t cblk0;               // first coarse workgroup of the instance
+};
+// h_single: the record of a single-instance solve (passed by value), else the device records
+void launch_cg_coarse(hipStream_t s, const CoarseRec *h_single, const CoarseRec *d_recs, const int32_t *d_cblk_inst,
+                      int grid, int par);
 int pcg_ell_max_width();
 void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
                           const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,

@@ -70,7 +70,7 @@ enum State : int32_t {
     ST_RES,       // r = b - K x (fp64)
     ST_START,     // u = M^-1 r, w = K u, reductions gamma, delta, sigma
     ST_ITER,      // one CG iteration
-    ST_FOLD,      // mixed: x += c, c = 0
+    ST_FOLD,      // mixed, last stage: x += c, c = 0 (refinements fold c at START)
     ST_ZEROX,     // ||b|| = 0: x = 0
     ST_DONE
 };
@@ -168,14 +168,16 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
         c.rel_res = rn / c.bnorm;
         if (c.first && guess != CGP_GUESS_LEARNED) c.rel_res_guess = c.rel_res;
         if (!c.first) ++c.refinements;
+        // mixed: the residual was of x + c, and c is folded into x before the end
+        const int32_t end = (mixed && !c.first) ? ST_FOLD : ST_DONE;
         if (rn <= tol * c.bnorm) {
             c.status = CGP_SOLVE_OK;
-            c.state = ST_DONE;
+            c.state = end;
             break;
         }
         if (c.it >= prm.max_iter) {
             c.status = CGP_SOLVE_NOCONV;
-            c.state = ST_DONE;
+            c.state = end;
             break;
         }
         // fp64: a failed verification restarts CG; mixed: a replaced residual keeps p and s
@@ -222,7 +224,7 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
             break;
         }
         if (mixed && (stop || rn <= prm.delta * c.rmax)) {
-            c.state = ST_FOLD;   // refine: the direction p (and s = K p) is kept
+            c.state = ST_RES;   // refine from the true residual of x + c; p (and s = K p) are kept
             break;
         }
         c.beta = g / c.gamma;
@@ -238,7 +240,7 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
         break;
     }
     case ST_FOLD:
-        c.state = ST_RES;
+        c.state = ST_DONE;
         break;
     case ST_ZEROX:
         c.rel_res = c.rel_res_guess = 0.0;
@@ -348,7 +350,6 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
             x[i] += static_cast<double>(D.c32[i]);
             D.c32[i] = 0.0f;
         }
-        carry(false, false, true);   // RES recomputes r and START rebuilds w; s = K p is kept
         break;
     case ST_JUDGE: {
         const double *p1 = D.prev1;
@@ -373,10 +374,12 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
     case ST_RES: {
         const bool first = c.first;
         if (mixed) {
+            // after the first, the iterate is x + c (c: the fp32 correction since the last START)
             float *r32 = D.r32 + wr * n;
             float *c32 = D.c32;
             staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
-                                   [&](int32_t j) { return x[j]; }, nop, [&](int32_t i, double y, double) {
+                                   [&](int32_t j) { return first ? x[j] : x[j] + static_cast<double>(c32[j]); },
+                                   nop, [&](int32_t i, double y, double) {
                                        const double ri = b[i] - y;
                                        r32[i] = static_cast<float>(ri);
                                        if (first) c32[i] = 0.0f;
@@ -411,6 +414,11 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
                                       w[i] = y;
                                       v[1] += static_cast<double>(y) * static_cast<double>(u);
                                   });
+            // fold the correction the residual stage saw into x; the next one starts at zero
+            for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) {
+                x[i] += static_cast<double>(D.c32[i]);
+                D.c32[i] = 0.0f;
+            }
         } else {
             const double *r = D.r + rd * n, *s = D.s + rd * n, *dv = D.dinv;
             double *w = D.w + wr * n;
@@ -607,22 +615,24 @@ __device__ inline void write_stats(const Ctl &c, const SolveParams &prm, int idx
 }
 
 // sums of the first NRED of an instance's per-workgroup partials by one wavefront
-// (fixed order); loads are issued four rows of 64 at a time so they are in flight together
+// (fixed order); loads are issued RED_ROWS rows of 64 at a time so they are in flight
+// together (two: their registers count against the tiled kernel's budget)
+constexpr int RED_ROWS = 2;
 __device__ inline void wave_reduce_partials(const double *part, int nblk, double (&S)[NPART]) {
     const int lane = threadIdx.x & 63;
     const CGP_GLOBAL double *pg = gld(part);
 #pragma unroll
     for (int s = 0; s < NPART; ++s) S[s] = 0.0;
-    for (int base = 0; base < nblk; base += 256) {
-        double t[4][NRED];
+    for (int base = 0; base < nblk; base += 64 * RED_ROWS) {
+        double t[RED_ROWS][NRED];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < RED_ROWS; ++u) {
             const int j = base + lane + 64 * u;
 #pragma unroll
             for (int s = 0; s < NRED; ++s) t[u][s] = j < nblk ? pg[s * nblk + j] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < RED_ROWS; ++u) {
 #pragma unroll
             for (int s = 0; s < NRED; ++s) S[s] += t[u][s];
         }
@@ -679,15 +689,21 @@ __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, 
         if (D.defl) S[NRED] = wave_coarse_term(D.cpart, D.ncb);
         const SolveParams prm = *prm_dev;
         Ctl c = prev;
-        if (prev.state != ST_DONE && threadIdx.x == 0) c = next_state(prev, S, prm, D.guess);
+        if (prev.state != ST_DONE && threadIdx.x == 0) {
+            c = next_state(prev, S, prm, D.guess);
+            c.stages = prev.stages + 1;
+        }
         if (threadIdx.x == 0) {
             sh.ctl = c;
             if (lb == 0) {
                 D.ctl[par] = c;   // carried forward every launch, DONE included
                 if (c.state == ST_DONE && prev.state != ST_DONE) {
                     write_stats(c, prm, D.stats_index);
-                    if (atomicAdd(done_count, 1) == prm.n_inst - 1)
-                        __hip_atomic_store(host_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    // the last instance to finish reports the launches it needed, then completion
+                    if (atomicAdd(done_count, 1) == prm.n_inst - 1) {
+                        __hip_atomic_store(host_flag + 1, c.stages, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    }
                 }
             }
         }
@@ -991,12 +1007,13 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
                 gst(D.c32)[j] = f.ox + al * pj;
             else
                 gst(D.x)[j] = f.ox + al * pj;
+        } else if constexpr (sizeof(T) == 4) {
+            // mixed: fold the correction the residual stage saw (f.ox = c) into x; the next
+            // correction starts with the coarse step (deflation) or at zero
+            gst(D.x)[j] = gld(D.x)[j] + static_cast<double>(f.ox);
+            gst(D.c32)[j] = zm;
         } else if (defl) {
-            // the correction is exact in fp64; in mixed precision it starts the fp32 correction
-            if constexpr (sizeof(T) == 4)
-                gst(D.c32)[j] = f.ox + zm;
-            else
-                gst(D.x)[j] = f.ox + zm;
+            gst(D.x)[j] = f.ox + zm;   // fp64: the coarse correction of x
         }
         const double r64 = static_cast<double>(r_own), u64 = static_cast<double>(u1);
         v[0] += r64 * u64;
@@ -1016,8 +1033,13 @@ __device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &
     const int wr = par, rd = par ^ 1;
     const CGP_GLOBAL int32_t *rowptr = gld(D.rowptr), *col = gld(D.col);
     const CGP_GLOBAL double *val = gld(D.val), *x = gld(D.x);
+    const CGP_GLOBAL float *cc = gld(D.c32);
+    const bool with_c = mixed && !c.first;   // the iterate is x + c after the first residual
     double kx = 0.0;
-    for (int32_t k = rowptr[own]; k < rowptr[own + 1]; ++k) kx += val[k] * x[col[k]];
+    for (int32_t k = rowptr[own]; k < rowptr[own + 1]; ++k) {
+        const int32_t j = col[k];
+        kx += val[k] * (with_c ? x[j] + static_cast<double>(cc[j]) : x[j]);
+    }
     const double bi = gld(D.b)[own], ri = bi - kx;
     if (mixed) {
         gst(D.r32)[wr * n + own] = static_cast<float>(ri);
@@ -1034,8 +1056,10 @@ __device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &
 }
 
 // fp32: at most 128 VGPRs, so that two workgroups share a compute unit and a grid of
-// up to twice the compute units (a 131841-row mesh cuts into 258 tiles) runs at once
-template <class T, int W>
+// up to twice the compute units (a 131841-row mesh cuts into 258 tiles) runs at once.
+// DEFL: the deflated iteration (its coupling records and coefficients take registers
+// the plain one does not need)
+template <class T, int W, bool DEFL>
 __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const InstDesc *__restrict__ insts,
                                                    const int32_t *__restrict__ block_inst, int n_inst,
                                                    const RowRange *__restrict__ ranges,
@@ -1055,7 +1079,7 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     // speculative loads for an iteration, in flight while the state is decoded
     TilePrefetch<T, W> f;
     tile_prefetch<T, W>(f, D, B, rd);
-    const bool defl = D.defl != 0;
+    constexpr bool defl = DEFL;
     DeflPrefetch<T> df;
     T *kzm = reinterpret_cast<T *>(sh.lds) + 3 * TILE_REGION;
     df.kr = -1;
@@ -1100,32 +1124,42 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
 
 // Coarse step of deflation after a tiled stage: mu = E^-1 q with q the stage's aggregate
 // sums (the fifth partial of its workgroups), one wavefront per aggregate, and per
-// workgroup the partial sum of mu_a q_a (fixed order); the next stage reads both.
-__global__ __launch_bounds__(64 * COARSE_ROWS) void k_cg_coarse(const InstDesc *__restrict__ insts,
-                                                               const int32_t *__restrict__ cblk_inst, int par) {
+// workgroup the partial sum of mu_a q_a (fixed order); the next stage reads both.  Every
+// stage gets one (only those after a residual, restart or iteration stage are read); the
+// record of a single instance arrives in the kernel arguments, so the products' loads are
+// the first memory accesses.
+__device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     __shared__ double red[COARSE_ROWS];
-    const InstDesc &D = insts[cblk_inst[blockIdx.x]];
-    const int cb = blockIdx.x - D.cblk0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m = D.nblk;
+    const int m = C.m;
     const int a = cb * COARSE_ROWS + wave;
-    const CGP_GLOBAL double *q = gld(D.partials) + static_cast<size_t>(par) * NPART * m + static_cast<size_t>(NRED) * m;
+    const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * m + static_cast<size_t>(NRED) * m;
     double acc = 0.0;
     if (a < m) {
-        const CGP_GLOBAL double *e = gld(D.einv) + static_cast<size_t>(a) * m;
+        const CGP_GLOBAL double *e = gld(C.einv) + static_cast<size_t>(a) * m;
         for (int b = lane; b < m; b += 64) acc += e[b] * q[b];
     }
     acc = wave_sum(acc);
     if (lane == 0) {
         red[wave] = a < m ? acc * q[a] : 0.0;
-        if (a < m) gst(D.mu)[a] = acc;
+        if (a < m) gst(C.mu)[a] = acc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < COARSE_ROWS; ++w) t += red[w];
-        gst(D.cpart)[cb] = t;
+        gst(C.cpart)[cb] = t;
     }
+}
+
+__global__ __launch_bounds__(64 * COARSE_ROWS) void k_cg_coarse1(const CoarseRec C, int par) {
+    coarse_rows(C, blockIdx.x, par);
+}
+
+__global__ __launch_bounds__(64 * COARSE_ROWS) void k_cg_coarse(const CoarseRec *__restrict__ recs,
+                                                               const int32_t *__restrict__ cblk_inst, int par) {
+    const CoarseRec C = recs[cblk_inst[blockIdx.x]];
+    coarse_rows(C, blockIdx.x - C.cblk0, par);
 }
 
 __global__ void k_cg_boot(InstDesc *insts, int n_inst, const SolveParams prm, SolveParams *prm_dev,
@@ -1306,23 +1340,31 @@ void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolvePar
     CGP_HIP(hipGetLastError());
 }
 
-void launch_cg_tile(hipStream_t s, bool mixed, int width, int n_inst, const InstDesc *d_insts,
+void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst, const InstDesc *d_insts,
                     const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
                     int32_t *d_done, int32_t *d_host_flag) {
-#define CGP_TILE(T, W)                                                                                          \
-    hipLaunchKernelGGL((k_cg_tile<T, W>), dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, n_inst, d_ranges, \
+#define CGP_TILE(T, W, F)                                                                                           \
+    hipLaunchKernelGGL((k_cg_tile<T, W, F>), dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, n_inst, d_ranges, \
                        d_prm, par, d_done, d_host_flag)
+#define CGP_TILE_W(T, F)                     \
+    if (width <= 8) CGP_TILE(T, 8, F); \
+    else CGP_TILE(T, 12, F)
     if (mixed) {
-        if (width <= 8) CGP_TILE(float, 8); else CGP_TILE(float, 12);
+        if (defl) { CGP_TILE_W(float, true); } else { CGP_TILE_W(float, false); }
     } else {
-        if (width <= 8) CGP_TILE(double, 8); else CGP_TILE(double, 12);
+        if (defl) { CGP_TILE_W(double, true); } else { CGP_TILE_W(double, false); }
     }
+#undef CGP_TILE_W
 #undef CGP_TILE
     CGP_HIP(hipGetLastError());
 }
 
-void launch_cg_coarse(hipStream_t s, const InstDesc *d_insts, const int32_t *d_cblk_inst, int grid, int par) {
-    hipLaunchKernelGGL(k_cg_coarse, dim3(grid), dim3(64 * COARSE_ROWS), 0, s, d_insts, d_cblk_inst, par);
+void launch_cg_coarse(hipStream_t s, const CoarseRec *h_single, const CoarseRec *d_recs, const int32_t *d_cblk_inst,
+                      int grid, int par) {
+    if (h_single)
+        hipLaunchKernelGGL(k_cg_coarse1, dim3(grid), dim3(64 * COARSE_ROWS), 0, s, *h_single, par);
+    else
+        hipLaunchKernelGGL(k_cg_coarse, dim3(grid), dim3(64 * COARSE_ROWS), 0, s, d_recs, d_cblk_inst, par);
     CGP_HIP(hipGetLastError());
 }
 
