@@ -17,9 +17,11 @@ so that the smooth error components that range(Z) captures, which a local
 preconditioner removes only slowly, cost no iterations.
 
 * ``rcb_parts``        recursive coordinate bisection of the nodes;
-* ``tile_parts``       the partition used as aggregates: RCB into ceil(n / 512)
+* ``tile_parts``       the tiles of the tiled solver: RCB into ceil(n / 512)
                        parts, more while a part or its matrix-graph
                        neighbourhood outgrows a workgroup's capacity;
+* ``aggregates``       the coarse space's aggregates: every tile bisected once
+                       more by the same rule (two per tile);
 * ``deflation_space``  Z and E (an aggregate without free rows gets E_aa = 1,
                        which keeps E positive definite and its coefficient 0);
 * ``dpcg``             the deflated PCG above in fp64, with the Jacobi, no, or
@@ -41,7 +43,8 @@ TILE_REGION = 2048     # rows within distance d of a part
 TILE_SPMV = 1536       # rows within distance d - 1 of a part
 MIN_ROWS = 64          # parts are never cut below this size
 # lower end of the Chebyshev interval as a fraction of its upper end, with deflation
-DEFL_CHEB_RATIO = 100.0
+DEFL_CHEB_RATIO = 30.0
+AGGREGATES_PER_TILE = 2
 
 
 def rcb_parts(xy: np.ndarray, ids: np.ndarray, parts: int) -> list[np.ndarray]:
@@ -109,6 +112,14 @@ def tile_parts(k: sp.csr_matrix, xy: np.ndarray, degree: int) -> list[np.ndarray
             return pieces
         parts += max(1, parts // 8)
     return None
+
+
+def aggregates(k: sp.csr_matrix, xy: np.ndarray, degree: int) -> list[np.ndarray] | None:
+    """The tiles of ``tile_parts``, each cut in two by ``rcb_parts``: aggregates 2t and 2t + 1."""
+    tiles = tile_parts(k, xy, degree)
+    if tiles is None:
+        return None
+    return [half for t in tiles for half in rcb_parts(xy, t, AGGREGATES_PER_TILE)]
 
 
 def deflation_space(k: sp.csr_matrix, dirichlet, pieces: list[np.ndarray]):

@@ -47,6 +47,21 @@ def test_tile_parts_partition_the_rows_within_capacity(degree):
     assert sizes.max() - sizes.min() <= 2
 
 
+def test_aggregates_halve_every_tile():
+    m, k = _system(97, 49, 11)
+    tiles = dfl.tile_parts(k, m.xy, 8)
+    aggs = dfl.aggregates(k, m.xy, 8)
+    assert len(aggs) == 2 * len(tiles)
+    for t, tile in enumerate(tiles):
+        a, b = aggs[2 * t], aggs[2 * t + 1]
+        np.testing.assert_array_equal(np.sort(np.concatenate([a, b])), tile)
+        assert len(a) == len(tile) // 2
+        # a cut across the longer side of the tile's bounding box
+        ext = m.xy[tile].max(axis=0) - m.xy[tile].min(axis=0)
+        ax = 0 if ext[0] >= ext[1] else 1
+        assert m.xy[a, ax].max() <= m.xy[b, ax].min()
+
+
 def test_empty_aggregate_gets_a_unit_diagonal():
     m, k = _system(9, 5, 3)
     dirich = np.flatnonzero(m.dirichlet)
@@ -88,7 +103,7 @@ def test_deflating_all_but_three_eigenvectors_terminates_in_three_iterations():
 @pytest.mark.parametrize("degree", [1, 4])
 def test_deflated_iteration_keeps_its_invariants_and_solves(degree):
     m, k = _system(65, 33, 7)
-    parts = dfl.tile_parts(k, m.xy, degree)
+    parts = dfl.aggregates(k, m.xy, degree)
     z, e = dfl.deflation_space(k, m.dirichlet, parts)
     b = np.random.default_rng(3).standard_normal(m.n_nodes) * (m.dirichlet == 0)
     hist = []
@@ -108,7 +123,7 @@ def test_deflated_iteration_keeps_its_invariants_and_solves(degree):
 
 def test_deflation_with_chebyshev_cuts_iterations_on_a_smooth_source():
     m, k = _system(257, 129, 9)
-    parts = dfl.tile_parts(k, m.xy, 8)
+    parts = dfl.aggregates(k, m.xy, 8)
     z, e = dfl.deflation_space(k, m.dirichlet, parts)
     u, v = ci.stream_velocity(m.xy, ci.fourier_modes(3))
     b = fem.source(m.xy, m.tri, m.dirichlet, u, v, fem.CURL, 1.0)
