@@ -370,7 +370,8 @@ def main():
         "E": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, 0, 0),
         "F": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, deg, 0),
     }
-    tiles = -(-nc // 512)   # aggregates of the deflated forms (the first tile count fits this mesh)
+    tiles = -(-nc // 512)   # tiles of the deflated forms (the first tile count fits this mesh)
+    aggs = 2 * tiles        # deflation aggregates: two per tile
 
     def run(form: str):
         prec, guess, fdeg, fdefl = forms[form]
@@ -445,7 +446,7 @@ def main():
         solve_ms = np.array([a.elapsed_time(b) for a, b in ev])
         pcg_ms = solve_ms.sum() - 1e-3 * gnn_us * len(solve_ms)
         nbytes = np.array([pcg_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed, rotating, fdeg,
-                                     tiles if fdefl else 0) for r in timed])
+                                     aggs if fdefl else 0) for r in timed])
         return {
             "solves_per_s": 2 * K / elapsed,
             "ms_per_step": 1e3 * elapsed / K,
@@ -457,7 +458,7 @@ def main():
                                    if guess == cgp.CGP_GUESS_LEARNED else None),
             "precision": "fp32+fp64 refinement" if mixed else "fp64",
             "preconditioner": (f"Chebyshev degree {fdeg}" if fdeg >= 2 else "Jacobi") +
-                              (f", deflated ({tiles} aggregates)" if fdefl else ""),
+                              (f", deflated ({aggs} aggregates)" if fdefl else ""),
             "guess": {cgp.CGP_GUESS_GIVEN: "previous solution", cgp.CGP_GUESS_EXTRAP: "extrapolation",
                       cgp.CGP_GUESS_LEARNED: "learned"}[guess],
             "all_converged": ok,
@@ -516,8 +517,8 @@ def main():
     tname = "float" if mixed_main else "double"
     if mdeg >= 1:
         kname = f"k_cg_tile<{tname}, 8>"
-        bpi = pcg_bytes(nc, nnz, 1, 0, mixed_main, False, mdeg, tiles if mdefl else 0) - \
-            pcg_bytes(nc, nnz, 0, 0, mixed_main, False, mdeg, tiles if mdefl else 0)
+        bpi = pcg_bytes(nc, nnz, 1, 0, mixed_main, False, mdeg, aggs if mdefl else 0) - \
+            pcg_bytes(nc, nnz, 0, 0, mixed_main, False, mdeg, aggs if mdefl else 0)
     else:
         kname = f"k_cg_step<{tname}, 4>"
         bpi = (8 * nnz + 44 * nc) if mixed_main else (12 * nnz + 88 * nc)

@@ -175,19 +175,21 @@ typedef struct {
     int32_t engine;       /* CGP_ENGINE_*                                                */
     int32_t launches_per_graph; /* CGP_ENGINE_STAGED: stages per replayed graph (0 = 16; even) */
     int32_t precond_degree; /* 0 or 1: Jacobi M = diag(K); 2..8: Chebyshev polynomial of this
-                             degree in D^-1 K over [hi/1000, hi] ([hi/100, hi] with
+                             degree in D^-1 K over [hi/1000, hi] ([hi/30, hi] with
                              deflation), hi = max_i sum_j |K_ij|/K_ii (Gershgorin),
                              applied as that many steps of Chebyshev iteration for
                              K z = r from z = 0 (CGP_ENGINE_STAGED only)                */
     int32_t deflation;    /* 0: off.  1: subdomain deflation (an extension): CG runs on the
-                             complement of the coarse space Z of the tiled iteration's
-                             tiles (free-row indicators; recursive coordinate bisection,
-                             <= 512 rows each), x0 is corrected so that Z^T r = 0 and each
+                             complement of a coarse space Z of aggregates (free-row
+                             indicators; the tiled iteration's tiles of <= 512 rows from
+                             recursive coordinate bisection, each bisected once more: two
+                             aggregates per tile), x0 is corrected so that Z^T r = 0 and each
                              direction is made K-orthogonal to range(Z) (Nicolaides;
                              Saad, Yeung, Erhel, Guyomarc'h).  Needs the tiled iteration
-                             (CGP_ENGINE_STAGED or AUTO), at most 1024 tiles per mesh,
-                             rows coupled to at most 4 tiles: CGP_E_UNSUPPORTED otherwise.
-                             E = Z^T K Z is factorised on the host on first use per mesh. */
+                             (CGP_ENGINE_STAGED or AUTO), at most 1024 aggregates per mesh,
+                             rows coupled to at most 4 aggregates: CGP_E_UNSUPPORTED
+                             otherwise.  E = Z^T K Z is inverted on the host on first use
+                             per mesh. */
 } cgp_solve_opts;
 
 typedef struct {

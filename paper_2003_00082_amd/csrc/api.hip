@@ -501,8 +501,8 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 size_t npart = 0, nmu = 0, ncb_total = 0;
                 for (int v : nb) {
                     npart += static_cast<size_t>(2) * NPART * v;
-                    nmu += v;
-                    ncb_total += (v + COARSE_ROWS - 1) / COARSE_ROWS;
+                    nmu += AGG_PER_TILE * v;
+                    ncb_total += (AGG_PER_TILE * v + COARSE_ROWS - 1) / COARSE_ROWS;
                 }
                 if (!defl) nmu = ncb_total = 0;
                 auto align = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -578,7 +578,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                         d.tval = T.eval64.p;
                         if (defl) {
                             d.defl = 1;
-                            d.ncb = (nb[i] + COARSE_ROWS - 1) / COARSE_ROWS;
+                            d.ncb = (AGG_PER_TILE * nb[i] + COARSE_ROWS - 1) / COARSE_ROWS;
                             d.cblk0 = cblk;
                             d.kzr = T.kzr.p;
                             d.kzg = T.kzg.p;
@@ -587,8 +587,8 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                             d.einv = T.einv.p;
                             d.mu = dmu;
                             d.cpart = dcpart;
-                            d.dir = m.lv[0].dir.p;
-                            dmu += nb[i];
+                            d.oagg = T.oagg.p;
+                            dmu += AGG_PER_TILE * nb[i];
                             dcpart += d.ncb;
                             for (int v = 0; v < d.ncb; ++v) hcbi.push_back(i);
                             CoarseRec cr{};
@@ -596,7 +596,8 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                             cr.partials = d.partials;
                             cr.mu = d.mu;
                             cr.cpart = d.cpart;
-                            cr.m = nb[i];
+                            cr.m = AGG_PER_TILE * nb[i];
+                            cr.tiles = nb[i];
                             cr.cblk0 = cblk;
                             p->crecs.push_back(cr);
                             cblk += d.ncb;
@@ -604,10 +605,10 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                         if (degree == 1) {
                             d.cheb[0] = 1.0;   // Jacobi: z = D^-1 r
                         } else {
-                            // Chebyshev iteration over [hi/1000, hi] ([hi/100, hi] with deflation, whose
+                            // Chebyshev iteration over [hi/1000, hi] ([hi/30, hi] with deflation, whose
                             // coarse space takes over the smooth end of the spectrum): the first step
                             // scales D^-1 r by 1/c, step k updates dz <- a1 dz + a2 D^-1 res
-                            const double hi = mesh_gershgorin(ctx->aux, m), lo = hi / (defl ? 100.0 : 1000.0);
+                            const double hi = mesh_gershgorin(ctx->aux, m), lo = hi / (defl ? 30.0 : 1000.0);
                             const double c = 0.5 * (hi + lo), e = 0.5 * (hi - lo), sig = c / e;
                             double rho = 1.0 / sig;
                             d.cheb[0] = 1.0 / c;

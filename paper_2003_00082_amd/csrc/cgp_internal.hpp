@@ -122,16 +122,19 @@ struct TilePlan {
     DBuf<uint16_t> ecol;
     DBuf<float> eval32;
     DBuf<double> eval64;
-    // subdomain deflation with the tiles as aggregates (built on first use; defl_state
-    // 0 = not built, 1 = built, -1 = not supported for this mesh)
+    // subdomain deflation, each tile cut in two aggregates (2t, 2t + 1) by one more
+    // bisection (built on first use; defl_state 0 = not built, 1 = built, -1 = not
+    // supported for this mesh)
     int32_t defl_state = 0;
+    DBuf<int8_t> oagg;        // per region entry, own rows only: 0 Dirichlet, 1 + half of the tile
     DBuf<int32_t> kzr;        // coupling record: region index of the row
     DBuf<int32_t> kzg;        // [4] per record: aggregates (tiles) the row couples to
     DBuf<float> kzv32;        // [4] per record: (K Z)_{row, aggregate}
     DBuf<double> kzv64;
-    DBuf<double> einv;        // [nparts x nparts] (Z^T K Z)^-1, row-major
+    DBuf<double> einv;        // [m x m] (Z^T K Z)^-1, row-major, m = AGG_PER_TILE * nparts
 };
 
+constexpr int AGG_PER_TILE = 2;          // deflation aggregates per tile
 constexpr int KZ_PER_ROW = 4;            // aggregates one row may couple to
 constexpr int MAX_DEFL_AGGREGATES = 1024;
 
@@ -180,9 +183,9 @@ struct RowRange {
 };
 
 // per-workgroup partial sums of a stage: gamma, delta, sigma, r.r and (deflation) the
-// aggregate sum of w or r over the workgroup's free rows; the first NRED are reduced over
-// the instance by the next stage, which puts the coarse term c in place of the fifth
-constexpr int NPART = 5;
+// sums of w or r over the free rows of the tile's two aggregates; the first NRED are
+// reduced over the instance by the next stage, which puts the coarse term c in S[NRED]
+constexpr int NPART = 6;
 constexpr int NRED = 4;
 
 // device-side description of one instance of a (batched) solve
@@ -234,10 +237,10 @@ struct InstDesc {
     const int32_t *kzg;
     const float *kzv32;
     const double *kzv;
-    const double *einv;                  // [nblk x nblk]
-    double *mu;                          // [nblk] E^-1 Z^T v of the last stage
+    const double *einv;                  // [m x m], m = AGG_PER_TILE * nblk
+    double *mu;                          // [m] E^-1 Z^T v of the last stage
     double *cpart;                       // [ncb] partial sums of mu . Z^T v
-    const uint8_t *dir;                  // Dirichlet flags of the rows
+    const int8_t *oagg;                  // own rows (by region entry): 0 Dirichlet, 1 + half of the tile
 };
 
 struct SolveParams {
@@ -275,11 +278,13 @@ void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst,
 constexpr int COARSE_ROWS = 4;   // aggregates per coarse workgroup (one wavefront each)
 struct CoarseRec {               // what the coarse step of one instance touches
     const double *einv;          // [m x m]
-    const double *partials;      // the instance's [2][NPART][m] stage partials
+    const double *partials;      // the instance's [2][NPART][tiles] stage partials
     double *mu;                  // [m]
     double *cpart;               // [ceil(m / COARSE_ROWS)]
-    int32_t m;                   // aggregates (= tiles = workgroups of the tiled stage)
+    int32_t m;                   // aggregates (AGG_PER_TILE per tile)
+    int32_t tiles;               // workgroups of the tiled stage
     int32_t cblk0;               // first coarse workgroup of the instance
+    int32_t pad_;
 };
 // h_single: the record of a single-instance solve (passed by value), else the device records
 void launch_cg_coarse(hipStream_t s, const CoarseRec *h_single, const CoarseRec *d_recs, const int32_t *d_cblk_inst,

@@ -861,17 +861,17 @@ __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, c
     }
 }
 
-// Deflation (aggregates = the tiles, Z their free-row indicators): the coarse
-// coefficients mu = E^-1 Z^T v written by the coarse kernel after the previous stage,
-// the thread's coupling record (a region row and its (K Z) entries) with the mu of the
-// aggregates it names, and the own row's aggregate coefficient and Dirichlet flag.
+// Deflation (aggregates: the two halves of every tile, Z their free-row indicators): the
+// coarse coefficients mu = E^-1 Z^T v written by the coarse kernel after the previous
+// stage, the thread's coupling record (a region row and its (K Z) entries) with the mu of
+// the aggregates it names, and the own row's aggregate code with the mu of both halves.
 template <class T>
 struct DeflPrefetch {
     int32_t kr;                // region index of the record, -1 for none
     T kv[KZ_PER_ROW];          // (K Z)_{row, a}
     T km[KZ_PER_ROW];          // mu_a (rounded to the iteration's precision)
-    T mown;                    // mu of the tile's own aggregate
-    bool ofree;                // the own row is not a Dirichlet row
+    T mu0, mu1;                // mu of the tile's two aggregates
+    int32_t code;              // own row: 0 Dirichlet (or none), 1 + half of the tile
 };
 
 template <class T>
@@ -882,11 +882,12 @@ template <>
 __device__ inline const float *kz_val<float>(const InstDesc &D) { return D.kzv32; }
 
 template <class T>
-__device__ inline void defl_prefetch(DeflPrefetch<T> &f, const InstDesc &D, const TileBlk &B, int lb, int32_t own) {
+__device__ inline void defl_prefetch(DeflPrefetch<T> &f, const InstDesc &D, const TileBlk &B, int lb) {
     const CGP_GLOBAL double *mu = gld(D.mu);
     f.kr = -1;
-    f.mown = static_cast<T>(mu[lb]);
-    f.ofree = own >= 0 ? gld(D.dir)[own] == 0 : false;
+    f.mu0 = static_cast<T>(mu[AGG_PER_TILE * lb]);
+    f.mu1 = static_cast<T>(mu[AGG_PER_TILE * lb + 1]);
+    f.code = static_cast<int>(threadIdx.x) < B.nt[0] ? gld(D.oagg)[static_cast<size_t>(B.reg_off) + threadIdx.x] : 0;
 #pragma unroll
     for (int e = 0; e < KZ_PER_ROW; ++e) {
         f.kv[e] = T(0);
@@ -921,14 +922,15 @@ __device__ inline T tile_row(const TilePrefetch<T, W> &f, int h, const T *x) {
 // neighbours from LDS) and its dz and z updates; r', the residual and z of a row
 // stay in the thread's registers (no other row reads them), dz alternates
 // between two LDS buffers, and the last step leaves the final z there for w = K z.
-// With deflation, kzm holds (K Z mu) over the region and mown, ofree describe the own
-// row: ITER takes p = u + beta p - Z mu, s = w + beta s - K Z mu (mu = E^-1 Z^T w of the
-// previous stage); START applies the coarse correction x += Z mu, r -= K Z mu (mu =
-// E^-1 Z^T r of the residual stage before it).  Both emit Z^T w' as the fifth partial.
+// With deflation, kzm holds (K Z mu) over the region and zm = (Z mu) at the own row
+// (its aggregate's mu), code its aggregate: ITER takes p = u + beta p - Z mu,
+// s = w + beta s - K Z mu (mu = E^-1 Z^T w of the previous stage); START applies the
+// coarse correction x += Z mu, r -= K Z mu (mu = E^-1 Z^T r of the residual stage before
+// it).  Both emit Z^T w' (the sums over the tile's two aggregates) as partials 4 and 5.
 template <class T, int W>
 __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, const InstDesc &D, const TileBlk &B,
                                  const int32_t *nt, const double *cheb, int wr, T *lds, const T *kzm, bool defl,
-                                 T mown, bool ofree, double (&v)[NPART]) {
+                                 T zm, int code, double (&v)[NPART]) {
     const int64_t n = D.n;
     const bool start = c.state == ST_START;
     const bool rs = c.restart;
@@ -999,7 +1001,6 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
             gst(D.u32)[j] = u1;
         else
             gst(D.u)[j] = u1;
-        const T zm = (defl && ofree) ? mown : T(0);   // (Z mu) at the own row
         if (!start) {
             const T pj = (rs ? f.ou : f.ou + be * f.op) - zm;
             gst(const_cast<T *>(vec_of<T>(D, 4)))[j] = pj;
@@ -1020,13 +1021,13 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
         v[1] += static_cast<double>(wn) * u64;
         v[2] += u64 * static_cast<double>(s_own);
         v[3] += r64 * r64;
-        if (defl && ofree) v[4] += static_cast<double>(wn);
+        if (defl && code > 0) v[NRED + code - 1] += static_cast<double>(wn);
     }
 }
 
 // The residual stage of a deflated solve, over the tile's own rows (so that the fifth
 // partial is the tile's aggregate sum Z^T r): r = b - K x in fp64 from the CSR matrix.
-__device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &B, int32_t own, bool ofree,
+__device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &B, int32_t own, int code,
                                 bool mixed, int par, double (&v)[NPART]) {
     if (static_cast<int>(threadIdx.x) >= B.nt[0]) return;
     const int64_t n = D.n;
@@ -1052,7 +1053,7 @@ __device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &
     }
     v[0] += ri * ri;
     if (c.first) v[1] += bi * bi;
-    if (ofree) v[4] += ri;
+    if (code > 0) v[NRED + code - 1] += ri;
 }
 
 // fp32: at most 128 VGPRs, so that two workgroups share a compute unit and a grid of
@@ -1083,10 +1084,10 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     DeflPrefetch<T> df;
     T *kzm = reinterpret_cast<T *>(sh.lds) + 3 * TILE_REGION;
     df.kr = -1;
-    df.mown = T(0);
-    df.ofree = false;
+    df.mu0 = df.mu1 = T(0);
+    df.code = 0;
     if (defl) {
-        defl_prefetch<T>(df, D, B, lb, static_cast<int>(threadIdx.x) < B.nt[0] ? f.g[0] : -1);
+        defl_prefetch<T>(df, D, B, lb);
 #pragma unroll
         for (int h = 0; h < TH; ++h) {
             const int t = threadIdx.x + h * BLOCK;
@@ -1108,10 +1109,10 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
             }
             __syncthreads();
         }
-        tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), kzm, defl, df.mown,
-                        df.ofree, v);
+        const T zm = df.code == 1 ? df.mu0 : (df.code == 2 ? df.mu1 : T(0));
+        tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), kzm, defl, zm, df.code, v);
     } else if (c.state == ST_RES && defl) {
-        tile_res(c, D, B, static_cast<int>(threadIdx.x) < B.nt[0] ? f.g[0] : -1, df.ofree, sizeof(T) == 4, par, v);
+        tile_res(c, D, B, static_cast<int>(threadIdx.x) < B.nt[0] ? f.g[0] : -1, df.code, sizeof(T) == 4, par, v);
     } else {
         const SolveParams prm = *prm_dev;
         const RowRange R = ranges[D.blk0 + lb];
@@ -1131,17 +1132,20 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
 __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     __shared__ double red[COARSE_ROWS];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m = C.m;
+    const int m = C.m, nt = C.tiles;
     const int a = cb * COARSE_ROWS + wave;
-    const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * m + static_cast<size_t>(NRED) * m;
+    // q_a: partial NRED + (a % 2) of tile a / 2
+    const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * nt + static_cast<size_t>(NRED) * nt;
+    static_assert(AGG_PER_TILE == 2, "aggregate a is half a % 2 of tile a / 2");
+    auto qa = [&](int i) { return q[static_cast<size_t>(i & 1) * nt + (i >> 1)]; };
     double acc = 0.0;
     if (a < m) {
         const CGP_GLOBAL double *e = gld(C.einv) + static_cast<size_t>(a) * m;
-        for (int b = lane; b < m; b += 64) acc += e[b] * q[b];
+        for (int b = lane; b < m; b += 64) acc += e[b] * qa(b);
     }
     acc = wave_sum(acc);
     if (lane == 0) {
-        red[wave] = a < m ? acc * q[a] : 0.0;
+        red[wave] = a < m ? acc * qa(a) : 0.0;
         if (a < m) gst(C.mu)[a] = acc;
     }
     __syncthreads();

@@ -219,34 +219,46 @@ TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
     return out;
 }
 
-// Deflation data of the tiled iteration, with the tiles as aggregates (Z: free-row
-// indicators of the tiles).  For every region row that couples to an aggregate through
-// K, a record (region index, up to KZ_PER_ROW aggregates, (K Z)_{row, a}); a row whose
-// couplings cancel (an interior row: zero row sum) gets none.  E = Z^T K Z is inverted
-// on the host (Cholesky), an aggregate without free rows getting E_aa = 1.
+// Deflation data of the tiled iteration.  Aggregates: every tile's own rows cut in two
+// by one more bisection (aggregates 2t and 2t + 1; Z: their free-row indicators).  For
+// every region row that couples to an aggregate through K, a record (region index, up to
+// KZ_PER_ROW aggregates, (K Z)_{row, a}); a row whose couplings cancel (an interior row:
+// zero row sum) gets none.  E = Z^T K Z is inverted on the host (Cholesky), an aggregate
+// without free rows getting E_aa = 1.
 bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
     if (P.defl_state != 0) return P.defl_state > 0;
     P.defl_state = -1;
-    const int na = P.nparts;
+    const int nt = P.nparts, na = AGG_PER_TILE * nt;
     if (na > MAX_DEFL_AGGREGATES) return false;
     const int64_t n = m.lv[0].n;
     const auto rowptr = d2h(s, m.rowptr.p, n + 1);
     const auto col = d2h(s, m.col.p, m.nnz);
     const auto val = d2h(s, m.val.p, m.nnz);
     const auto dir = d2h(s, m.lv[0].dir.p, n);
+    const auto xy = d2h(s, m.lv[0].xy.p, 2 * n);
     std::vector<int32_t> agg(n, -1);
-    for (int t = 0; t < na; ++t) {
+    std::vector<int8_t> oagg(P.hreg.size(), 0);
+    for (int t = 0; t < nt; ++t) {
         const TileBlk &B = P.hblk[t];
+        std::vector<int32_t> ids(P.hreg.begin() + B.reg_off, P.hreg.begin() + B.reg_off + B.nt[0]);
+        std::vector<size_t> cuts;
+        bisect(ids, 0, ids.size(), AGG_PER_TILE, xy, cuts);
+        size_t lo = 0;
+        for (int h = 0; h < AGG_PER_TILE; ++h) {
+            for (size_t q = lo; q < cuts[h]; ++q)
+                if (!dir[ids[q]]) agg[ids[q]] = AGG_PER_TILE * t + h;
+            lo = cuts[h];
+        }
         for (int32_t q = 0; q < B.nt[0]; ++q) {
             const int32_t j = P.hreg[static_cast<size_t>(B.reg_off) + q];
-            if (!dir[j]) agg[j] = t;
+            oagg[static_cast<size_t>(B.reg_off) + q] = agg[j] < 0 ? 0 : static_cast<int8_t>(1 + agg[j] - AGG_PER_TILE * t);
         }
     }
     // coupling records
     std::vector<TileBlk> blk = P.hblk;
     std::vector<int32_t> kzr, kzg;
     std::vector<double> kzv;
-    for (int t = 0; t < na; ++t) {
+    for (int t = 0; t < nt; ++t) {
         const TileBlk &B = P.hblk[t];
         blk[t].kz_off = static_cast<int32_t>(kzr.size());
         for (int32_t q = 0; q < B.nreg; ++q) {
@@ -281,7 +293,7 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
             if (keep > KZ_PER_ROW) return false;
             kzr.push_back(q);
             for (int e = 0; e < KZ_PER_ROW; ++e) {
-                kzg.push_back(e < keep ? ids[e] : t);
+                kzg.push_back(e < keep ? ids[e] : AGG_PER_TILE * t);
                 kzv.push_back(e < keep ? sums[e] : 0.0);
             }
         }
@@ -337,6 +349,7 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
     // in place: cached launch records of earlier solves point at this buffer
     P.hblk = blk;
     CGP_HIP(hipMemcpyAsync(P.blk.p, blk.data(), blk.size() * sizeof(TileBlk), hipMemcpyHostToDevice, s));
+    h2d(s, P.oagg, oagg);
     h2d(s, P.kzr, kzr);
     h2d(s, P.kzg, kzg);
     h2d(s, P.kzv64, kzv);

@@ -76,7 +76,7 @@ def test_fp64_deflated_solve_matches_oracle(ctx, cgp, cases, name, degree):
     x, st = _solve(ctx, cgp, c, degree=degree, tol=1e-10)
     assert st["status"] == "ok" and st["rel_res"] <= 1e-10
     assert rel(x, c.xs) <= 1e-8
-    parts = dfl.tile_parts(c.a, c.m.xy, degree)
+    parts = dfl.aggregates(c.a, c.m.xy, degree)
     z, e = dfl.deflation_space(c.a, c.m.dirichlet, parts)
     xo, info = dfl.dpcg(c.a, c.b, z, e, tol=1e-10, degree=degree)
     assert info["status"] == "ok"
