@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="ABCDEF")
     ap.add_argument("--deflation", type=int, default=1, choices=[0, 1], help="deflation in forms B, C, D")
-    ap.add_argument("--degree", type=int, default=8, help="Chebyshev preconditioner degree of forms B, C, D")
+    ap.add_argument("--degree", type=int, default=6, help="Chebyshev preconditioner degree of forms B, C, D, F")
     ap.add_argument("--refine-delta", type=float, default=1e-3,
                     help="fp32 Chebyshev forms: refine when the fp32 residual fell by this factor since the last "
                          "refinement (the Jacobi forms keep the library's default, 0.1)")
@@ -516,7 +516,7 @@ def main():
     mixed_main = mprec == cgp.CGP_FP32_IR
     tname = "float" if mixed_main else "double"
     if mdeg >= 1:
-        kname = f"k_cg_tile<{tname}, 8>"
+        kname = f"k_cg_tile<{tname}, 8, {'true' if mdefl else 'false'}>"
         bpi = pcg_bytes(nc, nnz, 1, 0, mixed_main, False, mdeg, aggs if mdefl else 0) - \
             pcg_bytes(nc, nnz, 0, 0, mixed_main, False, mdeg, aggs if mdefl else 0)
     else:

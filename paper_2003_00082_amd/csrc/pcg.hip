@@ -1130,22 +1130,35 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
 // record of a single instance arrives in the kernel arguments, so the products' loads are
 // the first memory accesses.
 __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
+    constexpr int PER_LANE = MAX_DEFL_AGGREGATES / 64;
     __shared__ double red[COARSE_ROWS];
+    __shared__ double qs[MAX_DEFL_AGGREGATES];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = C.m, nt = C.tiles;
     const int a = cb * COARSE_ROWS + wave;
-    // q_a: partial NRED + (a % 2) of tile a / 2
-    const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * nt + static_cast<size_t>(NRED) * nt;
+    // the wavefront's row of E^-1 (static) is loaded first, so that its loads and those of
+    // the stage's aggregate sums are in flight together
+    double e[PER_LANE];
+    const CGP_GLOBAL double *er = gld(C.einv) + static_cast<size_t>(a < m ? a : 0) * m;
+#pragma unroll
+    for (int k = 0; k < PER_LANE; ++k) {
+        const int b = lane + 64 * k;
+        e[k] = (a < m && b < m) ? er[b] : 0.0;
+    }
+    // q_a, the partial NRED + (a % 2) of tile a / 2, staged in LDS (coalesced)
     static_assert(AGG_PER_TILE == 2, "aggregate a is half a % 2 of tile a / 2");
-    auto qa = [&](int i) { return q[static_cast<size_t>(i & 1) * nt + (i >> 1)]; };
+    const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * nt + static_cast<size_t>(NRED) * nt;
+    for (int i = threadIdx.x; i < m; i += 64 * COARSE_ROWS) qs[i] = q[static_cast<size_t>(i & 1) * nt + (i >> 1)];
+    __syncthreads();
     double acc = 0.0;
-    if (a < m) {
-        const CGP_GLOBAL double *e = gld(C.einv) + static_cast<size_t>(a) * m;
-        for (int b = lane; b < m; b += 64) acc += e[b] * qa(b);
+#pragma unroll
+    for (int k = 0; k < PER_LANE; ++k) {
+        const int b = lane + 64 * k;
+        if (b < m) acc += e[k] * qs[b];
     }
     acc = wave_sum(acc);
     if (lane == 0) {
-        red[wave] = a < m ? acc * qa(a) : 0.0;
+        red[wave] = a < m ? acc * qs[a] : 0.0;
         if (a < m) gst(C.mu)[a] = acc;
     }
     __syncthreads();
