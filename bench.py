@@ -47,8 +47,9 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "3da4aeb0af2dd9c8", "profile": "profiles/cg_traffic_513x257.md",
-                    "k_cg_tile<float, 8> degree 8": 39.33e6, "k_cg_tile<double, 8> degree 8": 56.62e6}
+MEASURED_TRAFFIC = {"fingerprint": "ec46278ec7abce65", "profile": "profiles/cg_traffic_513x257.md",
+                    "k_cg_tile<float, 8, true> degree 6 deflated": 25.94e6,
+                    "k_cg_tile<double, 8, true> degree 6 deflated": 42.77e6}
 
 
 def kernel_fingerprint() -> str:
