@@ -31,6 +31,7 @@ struct Plan {
     SolveParams *d_prm = nullptr;    // staged driver: parameters of the current call
     int32_t *d_cblk_inst = nullptr;  // deflation: instance of each coarse-kernel workgroup
     CoarseRec *d_crecs = nullptr;    // deflation: per-instance coarse-step records (device)
+    InstDesc one{};                  // a single instance's record (passed by value to the stage kernels)
     std::vector<CoarseRec> crecs;    // the same on the host (a single instance's goes by value)
     int cgrid = 0;                   // deflation: coarse-kernel workgroups
     int grid = 0;
@@ -626,6 +627,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     poff += static_cast<size_t>(2) * NPART * nb[i];
                 }
                 CGP_HIP(hipMemcpyAsync(p->buf.p, host.data(), off_rng, hipMemcpyHostToDevice, ctx->aux));
+                p->one = hd[0];
                 if (defl) {
                     // mu and the coarse partials start at zero: the first stages read them before
                     // any coarse step has produced values for them
@@ -675,6 +677,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 for (int l = 0; l < count; ++l) {
                     if (tiled) {
                         launch_cg_tile(ctx->aux, o.precision == CGP_FP32_IR, tp[g0]->width, defl, gn, plan->d_insts,
+                                       gn == 1 ? &plan->one : nullptr,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
                                        plan->d_done, ctx->host_flag_dev);
                         if (defl)
@@ -682,6 +685,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                                              plan->d_cblk_inst, plan->cgrid, l & 1);
                     } else {
                         launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
+                                       gn == 1 ? &plan->one : nullptr,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
                                        plan->d_done, ctx->host_flag_dev);
                     }

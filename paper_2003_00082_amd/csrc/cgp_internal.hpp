@@ -268,12 +268,13 @@ void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_bloc
                    RowRange *d_ranges);
 void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
                     int32_t *d_done);
-void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts, const int32_t *d_block_inst,
-                    const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par, int32_t *d_done,
-                    int32_t *d_host_flag);
+// h_one: the record of a single-instance solve (passed by value to the kernel), else null
+void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts, const InstDesc *h_one,
+                    const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm,
+                    int par, int32_t *d_done, int32_t *d_host_flag);
 void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst, const InstDesc *d_insts,
-                    const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
-                    int32_t *d_done, int32_t *d_host_flag);
+                    const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
+                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag);
 // the coarse step of deflation after a tiled stage launch: mu = E^-1 (aggregate sums), c partials
 constexpr int COARSE_ROWS = 4;   // aggregates per coarse workgroup (one wavefront each)
 struct CoarseRec {               // what the coarse step of one instance touches

@@ -723,15 +723,16 @@ __device__ inline int xcd_block(int v, int G) {
     return x * q + (x < rm ? x : rm) + k;
 }
 
-template <class T, int H>
-__global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ insts,
+// ONE: a single instance, whose record arrives by value in the kernel arguments (one
+// dependent load less on every pointer the stage follows)
+template <class T, int H, bool ONE>
+__global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ insts, const InstDesc one,
                                                    const int32_t *__restrict__ block_inst, int n_inst,
                                                    const RowRange *__restrict__ ranges,
                                                    const SolveParams *__restrict__ prm_dev, int par,
                                                    int32_t *done_count, int32_t *host_flag) {
     __shared__ Shared sh;
-    const int inst = n_inst == 1 ? 0 : block_inst[blockIdx.x];
-    const InstDesc D = insts[inst];
+    const InstDesc &D = ONE ? one : insts[block_inst[blockIdx.x]];
     const int lb = xcd_block(blockIdx.x - D.blk0, D.nblk);
     const RowRange R = ranges[D.blk0 + lb];
     const int rd = par ^ 1;
@@ -1060,23 +1061,22 @@ __device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &
 // up to twice the compute units (a 131841-row mesh cuts into 258 tiles) runs at once.
 // DEFL: the deflated iteration (its coupling records and coefficients take registers
 // the plain one does not need)
-template <class T, int W, bool DEFL>
+template <class T, int W, bool DEFL, bool ONE>
 __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const InstDesc *__restrict__ insts,
-                                                   const int32_t *__restrict__ block_inst, int n_inst,
-                                                   const RowRange *__restrict__ ranges,
+                                                   const InstDesc one, const int32_t *__restrict__ block_inst,
+                                                   int n_inst, const RowRange *__restrict__ ranges,
                                                    const SolveParams *__restrict__ prm_dev, int par,
                                                    int32_t *done_count, int32_t *host_flag) {
     __shared__ Shared sh;
     __shared__ int32_t s_nt[TILE_MAX_DEGREE + 2];
     __shared__ double s_cheb[2 * TILE_MAX_DEGREE];
-    const int inst = n_inst == 1 ? 0 : block_inst[blockIdx.x];
-    const InstDesc D = insts[inst];
+    const InstDesc &D = ONE ? one : insts[block_inst[blockIdx.x]];
     const int lb = xcd_block(blockIdx.x - D.blk0, D.nblk);
     const TileBlk B = D.tblk[lb];
     const int rd = par ^ 1;
     // per-distance row counts and coefficients, indexed by a run-time degree: LDS
     if (threadIdx.x < TILE_MAX_DEGREE + 2) s_nt[threadIdx.x] = D.tblk[lb].nt[threadIdx.x];
-    if (threadIdx.x < 2 * TILE_MAX_DEGREE) s_cheb[threadIdx.x] = insts[inst].cheb[threadIdx.x];
+    if (threadIdx.x < 2 * TILE_MAX_DEGREE) s_cheb[threadIdx.x] = D.cheb[threadIdx.x];
     // speculative loads for an iteration, in flight while the state is decoded
     TilePrefetch<T, W> f;
     tile_prefetch<T, W>(f, D, B, rd);
@@ -1358,11 +1358,18 @@ void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolvePar
 }
 
 void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst, const InstDesc *d_insts,
-                    const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
-                    int32_t *d_done, int32_t *d_host_flag) {
-#define CGP_TILE(T, W, F)                                                                                           \
-    hipLaunchKernelGGL((k_cg_tile<T, W, F>), dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, n_inst, d_ranges, \
-                       d_prm, par, d_done, d_host_flag)
+                    const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
+                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag) {
+    const InstDesc none{};
+#define CGP_TILE(T, W, F)                                                                                          \
+    do {                                                                                                           \
+        if (h_one)                                                                                                 \
+            hipLaunchKernelGGL((k_cg_tile<T, W, F, true>), dim3(grid), dim3(BLOCK), 0, s, d_insts, *h_one,        \
+                               d_block_inst, n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_cg_tile<T, W, F, false>), dim3(grid), dim3(BLOCK), 0, s, d_insts, none,         \
+                               d_block_inst, n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                  \
+    } while (0)
 #define CGP_TILE_W(T, F)                     \
     if (width <= 8) CGP_TILE(T, 8, F); \
     else CGP_TILE(T, 12, F)
@@ -1386,13 +1393,20 @@ void launch_cg_coarse(hipStream_t s, const CoarseRec *h_single, const CoarseRec 
 }
 
 void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts,
-                    const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm, int par,
-                    int32_t *d_done, int32_t *d_host_flag) {
+                    const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
+                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag) {
     // staged entries per thread: 4 covers workgroups whose column range spans <= 2048 rows
     const bool small = halo <= 4 * BLOCK;
-#define CGP_STEP(T, H)                                                                                             \
-    hipLaunchKernelGGL((k_cg_step<T, H>), dim3(grid), dim3(BLOCK), 0, s, d_insts, d_block_inst, n_inst, d_ranges, \
-                       d_prm, par, d_done, d_host_flag)
+    const InstDesc none{};
+#define CGP_STEP(T, H)                                                                                            \
+    do {                                                                                                          \
+        if (h_one)                                                                                                \
+            hipLaunchKernelGGL((k_cg_step<T, H, true>), dim3(grid), dim3(BLOCK), 0, s, d_insts, *h_one,          \
+                               d_block_inst, n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                 \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_cg_step<T, H, false>), dim3(grid), dim3(BLOCK), 0, s, d_insts, none,           \
+                               d_block_inst, n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                 \
+    } while (0)
     if (mixed) {
         if (small) CGP_STEP(float, 4);
         else CGP_STEP(float, HMAX);
