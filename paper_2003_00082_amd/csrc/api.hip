@@ -363,7 +363,7 @@ cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif, c
         Mesh &m = get_mesh(ctx, mesh);
         CGP_REQUIRE(d_phif && d_uf && d_vf && d_fx && d_fy, "null device pointer");
         CGP_REQUIRE(std::isfinite(sigma) && std::isfinite(B0), "sigma and B0 must be finite");
-        launch_lorentz(ctx->stream, m, d_phif, d_uf, d_vf, sigma, B0, d_fx, d_fy, d_grad_elem);
+        launch_lorentz(ctx->stream, m, d_phif, d_uf, d_vf, sigma, B0, d_fx, d_fy, d_grad_elem, !ctx->capturing);
     });
 }
 
@@ -376,7 +376,7 @@ cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, 
         CGP_REQUIRE(std::isfinite(scale), "scale must be finite");
         CGP_REQUIRE(d_u != d_v, "d_u and d_v must differ");
         CGP_REQUIRE(d_u != d_pf && d_v != d_pf, "the output must not overwrite d_pf");
-        launch_velocity(ctx->stream, m, d_pf, d_ut, d_vt, scale, d_u, d_v);
+        launch_velocity(ctx->stream, m, d_pf, d_ut, d_vt, scale, d_u, d_v, !ctx->capturing);
     });
 }
 

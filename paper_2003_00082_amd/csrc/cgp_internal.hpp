@@ -138,6 +138,16 @@ constexpr int AGG_PER_TILE = 2;          // deflation aggregates per tile
 constexpr int KZ_PER_ROW = 4;            // aggregates one row may couple to
 constexpr int MAX_DEFL_AGGREGATES = 1024;
 
+// The nodal gradient of the finest level as a sparse operator: G_i = sum_j (cx_ij, cy_ij) q_j
+// (the area-weighted mean of the element gradients around node i), column-major ELL of
+// width W (entry k of node i at k * n + i; padding: the node itself with zero weights).
+constexpr int GRAD_MAX_W = 32;
+struct NodalGrad {
+    int32_t W = 0;        // 0: not built; -1: a node has more than GRAD_MAX_W neighbours
+    DBuf<int32_t> col;
+    DBuf<double> cx, cy;
+};
+
 struct Mesh {
     int32_t k = 0;
     std::vector<Level> lv;
@@ -158,6 +168,7 @@ struct Mesh {
     int32_t tuned_lanes[2] = {0, 0};   // autotuned SpMV lanes per precision (0 = not tuned)
     double gershgorin = 0.0;           // max_i sum_j |K_ij| / K_ii (0 = not computed)
     std::unique_ptr<TilePlan> tiles[TILE_MAX_DEGREE + 1];   // per preconditioner degree
+    NodalGrad grad;                     // finest level, built on the first force or correction
 };
 
 // builds (or returns) the tiled plan of a mesh for degree d; nullptr when the
@@ -303,11 +314,12 @@ void build_hierarchy(hipStream_t s, Mesh &m, const double *h_xy, int64_t n, cons
 void launch_restrict(hipStream_t s, const Mesh &m, const double *uf, const double *vf, int kind,
                      double scale, double *b, double *uc, double *vc);
 void launch_prolong(hipStream_t s, Mesh &m, const double *qc, double *qf);
-void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const double *uf,
+// build: may build the nodal-gradient operator now (not while the stream is captured)
+void launch_lorentz(hipStream_t s, Mesh &m, const double *phif, const double *uf,
                     const double *vf, double sigma, double b0, double *fx, double *fy,
-                    double *grad_elem);
-void launch_velocity(hipStream_t s, const Mesh &m, const double *pf, const double *ut, const double *vt,
-                     double scale, double *u, double *v);
+                    double *grad_elem, bool build);
+void launch_velocity(hipStream_t s, Mesh &m, const double *pf, const double *ut, const double *vt,
+                     double scale, double *u, double *v, bool build);
 
 // learned initial guess (gnn.hip)
 struct Model;

@@ -120,6 +120,115 @@ __global__ __launch_bounds__(TPB) void k_velocity(
     v[i] = b - scale * gy;
 }
 
+// The nodal gradient as an operator (built once per mesh): node i's vertices of its
+// incident triangles, ascending and unique, and their weights in G_i = sum_e A_e g_e /
+// sum_e A_e with A_e g_e = 1/2 sum_a q_a beta_a.
+__device__ inline int grad_vertices(int64_t i, const int32_t *__restrict__ ne_ptr, const int32_t *__restrict__ ne_idx,
+                                    const int32_t *__restrict__ tri, int32_t (&ids)[GRAD_MAX_W]) {
+    int cnt = 0;
+    for (int32_t k = ne_ptr[i]; k < ne_ptr[i + 1]; ++k) {
+        const int64_t e = ne_idx[k];
+        for (int a = 0; a < 3; ++a) {
+            const int32_t v = tri[3 * e + a];
+            int p = 0;
+            while (p < cnt && ids[p] < v) ++p;
+            if (p < cnt && ids[p] == v) continue;
+            if (cnt == GRAD_MAX_W) return -1;
+            for (int q = cnt; q > p; --q) ids[q] = ids[q - 1];
+            ids[p] = v;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+__global__ __launch_bounds__(TPB) void k_grad_count(int64_t n, const int32_t *__restrict__ ne_ptr,
+                                                    const int32_t *__restrict__ ne_idx,
+                                                    const int32_t *__restrict__ tri, int32_t *wmax) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t ids[GRAD_MAX_W];
+    const int cnt = grad_vertices(i, ne_ptr, ne_idx, tri, ids);
+    atomicMax(wmax, cnt < 0 ? GRAD_MAX_W + 1 : cnt);
+}
+
+__global__ __launch_bounds__(TPB) void k_grad_fill(int64_t n, int W, const int32_t *__restrict__ ne_ptr,
+                                                   const int32_t *__restrict__ ne_idx,
+                                                   const int32_t *__restrict__ tri, const double *__restrict__ xy,
+                                                   int32_t *__restrict__ col, double *__restrict__ cx,
+                                                   double *__restrict__ cy) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t ids[GRAD_MAX_W];
+    double wx[GRAD_MAX_W], wy[GRAD_MAX_W];
+    const int cnt = grad_vertices(i, ne_ptr, ne_idx, tri, ids);   // <= W (counted before)
+    for (int p = 0; p < GRAD_MAX_W; ++p) wx[p] = wy[p] = 0.0;
+    double area = 0.0;
+    for (int32_t k = ne_ptr[i]; k < ne_ptr[i + 1]; ++k) {
+        const int64_t e = ne_idx[k];
+        const int32_t a0 = tri[3 * e], a1 = tri[3 * e + 1], a2 = tri[3 * e + 2];
+        const double x0 = xy[2 * a0], y0 = xy[2 * a0 + 1];
+        const double x1 = xy[2 * a1], y1 = xy[2 * a1 + 1];
+        const double x2 = xy[2 * a2], y2 = xy[2 * a2 + 1];
+        const int32_t vs[3] = {a0, a1, a2};
+        const double bx[3] = {y1 - y2, y2 - y0, y0 - y1}, by[3] = {x2 - x1, x0 - x2, x1 - x0};
+        for (int a = 0; a < 3; ++a) {
+            int p = 0;
+            while (ids[p] != vs[a]) ++p;
+            wx[p] += 0.5 * bx[a];
+            wy[p] += 0.5 * by[a];
+        }
+        area += 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+    }
+    for (int p = 0; p < W; ++p) {
+        const bool live = p < cnt;
+        col[static_cast<int64_t>(p) * n + i] = live ? ids[p] : static_cast<int32_t>(i);
+        cx[static_cast<int64_t>(p) * n + i] = live ? wx[p] / area : 0.0;
+        cy[static_cast<int64_t>(p) * n + i] = live ? wy[p] / area : 0.0;
+    }
+}
+
+// G_i from the operator (coalesced column-major entries, gathered q)
+__device__ inline void grad_apply(int64_t i, int64_t n, int W, const int32_t *__restrict__ col,
+                                  const double *__restrict__ cx, const double *__restrict__ cy,
+                                  const double *__restrict__ q, double &gx, double &gy) {
+    gx = 0.0;
+    gy = 0.0;
+    for (int p = 0; p < W; ++p) {
+        const int64_t o = static_cast<int64_t>(p) * n + i;
+        const double qj = q[col[o]];
+        gx += cx[o] * qj;
+        gy += cy[o] * qj;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_lorentz_op(int64_t n, int W, const int32_t *__restrict__ col,
+                                                    const double *__restrict__ cx, const double *__restrict__ cy,
+                                                    const double *__restrict__ phi, const double *__restrict__ u,
+                                                    const double *__restrict__ v, double sigma, double b0,
+                                                    double *__restrict__ fx, double *__restrict__ fy) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double gx, gy;
+    grad_apply(i, n, W, col, cx, cy, phi, gx, gy);
+    fx[i] = sigma * b0 * (-gy - b0 * u[i]);
+    fy[i] = sigma * b0 * (gx - b0 * v[i]);
+}
+
+// u may alias ut and v vt (thread i reads and writes only entry i of them)
+__global__ __launch_bounds__(TPB) void k_velocity_op(int64_t n, int W, const int32_t *__restrict__ col,
+                                                     const double *__restrict__ cx, const double *__restrict__ cy,
+                                                     const double *__restrict__ p, const double *ut,
+                                                     const double *vt, double scale, double *u, double *v) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double gx, gy;
+    grad_apply(i, n, W, col, cx, cy, p, gx, gy);
+    const double a = ut[i], b = vt[i];
+    u[i] = a - scale * gx;
+    v[i] = b - scale * gy;
+}
+
 // element gradient g_e = sum_a phi_a beta_a / D_e
 __global__ __launch_bounds__(TPB) void k_elem_grad(int64_t T, const int32_t *__restrict__ tri,
                                                    const double *__restrict__ xy, const double *__restrict__ phi,
@@ -162,11 +271,46 @@ void launch_prolong(hipStream_t s, Mesh &m, const double *qc, double *qf) {
     }
 }
 
-void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const double *uf, const double *vf,
-                    double sigma, double b0, double *fx, double *fy, double *grad_elem) {
+// builds the nodal-gradient operator of the finest level on first use (unless `build` is
+// false: inside a stream capture); false when it is not there or a node has more than
+// GRAD_MAX_W neighbours (the per-triangle kernels are used then)
+bool nodal_grad(hipStream_t s, Mesh &m, bool build) {
+    NodalGrad &G = m.grad;
+    if (G.W == 0 && build) {
+        const Level &L = m.lv[m.k];
+        DBuf<int32_t> w;
+        w.alloc(1);
+        CGP_HIP(hipMemsetAsync(w.p, 0, sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_grad_count, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
+                           L.tri.p, w.p);
+        CGP_HIP(hipGetLastError());
+        int32_t W = 0;
+        CGP_HIP(hipMemcpyAsync(&W, w.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CGP_HIP(hipStreamSynchronize(s));
+        if (W > GRAD_MAX_W || W < 1) {
+            G.W = -1;
+        } else {
+            G.col.alloc(static_cast<size_t>(W) * L.n);
+            G.cx.alloc(static_cast<size_t>(W) * L.n);
+            G.cy.alloc(static_cast<size_t>(W) * L.n);
+            hipLaunchKernelGGL(k_grad_fill, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, W, L.ne_ptr.p,
+                               L.ne_idx.p, L.tri.p, L.xy.p, G.col.p, G.cx.p, G.cy.p);
+            CGP_HIP(hipGetLastError());
+            G.W = W;
+        }
+    }
+    return G.W > 0;
+}
+
+void launch_lorentz(hipStream_t s, Mesh &m, const double *phif, const double *uf, const double *vf,
+                    double sigma, double b0, double *fx, double *fy, double *grad_elem, bool build) {
     const Level &L = m.lv[m.k];
-    hipLaunchKernelGGL(k_lorentz, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
-                       L.tri.p, L.xy.p, phif, uf, vf, sigma, b0, fx, fy);
+    if (nodal_grad(s, m, build))
+        hipLaunchKernelGGL(k_lorentz_op, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.grad.W, m.grad.col.p,
+                           m.grad.cx.p, m.grad.cy.p, phif, uf, vf, sigma, b0, fx, fy);
+    else
+        hipLaunchKernelGGL(k_lorentz, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
+                           L.tri.p, L.xy.p, phif, uf, vf, sigma, b0, fx, fy);
     CGP_HIP(hipGetLastError());
     if (grad_elem) {
         hipLaunchKernelGGL(k_elem_grad, dim3(blocks_for(L.T, TPB)), dim3(TPB), 0, s, L.T, L.tri.p, L.xy.p,
@@ -175,11 +319,15 @@ void launch_lorentz(hipStream_t s, const Mesh &m, const double *phif, const doub
     }
 }
 
-void launch_velocity(hipStream_t s, const Mesh &m, const double *pf, const double *ut, const double *vt,
-                     double scale, double *u, double *v) {
+void launch_velocity(hipStream_t s, Mesh &m, const double *pf, const double *ut, const double *vt,
+                     double scale, double *u, double *v, bool build) {
     const Level &L = m.lv[m.k];
-    hipLaunchKernelGGL(k_velocity, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
-                       L.tri.p, L.xy.p, pf, ut, vt, scale, u, v);
+    if (nodal_grad(s, m, build))
+        hipLaunchKernelGGL(k_velocity_op, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.grad.W, m.grad.col.p,
+                           m.grad.cx.p, m.grad.cy.p, pf, ut, vt, scale, u, v);
+    else
+        hipLaunchKernelGGL(k_velocity, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
+                           L.tri.p, L.xy.p, pf, ut, vt, scale, u, v);
     CGP_HIP(hipGetLastError());
 }
 

@@ -223,9 +223,9 @@ def test_learned_guess_beats_extrapolation_on_held_out_steps(ctx, cgp, seq):
         ctx.model_free(md)
 
 
-@pytest.mark.parametrize("engine", [1, 2])
+@pytest.mark.parametrize("engine,deflation", [(1, 0), (2, 0), (1, 1)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_learned_solve(ctx, cgp, seq, engine, precision):
+def test_learned_solve(ctx, cgp, seq, engine, deflation, precision):
     md = ctx.model_create(seed=2)
     bad = ctx.model_create(seed=3)
     try:
@@ -241,7 +241,8 @@ def test_learned_solve(ctx, cgp, seq, engine, precision):
             phi = torch.zeros(seq.m.n_nodes, dtype=torch.float64, device=DEV)
             stats = cgp.stats_buffer(1)
             ctx.poisson_solve([seq.handle], [dt(b)], [phi], stats, prev1=[dt(p1)], prev2=[dt(p2)],
-                              precision=precision, guess=cgp.CGP_GUESS_LEARNED, model=model, tol=tol, engine=engine)
+                              precision=precision, guess=cgp.CGP_GUESS_LEARNED, model=model, tol=tol, engine=engine,
+                              precond_degree=6 if deflation else 0, deflation=deflation)
             st = ctx.solve_check(1, stats)[0]
             assert st["status"] == "ok" and st["rel_res"] <= tol
             assert st["guess_used"] == want
