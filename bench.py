@@ -47,9 +47,9 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "ec46278ec7abce65", "profile": "profiles/cg_traffic_513x257.md",
-                    "k_cg_tile<float, 8, true> degree 6 deflated": 25.94e6,
-                    "k_cg_tile<double, 8, true> degree 6 deflated": 42.77e6}
+MEASURED_TRAFFIC = {"fingerprint": "48a1e727cd8e0546", "profile": "profiles/cg_traffic_513x257.md",
+                    "k_cg_tile<float, 8, true, true> degree 6 deflated": 25.94e6,
+                    "k_cg_tile<double, 8, true, true> degree 6 deflated": 42.80e6}
 
 
 def kernel_fingerprint() -> str:
@@ -517,11 +517,11 @@ def main():
     mixed_main = mprec == cgp.CGP_FP32_IR
     tname = "float" if mixed_main else "double"
     if mdeg >= 1:
-        kname = f"k_cg_tile<{tname}, 8, {'true' if mdefl else 'false'}>"
+        kname = f"k_cg_tile<{tname}, 8, {'true' if mdefl else 'false'}, true>"   # deflation, one instance
         bpi = pcg_bytes(nc, nnz, 1, 0, mixed_main, False, mdeg, aggs if mdefl else 0) - \
             pcg_bytes(nc, nnz, 0, 0, mixed_main, False, mdeg, aggs if mdefl else 0)
     else:
-        kname = f"k_cg_step<{tname}, 4>"
+        kname = f"k_cg_step<{tname}, 4, true>"
         bpi = (8 * nnz + 44 * nc) if mixed_main else (12 * nnz + 88 * nc)
     traffic = None
     if kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"] and (nx, ny) == (513, 257):
