@@ -135,8 +135,10 @@ __global__ __launch_bounds__(TPB) void k_gnn_prep(int64_t n, const int32_t *rowp
     }
 }
 
-// scales[q] = sqrt(sum / n) (1 when zero), q = b, p1, r_e, d; one workgroup
-__global__ __launch_bounds__(TPB) void k_gnn_scales(int64_t n, const double *part, int nblk, double *scales) {
+// scales[q] = sqrt(sum / n) (1 when zero), q = b, p1, r_e, d, from the per-block partials of
+// k_gnn_prep, by a TPB-thread workgroup in a fixed order (every workgroup gets the same
+// values); out in LDS, valid after the call
+__device__ inline void reduce_scales(int64_t n, const double *part, int nblk, double *out) {
     __shared__ double red[TPB / 64][4];
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = threadIdx.x; j < nblk; j += TPB)
@@ -151,8 +153,9 @@ __global__ __launch_bounds__(TPB) void k_gnn_scales(int64_t n, const double *par
         double t = 0.0;
         for (int w = 0; w < TPB / 64; ++w) t += red[w][threadIdx.x];
         const double r = sqrt(t / static_cast<double>(n));
-        scales[threadIdx.x] = r > 0.0 ? r : 1.0;
+        out[threadIdx.x] = r > 0.0 ? r : 1.0;
     }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ forward layers
@@ -203,9 +206,12 @@ __device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const float *h, c
 //   MODE 2  message layer + decoder: y = h' w_d + c_d, guess = e + s_d y on free nodes
 struct FwdArgs {
     int64_t n;
+    const double *part;   // encoder: k_gnn_prep's partials, reduced to the scales by every workgroup
+    int npart;            // their workgroup count
     const int32_t *adj_ptr, *adj_col;
     const float *hin;
     const double *b, *p1, *p2, *re, *kd, *d, *e, *scales;
+    double *scales_out;   // encoder: where workgroup 0 stores the scales
     const uint8_t *dir;
     const bf16 *wT;
     const float *bias;
@@ -250,6 +256,13 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
     constexpr int KP = K + 8;
     __shared__ __align__(16) bf16 Wl[GH * KP];
     __shared__ __align__(16) float Ct[FWD_WAVES][32 * CTS];
+    __shared__ double s_scales[4];
+    if constexpr (MODE == 0) {
+        // the feature scales, reduced here instead of in a launch of their own; workgroup 0
+        // keeps them for the decoder and the training kernels
+        reduce_scales(A.n, A.part, A.npart, s_scales);
+        if (blockIdx.x == 0 && threadIdx.x < 4) A.scales_out[threadIdx.x] = s_scales[threadIdx.x];
+    }
     for (int t = threadIdx.x; t < GH * (K / 8); t += TPB) {
         const int row = t / (K / 8), ch = t % (K / 8);
         *reinterpret_cast<bf16x8 *>(Wl + row * KP + ch * 8) = ld8(A.wT + row * K + ch * 8);
@@ -265,7 +278,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
         if constexpr (MODE == 0) {
             float f[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             if (valid && half == 0) {
-                const double sb = A.scales[0], sp = A.scales[1], sr = A.scales[2], sd = A.scales[3];
+                const double sb = s_scales[0], sp = s_scales[1], sr = s_scales[2], sd = s_scales[3];
                 f[0] = static_cast<float>(A.b[i] / sb);
                 f[1] = static_cast<float>(A.p1[i] / sp);
                 f[2] = static_cast<float>(A.p2[i] / sp);
@@ -370,13 +383,17 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
 
 // one damped Jacobi sweep xout = xin + omega D^-1 (b - K xin); Dirichlet rows (identity, b = 0)
 // keep their zero
-__global__ __launch_bounds__(TPB) void k_gnn_smooth(int64_t n, const int32_t *rowptr, const int32_t *col,
-                                                    const double *val, const double *dinv, const double *b,
-                                                    const double *xin, double *xout, double omega) {
+// (the column-major ELL copy of K: coalesced entries, the same summation order as the CSR rows)
+__global__ __launch_bounds__(TPB) void k_gnn_smooth(int64_t n, int width, const int32_t *ecol, const double *eval,
+                                                    const double *dinv, const double *b, const double *xin,
+                                                    double *xout, double omega) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
     if (i >= n) return;
     double kx = 0.0;
-    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) kx += val[k] * xin[col[k]];
+    for (int k = 0; k < width; ++k) {
+        const int64_t o = static_cast<int64_t>(k) * n + i;
+        kx += eval[o] * xin[ecol[o]];
+    }
     xout[i] = xin[i] + omega * dinv[i] * (b[i] - kx);
 }
 
@@ -651,7 +668,6 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     const unsigned nb = blocks_for(n, TPB);
     hipLaunchKernelGGL(k_gnn_prep, dim3(nb), dim3(TPB), 0, s, n, m.rowptr.p, m.col.p, m.val.p, b, p1, p2, w.e.p,
                        w.d.p, w.re.p, w.kd.p, w.part.p);
-    hipLaunchKernelGGL(k_gnn_scales, dim3(1), dim3(TPB), 0, s, n, w.part.p, static_cast<int>(nb), w.scales.p);
     const int64_t ngroups = ((n + 31) / 32 + FWD_WAVES - 1) / FWD_WAVES;
     const unsigned nf = static_cast<unsigned>(std::min<int64_t>(ngroups, FWD_MAX_BLOCKS));
     const float *th = md.theta.p;
@@ -667,6 +683,9 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     A.d = w.d.p;
     A.e = w.e.p;
     A.scales = w.scales.p;
+    A.scales_out = w.scales.p;
+    A.part = w.part.p;
+    A.npart = static_cast<int>(nb);
     A.dir = m.lv[0].dir.p;
     A.wd = th + P_WD;
     A.wT = md.wqT.p + Q_W0;
@@ -696,8 +715,8 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     for (int q = 0; guess && q < SMOOTH_SWEEPS; ++q) {
         const double *xin = (q & 1) ? w.re.p : guess;
         double *xout = (q & 1) ? guess : w.re.p;
-        hipLaunchKernelGGL(k_gnn_smooth, dim3(nb), dim3(TPB), 0, s, n, m.rowptr.p, m.col.p, m.val.p, m.dinv.p, b,
-                           xin, xout, SMOOTH_OMEGA);
+        hipLaunchKernelGGL(k_gnn_smooth, dim3(nb), dim3(TPB), 0, s, n, m.max_row, m.ell_col.p, m.ell_val.p,
+                           m.dinv.p, b, xin, xout, SMOOTH_OMEGA);
     }
     CGP_HIP(hipGetLastError());
 }
