@@ -148,12 +148,29 @@ struct NodalGrad {
     DBuf<double> cx, cy;
 };
 
+// Workgroups are dispatched to the 8 XCDs round robin (workgroup v to XCD v % 8).  This
+// maps dispatch index v to a logical block so that every XCD takes a contiguous range of
+// row blocks or tiles: neighbouring blocks share halo rows, which are then read through
+// one L2 rather than fetched by several.  A bijection of [0, G), so every block and
+// partial-sum slot is still covered once.
+__device__ inline int xcd_block(int v, int G) {
+    const int x = v % 8, k = v / 8, q = G / 8, rm = G % 8;
+    return x * q + (x < rm ? x : rm) + k;
+}
+
+constexpr int NBR_NARROW = 6;   // neighbour-table width of a regular triangulation
+constexpr int NBR_WIDE = 8;
+
 struct Mesh {
     int32_t k = 0;
     std::vector<Level> lv;
     // level-0 full adjacency (sorted, self included) kept for the learned guess
     DBuf<int32_t> adj_ptr, adj_col;
     int64_t adj_nnz = 0;
+    // the same neighbours (self excluded) as a column-major table: neighbour k of node i at
+    // k * n + i, padded with n; width nbr_w = NBR_NARROW, or a multiple of NBR_WIDE
+    DBuf<int32_t> nbr;
+    int32_t nbr_w = 0;
     // level-0 system matrix
     int64_t nnz = 0;
     int32_t max_row = 0;

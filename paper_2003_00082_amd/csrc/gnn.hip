@@ -49,7 +49,7 @@ struct GnnWork {
     int64_t n = 0;
     DBuf<double> e, d, re, kd, part, scales, delta;
     DBuf<float> x;                // [n, 16] features (training)
-    DBuf<float> h[GL + 1];        // [n, 64] activations
+    DBuf<float> h[GL + 1];        // [n + 1, 64] activations; row n stays zero (neighbour-table padding)
     DBuf<float> a[GL + 1];        // pre-activations [n, 64] (training)
     DBuf<float> y;                // [n]
     DBuf<float> dy, dh, dhp, dm;  // training
@@ -103,7 +103,8 @@ __global__ __launch_bounds__(TPB) void k_gnn_prep(int64_t n, const int32_t *rowp
                                                   const double *p2, double *e, double *d, double *re, double *kd,
                                                   double *part) {
     __shared__ double red[TPB / 64][4];
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = static_cast<int64_t>(lb) * TPB + threadIdx.x;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < n) {
         double ke = 0.0, kdd = 0.0;
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_prep(int64_t n, const int32_t *rowp
     if (threadIdx.x < 4) {
         double t = 0.0;
         for (int w = 0; w < TPB / 64; ++w) t += red[w][threadIdx.x];
-        part[static_cast<int64_t>(threadIdx.x) * gridDim.x + blockIdx.x] = t;
+        part[static_cast<int64_t>(threadIdx.x) * gridDim.x + lb] = t;
     }
 }
 
@@ -193,14 +194,18 @@ __device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const float *h, c
 }
 
 // Forward layer, one wavefront per 32-row tile; a workgroup takes groups of four
-// consecutive tiles (grid-stride, the same trip count for all its wavefronts).  The
-// MFMA A operand of lane l is row l%32, columns 8(l/32)..+7 of each 16-wide k step,
-// i.e. the 8-value chunks 2s + l/32 of the row: the lane gathers exactly those
-// chunks of its own row and of its neighbours (fp32) straight into registers and
-// feeds each as its bfloat16 high part and remainder (two MFMAs per k step).
-// Weights arrive transposed ([64 x K] bf16) and are shared through LDS rows padded
-// by 16 bytes; the accumulator tile goes back through LDS so that each lane
-// finishes its own row's chunks (residual from the registers it gathered).
+// consecutive tiles (grid-stride, the same trip count for all its wavefronts; groups
+// numbered so that every XCD takes a contiguous range, whose rows' mesh neighbours
+// are then mostly in its own L2).  Global memory is read and written row-coalesced:
+// lane l covers columns 4(l%16)..+3 of rows l/16 + 4k, k = 0..7, so that 16 lanes move
+// one 256-byte row.  A 32 x 64 fp32 tile per wavefront in LDS turns these rows into the
+// MFMA A operand (lane l: row l%32, columns 8(l/32)..+7 of each 16-wide k step), fed as
+// its bfloat16 high part and remainder (two MFMAs per k step): first the rows' own
+// activations, then their neighbour means, and finally takes the accumulators back to
+// the row layout for the epilogue.  Neighbour lists come from the column-major table
+// (lanes 0..31 load those of the tile's rows, a shuffle hands them to the row layout).
+// Weights arrive transposed ([64 x K] bf16) and are shared through LDS rows padded by
+// 16 bytes.
 //   MODE 0  encoder: features of the row computed here from b, p1, p2, r_e, K d, d
 //   MODE 1  message layer: h' = relu([h, mean_nbr h] W + c) + h
 //   MODE 2  message layer + decoder: y = h' w_d + c_d, guess = e + s_d y on free nodes
@@ -208,7 +213,8 @@ struct FwdArgs {
     int64_t n;
     const double *part;   // encoder: k_gnn_prep's partials, reduced to the scales by every workgroup
     int npart;            // their workgroup count
-    const int32_t *adj_ptr, *adj_col;
+    const int32_t *nbr;   // message layers: the mesh's neighbour table, width nbw (a multiple of NB)
+    int nbw;
     const float *hin;
     const double *b, *p1, *p2, *re, *kd, *d, *e, *scales;
     double *scales_out;   // encoder: where workgroup 0 stores the scales
@@ -225,7 +231,7 @@ struct FwdArgs {
 
 constexpr int FWD_WAVES = TPB / 64;
 constexpr int FWD_MAX_BLOCKS = 2048;
-constexpr int CTS = 36;   // padded row of the 32x32 accumulator tile in LDS (floats)
+constexpr int ZS = GH + 4;   // padded row of a wavefront's 32 x 64 LDS tile (floats)
 
 __device__ inline bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
 
@@ -240,6 +246,16 @@ __device__ inline void stf8(float *p, const float (&v)[8]) {
     reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
     reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
 }
+__device__ inline float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ inline void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+__device__ inline float4 add4(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+// orders a wavefront's LDS writes before its later LDS reads (of other lanes' values): the
+// accesses of one wavefront are performed in order, so only code motion has to be stopped
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 // v = hi + lo with hi = bf16(v), lo = bf16(v - hi)
 __device__ inline void split8(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
 #pragma unroll
@@ -249,13 +265,12 @@ __device__ inline void split8(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
+template <int MODE, int NB>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k_gnn_fwd(FwdArgs A) {
     constexpr int K = MODE == 0 ? GFP : 2 * GH;
-    constexpr int KS = K / 16;
     constexpr int KP = K + 8;
     __shared__ __align__(16) bf16 Wl[GH * KP];
-    __shared__ __align__(16) float Ct[FWD_WAVES][32 * CTS];
+    __shared__ __align__(16) float Zt[FWD_WAVES][32 * ZS];
     __shared__ double s_scales[4];
     if constexpr (MODE == 0) {
         // the feature scales, reduced here instead of in a launch of their own; workgroup 0
@@ -269,12 +284,33 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
     }
     __syncthreads();
     const int l = threadIdx.x & 63, r = l & 31, half = l >> 5, wave = threadIdx.x >> 6;
-    float *C = Ct[wave];
+    const int rg = l >> 4, c4 = (l & 15) * 4;   // row layout: rows rg + 4k, columns c4..c4+3
+    float *Z = Zt[wave];
     const int64_t n = A.n, ntiles = (n + 31) / 32, ngroups = (ntiles + FWD_WAVES - 1) / FWD_WAVES;
-    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    for (int64_t g = xcd_block(blockIdx.x, gridDim.x); g < ngroups; g += gridDim.x) {
         const int64_t row0 = (g * FWD_WAVES + wave) * 32, i = row0 + r;
         const bool valid = i < n;
-        bf16x8 ah[KS], al[KS];
+        // the two 32-column halves of the output accumulate over the k steps in order: the
+        // row's own activations (k steps 0..3) before its neighbour mean (4..7)
+        f32x16 c[2] = {};
+        auto products = [&](const bf16x8 *ah, const bf16x8 *al, int s0, int s1) {
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int s = s0; s < s1; ++s) {
+                    const bf16x8 w = ld8(Wl + (ct * 32 + r) * KP + 16 * s + 8 * half);
+                    c[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s - s0], w, c[ct], 0, 0, 0);
+                    c[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s - s0], w, c[ct], 0, 0, 0);
+                }
+        };
+        // a 32 x 64 block of the tile in the operand layout, as high parts and remainders
+        auto operands = [&](bf16x8 *ah, bf16x8 *al) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const F8 v = ldf8(Z + r * ZS + (2 * j + half) * 8);
+                split8(v.v, ah[j], al[j]);
+            }
+        };
         if constexpr (MODE == 0) {
             float f[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             if (valid && half == 0) {
@@ -288,97 +324,127 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
                 f[6] = static_cast<float>(A.dir[i]);
                 f[7] = 1.0f;
             }
+            bf16x8 ah[1], al[1];
             split8(f, ah[0], al[0]);
             if (A.xout && valid) stf8(A.xout + i * GFP + 8 * half, f);
+            products(ah, al, 0, 1);
         } else {
             const float *h = A.hin;
-            float self[4][8], acc[4][8];
+            // the rows' own activations, through the tile into the operand layout (a row past
+            // the end reads the zero row n)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (valid) {
-                    const F8 c = ldf8(h + i * GH + (2 * j + half) * 8);
+            for (int k = 0; k < 8; ++k) {
+                const int64_t ir = row0 + rg + 4 * k;
+                st4(Z + (rg + 4 * k) * ZS + c4, ld4(h + (ir < n ? ir : n) * GH + c4));
+            }
+            wave_lds_sync();
+            {
+                bf16x8 ah[4], al[4];
+                operands(ah, al);
+                products(ah, al, 0, 4);
+            }
+            wave_lds_sync();
+            // neighbour means, in table order; padding slots, and every slot of a row past the
+            // end, name row n of h, which is zero
+            if constexpr (NB > 0) {
+                // a table of width NB: lanes 0..31 hold their row's neighbours, handed to the
+                // row layout by a shuffle; two rows' gathers in flight at a time
+                const int64_t ic = valid ? i : n - 1;
+                int32_t nb[NB];
+                int deg = 0;
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) self[j][q] = c.v[q];
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) self[j][q] = 0.0f;
+                for (int u = 0; u < NB; ++u) {
+                    const int32_t v = A.nbr[static_cast<int64_t>(u) * n + ic];
+                    nb[u] = valid ? v : static_cast<int32_t>(n);
+                    deg += nb[u] != n ? 1 : 0;
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) acc[j][q] = 0.0f;
-            }
-            int deg = 0;
-            if (valid) {
-                const int32_t k0 = A.adj_ptr[i], k1 = A.adj_ptr[i + 1];
-                for (int32_t k = k0; k < k1; k += 8) {
-                    int32_t nb[8];
+                for (int k = 0; k < 8; ++k) {
+                    float4 v[NB];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) nb[u] = k + u < k1 ? A.adj_col[k + u] : -1;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        if (nb[u] < 0 || nb[u] == i) continue;
-                        ++deg;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const F8 c = ldf8(h + static_cast<int64_t>(nb[u]) * GH + (2 * j + half) * 8);
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) acc[j][q] += c.v[q];
-                        }
+                    for (int u = 0; u < NB; ++u) {
+                        const int32_t j = __shfl(nb[u], rg + 4 * k, 64);
+                        v[u] = ld4(h + static_cast<int64_t>(j) * GH + c4);
                     }
+                    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) acc = add4(acc, v[u]);
+                    const int dg = __shfl(deg, rg + 4 * k, 64);
+                    const float inv = dg > 0 ? 1.0f / static_cast<float>(dg) : 0.0f;
+                    st4(Z + (rg + 4 * k) * ZS + c4, make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv));
+                    if (k & 1) __builtin_amdgcn_sched_barrier(0);
                 }
-            }
-            const float inv = deg > 0 ? 1.0f / static_cast<float>(deg) : 0.0f;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) acc[j][q] *= inv;
-                split8(self[j], ah[j], al[j]);
-                split8(acc[j], ah[4 + j], al[4 + j]);
-            }
-        }
-        float ypart = 0.0f;
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            f32x16 c = {};
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const bf16x8 w = ld8(Wl + (ct * 32 + r) * KP + 16 * s + 8 * half);
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], w, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], w, c, 0, 0, 0);
-            }
-#pragma unroll
-            for (int v = 0; v < 16; ++v) C[((v >> 2) * 8 + half * 4 + (v & 3)) * CTS + r] = c[v];
-            __syncthreads();
-#pragma unroll
-            for (int jj = 0; jj < 2; ++jj) {
-                const int cb = (2 * jj + half) * 8, col = ct * 32 + cb;
-                if (valid) {
-                    // the residual input is read again (a cache hit) rather than kept in registers
-                    // across the products
-                    F8 res{};
-                    if constexpr (MODE != 0) res = ldf8(A.hin + i * GH + col);
-                    float pre[8], hv[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        pre[q] = C[r * CTS + cb + q] + A.bias[col + q];
-                        hv[q] = fmaxf(pre[q], 0.0f);
-                        if constexpr (MODE != 0) hv[q] += res.v[q];
-                        if (MODE == 2) ypart += hv[q] * A.wd[col + q];
+            } else {
+                // a wider table: the row-layout lanes walk their rows' slots themselves
+#pragma unroll 1
+                for (int k = 0; k < 8; ++k) {
+                    const int64_t ir = row0 + rg + 4 * k;
+                    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    int dg = 0;
+                    for (int u = 0; u < A.nbw; ++u) {
+                        const int32_t j = ir < n ? A.nbr[static_cast<int64_t>(u) * n + ir] : static_cast<int32_t>(n);
+                        dg += j != n ? 1 : 0;
+                        acc = add4(acc, ld4(h + static_cast<int64_t>(j) * GH + c4));
                     }
-                    stf8(A.hout + i * GH + col, hv);
-                    if (A.aout) stf8(A.aout + i * GH + col, pre);
+                    const float inv = dg > 0 ? 1.0f / static_cast<float>(dg) : 0.0f;
+                    st4(Z + (rg + 4 * k) * ZS + c4, make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv));
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
+            {
+                bf16x8 ah[4], al[4];
+                operands(ah, al);
+                products(ah, al, 4, 8);
+            }
+            wave_lds_sync();
         }
-        if (MODE == 2) {
-            ypart += __shfl_xor(ypart, 32, 64);
-            if (valid && half == 0) {
-                const float y = ypart + A.wd[GH];
-                if (A.yout) A.yout[i] = y;
-                if (A.guess) A.guess[i] = A.dir[i] ? 0.0 : A.e[i] + A.scales[3] * static_cast<double>(y);
+        // the accumulators go back to the row layout through the tile
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) Z[acc_row(v) * ZS + ct * 32 + acc_col()] = c[ct][v];
+        wave_lds_sync();
+        const float4 bias = ld4(A.bias + c4);
+        float4 wd = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if constexpr (MODE == 2) wd = ld4(A.wd + c4);
+        // the residual input is read again (cache hits) rather than kept in registers, all
+        // eight rows before the first store (which the compiler cannot move loads across); a
+        // row past the end reads the zero row n
+        float4 res[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t ir = row0 + rg + 4 * k;
+            res[k] = MODE != 0 ? ld4(A.hin + (ir < n ? ir : n) * GH + c4) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t ir = row0 + rg + 4 * k;
+            const bool ok = ir < n;
+            const float4 z = ld4(Z + (rg + 4 * k) * ZS + c4);
+            const float4 pre = make_float4(z.x + bias.x, z.y + bias.y, z.z + bias.z, z.w + bias.w);
+            float4 hv = make_float4(fmaxf(pre.x, 0.0f), fmaxf(pre.y, 0.0f), fmaxf(pre.z, 0.0f), fmaxf(pre.w, 0.0f));
+            if constexpr (MODE != 0) hv = add4(hv, res[k]);
+            if (ok) {
+                st4(A.hout + ir * GH + c4, hv);
+                if (A.aout) st4(A.aout + ir * GH + c4, pre);
+            }
+            if constexpr (MODE == 2) {
+                float y = hv.x * wd.x + hv.y * wd.y + hv.z * wd.z + hv.w * wd.w;
+#pragma unroll
+                for (int m = 8; m >= 1; m >>= 1) y += __shfl_xor(y, m, 64);
+                if (ok && (l & 15) == 0) {
+                    y += A.wd[GH];
+                    if (A.yout) A.yout[ir] = y;
+                    if (A.guess) A.guess[ir] = A.dir[ir] ? 0.0 : A.e[ir] + A.scales[3] * static_cast<double>(y);
+                }
             }
         }
+        wave_lds_sync();   // the tile is written again by the next group
     }
+}
+
+__global__ void k_gnn_zero(float *p, int64_t count) {
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0.0f;
 }
 
 // one damped Jacobi sweep xout = xin + omega D^-1 (b - K xin); Dirichlet rows (identity, b = 0)
@@ -387,7 +453,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_fwd(FwdArgs A) {
 __global__ __launch_bounds__(TPB) void k_gnn_smooth(int64_t n, int width, const int32_t *ecol, const double *eval,
                                                     const double *dinv, const double *b, const double *xin,
                                                     double *xout, double omega) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x;
+    const int64_t i = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * TPB + threadIdx.x;
     if (i >= n) return;
     double kx = 0.0;
     for (int k = 0; k < width; ++k) {
@@ -628,7 +694,7 @@ __global__ __launch_bounds__(TPB) void k_gnn_quantize(const float *theta, bf16 *
 
 // ------------------------------------------------------------------ host side
 
-GnnWork &work_for(Model &md, const Mesh &m, bool training) {
+GnnWork &work_for(hipStream_t s, Model &md, const Mesh &m, bool training) {
     auto &slot = md.work[&m];
     if (!slot) slot = std::make_unique<GnnWork>();
     GnnWork &w = *slot;
@@ -643,7 +709,11 @@ GnnWork &work_for(Model &md, const Mesh &m, bool training) {
         w.part.alloc(4 * blocks_for(n, TPB));
         w.scales.alloc(4);
         w.x.alloc(n * GFP);
-        for (auto &h : w.h) h.alloc(n * GH);
+        for (auto &h : w.h) {
+            h.alloc((n + 1) * GH);
+            hipLaunchKernelGGL(k_gnn_zero, dim3(1), dim3(GH), 0, s, h.p + n * GH, static_cast<int64_t>(GH));
+        }
+        CGP_HIP(hipGetLastError());
         w.y.alloc(n);
     }
     if (training && w.dy.n == 0) {
@@ -673,8 +743,8 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     const float *th = md.theta.p;
     FwdArgs A{};
     A.n = n;
-    A.adj_ptr = m.adj_ptr.p;
-    A.adj_col = m.adj_col.p;
+    A.nbr = m.nbr.p;
+    A.nbw = m.nbr_w;
     A.b = b;
     A.p1 = p1;
     A.p2 = p2;
@@ -693,7 +763,8 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     A.hout = w.h[0].p;
     A.aout = training ? w.a[0].p : nullptr;
     A.xout = training ? w.x.p : nullptr;
-    hipLaunchKernelGGL(k_gnn_fwd<0>, dim3(nf), dim3(TPB), 0, s, A);
+    hipLaunchKernelGGL((k_gnn_fwd<0, 0>), dim3(nf), dim3(TPB), 0, s, A);
+    const int nbw = m.nbr_w == NBR_NARROW ? NBR_NARROW : m.nbr_w == NBR_WIDE ? NBR_WIDE : 0;
     A.xout = nullptr;
     for (int l = 1; l <= GL; ++l) {
         A.hin = w.h[l - 1].p;
@@ -702,11 +773,21 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
         A.wT = md.wqT.p + GFP * GH + (l - 1) * 2 * GH * GH;
         A.bias = th + P_L0 + (l - 1) * P_LSTRIDE + 2 * GH * GH;
         if (l < GL) {
-            hipLaunchKernelGGL(k_gnn_fwd<1>, dim3(nf), dim3(TPB), 0, s, A);
+            if (nbw == NBR_NARROW)
+                hipLaunchKernelGGL((k_gnn_fwd<1, NBR_NARROW>), dim3(nf), dim3(TPB), 0, s, A);
+            else if (nbw == NBR_WIDE)
+                hipLaunchKernelGGL((k_gnn_fwd<1, NBR_WIDE>), dim3(nf), dim3(TPB), 0, s, A);
+            else
+                hipLaunchKernelGGL((k_gnn_fwd<1, 0>), dim3(nf), dim3(TPB), 0, s, A);
         } else {
             A.yout = w.y.p;
             A.guess = guess;
-            hipLaunchKernelGGL(k_gnn_fwd<2>, dim3(nf), dim3(TPB), 0, s, A);
+            if (nbw == NBR_NARROW)
+                hipLaunchKernelGGL((k_gnn_fwd<2, NBR_NARROW>), dim3(nf), dim3(TPB), 0, s, A);
+            else if (nbw == NBR_WIDE)
+                hipLaunchKernelGGL((k_gnn_fwd<2, NBR_WIDE>), dim3(nf), dim3(TPB), 0, s, A);
+            else
+                hipLaunchKernelGGL((k_gnn_fwd<2, 0>), dim3(nf), dim3(TPB), 0, s, A);
         }
     }
     // smoothing of the guess, ping-pong through re (no longer needed): an even number of
@@ -825,13 +906,13 @@ void gnn_get_params(hipStream_t s, Model &md, float *h) {
 
 void gnn_predict(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
                  double *guess) {
-    GnnWork &w = work_for(md, m, false);
+    GnnWork &w = work_for(s, md, m, false);
     forward(s, md, m, w, b, p1, p2, guess, false);
 }
 
 void gnn_grad(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
               const double *target, double *h_loss, float *h_grad) {
-    GnnWork &w = work_for(md, m, true);
+    GnnWork &w = work_for(s, md, m, true);
     const double nfree = count_free(s, m);
     DBuf<double> loss;
     loss.alloc(1);
@@ -845,7 +926,7 @@ void gnn_grad(hipStream_t s, Model &md, const Mesh &m, const double *b, const do
 void gnn_train(hipStream_t s, Model &md, const Mesh &m, int n_samples, const double *const *b,
                const double *const *p1, const double *const *p2, const double *const *target, int epochs,
                double lr, uint64_t seed, double *h_loss) {
-    GnnWork &w = work_for(md, m, true);
+    GnnWork &w = work_for(s, md, m, true);
     const double nfree = count_free(s, m);
     DBuf<double> losses;
     losses.alloc(epochs);

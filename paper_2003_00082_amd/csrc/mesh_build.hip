@@ -358,6 +358,31 @@ __global__ void k_max_row(int64_t n, const int32_t *rowptr, int32_t *out) {
     if (i < n) atomicMax(out, rowptr[i + 1] - rowptr[i]);
 }
 
+// ------------------------------------------------------------------ neighbour table
+
+// longest list of mesh neighbours (self excluded) over the nodes
+__global__ void k_nbr_width(int64_t n, const int32_t *adj_ptr, const int32_t *adj_col, int32_t *out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = 0;
+    for (int32_t k = adj_ptr[i]; k < adj_ptr[i + 1]; ++k) c += adj_col[k] != i;
+    atomicMax(out, c);
+}
+
+// Column-major neighbour table: neighbour k (adjacency order, self skipped) of node i at
+// k * n + i, padded with n (a row past the end that the reader keeps at zero), so that a
+// gather of all neighbours of 64 consecutive nodes is a fixed number of coalesced index
+// loads with no per-row lookup and no branch.
+__global__ void k_nbr_fill(int64_t n, int32_t width, const int32_t *adj_ptr, const int32_t *adj_col,
+                           int32_t *nbr) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = 0;
+    for (int32_t k = adj_ptr[i]; k < adj_ptr[i + 1]; ++k)
+        if (adj_col[k] != i) nbr[static_cast<int64_t>(c++) * n + i] = adj_col[k];
+    for (; c < width; ++c) nbr[static_cast<int64_t>(c) * n + i] = static_cast<int32_t>(n);
+}
+
 // ------------------------------------------------------------------ ELL copy of K
 
 // Column-major ELL: entry k of row i at k * n + i, width = the longest row.  A
@@ -507,6 +532,17 @@ void build_hierarchy(hipStream_t s, Mesh &m, const double *h_xy, int64_t n, cons
             m.ell_val32.alloc(static_cast<size_t>(m.max_row) * L.n);
             hipLaunchKernelGGL(k_ell_fill, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.max_row, m.rowptr.p,
                                m.col.p, m.val.p, m.val32.p, m.ell_col.p, m.ell_val.p, m.ell_val32.p);
+            CGP_HIP(hipGetLastError());
+            // neighbour table of the learned guess: width 6 when it fits, else a multiple of 8
+            CGP_HIP(hipMemsetAsync(mr.p, 0, sizeof(int32_t), s));
+            hipLaunchKernelGGL(k_nbr_width, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, adj_ptr.p,
+                               adj_col.p, mr.p);
+            CGP_HIP(hipGetLastError());
+            const int32_t nw = read_i32(s, mr.p);
+            m.nbr_w = nw <= NBR_NARROW ? NBR_NARROW : (nw + NBR_WIDE - 1) / NBR_WIDE * NBR_WIDE;
+            m.nbr.alloc(static_cast<size_t>(m.nbr_w) * L.n);
+            hipLaunchKernelGGL(k_nbr_fill, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.nbr_w, adj_ptr.p,
+                               adj_col.p, m.nbr.p);
             CGP_HIP(hipGetLastError());
             CGP_HIP(hipStreamSynchronize(s));
         }

@@ -715,14 +715,6 @@ __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, 
 
 // Workgroups are dealt to the eight XCDs round-robin (workgroup v to XCD v % 8), each
 // XCD with its own L2.  The staged kernels renumber an instance's workgroups so that
-// every XCD takes a contiguous range of row blocks or tiles: neighbouring blocks share
-// halo rows, which are then read through one L2 rather than fetched by several.  A
-// bijection of [0, G), so every block and partial-sum slot is still covered once.
-__device__ inline int xcd_block(int v, int G) {
-    const int x = v % 8, k = v / 8, q = G / 8, rm = G % 8;
-    return x * q + (x < rm ? x : rm) + k;
-}
-
 // ONE: a single instance, whose record arrives by value in the kernel arguments (one
 // dependent load less on every pointer the stage follows)
 template <class T, int H, bool ONE>
