@@ -97,21 +97,44 @@ __device__ inline int acc_col() { return threadIdx.x & 31; }
 
 // ------------------------------------------------------------------ features
 
-// e, d, r_e = b - K e, K d per row; per-block partial sums of b^2, p1^2, r_e^2, d^2
-__global__ __launch_bounds__(TPB) void k_gnn_prep(int64_t n, const int32_t *rowptr, const int32_t *col,
-                                                  const double *val, const double *b, const double *p1,
-                                                  const double *p2, double *e, double *d, double *re, double *kd,
-                                                  double *part) {
+// scales[q] = sqrt(sum / n) (1 when zero), q = b, p1, r_e, d, from per-block partials, by
+// a TPB-thread workgroup in a fixed order
+__device__ inline void reduce_scales(int64_t n, const double *part, int nblk, double *out) {
+    __shared__ double red[TPB / 64][4];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < nblk; j += TPB)
+        for (int q = 0; q < 4; ++q) s[q] += part[static_cast<int64_t>(q) * nblk + j];
+    for (int q = 0; q < 4; ++q) {
+        double v = s[q];
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < TPB / 64; ++w) t += red[w][threadIdx.x];
+        const double r = sqrt(t / static_cast<double>(n));
+        out[threadIdx.x] = r > 0.0 ? r : 1.0;
+    }
+}
+
+// e, d, r_e = b - K e, K d per row (K from its column-major ELL copy: coalesced entries, the
+// CSR rows' summation order); per-block partial sums of b^2, p1^2, r_e^2, d^2
+__global__ __launch_bounds__(TPB) void k_gnn_prep(int64_t n, int width, const int32_t *ecol, const double *eval,
+                                                  const double *b, const double *p1, const double *p2, double *e,
+                                                  double *d, double *re, double *kd, double *part) {
     __shared__ double red[TPB / 64][4];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t i = static_cast<int64_t>(lb) * TPB + threadIdx.x;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < n) {
         double ke = 0.0, kdd = 0.0;
-        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int32_t j = col[k];
-            ke += val[k] * (2.0 * p1[j] - p2[j]);
-            kdd += val[k] * (p1[j] - p2[j]);
+        for (int k = 0; k < width; ++k) {
+            const int64_t o = static_cast<int64_t>(k) * n + i;
+            const int32_t j = ecol[o];
+            const double v = eval[o], a = p1[j], c = p2[j];
+            ke += v * (2.0 * a - c);
+            kdd += v * (a - c);
         }
         const double ei = 2.0 * p1[i] - p2[i], di = p1[i] - p2[i], ri = b[i] - ke;
         e[i] = ei;
@@ -136,27 +159,9 @@ __global__ __launch_bounds__(TPB) void k_gnn_prep(int64_t n, const int32_t *rowp
     }
 }
 
-// scales[q] = sqrt(sum / n) (1 when zero), q = b, p1, r_e, d, from the per-block partials of
-// k_gnn_prep, by a TPB-thread workgroup in a fixed order (every workgroup gets the same
-// values); out in LDS, valid after the call
-__device__ inline void reduce_scales(int64_t n, const double *part, int nblk, double *out) {
-    __shared__ double red[TPB / 64][4];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = threadIdx.x; j < nblk; j += TPB)
-        for (int q = 0; q < 4; ++q) s[q] += part[static_cast<int64_t>(q) * nblk + j];
-    for (int q = 0; q < 4; ++q) {
-        double v = s[q];
-        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        double t = 0.0;
-        for (int w = 0; w < TPB / 64; ++w) t += red[w][threadIdx.x];
-        const double r = sqrt(t / static_cast<double>(n));
-        out[threadIdx.x] = r > 0.0 ? r : 1.0;
-    }
-    __syncthreads();
+// the feature scales from k_gnn_prep's partials, by one workgroup
+__global__ __launch_bounds__(TPB) void k_gnn_scales(int64_t n, const double *part, int nblk, double *scales) {
+    reduce_scales(n, part, nblk, scales);
 }
 
 // ------------------------------------------------------------------ forward layers
@@ -211,13 +216,10 @@ __device__ inline void build_z(bf16 *Z, int64_t r0, int64_t n, const float *h, c
 //   MODE 2  message layer + decoder: y = h' w_d + c_d, guess = e + s_d y on free nodes
 struct FwdArgs {
     int64_t n;
-    const double *part;   // encoder: k_gnn_prep's partials, reduced to the scales by every workgroup
-    int npart;            // their workgroup count
     const int32_t *nbr;   // message layers: the mesh's neighbour table, width nbw (a multiple of NB)
     int nbw;
     const float *hin;
     const double *b, *p1, *p2, *re, *kd, *d, *e, *scales;
-    double *scales_out;   // encoder: where workgroup 0 stores the scales
     const uint8_t *dir;
     const bf16 *wT;
     const float *bias;
@@ -271,13 +273,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
     constexpr int KP = K + 8;
     __shared__ __align__(16) bf16 Wl[GH * KP];
     __shared__ __align__(16) float Zt[FWD_WAVES][32 * ZS];
-    __shared__ double s_scales[4];
-    if constexpr (MODE == 0) {
-        // the feature scales, reduced here instead of in a launch of their own; workgroup 0
-        // keeps them for the decoder and the training kernels
-        reduce_scales(A.n, A.part, A.npart, s_scales);
-        if (blockIdx.x == 0 && threadIdx.x < 4) A.scales_out[threadIdx.x] = s_scales[threadIdx.x];
-    }
+    __shared__ float ys[FWD_WAVES][32];   // decoder: the network output of the tile's rows
     for (int t = threadIdx.x; t < GH * (K / 8); t += TPB) {
         const int row = t / (K / 8), ch = t % (K / 8);
         *reinterpret_cast<bf16x8 *>(Wl + row * KP + ch * 8) = ld8(A.wT + row * K + ch * 8);
@@ -314,7 +310,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
         if constexpr (MODE == 0) {
             float f[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             if (valid && half == 0) {
-                const double sb = s_scales[0], sp = s_scales[1], sr = s_scales[2], sd = s_scales[3];
+                const double sb = A.scales[0], sp = A.scales[1], sr = A.scales[2], sd = A.scales[3];
                 f[0] = static_cast<float>(A.b[i] / sb);
                 f[1] = static_cast<float>(A.p1[i] / sp);
                 f[2] = static_cast<float>(A.p2[i] / sp);
@@ -432,11 +428,16 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
                 float y = hv.x * wd.x + hv.y * wd.y + hv.z * wd.z + hv.w * wd.w;
 #pragma unroll
                 for (int m = 8; m >= 1; m >>= 1) y += __shfl_xor(y, m, 64);
-                if (ok && (l & 15) == 0) {
-                    y += A.wd[GH];
-                    if (A.yout) A.yout[ir] = y;
-                    if (A.guess) A.guess[ir] = A.dir[ir] ? 0.0 : A.e[ir] + A.scales[3] * static_cast<double>(y);
-                }
+                if ((l & 15) == 0) ys[wave][rg + 4 * k] = y + A.wd[GH];
+            }
+        }
+        if constexpr (MODE == 2) {
+            // output and guess row by row in the operand layout's lanes 0..31: coalesced
+            wave_lds_sync();
+            if (valid && half == 0) {
+                const float y = ys[wave][r];
+                if (A.yout) A.yout[i] = y;
+                if (A.guess) A.guess[i] = A.dir[i] ? 0.0 : A.e[i] + A.scales[3] * static_cast<double>(y);
             }
         }
         wave_lds_sync();   // the tile is written again by the next group
@@ -736,8 +737,9 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
              const double *p2, double *guess, bool training) {
     const int64_t n = m.lv[0].n;
     const unsigned nb = blocks_for(n, TPB);
-    hipLaunchKernelGGL(k_gnn_prep, dim3(nb), dim3(TPB), 0, s, n, m.rowptr.p, m.col.p, m.val.p, b, p1, p2, w.e.p,
-                       w.d.p, w.re.p, w.kd.p, w.part.p);
+    hipLaunchKernelGGL(k_gnn_prep, dim3(nb), dim3(TPB), 0, s, n, m.max_row, m.ell_col.p, m.ell_val.p, b, p1, p2,
+                       w.e.p, w.d.p, w.re.p, w.kd.p, w.part.p);
+    hipLaunchKernelGGL(k_gnn_scales, dim3(1), dim3(TPB), 0, s, n, w.part.p, static_cast<int>(nb), w.scales.p);
     const int64_t ngroups = ((n + 31) / 32 + FWD_WAVES - 1) / FWD_WAVES;
     const unsigned nf = static_cast<unsigned>(std::min<int64_t>(ngroups, FWD_MAX_BLOCKS));
     const float *th = md.theta.p;
@@ -753,9 +755,6 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     A.d = w.d.p;
     A.e = w.e.p;
     A.scales = w.scales.p;
-    A.scales_out = w.scales.p;
-    A.part = w.part.p;
-    A.npart = static_cast<int>(nb);
     A.dir = m.lv[0].dir.p;
     A.wd = th + P_WD;
     A.wT = md.wqT.p + Q_W0;
