@@ -18,7 +18,8 @@ preconditioner removes only slowly, cost no iterations.
 
 * ``rcb_parts``        recursive coordinate bisection of the nodes;
 * ``tile_parts``       the tiles of the tiled solver: RCB into ceil(n / 512)
-                       parts, more while a part or its matrix-graph
+                       parts (or, when that exceeds 256, into 256 parts of up
+                       to 1024 rows), more while a part or its matrix-graph
                        neighbourhood outgrows a workgroup's capacity;
 * ``aggregates``       the coarse space's aggregates: every tile bisected once
                        more by the same rule (two per tile);
@@ -38,7 +39,9 @@ import scipy.sparse as sp
 
 from . import solve
 
-TILE_ROWS = 512        # rows of a part
+TILE_ROWS = 512        # rows of a part (one per thread of a workgroup)
+TILE_ROWS_MAX = 1024   # rows a part may have (two per thread)
+TILE_GRID = 256        # parts aimed for when more than this many parts of TILE_ROWS are needed
 TILE_REGION = 2048     # rows within distance d of a part
 TILE_SPMV = 1536       # rows within distance d - 1 of a part
 MIN_ROWS = 64          # parts are never cut below this size
@@ -87,21 +90,24 @@ def _rings(k: sp.csr_matrix, own: np.ndarray, degree: int) -> list[int]:
 
 
 def tile_parts(k: sp.csr_matrix, xy: np.ndarray, degree: int) -> list[np.ndarray] | None:
-    """Aggregates: RCB parts of at most TILE_ROWS rows whose distance-<=d neighbourhood
+    """Tiles: RCB parts of at most TILE_ROWS_MAX rows whose distance-<=d neighbourhood
     holds at most TILE_REGION rows and distance-<=(d-1) neighbourhood TILE_SPMV rows.
 
-    Starts from ceil(n / TILE_ROWS) parts and adds max(1, parts // 8) until every
-    part fits, giving up (None) past ceil(n / MIN_ROWS) parts.
+    Starts from ceil(n / TILE_ROWS) parts, or, when that exceeds TILE_GRID, from
+    max(TILE_GRID, ceil(n / TILE_ROWS_MAX)) parts, and adds max(1, parts // 8) until
+    every part fits, giving up (None) past ceil(n / MIN_ROWS) parts.
     """
     k = sp.csr_matrix(k)
     n = k.shape[0]
     parts = -(-n // TILE_ROWS)
+    if parts > TILE_GRID:
+        parts = max(TILE_GRID, -(-n // TILE_ROWS_MAX))
     max_parts = -(-n // MIN_ROWS)
     while parts <= max_parts:
         pieces = rcb_parts(xy, np.arange(n), parts)
         ok = True
         for own in pieces:
-            if len(own) > TILE_ROWS:
+            if len(own) > TILE_ROWS_MAX:
                 ok = False
                 break
             c = _rings(k, own, degree)

@@ -89,7 +89,11 @@ struct SolveWork {
 
 // ------------------------------------------------------------------ tiled iteration
 
-constexpr int TILE_ROWS = 512;        // own rows per workgroup (one per thread)
+constexpr int TILE_ROWS = 512;        // own rows per workgroup at one per thread (the preferred tile)
+constexpr int TILE_OWN = 2;           // own rows a thread can hold
+constexpr int TILE_ROWS_MAX = TILE_OWN * TILE_ROWS;   // own rows per workgroup
+constexpr int TILE_GRID = 256;        // tiles aimed for when the rows need more than this many
+                                      // preferred tiles: one per compute unit of the chip
 constexpr int TILE_REGION = 2048;     // region rows per workgroup (own rows + halo to distance d)
 constexpr int TILE_SPMV = 1536;       // region rows that carry a local matrix row
 constexpr int TILE_MAX_DEGREE = 8;

@@ -755,10 +755,13 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
 // (distance <= d), updates r there, runs the d-step Chebyshev iteration for
 // K z = r' on shrinking prefixes of the region (each product with K loses one
 // distance level) and ends with u' = z and w' = K u' on its own rows — one
-// global reduction per iteration however large d is.
+// global reduction per iteration however large d is.  Region row t belongs to
+// thread t % BLOCK; the own rows come first, so a thread holds one own row, or two
+// in a tile of more than BLOCK rows.
 constexpr int TH = TILE_REGION / BLOCK;   // region rows per thread
 constexpr int TS = TILE_SPMV / BLOCK;     // local matrix rows per thread
-static_assert(BLOCK == TILE_ROWS, "one own row per thread");
+static_assert(BLOCK == TILE_ROWS, "one own row per thread in a tile of TILE_ROWS rows");
+static_assert(TILE_OWN * BLOCK == TILE_ROWS_MAX && TILE_OWN <= TS, "own rows are local matrix rows");
 static_assert(4 * TILE_REGION * sizeof(double) <= LDS_DOUBLES * sizeof(double),
               "three region vectors and the deflation term in LDS");
 
@@ -766,7 +769,7 @@ template <class T, int W>
 struct TilePrefetch {
     int32_t g[TH];                 // region rows t = tid + h * BLOCK (global ids, -1 past the end)
     T r[TH], w[TH], s[TH], dv[TH];
-    T ou, op, ox;                  // own row: u = M^-1 r, p, c (mixed) or x (fp64)
+    T ou[TILE_OWN], op[TILE_OWN], ox[TILE_OWN];   // own rows: u = M^-1 r, p, c (mixed) or x (fp64)
     T ev[TS][W];                   // local matrix rows t = tid + h * BLOCK
     uint32_t ec[TS][W / 2];        // their region columns, two 16-bit indices per register
 };
@@ -840,16 +843,20 @@ __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, c
             f.dv[h] = dv[j];
         }
     }
-    if (static_cast<int>(threadIdx.x) < B.nt[0]) {
-        const int32_t j = f.g[0];
-        if constexpr (sizeof(T) == 4) {
-            f.ou = gld(D.u32)[j];
-            f.op = gld(D.p32)[j];
-            f.ox = gld(D.c32)[j];
-        } else {
-            f.ou = gld(D.u)[j];
-            f.op = gld(D.p)[j];
-            f.ox = gld(D.x)[j];
+#pragma unroll
+    for (int h = 0; h < TILE_OWN; ++h) {
+        f.ou[h] = f.op[h] = f.ox[h] = T(0);
+        if (static_cast<int>(threadIdx.x) + h * BLOCK < B.nt[0]) {
+            const int32_t j = f.g[h];
+            if constexpr (sizeof(T) == 4) {
+                f.ou[h] = gld(D.u32)[j];
+                f.op[h] = gld(D.p32)[j];
+                f.ox[h] = gld(D.c32)[j];
+            } else {
+                f.ou[h] = gld(D.u)[j];
+                f.op[h] = gld(D.p)[j];
+                f.ox[h] = gld(D.x)[j];
+            }
         }
     }
 }
@@ -864,7 +871,7 @@ struct DeflPrefetch {
     T kv[KZ_PER_ROW];          // (K Z)_{row, a}
     T km[KZ_PER_ROW];          // mu_a (rounded to the iteration's precision)
     T mu0, mu1;                // mu of the tile's two aggregates
-    int32_t code;              // own row: 0 Dirichlet (or none), 1 + half of the tile
+    int32_t code[TILE_OWN];    // own rows: 0 Dirichlet (or none), 1 + half of the tile
 };
 
 template <class T>
@@ -880,7 +887,11 @@ __device__ inline void defl_prefetch(DeflPrefetch<T> &f, const InstDesc &D, cons
     f.kr = -1;
     f.mu0 = static_cast<T>(mu[AGG_PER_TILE * lb]);
     f.mu1 = static_cast<T>(mu[AGG_PER_TILE * lb + 1]);
-    f.code = static_cast<int>(threadIdx.x) < B.nt[0] ? gld(D.oagg)[static_cast<size_t>(B.reg_off) + threadIdx.x] : 0;
+#pragma unroll
+    for (int h = 0; h < TILE_OWN; ++h) {
+        const int t = static_cast<int>(threadIdx.x) + h * BLOCK;
+        f.code[h] = t < B.nt[0] ? gld(D.oagg)[static_cast<size_t>(B.reg_off) + t] : 0;
+    }
 #pragma unroll
     for (int e = 0; e < KZ_PER_ROW; ++e) {
         f.kv[e] = T(0);
@@ -915,15 +926,15 @@ __device__ inline T tile_row(const TilePrefetch<T, W> &f, int h, const T *x) {
 // neighbours from LDS) and its dz and z updates; r', the residual and z of a row
 // stay in the thread's registers (no other row reads them), dz alternates
 // between two LDS buffers, and the last step leaves the final z there for w = K z.
-// With deflation, kzm holds (K Z mu) over the region and zm = (Z mu) at the own row
-// (its aggregate's mu), code its aggregate: ITER takes p = u + beta p - Z mu,
+// With deflation, kzm holds (K Z mu) over the region and zm = (Z mu) at the own rows
+// (their aggregate's mu), code their aggregate: ITER takes p = u + beta p - Z mu,
 // s = w + beta s - K Z mu (mu = E^-1 Z^T w of the previous stage); START applies the
 // coarse correction x += Z mu, r -= K Z mu (mu = E^-1 Z^T r of the residual stage before
 // it).  Both emit Z^T w' (the sums over the tile's two aggregates) as partials 4 and 5.
 template <class T, int W>
 __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, const InstDesc &D, const TileBlk &B,
                                  const int32_t *nt, const double *cheb, int wr, T *lds, const T *kzm, bool defl,
-                                 T zm, int code, double (&v)[NPART]) {
+                                 const T (&zm)[TILE_OWN], const int32_t (&code)[TILE_OWN], double (&v)[NPART]) {
     const int64_t n = D.n;
     const bool start = c.state == ST_START;
     const bool rs = c.restart;
@@ -931,7 +942,7 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
     T *Zl = lds, *Da = lds + TILE_REGION, *Db = Da + TILE_REGION;
     const int deg = D.degree;
     const T c0 = static_cast<T>(cheb[0]);
-    T s_own = T(0), r_own = T(0);
+    T s_own[TILE_OWN] = {}, r_own[TILE_OWN] = {};
     T rr[TS], zz[TS], qq[TS], dd[TS];
     // r' = r - alpha (w + beta s) over the region; first Chebyshev step z = c0 D^-1 r'
 #pragma unroll
@@ -941,9 +952,9 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
             const T kz = defl ? kzm[t] : T(0);
             const T sj = start ? f.s[h] : (rs ? f.w[h] : f.w[h] + be * f.s[h]) - kz;
             const T rj = start ? f.r[h] - kz : f.r[h] - al * sj;
-            if (h == 0) {
-                s_own = sj;
-                r_own = rj;
+            if (h < TILE_OWN) {
+                s_own[h] = sj;
+                r_own[h] = rj;
             }
             const T z = f.dv[h] * rj * c0;
             Zl[t] = z;
@@ -983,46 +994,47 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
         Uz = dst;
     }
     // own rows: u' = z, w' = K u', the recurrences and the reductions
-    if (static_cast<int>(threadIdx.x) < nt[0]) {
-        const int32_t j = f.g[0];
-        const T u1 = zz[0];
-        const T wn = tile_row(f, 0, Uz);
-        gst(const_cast<T *>(vec_of<T>(D, 0)) + wr * n)[j] = r_own;
+#pragma unroll
+    for (int h = 0; h < TILE_OWN; ++h) {
+        if (static_cast<int>(threadIdx.x) + h * BLOCK >= nt[0]) continue;
+        const int32_t j = f.g[h];
+        const T u1 = zz[h];
+        const T wn = tile_row(f, h, Uz);
+        gst(const_cast<T *>(vec_of<T>(D, 0)) + wr * n)[j] = r_own[h];
         gst(const_cast<T *>(vec_of<T>(D, 1)) + wr * n)[j] = wn;
-        gst(const_cast<T *>(vec_of<T>(D, 2)) + wr * n)[j] = s_own;
+        gst(const_cast<T *>(vec_of<T>(D, 2)) + wr * n)[j] = s_own[h];
         if constexpr (sizeof(T) == 4)
             gst(D.u32)[j] = u1;
         else
             gst(D.u)[j] = u1;
         if (!start) {
-            const T pj = (rs ? f.ou : f.ou + be * f.op) - zm;
+            const T pj = (rs ? f.ou[h] : f.ou[h] + be * f.op[h]) - zm[h];
             gst(const_cast<T *>(vec_of<T>(D, 4)))[j] = pj;
             if constexpr (sizeof(T) == 4)
-                gst(D.c32)[j] = f.ox + al * pj;
+                gst(D.c32)[j] = f.ox[h] + al * pj;
             else
-                gst(D.x)[j] = f.ox + al * pj;
+                gst(D.x)[j] = f.ox[h] + al * pj;
         } else if constexpr (sizeof(T) == 4) {
             // mixed: fold the correction the residual stage saw (f.ox = c) into x; the next
             // correction starts with the coarse step (deflation) or at zero
-            gst(D.x)[j] = gld(D.x)[j] + static_cast<double>(f.ox);
-            gst(D.c32)[j] = zm;
+            gst(D.x)[j] = gld(D.x)[j] + static_cast<double>(f.ox[h]);
+            gst(D.c32)[j] = zm[h];
         } else if (defl) {
-            gst(D.x)[j] = f.ox + zm;   // fp64: the coarse correction of x
+            gst(D.x)[j] = f.ox[h] + zm[h];   // fp64: the coarse correction of x
         }
-        const double r64 = static_cast<double>(r_own), u64 = static_cast<double>(u1);
+        const double r64 = static_cast<double>(r_own[h]), u64 = static_cast<double>(u1);
         v[0] += r64 * u64;
         v[1] += static_cast<double>(wn) * u64;
-        v[2] += u64 * static_cast<double>(s_own);
+        v[2] += u64 * static_cast<double>(s_own[h]);
         v[3] += r64 * r64;
-        if (defl && code > 0) v[NRED + code - 1] += static_cast<double>(wn);
+        if (defl && code[h] > 0) v[NRED + code[h] - 1] += static_cast<double>(wn);
     }
 }
 
 // The residual stage of a deflated solve, over the tile's own rows (so that the fifth
 // partial is the tile's aggregate sum Z^T r): r = b - K x in fp64 from the CSR matrix.
-__device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &B, int32_t own, int code,
-                                bool mixed, int par, double (&v)[NPART]) {
-    if (static_cast<int>(threadIdx.x) >= B.nt[0]) return;
+__device__ inline void tile_res_row(const Ctl &c, const InstDesc &D, int32_t own, int code, bool mixed, int par,
+                                    double (&v)[NPART]) {
     const int64_t n = D.n;
     const int wr = par, rd = par ^ 1;
     const CGP_GLOBAL int32_t *rowptr = gld(D.rowptr), *col = gld(D.col);
@@ -1047,6 +1059,14 @@ __device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &
     v[0] += ri * ri;
     if (c.first) v[1] += bi * bi;
     if (code > 0) v[NRED + code - 1] += ri;
+}
+
+template <class T, int W>
+__device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &B, const TilePrefetch<T, W> &f,
+                                const int32_t (&code)[TILE_OWN], bool mixed, int par, double (&v)[NPART]) {
+#pragma unroll
+    for (int h = 0; h < TILE_OWN; ++h)
+        if (static_cast<int>(threadIdx.x) + h * BLOCK < B.nt[0]) tile_res_row(c, D, f.g[h], code[h], mixed, par, v);
 }
 
 // fp32: at most 128 VGPRs, so that two workgroups share a compute unit and a grid of
@@ -1077,7 +1097,8 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     T *kzm = reinterpret_cast<T *>(sh.lds) + 3 * TILE_REGION;
     df.kr = -1;
     df.mu0 = df.mu1 = T(0);
-    df.code = 0;
+#pragma unroll
+    for (int h = 0; h < TILE_OWN; ++h) df.code[h] = 0;
     if (defl) {
         defl_prefetch<T>(df, D, B, lb);
 #pragma unroll
@@ -1101,10 +1122,12 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
             }
             __syncthreads();
         }
-        const T zm = df.code == 1 ? df.mu0 : (df.code == 2 ? df.mu1 : T(0));
+        T zm[TILE_OWN];
+#pragma unroll
+        for (int h = 0; h < TILE_OWN; ++h) zm[h] = df.code[h] == 1 ? df.mu0 : (df.code[h] == 2 ? df.mu1 : T(0));
         tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), kzm, defl, zm, df.code, v);
     } else if (c.state == ST_RES && defl) {
-        tile_res(c, D, B, static_cast<int>(threadIdx.x) < B.nt[0] ? f.g[0] : -1, df.code, sizeof(T) == 4, par, v);
+        tile_res<T, W>(c, D, B, f, df.code, sizeof(T) == 4, par, v);
     } else {
         const SolveParams prm = *prm_dev;
         const RowRange R = ranges[D.blk0 + lb];

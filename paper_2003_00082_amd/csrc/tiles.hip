@@ -79,7 +79,7 @@ bool build_tiles(int64_t n, int parts, int degree, int width, const std::vector<
     size_t b0 = 0;
     for (int p = 0; p < parts; ++p) {
         const size_t b1 = cuts[p];
-        if (b1 - b0 > static_cast<size_t>(TILE_ROWS)) return false;
+        if (b1 - b0 > static_cast<size_t>(TILE_ROWS_MAX)) return false;
         TileBlk &B = blk[p];
         B.reg_off = static_cast<int32_t>(reg.size());
         B.ell_off = static_cast<int32_t>(eval.size() / width);
@@ -191,8 +191,13 @@ TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
         std::vector<int32_t> reg;
         std::vector<uint16_t> ecol;
         std::vector<double> eval;
-        // more, smaller tiles until every region fits (tiles of at least 64 rows)
+        // tiles of up to TILE_ROWS rows (one own row per thread); a mesh that needs more than
+        // TILE_GRID of them takes TILE_GRID larger ones while they fit a workgroup (a grid
+        // just above the compute-unit count would run a few compute units two workgroups
+        // deep); then more, smaller tiles until every region fits (at least 64 rows)
         int parts = static_cast<int>((n + TILE_ROWS - 1) / TILE_ROWS);
+        if (parts > TILE_GRID)
+            parts = std::max(TILE_GRID, static_cast<int>((n + TILE_ROWS_MAX - 1) / TILE_ROWS_MAX));
         const int max_parts = static_cast<int>((n + 63) / 64);
         bool ok = false;
         while (!ok && parts <= max_parts) {

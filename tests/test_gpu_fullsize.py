@@ -10,6 +10,10 @@
   linear field and the force of a linear potential in closed form at every fine
   node, and a batch of 8 solves checked by the true fp64 residual the oracle
   recomputes (properties that hold at any size).
+* 513x257 deflated at the benchmark's degree 6: the mesh needs more than 256 tiles of
+  512 rows, so it is cut into 256 tiles of about 515 (threads holding two own rows);
+  the fp64 deflated solve against the oracle's deflated PCG on the oracle's own
+  aggregates (iteration counts within two) and SuperLU.
 * The 64-instance batch of uneven meshes: every instance's true residual, and
   four sampled instances against SuperLU.
 """
@@ -17,6 +21,7 @@ import numpy as np
 import pytest
 
 import cgp_inputs as ci
+from oracle import deflation as dfl
 from oracle import fem, mesh, solve
 
 pytestmark = pytest.mark.gpu
@@ -105,6 +110,35 @@ def test_sequence_step_513x257(ctx, cgp):
         ur, vr = fem.velocity_correction(hier.xy[1], hier.tri[1], pf, u, v, 0.01)
         np.testing.assert_allclose(un.cpu().numpy(), ur, rtol=0, atol=1e-12 * (scale + np.abs(u).max()))
         np.testing.assert_allclose(vn.cpu().numpy(), vr, rtol=0, atol=1e-12 * (scale + np.abs(v).max()))
+    finally:
+        ctx.mesh_free(h)
+
+
+def test_deflated_solve_past_the_tile_grid_513x257(ctx, cgp):
+    coarse = ci.jittered_rect(513, 257, 2000)
+    h = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 0)
+    try:
+        a = fem.system_matrix(coarse.xy, coarse.tri, coarse.dirichlet)
+        u, v = ci.stream_velocity(coarse.xy, ci.fourier_modes(31))
+        b = fem.source(coarse.xy, coarse.tri, coarse.dirichlet, u, v, fem.CURL, 1.0)
+        xs = solve.direct(a, b)
+        parts = dfl.aggregates(a, coarse.xy, 6)
+        assert len(parts) == 2 * 256 and max(len(p) for p in parts) > 256   # tiles of more than 512 rows
+        z, e = dfl.deflation_space(a, coarse.dirichlet, parts)
+        xo, info = dfl.dpcg(a, b, z, e, tol=1e-10, degree=6)
+        assert info["status"] == "ok"
+        for precision, tol, err in ((cgp.CGP_FP64, 1e-10, 1e-8), (cgp.CGP_FP32_IR, TOL, 1e-6)):
+            phi = torch.zeros(coarse.n_nodes, dtype=torch.float64, device=DEV)
+            stats = cgp.stats_buffer(1)
+            ctx.poisson_solve([h], [dt(b)], [phi], stats, precision=precision, guess=cgp.CGP_GUESS_ZERO, tol=tol,
+                              precond_degree=6, deflation=1)
+            st = ctx.solve_check(1, stats)[0]
+            assert st["status"] == "ok" and st["rel_res"] <= tol
+            x = phi.cpu().numpy()
+            assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= err
+            if precision == cgp.CGP_FP64:
+                assert abs(st["iters"] - info["iters"]) <= 2, (st, info)
+                assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
     finally:
         ctx.mesh_free(h)
 

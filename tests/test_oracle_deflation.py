@@ -47,6 +47,21 @@ def test_tile_parts_partition_the_rows_within_capacity(degree):
     assert sizes.max() - sizes.min() <= 2
 
 
+def test_a_mesh_past_the_tile_grid_takes_256_larger_tiles():
+    # 513 x 257 = 131841 rows need 258 tiles of 512: the rule takes 256 tiles (one per compute
+    # unit) of up to 1024 rows instead; 509 x 257 = 130813 rows fit 256 tiles of 512
+    for nx, size in ((513, (515, 516)), (509, (510, 511))):
+        m, k = _system(nx, 257, 11)
+        parts = dfl.tile_parts(k, m.xy, 6)
+        assert len(parts) == 256
+        np.testing.assert_array_equal(np.sort(np.concatenate(parts)), np.arange(m.n_nodes))
+        assert {len(p) for p in parts} <= set(size)
+    # a mesh needing more than 256 x 1024 rows starts from ceil(n / 1024) parts
+    m, k = _system(641, 513, 11)
+    parts = dfl.tile_parts(k, m.xy, 2)
+    assert len(parts) == -(-m.n_nodes // 1024) and max(len(p) for p in parts) <= 1024
+
+
 def test_aggregates_halve_every_tile():
     m, k = _system(97, 49, 11)
     tiles = dfl.tile_parts(k, m.xy, 8)
