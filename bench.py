@@ -47,9 +47,9 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "c960b4cd4d1383f9", "profile": "profiles/cg_traffic_513x257.md",
-                    "k_cg_tile<float, 8, true, true> degree 6 deflated": 25.94e6,
-                    "k_cg_tile<double, 8, true, true> degree 6 deflated": 42.80e6}
+MEASURED_TRAFFIC = {"fingerprint": "e640622f0a41703b", "profile": "profiles/cg_traffic_513x257.md",
+                    "k_cg_tile<float, 8, true, true> degree 6 deflated": 25.68e6,
+                    "k_cg_tile<double, 8, true, true> degree 6 deflated": 42.47e6}
 
 
 def kernel_fingerprint() -> str:
@@ -371,7 +371,11 @@ def main():
         "E": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, 0, 0),
         "F": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, deg, 0),
     }
-    tiles = -(-nc // 512)   # tiles of the deflated forms (the first tile count fits this mesh)
+    # tiles of the deflated forms: ceil(n / 512), or 256 of up to 1024 rows past 256 tiles (the
+    # partition's first count, which fits this mesh)
+    tiles = -(-nc // 512)
+    if tiles > 256:
+        tiles = max(256, -(-nc // 1024))
     aggs = 2 * tiles        # deflation aggregates: two per tile
 
     def run(form: str):

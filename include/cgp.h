@@ -71,7 +71,8 @@ enum { CGP_GUESS_ZERO = 0, CGP_GUESS_GIVEN = 1, CGP_GUESS_EXTRAP = 2, CGP_GUESS_
  *               replayed HIP graphs; the call returns once the host has seen every
  *               instance finish (it waits on the device, it does not enqueue only).
  *               Each workgroup owns a compact tile of at most 512 rows (recursive
- *               coordinate bisection) and works on the rows within graph distance
+ *               coordinate bisection; when that takes more than 256 tiles, 256 tiles
+ *               of up to 1024 rows) and works on the rows within graph distance
  *               d of it; meshes whose rows are wider than 12 entries or whose
  *               regions do not fit use STAGED_ROWS instead (Jacobi only)
  *   STAGED_ROWS as STAGED with workgroups owning consecutive row ranges (Jacobi only)
@@ -181,8 +182,8 @@ typedef struct {
                              K z = r from z = 0 (CGP_ENGINE_STAGED only)                */
     int32_t deflation;    /* 0: off.  1: subdomain deflation (an extension): CG runs on the
                              complement of a coarse space Z of aggregates (free-row
-                             indicators; the tiled iteration's tiles of <= 512 rows from
-                             recursive coordinate bisection, each bisected once more: two
+                             indicators; the tiled iteration's tiles from recursive
+                             coordinate bisection, each bisected once more: two
                              aggregates per tile), x0 is corrected so that Z^T r = 0 and each
                              direction is made K-orthogonal to range(Z) (Nicolaides;
                              Saad, Yeung, Erhel, Guyomarc'h).  Needs the tiled iteration
