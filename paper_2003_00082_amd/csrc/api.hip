@@ -600,6 +600,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                             cr.m = AGG_PER_TILE * nb[i];
                             cr.tiles = nb[i];
                             cr.cblk0 = cblk;
+                            cr.ctl = d.ctl;
                             p->crecs.push_back(cr);
                             cblk += d.ncb;
                         }

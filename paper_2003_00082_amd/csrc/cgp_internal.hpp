@@ -318,6 +318,7 @@ struct CoarseRec {               // what the coarse step of one instance touches
     int32_t tiles;               // workgroups of the tiled stage
     int32_t cblk0;               // first coarse workgroup of the instance
     int32_t pad_;
+    const Ctl *ctl;              // the instance's control state, by stage parity
 };
 // h_single: the record of a single-instance solve (passed by value), else the device records
 void launch_cg_coarse(hipStream_t s, const CoarseRec *h_single, const CoarseRec *d_recs, const int32_t *d_cblk_inst,

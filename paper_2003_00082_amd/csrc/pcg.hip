@@ -713,8 +713,8 @@ __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, 
 
 // ------------------------------------------------------------------ driver 1: one stage per launch
 
-// Workgroups are dealt to the eight XCDs round-robin (workgroup v to XCD v % 8), each
-// XCD with its own L2.  The staged kernels renumber an instance's workgroups so that
+// The staged kernels renumber an instance's workgroups with xcd_block, so that every XCD
+// takes a contiguous run of row blocks or tiles.
 // ONE: a single instance, whose record arrives by value in the kernel arguments (one
 // dependent load less on every pointer the stage follows)
 template <class T, int H, bool ONE>
@@ -1148,6 +1148,9 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     constexpr int PER_LANE = MAX_DEFL_AGGREGATES / 64;
     __shared__ double red[COARSE_ROWS];
     __shared__ double qs[MAX_DEFL_AGGREGATES];
+    // a stage that found the instance finished (launches past the end of the solve) has
+    // nothing for the next one; its state was stored by the stage kernel before this launch
+    if (gld(C.ctl)[par].state == ST_DONE) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = C.m, nt = C.tiles;
     const int a = cb * COARSE_ROWS + wave;
