@@ -712,9 +712,14 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             int64_t chunk = 0;
             bool finished = false;
             while (!finished) {
-                if (chunk >= 2) {
-                    // wait for the older chunk in flight (or for the device to report completion)
-                    hipEvent_t old = ctx->chunk_ev[chunk & 1];
+                // two chunks in flight, but none beyond the predicted end before the device has
+                // had the chance to report completion (every launch past the end costs a stage
+                // that finds the solve done)
+                const bool past = predicted > 0 && issued >= predicted;
+                if (chunk >= 2 || (past && chunk >= 1)) {
+                    // wait for the older chunk in flight, or past the prediction for the newest
+                    // (or for the device to report completion)
+                    hipEvent_t old = ctx->chunk_ev[(past ? chunk - 1 : chunk) & 1];
                     for (;;) {
                         if (*flag) {
                             finished = true;
