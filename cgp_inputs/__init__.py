@@ -35,6 +35,7 @@ __all__ = [
     "jittered_rect",
     "rect_with_hole",
     "permuted",
+    "wheel",
     "fourier_modes",
     "stream_velocity",
     "potential_velocity",
@@ -133,6 +134,37 @@ def rect_with_hole(nx: int, ny: int, hole: tuple[int, int, int, int], seed: int 
     new_id = np.cumsum(~inside) - 1
     tri = new_id[tri].astype(np.int32)
     return Mesh(xy[~inside], tri, dirichlet[~inside].astype(np.uint8))
+
+
+def wheel(rings: int, spokes: int, seed: int | None = None, jitter: float = 0.1) -> Mesh:
+    """Polar P1 mesh of the unit disk: a centre node and ``rings`` rings of ``spokes`` nodes.
+
+    The centre is a vertex of ``spokes`` triangles (the other nodes of at most six), so
+    node degrees up to ``spokes`` appear; the outer ring is Dirichlet.  Interior ring
+    nodes move radially by up to ``jitter`` of the ring spacing (the triangles stay CCW).
+    """
+    if rings < 1 or spokes < 3:
+        raise ValueError("need a ring and three spokes")
+    r = np.repeat(np.arange(1, rings + 1), spokes) / rings
+    t = np.tile(np.arange(spokes), rings) * (2.0 * np.pi / spokes)
+    if seed is not None and jitter != 0.0:
+        rng = np.random.default_rng(seed)
+        r = r + np.where(r < 1.0, jitter * rng.uniform(-1.0, 1.0, r.size) / rings, 0.0)
+    xy = np.concatenate([[[0.0, 0.0]], np.stack([r * np.cos(t), r * np.sin(t)], axis=1)])
+    node = lambda ring, j: 1 + ring * spokes + (j % spokes)
+    tri = [(0, node(0, j), node(0, j + 1)) for j in range(spokes)]
+    for ring in range(rings - 1):
+        for j in range(spokes):
+            a, b = node(ring, j), node(ring, j + 1)
+            c, d = node(ring + 1, j + 1), node(ring + 1, j)
+            tri += [(a, c, b), (a, d, c)]
+    tri = np.array(tri, dtype=np.int32)
+    e1 = xy[tri[:, 1]] - xy[tri[:, 0]]
+    e2 = xy[tri[:, 2]] - xy[tri[:, 0]]
+    assert np.all(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0] > 0.0), "wheel triangles must be CCW"
+    dirichlet = np.zeros(xy.shape[0], dtype=np.uint8)
+    dirichlet[1 + (rings - 1) * spokes:] = 1
+    return Mesh(xy, tri, dirichlet)
 
 
 def permuted(mesh: Mesh, seed: int) -> Mesh:

@@ -47,8 +47,8 @@ def ctx(cgp):
 class Seq:
     """Coarse right-hand sides and exact solutions of the phi equation over time steps."""
 
-    def __init__(self, nx, ny, seed, steps):
-        self.m = ci.jittered_rect(nx, ny, seed)
+    def __init__(self, nx, ny, seed, steps, mesh=None):
+        self.m = ci.jittered_rect(nx, ny, seed) if mesh is None else mesh
         m = self.m
         self.a = fem.system_matrix(m.xy, m.tri, m.dirichlet)
         self.mo = gnn.neighbour_mean_operator(gnn.triangle_adjacency(m.n_nodes, m.tri))
@@ -124,16 +124,14 @@ def test_created_models_are_seeded(ctx):
     assert np.all(pa[8 * 64:16 * 64] == 0)
 
 
-@pytest.mark.parametrize("seed", [1, 2])
-def test_predict_matches_oracle(ctx, seq, seed):
-    th = random_theta(seed)
+def _check_predict(ctx, seq, handle, th, steps):
     md = ctx.model_create()
     try:
         ctx.model_set_params(md, th)
-        for n in (2, 17):
+        for n in steps:
             b, p1, p2, _ = seq.sample(n)
             g = torch.full((seq.m.n_nodes,), np.nan, dtype=torch.float64, device=DEV)
-            ctx.model_predict(md, seq.handle, dt(b), dt(p1), dt(p2), g)
+            ctx.model_predict(md, handle, dt(b), dt(p1), dt(p2), g)
             ctx.sync()
             got = g.cpu().numpy()
             x, e, sd = gnn.features(seq.a, seq.m.dirichlet, b, p1, p2)
@@ -151,13 +149,43 @@ def test_predict_matches_oracle(ctx, seq, seed):
         ctx.model_free(md)
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_predict_matches_oracle(ctx, seq, seed):
+    _check_predict(ctx, seq, seq.handle, random_theta(seed), (2, 17))
+
+
+@pytest.mark.parametrize("spokes", [7, 12])
+def test_predict_matches_oracle_on_wider_neighbourhoods(ctx, spokes):
+    # a wheel's centre has `spokes` neighbours: neighbour tables of width 8 (one padding slot
+    # on most rows) and 16 (the general path), against 6 on the structured meshes
+    s = Seq(0, 0, 4300 + spokes, 4, mesh=ci.wheel(30, spokes, 9))
+    h = ctx.mesh_upload(s.m.xy, s.m.tri, s.m.dirichlet, 0)
+    try:
+        _check_predict(ctx, s, h, random_theta(5), (2, 3))
+    finally:
+        ctx.mesh_free(h)
+
+
 def test_grad_matches_oracle(ctx, seq):
+    _check_grad(ctx, seq, seq.handle, 9)
+
+
+def test_grad_matches_oracle_on_a_wheel(ctx):
+    s = Seq(0, 0, 4400, 4, mesh=ci.wheel(30, 12, 10))
+    h = ctx.mesh_upload(s.m.xy, s.m.tri, s.m.dirichlet, 0)
+    try:
+        _check_grad(ctx, s, h, 3)
+    finally:
+        ctx.mesh_free(h)
+
+
+def _check_grad(ctx, seq, handle, step):
     th = random_theta(3)
     md = ctx.model_create()
     try:
         ctx.model_set_params(md, th)
-        b, p1, p2, tgt = seq.sample(9)
-        loss, g = ctx.model_grad(md, seq.handle, dt(b), dt(p1), dt(p2), dt(tgt))
+        b, p1, p2, tgt = seq.sample(step)
+        loss, g = ctx.model_grad(md, handle, dt(b), dt(p1), dt(p2), dt(tgt))
         lref, gref = gnn.loss_and_grad(th.astype(np.float64), seq.a, seq.m.dirichlet, b, p1, p2, tgt, seq.mo,
                                        emulate=True)
         assert loss == pytest.approx(lref, rel=5e-5)
