@@ -664,7 +664,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             if (model)   // the network's guess goes into phi; the solver judges it against prev1
                 for (int i = 0; i < gn; ++i)
                     gnn_predict(ctx->stream, *model, *ms[g0 + i], h_d_b[g0 + i], h_d_prev1[g0 + i],
-                                h_d_prev2[g0 + i], h_d_phi[g0 + i]);
+                                h_d_prev2[g0 + i], h_d_phi[g0 + i], !ctx->capturing);
             if (persistent) {
                 launch_cg_persistent(ctx->stream, plan->d_insts, gn, plan->d_block_inst, plan->d_ranges, plan->grid,
                                      gp, ctx->sync.p, plan->d_done_at, ctx->timeout_ticks);
@@ -874,7 +874,8 @@ cgp_status cgp_model_predict(cgp_ctx ctx, cgp_model model, cgp_mesh mesh, const 
     return guarded([&] {
         use_device(ctx);
         CGP_REQUIRE(d_b && d_prev1 && d_prev2 && d_guess, "null device pointer");
-        gnn_predict(ctx->stream, get_model(ctx, model), get_mesh(ctx, mesh), d_b, d_prev1, d_prev2, d_guess);
+        gnn_predict(ctx->stream, get_model(ctx, model), get_mesh(ctx, mesh), d_b, d_prev1, d_prev2, d_guess,
+                    !ctx->capturing);
     });
 }
 

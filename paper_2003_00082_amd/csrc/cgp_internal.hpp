@@ -349,8 +349,10 @@ int64_t gnn_param_count();
 Model *gnn_create(hipStream_t s, uint64_t seed);   // owned by the caller, freed by gnn_destroy
 void gnn_set_params(hipStream_t s, Model &md, const float *h);
 void gnn_get_params(hipStream_t s, Model &md, float *h);
-void gnn_predict(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
-                 double *guess);
+// guess from the network, then smoothed; build: the smoothing's tiled plan may be built here
+// (a host synchronisation: not under graph capture), else it is used when already built
+void gnn_predict(hipStream_t s, Model &md, Mesh &m, const double *b, const double *p1, const double *p2,
+                 double *guess, bool build);
 void gnn_grad(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
               const double *target, double *h_loss, float *h_grad);
 void gnn_train(hipStream_t s, Model &md, const Mesh &m, int n_samples, const double *const *b,

@@ -464,6 +464,86 @@ __global__ __launch_bounds__(TPB) void k_gnn_smooth(int64_t n, int width, const 
     xout[i] = xin[i] + omega * dinv[i] * (b[i] - kx);
 }
 
+// All SMOOTH_SWEEPS sweeps in one launch: a workgroup per tile of the mesh's tiled
+// partition for distance SMOOTH_SWEEPS holds the guess over the tile's region (the rows
+// within graph distance SMOOTH_SWEEPS, own rows first, then by distance) in LDS; sweep k
+// updates the rows at distance <= SMOOTH_SWEEPS - k from the previous sweep's values of
+// their neighbours (two LDS buffers), so that the own rows end with the values of
+// SMOOTH_SWEEPS global sweeps.  Local matrix rows: the tiles' 16-bit region columns and
+// fp64 values in CSR order (padding: the row itself with value 0), as the ELL sweep sums.
+constexpr int SM_BLOCK = TILE_ROWS;
+template <int W>
+__global__ __launch_bounds__(SM_BLOCK) void k_gnn_smooth_tiles(const TileBlk *blk, const int32_t *reg,
+                                                               const uint16_t *ecol, const double *eval,
+                                                               const double *dinv, const double *b,
+                                                               const double *xin, double *xout, double omega) {
+    constexpr int TH = TILE_REGION / SM_BLOCK, TS = TILE_SPMV / SM_BLOCK, CW = tile_col_stride(W);
+    static_assert(TILE_OWN <= TS && TILE_OWN * SM_BLOCK == TILE_ROWS_MAX, "own rows are local matrix rows");
+    __shared__ double xa[TILE_REGION], xb[TILE_REGION];
+    __shared__ int32_t s_nt[TILE_MAX_DEGREE + 2];
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const TileBlk &B = blk[lb];
+    const int nreg = B.nreg, nspmv = B.nspmv, nown = B.nt[0];
+    if (threadIdx.x < TILE_MAX_DEGREE + 2) s_nt[threadIdx.x] = B.nt[threadIdx.x];
+    int32_t g[TH];
+#pragma unroll
+    for (int h = 0; h < TH; ++h) {
+        const int t = threadIdx.x + h * SM_BLOCK;
+        g[h] = t < nreg ? reg[B.reg_off + t] : -1;
+    }
+    double bb[TS], dd[TS], ev[TS][W];
+    uint16_t ec[TS][W];
+#pragma unroll
+    for (int h = 0; h < TS; ++h) {
+        const int t = threadIdx.x + h * SM_BLOCK;
+        bb[h] = dd[h] = 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            ev[h][q] = 0.0;
+            ec[h][q] = 0;
+        }
+        if (t < nspmv) {
+            const size_t row = static_cast<size_t>(B.ell_off) + t;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                ec[h][q] = ecol[row * CW + q];
+                ev[h][q] = eval[row * W + q];
+            }
+            bb[h] = b[g[h]];
+            dd[h] = dinv[g[h]];
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < TH; ++h) {
+        const int t = threadIdx.x + h * SM_BLOCK;
+        if (t < nreg) xa[t] = xin[g[h]];
+    }
+    __syncthreads();
+    double *src = xa, *dst = xb;
+    for (int k = 1; k <= SMOOTH_SWEEPS; ++k) {
+        const int lim = s_nt[SMOOTH_SWEEPS - k];
+#pragma unroll
+        for (int h = 0; h < TS; ++h) {
+            const int t = threadIdx.x + h * SM_BLOCK;
+            if (t < lim) {
+                double kx = 0.0;
+#pragma unroll
+                for (int q = 0; q < W; ++q) kx += ev[h][q] * src[ec[h][q]];
+                dst[t] = src[t] + omega * dd[h] * (bb[h] - kx);
+            }
+        }
+        __syncthreads();
+        double *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+#pragma unroll
+    for (int h = 0; h < TILE_OWN; ++h) {
+        const int t = threadIdx.x + h * SM_BLOCK;
+        if (t < nown) xout[g[h]] = src[t];
+    }
+}
+
 // ------------------------------------------------------------------ training
 
 // delta = (y - (target - e)/s_d) on free nodes
@@ -734,7 +814,7 @@ GnnWork &work_for(hipStream_t s, Model &md, const Mesh &m, bool training) {
 
 // features + forward; x, a[] and y saved when training; guess written when non-null
 void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *b, const double *p1,
-             const double *p2, double *guess, bool training) {
+             const double *p2, double *guess, bool training, const TilePlan *smooth_plan = nullptr) {
     const int64_t n = m.lv[0].n;
     const unsigned nb = blocks_for(n, TPB);
     hipLaunchKernelGGL(k_gnn_prep, dim3(nb), dim3(TPB), 0, s, n, m.max_row, m.ell_col.p, m.ell_val.p, b, p1, p2,
@@ -780,7 +860,9 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
                 hipLaunchKernelGGL((k_gnn_fwd<1, 0>), dim3(nf), dim3(TPB), 0, s, A);
         } else {
             A.yout = w.y.p;
-            A.guess = guess;
+            // with a tiled plan the raw guess goes to re (no longer needed) and the one-launch
+            // smoothing writes the result into guess
+            A.guess = guess && smooth_plan ? w.re.p : guess;
             if (nbw == NBR_NARROW)
                 hipLaunchKernelGGL((k_gnn_fwd<2, NBR_NARROW>), dim3(nf), dim3(TPB), 0, s, A);
             else if (nbw == NBR_WIDE)
@@ -789,7 +871,18 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
                 hipLaunchKernelGGL((k_gnn_fwd<2, 0>), dim3(nf), dim3(TPB), 0, s, A);
         }
     }
-    // smoothing of the guess, ping-pong through re (no longer needed): an even number of
+    if (guess && smooth_plan) {
+        const TilePlan &P = *smooth_plan;
+        if (P.width == 8)
+            hipLaunchKernelGGL(k_gnn_smooth_tiles<8>, dim3(P.nparts), dim3(SM_BLOCK), 0, s, P.blk.p, P.reg.p, P.ecol.p,
+                               P.eval64.p, m.dinv.p, b, w.re.p, guess, SMOOTH_OMEGA);
+        else
+            hipLaunchKernelGGL(k_gnn_smooth_tiles<12>, dim3(P.nparts), dim3(SM_BLOCK), 0, s, P.blk.p, P.reg.p,
+                               P.ecol.p, P.eval64.p, m.dinv.p, b, w.re.p, guess, SMOOTH_OMEGA);
+        CGP_HIP(hipGetLastError());
+        return;
+    }
+    // else one launch per sweep, ping-pong through re (no longer needed): an even number of
     // sweeps ends in guess
     static_assert(SMOOTH_SWEEPS % 2 == 0, "sweeps must end in the guess buffer");
     for (int q = 0; guess && q < SMOOTH_SWEEPS; ++q) {
@@ -903,10 +996,15 @@ void gnn_get_params(hipStream_t s, Model &md, float *h) {
     CGP_HIP(hipStreamSynchronize(s));
 }
 
-void gnn_predict(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,
-                 double *guess) {
+void gnn_predict(hipStream_t s, Model &md, Mesh &m, const double *b, const double *p1, const double *p2,
+                 double *guess, bool build) {
     GnnWork &w = work_for(s, md, m, false);
-    forward(s, md, m, w, b, p1, p2, guess, false);
+    // the tiled partition for the smoothing's distance (shared with the solver's plans of that
+    // degree), built on first use where that may synchronise the stream
+    const auto &cached = m.tiles[SMOOTH_SWEEPS];
+    const TilePlan *plan = build ? tile_plan(s, m, SMOOTH_SWEEPS)
+                                 : (cached && cached->nparts > 0 ? cached.get() : nullptr);
+    forward(s, md, m, w, b, p1, p2, guess, false, plan);
 }
 
 void gnn_grad(hipStream_t s, Model &md, const Mesh &m, const double *b, const double *p1, const double *p2,

@@ -1148,9 +1148,6 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     constexpr int PER_LANE = MAX_DEFL_AGGREGATES / 64;
     __shared__ double red[COARSE_ROWS];
     __shared__ double qs[MAX_DEFL_AGGREGATES];
-    // a stage that found the instance finished (launches past the end of the solve) has
-    // nothing for the next one; its state was stored by the stage kernel before this launch
-    if (gld(C.ctl)[par].state == ST_DONE) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = C.m, nt = C.tiles;
     const int a = cb * COARSE_ROWS + wave;
@@ -1163,6 +1160,10 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
         const int b = lane + 64 * k;
         e[k] = (a < m && b < m) ? er[b] : 0.0;
     }
+    // a stage that found the instance finished (launches past the end of the solve) has
+    // nothing for the next one; its state was stored by the stage kernel before this launch
+    // (read with the row's loads in flight)
+    if (gld(C.ctl)[par].state == ST_DONE) return;
     // q_a, the partial NRED + (a % 2) of tile a / 2, staged in LDS (coalesced)
     static_assert(AGG_PER_TILE == 2, "aggregate a is half a % 2 of tile a / 2");
     const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * nt + static_cast<size_t>(NRED) * nt;
