@@ -283,9 +283,18 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int rg = l >> 4, c4 = (l & 15) * 4;   // row layout: rows rg + 4k, columns c4..c4+3
     float *Z = Zt[wave];
     const int64_t n = A.n, ntiles = (n + 31) / 32, ngroups = (ntiles + FWD_WAVES - 1) / FWD_WAVES;
+    const double sd = MODE == 2 ? A.scales[3] : 0.0;
     for (int64_t g = xcd_block(blockIdx.x, gridDim.x); g < ngroups; g += gridDim.x) {
         const int64_t row0 = (g * FWD_WAVES + wave) * 32, i = row0 + r;
         const bool valid = i < n;
+        // decoder: the row's extrapolation and Dirichlet flag, loaded now so that they arrive
+        // with the layer's first loads
+        double e_row = 0.0;
+        bool dir_row = true;
+        if (MODE == 2 && A.guess && valid && half == 0) {
+            e_row = A.e[i];
+            dir_row = A.dir[i] != 0;
+        }
         // the two 32-column halves of the output accumulate over the k steps in order: the
         // row's own activations (k steps 0..3) before its neighbour mean (4..7)
         f32x16 c[2] = {};
@@ -437,7 +446,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
             if (valid && half == 0) {
                 const float y = ys[wave][r];
                 if (A.yout) A.yout[i] = y;
-                if (A.guess) A.guess[i] = A.dir[i] ? 0.0 : A.e[i] + A.scales[3] * static_cast<double>(y);
+                if (A.guess) A.guess[i] = dir_row ? 0.0 : e_row + sd * static_cast<double>(y);
             }
         }
         wave_lds_sync();   // the tile is written again by the next group
