@@ -11,7 +11,8 @@
  *   cgp_poisson_solve  solve the coarse Poisson system (Eqs. 12, 15);
  *   cgp_prolong        P1 prolongation back to the finest level (Eq. 20);
  *   cgp_lorentz_force  grad(phi_f) and the Lorentz source of Eqs. 13-14;
- *   cgp_velocity_correct  grad(p_f) and the projection of Eqs. 16-17.
+ *   cgp_velocity_correct  grad(p_f) and the projection of Eqs. 16-17;
+ *   cgp_momentum_step  the semi-implicit momentum step of Eqs. 13-14 (fine mesh).
  *
  * Conventions for every call:
  *   - Return value: CGP_OK (0) or a negative cgp_status.  No C++ exception
@@ -275,6 +276,41 @@ cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif,
  * (d_u == d_ut, d_v == d_vt); d_u != d_v and neither is d_pf (CGP_E_INVALID). */
 cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, const double *d_ut,
                                 const double *d_vt, double scale, double *d_u, double *d_v);
+
+/* Step 4 of the CGP algorithm, Eqs. 13-14 (the general scheme Eq. 8): the
+ * intermediate velocity (u~, v~) on the finest level from
+ *   (rho/dt) M w~ + rho C(u^n) w~ + mu K w~ = (rho/dt) M w^n + M f,   w = u, v,
+ * Galerkin P1 (Section 2.3): M the mass matrix, C(u^n)_ij = int psi_i (u^n . grad psi_j)
+ * with u^n interpolated in P1, K the stiffness; f = (d_fx, d_fy), the nodal
+ * Lorentz source (cgp_lorentz_force), interpolated in P1.  The time derivative uses
+ * u^n (Eq. 8).  Dirichlet rows (the mesh's Dirichlet nodes) are identity rows: the
+ * boundary values are the caller's, passed in d_ut / d_vt at those nodes.
+ *   d_un, d_vn, d_fx, d_fy  [N_f] fp64 at the finest level's nodes (read only)
+ *   d_ut, d_vt   [N_f] in: initial guess, with the boundary values at Dirichlet nodes;
+ *                out: the intermediate velocity (updated in place)
+ *   rho, mu, dt  > 0, >= 0, > 0 (finite)
+ *   tol          relative residual ||b - A w|| <= tol ||b|| of each component (> 0)
+ *   max_iter     >= 1
+ *   h_stats      host, optional: per component iterations, status (CGP_SOLVE_*),
+ *                final relative residual of the recurrence
+ * Both components share one matrix and are solved together by Jacobi-preconditioned
+ * BiCGStab (van der Vorst) in fp64, one launch per half-step.  The matrix is
+ * assembled on every call (it depends on u^n); its pattern (the finest level's
+ * adjacency) and the workspace are built on the first call for a mesh.  The call
+ * returns after the solve (it synchronises the context's stream); CGP_E_NOCONV or
+ * CGP_E_BREAKDOWN when a component did not reach tol (its last iterate is in the
+ * output).  Nodes of more than 32 neighbours: CGP_E_UNSUPPORTED.  d_ut and d_vt must
+ * differ from each other and from the inputs (CGP_E_INVALID).  Not capturable. */
+typedef struct {
+    int32_t iters[2];
+    int32_t status[2];
+    double rel_res[2];
+} cgp_momentum_stats;
+
+cgp_status cgp_momentum_step(cgp_ctx ctx, cgp_mesh mesh, const double *d_un, const double *d_vn,
+                             const double *d_fx, const double *d_fy, double rho, double mu, double dt,
+                             double tol, int32_t max_iter, double *d_ut, double *d_vt,
+                             cgp_momentum_stats *h_stats);
 
 /* ------------------------------------------------------------------ learned initial guess */
 

@@ -62,6 +62,10 @@ class SolveStats(ctypes.Structure):
                 ("guess_used", ctypes.c_int32), ("rel_res", ctypes.c_double), ("rel_res_guess", ctypes.c_double)]
 
 
+class MomentumStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32 * 2), ("status", ctypes.c_int32 * 2), ("rel_res", ctypes.c_double * 2)]
+
+
 STATS_BYTES = ctypes.sizeof(SolveStats)   # 32
 _lib = None
 
@@ -92,6 +96,7 @@ _SIGS = {
     "cgp_prolong": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_lorentz_force": ([_vp, _i32, _vp, _vp, _vp, _f64, _f64, _vp, _vp, _vp], _i32),
     "cgp_velocity_correct": ([_vp, _i32, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
+    "cgp_momentum_step": ([_vp, _i32, _vp, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _vp, _vp, _vp], _i32),
     "cgp_model_param_count": ([], _i64),
     "cgp_model_create": ([_vp, ctypes.c_uint64, ctypes.POINTER(_i32)], _i32),
     "cgp_model_free": ([_vp, _i32], _i32),
@@ -244,6 +249,17 @@ class Context:
     def velocity_correct(self, mesh: int, pf, ut, vt, scale: float, u, v):
         _check(load().cgp_velocity_correct(self.handle, mesh, _ptr(pf), _ptr(ut), _ptr(vt), float(scale), _ptr(u),
                                            _ptr(v)))
+
+    def momentum_step(self, mesh: int, un, vn, fx, fy, rho: float, mu: float, dt: float, ut, vt, *,
+                      tol: float = 1e-10, max_iter: int = 500):
+        """The momentum step of Eqs. 13-14 on the finest level; ``ut``/``vt`` carry the initial
+        guess and the boundary values in, the intermediate velocity out.  Returns the per-component
+        statistics (iterations, status, relative residual); synchronises the stream."""
+        st = MomentumStats()
+        _check(load().cgp_momentum_step(self.handle, mesh, _ptr(un), _ptr(vn), _ptr(fx), _ptr(fy), float(rho),
+                                        float(mu), float(dt), float(tol), int(max_iter), _ptr(ut), _ptr(vt),
+                                        ctypes.byref(st)))
+        return {"iters": list(st.iters), "status": list(st.status), "rel_res": list(st.rel_res)}
 
     def poisson_solve(self, meshes, b, phi, stats, *, prev1=None, prev2=None, precision=CGP_FP64,
                       guess=CGP_GUESS_GIVEN, tol=1e-8, refine_delta=0.0, max_iter=0, model=-1, spmv_lanes=0,

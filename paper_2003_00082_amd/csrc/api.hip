@@ -380,6 +380,27 @@ cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, 
     });
 }
 
+cgp_status cgp_momentum_step(cgp_ctx ctx, cgp_mesh mesh, const double *d_un, const double *d_vn,
+                             const double *d_fx, const double *d_fy, double rho, double mu, double dt,
+                             double tol, int32_t max_iter, double *d_ut, double *d_vt,
+                             cgp_momentum_stats *h_stats) {
+    return guarded([&] {
+        use_device(ctx);
+        Mesh &m = get_mesh(ctx, mesh);
+        CGP_REQUIRE(!ctx->capturing, "cgp_momentum_step cannot be captured");
+        CGP_REQUIRE(d_un && d_vn && d_fx && d_fy && d_ut && d_vt, "null device pointer");
+        CGP_REQUIRE(std::isfinite(rho) && rho > 0.0, "rho must be positive");
+        CGP_REQUIRE(std::isfinite(mu) && mu >= 0.0, "mu must be non-negative");
+        CGP_REQUIRE(std::isfinite(dt) && dt > 0.0, "dt must be positive");
+        CGP_REQUIRE(std::isfinite(tol) && tol > 0.0, "tol must be positive");
+        CGP_REQUIRE(max_iter >= 1, "max_iter must be at least 1");
+        CGP_REQUIRE(d_ut != d_vt, "d_ut and d_vt must differ");
+        for (const double *in : {d_un, d_vn, d_fx, d_fy})
+            CGP_REQUIRE(in != d_ut && in != d_vt, "the outputs must not overwrite an input");
+        momentum_step(ctx->stream, m, d_un, d_vn, d_fx, d_fy, rho, mu, dt, tol, max_iter, d_ut, d_vt, h_stats);
+    });
+}
+
 cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_meshes, const double *const *h_d_b,
                              double *const *h_d_phi, const double *const *h_d_prev1,
                              const double *const *h_d_prev2, const cgp_solve_opts *h_opts,

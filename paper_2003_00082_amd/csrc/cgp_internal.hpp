@@ -162,6 +162,18 @@ __device__ inline int xcd_block(int v, int G) {
     return x * q + (x < rm ? x : rm) + k;
 }
 
+// Workspace of the momentum step on the finest level: the adjacency pattern (self
+// included, sorted) with the operator's values, its Jacobi inverse, the two right-hand
+// sides and the BiCGStab vectors of both components ([2][n] each; p and v by parity).
+struct MomentumWork {
+    int64_t n = 0, nnz = 0;
+    DBuf<int32_t> ptr, col;
+    DBuf<double> val, dinv, b, r, rh, p, v, s, t;
+    DBuf<double> part;       // per-workgroup partial sums of the three half-steps
+    DBuf<double> scal;       // recurrence scalars and norms
+    DBuf<int32_t> state;     // per component: status, iterations
+};
+
 constexpr int NBR_NARROW = 6;   // neighbour-table width of a regular triangulation
 constexpr int NBR_WIDE = 8;
 
@@ -190,6 +202,7 @@ struct Mesh {
     double gershgorin = 0.0;           // max_i sum_j |K_ij| / K_ii (0 = not computed)
     std::unique_ptr<TilePlan> tiles[TILE_MAX_DEGREE + 1];   // per preconditioner degree
     NodalGrad grad;                     // finest level, built on the first force or correction
+    std::unique_ptr<MomentumWork> mom;  // finest level, built on the first momentum step
 };
 
 // builds (or returns) the tiled plan of a mesh for degree d; nullptr when the
@@ -349,6 +362,14 @@ int64_t gnn_param_count();
 Model *gnn_create(hipStream_t s, uint64_t seed);   // owned by the caller, freed by gnn_destroy
 void gnn_set_params(hipStream_t s, Model &md, const float *h);
 void gnn_get_params(hipStream_t s, Model &md, float *h);
+// the finest level's adjacency (self included, sorted rows)
+void level_adjacency(hipStream_t s, const Level &L, DBuf<int32_t> &adj_ptr, DBuf<int32_t> &adj_col,
+                     int64_t &adj_nnz);
+// the momentum step of Eqs. 13-14 on the finest level (synchronises the stream)
+void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, const double *fx,
+                   const double *fy, double rho, double mu, double dt, double tol, int max_iter, double *ut,
+                   double *vt, cgp_momentum_stats *stats);
+
 // guess from the network, then smoothed; build: the smoothing's tiled plan may be built here
 // (a host synchronisation: not under graph capture), else it is used when already built
 void gnn_predict(hipStream_t s, Model &md, Mesh &m, const double *b, const double *p1, const double *p2,

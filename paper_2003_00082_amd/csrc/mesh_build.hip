@@ -459,6 +459,11 @@ void build_adjacency(hipStream_t s, const Level &L, DBuf<int32_t> &adj_ptr, DBuf
 
 }  // namespace
 
+void level_adjacency(hipStream_t s, const Level &L, DBuf<int32_t> &adj_ptr, DBuf<int32_t> &adj_col,
+                     int64_t &adj_nnz) {
+    build_adjacency(s, L, adj_ptr, adj_col, adj_nnz);
+}
+
 int64_t exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t n) {
     scan_rec(s, in, out, n);
     return read_i32(s, out + n);

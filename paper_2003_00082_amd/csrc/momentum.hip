@@ -1,0 +1,476 @@
+// The semi-implicit momentum step of the CGP algorithm (step 4, Eqs. 13-14; the general
+// scheme Eq. 8) on the finest level, Galerkin P1 (Section 2.3): for w = u and w = v
+//
+//   A w~ = b,  A = (rho/dt) M + rho C(u^n) + mu K,  b = (rho/dt) M w^n + M f,
+//
+// M_ij = int psi_i psi_j, C_ij = int psi_i (u^n . grad psi_j) (u^n in P1), K the
+// stiffness; Dirichlet rows are identity rows with the caller's boundary values.
+//
+// The operator is assembled row by row (one thread per row: the incident triangles in
+// ascending id order, no atomics) into the finest level's adjacency pattern, together
+// with both right-hand sides.  Both components share it and are solved together by
+// Jacobi-preconditioned BiCGStab (van der Vorst) in fp64: a thread applies each matrix
+// row it reads to both components.  An iteration is three launches,
+//   H1  p' = r + beta (p - omega v), v' = A D^-1 p'         partials  rh.v'
+//   H2  s = r - alpha v', t = A D^-1 s                        partials  t.s, t.t
+//   H3  x += alpha D^-1 p' + omega D^-1 s, r' = s - omega t   partials  rh.r', r'.r'
+// where the preconditioned vectors of the neighbours are formed on the fly from the
+// previous launch's vectors (so no launch waits on another's row updates), and every
+// workgroup derives the scalars it needs from the previous launch's per-workgroup
+// partials in a fixed order (no floating-point atomics: bitwise reproducible).  The
+// grid is one workgroup per compute unit, each over a contiguous block of rows.
+#include <cmath>
+
+#include "cgp_internal.hpp"
+
+namespace cgp {
+
+namespace {
+
+constexpr int MB = 512;          // threads per workgroup
+constexpr int MG = 256;          // workgroups of the BiCGStab launches
+constexpr int MAX_ROW = 33;      // a node and at most 32 neighbours
+constexpr int MQ = 4;            // partial sums per component and launch
+constexpr int CHECK_EVERY = 8;   // iterations between the host's looks at the status
+
+// scalar slots per component (scal[c * NS + ...]); slots indexed by parity hold the
+// values of iteration it at it & 1
+enum { S_BB = 0, S_RHO = 1, S_ALPHA = 3, S_OMEGA = 5, S_RR = 7, NS = 8 };
+// state per component: status (-1 running, else CGP_SOLVE_*), iterations
+enum { ST_STATUS = 0, ST_ITERS = 1, NSTATE = 2 };
+
+// one thread per row: the operator row and both right-hand sides
+__global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, const int32_t *ptr, const int32_t *col,
+                                                      const int32_t *ne_ptr, const int32_t *ne_idx,
+                                                      const int32_t *tri, const double *xy, const uint8_t *dir,
+                                                      const double *un, const double *vn, const double *fx,
+                                                      const double *fy, const double *gu, const double *gv,
+                                                      double rho, double mu, double dt, double *val, double *dinv,
+                                                      double *b) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t p0 = ptr[i], p1 = ptr[i + 1];
+    int32_t pd = p0;
+    for (int32_t k = p0; k < p1; ++k) {
+        val[k] = 0.0;
+        if (col[k] == i) pd = k;
+    }
+    if (dir[i]) {
+        val[pd] = 1.0;
+        dinv[i] = 1.0;
+        b[i] = gu[i];
+        b[n + i] = gv[i];
+        return;
+    }
+    const double rdt = rho / dt;
+    double bu = 0.0, bv = 0.0;
+    for (int32_t q = ne_ptr[i]; q < ne_ptr[i + 1]; ++q) {
+        const int64_t e = ne_idx[q];
+        const int32_t v3[3] = {tri[3 * e], tri[3 * e + 1], tri[3 * e + 2]};
+        const int li = v3[0] == i ? 0 : (v3[1] == i ? 1 : 2);
+        const double xa = xy[2 * v3[0]], ya = xy[2 * v3[0] + 1];
+        const double xb = xy[2 * v3[1]], yb = xy[2 * v3[1] + 1];
+        const double xc = xy[2 * v3[2]], yc = xy[2 * v3[2] + 1];
+        const double twice = (xb - xa) * (yc - ya) - (xc - xa) * (yb - ya);
+        const double area = 0.5 * twice;
+        const double gx[3] = {(yb - yc) / twice, (yc - ya) / twice, (ya - yb) / twice};
+        const double gy[3] = {(xc - xb) / twice, (xa - xc) / twice, (xb - xa) / twice};
+        // int psi_i psi_k = A (1 + delta_ik) / 12: the advecting velocity's weight in row i
+        const double ax = area / 12.0 * (un[v3[0]] + un[v3[1]] + un[v3[2]] + un[i]);
+        const double ay = area / 12.0 * (vn[v3[0]] + vn[v3[1]] + vn[v3[2]] + vn[i]);
+        for (int lj = 0; lj < 3; ++lj) {
+            const int32_t j = v3[lj];
+            const double mij = area * (lj == li ? 2.0 : 1.0) / 12.0;
+            const double a = rdt * mij + rho * (ax * gx[lj] + ay * gy[lj]) +
+                             mu * area * (gx[li] * gx[lj] + gy[li] * gy[lj]);
+            int32_t k = p0;
+            while (k < p1 - 1 && col[k] != j) ++k;   // j is in the row: a vertex of a triangle of node i
+            val[k] += a;
+            bu += mij * (rdt * un[j] + fx[j]);
+            bv += mij * (rdt * vn[j] + fy[j]);
+        }
+    }
+    dinv[i] = 1.0 / val[pd];
+    b[i] = bu;
+    b[n + i] = bv;
+}
+
+// the workgroup's partial sums (q values per component) in a fixed order, to
+// part[(c * MQ + q) * MG + block]
+__device__ inline void block_partials(const double (&v)[2][MQ], double *part, int blk) {
+    __shared__ double red[MB / 64][2][MQ];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < MQ; ++q) {
+            double x = v[c][q];
+            for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+            if (lane == 0) red[wave][c][q] = x;
+        }
+    __syncthreads();
+    if (threadIdx.x < 2 * MQ) {
+        const int c = threadIdx.x / MQ, q = threadIdx.x % MQ;
+        double t = 0.0;
+        for (int w = 0; w < MB / 64; ++w) t += red[w][c][q];
+        part[(c * MQ + q) * MG + blk] = t;
+    }
+}
+
+// the sums of a launch's partials (every workgroup, the same fixed order): sums[c][q]
+__device__ inline void reduce_partials(const double *part, double (*sums)[MQ]) {
+    __shared__ double red[2 * MQ];
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+#pragma unroll
+        for (int cq = 0; cq < 2 * MQ; ++cq) {
+            double x = 0.0;
+            for (int k = lane; k < MG; k += 64) x += part[cq * MG + k];
+            for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+            if (lane == 0) red[cq] = x;
+        }
+    }
+    __syncthreads();
+    for (int cq = 0; cq < 2 * MQ; ++cq) sums[cq / MQ][cq % MQ] = red[cq];
+}
+
+struct Rows {
+    int64_t r0, r1;
+};
+__device__ inline Rows block_rows(int64_t n) {
+    const int64_t per = (n + MG - 1) / MG;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * per;
+    return {r0, r0 + per < n ? r0 + per : n};
+}
+
+struct Vecs {
+    int64_t n;
+    const int32_t *ptr, *col;
+    const double *val, *dinv, *b;
+    double *x[2];
+    double *r, *rh, *p, *v, *s, *t;   // [2][n]; p and v: [2 parities][2][n]
+    double *part1, *part2, *part3;
+    double *scal;
+    int32_t *state;
+    double tol;
+    int max_iter;
+};
+
+// H0: r = b - A x, rh = r, p = v = 0 (parity 0); partials rh.r, r.r, b.b
+__global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
+    const Rows R = block_rows(V.n);
+    double acc[2][MQ] = {};
+    const int64_t n = V.n;
+    for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
+        double ax0 = 0.0, ax1 = 0.0;
+        for (int32_t k = V.ptr[i]; k < V.ptr[i + 1]; ++k) {
+            const int32_t j = V.col[k];
+            ax0 += V.val[k] * V.x[0][j];
+            ax1 += V.val[k] * V.x[1][j];
+        }
+        const double rr[2] = {V.b[i] - ax0, V.b[n + i] - ax1};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            V.r[c * n + i] = rr[c];
+            V.rh[c * n + i] = rr[c];
+            V.p[c * n + i] = 0.0;
+            V.v[c * n + i] = 0.0;
+            acc[c][0] += rr[c] * rr[c];
+            acc[c][1] += rr[c] * rr[c];
+            acc[c][2] += V.b[c * n + i] * V.b[c * n + i];
+        }
+    }
+    block_partials(acc, V.part3, blockIdx.x);
+}
+
+// H1 of iteration it >= 1 (reads H3's partials of it - 1, or H0's)
+__global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
+    __shared__ double sums[2][MQ];
+    __shared__ double beta_s[2], omega_s[2];
+    __shared__ int run_s[2], zero_s[2];
+    reduce_partials(V.part3, sums);
+    const int rd = (it - 1) & 1, wr = it & 1;
+    if (threadIdx.x < 2) {
+        const int c = threadIdx.x;
+        double *sc = V.scal + c * NS;
+        int32_t *st = V.state + c * NSTATE;
+        int run = st[ST_STATUS] < 0, zero = 0;
+        double beta = 0.0, omega = 0.0;
+        if (run) {
+            const double rho = sums[c][0], rr = sums[c][1];
+            const double bb = it == 1 ? sums[c][2] : sc[S_BB];
+            int status = -1;
+            if (bb == 0.0) {
+                status = CGP_SOLVE_OK;   // b = 0: the solution is 0
+                zero = 1;
+            } else if (!(rr <= V.tol * V.tol * bb)) {
+                if (it > V.max_iter) status = CGP_SOLVE_NOCONV;
+                else if (it > 1) {
+                    const double rho0 = sc[S_RHO + rd], alpha = sc[S_ALPHA + rd];
+                    omega = sc[S_OMEGA + rd];
+                    beta = (rho / rho0) * (alpha / omega);
+                    if (!std::isfinite(beta) || rho == 0.0) status = CGP_SOLVE_BREAKDOWN;
+                }
+            } else {
+                status = CGP_SOLVE_OK;
+            }
+            if (blockIdx.x == 0) {
+                if (it == 1) sc[S_BB] = bb;
+                sc[S_RHO + wr] = rho;
+                sc[S_RR] = rr;
+                if (status >= 0) {
+                    st[ST_STATUS] = status;
+                    st[ST_ITERS] = it - 1;
+                }
+            }
+            run = status < 0;
+        }
+        run_s[c] = run;
+        zero_s[c] = zero;
+        beta_s[c] = beta;
+        omega_s[c] = omega;
+    }
+    __syncthreads();
+    const Rows R = block_rows(V.n);
+    const int64_t n = V.n;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+        if (zero_s[c])
+            for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) V.x[c][i] = 0.0;
+    const double *pr = V.p + rd * 2 * n, *vr = V.v + rd * 2 * n;
+    double *pw = V.p + wr * 2 * n, *vw = V.v + wr * 2 * n;
+    const double be[2] = {beta_s[0], beta_s[1]}, om[2] = {omega_s[0], omega_s[1]};
+    const bool run[2] = {run_s[0] != 0, run_s[1] != 0};
+    double acc[2][MQ] = {};
+    if (run[0] || run[1]) {
+        for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
+            double y[2] = {0.0, 0.0};
+            for (int32_t k = V.ptr[i]; k < V.ptr[i + 1]; ++k) {
+                const int32_t j = V.col[k];
+                const double a = V.val[k] * V.dinv[j];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (run[c])
+                        y[c] += a * (V.r[c * n + j] + be[c] * (pr[c * n + j] - om[c] * vr[c * n + j]));
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (!run[c]) continue;
+                pw[c * n + i] = V.r[c * n + i] + be[c] * (pr[c * n + i] - om[c] * vr[c * n + i]);
+                vw[c * n + i] = y[c];
+                acc[c][0] += V.rh[c * n + i] * y[c];
+            }
+        }
+    }
+    block_partials(acc, V.part1, blockIdx.x);
+}
+
+// H2 of iteration it (reads H1's partials)
+__global__ __launch_bounds__(MB) void k_mom_h2(Vecs V, int it) {
+    __shared__ double sums[2][MQ];
+    __shared__ double alpha_s[2];
+    __shared__ int run_s[2];
+    reduce_partials(V.part1, sums);
+    const int wr = it & 1;
+    if (threadIdx.x < 2) {
+        const int c = threadIdx.x;
+        double *sc = V.scal + c * NS;
+        int32_t *st = V.state + c * NSTATE;
+        int run = st[ST_STATUS] < 0;
+        double alpha = 0.0;
+        if (run) {
+            alpha = sc[S_RHO + wr] / sums[c][0];
+            if (!std::isfinite(alpha)) {
+                run = 0;
+                if (blockIdx.x == 0) {
+                    st[ST_STATUS] = CGP_SOLVE_BREAKDOWN;
+                    st[ST_ITERS] = it - 1;
+                }
+            } else if (blockIdx.x == 0) {
+                sc[S_ALPHA + wr] = alpha;
+            }
+        }
+        run_s[c] = run;
+        alpha_s[c] = alpha;
+    }
+    __syncthreads();
+    const Rows R = block_rows(V.n);
+    const int64_t n = V.n;
+    const double *vw = V.v + wr * 2 * n;
+    const double al[2] = {alpha_s[0], alpha_s[1]};
+    const bool run[2] = {run_s[0] != 0, run_s[1] != 0};
+    double acc[2][MQ] = {};
+    if (run[0] || run[1]) {
+        for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
+            double t[2] = {0.0, 0.0};
+            for (int32_t k = V.ptr[i]; k < V.ptr[i + 1]; ++k) {
+                const int32_t j = V.col[k];
+                const double a = V.val[k] * V.dinv[j];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (run[c]) t[c] += a * (V.r[c * n + j] - al[c] * vw[c * n + j]);
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (!run[c]) continue;
+                const double si = V.r[c * n + i] - al[c] * vw[c * n + i];
+                V.s[c * n + i] = si;
+                V.t[c * n + i] = t[c];
+                acc[c][0] += t[c] * si;
+                acc[c][1] += t[c] * t[c];
+            }
+        }
+    }
+    block_partials(acc, V.part2, blockIdx.x);
+}
+
+// H3 of iteration it (reads H2's partials)
+__global__ __launch_bounds__(MB) void k_mom_h3(Vecs V, int it) {
+    __shared__ double sums[2][MQ];
+    __shared__ double alpha_s[2], omega_s[2];
+    __shared__ int run_s[2];
+    reduce_partials(V.part2, sums);
+    const int wr = it & 1;
+    if (threadIdx.x < 2) {
+        const int c = threadIdx.x;
+        double *sc = V.scal + c * NS;
+        const int run = V.state[c * NSTATE + ST_STATUS] < 0;
+        // t = 0 (s = 0 or a singular operator): omega = 0, r' = s; the next H1 stops the solve
+        const double tt = sums[c][1];
+        const double omega = run && tt != 0.0 ? sums[c][0] / tt : 0.0;
+        if (run && blockIdx.x == 0) sc[S_OMEGA + wr] = omega;
+        run_s[c] = run;
+        omega_s[c] = omega;
+        alpha_s[c] = run ? sc[S_ALPHA + wr] : 0.0;
+    }
+    __syncthreads();
+    const Rows R = block_rows(V.n);
+    const int64_t n = V.n;
+    const double *pw = V.p + wr * 2 * n;
+    const double al[2] = {alpha_s[0], alpha_s[1]}, om[2] = {omega_s[0], omega_s[1]};
+    const bool run[2] = {run_s[0] != 0, run_s[1] != 0};
+    double acc[2][MQ] = {};
+    if (run[0] || run[1]) {
+        for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
+            const double di = V.dinv[i];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (!run[c]) continue;
+                const double si = V.s[c * n + i], ri = si - om[c] * V.t[c * n + i];
+                V.x[c][i] += al[c] * di * pw[c * n + i] + om[c] * di * si;
+                V.r[c * n + i] = ri;
+                acc[c][0] += V.rh[c * n + i] * ri;
+                acc[c][1] += ri * ri;
+            }
+        }
+    }
+    block_partials(acc, V.part3, blockIdx.x);
+}
+
+__global__ void k_mom_reset(int32_t *state) {
+    if (threadIdx.x < 2) {
+        state[threadIdx.x * NSTATE + ST_STATUS] = -1;
+        state[threadIdx.x * NSTATE + ST_ITERS] = 0;
+    }
+}
+
+MomentumWork &momentum_work(hipStream_t s, Mesh &m) {
+    Level &L = m.lv[m.k];
+    if (!m.mom) {
+        auto w = std::make_unique<MomentumWork>();
+        w->n = L.n;
+        level_adjacency(s, L, w->ptr, w->col, w->nnz);
+        std::vector<int32_t> hp(L.n + 1);
+        CGP_HIP(hipMemcpyAsync(hp.data(), w->ptr.p, (L.n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CGP_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < L.n; ++i)
+            if (hp[i + 1] - hp[i] > MAX_ROW) throw Error{CGP_E_UNSUPPORTED, "a node has more than 32 neighbours"};
+        const size_t n = static_cast<size_t>(L.n);
+        w->val.alloc(w->nnz);
+        w->dinv.alloc(n);
+        w->b.alloc(2 * n);
+        w->r.alloc(2 * n);
+        w->rh.alloc(2 * n);
+        w->p.alloc(4 * n);
+        w->v.alloc(4 * n);
+        w->s.alloc(2 * n);
+        w->t.alloc(2 * n);
+        w->part.alloc(3 * 2 * MQ * MG);
+        w->scal.alloc(2 * NS);
+        w->state.alloc(2 * NSTATE);
+        m.mom = std::move(w);
+    }
+    return *m.mom;
+}
+
+}  // namespace
+
+void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, const double *fx,
+                   const double *fy, double rho, double mu, double dt, double tol, int max_iter, double *ut,
+                   double *vt, cgp_momentum_stats *stats) {
+    Level &L = m.lv[m.k];
+    MomentumWork &w = momentum_work(s, m);
+    const int64_t n = L.n;
+    hipLaunchKernelGGL(k_mom_assemble, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.ptr.p, w.col.p, L.ne_ptr.p,
+                       L.ne_idx.p, L.tri.p, L.xy.p, L.dir.p, un, vn, fx, fy, ut, vt, rho, mu, dt, w.val.p, w.dinv.p,
+                       w.b.p);
+    Vecs V{};
+    V.n = n;
+    V.ptr = w.ptr.p;
+    V.col = w.col.p;
+    V.val = w.val.p;
+    V.dinv = w.dinv.p;
+    V.b = w.b.p;
+    V.x[0] = ut;
+    V.x[1] = vt;
+    V.r = w.r.p;
+    V.rh = w.rh.p;
+    V.p = w.p.p;
+    V.v = w.v.p;
+    V.s = w.s.p;
+    V.t = w.t.p;
+    V.part1 = w.part.p;
+    V.part2 = w.part.p + 2 * MQ * MG;
+    V.part3 = w.part.p + 4 * MQ * MG;
+    V.scal = w.scal.p;
+    V.state = w.state.p;
+    V.tol = tol;
+    V.max_iter = max_iter;
+    hipLaunchKernelGGL(k_mom_reset, dim3(1), dim3(64), 0, s, w.state.p);
+    hipLaunchKernelGGL(k_mom_start, dim3(MG), dim3(MB), 0, s, V);
+    CGP_HIP(hipGetLastError());
+    int32_t hs[2 * NSTATE] = {-1, 0, -1, 0};
+    // H1 of iteration max_iter + 1 only records the outcome; the host looks at the status
+    // every CHECK_EVERY iterations (the kernels of a finished component do nothing)
+    for (int it = 1; it <= max_iter + 1; ++it) {
+        hipLaunchKernelGGL(k_mom_h1, dim3(MG), dim3(MB), 0, s, V, it);
+        if (it <= max_iter) {
+            hipLaunchKernelGGL(k_mom_h2, dim3(MG), dim3(MB), 0, s, V, it);
+            hipLaunchKernelGGL(k_mom_h3, dim3(MG), dim3(MB), 0, s, V, it);
+        }
+        CGP_HIP(hipGetLastError());
+        if (it % CHECK_EVERY == 0 || it == max_iter + 1) {
+            CGP_HIP(hipMemcpyAsync(hs, w.state.p, sizeof(hs), hipMemcpyDeviceToHost, s));
+            CGP_HIP(hipStreamSynchronize(s));
+            if (hs[ST_STATUS] >= 0 && hs[NSTATE + ST_STATUS] >= 0) break;
+        }
+    }
+    double sc[2 * NS];
+    CGP_HIP(hipMemcpyAsync(sc, w.scal.p, sizeof(sc), hipMemcpyDeviceToHost, s));
+    CGP_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        for (int c = 0; c < 2; ++c) {
+            stats->iters[c] = hs[c * NSTATE + ST_ITERS];
+            stats->status[c] = hs[c * NSTATE + ST_STATUS] < 0 ? CGP_SOLVE_ABORTED : hs[c * NSTATE + ST_STATUS];
+            const double bb = sc[c * NS + S_BB], rr = sc[c * NS + S_RR];
+            stats->rel_res[c] = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        }
+    }
+    for (int c = 0; c < 2; ++c) {
+        if (hs[c * NSTATE + ST_STATUS] == CGP_SOLVE_NOCONV) throw Error{CGP_E_NOCONV, "momentum step did not converge"};
+        if (hs[c * NSTATE + ST_STATUS] == CGP_SOLVE_BREAKDOWN) throw Error{CGP_E_BREAKDOWN, "momentum step broke down"};
+        if (hs[c * NSTATE + ST_STATUS] < 0) throw Error{CGP_E_ABORTED, "momentum step did not finish"};
+    }
+}
+
+}  // namespace cgp

@@ -46,3 +46,6 @@ def test_struct_layouts_match_the_header():
     import paper_2003_00082_amd as cgp
     assert ctypes.sizeof(cgp.SolveStats) == 32
     assert ctypes.sizeof(cgp.SolveOpts) == 56
+    # cgp_momentum_stats: int32 iters[2], int32 status[2], double rel_res[2]
+    assert ctypes.sizeof(cgp.MomentumStats) == 32
+    assert cgp.MomentumStats.rel_res.offset == 16
