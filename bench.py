@@ -80,8 +80,11 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=200, help="steps solved (fp64) to train the networks")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch"],
-                    help="sequence: one 513x257 CGP sequence (default); batch: 64-instance Stuart sweep")
+    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "momentum"],
+                    help="sequence: one 513x257 CGP sequence (default); batch: 64-instance Stuart sweep; "
+                         "momentum: the fine-mesh momentum step of Eqs. 13-14")
+    ap.add_argument("--mu", type=float, default=0.01, help="momentum: dynamic viscosity (rho = 1)")
+    ap.add_argument("--mom-tol", type=float, default=1e-8, help="momentum: relative residual of each component")
     ap.add_argument("--instances", type=int, default=64, help="batch: number of instances")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -285,6 +288,108 @@ def batch_main(args):
     ctx.close()
 
 
+def momentum_bytes(n: int, nnz: int, iters: int) -> float:
+    """Algorithmic HBM bytes of one momentum step (both components, fp64): the assembly
+    (reads the mesh's incidence, coordinates and the four input fields, writes the matrix
+    values, D^-1 and both right-hand sides: ~12 nnz + 104 n with the pattern read once) and
+    per BiCGStab iteration three launches, each reading the matrix once for both
+    components: H1 12 nnz + 104 n (reads D^-1, r, p, v, rh; writes p, v), H2 12 nnz + 72 n
+    (reads D^-1, r, v; writes s, t), H3 120 n (reads D^-1, s, t, p, x, rh; writes x, r);
+    the start (residual) 12 nnz + 88 n."""
+    return float(12 * nnz + 104 * n + 12 * nnz + 88 * n + iters * (24 * nnz + 296 * n))
+
+
+def momentum_main(args):
+    """The momentum step of Eqs. 13-14 on the 1025x513 fine mesh of the sequence workload
+    (525825 nodes): the operator (rho/dt) M + rho C(u^n) + mu K assembled from the step's
+    velocity and both components solved by BiCGStab to --mom-tol, one call per step on a
+    drifting Fourier flow whose Lorentz source comes from the library's force kernel."""
+    import numpy as np
+    import torch
+
+    import cgp_inputs as ci
+    import paper_2003_00082_amd as cgp
+
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    nx, ny = args.nx, args.ny
+    coarse = ci.jittered_rect(nx, ny, 2000)
+    ctx = cgp.Context(0)
+    h = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+    fine_xy = ctx.mesh_download(h, 1)[0]
+    nf = fine_xy.shape[0]
+    rho, mu, dt, tol = 1.0, args.mu, ci.DT, args.mom_tol
+    seq = ci.FourierSequence(fine_xy, ci.fourier_modes(2500), ci.fourier_modes(2700))
+    W, K = args.warmup, args.steps
+    xyd = torch.from_numpy(fine_xy).to(dev)
+    phif = torch.sin(2.0 * xyd[:, 0]) * torch.cos(3.0 * xyd[:, 1])
+    steps = {}
+    for n in range(-W, K):
+        u, v, _, _ = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in seq.at(n))
+        fx, fy = torch.empty(nf, **f64), torch.empty(nf, **f64)
+        ctx.lorentz_force(h, phif, u, v, args.stuart, 1.0, fx, fy)
+        steps[n] = (u, v, fx, fy)
+    ctx.sync()
+    info = ctx.mesh_info(h, 1)
+    nnz_f = None
+
+    def one(n):
+        u, v, fx, fy = steps[n]
+        ut, vt = u.clone(), v.clone()      # boundary values of u^n, u^n as the initial guess
+        return ctx.momentum_step(h, u, v, fx, fy, rho, mu, dt, ut, vt, tol=tol, max_iter=5000)
+
+    for n in range(-W, 0):
+        one(n)
+    torch.cuda.synchronize()
+    its, ok = [], True
+    t0 = time.perf_counter()
+    for n in range(K):
+        st = one(n)
+        its.append(max(st["iters"]))
+        ok = ok and st["status"] == [0, 0] and max(st["rel_res"]) <= tol
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # the fine level's matrix pattern: the adjacency (self included) of a refined triangulation
+    nnz_f = nf + 2 * (info["n_nodes"] + info["n_tris"] - 1)   # Euler: E = N + T - 1 edges, one hole-free domain
+    nbytes = sum(momentum_bytes(nf, nnz_f, it) for it in its)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import momentum as mom
+        from oracle import mesh as omesh
+        hier = omesh.Hierarchy(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+        u, v, fx, fy = (t.cpu().numpy() for t in steps[0])
+        t1 = time.perf_counter()
+        mom.step(hier.xy[1], hier.tri[1], hier.dirichlet[1], u, v, fx, fy, rho, mu, dt)
+        sec = time.perf_counter() - t1
+        cpu = {"value": 1.0 / sec, "unit": "momentum steps/s", "cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"step 0: assembly and sparse LU of the operator, both components ({sec:.1f} s)"}
+    out = {
+        "metric": "momentum steps/s (Eqs. 13-14, both components to the tolerance)",
+        "value": K / elapsed,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"momentum step on the fine mesh of the {nx}x{ny} coarse mesh refined once "
+                               f"({nf} nodes), rho 1, mu {mu:g}, dt {dt:g}, BiCGStab to {tol:g}",
+                   "fine_nodes": nf, "nnz": nnz_f},
+        "mean_iters": float(np.mean(its)), "max_iters": int(np.max(its)), "all_converged": ok,
+        "roofline": {"bound": "hbm", "achieved": nbytes / elapsed / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": nbytes / elapsed / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "note": "algorithmic bytes of the assembly and all iterations / whole step time (host "
+                             "status checks every 8 iterations included)"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -295,6 +400,12 @@ def main():
         if args.steps == 200:
             args.steps = 6
         return batch_main(args)
+    if args.workload == "momentum":
+        if args.steps == 200:
+            args.steps = 20
+        if args.warmup == 10:
+            args.warmup = 2
+        return momentum_main(args)
     import numpy as np
     import torch
 

@@ -163,11 +163,14 @@ __device__ inline int xcd_block(int v, int G) {
 }
 
 // Workspace of the momentum step on the finest level: the adjacency pattern (self
-// included, sorted) with the operator's values, its Jacobi inverse, the two right-hand
-// sides and the BiCGStab vectors of both components ([2][n] each; p and v by parity).
+// included, sorted; CSR and a column-major ELL copy) with the operator's values (ELL),
+// its Jacobi inverse, the two right-hand sides and the BiCGStab vectors of both
+// components ([n][2] each, interleaved; p and v by parity).
 struct MomentumWork {
     int64_t n = 0, nnz = 0;
-    DBuf<int32_t> ptr, col;
+    int32_t width = 0;       // the longest row: the width of the column-major ELL copy
+    DBuf<int32_t> ptr, col;  // CSR pattern (built once)
+    DBuf<int32_t> ecol;      // ELL columns: entry k of row i at k * n + i (padding: i)
     DBuf<double> val, dinv, b, r, rh, p, v, s, t;
     DBuf<double> part;       // per-workgroup partial sums of the three half-steps
     DBuf<double> scal;       // recurrence scalars and norms

@@ -7,8 +7,10 @@
 // stiffness; Dirichlet rows are identity rows with the caller's boundary values.
 //
 // The operator is assembled row by row (one thread per row: the incident triangles in
-// ascending id order, no atomics) into the finest level's adjacency pattern, together
-// with both right-hand sides.  Both components share it and are solved together by
+// ascending id order, no atomics) into a column-major ELL copy of the finest level's
+// adjacency pattern (entry k of row i at k * n + i, width = the longest row, padding: the
+// row itself with value 0, so that a wavefront reads entry k of 64 consecutive rows with
+// one coalesced load), together with both right-hand sides.  Both components share it and are solved together by
 // Jacobi-preconditioned BiCGStab (van der Vorst) in fp64: a thread applies each matrix
 // row it reads to both components.  An iteration is three launches,
 //   H1  p' = r + beta (p - omega v), v' = A D^-1 p'         partials  rh.v'
@@ -19,6 +21,7 @@
 // workgroup derives the scalars it needs from the previous launch's per-workgroup
 // partials in a fixed order (no floating-point atomics: bitwise reproducible).  The
 // grid is one workgroup per compute unit, each over a contiguous block of rows.
+#include <algorithm>
 #include <cmath>
 
 #include "cgp_internal.hpp"
@@ -40,7 +43,7 @@ enum { S_BB = 0, S_RHO = 1, S_ALPHA = 3, S_OMEGA = 5, S_RR = 7, NS = 8 };
 enum { ST_STATUS = 0, ST_ITERS = 1, NSTATE = 2 };
 
 // one thread per row: the operator row and both right-hand sides
-__global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, const int32_t *ptr, const int32_t *col,
+__global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, const int32_t *ecol,
                                                       const int32_t *ne_ptr, const int32_t *ne_idx,
                                                       const int32_t *tri, const double *xy, const uint8_t *dir,
                                                       const double *un, const double *vn, const double *fx,
@@ -49,17 +52,17 @@ __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, const int32_t *
                                                       double *b) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int32_t p0 = ptr[i], p1 = ptr[i + 1];
-    int32_t pd = p0;
-    for (int32_t k = p0; k < p1; ++k) {
-        val[k] = 0.0;
-        if (col[k] == i) pd = k;
+    int64_t pd = i;   // the diagonal entry (the first entry whose column is the row)
+    for (int k = width - 1; k >= 0; --k) {
+        const int64_t o = static_cast<int64_t>(k) * n + i;
+        val[o] = 0.0;
+        if (ecol[o] == i) pd = o;
     }
     if (dir[i]) {
         val[pd] = 1.0;
         dinv[i] = 1.0;
-        b[i] = gu[i];
-        b[n + i] = gv[i];
+        b[2 * i] = gu[i];
+        b[2 * i + 1] = gv[i];
         return;
     }
     const double rdt = rho / dt;
@@ -83,16 +86,16 @@ __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, const int32_t *
             const double mij = area * (lj == li ? 2.0 : 1.0) / 12.0;
             const double a = rdt * mij + rho * (ax * gx[lj] + ay * gy[lj]) +
                              mu * area * (gx[li] * gx[lj] + gy[li] * gy[lj]);
-            int32_t k = p0;
-            while (k < p1 - 1 && col[k] != j) ++k;   // j is in the row: a vertex of a triangle of node i
-            val[k] += a;
+            int k = 0;   // j is in the row (a vertex of a triangle of node i); padding comes last
+            while (k < width - 1 && ecol[static_cast<int64_t>(k) * n + i] != j) ++k;
+            val[static_cast<int64_t>(k) * n + i] += a;
             bu += mij * (rdt * un[j] + fx[j]);
             bv += mij * (rdt * vn[j] + fy[j]);
         }
     }
     dinv[i] = 1.0 / val[pd];
-    b[i] = bu;
-    b[n + i] = bv;
+    b[2 * i] = bu;
+    b[2 * i + 1] = bv;
 }
 
 // the workgroup's partial sums (q values per component) in a fixed order, to
@@ -134,6 +137,9 @@ __device__ inline void reduce_partials(const double *part, double (*sums)[MQ]) {
     for (int cq = 0; cq < 2 * MQ; ++cq) sums[cq / MQ][cq % MQ] = red[cq];
 }
 
+// both components of row j of an interleaved [n][2] vector
+__device__ inline double2 ld2(const double *v, int64_t j) { return reinterpret_cast<const double2 *>(v)[j]; }
+
 struct Rows {
     int64_t r0, r1;
 };
@@ -143,12 +149,21 @@ __device__ inline Rows block_rows(int64_t n) {
     return {r0, r0 + per < n ? r0 + per : n};
 }
 
+// column-major ELL copy of the CSR pattern (padding: the row itself)
+__global__ void k_mom_ell(int64_t n, int width, const int32_t *ptr, const int32_t *col, int32_t *ecol) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t p0 = ptr[i], len = ptr[i + 1] - p0;
+    for (int k = 0; k < width; ++k) ecol[static_cast<int64_t>(k) * n + i] = k < len ? col[p0 + k] : static_cast<int32_t>(i);
+}
+
 struct Vecs {
     int64_t n;
-    const int32_t *ptr, *col;
+    int width;
+    const int32_t *col;   // ELL: entry k of row i at k * n + i
     const double *val, *dinv, *b;
     double *x[2];
-    double *r, *rh, *p, *v, *s, *t;   // [2][n]; p and v: [2 parities][2][n]
+    double *r, *rh, *p, *v, *s, *t;   // [n][2] (the components interleaved); p and v: [2 parities][n][2]
     double *part1, *part2, *part3;
     double *scal;
     int32_t *state;
@@ -163,21 +178,22 @@ __global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
     const int64_t n = V.n;
     for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
         double ax0 = 0.0, ax1 = 0.0;
-        for (int32_t k = V.ptr[i]; k < V.ptr[i + 1]; ++k) {
-            const int32_t j = V.col[k];
-            ax0 += V.val[k] * V.x[0][j];
-            ax1 += V.val[k] * V.x[1][j];
+        for (int k = 0; k < V.width; ++k) {
+            const int64_t o = static_cast<int64_t>(k) * n + i;
+            const int32_t j = V.col[o];
+            ax0 += V.val[o] * V.x[0][j];
+            ax1 += V.val[o] * V.x[1][j];
         }
-        const double rr[2] = {V.b[i] - ax0, V.b[n + i] - ax1};
+        const double rr[2] = {V.b[2 * i] - ax0, V.b[2 * i + 1] - ax1};
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            V.r[c * n + i] = rr[c];
-            V.rh[c * n + i] = rr[c];
-            V.p[c * n + i] = 0.0;
-            V.v[c * n + i] = 0.0;
+            V.r[2 * i + c] = rr[c];
+            V.rh[2 * i + c] = rr[c];
+            V.p[2 * i + c] = 0.0;
+            V.v[2 * i + c] = 0.0;
             acc[c][0] += rr[c] * rr[c];
             acc[c][1] += rr[c] * rr[c];
-            acc[c][2] += V.b[c * n + i] * V.b[c * n + i];
+            acc[c][2] += V.b[2 * i + c] * V.b[2 * i + c];
         }
     }
     block_partials(acc, V.part3, blockIdx.x);
@@ -245,20 +261,21 @@ __global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
     if (run[0] || run[1]) {
         for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
             double y[2] = {0.0, 0.0};
-            for (int32_t k = V.ptr[i]; k < V.ptr[i + 1]; ++k) {
-                const int32_t j = V.col[k];
-                const double a = V.val[k] * V.dinv[j];
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    if (run[c])
-                        y[c] += a * (V.r[c * n + j] + be[c] * (pr[c * n + j] - om[c] * vr[c * n + j]));
+            for (int k = 0; k < V.width; ++k) {
+                const int64_t o = static_cast<int64_t>(k) * n + i;
+                const int32_t j = V.col[o];
+                const double a = V.val[o] * V.dinv[j];
+                // both components of a neighbour in one 16-byte load per vector
+                const double2 rj = ld2(V.r, j), pj = ld2(pr, j), vj = ld2(vr, j);
+                y[0] += a * (rj.x + be[0] * (pj.x - om[0] * vj.x));
+                y[1] += a * (rj.y + be[1] * (pj.y - om[1] * vj.y));
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!run[c]) continue;
-                pw[c * n + i] = V.r[c * n + i] + be[c] * (pr[c * n + i] - om[c] * vr[c * n + i]);
-                vw[c * n + i] = y[c];
-                acc[c][0] += V.rh[c * n + i] * y[c];
+                pw[2 * i + c] = V.r[2 * i + c] + be[c] * (pr[2 * i + c] - om[c] * vr[2 * i + c]);
+                vw[2 * i + c] = y[c];
+                acc[c][0] += V.rh[2 * i + c] * y[c];
             }
         }
     }
@@ -303,19 +320,20 @@ __global__ __launch_bounds__(MB) void k_mom_h2(Vecs V, int it) {
     if (run[0] || run[1]) {
         for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
             double t[2] = {0.0, 0.0};
-            for (int32_t k = V.ptr[i]; k < V.ptr[i + 1]; ++k) {
-                const int32_t j = V.col[k];
-                const double a = V.val[k] * V.dinv[j];
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    if (run[c]) t[c] += a * (V.r[c * n + j] - al[c] * vw[c * n + j]);
+            for (int k = 0; k < V.width; ++k) {
+                const int64_t o = static_cast<int64_t>(k) * n + i;
+                const int32_t j = V.col[o];
+                const double a = V.val[o] * V.dinv[j];
+                const double2 rj = ld2(V.r, j), vj = ld2(vw, j);
+                t[0] += a * (rj.x - al[0] * vj.x);
+                t[1] += a * (rj.y - al[1] * vj.y);
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!run[c]) continue;
-                const double si = V.r[c * n + i] - al[c] * vw[c * n + i];
-                V.s[c * n + i] = si;
-                V.t[c * n + i] = t[c];
+                const double si = V.r[2 * i + c] - al[c] * vw[2 * i + c];
+                V.s[2 * i + c] = si;
+                V.t[2 * i + c] = t[c];
                 acc[c][0] += t[c] * si;
                 acc[c][1] += t[c] * t[c];
             }
@@ -356,10 +374,10 @@ __global__ __launch_bounds__(MB) void k_mom_h3(Vecs V, int it) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!run[c]) continue;
-                const double si = V.s[c * n + i], ri = si - om[c] * V.t[c * n + i];
-                V.x[c][i] += al[c] * di * pw[c * n + i] + om[c] * di * si;
-                V.r[c * n + i] = ri;
-                acc[c][0] += V.rh[c * n + i] * ri;
+                const double si = V.s[2 * i + c], ri = si - om[c] * V.t[2 * i + c];
+                V.x[c][i] += al[c] * di * pw[2 * i + c] + om[c] * di * si;
+                V.r[2 * i + c] = ri;
+                acc[c][0] += V.rh[2 * i + c] * ri;
                 acc[c][1] += ri * ri;
             }
         }
@@ -383,10 +401,16 @@ MomentumWork &momentum_work(hipStream_t s, Mesh &m) {
         std::vector<int32_t> hp(L.n + 1);
         CGP_HIP(hipMemcpyAsync(hp.data(), w->ptr.p, (L.n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         CGP_HIP(hipStreamSynchronize(s));
-        for (int64_t i = 0; i < L.n; ++i)
-            if (hp[i + 1] - hp[i] > MAX_ROW) throw Error{CGP_E_UNSUPPORTED, "a node has more than 32 neighbours"};
+        int width = 1;
+        for (int64_t i = 0; i < L.n; ++i) width = std::max(width, hp[i + 1] - hp[i]);
+        if (width > MAX_ROW) throw Error{CGP_E_UNSUPPORTED, "a node has more than 32 neighbours"};
         const size_t n = static_cast<size_t>(L.n);
-        w->val.alloc(w->nnz);
+        w->width = width;
+        w->ecol.alloc(static_cast<size_t>(width) * n);
+        hipLaunchKernelGGL(k_mom_ell, dim3(blocks_for(L.n, 256)), dim3(256), 0, s, L.n, width, w->ptr.p, w->col.p,
+                           w->ecol.p);
+        CGP_HIP(hipGetLastError());
+        w->val.alloc(static_cast<size_t>(width) * n);
         w->dinv.alloc(n);
         w->b.alloc(2 * n);
         w->r.alloc(2 * n);
@@ -411,13 +435,13 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
     Level &L = m.lv[m.k];
     MomentumWork &w = momentum_work(s, m);
     const int64_t n = L.n;
-    hipLaunchKernelGGL(k_mom_assemble, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.ptr.p, w.col.p, L.ne_ptr.p,
+    hipLaunchKernelGGL(k_mom_assemble, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.width, w.ecol.p, L.ne_ptr.p,
                        L.ne_idx.p, L.tri.p, L.xy.p, L.dir.p, un, vn, fx, fy, ut, vt, rho, mu, dt, w.val.p, w.dinv.p,
                        w.b.p);
     Vecs V{};
     V.n = n;
-    V.ptr = w.ptr.p;
-    V.col = w.col.p;
+    V.width = w.width;
+    V.col = w.ecol.p;
     V.val = w.val.p;
     V.dinv = w.dinv.p;
     V.b = w.b.p;
