@@ -169,6 +169,7 @@ __device__ inline int xcd_block(int v, int G) {
 struct MomentumWork {
     int64_t n = 0, nnz = 0;
     int32_t width = 0;       // the longest row: the width of the column-major ELL copy
+    int32_t last_iters = 0;  // BiCGStab iterations of the previous call (0: none yet)
     DBuf<int32_t> ptr, col;  // CSR pattern (built once)
     DBuf<int32_t> ecol;      // ELL columns: entry k of row i at k * n + i (padding: i)
     DBuf<double> val, dinv, b, r, rh, p, v, s, t;

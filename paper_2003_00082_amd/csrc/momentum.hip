@@ -34,7 +34,8 @@ constexpr int MB = 512;          // threads per workgroup
 constexpr int MG = 256;          // workgroups of the BiCGStab launches
 constexpr int MAX_ROW = 33;      // a node and at most 32 neighbours
 constexpr int MQ = 4;            // partial sums per component and launch
-constexpr int CHECK_EVERY = 8;   // iterations between the host's looks at the status
+constexpr int CHECK_EVERY = 4;   // iterations between the host's looks at the status near the
+                                 // predicted end (the previous call's count), 32 before it
 
 // scalar slots per component (scal[c * NS + ...]); slots indexed by parity hold the
 // values of iteration it at it & 1
@@ -465,7 +466,8 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
     CGP_HIP(hipGetLastError());
     int32_t hs[2 * NSTATE] = {-1, 0, -1, 0};
     // H1 of iteration max_iter + 1 only records the outcome; the host looks at the status
-    // every CHECK_EVERY iterations (the kernels of a finished component do nothing)
+    // every 32 iterations, and every CHECK_EVERY from shortly before the iteration count of
+    // the previous call (the kernels of a finished component do nothing)
     for (int it = 1; it <= max_iter + 1; ++it) {
         hipLaunchKernelGGL(k_mom_h1, dim3(MG), dim3(MB), 0, s, V, it);
         if (it <= max_iter) {
@@ -473,12 +475,14 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
             hipLaunchKernelGGL(k_mom_h3, dim3(MG), dim3(MB), 0, s, V, it);
         }
         CGP_HIP(hipGetLastError());
-        if (it % CHECK_EVERY == 0 || it == max_iter + 1) {
+        const bool near = it + CHECK_EVERY > w.last_iters;
+        if ((near ? it % CHECK_EVERY : it % 32) == 0 || it == max_iter + 1) {
             CGP_HIP(hipMemcpyAsync(hs, w.state.p, sizeof(hs), hipMemcpyDeviceToHost, s));
             CGP_HIP(hipStreamSynchronize(s));
             if (hs[ST_STATUS] >= 0 && hs[NSTATE + ST_STATUS] >= 0) break;
         }
     }
+    w.last_iters = std::max(hs[ST_ITERS], hs[NSTATE + ST_ITERS]);
     double sc[2 * NS];
     CGP_HIP(hipMemcpyAsync(sc, w.scal.p, sizeof(sc), hipMemcpyDeviceToHost, s));
     CGP_HIP(hipStreamSynchronize(s));
