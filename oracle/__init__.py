@@ -18,7 +18,9 @@ incompressible MHD flow simulations", arXiv 2003.00082):
 * ``oracle.gnn``    the learned initial-guess network, forward and analytic
                     backward in fp64 with bf16 rounding emulated;
 * ``oracle.momentum``  the semi-implicit momentum step of Eqs. 13-14 on the fine
-                    mesh (P1 mass, convection and viscous operators, direct solve).
+                    mesh (P1 mass, convection and viscous operators, direct solve);
+* ``oracle.locate`` P1 interpolation at arbitrary points by brute-force point
+                    location (the general, non-nested restriction of Section 2.3).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP path.

@@ -45,7 +45,7 @@ def meshes_for_bitexact():
 
 
 @pytest.mark.parametrize("name", list(meshes_for_bitexact()))
-@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_hierarchy_is_bit_exact(ctx, name, k):
     m = meshes_for_bitexact()[name]
     h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, k)
@@ -131,7 +131,27 @@ def test_restrict_matches_oracle(ctx, cgp, c1):
         np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("k", [1, 2])
+def test_restrict_from_the_fourth_level(ctx, cgp):
+    # k = 3 (four nested levels, the paper's deepest coarsening): injection from level 3
+    m = ci.jittered_rect(17, 9, 91)
+    h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 3)
+    ref = mesh.Hierarchy(m.xy, m.tri, m.dirichlet, 3)
+    try:
+        nc, nf = m.n_nodes, ref.n_nodes(3)
+        rng = np.random.default_rng(9)
+        u, v = rng.standard_normal(nf), rng.standard_normal(nf)
+        b, uc, vc = (torch.empty(nc, dtype=torch.float64, device=DEV) for _ in range(3))
+        ctx.restrict(h, dt(u), dt(v), cgp.CGP_SRC_CURL, 1.0, b, uc, vc)
+        ctx.sync()
+        np.testing.assert_array_equal(uc.cpu().numpy(), mesh.restrict_inject(u, nc))
+        np.testing.assert_array_equal(vc.cpu().numpy(), mesh.restrict_inject(v, nc))
+        b_ref = fem.source(m.xy, m.tri, m.dirichlet, u[:nc], v[:nc], fem.CURL, 1.0)
+        np.testing.assert_allclose(b.cpu().numpy(), b_ref, rtol=0, atol=1e-12 * np.abs(b_ref).max())
+    finally:
+        ctx.mesh_free(h)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_prolong_is_bit_exact(ctx, k):
     m = ci.jittered_rect(21, 11, 77)
     h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, k)
@@ -146,7 +166,7 @@ def test_prolong_is_bit_exact(ctx, k):
         ctx.mesh_free(h)
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_lorentz_force_matches_oracle(ctx, k):
     m = ci.jittered_rect(21, 11, 78)
     h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, k)
