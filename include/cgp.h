@@ -12,7 +12,8 @@
  *   cgp_prolong        P1 prolongation back to the finest level (Eq. 20);
  *   cgp_lorentz_force  grad(phi_f) and the Lorentz source of Eqs. 13-14;
  *   cgp_velocity_correct  grad(p_f) and the projection of Eqs. 16-17;
- *   cgp_momentum_step  the semi-implicit momentum step of Eqs. 13-14 (fine mesh).
+ *   cgp_momentum_step  the semi-implicit momentum step of Eqs. 13-14 (fine mesh);
+ *   cgp_interpolate    a level's P1 field at arbitrary points (the non-nested restriction).
  *
  * Conventions for every call:
  *   - Return value: CGP_OK (0) or a negative cgp_status.  No C++ exception
@@ -276,6 +277,23 @@ cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif,
  * (d_u == d_ut, d_v == d_vt); d_u != d_v and neither is d_pf (CGP_E_INVALID). */
 cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, const double *d_ut,
                                 const double *d_vt, double scale, double *d_u, double *d_v);
+
+/* The general restriction of Section 2.3, for a coarse mesh that is not nested in the
+ * fine one: the P1 field of a level evaluated at arbitrary points (e.g. the nodes of
+ * another coarse mesh).  Each point is located in a triangle of the level (barycentric
+ * coordinates >= -1e-12; among several, e.g. on an edge, the triangle with the largest
+ * smallest coordinate, the lowest id on a tie) and the field interpolated there.
+ *   level      0..k
+ *   n_pts      >= 0
+ *   d_pts      [2 n_pts] fp64, (x, y) interleaved
+ *   d_field    [N_level] fp64, the level's nodal values
+ *   d_out      [n_pts] fp64: the interpolated values, NaN for a point outside the mesh
+ *   d_tri      [n_pts] int32 or NULL: the containing triangle, -1 outside
+ * The level's point locator (a uniform grid of triangle buckets) is built on the first call
+ * for that level (a host synchronisation; CGP_E_INVALID under graph capture until then).
+ * d_out must not be d_field or d_pts (CGP_E_INVALID). */
+cgp_status cgp_interpolate(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t n_pts, const double *d_pts,
+                           const double *d_field, double *d_out, int32_t *d_tri);
 
 /* Step 4 of the CGP algorithm, Eqs. 13-14 (the general scheme Eq. 8): the
  * intermediate velocity (u~, v~) on the finest level from

@@ -97,6 +97,7 @@ _SIGS = {
     "cgp_lorentz_force": ([_vp, _i32, _vp, _vp, _vp, _f64, _f64, _vp, _vp, _vp], _i32),
     "cgp_velocity_correct": ([_vp, _i32, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
     "cgp_momentum_step": ([_vp, _i32, _vp, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _vp, _vp, _vp], _i32),
+    "cgp_interpolate": ([_vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp], _i32),
     "cgp_model_param_count": ([], _i64),
     "cgp_model_create": ([_vp, ctypes.c_uint64, ctypes.POINTER(_i32)], _i32),
     "cgp_model_free": ([_vp, _i32], _i32),
@@ -249,6 +250,12 @@ class Context:
     def velocity_correct(self, mesh: int, pf, ut, vt, scale: float, u, v):
         _check(load().cgp_velocity_correct(self.handle, mesh, _ptr(pf), _ptr(ut), _ptr(vt), float(scale), _ptr(u),
                                            _ptr(v)))
+
+    def interpolate(self, mesh: int, level: int, pts, field, out, tri=None):
+        """``field`` of ``level`` at the points ``pts`` ([n, 2] fp64 device tensor) into ``out``
+        (NaN outside the mesh); ``tri`` (optional int32 tensor) receives the containing triangles."""
+        _check(load().cgp_interpolate(self.handle, mesh, int(level), int(out.numel()), _ptr(pts), _ptr(field),
+                                      _ptr(out), _ptr(tri) if tri is not None else None))
 
     def momentum_step(self, mesh: int, un, vn, fx, fy, rho: float, mu: float, dt: float, ut, vt, *,
                       tol: float = 1e-10, max_iter: int = 500):

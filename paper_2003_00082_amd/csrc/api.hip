@@ -380,6 +380,21 @@ cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, 
     });
 }
 
+cgp_status cgp_interpolate(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t n_pts, const double *d_pts,
+                           const double *d_field, double *d_out, int32_t *d_tri) {
+    return guarded([&] {
+        use_device(ctx);
+        Mesh &m = get_mesh(ctx, mesh);
+        CGP_REQUIRE(level >= 0 && level <= m.k, "level out of range");
+        CGP_REQUIRE(n_pts >= 0, "n_pts must be non-negative");
+        CGP_REQUIRE(n_pts == 0 || (d_pts && d_field && d_out), "null device pointer");
+        CGP_REQUIRE(n_pts == 0 || (d_out != d_field && static_cast<const void *>(d_out) !=
+                                                             static_cast<const void *>(d_pts)),
+                    "d_out must not overwrite an input");
+        interpolate_points(ctx->stream, m, level, n_pts, d_pts, d_field, d_out, d_tri, !ctx->capturing);
+    });
+}
+
 cgp_status cgp_momentum_step(cgp_ctx ctx, cgp_mesh mesh, const double *d_un, const double *d_vn,
                              const double *d_fx, const double *d_fy, double rho, double mu, double dt,
                              double tol, int32_t max_iter, double *d_ut, double *d_vt,

@@ -178,6 +178,18 @@ struct MomentumWork {
     DBuf<int32_t> state;     // per component: status, iterations
 };
 
+// Point location on one level: a uniform grid of square cells of side h from (x0, y0),
+// gx x gy cells, each listing (CSR) the triangles whose bounding box overlaps it.
+struct Locator {
+    double x0 = 0.0, y0 = 0.0, h = 1.0;
+    int32_t gx = 1, gy = 1;
+    const int32_t *cell_ptr = nullptr, *cell_tri = nullptr;
+};
+struct LocatorData {
+    Locator loc;
+    DBuf<int32_t> cell_ptr, cell_tri;
+};
+
 constexpr int NBR_NARROW = 6;   // neighbour-table width of a regular triangulation
 constexpr int NBR_WIDE = 8;
 
@@ -207,6 +219,7 @@ struct Mesh {
     std::unique_ptr<TilePlan> tiles[TILE_MAX_DEGREE + 1];   // per preconditioner degree
     NodalGrad grad;                     // finest level, built on the first force or correction
     std::unique_ptr<MomentumWork> mom;  // finest level, built on the first momentum step
+    std::vector<std::unique_ptr<LocatorData>> loc;   // per level, built on the first interpolation
 };
 
 // builds (or returns) the tiled plan of a mesh for degree d; nullptr when the
@@ -369,6 +382,11 @@ void gnn_get_params(hipStream_t s, Model &md, float *h);
 // the finest level's adjacency (self included, sorted rows)
 void level_adjacency(hipStream_t s, const Level &L, DBuf<int32_t> &adj_ptr, DBuf<int32_t> &adj_col,
                      int64_t &adj_nnz);
+// a level's P1 field at np points (x, y interleaved): out (NaN outside the mesh) and, when
+// tri_out is not null, the containing triangle (-1 outside); build: the level's locator
+// may be built here (a host synchronisation), else it must exist
+void interpolate_points(hipStream_t s, Mesh &m, int level, int64_t np, const double *pts, const double *field,
+                        double *out, int32_t *tri_out, bool build);
 // the momentum step of Eqs. 13-14 on the finest level (synchronises the stream)
 void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, const double *fx,
                    const double *fy, double rho, double mu, double dt, double tol, int max_iter, double *ut,
