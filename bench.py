@@ -80,9 +80,10 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=200, help="steps solved (fp64) to train the networks")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "momentum"],
+    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "momentum", "interpolate"],
                     help="sequence: one 513x257 CGP sequence (default); batch: 64-instance Stuart sweep; "
-                         "momentum: the fine-mesh momentum step of Eqs. 13-14")
+                         "momentum: the fine-mesh momentum step of Eqs. 13-14; interpolate: the restriction "
+                         "of a fine field onto the nodes of a non-nested coarse mesh by point location")
     ap.add_argument("--mu", type=float, default=0.01, help="momentum: dynamic viscosity (rho = 1)")
     ap.add_argument("--mom-tol", type=float, default=1e-8, help="momentum: relative residual of each component")
     ap.add_argument("--instances", type=int, default=64, help="batch: number of instances")
@@ -383,10 +384,99 @@ def momentum_main(args):
         "roofline": {"bound": "hbm", "achieved": nbytes / elapsed / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": nbytes / elapsed / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "note": "algorithmic bytes of the assembly and all iterations / whole step time (host "
-                             "status checks every 8 iterations included)"},
+                             "status checks included: every 32 iterations, every 4 near the previous step's count)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+    ctx.close()
+
+
+# algorithmic bytes of one located point: its coordinates (16), the value and triangle written
+# (8 + 4), and the containing triangle's three node ids (12), coordinates (48) and field values (24)
+INTERP_BYTES_PER_POINT = 16 + 8 + 4 + 12 + 48 + 24
+
+
+def interpolate_main(args):
+    """The general restriction of Section 2.3 onto a coarse mesh not nested in the fine one: the
+    fine P1 field of the 1025x513 fine level (525825 nodes, 1048576 triangles) evaluated at the
+    131841 nodes of another jittered 513x257 mesh of the same domain, one library call per step
+    (every point located in a fine triangle through the level's bucket grid, built before the
+    timed region)."""
+    import numpy as np
+    import torch
+
+    import cgp_inputs as ci
+    import paper_2003_00082_amd as cgp
+
+    dev = torch.device("cuda:0")
+    nx, ny = args.nx, args.ny
+    coarse = ci.jittered_rect(nx, ny, 2000)
+    target = ci.jittered_rect(nx, ny, 3001)          # same domain, interior nodes jittered apart
+    ctx = cgp.Context(0)
+    stream = ctx.stream
+    h = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+    fine_xy, fine_tri, _, _ = ctx.mesh_download(h, 1)
+    nf, npts = fine_xy.shape[0], target.n_nodes
+    seq = ci.FourierSequence(fine_xy, ci.fourier_modes(2500), ci.fourier_modes(2700))
+    W, K = args.warmup, args.steps
+    fields = [torch.from_numpy(np.ascontiguousarray(seq.at(n)[0])).to(dev) for n in range(min(K + W, 32))]
+    pts = torch.from_numpy(np.ascontiguousarray(target.xy)).to(dev)
+    out = torch.empty(npts, dtype=torch.float64, device=dev)
+    tri = torch.empty(npts, dtype=torch.int32, device=dev)
+    for n in range(W):                                # the first call builds the locator
+        ctx.interpolate(h, 1, pts, fields[n % len(fields)], out, tri)
+    ctx.sync()
+    ok = bool((tri >= 0).all().item())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for n in range(K):
+        ctx.interpolate(h, 1, pts, fields[n % len(fields)], out, tri)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launch_us = 1e3 * e0.elapsed_time(e1) / K
+    nbytes = INTERP_BYTES_PER_POINT * npts
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import locate as oloc
+        sample = np.random.default_rng(5).choice(npts, 100, replace=False)
+        q = fields[(K - 1) % len(fields)].cpu().numpy()
+        t1 = time.perf_counter()
+        val, _ = oloc.interpolate(fine_xy, fine_tri, q, target.xy[sample])
+        sec = time.perf_counter() - t1
+        ok = ok and bool(np.allclose(out.cpu().numpy()[sample], val, rtol=0, atol=1e-12))
+        cpu = {"value": len(sample) / sec, "unit": "points/s", "cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"{len(sample)} of the {npts} points, brute-force location over the {fine_tri.shape[0]} "
+                         f"fine triangles ({sec:.1f} s)"}
+    out_line = {
+        "metric": "points/s located and interpolated (restriction onto a non-nested coarse mesh)",
+        "value": npts * K / elapsed,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"fine field of the {nx}x{ny} coarse mesh refined once ({nf} nodes, "
+                               f"{fine_tri.shape[0]} triangles) at the {npts} nodes of another jittered {nx}x{ny} mesh",
+                   "points": npts, "fine_nodes": nf},
+        "all_inside": ok,
+        "roofline": {"bound": "hbm", "achieved": nbytes / (launch_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": nbytes / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_interpolate", "kernel_avg_us": launch_us,
+                     "algorithmic_bytes_per_launch": nbytes,
+                     "note": f"{INTERP_BYTES_PER_POINT} B per point (coordinates in, value and triangle out, the "
+                             "containing triangle's ids, coordinates and field values); the bucket's other "
+                             "candidate triangles are not counted"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out_line))
     ctx.close()
 
 
@@ -406,6 +496,8 @@ def main():
         if args.warmup == 10:
             args.warmup = 2
         return momentum_main(args)
+    if args.workload == "interpolate":
+        return interpolate_main(args)
     import numpy as np
     import torch
 

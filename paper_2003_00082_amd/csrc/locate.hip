@@ -4,9 +4,9 @@
 //
 // Location: a uniform grid over the level's bounding box, cells of about two triangles'
 // size, each listing the triangles whose bounding box (widened by a relative 1e-9)
-// overlaps it, built once per level on the host (CSR).  One thread per point scans its
-// cell's triangles in ascending id and keeps the one with the largest smallest barycentric
-// coordinate (the first on a tie); the point is inside when that coordinate is >= -1e-12.
+// overlaps it, built once per level on the host (CSR).  A group of lanes per point tests its
+// cell's triangles and keeps the one with the largest smallest barycentric coordinate (the
+// lowest id on a tie); the point is inside when that coordinate is >= -1e-12.
 // A triangle that contains the point overlaps the point's cell, so the scan is exact.
 #include <algorithm>
 #include <cmath>
@@ -20,43 +20,68 @@ namespace {
 constexpr double LOC_EPS = 1e-12;    // tolerance on the barycentric coordinates
 constexpr double BOX_SLACK = 1e-9;   // relative widening of the triangles' boxes when binned
 
-__global__ __launch_bounds__(256) void k_interpolate(int64_t np, const double *pts, const double *xy,
-                                                     const int32_t *tri, Locator L, const double *field,
-                                                     double *out, int32_t *tri_out) {
-    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= np) return;
-    const double px = pts[2 * q], py = pts[2 * q + 1];
+constexpr int LANES = 8;               // lanes per point: each tests every LANES-th candidate
+constexpr int LOC_BLOCK = 256;
+
+// One group of LANES lanes per point.  Each lane keeps its best candidate by the order
+// (smallest barycentric coordinate descending, triangle id ascending); the order is total, so
+// the butterfly over the group gives every lane the same winner as a serial scan would.
+__global__ __launch_bounds__(LOC_BLOCK) void k_interpolate(int64_t np, const double *pts, const double *xy,
+                                                           const int32_t *tri, Locator L, const double *field,
+                                                           double *out, int32_t *tri_out) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * LOC_BLOCK + threadIdx.x;
+    const int64_t q = gid / LANES;
+    const int lane = static_cast<int>(gid % LANES);
+    const bool valid = q < np;
     int32_t best = -1;
-    double bl[3] = {0.0, 0.0, 0.0}, bmin = -INFINITY;
-    const double fx = (px - L.x0) / L.h, fy = (py - L.y0) / L.h;
-    if (fx >= -1.0 && fy >= -1.0 && fx <= L.gx + 1.0 && fy <= L.gy + 1.0) {
-        const int cx = std::min(std::max(static_cast<int>(floor(fx)), 0), L.gx - 1);
-        const int cy = std::min(std::max(static_cast<int>(floor(fy)), 0), L.gy - 1);
-        const int64_t c = static_cast<int64_t>(cy) * L.gx + cx;
-        for (int32_t k = L.cell_ptr[c]; k < L.cell_ptr[c + 1]; ++k) {
-            const int32_t t = L.cell_tri[k];
-            const int32_t a = tri[3 * t], b = tri[3 * t + 1], d = tri[3 * t + 2];
-            const double ax = xy[2 * a], ay = xy[2 * a + 1];
-            const double e1x = xy[2 * b] - ax, e1y = xy[2 * b + 1] - ay;
-            const double e2x = xy[2 * d] - ax, e2y = xy[2 * d + 1] - ay;
-            const double dx = px - ax, dy = py - ay;
-            const double det = e1x * e2y - e1y * e2x;
-            const double l1 = (dx * e2y - dy * e2x) / det, l2 = (e1x * dy - e1y * dx) / det;
-            const double l0 = 1.0 - l1 - l2;
-            const double m = fmin(l0, fmin(l1, l2));
-            if (m > bmin || (m == bmin && t < best)) {
-                bmin = m;
-                best = t;
-                bl[0] = l0;
-                bl[1] = l1;
-                bl[2] = l2;
+    double bl0 = 0.0, bl1 = 0.0, bl2 = 0.0, bmin = -INFINITY;
+    if (valid) {
+        const double px = pts[2 * q], py = pts[2 * q + 1];
+        const double fx = (px - L.x0) / L.h, fy = (py - L.y0) / L.h;
+        if (fx >= -1.0 && fy >= -1.0 && fx <= L.gx + 1.0 && fy <= L.gy + 1.0) {
+            const int cx = std::min(std::max(static_cast<int>(floor(fx)), 0), L.gx - 1);
+            const int cy = std::min(std::max(static_cast<int>(floor(fy)), 0), L.gy - 1);
+            const int64_t c = static_cast<int64_t>(cy) * L.gx + cx;
+            const int32_t end = L.cell_ptr[c + 1];
+            for (int32_t k = L.cell_ptr[c] + lane; k < end; k += LANES) {
+                const int32_t t = L.cell_tri[k];
+                const int32_t a = tri[3 * t], b = tri[3 * t + 1], d = tri[3 * t + 2];
+                const double ax = xy[2 * a], ay = xy[2 * a + 1];
+                const double e1x = xy[2 * b] - ax, e1y = xy[2 * b + 1] - ay;
+                const double e2x = xy[2 * d] - ax, e2y = xy[2 * d + 1] - ay;
+                const double dx = px - ax, dy = py - ay;
+                const double det = e1x * e2y - e1y * e2x;
+                const double l1 = (dx * e2y - dy * e2x) / det, l2 = (e1x * dy - e1y * dx) / det;
+                const double l0 = 1.0 - l1 - l2;
+                const double m = fmin(l0, fmin(l1, l2));
+                if (m > bmin || (m == bmin && t < best)) {
+                    bmin = m;
+                    best = t;
+                    bl0 = l0;
+                    bl1 = l1;
+                    bl2 = l2;
+                }
             }
         }
     }
-    if (best >= 0 && bmin >= -LOC_EPS) {
-        out[q] = bl[0] * field[tri[3 * best]] + bl[1] * field[tri[3 * best + 1]] + bl[2] * field[tri[3 * best + 2]];
+    // every lane of the wave takes part (groups never straddle a wave: LANES divides 64)
+    double wmin = bmin;
+    int32_t wbest = best;
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) {
+        const double om = __shfl_xor(wmin, o, LANES);
+        const int32_t ob = __shfl_xor(wbest, o, LANES);
+        if (ob >= 0 && (wbest < 0 || om > wmin || (om == wmin && ob < wbest))) {
+            wmin = om;
+            wbest = ob;
+        }
+    }
+    if (!valid) return;
+    if (wbest >= 0 && wmin >= -LOC_EPS) {
+        if (best != wbest) return;   // the winner's lane writes (a triangle is listed once per cell)
+        out[q] = bl0 * field[tri[3 * best]] + bl1 * field[tri[3 * best + 1]] + bl2 * field[tri[3 * best + 2]];
         if (tri_out) tri_out[q] = best;
-    } else {
+    } else if (lane == 0) {
         out[q] = NAN;
         if (tri_out) tri_out[q] = -1;
     }
@@ -142,7 +167,7 @@ void interpolate_points(hipStream_t s, Mesh &m, int level, int64_t np, const dou
     }
     if (np == 0) return;
     const Level &L = m.lv[level];
-    hipLaunchKernelGGL(k_interpolate, dim3(blocks_for(np, 256)), dim3(256), 0, s, np, pts, L.xy.p, L.tri.p,
+    hipLaunchKernelGGL(k_interpolate, dim3(blocks_for(np * LANES, LOC_BLOCK)), dim3(LOC_BLOCK), 0, s, np, pts, L.xy.p, L.tri.p,
                        slot->loc, field, out, tri_out);
     CGP_HIP(hipGetLastError());
 }
