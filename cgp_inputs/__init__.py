@@ -25,6 +25,16 @@ Recipes (all RNG = numpy PCG64 via ``numpy.random.default_rng(seed)``):
   ``u = d psi / dy``, ``v = -d psi / dx`` evaluated analytically at given points.
 * ``potential_velocity``: ``grad chi`` for a second mode set (adds a divergent
   part, used for the pressure-equation source).
+* ``cylinder_channel``: the geometry of Section 3 (box [0, 38] x [0, 32], a cylinder of
+  diameter 1 centred at (8, 16)) meshed by a Delaunay triangulation of graded points:
+  ``n_circle`` nodes on the cylinder, rings around it (radial step 0.866 of the local
+  size, alternate rings rotated by half a step), nodes along the box sides at the local
+  size, and seeded dart throwing (PCG64, 3000 consecutive rejections end it) in the
+  rest, a candidate kept when it is at least 0.8 of the local size from every node.
+  Local size h = min(h0 + g r', h_max), h0 = pi d / n_circle, r' = the distance from the
+  cylinder's surface with the downstream distance scaled by ``wake`` (finer in the wake).
+  Triangles with their centroid inside the cylinder are removed.  The defaults give
+  1733 nodes and 3335 triangles, close to the paper's coarsest (k = 3) mesh.
 """
 from __future__ import annotations
 
@@ -42,6 +52,9 @@ __all__ = [
     "FourierSequence",
     "stuart_numbers",
     "batch_sizes",
+    "Channel",
+    "cylinder_channel",
+    "channel_boundary",
     "DT",
 ]
 
@@ -266,3 +279,140 @@ def batch_sizes(count: int, seed: int, mmin: int = 32, mmax: int = 256) -> list[
     rng = np.random.default_rng(seed)
     m = rng.integers(mmin, mmax + 1, size=count)
     return [(int(2 * mi + 1), int(mi + 1)) for mi in m]
+
+
+class Channel(Mesh):
+    """A cylinder-in-channel mesh: ``Mesh`` (``dirichlet`` = the box sides, the far field of
+    the electric potential) plus the geometry and per-node boundary classes (``inflow``,
+    ``outflow``, ``walls``, ``cylinder``, uint8)."""
+
+    def __init__(self, xy, tri, geometry: dict):
+        b = channel_boundary(xy, tri, geometry)
+        super().__init__(xy, tri, (b["inflow"] | b["outflow"] | b["walls"]).astype(np.uint8))
+        self.geometry = dict(geometry)
+        self.inflow, self.outflow, self.walls, self.cylinder = b["inflow"], b["outflow"], b["walls"], b["cylinder"]
+
+
+def channel_boundary(xy: np.ndarray, tri: np.ndarray, geometry: dict) -> dict:
+    """Boundary classes of the nodes of a channel mesh (any level): a node is on the boundary
+    when one of its edges belongs to one triangle; it is inflow (x = 0), outflow (x = L),
+    wall (y = 0 or H) by position, and cylinder otherwise.  Also ``cyl_edges`` [m, 3]:
+    (a, b, triangle) for every boundary edge with both ends on the cylinder."""
+    xy = np.asarray(xy, dtype=np.float64)
+    tri = np.asarray(tri, dtype=np.int64)
+    n = xy.shape[0]
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    owner = np.tile(np.arange(tri.shape[0]), 3)
+    key = np.minimum(e[:, 0], e[:, 1]) * n + np.maximum(e[:, 0], e[:, 1])
+    uniq, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+    bnd = cnt[inv] == 1
+    on = np.zeros(n, dtype=bool)
+    on[e[bnd].ravel()] = True
+    L, H = geometry["L"], geometry["H"]
+    tol = 1e-9 * max(L, H)
+    x, y = xy[:, 0], xy[:, 1]
+    inflow = on & (np.abs(x) <= tol)
+    outflow = on & (np.abs(x - L) <= tol)
+    walls = on & ((np.abs(y) <= tol) | (np.abs(y - H) <= tol))
+    cyl = on & ~inflow & ~outflow & ~walls
+    be = e[bnd]
+    both = cyl[be[:, 0]] & cyl[be[:, 1]]
+    cyl_edges = np.concatenate([be[both], owner[bnd][both][:, None]], axis=1).astype(np.int32)
+    return {"inflow": inflow.astype(np.uint8), "outflow": outflow.astype(np.uint8),
+            "walls": walls.astype(np.uint8), "cylinder": cyl.astype(np.uint8), "cyl_edges": cyl_edges}
+
+
+def cylinder_channel(seed: int = 0, n_circle: int = 40, growth: float = 0.16, h_max: float = 1.6,
+                     wake: float = 0.3, L: float = 38.0, H: float = 32.0, xc: float = 8.0, yc: float = 16.0,
+                     d: float = 1.0) -> Channel:
+    """Graded Delaunay mesh of the box [0, L] x [0, H] minus the disk of diameter d at (xc, yc)."""
+    from scipy.spatial import Delaunay
+
+    r0 = 0.5 * d
+    h0 = 2.0 * np.pi * r0 / n_circle
+
+    def size(x, y):
+        dx = np.where(x > xc, (x - xc) * wake, x - xc)
+        r = np.sqrt(dx * dx + (y - yc) ** 2)
+        return np.minimum(h0 + growth * np.maximum(r - r0, 0.0), h_max)
+
+    th = 2.0 * np.pi * np.arange(n_circle) / n_circle
+    pts = [np.stack([xc + r0 * np.cos(th), yc + r0 * np.sin(th)], axis=1)]
+    r, r_last = r0, r0
+    r_stop = 0.5 * min(xc, L - xc, yc, H - yc)
+    while True:
+        r = r + 0.866 * min(h0 + growth * (r - r0), h_max)
+        if r > r_stop:
+            break
+        n = max(int(round(2.0 * np.pi * r / min(h0 + growth * (r - r0), h_max))), 6)
+        t = 2.0 * np.pi * (np.arange(n) + (0.5 if len(pts) % 2 else 0.0)) / n
+        pts.append(np.stack([xc + r * np.cos(t), yc + r * np.sin(t)], axis=1))
+        r_last = r
+
+    def side(p0, p1):
+        p0, p1 = np.asarray(p0, dtype=np.float64), np.asarray(p1, dtype=np.float64)
+        ln = float(np.hypot(*(p1 - p0)))
+        s = [0.0]
+        while s[-1] < ln:
+            q = p0 + (p1 - p0) * (s[-1] / ln)
+            s.append(s[-1] + float(size(q[0:1], q[1:2])[0]))
+        s = np.array(s[:-1]) * (ln / s[-1])
+        return p0[None, :] + (p1 - p0)[None, :] * (s[:, None] / ln)
+
+    pts.append(np.concatenate([side((0.0, 0.0), (L, 0.0)), side((L, 0.0), (L, H)),
+                               side((L, H), (0.0, H)), side((0.0, H), (0.0, 0.0))]))
+    fixed = np.concatenate(pts)
+    allp = [tuple(p) for p in fixed]
+    allh = list(size(fixed[:, 0], fixed[:, 1]))
+    gc = 0.5
+    grid: dict = {}
+    for i, (px, py) in enumerate(allp):
+        grid.setdefault((int(px / gc), int(py / gc)), []).append(i)
+    rng = np.random.default_rng(seed)
+    fails = 0
+    while fails < 3000:
+        qx, qy = rng.uniform(0.0, L), rng.uniform(0.0, H)
+        hq = float(size(np.array([qx]), np.array([qy]))[0])
+        if (np.hypot(qx - xc, qy - yc) < r_last + 0.6 * hq or qx < 0.6 * hq or qx > L - 0.6 * hq
+                or qy < 0.6 * hq or qy > H - 0.6 * hq):
+            fails += 1
+            continue
+        cx, cy = int(qx / gc), int(qy / gc)
+        reach = int(np.ceil(hq / gc)) + 1
+        ok = True
+        for ix in range(cx - reach, cx + reach + 1):
+            for iy in range(cy - reach, cy + reach + 1):
+                for j in grid.get((ix, iy), ()):
+                    lim = 0.8 * min(hq, allh[j])
+                    if (allp[j][0] - qx) ** 2 + (allp[j][1] - qy) ** 2 < lim * lim:
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if not ok:
+            fails += 1
+            continue
+        fails = 0
+        grid.setdefault((cx, cy), []).append(len(allp))
+        allp.append((qx, qy))
+        allh.append(hq)
+    xy = np.array(allp, dtype=np.float64)
+    # node order along a Z curve of 2^10 x 2^10 cells (locality of the gathers)
+    ix = np.minimum((xy[:, 0] / L * 1024).astype(np.int64), 1023)
+    iy = np.minimum((xy[:, 1] / H * 1024).astype(np.int64), 1023)
+    code = np.zeros(xy.shape[0], dtype=np.int64)
+    for b in range(10):
+        code |= ((ix >> b) & 1) << (2 * b) | ((iy >> b) & 1) << (2 * b + 1)
+    order = np.argsort(code, kind="stable")
+    xy = xy[order]
+    tri = Delaunay(xy).simplices.astype(np.int64)
+    c = xy[tri].mean(axis=1)
+    tri = tri[np.hypot(c[:, 0] - xc, c[:, 1] - yc) > r0]
+    e1 = xy[tri[:, 1]] - xy[tri[:, 0]]
+    e2 = xy[tri[:, 2]] - xy[tri[:, 0]]
+    cw = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0] < 0.0
+    tri[cw] = tri[cw][:, [0, 2, 1]]
+    geometry = {"L": L, "H": H, "xc": xc, "yc": yc, "d": d, "n_circle": n_circle}
+    return Channel(xy, tri.astype(np.int32), geometry)

@@ -133,11 +133,18 @@ def lorentz_force(xy, tri, phi_f, u_f, v_f, sigma: float, b0: float):
     return fx, fy, element_gradient(xy, tri, phi_f)
 
 
-def velocity_correction(xy, tri, p_f, ut, vt, scale: float):
+def velocity_correction(xy, tri, p_f, ut, vt, scale: float, mask=None):
     """Eqs. 16-17: u = ut - scale dp/dx, v = vt - scale dp/dy with scale = dt/rho.
 
     The derivatives of the prolonged pressure are its nodal gradient (the same
-    area-weighted mean of element gradients as the Lorentz source uses).
+    area-weighted mean of element gradients as the Lorentz source uses).  ``mask``
+    (per node, optional): a component whose bit is set (0: u, 1: v) keeps its
+    intermediate value there (its Dirichlet value from the momentum step).
     """
     g = nodal_gradient(xy, tri, p_f)
-    return ut - scale * g[:, 0], vt - scale * g[:, 1]
+    u, v = ut - scale * g[:, 0], vt - scale * g[:, 1]
+    if mask is not None:
+        m = np.asarray(mask, dtype=np.uint8)
+        u = np.where((m & 1) != 0, ut, u)
+        v = np.where((m & 2) != 0, vt, v)
+    return u, v

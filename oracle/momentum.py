@@ -83,13 +83,20 @@ def rhs(xy, tri, dirichlet, wn, f, g, rho: float, dt: float) -> np.ndarray:
     return b
 
 
-def step(xy, tri, dirichlet, un, vn, fx, fy, rho: float, mu: float, dt: float, gu=None, gv=None):
+def step(xy, tri, dirichlet, un, vn, fx, fy, rho: float, mu: float, dt: float, gu=None, gv=None, mask=None):
     """The intermediate velocity (u~, v~) of Eqs. 13-14 by a direct solve; boundary values
-    gu, gv (default: those of u^n, v^n)."""
+    gu, gv (default: those of u^n, v^n).  ``mask`` (per node, optional) sets the Dirichlet
+    rows of each component apart: bit 0 for u, bit 1 for v (a slip wall fixes v only, a
+    natural outflow neither); without it both components use ``dirichlet``."""
     gu = un if gu is None else gu
     gv = vn if gv is None else gv
-    a = sp.csc_matrix(operator(xy, tri, dirichlet, un, vn, rho, mu, dt))
-    lu = spla.splu(a)
-    ut = lu.solve(rhs(xy, tri, dirichlet, un, fx, gu, rho, dt))
-    vt = lu.solve(rhs(xy, tri, dirichlet, vn, fy, gv, rho, dt))
+    if mask is None:
+        du = dv = np.asarray(dirichlet, dtype=bool)
+    else:
+        m = np.asarray(mask, dtype=np.uint8)
+        du, dv = (m & 1) != 0, (m & 2) != 0
+    lu_u = spla.splu(sp.csc_matrix(operator(xy, tri, du, un, vn, rho, mu, dt)))
+    lu_v = lu_u if np.array_equal(du, dv) else spla.splu(sp.csc_matrix(operator(xy, tri, dv, un, vn, rho, mu, dt)))
+    ut = lu_u.solve(rhs(xy, tri, du, un, fx, gu, rho, dt))
+    vt = lu_v.solve(rhs(xy, tri, dv, vn, fy, gv, rho, dt))
     return ut, vt
