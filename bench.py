@@ -80,11 +80,14 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=200, help="steps solved (fp64) to train the networks")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "momentum", "interpolate"],
+    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "momentum", "interpolate", "channel"],
                     help="sequence: one 513x257 CGP sequence (default); batch: 64-instance Stuart sweep; "
                          "momentum: the fine-mesh momentum step of Eqs. 13-14; interpolate: the restriction "
-                         "of a fine field onto the nodes of a non-nested coarse mesh by point location")
-    ap.add_argument("--mu", type=float, default=0.01, help="momentum: dynamic viscosity (rho = 1)")
+                         "of a fine field onto the nodes of a non-nested coarse mesh by point location; channel: "
+                         "whole CGP time steps of the flow past a cylinder (Section 3), with drag and lift")
+    ap.add_argument("--mu", type=float, default=0.01, help="momentum, channel: dynamic viscosity (rho = 1)")
+    ap.add_argument("--channel-k", type=int, default=3, help="channel: refinements of the coarse mesh")
+    ap.add_argument("--channel-stuart", type=float, default=0.5, help="channel: Stuart number (the paper: 0.01, 0.5)")
     ap.add_argument("--mom-tol", type=float, default=1e-8, help="momentum: relative residual of each component")
     ap.add_argument("--instances", type=int, default=64, help="batch: number of instances")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -480,6 +483,169 @@ def interpolate_main(args):
     ctx.close()
 
 
+class ChannelRun:
+    """The flow past a cylinder of Section 3 on the device: two hierarchies of one channel
+    mesh (the electric potential's Dirichlet set: the box sides; the pressure's: the
+    outflow), the fine level's per-component velocity mask (inflow and cylinder: both
+    components, slip walls: v, outflow: none), the cylinder's boundary edges, and the
+    buffers of one CGP time step (Section 2.3's steps 1-8, every one a library call)."""
+
+    def __init__(self, ctx, coarse, k: int, *, rho=1.0, mu=0.01, dt=0.05, sigma=0.01, b0=1.0,
+                 solve_kw=None, mom_tol=1e-8, mom_max_iter=5000):
+        import numpy as np
+        import torch
+
+        import cgp_inputs as ci
+        import paper_2003_00082_amd as cgp
+
+        self.ctx, self.cgp = ctx, cgp
+        self.rho, self.mu, self.dt, self.sigma, self.b0 = rho, mu, dt, sigma, b0
+        self.mom_tol, self.mom_max_iter = mom_tol, mom_max_iter
+        self.solve_kw = dict(solve_kw or {})
+        dev = torch.device("cuda:0")
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.h_phi = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, k)
+        self.h_p = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.outflow, k)
+        self.k = k
+        xy, tri, _, _ = ctx.mesh_download(self.h_p, k)
+        self.fine_xy, self.fine_tri = xy, tri
+        bnd = ci.channel_boundary(xy, tri, coarse.geometry)
+        self.vmask_np = ((bnd["inflow"] | bnd["cylinder"]) * 3 | bnd["walls"] * 2).astype(np.uint8)
+        self.cyl_np = bnd["cylinder"].astype(bool)
+        self.edges_np = bnd["cyl_edges"]
+        nc, nf = coarse.n_nodes, xy.shape[0]
+        self.nc, self.nf = nc, nf
+        self.vmask = torch.from_numpy(self.vmask_np).to(dev)
+        self.edges = torch.from_numpy(np.ascontiguousarray(self.edges_np)).to(dev)
+        # impulsive start: the free stream everywhere but on the cylinder
+        u0 = np.where(self.cyl_np, 0.0, 1.0)
+        self.u = torch.from_numpy(u0).to(dev)
+        self.v = torch.zeros(nf, **f64)
+        self.ut, self.vt = torch.empty(nf, **f64), torch.empty(nf, **f64)
+        self.fx, self.fy = torch.empty(nf, **f64), torch.empty(nf, **f64)
+        self.phi_c, self.p_c = torch.zeros(nc, **f64), torch.zeros(nc, **f64)
+        self.phi_f, self.p_f = torch.empty(nf, **f64), torch.empty(nf, **f64)
+        self.b_phi, self.b_p = torch.empty(nc, **f64), torch.empty(nc, **f64)
+        self.force = torch.zeros(5, **f64)
+        self.stats = cgp.stats_buffer(2)
+        self.mom_iters = []
+
+    def step(self):
+        ctx, cgp = self.ctx, self.cgp
+        S = cgp.STATS_BYTES
+        ctx.restrict(self.h_phi, self.u, self.v, cgp.CGP_SRC_CURL, self.b0, self.b_phi)          # steps 1-2
+        ctx.poisson_solve([self.h_phi], [self.b_phi], [self.phi_c], self.stats[:S], guess=cgp.CGP_GUESS_GIVEN,
+                          **self.solve_kw)
+        ctx.prolong(self.h_phi, self.phi_c, self.phi_f)                                            # step 3
+        ctx.lorentz_force(self.h_phi, self.phi_f, self.u, self.v, self.sigma, self.b0, self.fx, self.fy)
+        self.ut.copy_(self.u)                                                                    # step 4
+        self.vt.copy_(self.v)
+        st = ctx.momentum_step(self.h_p, self.u, self.v, self.fx, self.fy, self.rho, self.mu, self.dt, self.ut,
+                               self.vt, tol=self.mom_tol, max_iter=self.mom_max_iter, mask=self.vmask)
+        self.mom_iters.append(max(st["iters"]))
+        ctx.restrict(self.h_p, self.ut, self.vt, cgp.CGP_SRC_DIV, self.rho / self.dt, self.b_p)   # steps 5-6
+        ctx.poisson_solve([self.h_p], [self.b_p], [self.p_c], self.stats[S:], guess=cgp.CGP_GUESS_GIVEN,
+                          **self.solve_kw)
+        ctx.prolong(self.h_p, self.p_c, self.p_f)                                                  # step 7
+        ctx.velocity_correct(self.h_p, self.p_f, self.ut, self.vt, self.dt / self.rho, self.u, self.v,
+                             mask=self.vmask)                                                    # step 8
+        ctx.surface_force(self.h_p, self.k, self.edges, self.p_f, self.u, self.v, self.mu, self.force)
+        return st
+
+    def check(self):
+        return self.ctx.solve_check(2, self.stats)
+
+    def close(self):
+        self.ctx.mesh_free(self.h_phi)
+        self.ctx.mesh_free(self.h_p)
+
+
+def channel_main(args):
+    """Whole CGP time steps of the flow past a cylinder (Section 3: box 38 x 32, a cylinder of
+    diameter 1 at (8, 16), Re = 100 with rho = d = u_inf = 1 and mu = 0.01, dt = 0.05, Stuart
+    number --channel-stuart with B0 = 1): the graded coarse mesh of 1733 nodes refined --channel-k times
+    (k = 3: 106929 nodes, 213440 triangles, the paper's 215680:3370 setting in spirit), the
+    electric potential and the pressure solved on the coarse level (fp32 + fp64 refinement,
+    Chebyshev degree 6, deflation, 1e-8), the momentum step on the fine level (BiCGStab to
+    --mom-tol), drag and lift every step."""
+    import numpy as np
+    import torch
+
+    import cgp_inputs as ci
+    import paper_2003_00082_amd as cgp
+
+    coarse = ci.cylinder_channel()
+    ctx = cgp.Context(0)
+    kw = dict(precision=cgp.CGP_FP32_IR, tol=TOL, precond_degree=args.degree, deflation=args.deflation,
+              refine_delta=args.refine_delta)
+    run = ChannelRun(ctx, coarse, args.channel_k, sigma=args.channel_stuart, solve_kw=kw, mom_tol=args.mom_tol,
+                     mu=args.mu)
+    W, K = args.warmup, args.steps
+    for _ in range(W):
+        run.step()
+    run.check()
+    torch.cuda.synchronize()
+    run.mom_iters.clear()
+    cd, cl, cdv, clv = [], [], [], []
+    t0 = time.perf_counter()
+    for _ in range(K):
+        run.step()
+        f = run.force                      # read after the timed loop (one copy per step kept on the device)
+        cd.append(f.clone())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solves = run.check()
+    forces = torch.stack(cd).cpu().numpy()
+    coef = 2.0 * forces[:, :4] / (1.0 * 1.0 * 1.0)
+    ok = all(s["status"] == "ok" for s in solves) and bool((forces[:, 4] == 0).all())
+    info = ctx.mesh_info(run.h_p, run.k)
+    nnz_f = run.nf + 2 * (info["n_nodes"] + info["n_tris"])   # Euler with one hole: E = N + T
+    mbytes = sum(momentum_bytes(run.nf, nnz_f, it) for it in run.mom_iters)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import channel as och
+        from oracle import mesh as omesh
+        hphi = omesh.Hierarchy(coarse.xy, coarse.tri, coarse.dirichlet, run.k)
+        hp = omesh.Hierarchy(coarse.xy, coarse.tri, coarse.outflow, run.k)
+        u0 = np.where(run.cyl_np, 0.0, 1.0)
+        t1 = time.perf_counter()
+        och.cgp_step(hphi, hp, u0, np.zeros(run.nf), run.vmask_np, u0, np.zeros(run.nf), 1.0, args.mu, 0.05,
+                     args.channel_stuart, 1.0)
+        sec = time.perf_counter() - t1
+        cpu = {"value": 1.0 / sec, "unit": "CGP time steps/s", "cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"the first time step (direct solves of both coarse Poisson problems and of the momentum "
+                         f"step, {sec:.1f} s)"}
+    out = {
+        "metric": "CGP time steps/s, flow past a cylinder (phi and p on the coarse mesh, momentum on the fine)",
+        "value": K / elapsed,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (coarse solves f32+f64 refinement)",
+        "data": "synthetic",
+        "config": {"workload": f"cylinder in a 38x32 channel, Re 100, Stuart {args.channel_stuart:g}, dt 0.05: coarse "
+                               f"{run.nc} nodes, fine k={run.k} {run.nf} nodes",
+                   "coarse_nodes": run.nc, "fine_nodes": run.nf, "k": run.k},
+        "all_converged": ok,
+        "mean_momentum_iters": float(np.mean(run.mom_iters)),
+        "mean_poisson_iters": {"phi": solves[0]["iters"], "p": solves[1]["iters"]},
+        "drag_lift_last": {"C_D": float(coef[-1, 0] + coef[-1, 2]), "C_L": float(coef[-1, 1] + coef[-1, 3]),
+                           "C_Df": float(coef[-1, 2]), "C_Lf": float(coef[-1, 3])},
+        "roofline": {"bound": "hbm", "achieved": mbytes / elapsed / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": mbytes / elapsed / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "note": "algorithmic bytes of the momentum steps (the dominant part) over the whole step time"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    run.close()
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -498,6 +664,12 @@ def main():
         return momentum_main(args)
     if args.workload == "interpolate":
         return interpolate_main(args)
+    if args.workload == "channel":
+        if args.steps == 200:
+            args.steps = 20
+        if args.warmup == 10:
+            args.warmup = 3
+        return channel_main(args)
     import numpy as np
     import torch
 

@@ -13,7 +13,8 @@
  *   cgp_lorentz_force  grad(phi_f) and the Lorentz source of Eqs. 13-14;
  *   cgp_velocity_correct  grad(p_f) and the projection of Eqs. 16-17;
  *   cgp_momentum_step  the semi-implicit momentum step of Eqs. 13-14 (fine mesh);
- *   cgp_interpolate    a level's P1 field at arbitrary points (the non-nested restriction).
+ *   cgp_interpolate    a level's P1 field at arbitrary points (the non-nested restriction);
+ *   cgp_surface_force  pressure and viscous force of the fluid on a body (drag and lift).
  *
  * Conventions for every call:
  *   - Return value: CGP_OK (0) or a negative cgp_status.  No C++ exception
@@ -272,11 +273,30 @@ cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif,
  * with G the nodal gradient of the prolonged pressure d_pf [N_k] (the same
  * area-weighted mean of element gradients as cgp_lorentz_force).  d_ut, d_vt
  * [N_k] hold the intermediate velocity of Eqs. 13-14; d_u, d_v [N_k] receive
- * the corrected velocity at every node (velocity boundary values belong to the
- * momentum step and are re-imposed by the caller).  In place is allowed
- * (d_u == d_ut, d_v == d_vt); d_u != d_v and neither is d_pf (CGP_E_INVALID). */
+ * the corrected velocity.  d_mask [N_k] uint8 or NULL: where bit 0 (u) or bit 1 (v)
+ * is set that component keeps its intermediate value (its Dirichlet value from the
+ * momentum step, the same mask as cgp_momentum_step's); NULL corrects every node.  In
+ * place is allowed (d_u == d_ut, d_v == d_vt); d_u != d_v and neither is d_pf
+ * (CGP_E_INVALID). */
 cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, const double *d_ut,
-                                const double *d_vt, double scale, double *d_u, double *d_v);
+                                const double *d_vt, const uint8_t *d_mask, double scale, double *d_u,
+                                double *d_v);
+
+/* The force of the fluid on a body (Section 3's cylinder: drag and lift, and their
+ * viscous parts), the traction integral of the Newtonian stress -p I + mu (grad w +
+ * grad w^T) over the body's boundary edges of a level:
+ *   F_p = -sum_edges (p_a + p_b)/2 n |ab|,   F_v = sum_edges mu (grad w + grad w^T)_t n |ab|
+ * with n the unit normal out of the body (towards the fluid triangle t's third vertex)
+ * and grad w the constant P1 gradient of (u, v) on t.
+ *   d_edges   [3 n_edges] int32 (device): a, b (the edge's nodes), t (the triangle that
+ *             owns the edge) of the level
+ *   d_p, d_u, d_v  [N_level] fp64 (the prolonged pressure and the velocity)
+ *   d_force   [5] fp64 (device) out: F_p (x, y), F_v (x, y), and the number of edges
+ *             skipped because an index was out of range or a, b were not nodes of t
+ * One workgroup with a fixed-order reduction (the result does not depend on timing).
+ * Coefficients: C = 2 F / (rho u_inf^2 d). */
+cgp_status cgp_surface_force(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t n_edges, const int32_t *d_edges,
+                             const double *d_p, const double *d_u, const double *d_v, double mu, double *d_force);
 
 /* The general restriction of Section 2.3, for a coarse mesh that is not nested in the
  * fine one: the P1 field of a level evaluated at arbitrary points (e.g. the nodes of
@@ -301,9 +321,12 @@ cgp_status cgp_interpolate(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t n_
  * Galerkin P1 (Section 2.3): M the mass matrix, C(u^n)_ij = int psi_i (u^n . grad psi_j)
  * with u^n interpolated in P1, K the stiffness; f = (d_fx, d_fy), the nodal
  * Lorentz source (cgp_lorentz_force), interpolated in P1.  The time derivative uses
- * u^n (Eq. 8).  Dirichlet rows (the mesh's Dirichlet nodes) are identity rows: the
- * boundary values are the caller's, passed in d_ut / d_vt at those nodes.
+ * u^n (Eq. 8).  Dirichlet rows are identity rows: the boundary values are the
+ * caller's, passed in d_ut / d_vt at those nodes.
  *   d_un, d_vn, d_fx, d_fy  [N_f] fp64 at the finest level's nodes (read only)
+ *   d_mask       [N_f] uint8 or NULL: the Dirichlet rows of each component, bit 0 for u
+ *                and bit 1 for v (Section 3's channel: inflow and cylinder 3, slip walls
+ *                2, natural outflow 0); NULL: the mesh's Dirichlet nodes, both components
  *   d_ut, d_vt   [N_f] in: initial guess, with the boundary values at Dirichlet nodes;
  *                out: the intermediate velocity (updated in place)
  *   rho, mu, dt  > 0, >= 0, > 0 (finite)
@@ -311,7 +334,8 @@ cgp_status cgp_interpolate(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t n_
  *   max_iter     >= 1
  *   h_stats      host, optional: per component iterations, status (CGP_SOLVE_*),
  *                final relative residual of the recurrence
- * Both components share one matrix and are solved together by Jacobi-preconditioned
+ * Both components share one matrix (a row fixed for one component only is that
+ * component's identity row inside the products) and are solved together by Jacobi-preconditioned
  * BiCGStab (van der Vorst) in fp64, one launch per half-step.  The matrix is
  * assembled on every call (it depends on u^n); its pattern (the finest level's
  * adjacency) and the workspace are built on the first call for a mesh.  The call
@@ -326,8 +350,8 @@ typedef struct {
 } cgp_momentum_stats;
 
 cgp_status cgp_momentum_step(cgp_ctx ctx, cgp_mesh mesh, const double *d_un, const double *d_vn,
-                             const double *d_fx, const double *d_fy, double rho, double mu, double dt,
-                             double tol, int32_t max_iter, double *d_ut, double *d_vt,
+                             const double *d_fx, const double *d_fy, const uint8_t *d_mask, double rho,
+                             double mu, double dt, double tol, int32_t max_iter, double *d_ut, double *d_vt,
                              cgp_momentum_stats *h_stats);
 
 /* ------------------------------------------------------------------ learned initial guess */

@@ -95,8 +95,10 @@ _SIGS = {
     "cgp_autotune": ([_vp, _i32, _vp, _i32, _vp], _i32),
     "cgp_prolong": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_lorentz_force": ([_vp, _i32, _vp, _vp, _vp, _f64, _f64, _vp, _vp, _vp], _i32),
-    "cgp_velocity_correct": ([_vp, _i32, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
-    "cgp_momentum_step": ([_vp, _i32, _vp, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _vp, _vp, _vp], _i32),
+    "cgp_velocity_correct": ([_vp, _i32, _vp, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
+    "cgp_surface_force": ([_vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _f64, _vp], _i32),
+    "cgp_momentum_step": ([_vp, _i32, _vp, _vp, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _vp, _vp, _vp],
+                          _i32),
     "cgp_interpolate": ([_vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp], _i32),
     "cgp_model_param_count": ([], _i64),
     "cgp_model_create": ([_vp, ctypes.c_uint64, ctypes.POINTER(_i32)], _i32),
@@ -247,9 +249,16 @@ class Context:
         _check(load().cgp_lorentz_force(self.handle, mesh, _ptr(phif), _ptr(uf), _ptr(vf), float(sigma), float(b0),
                                         _ptr(fx), _ptr(fy), _ptr(grad_elem)))
 
-    def velocity_correct(self, mesh: int, pf, ut, vt, scale: float, u, v):
-        _check(load().cgp_velocity_correct(self.handle, mesh, _ptr(pf), _ptr(ut), _ptr(vt), float(scale), _ptr(u),
-                                           _ptr(v)))
+    def velocity_correct(self, mesh: int, pf, ut, vt, scale: float, u, v, mask=None):
+        _check(load().cgp_velocity_correct(self.handle, mesh, _ptr(pf), _ptr(ut), _ptr(vt), _ptr(mask), float(scale),
+                                           _ptr(u), _ptr(v)))
+
+    def surface_force(self, mesh: int, level: int, edges, p, u, v, mu: float, out):
+        """Pressure and viscous force on a body over its boundary edges (``edges``: [m, 3] int32
+        device tensor of a, b, t); ``out`` (5 fp64 on the device) receives F_p, F_v and the
+        number of edges skipped."""
+        _check(load().cgp_surface_force(self.handle, mesh, int(level), int(edges.shape[0]), _ptr(edges), _ptr(p),
+                                        _ptr(u), _ptr(v), float(mu), _ptr(out)))
 
     def interpolate(self, mesh: int, level: int, pts, field, out, tri=None):
         """``field`` of ``level`` at the points ``pts`` ([n, 2] fp64 device tensor) into ``out``
@@ -258,12 +267,12 @@ class Context:
                                       _ptr(out), _ptr(tri) if tri is not None else None))
 
     def momentum_step(self, mesh: int, un, vn, fx, fy, rho: float, mu: float, dt: float, ut, vt, *,
-                      tol: float = 1e-10, max_iter: int = 500):
+                      tol: float = 1e-10, max_iter: int = 500, mask=None):
         """The momentum step of Eqs. 13-14 on the finest level; ``ut``/``vt`` carry the initial
         guess and the boundary values in, the intermediate velocity out.  Returns the per-component
         statistics (iterations, status, relative residual); synchronises the stream."""
         st = MomentumStats()
-        _check(load().cgp_momentum_step(self.handle, mesh, _ptr(un), _ptr(vn), _ptr(fx), _ptr(fy), float(rho),
+        _check(load().cgp_momentum_step(self.handle, mesh, _ptr(un), _ptr(vn), _ptr(fx), _ptr(fy), _ptr(mask), float(rho),
                                         float(mu), float(dt), float(tol), int(max_iter), _ptr(ut), _ptr(vt),
                                         ctypes.byref(st)))
         return {"iters": list(st.iters), "status": list(st.status), "rel_res": list(st.rel_res)}

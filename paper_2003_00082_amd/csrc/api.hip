@@ -368,7 +368,8 @@ cgp_status cgp_lorentz_force(cgp_ctx ctx, cgp_mesh mesh, const double *d_phif, c
 }
 
 cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, const double *d_ut,
-                                const double *d_vt, double scale, double *d_u, double *d_v) {
+                                const double *d_vt, const uint8_t *d_mask, double scale, double *d_u,
+                                double *d_v) {
     return guarded([&] {
         use_device(ctx);
         Mesh &m = get_mesh(ctx, mesh);
@@ -376,7 +377,20 @@ cgp_status cgp_velocity_correct(cgp_ctx ctx, cgp_mesh mesh, const double *d_pf, 
         CGP_REQUIRE(std::isfinite(scale), "scale must be finite");
         CGP_REQUIRE(d_u != d_v, "d_u and d_v must differ");
         CGP_REQUIRE(d_u != d_pf && d_v != d_pf, "the output must not overwrite d_pf");
-        launch_velocity(ctx->stream, m, d_pf, d_ut, d_vt, scale, d_u, d_v, !ctx->capturing);
+        launch_velocity(ctx->stream, m, d_pf, d_ut, d_vt, d_mask, scale, d_u, d_v, !ctx->capturing);
+    });
+}
+
+cgp_status cgp_surface_force(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t n_edges, const int32_t *d_edges,
+                             const double *d_p, const double *d_u, const double *d_v, double mu, double *d_force) {
+    return guarded([&] {
+        use_device(ctx);
+        Mesh &m = get_mesh(ctx, mesh);
+        CGP_REQUIRE(level >= 0 && level <= m.k, "level out of range");
+        CGP_REQUIRE(n_edges >= 0, "n_edges must be non-negative");
+        CGP_REQUIRE(d_p && d_u && d_v && d_force && (n_edges == 0 || d_edges), "null device pointer");
+        CGP_REQUIRE(std::isfinite(mu) && mu >= 0.0, "mu must be non-negative");
+        launch_surface_force(ctx->stream, m, level, n_edges, d_edges, d_p, d_u, d_v, mu, d_force);
     });
 }
 
@@ -396,8 +410,8 @@ cgp_status cgp_interpolate(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t n_
 }
 
 cgp_status cgp_momentum_step(cgp_ctx ctx, cgp_mesh mesh, const double *d_un, const double *d_vn,
-                             const double *d_fx, const double *d_fy, double rho, double mu, double dt,
-                             double tol, int32_t max_iter, double *d_ut, double *d_vt,
+                             const double *d_fx, const double *d_fy, const uint8_t *d_mask, double rho,
+                             double mu, double dt, double tol, int32_t max_iter, double *d_ut, double *d_vt,
                              cgp_momentum_stats *h_stats) {
     return guarded([&] {
         use_device(ctx);
@@ -412,7 +426,8 @@ cgp_status cgp_momentum_step(cgp_ctx ctx, cgp_mesh mesh, const double *d_un, con
         CGP_REQUIRE(d_ut != d_vt, "d_ut and d_vt must differ");
         for (const double *in : {d_un, d_vn, d_fx, d_fy})
             CGP_REQUIRE(in != d_ut && in != d_vt, "the outputs must not overwrite an input");
-        momentum_step(ctx->stream, m, d_un, d_vn, d_fx, d_fy, rho, mu, dt, tol, max_iter, d_ut, d_vt, h_stats);
+        momentum_step(ctx->stream, m, d_un, d_vn, d_fx, d_fy, d_mask, rho, mu, dt, tol, max_iter, d_ut, d_vt,
+                      h_stats);
     });
 }
 

@@ -371,7 +371,10 @@ void launch_lorentz(hipStream_t s, Mesh &m, const double *phif, const double *uf
                     const double *vf, double sigma, double b0, double *fx, double *fy,
                     double *grad_elem, bool build);
 void launch_velocity(hipStream_t s, Mesh &m, const double *pf, const double *ut, const double *vt,
-                     double scale, double *u, double *v, bool build);
+                     const uint8_t *mask, double scale, double *u, double *v, bool build);
+// the force of the fluid on a body over its boundary edges (a, b, t) of a level: out[5]
+void launch_surface_force(hipStream_t s, Mesh &m, int level, int64_t n_edges, const int32_t *edges,
+                          const double *p, const double *u, const double *v, double mu, double *out);
 
 // learned initial guess (gnn.hip)
 struct Model;
@@ -389,7 +392,7 @@ void interpolate_points(hipStream_t s, Mesh &m, int level, int64_t np, const dou
                         double *out, int32_t *tri_out, bool build);
 // the momentum step of Eqs. 13-14 on the finest level (synchronises the stream)
 void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, const double *fx,
-                   const double *fy, double rho, double mu, double dt, double tol, int max_iter, double *ut,
+                   const double *fy, const uint8_t *mask, double rho, double mu, double dt, double tol, int max_iter, double *ut,
                    double *vt, cgp_momentum_stats *stats);
 
 // guess from the network, then smoothed; build: the smoothing's tiled plan may be built here

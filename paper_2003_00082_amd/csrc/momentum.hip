@@ -4,7 +4,10 @@
 //   A w~ = b,  A = (rho/dt) M + rho C(u^n) + mu K,  b = (rho/dt) M w^n + M f,
 //
 // M_ij = int psi_i psi_j, C_ij = int psi_i (u^n . grad psi_j) (u^n in P1), K the
-// stiffness; Dirichlet rows are identity rows with the caller's boundary values.
+// stiffness; Dirichlet rows are identity rows with the caller's boundary values.  The
+// Dirichlet rows of the two components may differ (a slip wall fixes v only, a natural
+// outflow neither: Section 3): such a row is assembled in full and each product replaces
+// it by the identity for the component that is fixed there.
 //
 // The operator is assembled row by row (one thread per row: the incident triangles in
 // ascending id order, no atomics) into a column-major ELL copy of the finest level's
@@ -46,8 +49,8 @@ enum { ST_STATUS = 0, ST_ITERS = 1, NSTATE = 2 };
 // one thread per row: the operator row and both right-hand sides
 __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, const int32_t *ecol,
                                                       const int32_t *ne_ptr, const int32_t *ne_idx,
-                                                      const int32_t *tri, const double *xy, const uint8_t *dir,
-                                                      const double *un, const double *vn, const double *fx,
+                                                      const int32_t *tri, const double *xy, const uint8_t *mask,
+                                                      int both, const double *un, const double *vn, const double *fx,
                                                       const double *fy, const double *gu, const double *gv,
                                                       double rho, double mu, double dt, double *val, double *dinv,
                                                       double *b) {
@@ -59,7 +62,8 @@ __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, cons
         val[o] = 0.0;
         if (ecol[o] == i) pd = o;
     }
-    if (dir[i]) {
+    const int rm = both ? (mask[i] ? 3 : 0) : (mask[i] & 3);
+    if (rm == 3) {
         val[pd] = 1.0;
         dinv[i] = 1.0;
         b[2 * i] = gu[i];
@@ -94,9 +98,11 @@ __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, cons
             bv += mij * (rdt * vn[j] + fy[j]);
         }
     }
+    // a component with its own Dirichlet row keeps the full row here; the products replace
+    // that component's row by the identity
     dinv[i] = 1.0 / val[pd];
-    b[2 * i] = bu;
-    b[2 * i + 1] = bv;
+    b[2 * i] = (rm & 1) ? gu[i] : bu;
+    b[2 * i + 1] = (rm & 2) ? gv[i] : bv;
 }
 
 // the workgroup's partial sums (q values per component) in a fixed order, to
@@ -163,6 +169,8 @@ struct Vecs {
     int width;
     const int32_t *col;   // ELL: entry k of row i at k * n + i
     const double *val, *dinv, *b;
+    const uint8_t *mask;   // per row: bit c = component c has a Dirichlet (identity) row
+    int both;              // mask holds the mesh's flags: nonzero = both components
     double *x[2];
     double *r, *rh, *p, *v, *s, *t;   // [n][2] (the components interleaved); p and v: [2 parities][n][2]
     double *part1, *part2, *part3;
@@ -171,6 +179,11 @@ struct Vecs {
     double tol;
     int max_iter;
 };
+
+__device__ inline int row_mask(const Vecs &V, int64_t i) {
+    const int m = V.mask[i];
+    return V.both ? (m ? 3 : 0) : (m & 3);
+}
 
 // H0: r = b - A x, rh = r, p = v = 0 (parity 0); partials rh.r, r.r, b.b
 __global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
@@ -185,6 +198,9 @@ __global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
             ax0 += V.val[o] * V.x[0][j];
             ax1 += V.val[o] * V.x[1][j];
         }
+        const int rm = row_mask(V, i);
+        if (rm & 1) ax0 = V.x[0][i];
+        if (rm & 2) ax1 = V.x[1][i];
         const double rr[2] = {V.b[2 * i] - ax0, V.b[2 * i + 1] - ax1};
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -271,10 +287,13 @@ __global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
                 y[0] += a * (rj.x + be[0] * (pj.x - om[0] * vj.x));
                 y[1] += a * (rj.y + be[1] * (pj.y - om[1] * vj.y));
             }
+            const int rm = row_mask(V, i);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!run[c]) continue;
-                pw[2 * i + c] = V.r[2 * i + c] + be[c] * (pr[2 * i + c] - om[c] * vr[2 * i + c]);
+                const double pi = V.r[2 * i + c] + be[c] * (pr[2 * i + c] - om[c] * vr[2 * i + c]);
+                if (rm & (1 << c)) y[c] = V.dinv[i] * pi;   // identity row of this component
+                pw[2 * i + c] = pi;
                 vw[2 * i + c] = y[c];
                 acc[c][0] += V.rh[2 * i + c] * y[c];
             }
@@ -329,10 +348,12 @@ __global__ __launch_bounds__(MB) void k_mom_h2(Vecs V, int it) {
                 t[0] += a * (rj.x - al[0] * vj.x);
                 t[1] += a * (rj.y - al[1] * vj.y);
             }
+            const int rm = row_mask(V, i);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!run[c]) continue;
                 const double si = V.r[2 * i + c] - al[c] * vw[2 * i + c];
+                if (rm & (1 << c)) t[c] = V.dinv[i] * si;
                 V.s[2 * i + c] = si;
                 V.t[2 * i + c] = t[c];
                 acc[c][0] += t[c] * si;
@@ -431,13 +452,14 @@ MomentumWork &momentum_work(hipStream_t s, Mesh &m) {
 }  // namespace
 
 void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, const double *fx,
-                   const double *fy, double rho, double mu, double dt, double tol, int max_iter, double *ut,
+                   const double *fy, const uint8_t *mask, double rho, double mu, double dt, double tol, int max_iter, double *ut,
                    double *vt, cgp_momentum_stats *stats) {
     Level &L = m.lv[m.k];
     MomentumWork &w = momentum_work(s, m);
     const int64_t n = L.n;
     hipLaunchKernelGGL(k_mom_assemble, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.width, w.ecol.p, L.ne_ptr.p,
-                       L.ne_idx.p, L.tri.p, L.xy.p, L.dir.p, un, vn, fx, fy, ut, vt, rho, mu, dt, w.val.p, w.dinv.p,
+                       L.ne_idx.p, L.tri.p, L.xy.p, mask ? mask : L.dir.p, mask ? 0 : 1, un, vn, fx, fy, ut, vt, rho,
+                       mu, dt, w.val.p, w.dinv.p,
                        w.b.p);
     Vecs V{};
     V.n = n;
@@ -446,6 +468,8 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
     V.val = w.val.p;
     V.dinv = w.dinv.p;
     V.b = w.b.p;
+    V.mask = mask ? mask : L.dir.p;
+    V.both = mask ? 0 : 1;
     V.x[0] = ut;
     V.x[1] = vt;
     V.r = w.r.p;

@@ -110,14 +110,15 @@ __global__ __launch_bounds__(TPB) void k_lorentz(
 __global__ __launch_bounds__(TPB) void k_velocity(
     int64_t n, const int32_t *__restrict__ ne_ptr, const int32_t *__restrict__ ne_idx,
     const int32_t *__restrict__ tri, const double *__restrict__ xy, const double *__restrict__ p,
-    const double *ut, const double *vt, double scale, double *u, double *v) {
+    const double *ut, const double *vt, const uint8_t *mask, double scale, double *u, double *v) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double gx, gy;
     nodal_gradient(i, ne_ptr, ne_idx, tri, xy, p, gx, gy);
     const double a = ut[i], b = vt[i];
-    u[i] = a - scale * gx;
-    v[i] = b - scale * gy;
+    const int m = mask ? mask[i] : 0;
+    u[i] = (m & 1) ? a : a - scale * gx;
+    v[i] = (m & 2) ? b : b - scale * gy;
 }
 
 // The nodal gradient as an operator (built once per mesh): node i's vertices of its
@@ -219,14 +220,81 @@ __global__ __launch_bounds__(TPB) void k_lorentz_op(int64_t n, int W, const int3
 __global__ __launch_bounds__(TPB) void k_velocity_op(int64_t n, int W, const int32_t *__restrict__ col,
                                                      const double *__restrict__ cx, const double *__restrict__ cy,
                                                      const double *__restrict__ p, const double *ut,
-                                                     const double *vt, double scale, double *u, double *v) {
+                                                     const double *vt, const uint8_t *mask, double scale,
+                                                     double *u, double *v) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double gx, gy;
     grad_apply(i, n, W, col, cx, cy, p, gx, gy);
     const double a = ut[i], b = vt[i];
-    u[i] = a - scale * gx;
-    v[i] = b - scale * gy;
+    const int m = mask ? mask[i] : 0;
+    u[i] = (m & 1) ? a : a - scale * gx;
+    v[i] = (m & 2) ? b : b - scale * gy;
+}
+
+constexpr int SF_BLOCK = 256;
+
+// The force of the fluid on a body over its boundary edges (a, b, t), t the fluid triangle
+// owning edge ab: -int p n ds (p linear along the edge) and int mu (grad w + grad w^T) n ds
+// (t's constant gradient), n the unit normal out of the body (towards t's third vertex).
+// One workgroup, the edges strided over its threads, a fixed-order reduction: out[0..1]
+// pressure, out[2..3] viscous, out[4] the number of edges skipped (an index out of range,
+// or a or b not a vertex of t).
+__global__ __launch_bounds__(SF_BLOCK) void k_surface_force(int64_t ne, const int32_t *edges, int64_t n,
+                                                            int64_t T, const int32_t *tri, const double *xy,
+                                                            const double *p, const double *u, const double *v,
+                                                            double mu, double *out) {
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = threadIdx.x; k < ne; k += SF_BLOCK) {
+        const int32_t a = edges[3 * k], b = edges[3 * k + 1], t = edges[3 * k + 2];
+        if (a < 0 || a >= n || b < 0 || b >= n || a == b || t < 0 || t >= T) {
+            acc[4] += 1.0;
+            continue;
+        }
+        const int32_t v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
+        const int ha = (v0 == a) + (v1 == a) + (v2 == a), hb = (v0 == b) + (v1 == b) + (v2 == b);
+        if (ha != 1 || hb != 1) {
+            acc[4] += 1.0;
+            continue;
+        }
+        const int32_t c = v0 != a && v0 != b ? v0 : (v1 != a && v1 != b ? v1 : v2);
+        const double ax = xy[2 * a], ay = xy[2 * a + 1];
+        const double dx = xy[2 * b] - ax, dy = xy[2 * b + 1] - ay;
+        const double len = sqrt(dx * dx + dy * dy);
+        double nx = dy / len, ny = -dx / len;
+        if ((xy[2 * c] - ax) * nx + (xy[2 * c + 1] - ay) * ny < 0.0) {
+            nx = -nx;
+            ny = -ny;
+        }
+        const double pm = 0.5 * (p[a] + p[b]);
+        acc[0] -= pm * nx * len;
+        acc[1] -= pm * ny * len;
+        // the triangle's constant gradients of u and v
+        const double x0 = xy[2 * v0], y0 = xy[2 * v0 + 1], x1 = xy[2 * v1], y1 = xy[2 * v1 + 1];
+        const double x2 = xy[2 * v2], y2 = xy[2 * v2 + 1];
+        const double d = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+        const double ux = (u[v0] * (y1 - y2) + u[v1] * (y2 - y0) + u[v2] * (y0 - y1)) / d;
+        const double uy = (u[v0] * (x2 - x1) + u[v1] * (x0 - x2) + u[v2] * (x1 - x0)) / d;
+        const double vx = (v[v0] * (y1 - y2) + v[v1] * (y2 - y0) + v[v2] * (y0 - y1)) / d;
+        const double vy = (v[v0] * (x2 - x1) + v[v1] * (x0 - x2) + v[v2] * (x1 - x0)) / d;
+        const double sxy = uy + vx;
+        acc[2] += mu * (2.0 * ux * nx + sxy * ny) * len;
+        acc[3] += mu * (sxy * nx + 2.0 * vy * ny) * len;
+    }
+    __shared__ double red[SF_BLOCK / 64][5];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        double x = acc[q];
+        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+        if (lane == 0) red[wave][q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double x = 0.0;
+        for (int w = 0; w < SF_BLOCK / 64; ++w) x += red[w][threadIdx.x];
+        out[threadIdx.x] = x;
+    }
 }
 
 // element gradient g_e = sum_a phi_a beta_a / D_e
@@ -320,14 +388,22 @@ void launch_lorentz(hipStream_t s, Mesh &m, const double *phif, const double *uf
 }
 
 void launch_velocity(hipStream_t s, Mesh &m, const double *pf, const double *ut, const double *vt,
-                     double scale, double *u, double *v, bool build) {
+                     const uint8_t *mask, double scale, double *u, double *v, bool build) {
     const Level &L = m.lv[m.k];
     if (nodal_grad(s, m, build))
         hipLaunchKernelGGL(k_velocity_op, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.grad.W, m.grad.col.p,
-                           m.grad.cx.p, m.grad.cy.p, pf, ut, vt, scale, u, v);
+                           m.grad.cx.p, m.grad.cy.p, pf, ut, vt, mask, scale, u, v);
     else
         hipLaunchKernelGGL(k_velocity, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
-                           L.tri.p, L.xy.p, pf, ut, vt, scale, u, v);
+                           L.tri.p, L.xy.p, pf, ut, vt, mask, scale, u, v);
+    CGP_HIP(hipGetLastError());
+}
+
+void launch_surface_force(hipStream_t s, Mesh &m, int level, int64_t n_edges, const int32_t *edges,
+                          const double *p, const double *u, const double *v, double mu, double *out) {
+    const Level &L = m.lv[level];
+    hipLaunchKernelGGL(k_surface_force, dim3(1), dim3(SF_BLOCK), 0, s, n_edges, edges, L.n, L.T, L.tri.p, L.xy.p,
+                       p, u, v, mu, out);
     CGP_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,186 @@
+"""The cylinder-channel workload of Section 3 on the GPU (through the C ABI) against the
+oracle: per-component Dirichlet rows of the momentum step, the masked velocity correction,
+the surface force (drag and lift), and whole CGP time steps."""
+import numpy as np
+import pytest
+
+import cgp_inputs as ci
+from oracle import channel as och
+from oracle import fem, mesh
+from oracle import momentum as mom
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def cgp():
+    import paper_2003_00082_amd as lib
+    lib.load()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def ctx(cgp):
+    c = cgp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def small():
+    return ci.cylinder_channel(seed=3, n_circle=16, growth=0.5, h_max=4.0)
+
+
+def dt(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def fine_level(small, k):
+    hier = mesh.Hierarchy(small.xy, small.tri, small.dirichlet, k)
+    xy, tri = hier.xy[k], hier.tri[k]
+    b = ci.channel_boundary(xy, tri, small.geometry)
+    vmask = ((b["inflow"] | b["cylinder"]) * 3 | b["walls"] * 2).astype(np.uint8)
+    return xy, tri, vmask, b
+
+
+def test_masked_momentum_step_matches_the_oracle(ctx, small):
+    h = ctx.mesh_upload(small.xy, small.tri, small.outflow, 1)
+    try:
+        xy, tri, vmask, b = fine_level(small, 1)
+        n = xy.shape[0]
+        rng = np.random.default_rng(31)
+        un, vn = 1.0 + 0.3 * rng.standard_normal(n), 0.3 * rng.standard_normal(n)
+        fx, fy = rng.standard_normal(n), rng.standard_normal(n)
+        gu = np.where(b["cylinder"].astype(bool), 0.0, 1.0)
+        gv = np.zeros(n)
+        ut0, vt0 = np.where(vmask & 1, gu, un), np.where(vmask & 2, gv, vn)
+        for mu_, dt_ in ((0.01, 0.05), (0.5, 0.2)):
+            ut, vt = dt(ut0), dt(vt0)
+            st = ctx.momentum_step(h, dt(un), dt(vn), dt(fx), dt(fy), 1.0, mu_, dt_, ut, vt, tol=1e-13,
+                                   max_iter=2000, mask=dt(vmask, torch.uint8))
+            assert st["status"] == [0, 0], st
+            ur, vr = mom.step(xy, tri, None, un, vn, fx, fy, 1.0, mu_, dt_, gu=ut0, gv=vt0, mask=vmask)
+            a, c = ut.cpu().numpy(), vt.cpu().numpy()
+            assert rel(a, ur) <= 1e-10 and rel(c, vr) <= 1e-10
+            np.testing.assert_array_equal(a[(vmask & 1) != 0], ut0[(vmask & 1) != 0])   # fixed rows: exact
+            np.testing.assert_array_equal(c[(vmask & 2) != 0], vt0[(vmask & 2) != 0])
+    finally:
+        ctx.mesh_free(h)
+
+
+def test_manufactured_per_component_rows(ctx):
+    # u* = c + gamma y fixed on the walls only, v* = c2 + gamma2 x fixed on the sides only;
+    # wrong boundary values elsewhere catch a row made Dirichlet by mistake
+    m = ci.jittered_rect(21, 11, 32)
+    h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 0)
+    try:
+        x, y = m.xy[:, 0], m.xy[:, 1]
+        lr = (np.abs(x) < 1e-12) | (np.abs(x - 2.0) < 1e-12)
+        tb = (np.abs(y) < 1e-12) | (np.abs(y - 1.0) < 1e-12)
+        mask = (tb * 1 | lr * 2).astype(np.uint8)
+        rho, mu_, dt_ = 1.0, 0.3, 0.1
+        a = np.array([0.4, -0.2])
+        un, vn = np.full(m.n_nodes, a[0]), np.full(m.n_nodes, a[1])
+        us, vs = 0.5 + 1.5 * y, -0.2 + 0.8 * x
+        fx = (rho / dt_) * (us - un) + rho * a[1] * 1.5
+        fy = (rho / dt_) * (vs - vn) + rho * a[0] * 0.8
+        ut, vt = dt(np.where(tb, us, us + 1.0)), dt(np.where(lr, vs, vs - 1.0))
+        st = ctx.momentum_step(h, dt(un), dt(vn), dt(fx), dt(fy), rho, mu_, dt_, ut, vt, tol=1e-14, max_iter=2000,
+                               mask=dt(mask, torch.uint8))
+        assert st["status"] == [0, 0], st
+        np.testing.assert_allclose(ut.cpu().numpy(), us, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(vt.cpu().numpy(), vs, rtol=0, atol=1e-11)
+    finally:
+        ctx.mesh_free(h)
+
+
+def test_masked_velocity_correction(ctx, small):
+    h = ctx.mesh_upload(small.xy, small.tri, small.outflow, 1)
+    try:
+        xy, tri, vmask, _ = fine_level(small, 1)
+        rng = np.random.default_rng(33)
+        n = xy.shape[0]
+        p, ut, vt = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+        u, v = torch.empty(n, dtype=torch.float64, device=DEV), torch.empty(n, dtype=torch.float64, device=DEV)
+        ctx.velocity_correct(h, dt(p), dt(ut), dt(vt), 0.05, u, v, mask=dt(vmask, torch.uint8))
+        ctx.sync()
+        ur, vr = fem.velocity_correction(xy, tri, p, ut, vt, 0.05, mask=vmask)
+        np.testing.assert_allclose(u.cpu().numpy(), ur, rtol=0, atol=1e-12 * np.abs(ur).max())
+        np.testing.assert_allclose(v.cpu().numpy(), vr, rtol=0, atol=1e-12 * np.abs(vr).max())
+        np.testing.assert_array_equal(u.cpu().numpy()[(vmask & 1) != 0], ut[(vmask & 1) != 0])
+    finally:
+        ctx.mesh_free(h)
+
+
+def test_surface_force(ctx, small, cgp):
+    h = ctx.mesh_upload(small.xy, small.tri, small.outflow, 2)
+    try:
+        xy, tri, _, b = fine_level(small, 2)
+        edges = b["cyl_edges"]
+        assert edges.shape[0] == 4 * 16
+        rng = np.random.default_rng(34)
+        n = xy.shape[0]
+        p, u, v = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+        out = torch.zeros(5, dtype=torch.float64, device=DEV)
+        ctx.surface_force(h, 2, dt(edges, torch.int32), dt(p), dt(u), dt(v), 0.01, out)
+        ctx.sync()
+        fp, fv = och.surface_force(xy, tri, edges, p, u, v, 0.01)
+        got = out.cpu().numpy()
+        np.testing.assert_allclose(got[:2], fp, rtol=0, atol=1e-12 * np.abs(fp).max())
+        np.testing.assert_allclose(got[2:4], fv, rtol=0, atol=1e-12 * np.abs(fv).max())
+        assert got[4] == 0.0
+        # edges with an index out of range or not of their triangle are skipped and counted
+        bad = np.concatenate([edges[:3], [[0, 1, tri.shape[0]], [-1, 2, 0], [edges[0, 0], edges[0, 1], edges[5, 2]]]])
+        ctx.surface_force(h, 2, dt(bad, torch.int32), dt(p), dt(u), dt(v), 0.01, out)
+        ctx.sync()
+        got = out.cpu().numpy()
+        fp, fv = och.surface_force(xy, tri, edges[:3], p, u, v, 0.01)
+        np.testing.assert_allclose(got[:4], np.concatenate([fp, fv]), rtol=0, atol=1e-12)
+        assert got[4] == 3.0
+        # no edges: zero; level out of range: an error
+        ctx.surface_force(h, 2, torch.empty((0, 3), dtype=torch.int32, device=DEV), dt(p), dt(u), dt(v), 0.01, out)
+        ctx.sync()
+        assert not out.cpu().numpy().any()
+        with pytest.raises(cgp.CGPError):
+            ctx.surface_force(h, 3, dt(edges, torch.int32), dt(p), dt(u), dt(v), 0.01, out)
+    finally:
+        ctx.mesh_free(h)
+
+
+def test_cgp_time_steps_match_the_oracle(ctx, cgp, small):
+    import bench
+    k = 2
+    run = bench.ChannelRun(ctx, small, k, sigma=0.5, solve_kw=dict(precision=cgp.CGP_FP64, tol=1e-13),
+                           mom_tol=1e-13)
+    try:
+        hphi = mesh.Hierarchy(small.xy, small.tri, small.dirichlet, k)
+        hp = mesh.Hierarchy(small.xy, small.tri, small.outflow, k)
+        np.testing.assert_array_equal(run.fine_xy, hp.xy[k])
+        n = run.nf
+        u = np.where(run.cyl_np, 0.0, 1.0)
+        v = np.zeros(n)
+        g = u.copy()
+        for step in range(3):
+            run.step()
+            ctx.sync()
+            u, v, phi_f, p_f, _, _, _, _ = och.cgp_step(hphi, hp, u, v, run.vmask_np, g, np.zeros(n), 1.0, 0.01,
+                                                       0.05, 0.5, 1.0)
+            assert all(s["status"] == "ok" for s in run.check())
+            assert rel(run.u.cpu().numpy(), u) <= 1e-9, step
+            assert rel(run.v.cpu().numpy(), v) <= 1e-8, step
+            assert rel(run.p_f.cpu().numpy(), p_f) <= 1e-8, step
+            assert rel(run.phi_f.cpu().numpy(), phi_f) <= 1e-8, step
+            fp, fv = och.surface_force(hp.xy[k], hp.tri[k], run.edges_np, p_f, u, v, 0.01)
+            got = run.force.cpu().numpy()
+            assert got[4] == 0.0
+            np.testing.assert_allclose(got[:2], fp, rtol=1e-7, atol=1e-10)
+            np.testing.assert_allclose(got[2:4], fv, rtol=1e-7, atol=1e-10)
+    finally:
+        run.close()
