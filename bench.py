@@ -47,7 +47,7 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "ca19b207fe17b57c", "profile": "profiles/cg_traffic_513x257.md",
+MEASURED_TRAFFIC = {"fingerprint": "473c59fe4db1fa55", "profile": "profiles/cg_traffic_513x257.md",
                     "k_cg_tile<float, 8, true, true> degree 6 deflated": 25.69e6,
                     "k_cg_tile<double, 8, true, true> degree 6 deflated": 42.61e6}
 

@@ -127,17 +127,26 @@ __device__ inline void block_partials(const double (&v)[2][MQ], double *part, in
     }
 }
 
-// the sums of a launch's partials (every workgroup, the same fixed order): sums[c][q]
+// the sums of a launch's partials (every workgroup, the same fixed order): sums[c][q]; the
+// first wavefront issues all its loads before the first add (a fixed trip count), so the
+// reduction costs one memory latency, not one per load
+static_assert(MG % 64 == 0, "the partials are reduced by one wavefront");
 __device__ inline void reduce_partials(const double *part, double (*sums)[MQ]) {
     __shared__ double red[2 * MQ];
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
+        double x[2 * MQ][MG / 64];
+#pragma unroll
+        for (int cq = 0; cq < 2 * MQ; ++cq)
+#pragma unroll
+            for (int t = 0; t < MG / 64; ++t) x[cq][t] = part[cq * MG + t * 64 + lane];
 #pragma unroll
         for (int cq = 0; cq < 2 * MQ; ++cq) {
-            double x = 0.0;
-            for (int k = lane; k < MG; k += 64) x += part[cq * MG + k];
-            for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-            if (lane == 0) red[cq] = x;
+            double y = 0.0;
+#pragma unroll
+            for (int t = 0; t < MG / 64; ++t) y += x[cq][t];
+            for (int m = 32; m >= 1; m >>= 1) y += __shfl_xor(y, m, 64);
+            if (lane == 0) red[cq] = y;
         }
     }
     __syncthreads();
