@@ -11,7 +11,8 @@
 //
 // The operator is assembled row by row (one thread per row: the incident triangles in
 // ascending id order, no atomics) into a column-major ELL copy of the finest level's
-// adjacency pattern (entry k of row i at k * n + i, width = the longest row, padding: the
+// adjacency pattern (entry k of row i at k * n + i, width = the longest row rounded up to 7,
+// 8, 12, 16, 24 or 33, padding: the
 // row itself with value 0, so that a wavefront reads entry k of 64 consecutive rows with
 // one coalesced load), together with both right-hand sides.  Both components share it and are solved together by
 // Jacobi-preconditioned BiCGStab (van der Vorst) in fp64: a thread applies each matrix
@@ -194,14 +195,24 @@ __device__ inline int row_mask(const Vecs &V, int64_t i) {
     return V.both ? (m ? 3 : 0) : (m & 3);
 }
 
+// The product kernels are instantiated for the ELL width W (the longest row rounded up to
+// a bin, the padding: the row itself with value 0): the loop over a row's entries unrolls,
+// so a thread issues a row's gathers before the first one returns.
+
+// rows of up to 12 entries unroll fully; longer ones by 8 (a full unroll would spill)
+template <int W>
+constexpr int UNROLL = W <= 12 ? W : 8;
+
 // H0: r = b - A x, rh = r, p = v = 0 (parity 0); partials rh.r, r.r, b.b
+template <int W>
 __global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
     const Rows R = block_rows(V.n);
     double acc[2][MQ] = {};
     const int64_t n = V.n;
     for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
         double ax0 = 0.0, ax1 = 0.0;
-        for (int k = 0; k < V.width; ++k) {
+#pragma unroll UNROLL<W>
+        for (int k = 0; k < W; ++k) {
             const int64_t o = static_cast<int64_t>(k) * n + i;
             const int32_t j = V.col[o];
             ax0 += V.val[o] * V.x[0][j];
@@ -226,6 +237,7 @@ __global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
 }
 
 // H1 of iteration it >= 1 (reads H3's partials of it - 1, or H0's)
+template <int W>
 __global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
     __shared__ double sums[2][MQ];
     __shared__ double beta_s[2], omega_s[2];
@@ -287,7 +299,8 @@ __global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
     if (run[0] || run[1]) {
         for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
             double y[2] = {0.0, 0.0};
-            for (int k = 0; k < V.width; ++k) {
+#pragma unroll UNROLL<W>
+            for (int k = 0; k < W; ++k) {
                 const int64_t o = static_cast<int64_t>(k) * n + i;
                 const int32_t j = V.col[o];
                 const double a = V.val[o] * V.dinv[j];
@@ -312,6 +325,7 @@ __global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
 }
 
 // H2 of iteration it (reads H1's partials)
+template <int W>
 __global__ __launch_bounds__(MB) void k_mom_h2(Vecs V, int it) {
     __shared__ double sums[2][MQ];
     __shared__ double alpha_s[2];
@@ -349,7 +363,8 @@ __global__ __launch_bounds__(MB) void k_mom_h2(Vecs V, int it) {
     if (run[0] || run[1]) {
         for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
             double t[2] = {0.0, 0.0};
-            for (int k = 0; k < V.width; ++k) {
+#pragma unroll UNROLL<W>
+            for (int k = 0; k < W; ++k) {
                 const int64_t o = static_cast<int64_t>(k) * n + i;
                 const int32_t j = V.col[o];
                 const double a = V.val[o] * V.dinv[j];
@@ -416,6 +431,32 @@ __global__ __launch_bounds__(MB) void k_mom_h3(Vecs V, int it) {
     block_partials(acc, V.part3, blockIdx.x);
 }
 
+struct MomKernels {
+    void (*start)(Vecs);
+    void (*h1)(Vecs, int);
+    void (*h2)(Vecs, int);
+};
+template <int W>
+MomKernels mom_kernels() {
+    return {k_mom_start<W>, k_mom_h1<W>, k_mom_h2<W>};
+}
+// the ELL width of a longest row of `len` entries
+int width_bin(int len) {
+    for (int w : {7, 8, 12, 16, 24})
+        if (len <= w) return w;
+    return MAX_ROW;
+}
+MomKernels pick_kernels(int width) {
+    switch (width) {
+    case 7: return mom_kernels<7>();
+    case 8: return mom_kernels<8>();
+    case 12: return mom_kernels<12>();
+    case 16: return mom_kernels<16>();
+    case 24: return mom_kernels<24>();
+    default: return mom_kernels<MAX_ROW>();
+    }
+}
+
 __global__ void k_mom_reset(int32_t *state) {
     if (threadIdx.x < 2) {
         state[threadIdx.x * NSTATE + ST_STATUS] = -1;
@@ -436,7 +477,8 @@ MomentumWork &momentum_work(hipStream_t s, Mesh &m) {
         for (int64_t i = 0; i < L.n; ++i) width = std::max(width, hp[i + 1] - hp[i]);
         if (width > MAX_ROW) throw Error{CGP_E_UNSUPPORTED, "a node has more than 32 neighbours"};
         const size_t n = static_cast<size_t>(L.n);
-        w->width = width;
+        w->width = width_bin(width);
+        width = w->width;
         w->ecol.alloc(static_cast<size_t>(width) * n);
         hipLaunchKernelGGL(k_mom_ell, dim3(blocks_for(L.n, 256)), dim3(256), 0, s, L.n, width, w->ptr.p, w->col.p,
                            w->ecol.p);
@@ -495,16 +537,17 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
     V.tol = tol;
     V.max_iter = max_iter;
     hipLaunchKernelGGL(k_mom_reset, dim3(1), dim3(64), 0, s, w.state.p);
-    hipLaunchKernelGGL(k_mom_start, dim3(MG), dim3(MB), 0, s, V);
+    const MomKernels K = pick_kernels(w.width);
+    hipLaunchKernelGGL(K.start, dim3(MG), dim3(MB), 0, s, V);
     CGP_HIP(hipGetLastError());
     int32_t hs[2 * NSTATE] = {-1, 0, -1, 0};
     // H1 of iteration max_iter + 1 only records the outcome; the host looks at the status
     // every 32 iterations, and every CHECK_EVERY from shortly before the iteration count of
     // the previous call (the kernels of a finished component do nothing)
     for (int it = 1; it <= max_iter + 1; ++it) {
-        hipLaunchKernelGGL(k_mom_h1, dim3(MG), dim3(MB), 0, s, V, it);
+        hipLaunchKernelGGL(K.h1, dim3(MG), dim3(MB), 0, s, V, it);
         if (it <= max_iter) {
-            hipLaunchKernelGGL(k_mom_h2, dim3(MG), dim3(MB), 0, s, V, it);
+            hipLaunchKernelGGL(K.h2, dim3(MG), dim3(MB), 0, s, V, it);
             hipLaunchKernelGGL(k_mom_h3, dim3(MG), dim3(MB), 0, s, V, it);
         }
         CGP_HIP(hipGetLastError());
