@@ -184,3 +184,34 @@ def test_cgp_time_steps_match_the_oracle(ctx, cgp, small):
             np.testing.assert_allclose(got[2:4], fv, rtol=1e-7, atol=1e-10)
     finally:
         run.close()
+
+
+def test_full_size_step_in_the_benchmark_configuration(ctx, cgp):
+    # the channel workload as bench.py times it (coarse 1733 nodes, k = 3: 107244 fine nodes;
+    # coarse solves fp32 + fp64 refinement, Chebyshev 6, deflation, 1e-8; momentum to 1e-8)
+    # against the oracle's direct solves: the errors are the solvers' tolerances times the
+    # operators' condition numbers
+    import bench
+    coarse = ci.cylinder_channel()
+    kw = dict(precision=cgp.CGP_FP32_IR, tol=1e-8, precond_degree=6, deflation=1, refine_delta=1e-3)
+    run = bench.ChannelRun(ctx, coarse, 3, sigma=0.5, solve_kw=kw, mom_tol=1e-8)
+    try:
+        assert run.nf == 107244
+        st = run.step()
+        ctx.sync()
+        assert st["status"] == [0, 0] and all(s["status"] == "ok" for s in run.check())
+        hphi = mesh.Hierarchy(coarse.xy, coarse.tri, coarse.dirichlet, 3)
+        hp = mesh.Hierarchy(coarse.xy, coarse.tri, coarse.outflow, 3)
+        u0 = np.where(run.cyl_np, 0.0, 1.0)
+        u, v, phi_f, p_f, _, _, _, _ = och.cgp_step(hphi, hp, u0, np.zeros(run.nf), run.vmask_np, u0,
+                                                   np.zeros(run.nf), 1.0, 0.01, 0.05, 0.5, 1.0)
+        assert rel(run.u.cpu().numpy(), u) <= 1e-6
+        assert rel(run.v.cpu().numpy(), v) <= 1e-5
+        assert rel(run.p_f.cpu().numpy(), p_f) <= 1e-5
+        assert rel(run.phi_f.cpu().numpy(), phi_f) <= 1e-5
+        fp, fv = och.surface_force(hp.xy[3], hp.tri[3], run.edges_np, p_f, u, v, 0.01)
+        got = run.force.cpu().numpy()
+        np.testing.assert_allclose(got[:2], fp, rtol=1e-5, atol=1e-8)
+        np.testing.assert_allclose(got[2:4], fv, rtol=1e-5, atol=1e-8)
+    finally:
+        run.close()
