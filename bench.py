@@ -650,7 +650,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances of a batch or "
-              "mesh partitions would shard across GPUs, which this build does not do.", file=sys.stderr)
+              "mesh partitions would shard across GPUs; the library drives one GPU.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         if args.steps == 200:
