@@ -4,7 +4,9 @@
 //
 // Location: a uniform grid over the level's bounding box, cells of about two triangles'
 // size, each listing the triangles whose bounding box (widened by a relative 1e-9)
-// overlaps it, built once per level on the host (CSR).  A group of lanes per point tests its
+// overlaps it, built once per level on the host (CSR; an entry is the triangle's id and its
+// three node ids in one 16-byte record, so that a candidate costs one load before its
+// coordinates).  A group of lanes per point tests its
 // cell's triangles and keeps the one with the largest smallest barycentric coordinate (the
 // lowest id on a tie); the point is inside when that coordinate is >= -1e-12.
 // A triangle that contains the point overlaps the point's cell, so the scan is exact.
@@ -27,7 +29,7 @@ constexpr int LOC_BLOCK = 256;
 // (smallest barycentric coordinate descending, triangle id ascending); the order is total, so
 // the butterfly over the group gives every lane the same winner as a serial scan would.
 __global__ __launch_bounds__(LOC_BLOCK) void k_interpolate(int64_t np, const double *pts, const double *xy,
-                                                           const int32_t *tri, Locator L, const double *field,
+                                                           Locator L, const double *field,
                                                            double *out, int32_t *tri_out) {
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * LOC_BLOCK + threadIdx.x;
     const int64_t q = gid / LANES;
@@ -35,6 +37,7 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_interpolate(int64_t np, const dou
     const bool valid = q < np;
     int32_t best = -1;
     double bl0 = 0.0, bl1 = 0.0, bl2 = 0.0, bmin = -INFINITY;
+    int32_t bv0 = 0, bv1 = 0, bv2 = 0;   // the best triangle's nodes
     if (valid) {
         const double px = pts[2 * q], py = pts[2 * q + 1];
         const double fx = (px - L.x0) / L.h, fy = (py - L.y0) / L.h;
@@ -44,8 +47,8 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_interpolate(int64_t np, const dou
             const int64_t c = static_cast<int64_t>(cy) * L.gx + cx;
             const int32_t end = L.cell_ptr[c + 1];
             for (int32_t k = L.cell_ptr[c] + lane; k < end; k += LANES) {
-                const int32_t t = L.cell_tri[k];
-                const int32_t a = tri[3 * t], b = tri[3 * t + 1], d = tri[3 * t + 2];
+                const int4 en = reinterpret_cast<const int4 *>(L.cell_tri)[k];
+                const int32_t t = en.x, a = en.y, b = en.z, d = en.w;
                 const double ax = xy[2 * a], ay = xy[2 * a + 1];
                 const double e1x = xy[2 * b] - ax, e1y = xy[2 * b + 1] - ay;
                 const double e2x = xy[2 * d] - ax, e2y = xy[2 * d + 1] - ay;
@@ -60,6 +63,9 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_interpolate(int64_t np, const dou
                     bl0 = l0;
                     bl1 = l1;
                     bl2 = l2;
+                    bv0 = a;
+                    bv1 = b;
+                    bv2 = d;
                 }
             }
         }
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_interpolate(int64_t np, const dou
     if (!valid) return;
     if (wbest >= 0 && wmin >= -LOC_EPS) {
         if (best != wbest) return;   // the winner's lane writes (a triangle is listed once per cell)
-        out[q] = bl0 * field[tri[3 * best]] + bl1 * field[tri[3 * best + 1]] + bl2 * field[tri[3 * best + 2]];
+        out[q] = bl0 * field[bv0] + bl1 * field[bv1] + bl2 * field[bv2];
         if (tri_out) tri_out[q] = best;
     } else if (lane == 0) {
         out[q] = NAN;
@@ -136,13 +142,19 @@ std::unique_ptr<LocatorData> build_locator(hipStream_t s, const Level &L) {
             for (int cx = cx0; cx <= cx1; ++cx) ++cnt[static_cast<int64_t>(cy) * G.gx + cx + 1];
     }
     for (int64_t c = 0; c < nc; ++c) cnt[c + 1] += cnt[c];
-    std::vector<int32_t> list(cnt[nc]);
+    std::vector<int32_t> list(4 * static_cast<size_t>(cnt[nc]));
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
     for (int64_t t = 0; t < L.T; ++t) {   // ascending triangle id within every cell
         int cx0, cx1, cy0, cy1;
         cells(t, cx0, cx1, cy0, cy1);
         for (int cy = cy0; cy <= cy1; ++cy)
-            for (int cx = cx0; cx <= cx1; ++cx) list[fill[static_cast<int64_t>(cy) * G.gx + cx]++] = static_cast<int32_t>(t);
+            for (int cx = cx0; cx <= cx1; ++cx) {
+                int32_t *en = &list[4 * static_cast<size_t>(fill[static_cast<int64_t>(cy) * G.gx + cx]++)];
+                en[0] = static_cast<int32_t>(t);
+                en[1] = tri[3 * t];
+                en[2] = tri[3 * t + 1];
+                en[3] = tri[3 * t + 2];
+            }
     }
     out->cell_ptr.alloc(cnt.size());
     out->cell_tri.alloc(list.size());
@@ -167,7 +179,7 @@ void interpolate_points(hipStream_t s, Mesh &m, int level, int64_t np, const dou
     }
     if (np == 0) return;
     const Level &L = m.lv[level];
-    hipLaunchKernelGGL(k_interpolate, dim3(blocks_for(np * LANES, LOC_BLOCK)), dim3(LOC_BLOCK), 0, s, np, pts, L.xy.p, L.tri.p,
+    hipLaunchKernelGGL(k_interpolate, dim3(blocks_for(np * LANES, LOC_BLOCK)), dim3(LOC_BLOCK), 0, s, np, pts, L.xy.p,
                        slot->loc, field, out, tri_out);
     CGP_HIP(hipGetLastError());
 }
