@@ -150,3 +150,20 @@ def test_cgp_step_keeps_uniform_flow_in_an_empty_channel():
     np.testing.assert_allclose(u, 1.0, rtol=0, atol=1e-12)
     np.testing.assert_allclose(v, 0.0, rtol=0, atol=1e-12)
     assert np.abs(p).max() < 1e-10 and np.abs(phi).max() < 1e-10
+
+
+def test_channel_hierarchy_follows_the_papers_counts_law():
+    # Section 3's four meshes satisfy N' = 2 N + T, T' = 4 T (one hole); so does the
+    # stand-in channel mesh under the oracle's refinement, and its boundary classes carry over
+    m = ci.cylinder_channel()
+    h = mesh.Hierarchy(m.xy, m.tri, m.dirichlet, 3)
+    for lvl in range(3):
+        n, t = h.n_nodes(lvl), h.tri[lvl].shape[0]
+        assert h.tri[lvl + 1].shape[0] == 4 * t and h.n_nodes(lvl + 1) == 2 * n + t
+    assert (h.n_nodes(3), h.tri[3].shape[0]) == (107244, 213440)
+    b = ci.channel_boundary(h.xy[3], h.tri[3], m.geometry)
+    assert b["cyl_edges"].shape[0] == 8 * m.geometry["n_circle"]
+    assert int(b["cylinder"].sum()) == 8 * m.geometry["n_circle"]
+    nb_f = int((b["inflow"] | b["outflow"] | b["walls"] | b["cylinder"]).sum())
+    nb_c = int((m.inflow | m.outflow | m.walls | m.cylinder).sum())
+    assert nb_f == 8 * nb_c                               # every boundary edge split in 2, three times
