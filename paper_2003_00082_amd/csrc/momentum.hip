@@ -16,12 +16,15 @@
 // row itself with value 0, so that a wavefront reads entry k of 64 consecutive rows with
 // one coalesced load), together with both right-hand sides.  Both components share it and are solved together by
 // Jacobi-preconditioned BiCGStab (van der Vorst) in fp64: a thread applies each matrix
-// row it reads to both components.  An iteration is three launches,
-//   H1  p' = r + beta (p - omega v), v' = A D^-1 p'         partials  rh.v'
-//   H2  s = r - alpha v', t = A D^-1 s                        partials  t.s, t.t
-//   H3  x += alpha D^-1 p' + omega D^-1 s, r' = s - omega t   partials  rh.r', r'.r'
-// where the preconditioned vectors of the neighbours are formed on the fly from the
-// previous launch's vectors (so no launch waits on another's row updates), and every
+// row it reads to both components.  An iteration is two launches,
+//   HA  x += alpha D^-1 p + omega D^-1 s, r = s - omega t (the end of the previous
+//       iteration), p' = r + beta (p - omega v), v' = A D^-1 p'    partials  rh.v', r.r
+//   HB  s = r - alpha v', t = A D^-1 s                             partials  t.s, t.t, rh.t, rh.s
+// with omega = t.s / t.t and rh.r = rh.s - omega rh.t formed from HB's partials, so that
+// the update of x and r needs no launch of its own; the test on
+// |r| uses r.r summed row by row in HA.  The preconditioned vectors of the neighbours are
+// formed on the fly from the previous launch's vectors (so no launch waits on another's
+// row updates), and every
 // workgroup derives the scalars it needs from the previous launch's per-workgroup
 // partials in a fixed order (no floating-point atomics: bitwise reproducible).  The
 // grid is one workgroup per compute unit, each over a contiguous block of rows.
@@ -43,9 +46,11 @@ constexpr int CHECK_EVERY = 4;   // iterations between the host's looks at the s
 
 // scalar slots per component (scal[c * NS + ...]); slots indexed by parity hold the
 // values of iteration it at it & 1
-enum { S_BB = 0, S_RHO = 1, S_ALPHA = 3, S_OMEGA = 5, S_RR = 7, NS = 8 };
-// state per component: status (-1 running, else CGP_SOLVE_*), iterations
+enum { S_BB = 0, S_RHO = 1, S_ALPHA = 3, S_RR = 5, NS = 6 };
+// state per component: status (-1 running, ST_SUSPECT: HA found beta undefined and HB
+// decides between converged and breakdown, else CGP_SOLVE_*), iterations
 enum { ST_STATUS = 0, ST_ITERS = 1, NSTATE = 2 };
+constexpr int ST_SUSPECT = -2;
 
 // one thread per row: the operator row and both right-hand sides
 __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, const int32_t *ecol,
@@ -199,11 +204,14 @@ __device__ inline int row_mask(const Vecs &V, int64_t i) {
 // a bin, the padding: the row itself with value 0): the loop over a row's entries unrolls,
 // so a thread issues a row's gathers before the first one returns.
 
-// rows of up to 12 entries unroll fully; longer ones by 8 (a full unroll would spill)
+// rows of up to 12 entries unroll fully; longer ones by 8 (a full unroll would spill);
+// HA, which gathers four vectors per entry, unrolls rows of 12 by 6
 template <int W>
 constexpr int UNROLL = W <= 12 ? W : 8;
+template <int W>
+constexpr int UNROLL_HA = W <= 8 ? W : (W == 12 ? 6 : 8);
 
-// H0: r = b - A x, rh = r, p = v = 0 (parity 0); partials rh.r, r.r, b.b
+// H0: r = b - A x, rh = s = r, t = 0, p = v = 0 (parity 0); partials rh.r, r.r, b.b
 template <int W>
 __global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
     const Rows R = block_rows(V.n);
@@ -226,6 +234,8 @@ __global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
         for (int c = 0; c < 2; ++c) {
             V.r[2 * i + c] = rr[c];
             V.rh[2 * i + c] = rr[c];
+            V.s[2 * i + c] = rr[c];
+            V.t[2 * i + c] = 0.0;
             V.p[2 * i + c] = 0.0;
             V.v[2 * i + c] = 0.0;
             acc[c][0] += rr[c] * rr[c];
@@ -236,53 +246,87 @@ __global__ __launch_bounds__(MB) void k_mom_start(Vecs V) {
     block_partials(acc, V.part3, blockIdx.x);
 }
 
-// H1 of iteration it >= 1 (reads H3's partials of it - 1, or H0's)
+// The status of a component as the previous launch left it (every launch reads the
+// previous launch's copy and its workgroup 0 writes its own, so no workgroup reads what
+// another one of the same launch writes).  Launch q (H0 = 0, HA of iteration it = 2 it - 1,
+// HB of iteration it = 2 it) reads copy (q - 1) & 1 and writes copy q & 1.
+__device__ inline const int32_t *state_in(const Vecs &V, int q, int c) {
+    return V.state + ((q - 1) & 1) * 2 * NSTATE + c * NSTATE;
+}
+__device__ inline int32_t *state_out(const Vecs &V, int q, int c) {
+    return V.state + (q & 1) * 2 * NSTATE + c * NSTATE;
+}
+
+// HA of iteration it >= 1: the end of iteration it - 1 and the start of iteration it.
+// From HB's partials of it - 1 (t.s, t.t, rh.t, rh.s):
+//   omega = t.s / t.t,  rho = rh.r = rh.s - omega rh.t,  beta = (rho / rho')(alpha / omega)
+// (rho' = rh.r of it - 2, alpha of it - 1; every inner product summed afresh, so that no
+// rounding error is carried from one iteration to the next);
+// per row
+//   x += alpha D^-1 p + omega D^-1 s,  r = s - omega t,
+//   p' = r + beta (p - omega v),  v' = A D^-1 p'          partials rh.v', r.r
+// with the neighbours' p' formed from their s, t, p, v.  Iteration 1 starts from H0's
+// partials: rho = rh.r, b.b, and the test of the initial residual.
 template <int W>
-__global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
+__global__ __launch_bounds__(MB) void k_mom_ha(Vecs V, int it) {
     __shared__ double sums[2][MQ];
-    __shared__ double beta_s[2], omega_s[2];
-    __shared__ int run_s[2], zero_s[2];
-    reduce_partials(V.part3, sums);
-    const int rd = (it - 1) & 1, wr = it & 1;
+    __shared__ double al_s[2], om_s[2], be_s[2];
+    __shared__ int upd_s[2], run_s[2], zero_s[2];
+    reduce_partials(it == 1 ? V.part3 : V.part2, sums);
+    const int q = 2 * it - 1, rd = (it - 1) & 1, wr = it & 1;
     if (threadIdx.x < 2) {
         const int c = threadIdx.x;
         double *sc = V.scal + c * NS;
-        int32_t *st = V.state + c * NSTATE;
-        int run = st[ST_STATUS] < 0, zero = 0;
-        double beta = 0.0, omega = 0.0;
-        if (run) {
-            const double rho = sums[c][0], rr = sums[c][1];
-            const double bb = it == 1 ? sums[c][2] : sc[S_BB];
-            int status = -1;
-            if (bb == 0.0) {
-                status = CGP_SOLVE_OK;   // b = 0: the solution is 0
-                zero = 1;
-            } else if (!(rr <= V.tol * V.tol * bb)) {
-                if (it > V.max_iter) status = CGP_SOLVE_NOCONV;
-                else if (it > 1) {
-                    const double rho0 = sc[S_RHO + rd], alpha = sc[S_ALPHA + rd];
-                    omega = sc[S_OMEGA + rd];
-                    beta = (rho / rho0) * (alpha / omega);
-                    if (!std::isfinite(beta) || rho == 0.0) status = CGP_SOLVE_BREAKDOWN;
+        const int32_t *si = state_in(V, q, c);
+        int status = si[ST_STATUS], iters = si[ST_ITERS];
+        const int was = status < 0;
+        int upd = 0, zero = 0;
+        double alpha = 0.0, omega = 0.0, beta = 0.0;
+        if (was) {
+            if (it == 1) {
+                const double rho = sums[c][0], rr = sums[c][1], bb = sums[c][2];
+                if (bb == 0.0) {
+                    status = CGP_SOLVE_OK;   // b = 0: the solution is 0
+                    zero = 1;
+                } else if (rr <= V.tol * V.tol * bb) {
+                    status = CGP_SOLVE_OK;
+                }
+                if (status >= 0) iters = 0;
+                if (blockIdx.x == 0) {
+                    sc[S_BB] = bb;
+                    sc[S_RHO + 0] = rho;
+                    sc[S_RR] = rr;
                 }
             } else {
-                status = CGP_SOLVE_OK;
-            }
-            if (blockIdx.x == 0) {
-                if (it == 1) sc[S_BB] = bb;
-                sc[S_RHO + wr] = rho;
-                sc[S_RR] = rr;
-                if (status >= 0) {
-                    st[ST_STATUS] = status;
-                    st[ST_ITERS] = it - 1;
+                const double ts = sums[c][0], tt = sums[c][1], rht = sums[c][2], rhs = sums[c][3];
+                alpha = sc[S_ALPHA + rd];
+                // t = 0 (s = 0 or a singular operator): omega = 0, r = s
+                omega = tt != 0.0 ? ts / tt : 0.0;
+                const double rho_p = sc[S_RHO + (it & 1)];   // rho of iteration it - 2
+                const double rho = rhs - omega * rht;
+                upd = 1;
+                if (it <= V.max_iter) {
+                    beta = (rho / rho_p) * (alpha / omega);
+                    // near convergence t.t or rho can vanish: HB tests the residual first
+                    if (!std::isfinite(beta) || rho == 0.0) {
+                        status = ST_SUSPECT;
+                        iters = it - 1;
+                    }
                 }
+                if (blockIdx.x == 0) sc[S_RHO + rd] = rho;
             }
-            run = status < 0;
         }
-        run_s[c] = run;
+        if (blockIdx.x == 0) {
+            int32_t *so = state_out(V, q, c);
+            so[ST_STATUS] = status;
+            so[ST_ITERS] = iters;
+        }
+        upd_s[c] = upd;
         zero_s[c] = zero;
-        beta_s[c] = beta;
-        omega_s[c] = omega;
+        run_s[c] = status == -1 && it <= V.max_iter;
+        al_s[c] = alpha;
+        om_s[c] = omega;
+        be_s[c] = beta;
     }
     __syncthreads();
     const Rows R = block_rows(V.n);
@@ -293,28 +337,42 @@ __global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
             for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) V.x[c][i] = 0.0;
     const double *pr = V.p + rd * 2 * n, *vr = V.v + rd * 2 * n;
     double *pw = V.p + wr * 2 * n, *vw = V.v + wr * 2 * n;
-    const double be[2] = {beta_s[0], beta_s[1]}, om[2] = {omega_s[0], omega_s[1]};
-    const bool run[2] = {run_s[0] != 0, run_s[1] != 0};
+    const double al[2] = {al_s[0], al_s[1]}, om[2] = {om_s[0], om_s[1]}, be[2] = {be_s[0], be_s[1]};
+    const bool upd[2] = {upd_s[0] != 0, upd_s[1] != 0}, run[2] = {run_s[0] != 0, run_s[1] != 0};
     double acc[2][MQ] = {};
-    if (run[0] || run[1]) {
+    if (upd[0] || upd[1] || run[0] || run[1]) {
         for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
+            const double di = V.dinv[i];
+            double rn[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double sv = V.s[2 * i + c];
+                rn[c] = sv - om[c] * V.t[2 * i + c];
+                if (upd[c]) {
+                    V.x[c][i] += al[c] * di * pr[2 * i + c] + om[c] * di * sv;
+                    V.r[2 * i + c] = rn[c];
+                }
+                // r.r whenever r is new or in use: HB tests it even when no product follows
+                if (upd[c] || run[c]) acc[c][1] += rn[c] * rn[c];
+            }
+            if (!run[0] && !run[1]) continue;
             double y[2] = {0.0, 0.0};
-#pragma unroll UNROLL<W>
+#pragma unroll UNROLL_HA<W>
             for (int k = 0; k < W; ++k) {
                 const int64_t o = static_cast<int64_t>(k) * n + i;
                 const int32_t j = V.col[o];
                 const double a = V.val[o] * V.dinv[j];
-                // both components of a neighbour in one 16-byte load per vector
-                const double2 rj = ld2(V.r, j), pj = ld2(pr, j), vj = ld2(vr, j);
-                y[0] += a * (rj.x + be[0] * (pj.x - om[0] * vj.x));
-                y[1] += a * (rj.y + be[1] * (pj.y - om[1] * vj.y));
+                // the neighbour's p' from its s, t, p, v (one 16-byte load per vector)
+                const double2 sj = ld2(V.s, j), tj = ld2(V.t, j), pj = ld2(pr, j), vj = ld2(vr, j);
+                y[0] += a * ((sj.x - om[0] * tj.x) + be[0] * (pj.x - om[0] * vj.x));
+                y[1] += a * ((sj.y - om[1] * tj.y) + be[1] * (pj.y - om[1] * vj.y));
             }
             const int rm = row_mask(V, i);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!run[c]) continue;
-                const double pi = V.r[2 * i + c] + be[c] * (pr[2 * i + c] - om[c] * vr[2 * i + c]);
-                if (rm & (1 << c)) y[c] = V.dinv[i] * pi;   // identity row of this component
+                const double pi = rn[c] + be[c] * (pr[2 * i + c] - om[c] * vr[2 * i + c]);
+                if (rm & (1 << c)) y[c] = di * pi;   // identity row of this component
                 pw[2 * i + c] = pi;
                 vw[2 * i + c] = y[c];
                 acc[c][0] += V.rh[2 * i + c] * y[c];
@@ -324,33 +382,51 @@ __global__ __launch_bounds__(MB) void k_mom_h1(Vecs V, int it) {
     block_partials(acc, V.part1, blockIdx.x);
 }
 
-// H2 of iteration it (reads H1's partials)
+// HB of iteration it (reads HA's partials rh.v', r.r): the test of r (the residual after
+// iteration it - 1, summed row by row), then alpha = rho / rh.v',
+//   s = r - alpha v',  t = A D^-1 s                             partials t.s, t.t, rh.t, rh.s
 template <int W>
-__global__ __launch_bounds__(MB) void k_mom_h2(Vecs V, int it) {
+__global__ __launch_bounds__(MB) void k_mom_hb(Vecs V, int it) {
     __shared__ double sums[2][MQ];
     __shared__ double alpha_s[2];
     __shared__ int run_s[2];
     reduce_partials(V.part1, sums);
-    const int wr = it & 1;
+    const int q = 2 * it, wr = it & 1;
     if (threadIdx.x < 2) {
         const int c = threadIdx.x;
         double *sc = V.scal + c * NS;
-        int32_t *st = V.state + c * NSTATE;
-        int run = st[ST_STATUS] < 0;
+        const int32_t *si = state_in(V, q, c);
+        int status = si[ST_STATUS], iters = si[ST_ITERS];
         double alpha = 0.0;
-        if (run) {
-            alpha = sc[S_RHO + wr] / sums[c][0];
-            if (!std::isfinite(alpha)) {
-                run = 0;
-                if (blockIdx.x == 0) {
-                    st[ST_STATUS] = CGP_SOLVE_BREAKDOWN;
-                    st[ST_ITERS] = it - 1;
+        if (status < 0) {
+            const double rhv = sums[c][0], rr = sums[c][1];
+            if (status == ST_SUSPECT) {
+                status = rr <= V.tol * V.tol * sc[S_BB] ? CGP_SOLVE_OK : CGP_SOLVE_BREAKDOWN;
+                iters = it - 1;
+            } else if (rr <= V.tol * V.tol * sc[S_BB]) {
+                status = CGP_SOLVE_OK;
+                iters = it - 1;
+            } else if (it > V.max_iter) {
+                status = CGP_SOLVE_NOCONV;
+                iters = it - 1;
+            } else {
+                alpha = sc[S_RHO + ((it - 1) & 1)] / rhv;
+                if (!std::isfinite(alpha)) {
+                    status = CGP_SOLVE_BREAKDOWN;
+                    iters = it - 1;
                 }
-            } else if (blockIdx.x == 0) {
-                sc[S_ALPHA + wr] = alpha;
+            }
+            if (blockIdx.x == 0) {
+                sc[S_RR] = rr;
+                sc[S_ALPHA + wr] = alpha;   // (unused once the component has finished)
             }
         }
-        run_s[c] = run;
+        if (blockIdx.x == 0) {
+            int32_t *so = state_out(V, q, c);
+            so[ST_STATUS] = status;
+            so[ST_ITERS] = iters;
+        }
+        run_s[c] = status < 0;
         alpha_s[c] = alpha;
     }
     __syncthreads();
@@ -382,63 +458,22 @@ __global__ __launch_bounds__(MB) void k_mom_h2(Vecs V, int it) {
                 V.t[2 * i + c] = t[c];
                 acc[c][0] += t[c] * si;
                 acc[c][1] += t[c] * t[c];
+                acc[c][2] += V.rh[2 * i + c] * t[c];
+                acc[c][3] += V.rh[2 * i + c] * si;
             }
         }
     }
     block_partials(acc, V.part2, blockIdx.x);
 }
 
-// H3 of iteration it (reads H2's partials)
-__global__ __launch_bounds__(MB) void k_mom_h3(Vecs V, int it) {
-    __shared__ double sums[2][MQ];
-    __shared__ double alpha_s[2], omega_s[2];
-    __shared__ int run_s[2];
-    reduce_partials(V.part2, sums);
-    const int wr = it & 1;
-    if (threadIdx.x < 2) {
-        const int c = threadIdx.x;
-        double *sc = V.scal + c * NS;
-        const int run = V.state[c * NSTATE + ST_STATUS] < 0;
-        // t = 0 (s = 0 or a singular operator): omega = 0, r' = s; the next H1 stops the solve
-        const double tt = sums[c][1];
-        const double omega = run && tt != 0.0 ? sums[c][0] / tt : 0.0;
-        if (run && blockIdx.x == 0) sc[S_OMEGA + wr] = omega;
-        run_s[c] = run;
-        omega_s[c] = omega;
-        alpha_s[c] = run ? sc[S_ALPHA + wr] : 0.0;
-    }
-    __syncthreads();
-    const Rows R = block_rows(V.n);
-    const int64_t n = V.n;
-    const double *pw = V.p + wr * 2 * n;
-    const double al[2] = {alpha_s[0], alpha_s[1]}, om[2] = {omega_s[0], omega_s[1]};
-    const bool run[2] = {run_s[0] != 0, run_s[1] != 0};
-    double acc[2][MQ] = {};
-    if (run[0] || run[1]) {
-        for (int64_t i = R.r0 + threadIdx.x; i < R.r1; i += MB) {
-            const double di = V.dinv[i];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                if (!run[c]) continue;
-                const double si = V.s[2 * i + c], ri = si - om[c] * V.t[2 * i + c];
-                V.x[c][i] += al[c] * di * pw[2 * i + c] + om[c] * di * si;
-                V.r[2 * i + c] = ri;
-                acc[c][0] += V.rh[2 * i + c] * ri;
-                acc[c][1] += ri * ri;
-            }
-        }
-    }
-    block_partials(acc, V.part3, blockIdx.x);
-}
-
 struct MomKernels {
     void (*start)(Vecs);
-    void (*h1)(Vecs, int);
-    void (*h2)(Vecs, int);
+    void (*ha)(Vecs, int);
+    void (*hb)(Vecs, int);
 };
 template <int W>
 MomKernels mom_kernels() {
-    return {k_mom_start<W>, k_mom_h1<W>, k_mom_h2<W>};
+    return {k_mom_start<W>, k_mom_ha<W>, k_mom_hb<W>};
 }
 // the ELL width of a longest row of `len` entries
 int width_bin(int len) {
@@ -458,7 +493,7 @@ MomKernels pick_kernels(int width) {
 }
 
 __global__ void k_mom_reset(int32_t *state) {
-    if (threadIdx.x < 2) {
+    if (threadIdx.x < 4) {   // both copies, both components
         state[threadIdx.x * NSTATE + ST_STATUS] = -1;
         state[threadIdx.x * NSTATE + ST_ITERS] = 0;
     }
@@ -494,7 +529,7 @@ MomentumWork &momentum_work(hipStream_t s, Mesh &m) {
         w->t.alloc(2 * n);
         w->part.alloc(3 * 2 * MQ * MG);
         w->scal.alloc(2 * NS);
-        w->state.alloc(2 * NSTATE);
+        w->state.alloc(2 * 2 * NSTATE);
         m.mom = std::move(w);
     }
     return *m.mom;
@@ -541,15 +576,13 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
     hipLaunchKernelGGL(K.start, dim3(MG), dim3(MB), 0, s, V);
     CGP_HIP(hipGetLastError());
     int32_t hs[2 * NSTATE] = {-1, 0, -1, 0};
-    // H1 of iteration max_iter + 1 only records the outcome; the host looks at the status
-    // every 32 iterations, and every CHECK_EVERY from shortly before the iteration count of
-    // the previous call (the kernels of a finished component do nothing)
+    // HA and HB of iteration max_iter + 1 only finish iteration max_iter and record the
+    // outcome; the host looks at the status (the copy HB writes) every 32 iterations, and
+    // every CHECK_EVERY from shortly before the iteration count of the previous call (the
+    // kernels of a finished component do nothing)
     for (int it = 1; it <= max_iter + 1; ++it) {
-        hipLaunchKernelGGL(K.h1, dim3(MG), dim3(MB), 0, s, V, it);
-        if (it <= max_iter) {
-            hipLaunchKernelGGL(K.h2, dim3(MG), dim3(MB), 0, s, V, it);
-            hipLaunchKernelGGL(k_mom_h3, dim3(MG), dim3(MB), 0, s, V, it);
-        }
+        hipLaunchKernelGGL(K.ha, dim3(MG), dim3(MB), 0, s, V, it);
+        hipLaunchKernelGGL(K.hb, dim3(MG), dim3(MB), 0, s, V, it);
         CGP_HIP(hipGetLastError());
         const bool near = it + CHECK_EVERY > w.last_iters;
         if ((near ? it % CHECK_EVERY : it % 32) == 0 || it == max_iter + 1) {

@@ -211,7 +211,9 @@ def test_full_size_step_in_the_benchmark_configuration(ctx, cgp):
         assert rel(run.phi_f.cpu().numpy(), phi_f) <= 1e-5
         fp, fv = och.surface_force(hp.xy[3], hp.tri[3], run.edges_np, p_f, u, v, 0.01)
         got = run.force.cpu().numpy()
-        np.testing.assert_allclose(got[:2], fp, rtol=1e-5, atol=1e-8)
-        np.testing.assert_allclose(got[2:4], fv, rtol=1e-5, atol=1e-8)
+        # the solvers' tolerances bound the error relative to the force's magnitude (the lift
+        # of this symmetric start is five orders below the drag)
+        np.testing.assert_allclose(got[:2], fp, rtol=0, atol=1e-5 * np.abs(fp).max())
+        np.testing.assert_allclose(got[2:4], fv, rtol=0, atol=1e-5 * np.abs(fv).max())
     finally:
         run.close()
