@@ -295,12 +295,12 @@ def batch_main(args):
 def momentum_bytes(n: int, nnz: int, iters: int) -> float:
     """Algorithmic HBM bytes of one momentum step (both components, fp64): the assembly
     (reads the mesh's incidence, coordinates and the four input fields, writes the matrix
-    values, D^-1 and both right-hand sides: ~12 nnz + 104 n with the pattern read once) and
-    per BiCGStab iteration three launches, each reading the matrix once for both
-    components: H1 12 nnz + 104 n (reads D^-1, r, p, v, rh; writes p, v), H2 12 nnz + 72 n
-    (reads D^-1, r, v; writes s, t), H3 120 n (reads D^-1, s, t, p, x, rh; writes x, r);
-    the start (residual) 12 nnz + 88 n."""
-    return float(12 * nnz + 104 * n + 12 * nnz + 88 * n + iters * (24 * nnz + 296 * n))
+    values, D^-1 and both right-hand sides: ~12 nnz + 104 n with the pattern read once), the
+    start (residual; writes r, rh, s, t, p, v: 12 nnz + 128 n) and per BiCGStab iteration two
+    launches, each reading the matrix once for both components: HA 12 nnz + 168 n (reads D^-1,
+    s, t, p, v, x, rh; writes x, r, p', v'), HB 12 nnz + 88 n (reads D^-1, r, v', rh; writes
+    s, t)."""
+    return float(12 * nnz + 104 * n + 12 * nnz + 128 * n + iters * (24 * nnz + 256 * n))
 
 
 def momentum_main(args):
