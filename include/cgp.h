@@ -336,7 +336,7 @@ cgp_status cgp_interpolate(cgp_ctx ctx, cgp_mesh mesh, int32_t level, int64_t n_
  *                final relative residual of the recurrence
  * Both components share one matrix (a row fixed for one component only is that
  * component's identity row inside the products) and are solved together by Jacobi-preconditioned
- * BiCGStab (van der Vorst) in fp64, one launch per half-step.  The matrix is
+ * BiCGStab (van der Vorst) in fp64, two launches per iteration.  The matrix is
  * assembled on every call (it depends on u^n); its pattern (the finest level's
  * adjacency) and the workspace are built on the first call for a mesh.  The call
  * returns after the solve (it synchronises the context's stream); CGP_E_NOCONV or
