@@ -162,14 +162,19 @@ __device__ inline int xcd_block(int v, int G) {
     return x * q + (x < rm ? x : rm) + k;
 }
 
-// Workspace of the momentum step on the finest level: the adjacency pattern (self
-// included, sorted; CSR and a column-major ELL copy) with the operator's values (ELL),
-// its Jacobi inverse, the two right-hand sides and the BiCGStab vectors of both
-// components ([n][2] each, interleaved; p and v by parity).
+// Workspace of the momentum step on the finest level, in its own numbering of the nodes
+// (along a Z curve of their coordinates, so that a row's neighbours lie close in memory;
+// perm: own -> mesh, inv: mesh -> own): the adjacency pattern (self included, sorted; CSR
+// and a column-major ELL copy) with the operator's values (ELL), its Jacobi inverse, the
+// rows' Dirichlet bits, the two right-hand sides, the iterate of both components and the
+// BiCGStab vectors ([n][2] each, interleaved; p and v by parity).
 struct MomentumWork {
     int64_t n = 0, nnz = 0;
     int32_t width = 0;       // the longest row: the width of the column-major ELL copy
     int32_t last_iters = 0;  // BiCGStab iterations of the previous call (0: none yet)
+    DBuf<int32_t> perm, inv;
+    DBuf<uint8_t> rowmask;
+    DBuf<double> x;          // [2][n]: u, then v
     DBuf<int32_t> ptr, col;  // CSR pattern (built once)
     DBuf<int32_t> ecol;      // ELL columns: entry k of row i at k * n + i (padding: i)
     DBuf<double> val, dinv, b, r, rh, p, v, s, t;

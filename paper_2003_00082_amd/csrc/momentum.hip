@@ -54,9 +54,10 @@ constexpr int ST_SUSPECT = -2;
 
 // one thread per row: the operator row and both right-hand sides
 __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, const int32_t *ecol,
+                                                      const int32_t *perm, const int32_t *inv,
                                                       const int32_t *ne_ptr, const int32_t *ne_idx,
                                                       const int32_t *tri, const double *xy, const uint8_t *mask,
-                                                      int both, const double *un, const double *vn, const double *fx,
+                                                      int both, uint8_t *rowmask, const double *un, const double *vn, const double *fx,
                                                       const double *fy, const double *gu, const double *gv,
                                                       double rho, double mu, double dt, double *val, double *dinv,
                                                       double *b) {
@@ -68,20 +69,23 @@ __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, cons
         val[o] = 0.0;
         if (ecol[o] == i) pd = o;
     }
-    const int rm = both ? (mask[i] ? 3 : 0) : (mask[i] & 3);
+    // row i of the own numbering is mesh node o; the mesh's arrays are read at mesh indices
+    const int32_t o = perm[i];
+    const int rm = both ? (mask[o] ? 3 : 0) : (mask[o] & 3);
+    rowmask[i] = static_cast<uint8_t>(rm);
     if (rm == 3) {
         val[pd] = 1.0;
         dinv[i] = 1.0;
-        b[2 * i] = gu[i];
-        b[2 * i + 1] = gv[i];
+        b[2 * i] = gu[o];
+        b[2 * i + 1] = gv[o];
         return;
     }
     const double rdt = rho / dt;
     double bu = 0.0, bv = 0.0;
-    for (int32_t q = ne_ptr[i]; q < ne_ptr[i + 1]; ++q) {
+    for (int32_t q = ne_ptr[o]; q < ne_ptr[o + 1]; ++q) {
         const int64_t e = ne_idx[q];
         const int32_t v3[3] = {tri[3 * e], tri[3 * e + 1], tri[3 * e + 2]};
-        const int li = v3[0] == i ? 0 : (v3[1] == i ? 1 : 2);
+        const int li = v3[0] == o ? 0 : (v3[1] == o ? 1 : 2);
         const double xa = xy[2 * v3[0]], ya = xy[2 * v3[0] + 1];
         const double xb = xy[2 * v3[1]], yb = xy[2 * v3[1] + 1];
         const double xc = xy[2 * v3[2]], yc = xy[2 * v3[2] + 1];
@@ -90,15 +94,15 @@ __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, cons
         const double gx[3] = {(yb - yc) / twice, (yc - ya) / twice, (ya - yb) / twice};
         const double gy[3] = {(xc - xb) / twice, (xa - xc) / twice, (xb - xa) / twice};
         // int psi_i psi_k = A (1 + delta_ik) / 12: the advecting velocity's weight in row i
-        const double ax = area / 12.0 * (un[v3[0]] + un[v3[1]] + un[v3[2]] + un[i]);
-        const double ay = area / 12.0 * (vn[v3[0]] + vn[v3[1]] + vn[v3[2]] + vn[i]);
+        const double ax = area / 12.0 * (un[v3[0]] + un[v3[1]] + un[v3[2]] + un[o]);
+        const double ay = area / 12.0 * (vn[v3[0]] + vn[v3[1]] + vn[v3[2]] + vn[o]);
         for (int lj = 0; lj < 3; ++lj) {
-            const int32_t j = v3[lj];
+            const int32_t j = v3[lj], jo = inv[j];   // mesh index, own index
             const double mij = area * (lj == li ? 2.0 : 1.0) / 12.0;
             const double a = rdt * mij + rho * (ax * gx[lj] + ay * gy[lj]) +
                              mu * area * (gx[li] * gx[lj] + gy[li] * gy[lj]);
             int k = 0;   // j is in the row (a vertex of a triangle of node i); padding comes last
-            while (k < width - 1 && ecol[static_cast<int64_t>(k) * n + i] != j) ++k;
+            while (k < width - 1 && ecol[static_cast<int64_t>(k) * n + i] != jo) ++k;
             val[static_cast<int64_t>(k) * n + i] += a;
             bu += mij * (rdt * un[j] + fx[j]);
             bv += mij * (rdt * vn[j] + fy[j]);
@@ -107,8 +111,24 @@ __global__ __launch_bounds__(256) void k_mom_assemble(int64_t n, int width, cons
     // a component with its own Dirichlet row keeps the full row here; the products replace
     // that component's row by the identity
     dinv[i] = 1.0 / val[pd];
-    b[2 * i] = (rm & 1) ? gu[i] : bu;
-    b[2 * i + 1] = (rm & 2) ? gv[i] : bv;
+    b[2 * i] = (rm & 1) ? gu[o] : bu;
+    b[2 * i + 1] = (rm & 2) ? gv[o] : bv;
+}
+
+// the iterate in the own numbering from the caller's vectors, and back
+__global__ void k_mom_gather(int64_t n, const int32_t *perm, const double *u, const double *v, double *x) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t o = perm[i];
+    x[i] = u[o];
+    x[n + i] = v[o];
+}
+__global__ void k_mom_scatter(int64_t n, const int32_t *perm, const double *x, double *u, double *v) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t o = perm[i];
+    u[o] = x[i];
+    v[o] = x[n + i];
 }
 
 // the workgroup's partial sums (q values per component) in a fixed order, to
@@ -165,9 +185,10 @@ __device__ inline double2 ld2(const double *v, int64_t j) { return reinterpret_c
 struct Rows {
     int64_t r0, r1;
 };
+// contiguous row blocks, consecutive ones on the same XCD (its L2 holds the neighbours)
 __device__ inline Rows block_rows(int64_t n) {
     const int64_t per = (n + MG - 1) / MG;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * per;
+    const int64_t r0 = static_cast<int64_t>(xcd_block(blockIdx.x, MG)) * per;
     return {r0, r0 + per < n ? r0 + per : n};
 }
 
@@ -185,7 +206,6 @@ struct Vecs {
     const int32_t *col;   // ELL: entry k of row i at k * n + i
     const double *val, *dinv, *b;
     const uint8_t *mask;   // per row: bit c = component c has a Dirichlet (identity) row
-    int both;              // mask holds the mesh's flags: nonzero = both components
     double *x[2];
     double *r, *rh, *p, *v, *s, *t;   // [n][2] (the components interleaved); p and v: [2 parities][n][2]
     double *part1, *part2, *part3;
@@ -195,10 +215,7 @@ struct Vecs {
     int max_iter;
 };
 
-__device__ inline int row_mask(const Vecs &V, int64_t i) {
-    const int m = V.mask[i];
-    return V.both ? (m ? 3 : 0) : (m & 3);
-}
+__device__ inline int row_mask(const Vecs &V, int64_t i) { return V.mask[i]; }
 
 // The product kernels are instantiated for the ELL width W (the longest row rounded up to
 // a bin, the padding: the row itself with value 0): the loop over a row's entries unrolls,
@@ -504,14 +521,60 @@ MomentumWork &momentum_work(hipStream_t s, Mesh &m) {
     if (!m.mom) {
         auto w = std::make_unique<MomentumWork>();
         w->n = L.n;
-        level_adjacency(s, L, w->ptr, w->col, w->nnz);
-        std::vector<int32_t> hp(L.n + 1);
-        CGP_HIP(hipMemcpyAsync(hp.data(), w->ptr.p, (L.n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        const size_t n = static_cast<size_t>(L.n);
+        // the mesh's adjacency and coordinates on the host
+        DBuf<int32_t> mptr, mcol;
+        level_adjacency(s, L, mptr, mcol, w->nnz);
+        std::vector<int32_t> hp(n + 1), hc(static_cast<size_t>(w->nnz));
+        std::vector<double> hxy(2 * n);
+        CGP_HIP(hipMemcpyAsync(hp.data(), mptr.p, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CGP_HIP(hipMemcpyAsync(hc.data(), mcol.p, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CGP_HIP(hipMemcpyAsync(hxy.data(), L.xy.p, hxy.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         CGP_HIP(hipStreamSynchronize(s));
         int width = 1;
-        for (int64_t i = 0; i < L.n; ++i) width = std::max(width, hp[i + 1] - hp[i]);
+        for (size_t i = 0; i < n; ++i) width = std::max(width, hp[i + 1] - hp[i]);
         if (width > MAX_ROW) throw Error{CGP_E_UNSUPPORTED, "a node has more than 32 neighbours"};
-        const size_t n = static_cast<size_t>(L.n);
+        // own numbering: the nodes sorted along a Z curve of 2^20 x 2^20 cells of the bounding box
+        double x0 = hxy[0], x1 = hxy[0], y0 = hxy[1], y1 = hxy[1];
+        for (size_t i = 0; i < n; ++i) {
+            x0 = std::min(x0, hxy[2 * i]);
+            x1 = std::max(x1, hxy[2 * i]);
+            y0 = std::min(y0, hxy[2 * i + 1]);
+            y1 = std::max(y1, hxy[2 * i + 1]);
+        }
+        const double sx = x1 > x0 ? 1048575.0 / (x1 - x0) : 0.0, sy = y1 > y0 ? 1048575.0 / (y1 - y0) : 0.0;
+        std::vector<uint64_t> code(n);
+        for (size_t i = 0; i < n; ++i) {
+            const uint64_t cx = static_cast<uint64_t>((hxy[2 * i] - x0) * sx);
+            const uint64_t cy = static_cast<uint64_t>((hxy[2 * i + 1] - y0) * sy);
+            uint64_t z = 0;
+            for (int bit = 0; bit < 20; ++bit) z |= ((cx >> bit) & 1) << (2 * bit) | ((cy >> bit) & 1) << (2 * bit + 1);
+            code[i] = z;
+        }
+        std::vector<int32_t> perm(n), inv(n);
+        for (size_t i = 0; i < n; ++i) perm[i] = static_cast<int32_t>(i);
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+        for (size_t i = 0; i < n; ++i) inv[perm[i]] = static_cast<int32_t>(i);
+        // the pattern in the own numbering (rows sorted)
+        std::vector<int32_t> np(n + 1, 0), nc(hc.size());
+        for (size_t i = 0; i < n; ++i) np[i + 1] = np[i] + (hp[perm[i] + 1] - hp[perm[i]]);
+        for (size_t i = 0; i < n; ++i) {
+            const int32_t o = perm[i];
+            int32_t *dst = &nc[np[i]];
+            for (int32_t q = hp[o]; q < hp[o + 1]; ++q) dst[q - hp[o]] = inv[hc[q]];
+            std::sort(dst, dst + (hp[o + 1] - hp[o]));
+        }
+        w->ptr.alloc(n + 1);
+        w->col.alloc(nc.size());
+        w->perm.alloc(n);
+        w->inv.alloc(n);
+        CGP_HIP(hipMemcpyAsync(w->ptr.p, np.data(), np.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        CGP_HIP(hipMemcpyAsync(w->col.p, nc.data(), nc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        CGP_HIP(hipMemcpyAsync(w->perm.p, perm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        CGP_HIP(hipMemcpyAsync(w->inv.p, inv.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        CGP_HIP(hipStreamSynchronize(s));
+        w->rowmask.alloc(n);
+        w->x.alloc(2 * n);
         w->width = width_bin(width);
         width = w->width;
         w->ecol.alloc(static_cast<size_t>(width) * n);
@@ -543,10 +606,10 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
     Level &L = m.lv[m.k];
     MomentumWork &w = momentum_work(s, m);
     const int64_t n = L.n;
-    hipLaunchKernelGGL(k_mom_assemble, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.width, w.ecol.p, L.ne_ptr.p,
-                       L.ne_idx.p, L.tri.p, L.xy.p, mask ? mask : L.dir.p, mask ? 0 : 1, un, vn, fx, fy, ut, vt, rho,
-                       mu, dt, w.val.p, w.dinv.p,
-                       w.b.p);
+    hipLaunchKernelGGL(k_mom_assemble, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.width, w.ecol.p, w.perm.p,
+                       w.inv.p, L.ne_ptr.p, L.ne_idx.p, L.tri.p, L.xy.p, mask ? mask : L.dir.p, mask ? 0 : 1,
+                       w.rowmask.p, un, vn, fx, fy, ut, vt, rho, mu, dt, w.val.p, w.dinv.p, w.b.p);
+    hipLaunchKernelGGL(k_mom_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.perm.p, ut, vt, w.x.p);
     Vecs V{};
     V.n = n;
     V.width = w.width;
@@ -554,10 +617,9 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
     V.val = w.val.p;
     V.dinv = w.dinv.p;
     V.b = w.b.p;
-    V.mask = mask ? mask : L.dir.p;
-    V.both = mask ? 0 : 1;
-    V.x[0] = ut;
-    V.x[1] = vt;
+    V.mask = w.rowmask.p;
+    V.x[0] = w.x.p;
+    V.x[1] = w.x.p + n;
     V.r = w.r.p;
     V.rh = w.rh.p;
     V.p = w.p.p;
@@ -591,6 +653,8 @@ void momentum_step(hipStream_t s, Mesh &m, const double *un, const double *vn, c
             if (hs[ST_STATUS] >= 0 && hs[NSTATE + ST_STATUS] >= 0) break;
         }
     }
+    hipLaunchKernelGGL(k_mom_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.perm.p, w.x.p, ut, vt);
+    CGP_HIP(hipGetLastError());
     w.last_iters = std::max(hs[ST_ITERS], hs[NSTATE + ST_ITERS]);
     double sc[2 * NS];
     CGP_HIP(hipMemcpyAsync(sc, w.scal.p, sizeof(sc), hipMemcpyDeviceToHost, s));
