@@ -47,9 +47,24 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "473c59fe4db1fa55", "profile": "profiles/cg_traffic_513x257.md",
+MEASURED_TRAFFIC = {"fingerprint": "e6353bf9d04abf22", "profile": "profiles/cg_traffic_513x257.md",
                     "k_cg_tile<float, 8, true, true> degree 6 deflated": 25.69e6,
                     "k_cg_tile<double, 8, true, true> degree 6 deflated": 42.61e6}
+
+
+# HBM bytes per launch of the momentum step's two BiCGStab kernels on the 1025x513 fine mesh
+# (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled as above), valid for the recorded source.
+MEASURED_MOM_TRAFFIC = {"fingerprint": "f16d9aa9c1861457", "profile": "profiles/momentum_1025x513.md",
+                        "k_mom_ha<7>": 159.30e6, "k_mom_hb<7>": 103.94e6}
+
+
+def momentum_fingerprint() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("momentum.hip", "cgp_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2003_00082_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def kernel_fingerprint() -> str:
@@ -385,13 +400,20 @@ def momentum_main(args):
                    "fine_nodes": nf, "nnz": nnz_f},
         "mean_iters": float(np.mean(its)), "max_iters": int(np.max(its)), "all_converged": ok,
         "roofline": {"bound": "hbm", "achieved": nbytes / elapsed / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": nbytes / elapsed / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": nbytes / elapsed / 1e9 / HBM_PEAK_GBS,
+                     "traffic": (MEASURED_MOM_TRAFFIC["k_mom_ha<7>"]
+                                 if momentum_fingerprint() == MEASURED_MOM_TRAFFIC["fingerprint"]
+                                 and (nx, ny) == (513, 257) else None),
+                     "traffic_kernel": "k_mom_ha<7> (HBM bytes per launch, rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                       "copy-calibrated; algorithmic 12 nnz + 168 n = 132.4 MB)",
                      "note": "algorithmic bytes of the assembly and all iterations / whole step time (host "
                              "status checks included: every 32 iterations, every 4 near the previous step's count)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
     ctx.close()
+    if args.calibrate_copy:
+        calibrate_copy()
 
 
 # algorithmic bytes of one located point: its coordinates (16), the value and triangle written
