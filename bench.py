@@ -47,14 +47,14 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "e6353bf9d04abf22", "profile": "profiles/cg_traffic_513x257.md",
+MEASURED_TRAFFIC = {"fingerprint": "76f97e3fb1e5a8e5", "profile": "profiles/cg_traffic_513x257.md",
                     "k_cg_tile<float, 8, true, true> degree 6 deflated": 25.69e6,
                     "k_cg_tile<double, 8, true, true> degree 6 deflated": 42.61e6}
 
 
 # HBM bytes per launch of the momentum step's two BiCGStab kernels on the 1025x513 fine mesh
 # (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled as above), valid for the recorded source.
-MEASURED_MOM_TRAFFIC = {"fingerprint": "f16d9aa9c1861457", "profile": "profiles/momentum_1025x513.md",
+MEASURED_MOM_TRAFFIC = {"fingerprint": "7d5fea3bf168dc22", "profile": "profiles/momentum_1025x513.md",
                         "k_mom_ha<7>": 159.30e6, "k_mom_hb<7>": 103.94e6}
 
 

@@ -170,7 +170,7 @@ __device__ inline int xcd_block(int v, int G) {
 // BiCGStab vectors ([n][2] each, interleaved; p and v by parity).
 struct MomentumWork {
     int64_t n = 0, nnz = 0;
-    int32_t width = 0;       // the longest row: the width of the column-major ELL copy
+    int32_t width = 0;       // the ELL width: the longest row rounded up to a bin
     int32_t last_iters = 0;  // BiCGStab iterations of the previous call (0: none yet)
     DBuf<int32_t> perm, inv;
     DBuf<uint8_t> rowmask;
@@ -178,9 +178,9 @@ struct MomentumWork {
     DBuf<int32_t> ptr, col;  // CSR pattern (built once)
     DBuf<int32_t> ecol;      // ELL columns: entry k of row i at k * n + i (padding: i)
     DBuf<double> val, dinv, b, r, rh, p, v, s, t;
-    DBuf<double> part;       // per-workgroup partial sums of the three half-steps
+    DBuf<double> part;       // per-workgroup partial sums of the start and of the two launches
     DBuf<double> scal;       // recurrence scalars and norms
-    DBuf<int32_t> state;     // per component: status, iterations
+    DBuf<int32_t> state;     // two copies (by launch parity) of each component's status and iterations
 };
 
 // Point location on one level: a uniform grid of square cells of side h from (x0, y0),
