@@ -7,7 +7,11 @@ hand-worked cases and torch's own conversion, the analytic backward pass
 against central differences, the loss against the energy norm of the guess
 error written in the solution's units, the zero-decoder case that reduces to
 the extrapolation 2 phi^{n-1} - phi^{n-2}, homogeneity of degree one in the
-inputs, and equivariance under a renumbering of the nodes.
+inputs, and equivariance under a renumbering of the nodes.  A hand-worked
+forward pass on a two-triangle mesh (encoder, neighbour means without the node
+itself, the [h, m] order, relu(a) + h, biases, decoder) and hand-worked
+features (r_e = b - K e, K d, the RMS scales, the Dirichlet zero) fix the
+values themselves; copies of the oracle with a planted mistake miss them.
 """
 import numpy as np
 import pytest
@@ -159,3 +163,150 @@ def test_guess_is_equivariant_under_renumbering():
         mo = gnn.neighbour_mean_operator(gnn.triangle_adjacency(m.n_nodes, m.tri))
         out.append(gnn.guess(th, k, m.dirichlet, bb, q1, q2, mo, emulate=False))
     np.testing.assert_allclose(out[1], out[0][perm], rtol=1e-10, atol=1e-12 * np.abs(out[0]).max())
+
+
+# ---------------------------------------------------------------- hand-worked forward pass
+#
+# A unit square cut into the triangles (0, 1, 2) and (0, 2, 3): node 0 ~ {1, 2, 3},
+# node 1 ~ {0, 2}, node 2 ~ {0, 1, 3}, node 3 ~ {0, 2}.  Only hidden units 0 and 1 carry
+# weights; every weight is a small power-of-two multiple (exact in bfloat16), so the
+# emulated and the plain fp64 network give the same values, worked out by hand below.
+
+_SQ_TRI = np.array([[0, 1, 2], [0, 2, 3]])
+# features [b, p1, p2, r_e, K d, d, dirichlet, 1] of the four nodes (only b and p1 are weighted)
+_SQ_X = np.array([[1.0, 0.5, 0, 0, 0, 0, 0, 1],
+                  [-1.0, -1.0, 0, 0, 0, 0, 0, 1],
+                  [0.5, 1.0, 0, 0, 0, 0, 0, 1],
+                  [2.0, 0.0, 0, 0, 0, 0, 1, 1]])
+
+
+def _hand_params():
+    p = {name: np.zeros(shape) for name, shape in gnn.param_shapes()}
+    H = gnn.HIDDEN
+    # encoder: u0 = relu(b + 1/2), u1 = relu(-p1 + 1/4)
+    p["W0"][0, 0], p["c0"][0] = 1.0, 0.5
+    p["W0"][1, 1], p["c0"][1] = -1.0, 0.25
+    # layer 1 (rows 0..63 multiply h, rows 64..127 the neighbour mean m):
+    #   a0 = 2 h0 - m1 - 1,  a1 = m0 - 2 h1
+    p["W1"][0, 0], p["W1"][H + 1, 0], p["c1"][0] = 2.0, -1.0, -1.0
+    p["W1"][H + 0, 1], p["W1"][1, 1] = 1.0, -2.0
+    # layer 2: a0 = m0 - 2,  a1 = h1 - h0 + 1/2
+    p["W2"][H + 0, 0], p["c2"][0] = 1.0, -2.0
+    p["W2"][1, 1], p["W2"][0, 1], p["c2"][1] = 1.0, -1.0, 0.5
+    # layer 3: a0 = m1 - h0 + 1,  a1 = -1 (unit 1 passes through the residual)
+    p["W3"][H + 1, 0], p["W3"][0, 0], p["c3"][0] = 1.0, -1.0, 1.0
+    p["c3"][1] = -1.0
+    # decoder: y = h0 - 2 h1 + 1/8
+    p["wd"][0], p["wd"][1], p["cd"][0] = 1.0, -2.0, 0.125
+    return gnn.pack(p)
+
+
+# By hand (node order 0, 1, 2, 3):
+#   encoder   h0 = relu(b + 1/2)   = [3/2, 0, 1, 5/2]
+#             h1 = relu(1/4 - p1)  = [0, 5/4, 0, 1/4]
+#   layer 1   m0 = [(0+1+5/2)/3, (3/2+1)/2, (3/2+0+5/2)/3, (3/2+1)/2] = [7/6, 5/4, 4/3, 5/4]
+#             m1 = [(5/4+0+1/4)/3, 0, (0+5/4+1/4)/3, 0]               = [1/2, 0, 1/2, 0]
+#             a0 = 2 h0 - m1 - 1 = [3/2, -1, 1/2, 4]   -> h0 = relu(a0) + h0 = [3, 0, 3/2, 13/2]
+#             a1 = m0 - 2 h1     = [7/6, -5/4, 4/3, 3/4] -> h1 = [7/6, 5/4, 4/3, 1]
+#             (node 1, unit 1: relu(a) + h = 5/4, while relu(a + h) would be 0)
+#   layer 2   m0 = [(0+3/2+13/2)/3, (3+3/2)/2, (3+0+13/2)/3, (3+3/2)/2] = [8/3, 9/4, 19/6, 9/4]
+#             a0 = m0 - 2 = [2/3, 1/4, 7/6, 1/4]   -> h0 = [11/3, 1/4, 8/3, 27/4]
+#             a1 = h1 - h0 + 1/2 = [-4/3, 7/4, 1/3, -5] -> h1 = [7/6, 3, 5/3, 1]
+#   layer 3   m1 = [(3+5/3+1)/3, (7/6+5/3)/2, (7/6+3+1)/3, (7/6+5/3)/2] = [17/9, 17/12, 31/18, 17/12]
+#             a0 = m1 - h0 + 1 = [-7/9, 13/6, 1/18, -13/3] -> h0 = [11/3, 29/12, 49/18, 27/4]
+#             h1 unchanged = [7/6, 3, 5/3, 1]
+#   decoder   y = h0 - 2 h1 + 1/8 = [35/24, -83/24, -35/72, 39/8]
+_SQ_Y = np.array([35 / 24, -83 / 24, -35 / 72, 39 / 8])
+_SQ_H3 = np.array([[11 / 3, 7 / 6], [29 / 12, 3.0], [49 / 18, 5 / 3], [27 / 4, 1.0]])
+
+
+def _square_mean_op():
+    return gnn.neighbour_mean_operator(gnn.triangle_adjacency(4, _SQ_TRI))
+
+
+def test_forward_hand_worked_square():
+    mo = _square_mean_op()
+    th = _hand_params()
+    for emulate in (False, True):
+        y, cache = gnn.forward(th, _SQ_X, mo, emulate=emulate)
+        np.testing.assert_allclose(y, _SQ_Y, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(cache["h"][-1][:, :2], _SQ_H3, rtol=0, atol=1e-14)
+        np.testing.assert_array_equal(cache["h"][-1][:, 2:], 0.0)
+
+
+# features of the same square with a hand-written stiffness (right isosceles triangles:
+# K = [[1, -1/2, 0, -1/2], [-1/2, 1, -1/2, 0], [0, -1/2, 1, -1/2], [-1/2, 0, -1/2, 1]]),
+# node 3 Dirichlet, b = [1, 0, -1, 0], p1 = [1, 2, 0, 1], p2 = [0, 1, 1, 1]:
+#   e = 2 p1 - p2 = [2, 3, -1, 1],  d = p1 - p2 = [1, 1, -1, 0]
+#   K e = [0, 5/2, -3, 1/2]  -> r_e = b - K e = [1, -5/2, 2, -1/2]
+#   K d = [1/2, 1, -3/2, 0]
+#   s_b = sqrt(2/4), s_p = rms(p1) = sqrt(6/4), s_r = rms(r_e) = sqrt(23/8), s_d = sqrt(3/4)
+def test_features_hand_worked_square():
+    import scipy.sparse as sp
+    k = sp.csr_matrix(np.array([[1, -0.5, 0, -0.5], [-0.5, 1, -0.5, 0], [0, -0.5, 1, -0.5],
+                                [-0.5, 0, -0.5, 1]]))
+    dirichlet = np.array([0, 0, 0, 1], dtype=np.uint8)
+    b, p1, p2 = np.array([1.0, 0, -1, 0]), np.array([1.0, 2, 0, 1]), np.array([0.0, 1, 1, 1])
+    x, e, sd = gnn.features(k, dirichlet, b, p1, p2)
+    sb, sp_, sr = np.sqrt(0.5), np.sqrt(1.5), np.sqrt(23 / 8)
+    want = np.array([
+        [1 / sb, 1 / sp_, 0 / sp_, 1 / sr, 0.5 / sr, 1 / np.sqrt(0.75), 0, 1],
+        [0 / sb, 2 / sp_, 1 / sp_, -2.5 / sr, 1 / sr, 1 / np.sqrt(0.75), 0, 1],
+        [-1 / sb, 0 / sp_, 1 / sp_, 2 / sr, -1.5 / sr, -1 / np.sqrt(0.75), 0, 1],
+        [0 / sb, 1 / sp_, 1 / sp_, -0.5 / sr, 0 / sr, 0 / np.sqrt(0.75), 1, 1]])
+    np.testing.assert_allclose(x, want, rtol=1e-15, atol=1e-15)
+    np.testing.assert_array_equal(e, [2, 3, -1, 1])
+    assert sd == pytest.approx(np.sqrt(0.75), rel=1e-15)
+    # the guess before smoothing: e + s_d y on free nodes, 0 on the Dirichlet node; with only
+    # the decoder bias set, y = c_d at every node
+    p = {name: np.zeros(shape) for name, shape in gnn.param_shapes()}
+    p["cd"][0] = 2.0
+    mo = _square_mean_op()
+    g = gnn.guess(gnn.pack(p), k, dirichlet, b, p1, p2, mo, sweeps=0)
+    np.testing.assert_allclose(g, [2 + 2 * np.sqrt(0.75), 3 + 2 * np.sqrt(0.75), -1 + 2 * np.sqrt(0.75), 0.0],
+                               rtol=1e-15, atol=1e-15)
+
+
+def _mutant_forward(kind):
+    """The oracle's forward pass with one planted mistake (for the pins above to catch)."""
+    def fwd(theta, x, mean_op, emulate=True):
+        p = gnn.unpack(theta)
+        h = np.maximum(x @ p["W0"][:gnn.F_IN] + (0.0 if kind == "nobias" else p["c0"]), 0.0)
+        for l in range(1, gnn.LAYERS + 1):
+            m = mean_op @ h
+            z = np.concatenate([m, h] if kind == "swap" else [h, m], axis=1)
+            a = z @ p[f"W{l}"] + (0.0 if kind == "nobias" else p[f"c{l}"])
+            h = np.maximum(a + h, 0.0) if kind == "relu_sum" else np.maximum(a, 0.0) + h
+        return h @ p["wd"] + p["cd"][0], None
+    return fwd
+
+
+@pytest.mark.parametrize("kind", ["relu_sum", "swap", "nobias"])
+def test_planted_forward_mistakes_fail_the_hand_pin(kind):
+    y, _ = _mutant_forward(kind)(_hand_params(), _SQ_X, _square_mean_op())
+    assert np.abs(y - _SQ_Y).max() > 1e-3
+    # and the unmutated copy reproduces the oracle (so the mutant differs by its mistake only)
+    y0, _ = _mutant_forward("none")(_hand_params(), _SQ_X, _square_mean_op())
+    np.testing.assert_allclose(y0, gnn.forward(_hand_params(), _SQ_X, _square_mean_op(), emulate=False)[0],
+                               rtol=0, atol=1e-14)
+
+
+def test_planted_feature_mistake_fails_the_hand_pin():
+    """The oracle's feature map with r_e = b + K e planted in place of b - K e misses the
+    hand-worked features above."""
+    import scipy.sparse as sp
+    k = sp.csr_matrix(np.array([[1, -0.5, 0, -0.5], [-0.5, 1, -0.5, 0], [0, -0.5, 1, -0.5],
+                                [-0.5, 0, -0.5, 1]]))
+    dirichlet = np.array([0, 0, 0, 1], dtype=np.uint8)
+    b, p1, p2 = np.array([1.0, 0, -1, 0]), np.array([1.0, 2, 0, 1]), np.array([0.0, 1, 1, 1])
+
+    class Planted:
+        def __matmul__(self, v):      # b - (K @ e) becomes b - (-K e) = b + K e for the first product
+            Planted.calls += 1
+            return -(k @ v) if Planted.calls == 1 else k @ v
+    Planted.calls = 0
+    x_bad, _, _ = gnn.features(Planted(), dirichlet, b, p1, p2)
+    x_ok, _, _ = gnn.features(k, dirichlet, b, p1, p2)
+    want_re = np.array([1, -2.5, 2, -0.5]) / np.sqrt(23 / 8)
+    np.testing.assert_allclose(x_ok[:, 3], want_re, rtol=1e-15)
+    assert np.abs(x_bad[:, 3] - want_re).max() > 0.1
