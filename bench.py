@@ -79,24 +79,29 @@ def kernel_fingerprint() -> str:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="timed CGP time steps")
-    ap.add_argument("--warmup", type=int, default=10, help="untimed steps before the timed ones")
-    ap.add_argument("--nx", type=int, default=513)
-    ap.add_argument("--ny", type=int, default=257)
+    ap.add_argument("--steps", type=int, default=None, help="timed CGP time steps (c5: 20, sequence: 200)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps before the timed ones (c5: 5, "
+                                                             "sequence: 10)")
+    ap.add_argument("--nx", type=int, default=None, help="coarse grid nodes along x (c5: 1025, sequence: 513)")
+    ap.add_argument("--ny", type=int, default=None, help="coarse grid nodes along y (c5: 513, sequence: 257)")
+    ap.add_argument("--batch", type=int, default=8, help="c5: instances per batched solve")
     ap.add_argument("--stuart", type=float, default=1.0, help="Stuart number N (sigma of the Lorentz force)")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample: steps (2 solves each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="ABCDEF")
+    ap.add_argument("--forms", default=None, help="forms to run (c5: ABCD, sequence: ABCDEF)")
     ap.add_argument("--deflation", type=int, default=1, choices=[0, 1], help="deflation in forms B, C, D")
     ap.add_argument("--degree", type=int, default=6, help="Chebyshev preconditioner degree of forms B, C, D, F")
     ap.add_argument("--refine-delta", type=float, default=1e-3,
                     help="fp32 Chebyshev forms: refine when the fp32 residual fell by this factor since the last "
                          "refinement (the Jacobi forms keep the library's default, 0.1)")
-    ap.add_argument("--train-steps", type=int, default=200, help="steps solved (fp64) to train the networks")
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=None,
+                    help="steps solved (fp64) to train the networks (c5: 100, sequence: 200)")
+    ap.add_argument("--epochs", type=int, default=None, help="training epochs (c5: 6, sequence: 8)")
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "momentum", "interpolate", "channel"],
-                    help="sequence: one 513x257 CGP sequence (default); batch: 64-instance Stuart sweep; "
+    ap.add_argument("--workload", default="c5",
+                    choices=["c5", "sequence", "batch", "momentum", "interpolate", "channel"],
+                    help="c5: two-level CGP on batches of 8 Stuart numbers, coarse 1025x513, fine k=2 "
+                         "(default); sequence: one 513x257 CGP sequence; batch: 64-instance Stuart sweep; "
                          "momentum: the fine-mesh momentum step of Eqs. 13-14; interpolate: the restriction "
                          "of a fine field onto the nodes of a non-nested coarse mesh by point location; channel: "
                          "whole CGP time steps of the flow past a cylinder (Section 3), with drag and lift")
@@ -107,7 +112,14 @@ def parse():
     ap.add_argument("--instances", type=int, default=64, help="batch: number of instances")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
-    return ap.parse_args()
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    c5 = args.workload == "c5"
+    for name, v5, vs in (("steps", 20, 200), ("warmup", 5, 10), ("forms", "ABCD", "ABCDEF"),
+                         ("train_steps", 100, 200), ("epochs", 6, 8)):
+        if getattr(args, name) is None:
+            setattr(args, name, v5 if c5 else vs)
+    return args
 
 
 def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extrap: bool,
@@ -331,7 +343,7 @@ def momentum_main(args):
 
     dev = torch.device("cuda:0")
     f64 = dict(dtype=torch.float64, device=dev)
-    nx, ny = args.nx, args.ny
+    nx, ny = args.nx or 513, args.ny or 257
     coarse = ci.jittered_rect(nx, ny, 2000)
     ctx = cgp.Context(0)
     h = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 1)
@@ -434,7 +446,7 @@ def interpolate_main(args):
     import paper_2003_00082_amd as cgp
 
     dev = torch.device("cuda:0")
-    nx, ny = args.nx, args.ny
+    nx, ny = args.nx or 513, args.ny or 257
     coarse = ci.jittered_rect(nx, ny, 2000)
     target = ci.jittered_rect(nx, ny, 3001)          # same domain, interior nodes jittered apart
     ctx = cgp.Context(0)
@@ -668,12 +680,391 @@ def channel_main(args):
     ctx.close()
 
 
+def c5_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool) -> float:
+    """Algorithmic HBM bytes of one solve by the per-iteration figures: a CG iteration reads
+    the matrix once (value + int32 column per entry) and the recurrence vectors of its rows,
+    8 nnz + 52 n in fp32 (values 4 B; r, w, s, D^-1, u, p, c read and r, w, s, u, p, c
+    written), 12 nnz + 100 n in fp64; a refinement (fp32 with fp64 refinement) adds one fp64
+    residual, 12 nnz + 28 n (matrix, x and b in, r out)."""
+    it = (8 * nnz + 52 * n) if mixed else (12 * nnz + 100 * n)
+    return float(iters * it + refinements * (12 * nnz + 28 * n))
+
+
+def c5_main(args):
+    """Two-level CGP on batches of Stuart numbers (the default workload).
+
+    ``--batch`` (8) instances, each a coarse 1025 x 513 jittered P1 mesh of [0,2]x[0,1]
+    (525825 nodes, nnz 3656209; mesh seed 5000 + i) refined twice (4097 x 2049 = 8394753
+    fine nodes), its own drifting 8-mode Fourier flow (mode seeds 5500 + i, 5700 + i,
+    evaluated on the device), Stuart numbers log-spaced over [0.1, 10].  A step is the whole
+    hot path for every instance: restrict + curl source (Eq. 19, Eq. 12) -> ONE batched phi
+    solve of all instances -> prolong (Eq. 20) -> Lorentz force (Eqs. 13-14) -> restrict +
+    divergence source (Eq. 15) -> ONE batched p solve -> prolong -> velocity correction
+    (Eqs. 16-17); both solves to a true relative residual of 1e-8.  Forms: A plain fp64
+    Jacobi-PCG from the previous solution; B the learned guess + fp32 CG refined in fp64,
+    Chebyshev degree d, deflated; C as B from the extrapolation; D fp64, Chebyshev degree d,
+    deflated, from the previous solution."""
+    import numpy as np
+    import torch
+
+    import cgp_inputs as ci
+    import paper_2003_00082_amd as cgp
+
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    M = args.batch
+    nx = args.nx or 1025
+    ny = args.ny or 513
+    kf = 2
+    W, K = args.warmup, args.steps
+    TR = args.train_steps if any(f in args.forms for f in "B") else 0
+    ctx = cgp.Context(0)
+    stream = torch.cuda.current_stream()
+    H, nc, nnz, nf = [], [], [], []
+    t_setup = time.perf_counter()
+    seqs = []
+    coarse0 = None
+    for i in range(M):
+        m = ci.jittered_rect(nx, ny, 5000 + i)
+        if i == 0:
+            coarse0 = m
+        h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, kf)
+        H.append(h)
+        i0, i2 = ctx.mesh_info(h, 0), ctx.mesh_info(h, kf)
+        nc.append(i0["n_nodes"])
+        nnz.append(i0["nnz"])
+        nf.append(i2["n_nodes"])
+        xy_f = torch.from_numpy(ctx.mesh_download(h, kf)[0]).to(dev)
+        seqs.append(ci.DeviceFourierSequence(xy_f, ci.fourier_modes(5500 + i), ci.fourier_modes(5700 + i)))
+    gbytes = (W + K) * M * 4 * nf[0] * 8 / 1e9
+    if gbytes > 160:
+        raise SystemExit(f"{W + K} resident steps would take {gbytes:.0f} GB of inputs; use fewer --steps")
+    vel = {n: [seqs[i].at(n) for i in range(M)] for n in range(-W, K)}   # inputs resident in HBM
+    sig = ci.stuart_numbers(M)
+    rho_dt = 1.0 / ci.DT
+    bphi = [torch.empty(n, **f64) for n in nc]
+    bp = [torch.empty(n, **f64) for n in nc]
+    qf = [torch.empty(n, **f64) for n in nf]
+    fx = [torch.empty(n, **f64) for n in nf]
+    fy = [torch.empty(n, **f64) for n in nf]
+    un = [torch.empty(n, **f64) for n in nf]
+    vn = [torch.empty(n, **f64) for n in nf]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+
+    # ---- networks for form B: fp64 solutions of instance 0 over the TR steps before the warm-up
+    models, train_info = {}, None
+    if TR > 0:
+        t0 = time.perf_counter()
+        sols = {"phi": [], "p": []}
+        rhs_t = {"phi": [], "p": []}
+        x = {"phi": torch.zeros(nc[0], **f64), "p": torch.zeros(nc[0], **f64)}
+        st1 = cgp.stats_buffer(1)
+        for n in range(-W - TR, -W):
+            u, v, ut, vt = seqs[0].at(n)
+            for eq, kind, uu, vv, sc in (("phi", cgp.CGP_SRC_CURL, u, v, 1.0),
+                                         ("p", cgp.CGP_SRC_DIV, ut, vt, rho_dt)):
+                bb = torch.empty(nc[0], **f64)
+                ctx.restrict(H[0], uu, vv, kind, sc, bb)
+                ctx.poisson_solve([H[0]], [bb], [x[eq]], st1, guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64,
+                                  tol=1e-10, precond_degree=args.degree, deflation=1)
+                rhs_t[eq].append(bb)
+                sols[eq].append(x[eq].clone())
+            del u, v, ut, vt
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        hist = {}
+        for j, eq in enumerate(("phi", "p")):
+            md = ctx.model_create(seed=11 + j)
+            S, Bv = sols[eq], rhs_t[eq]
+            idx = range(2, len(S))
+            hist[eq] = ctx.model_train(md, H[0], [Bv[q] for q in idx], [S[q - 1] for q in idx],
+                                       [S[q - 2] for q in idx], [S[q] for q in idx], epochs=args.epochs,
+                                       lr=args.lr, seed=5 + j)
+            models[eq] = md
+        torch.cuda.synchronize()
+        train_info = {"train_steps": TR, "samples_per_network": TR - 2, "trained_on": "instance 0",
+                      "epochs": args.epochs, "lr": args.lr, "data_s": t_data,
+                      "train_s": time.perf_counter() - t0,
+                      "loss_first_epoch": {k: float(v[0]) for k, v in hist.items()},
+                      "loss_last_epoch": {k: float(v[-1]) for k, v in hist.items()}}
+        del sols, rhs_t
+
+    deg = args.degree
+    forms = {   # precision, guess, preconditioner degree (0 = Jacobi, row-range kernel), deflation
+        "A": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, 0, 0),
+        "B": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, deg, 1),
+        "C": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, deg, 1),
+        "D": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, deg, 1),
+    }
+    dtype_st = np.dtype([("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"),
+                         ("rel0", "f8")])
+
+    def run(form: str):
+        prec, guess, fdeg, fdefl = forms[form]
+        mixed = prec == cgp.CGP_FP32_IR
+        rotating = guess in (cgp.CGP_GUESS_EXTRAP, cgp.CGP_GUESS_LEARNED)
+        bufs = {eq: [[torch.zeros(n, **f64) for n in nc] for _ in range(3 if rotating else 1)]
+                for eq in ("phi", "p")}
+        nsl = 2 * (W + 2 * K)
+        stats = torch.zeros(nsl * M * cgp.STATS_BYTES, dtype=torch.uint8, device=dev)
+        keep = {}
+
+        def solve(eq, bvecs, n, slot):
+            Bq = bufs[eq]
+            kw = dict(precision=prec, guess=guess, precond_degree=fdeg, deflation=fdefl,
+                      refine_delta=args.refine_delta if fdeg >= 2 else 0.0)
+            if rotating:
+                cur, p1, p2 = Bq[n % 3], Bq[(n - 1) % 3], Bq[(n - 2) % 3]
+                kw.update(prev1=p1, prev2=p2)
+                if guess == cgp.CGP_GUESS_LEARNED:
+                    kw.update(model=models[eq])
+            else:
+                cur = Bq[0]
+            st = stats[slot * M * cgp.STATS_BYTES:(slot + 1) * M * cgp.STATS_BYTES]
+            ctx.poisson_solve(H, bvecs, cur, st, tol=TOL, **kw)
+            return cur
+
+        def step(n, slot):
+            for i in range(M):
+                u, v, _, _ = vel[n][i]
+                ctx.restrict(H[i], u, v, cgp.CGP_SRC_CURL, 1.0, bphi[i])
+            phi = solve("phi", bphi, n, slot)
+            for i in range(M):
+                u, v, ut, vt = vel[n][i]
+                ctx.prolong(H[i], phi[i], qf[i])
+                ctx.lorentz_force(H[i], qf[i], u, v, float(sig[i]), 1.0, fx[i], fy[i])
+                ctx.restrict(H[i], ut, vt, cgp.CGP_SRC_DIV, rho_dt, bp[i])
+            p = solve("p", bp, n, slot + 1)
+            for i in range(M):
+                _, _, ut, vt = vel[n][i]
+                ctx.prolong(H[i], p[i], qf[i])
+                ctx.velocity_correct(H[i], qf[i], ut, vt, 1.0 / rho_dt, un[i], vn[i])
+            if n == 0 and "phi" not in keep:
+                keep["phi"], keep["p"] = phi[0].clone(), p[0].clone()
+
+        for q, n in enumerate(range(-W, 0)):
+            step(n, 2 * q)
+        torch.cuda.synchronize()
+        l0 = ctx.stage_launches
+        t0 = time.perf_counter()
+        for n in range(K):
+            step(n, 2 * (W + n))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        launches = ctx.stage_launches - l0
+        # the stage kernels' own durations: the timed steps once more, each kernel between HIP events
+        timing = None
+        if fdeg >= 1 or form == "A":
+            ctx.stage_timing(True)
+            for n in range(K):
+                step(n, 2 * (W + K + n))
+            torch.cuda.synchronize()
+            timing = ctx.stage_timing_read()
+            ctx.stage_timing(False)
+        gnn_us = None
+        if guess == cgp.CGP_GUESS_LEARNED:
+            g = torch.empty(nc[0], **f64)
+            Bq = bufs["phi"]
+            reps = 10
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                ctx.model_predict(models["phi"], H[0], bphi[0], Bq[0][0], Bq[1][0], g)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gnn_us = 1e3 * e0.elapsed_time(e1) / reps
+        host = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=dtype_st).reshape(nsl, M)
+        timed = host[2 * W:2 * (W + K)]
+        rerun = host[2 * (W + K):]
+        ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
+        out = {
+            "solves_per_s": 2 * M * K / elapsed,
+            "ms_per_step": 1e3 * elapsed / K,
+            "mean_iters": float(timed["iters"].mean()),
+            "max_iters": int(timed["iters"].max()),
+            "mean_refinements": float(timed["ref"].mean()),
+            "max_rel_res": float(timed["rel"].max()),
+            "mean_guess_rel_res": float(timed["rel0"].mean()),
+            "learned_guess_kept": (float(np.mean(timed["guess"] == cgp.CGP_GUESS_LEARNED))
+                                   if guess == cgp.CGP_GUESS_LEARNED else None),
+            "precision": "fp32+fp64 refinement" if mixed else "fp64",
+            "preconditioner": (f"Chebyshev degree {fdeg}" if fdeg >= 2 else "Jacobi") +
+                              (", deflated" if fdefl else ""),
+            "guess": {cgp.CGP_GUESS_GIVEN: "previous solution", cgp.CGP_GUESS_EXTRAP: "extrapolation",
+                      cgp.CGP_GUESS_LEARNED: "learned"}[guess],
+            "all_converged": ok,
+            "stage_launches_per_step": launches / K,
+            "gnn_predict_us_per_instance": gnn_us,
+            "step0": {k: v.cpu().numpy() for k, v in keep.items()},
+        }
+        if timing is not None and timing["stage_launches"] > 0:
+            alg = sum(c5_bytes(nc[i], nnz[i], int(rerun["iters"][s, i]), int(rerun["ref"][s, i]), mixed)
+                      for s in range(2 * K) for i in range(M))
+            iters = int(rerun["iters"].sum())
+            out["kernel_timing"] = {
+                "stage_launches": timing["stage_launches"],
+                "stage_avg_us": timing["stage_us"] / timing["stage_launches"],
+                "coarse_launches": timing["coarse_launches"],
+                "coarse_avg_us": (timing["coarse_us"] / timing["coarse_launches"]
+                                  if timing["coarse_launches"] else None),
+                "cg_iterations": iters,
+                "iterations_per_launch": iters / timing["stage_launches"],
+                "algorithmic_bytes": alg,
+                "achieved_GBs": alg / (timing["stage_us"] * 1e-6) / 1e9,
+            }
+        return out
+
+    res = {}
+    for f in args.forms:
+        res[f] = run(f)
+        print(json.dumps({"form": f, "solves_per_s": res[f]["solves_per_s"], "mean_iters": res[f]["mean_iters"]}),
+              file=sys.stderr, flush=True)
+    main_form = "B" if "B" in res else args.forms[0]
+    R = res[main_form]
+
+    cpu = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        from oracle import fem, solve
+        nc0 = nc[0]
+        a = fem.system_matrix(coarse0.xy, coarse0.tri, coarse0.dirichlet)
+
+        def rhs_phi(n):
+            u, v, _, _ = seqs[0].at(n)
+            return fem.source(coarse0.xy, coarse0.tri, coarse0.dirichlet, u[:nc0].cpu().numpy(),
+                              v[:nc0].cpu().numpy(), fem.CURL, 1.0)
+
+        b_prev, b0 = rhs_phi(-1), rhs_phi(0)
+        t0 = time.perf_counter()
+        import scipy.sparse.linalg as spla
+        lu = spla.splu(a.tocsc())
+        exact_prev, exact0 = lu.solve(b_prev), lu.solve(b0)
+        direct_s = time.perf_counter() - t0
+        for f, r in res.items():
+            errs[f] = float(np.linalg.norm(r["step0"]["phi"] - exact0) / np.linalg.norm(exact0))
+        t0 = time.perf_counter()
+        x, inf = solve.pcg(a, b0, exact_prev, tol=TOL)
+        cpu_t = time.perf_counter() - t0
+        cpu = {"value": 1.0 / cpu_t, "unit": "solves/s", "cores": solve.threads(), "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": f"fp64 Jacobi-PCG (C, OpenMP) of instance 0's phi solve at step 0 from the exact "
+                         f"previous solution (form A's algorithm on one {nc0}-row instance): "
+                         f"{inf['iters']} iterations, {cpu_t:.1f} s; the exact solutions by SuperLU took "
+                         f"{direct_s:.1f} s (not timed)",
+               "err_vs_superlu": float(np.linalg.norm(x - exact0) / np.linalg.norm(exact0))}
+        one = one_thread_sample(a, b0, exact_prev)
+        if one is not None:
+            cpu["one_thread"] = one
+
+    tname = "float" if forms[main_form][0] == cgp.CGP_FP32_IR else "double"
+    kt = R.get("kernel_timing") or {}
+    kname = (f"k_cg_tile<{tname}, 8, true, false>" if forms[main_form][2] >= 1
+             else f"k_cg_step<{tname}, 4, false>")
+    traffic = None
+    out = {
+        "metric": METRIC,
+        "value": R["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": R["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": ("f32+f64" if forms[main_form][0] == cgp.CGP_FP32_IR else "f64") +
+                 (" (network bf16)" if main_form == "B" else ""),
+        "data": "synthetic",
+        "config": {"workload": f"two-level CGP, batches of {M} Stuart numbers: coarse {nx}x{ny} jittered P1 "
+                               f"({nc[0]} nodes, nnz {nnz[0]}) per instance, fine k={kf} ({nf[0]} nodes), "
+                               f"{K}-step drifting 8-mode Fourier flow per instance, phi and p solves of all "
+                               f"instances batched, to {TOL:g} true relative residual",
+                   "instances": M, "coarse_nodes": nc[0], "fine_nodes": nf[0], "nnz": nnz[0], "k": kf,
+                   "tol": TOL, "stuart": [float(s) for s in sig]},
+        "forms": {f: {k: v for k, v in r.items() if k != "step0"} | {"phi_err_vs_superlu_step0": errs.get(f)}
+                  for f, r in res.items()},
+        "speedup_over_A": ({f: res[f]["solves_per_s"] / res["A"]["solves_per_s"] for f in res}
+                           if "A" in res else None),
+        "preconditioner_degree": deg,
+        "training": train_info,
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm",
+                     "achieved": kt.get("achieved_GBs"),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (kt["achieved_GBs"] / HBM_PEAK_GBS) if kt else None,
+                     "traffic": traffic,
+                     "kernel": kname,
+                     "kernel_avg_us": kt.get("stage_avg_us"),
+                     "bytes_model": "per CG iteration and instance 8 nnz + 52 n (fp32) or 12 nnz + 100 n "
+                                    "(fp64), per refinement 12 nnz + 28 n; achieved = these bytes of the "
+                                    "re-timed steps / the summed HIP-event durations of the stage kernel",
+                     "iterations_per_launch": kt.get("iterations_per_launch")},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def one_thread_sample(a, b, x0, max_iter: int = 300):
+    """The oracle's fp64 Jacobi-PCG on one thread, bounded to ``max_iter`` iterations, in a child
+    process started with OMP_NUM_THREADS=1 (the OpenMP thread count is fixed when the oracle's
+    C part loads).  Returns seconds per iteration and the iterations run, or None on failure."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    a = a.tocsr()
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "sample.npz")
+        np.savez(path, indptr=a.indptr, indices=a.indices, data=a.data, b=b, x0=x0,
+                 max_iter=np.array([max_iter]))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker", path], env=env,
+                           capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_worker(path: str):
+    """Child of one_thread_sample: time the oracle's PCG on the saved system."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    from oracle import solve
+    z = np.load(path)
+    n = z["b"].size
+    a = sp.csr_matrix((z["data"], z["indices"], z["indptr"]), shape=(n, n))
+    t0 = time.perf_counter()
+    _, inf = solve.pcg(a, z["b"], z["x0"], tol=1e-300, max_iter=int(z["max_iter"][0]))
+    dt = time.perf_counter() - t0
+    print(json.dumps({"threads": solve.threads(), "iterations": inf["iters"], "seconds": dt,
+                      "seconds_per_iteration": dt / max(inf["iters"], 1)}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances of a batch or "
               "mesh partitions would shard across GPUs; the library drives one GPU.", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_worker:
+        return cpu_worker(args.cpu_worker)
+    if args.workload == "c5":
+        return c5_main(args)
     if args.workload == "batch":
         if args.steps == 200:
             args.steps = 6
@@ -699,7 +1090,7 @@ def main():
     import paper_2003_00082_amd as cgp
 
     dev = torch.device("cuda:0")
-    nx, ny = args.nx, args.ny
+    nx, ny = args.nx or 513, args.ny or 257
     coarse = ci.jittered_rect(nx, ny, 2000)
     ctx = cgp.Context(0)
     h = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 1)

@@ -50,6 +50,7 @@ __all__ = [
     "stream_velocity",
     "potential_velocity",
     "FourierSequence",
+    "DeviceFourierSequence",
     "stuart_numbers",
     "batch_sizes",
     "Channel",
@@ -265,6 +266,44 @@ class FourierSequence:
         ut = u - s2 @ (c2["c"] * c2["kx"])
         vt = v - s2 @ (c2["c"] * c2["ky"])
         return u, v, ut, vt
+
+
+class DeviceFourierSequence:
+    """The flow of ``FourierSequence`` evaluated with torch on a device, for point sets too
+    large to tabulate on the host (the 8.39M nodes of a twice-refined 1025 x 513 mesh).
+
+    ``xy`` is an ``[n, 2]`` float64 tensor on the device; ``at(n)`` returns four device
+    tensors ``(u, v, u + chi_x, v + chi_y)`` at time ``n * DT``, computed directly from the
+    mode sums (sin of the full phase, not the host class's expansion, so values agree with
+    ``FourierSequence`` to rounding, not bitwise).
+    """
+
+    def __init__(self, xy, modes: dict, chi_modes: dict):
+        import torch
+        self.xy = xy
+        self.sets = []
+        for md in (modes, chi_modes):
+            t = {k: torch.tensor(np.asarray(v, dtype=np.float64), device=xy.device) for k, v in md.items()}
+            self.sets.append(t)
+
+    def _sin(self, which: int, t: float):
+        md = self.sets[which]
+        ph = (self.xy[:, 0:1] * md["kx"][None, :] + self.xy[:, 1:2] * md["ky"][None, :]
+              + md["theta"][None, :] + md["omega"][None, :] * t)
+        return ph.sin_()
+
+    def at(self, n: int):
+        t = n * DT
+        s = self._sin(0, t)
+        m = self.sets[0]
+        u = -(s @ (m["c"] * m["ky"]))
+        v = s @ (m["c"] * m["kx"])
+        del s
+        s2 = self._sin(1, t)
+        c2 = self.sets[1]
+        ut = u - s2 @ (c2["c"] * c2["kx"])
+        vt = v - s2 @ (c2["c"] * c2["ky"])
+        return u.contiguous(), v.contiguous(), ut.contiguous(), vt.contiguous()
 
 
 def stuart_numbers(count: int) -> np.ndarray:

@@ -190,7 +190,7 @@ typedef struct {
                              aggregates per tile), x0 is corrected so that Z^T r = 0 and each
                              direction is made K-orthogonal to range(Z) (Nicolaides;
                              Saad, Yeung, Erhel, Guyomarc'h).  Needs the tiled iteration
-                             (CGP_ENGINE_STAGED or AUTO), at most 1024 aggregates per mesh,
+                             (CGP_ENGINE_STAGED or AUTO), at most 2048 aggregates per mesh,
                              rows coupled to at most 4 aggregates: CGP_E_UNSUPPORTED
                              otherwise.  E = Z^T K Z is inverted on the host on first use
                              per mesh. */
@@ -242,6 +242,18 @@ cgp_status cgp_solve_check(cgp_ctx ctx, int32_t n_inst, const cgp_solve_stats *d
  * (including the launches of the last replayed graph that found every instance
  * already finished); for averaging per-launch time. */
 int64_t cgp_stage_launches(cgp_ctx ctx);
+/* Stage timing, for measuring the solver's kernels (not for production runs).  With
+ * enable = 1 (which also zeroes the totals) the staged engine enqueues the stage kernels of
+ * later solves one by one on the context's stream, in the same chunks it would replay as
+ * graphs, with a HIP event before the first kernel of a chunk and after every kernel; the
+ * call waits for each chunk and adds each kernel's event-to-event time to the totals (the
+ * tiled or row-range stage kernel, and the deflation coarse step).  Results are the same as
+ * without timing.  enable = 0 returns to graph replay.  Not during graph capture. */
+cgp_status cgp_stage_timing(cgp_ctx ctx, int32_t enable);
+/* Totals since timing was enabled: stage-kernel launches and their summed duration (us),
+ * coarse-step launches and theirs.  Any output may be NULL. */
+cgp_status cgp_stage_timing_read(cgp_ctx ctx, int64_t *h_stage_launches, double *h_stage_us,
+                                 int64_t *h_coarse_launches, double *h_coarse_us);
 /* Pick spmv_lanes per mesh by timing the solver's matrix-vector stage on the
  * device (one entry per mesh in h_lanes_out, also remembered by the mesh and
  * used when cgp_solve_opts.spmv_lanes == 0).  Synchronous. */

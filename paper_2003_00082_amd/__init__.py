@@ -82,6 +82,9 @@ _SIGS = {
     "cgp_last_error": ([], ctypes.c_char_p),
     "cgp_device_cus": ([_vp], _i32),
     "cgp_stage_launches": ([_vp], _i64),
+    "cgp_stage_timing": ([_vp, _i32], _i32),
+    "cgp_stage_timing_read": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_f64), ctypes.POINTER(_i64),
+                               ctypes.POINTER(_f64)], _i32),
     "cgp_mesh_upload": ([_vp, _vp, _i64, _vp, _i64, _vp, _i32, ctypes.POINTER(_i32)], _i32),
     "cgp_mesh_info": ([_vp, _i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                        ctypes.POINTER(_i64)], _i32),
@@ -191,6 +194,17 @@ class Context:
     @property
     def stage_launches(self) -> int:
         return int(load().cgp_stage_launches(self.handle))
+
+    def stage_timing(self, enable: bool):
+        """Enable (resetting the totals) or disable the per-kernel timing of the staged solver."""
+        _check(load().cgp_stage_timing(self.handle, 1 if enable else 0))
+
+    def stage_timing_read(self) -> dict:
+        nl, us, ncl, cus = _i64(), _f64(), _i64(), _f64()
+        _check(load().cgp_stage_timing_read(self.handle, ctypes.byref(nl), ctypes.byref(us), ctypes.byref(ncl),
+                                            ctypes.byref(cus)))
+        return {"stage_launches": nl.value, "stage_us": us.value, "coarse_launches": ncl.value,
+                "coarse_us": cus.value}
 
     # ---------------------------------------------------------------- meshes
     def mesh_upload(self, xy, tri, dirichlet, k_levels: int) -> int:

@@ -85,6 +85,11 @@ struct cgp_ctx_s {
     uint64_t timeout_ticks = 0;
     int64_t stage_launches = 0;
     bool capturing = false;
+    // stage timing (cgp_stage_timing): stage kernels launched one by one between HIP events
+    bool time_stages = false;
+    std::vector<hipEvent_t> tev;
+    int64_t timed_launches[2] = {0, 0};   // stage kernels, coarse kernels
+    double timed_us[2] = {0.0, 0.0};
 };
 
 namespace {
@@ -220,6 +225,7 @@ cgp_status cgp_destroy(cgp_ctx ctx) {
         ctx->plans.clear();
         ctx->models.clear();
         if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+        for (auto &e : ctx->tev) (void)hipEventDestroy(e);
         for (auto &e : ctx->chunk_ev)
             if (e) (void)hipEventDestroy(e);
         if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
@@ -246,6 +252,30 @@ cgp_status cgp_sync(cgp_ctx ctx) {
 int32_t cgp_device_cus(cgp_ctx ctx) { return ctx ? ctx->cus : 0; }
 
 int64_t cgp_stage_launches(cgp_ctx ctx) { return ctx ? ctx->stage_launches : 0; }
+
+cgp_status cgp_stage_timing(cgp_ctx ctx, int32_t enable) {
+    return guarded([&] {
+        CGP_REQUIRE(ctx != nullptr, "null context");
+        CGP_REQUIRE(enable == 0 || enable == 1, "enable must be 0 or 1");
+        CGP_REQUIRE(!ctx->capturing, "stage timing cannot change during graph capture");
+        ctx->time_stages = enable == 1;
+        if (enable) {
+            ctx->timed_launches[0] = ctx->timed_launches[1] = 0;
+            ctx->timed_us[0] = ctx->timed_us[1] = 0.0;
+        }
+    });
+}
+
+cgp_status cgp_stage_timing_read(cgp_ctx ctx, int64_t *h_stage_launches, double *h_stage_us,
+                                 int64_t *h_coarse_launches, double *h_coarse_us) {
+    return guarded([&] {
+        CGP_REQUIRE(ctx != nullptr, "null context");
+        if (h_stage_launches) *h_stage_launches = ctx->timed_launches[0];
+        if (h_stage_us) *h_stage_us = ctx->timed_us[0];
+        if (h_coarse_launches) *h_coarse_launches = ctx->timed_launches[1];
+        if (h_coarse_us) *h_coarse_us = ctx->timed_us[1];
+    });
+}
 
 // ------------------------------------------------------------------ meshes
 
@@ -723,25 +753,36 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             }
             // staged: graphs of stage launches (an even count each, so that the buffer parity runs
             // on from one graph to the next), replayed until every instance is done
+            // `count` stage launches (and with deflation the coarse step after each) on stream st;
+            // ev (optional, 1 + kernels events): recorded before the first kernel and after each
+            const int kps = (tiled && defl) ? 2 : 1;
+            auto enqueue = [&](int count, hipStream_t st, hipEvent_t *ev) {
+                if (ev) CGP_HIP(hipEventRecord(ev[0], st));
+                for (int l = 0; l < count; ++l) {
+                    if (tiled) {
+                        launch_cg_tile(st, o.precision == CGP_FP32_IR, tp[g0]->width, defl, gn, plan->d_insts,
+                                       gn == 1 ? &plan->one : nullptr,
+                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
+                                       plan->d_done, ctx->host_flag_dev);
+                        if (ev) CGP_HIP(hipEventRecord(ev[kps * l + 1], st));
+                        if (defl) {
+                            launch_cg_coarse(st, gn == 1 ? plan->crecs.data() : nullptr, plan->d_crecs,
+                                             plan->d_cblk_inst, plan->cgrid, l & 1);
+                            if (ev) CGP_HIP(hipEventRecord(ev[kps * l + 2], st));
+                        }
+                    } else {
+                        launch_cg_step(st, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
+                                       gn == 1 ? &plan->one : nullptr,
+                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
+                                       plan->d_done, ctx->host_flag_dev);
+                        if (ev) CGP_HIP(hipEventRecord(ev[l + 1], st));
+                    }
+                }
+            };
             auto capture = [&](int count, hipGraph_t &graph, hipGraphExec_t &exec) {
                 // the launch template is recorded on the private stream (the caller's may be the null stream)
                 CGP_HIP(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeRelaxed));
-                for (int l = 0; l < count; ++l) {
-                    if (tiled) {
-                        launch_cg_tile(ctx->aux, o.precision == CGP_FP32_IR, tp[g0]->width, defl, gn, plan->d_insts,
-                                       gn == 1 ? &plan->one : nullptr,
-                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
-                                       plan->d_done, ctx->host_flag_dev);
-                        if (defl)
-                            launch_cg_coarse(ctx->aux, gn == 1 ? plan->crecs.data() : nullptr, plan->d_crecs,
-                                             plan->d_cblk_inst, plan->cgrid, l & 1);
-                    } else {
-                        launch_cg_step(ctx->aux, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
-                                       gn == 1 ? &plan->one : nullptr,
-                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
-                                       plan->d_done, ctx->host_flag_dev);
-                    }
-                }
+                enqueue(count, ctx->aux, nullptr);
                 CGP_HIP(hipStreamEndCapture(ctx->aux, &graph));
                 CGP_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             };
@@ -762,6 +803,34 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             int64_t issued = 0;
             int64_t chunk = 0;
             bool finished = false;
+            if (ctx->time_stages) {
+                // the same chunks, enqueued launch by launch between events; each chunk is waited
+                // for and its kernels' durations added up before the next one is enqueued
+                while (!*flag) {
+                    if (issued >= max_stages + 2 * plan->launches)
+                        throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
+                    const bool tail = plan->tail_exec && predicted > 0 && issued + plan->launches > predicted;
+                    const int count = tail ? TAIL_LAUNCHES : plan->launches;
+                    const size_t nev = static_cast<size_t>(kps) * count + 1;
+                    while (ctx->tev.size() < nev) {
+                        hipEvent_t e;
+                        CGP_HIP(hipEventCreate(&e));
+                        ctx->tev.push_back(e);
+                    }
+                    enqueue(count, ctx->stream, ctx->tev.data());
+                    CGP_HIP(hipEventSynchronize(ctx->tev[nev - 1]));
+                    for (size_t q = 1; q < nev; ++q) {
+                        float msec = 0.f;
+                        CGP_HIP(hipEventElapsedTime(&msec, ctx->tev[q - 1], ctx->tev[q]));
+                        const int kind = (kps == 2 && (q % 2) == 0) ? 1 : 0;
+                        ctx->timed_us[kind] += 1e3 * static_cast<double>(msec);
+                        ++ctx->timed_launches[kind];
+                    }
+                    ctx->stage_launches += count;
+                    issued += count;
+                }
+                finished = true;
+            }
             while (!finished) {
                 // two chunks in flight, but none beyond the predicted end before the device has
                 // had the chance to report completion (every launch past the end costs a stage

@@ -140,7 +140,7 @@ struct TilePlan {
 
 constexpr int AGG_PER_TILE = 2;          // deflation aggregates per tile
 constexpr int KZ_PER_ROW = 4;            // aggregates one row may couple to
-constexpr int MAX_DEFL_AGGREGATES = 1024;
+constexpr int MAX_DEFL_AGGREGATES = 2048;   // the coarse step holds a row of E^-1 in 32 registers per lane
 
 // The nodal gradient of the finest level as a sparse operator: G_i = sum_j (cx_ij, cy_ij) q_j
 // (the area-weighted mean of the element gradients around node i), column-major ELL of

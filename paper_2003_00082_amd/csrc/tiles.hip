@@ -333,24 +333,32 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
             L[static_cast<size_t>(i) * na + j] = v / d;
         }
     }
-    // Li = L^-1 (lower triangular), by columns
+    // Li = L^-1 (lower triangular) by forward substitution, one row at a time: row i of Li is
+    // (e_i - sum_{k<i} L_ik Li_k) / L_ii, the update running along contiguous rows
     std::vector<double> Li(static_cast<size_t>(na) * na, 0.0);
-    for (int c = 0; c < na; ++c) {
-        Li[static_cast<size_t>(c) * na + c] = 1.0 / L[static_cast<size_t>(c) * na + c];
-        for (int i = c + 1; i < na; ++i) {
-            double v = 0.0;
-            for (int k = c; k < i; ++k) v -= L[static_cast<size_t>(i) * na + k] * Li[static_cast<size_t>(k) * na + c];
-            Li[static_cast<size_t>(i) * na + c] = v / L[static_cast<size_t>(i) * na + i];
+    for (int i = 0; i < na; ++i) {
+        double *xi = &Li[static_cast<size_t>(i) * na];
+        xi[i] = 1.0;
+        for (int k = 0; k < i; ++k) {
+            const double a = L[static_cast<size_t>(i) * na + k];
+            const double *xk = &Li[static_cast<size_t>(k) * na];
+            for (int c = 0; c <= k; ++c) xi[c] -= a * xk[c];
+        }
+        const double d = L[static_cast<size_t>(i) * na + i];
+        for (int c = 0; c <= i; ++c) xi[c] /= d;
+    }
+    // E^-1 = Li^T Li as a sum of rank-one updates by the rows of Li (lower triangle), mirrored
+    std::vector<double> Ei(static_cast<size_t>(na) * na, 0.0);
+    for (int k = 0; k < na; ++k) {
+        const double *lk = &Li[static_cast<size_t>(k) * na];
+        for (int a = 0; a <= k; ++a) {
+            const double la = lk[a];
+            double *ea = &Ei[static_cast<size_t>(a) * na];
+            for (int b = 0; b <= a; ++b) ea[b] += la * lk[b];
         }
     }
-    std::vector<double> Ei(static_cast<size_t>(na) * na, 0.0);
     for (int a = 0; a < na; ++a)
-        for (int b = 0; b <= a; ++b) {
-            double v = 0.0;
-            for (int k = a; k < na; ++k) v += Li[static_cast<size_t>(k) * na + a] * Li[static_cast<size_t>(k) * na + b];
-            Ei[static_cast<size_t>(a) * na + b] = v;
-            Ei[static_cast<size_t>(b) * na + a] = v;
-        }
+        for (int b = 0; b < a; ++b) Ei[static_cast<size_t>(b) * na + a] = Ei[static_cast<size_t>(a) * na + b];
     // in place: cached launch records of earlier solves point at this buffer
     P.hblk = blk;
     CGP_HIP(hipMemcpyAsync(P.blk.p, blk.data(), blk.size() * sizeof(TileBlk), hipMemcpyHostToDevice, s));
