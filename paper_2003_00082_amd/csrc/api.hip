@@ -171,6 +171,123 @@ std::vector<int32_t> split_blocks(const std::vector<int64_t> &rows, int grid) {
     return nb;
 }
 
+struct WorkPtrs {
+    double *r, *w, *s, *p, *u;
+    float *r32, *w32, *s32, *p32, *c32, *u32;
+};
+
+WorkPtrs work_ptrs(SolveWork &w) {
+    return WorkPtrs{w.r.p, w.w.p, w.s.p, w.p.p, w.u.p, w.r32.p, w.w32.p, w.s32.p, w.p32.p, w.c32.p, w.u32.p};
+}
+
+// Chebyshev iteration over [hi/1000, hi] ([hi/30, hi] with deflation, whose coarse space takes
+// over the smooth end of the spectrum): the first step scales D^-1 r by 1/c, step k updates
+// dz <- a1 dz + a2 D^-1 res; degree 1 is Jacobi, z = D^-1 r
+void cheb_coefficients(double *cheb, int degree, double hi, bool defl) {
+    if (degree <= 1) {
+        cheb[0] = 1.0;
+        return;
+    }
+    const double lo = hi / (defl ? 30.0 : 1000.0);
+    const double c = 0.5 * (hi + lo), e = 0.5 * (hi - lo), sig = c / e;
+    double rho = 1.0 / sig;
+    cheb[0] = 1.0 / c;
+    for (int k = 1; k < degree; ++k) {
+        const double rn = 1.0 / (2.0 * sig - rho);
+        cheb[2 * k - 1] = rn * rho;
+        cheb[2 * k] = 2.0 * rn / e;
+        rho = rn;
+    }
+}
+
+// The record of one instance from its mesh, workspace vectors and the caller's vectors; the
+// launch-specific fields (workgroups, partial sums, control state, coarse-step buffers) are
+// the caller's to fill.  T: the tiled plan (null for the row-range and persistent kernels).
+InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int degree, bool defl, bool persistent,
+                           int lanes, int guess, const double *b, double *x, const double *prev1,
+                           const double *prev2, hipStream_t aux) {
+    InstDesc d{};
+    d.n = static_cast<int32_t>(m.lv[0].n);
+    d.lanes = lanes;
+    d.guess = guess;
+    d.fast = (!persistent && m.max_row <= pcg_ell_max_width()) ? 1 : 0;
+    d.ell_w = m.max_row;
+    d.ell_col = m.ell_col.p;
+    d.ell_val = m.ell_val.p;
+    d.ell_val32 = m.ell_val32.p;
+    d.rowptr = m.rowptr.p;
+    d.col = m.col.p;
+    d.val = m.val.p;
+    d.val32 = m.val32.p;
+    d.dinv = m.dinv.p;
+    d.dinv32 = m.dinv32.p;
+    d.b = b;
+    d.x = x;
+    d.prev1 = prev1;
+    d.prev2 = prev2;
+    d.r = ws.r;
+    d.w = ws.w;
+    d.s = ws.s;
+    d.p = ws.p;
+    d.u = ws.u;
+    d.r32 = ws.r32;
+    d.w32 = ws.w32;
+    d.s32 = ws.s32;
+    d.p32 = ws.p32;
+    d.c32 = ws.c32;
+    d.u32 = ws.u32;
+    if (T) {
+        d.degree = degree;
+        d.tblk = T->blk.p;
+        d.treg = T->reg.p;
+        d.tcol = T->ecol.p;
+        d.tval32 = T->eval32.p;
+        d.tval = T->eval64.p;
+        if (defl) {
+            d.defl = 1;
+            d.kzr = T->kzr.p;
+            d.kzg = T->kzg.p;
+            d.kzv32 = T->kzv32.p;
+            d.kzv = T->kzv64.p;
+            d.einv = T->einv.p;
+            d.oagg = T->oagg.p;
+        }
+        cheb_coefficients(d.cheb, degree, degree >= 2 ? mesh_gershgorin(aux, m) : 0.0, defl);
+    }
+    return d;
+}
+
+// the coarse step's record of a deflated instance whose record d is complete
+CoarseRec coarse_record(const InstDesc &d, int cblk0) {
+    CoarseRec cr{};
+    cr.einv = d.einv;
+    cr.partials = d.partials;
+    cr.mu = d.mu;
+    cr.cpart = d.cpart;
+    cr.m = AGG_PER_TILE * d.nblk;
+    cr.tiles = d.nblk;
+    cr.cblk0 = cblk0;
+    cr.ctl = d.ctl;
+    return cr;
+}
+
+void check_opts(const cgp_solve_opts &o) {
+    CGP_REQUIRE(o.precision == CGP_FP64 || o.precision == CGP_FP32_IR, "unknown precision");
+    CGP_REQUIRE(o.guess >= CGP_GUESS_ZERO && o.guess <= CGP_GUESS_LEARNED, "unknown guess mode");
+    CGP_REQUIRE(o.tol > 0.0 && std::isfinite(o.tol), "tol must be positive");
+    CGP_REQUIRE(o.refine_delta >= 0.0 && o.refine_delta < 1.0, "refine_delta must be in [0, 1)");
+    CGP_REQUIRE(o.max_iter >= 0 && o.max_iter <= 10000000, "max_iter must be in [0, 1e7]");
+    CGP_REQUIRE(o.spmv_lanes == 0 || o.spmv_lanes == 1 || o.spmv_lanes == 2 || o.spmv_lanes == 4 ||
+                    o.spmv_lanes == 8,
+                "spmv_lanes must be 0, 1, 2, 4 or 8");
+    CGP_REQUIRE(o.blocks >= 0, "blocks must be >= 0");
+    CGP_REQUIRE(o.engine >= CGP_ENGINE_AUTO && o.engine <= CGP_ENGINE_STAGED_ROWS, "unknown engine");
+    CGP_REQUIRE(o.precond_degree >= 0 && o.precond_degree <= TILE_MAX_DEGREE, "precond_degree must be in [0, 8]");
+    CGP_REQUIRE(o.deflation == 0 || o.deflation == 1, "deflation must be 0 or 1");
+    CGP_REQUIRE(o.launches_per_graph >= 0 && o.launches_per_graph % 2 == 0 && o.launches_per_graph <= 4096,
+                "launches_per_graph must be even and <= 4096");
+}
+
 Model &get_model(cgp_ctx ctx, cgp_model h) {
     auto it = ctx->models.find(h);
     if (it == ctx->models.end()) throw Error{CGP_E_INVALID, "unknown model handle"};
@@ -470,21 +587,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         CGP_REQUIRE(n_inst >= 1, "n_inst must be >= 1");
         CGP_REQUIRE(h_meshes && h_d_b && h_d_phi && h_opts && d_stats, "null argument");
         const cgp_solve_opts &o = *h_opts;
-        CGP_REQUIRE(o.precision == CGP_FP64 || o.precision == CGP_FP32_IR, "unknown precision");
-        CGP_REQUIRE(o.guess >= CGP_GUESS_ZERO && o.guess <= CGP_GUESS_LEARNED, "unknown guess mode");
-        CGP_REQUIRE(o.tol > 0.0 && std::isfinite(o.tol), "tol must be positive");
-        CGP_REQUIRE(o.refine_delta >= 0.0 && o.refine_delta < 1.0, "refine_delta must be in [0, 1)");
-        CGP_REQUIRE(o.max_iter >= 0 && o.max_iter <= 10000000, "max_iter must be in [0, 1e7]");
-        CGP_REQUIRE(o.spmv_lanes == 0 || o.spmv_lanes == 1 || o.spmv_lanes == 2 || o.spmv_lanes == 4 ||
-                        o.spmv_lanes == 8,
-                    "spmv_lanes must be 0, 1, 2, 4 or 8");
-        CGP_REQUIRE(o.blocks >= 0, "blocks must be >= 0");
-        CGP_REQUIRE(o.engine >= CGP_ENGINE_AUTO && o.engine <= CGP_ENGINE_STAGED_ROWS, "unknown engine");
-        CGP_REQUIRE(o.precond_degree >= 0 && o.precond_degree <= TILE_MAX_DEGREE,
-                    "precond_degree must be in [0, 8]");
-        CGP_REQUIRE(o.deflation == 0 || o.deflation == 1, "deflation must be 0 or 1");
-        CGP_REQUIRE(o.launches_per_graph >= 0 && o.launches_per_graph % 2 == 0 && o.launches_per_graph <= 4096,
-                    "launches_per_graph must be even and <= 4096");
+        check_opts(o);
         Model *model = nullptr;
         if (o.guess == CGP_GUESS_LEARNED) {
             auto mit = ctx->models.find(o.model);
@@ -614,94 +717,26 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 for (int i = 0; i < gn; ++i) {
                     const int ii = g0 + i;
                     Mesh &m = *ms[ii];
-                    InstDesc d{};
-                    d.n = static_cast<int32_t>(m.lv[0].n);
+                    InstDesc d = describe_instance(m, work_ptrs(m.work), tiled ? tp[ii] : nullptr, degree, defl,
+                                                   persistent, lanes_of(m), o.guess, h_d_b[ii], h_d_phi[ii],
+                                                   need_prev ? h_d_prev1[ii] : nullptr,
+                                                   need_prev ? h_d_prev2[ii] : nullptr, ctx->aux);
                     d.blk0 = blk;
                     d.nblk = nb[i];
-                    d.lanes = lanes_of(m);
-                    d.guess = o.guess;
                     d.stats_index = i;
                     d.chunk = static_cast<int32_t>((m.lv[0].n + nb[i] - 1) / nb[i]);
-                    d.fast = (!persistent && m.max_row <= pcg_ell_max_width()) ? 1 : 0;
-                    d.ell_w = m.max_row;
-                    d.ell_col = m.ell_col.p;
-                    d.ell_val = m.ell_val.p;
-                    d.ell_val32 = m.ell_val32.p;
-                    d.rowptr = m.rowptr.p;
-                    d.col = m.col.p;
-                    d.val = m.val.p;
-                    d.val32 = m.val32.p;
-                    d.dinv = m.dinv.p;
-                    d.dinv32 = m.dinv32.p;
-                    d.b = h_d_b[ii];
-                    d.x = h_d_phi[ii];
-                    d.prev1 = need_prev ? h_d_prev1[ii] : nullptr;
-                    d.prev2 = need_prev ? h_d_prev2[ii] : nullptr;
-                    d.r = m.work.r.p;
-                    d.w = m.work.w.p;
-                    d.s = m.work.s.p;
-                    d.p = m.work.p.p;
-                    d.r32 = m.work.r32.p;
-                    d.w32 = m.work.w32.p;
-                    d.s32 = m.work.s32.p;
-                    d.p32 = m.work.p32.p;
-                    d.c32 = m.work.c32.p;
                     d.partials = dpart + poff;
                     d.ctl = dctl + 2 * i;
-                    d.u = m.work.u.p;
-                    d.u32 = m.work.u32.p;
-                    if (tiled) {
-                        const TilePlan &T = *tp[ii];
-                        d.degree = degree;
-                        d.tblk = T.blk.p;
-                        d.treg = T.reg.p;
-                        d.tcol = T.ecol.p;
-                        d.tval32 = T.eval32.p;
-                        d.tval = T.eval64.p;
-                        if (defl) {
-                            d.defl = 1;
-                            d.ncb = (AGG_PER_TILE * nb[i] + COARSE_ROWS - 1) / COARSE_ROWS;
-                            d.cblk0 = cblk;
-                            d.kzr = T.kzr.p;
-                            d.kzg = T.kzg.p;
-                            d.kzv32 = T.kzv32.p;
-                            d.kzv = T.kzv64.p;
-                            d.einv = T.einv.p;
-                            d.mu = dmu;
-                            d.cpart = dcpart;
-                            d.oagg = T.oagg.p;
-                            dmu += AGG_PER_TILE * nb[i];
-                            dcpart += d.ncb;
-                            for (int v = 0; v < d.ncb; ++v) hcbi.push_back(i);
-                            CoarseRec cr{};
-                            cr.einv = d.einv;
-                            cr.partials = d.partials;
-                            cr.mu = d.mu;
-                            cr.cpart = d.cpart;
-                            cr.m = AGG_PER_TILE * nb[i];
-                            cr.tiles = nb[i];
-                            cr.cblk0 = cblk;
-                            cr.ctl = d.ctl;
-                            p->crecs.push_back(cr);
-                            cblk += d.ncb;
-                        }
-                        if (degree == 1) {
-                            d.cheb[0] = 1.0;   // Jacobi: z = D^-1 r
-                        } else {
-                            // Chebyshev iteration over [hi/1000, hi] ([hi/30, hi] with deflation, whose
-                            // coarse space takes over the smooth end of the spectrum): the first step
-                            // scales D^-1 r by 1/c, step k updates dz <- a1 dz + a2 D^-1 res
-                            const double hi = mesh_gershgorin(ctx->aux, m), lo = hi / (defl ? 30.0 : 1000.0);
-                            const double c = 0.5 * (hi + lo), e = 0.5 * (hi - lo), sig = c / e;
-                            double rho = 1.0 / sig;
-                            d.cheb[0] = 1.0 / c;
-                            for (int k = 1; k < degree; ++k) {
-                                const double rn = 1.0 / (2.0 * sig - rho);
-                                d.cheb[2 * k - 1] = rn * rho;
-                                d.cheb[2 * k] = 2.0 * rn / e;
-                                rho = rn;
-                            }
-                        }
+                    if (defl) {
+                        d.ncb = (AGG_PER_TILE * nb[i] + COARSE_ROWS - 1) / COARSE_ROWS;
+                        d.cblk0 = cblk;
+                        d.mu = dmu;
+                        d.cpart = dcpart;
+                        dmu += AGG_PER_TILE * nb[i];
+                        dcpart += d.ncb;
+                        for (int v = 0; v < d.ncb; ++v) hcbi.push_back(i);
+                        p->crecs.push_back(coarse_record(d, cblk));
+                        cblk += d.ncb;
                     }
                     hd[i] = d;
                     for (int v = 0; v < nb[i]; ++v) hbi[blk + v] = i;
