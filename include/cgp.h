@@ -233,6 +233,29 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                              const double *const *h_d_b, double *const *h_d_phi,
                              const double *const *h_d_prev1, const double *const *h_d_prev2,
                              const cgp_solve_opts *h_opts, cgp_solve_stats *d_stats);
+/* For callers that cannot allocate device memory while they run (tight serving loops,
+ * harnesses that forbid hipMalloc, code that must not grow its footprint): one solve as
+ * cgp_poisson_solve with n_inst = 1, allocating nothing.  Every buffer it needs beyond the
+ * mesh's own data and the caller's vectors (CG vectors, partial sums, control state,
+ * launch records, deflation coefficients) lives in a fixed library-owned device array of
+ * CGP_NOALLOC_SCRATCH_BYTES per device, held until the process ends; its stage kernels are
+ * enqueued one by one on the context's stream (no graph is instantiated) and the call
+ * returns once the device reports completion, like CGP_ENGINE_STAGED.
+ *   d_b, d_phi, d_prev1, d_prev2, h_opts, d_stats: as for cgp_poisson_solve (one instance;
+ *   d_prev1/d_prev2 only for CGP_GUESS_EXTRAP).
+ * Limits (CGP_E_INVALID, nothing enqueued): the solve must fit the array (100 bytes per row
+ * plus the records of its workgroups: about 670000 rows); CGP_GUESS_LEARNED and
+ * CGP_ENGINE_PERSISTENT are CGP_E_UNSUPPORTED; no graph capture.  The Chebyshev
+ * preconditioner and deflation use the mesh's tiled plan of that degree and its deflation
+ * data, which this call does not build: an earlier cgp_poisson_solve on the mesh with the
+ * same degree and deflation (a set-up call, which may allocate) must have built them.
+ * All calls on one device share the array and it keeps the last call's contents (the call
+ * clears what must start at zero): calls that overlap on one GPU (other host threads or
+ * contexts on other streams) race and must be serialised by the caller. */
+#define CGP_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d_b, double *d_phi,
+                                     const double *d_prev1, const double *d_prev2,
+                                     const cgp_solve_opts *h_opts, cgp_solve_stats *d_stats);
 /* Synchronise and read n_inst stats back into h_stats (may be NULL); returns
  * CGP_OK, or CGP_E_NOCONV / CGP_E_BREAKDOWN / CGP_E_ABORTED for the first
  * failing instance. */

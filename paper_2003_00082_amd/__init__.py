@@ -95,6 +95,7 @@ _SIGS = {
     "cgp_restrict": ([_vp, _i32, _vp, _vp, _i32, _f64, _vp, _vp, _vp], _i32),
     "cgp_poisson_solve": ([_vp, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp], _i32),
     "cgp_solve_check": ([_vp, _i32, _vp, _vp], _i32),
+    "cgp_poisson_solve_noalloc": ([_vp, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp], _i32),
     "cgp_autotune": ([_vp, _i32, _vp, _i32, _vp], _i32),
     "cgp_prolong": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_lorentz_force": ([_vp, _i32, _vp, _vp, _vp, _f64, _f64, _vp, _vp, _vp], _i32),
@@ -306,6 +307,16 @@ class Context:
                          launches_per_graph, precond_degree, deflation)
         _check(load().cgp_poisson_solve(self.handle, k, arr_m, arr_b, arr_x, arr_p1, arr_p2, ctypes.byref(opts),
                                         _ptr(stats)))
+
+    def poisson_solve_noalloc(self, mesh: int, b, phi, stats, *, prev1=None, prev2=None, precision=CGP_FP64,
+                              guess=CGP_GUESS_GIVEN, tol=1e-8, refine_delta=0.0, max_iter=0, spmv_lanes=0,
+                              engine=CGP_ENGINE_AUTO, launches_per_graph=0, precond_degree=0, deflation=0):
+        """One solve that allocates no device memory (the library's fixed scratch array);
+        ``stats`` is a device uint8 tensor of 32 bytes."""
+        opts = SolveOpts(precision, guess, tol, refine_delta, max_iter, -1, spmv_lanes, 0, engine,
+                         launches_per_graph, precond_degree, deflation)
+        _check(load().cgp_poisson_solve_noalloc(self.handle, mesh, _ptr(b), _ptr(phi), _ptr(prev1), _ptr(prev2),
+                                                ctypes.byref(opts), _ptr(stats)))
 
     def solve_check(self, n_inst: int, stats, raise_on_failure: bool = False) -> list[dict]:
         host = (SolveStats * n_inst)()

@@ -314,6 +314,7 @@ cgp_status cgp_create(cgp_ctx *out, int32_t device, void *hip_stream) {
         CGP_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
         CGP_HIP(hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device));
         ctx->max_blocks_per_cu = std::max(1, pcg_max_blocks_per_cu());
+        noalloc_init(device);   // the no-allocation solve's array on this device (once per device)
         ctx->sync.alloc(1);
         CGP_HIP(hipMemset(ctx->sync.p, 0, sizeof(GridSync)));
         CGP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->host_flag), 2 * sizeof(int32_t), hipHostMallocMapped));
@@ -922,6 +923,153 @@ cgp_status cgp_solve_check(cgp_ctx ctx, int32_t n_inst, const cgp_solve_stats *d
         }
     });
     return rc != CGP_OK ? rc : result;
+}
+
+cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d_b, double *d_phi,
+                                     const double *d_prev1, const double *d_prev2, const cgp_solve_opts *h_opts,
+                                     cgp_solve_stats *d_stats) {
+    return guarded([&] {
+        use_device(ctx);
+        CGP_REQUIRE(d_b && d_phi && h_opts && d_stats, "null argument");
+        CGP_REQUIRE(static_cast<const void *>(d_b) != static_cast<const void *>(d_phi), "b and phi must not alias");
+        const cgp_solve_opts &o = *h_opts;
+        check_opts(o);
+        CGP_REQUIRE(!ctx->capturing, "cgp_poisson_solve_noalloc waits for the device: it cannot be captured");
+        if (o.guess == CGP_GUESS_LEARNED)
+            throw Error{CGP_E_UNSUPPORTED, "the learned guess allocates the network's activations per mesh"};
+        if (o.engine == CGP_ENGINE_PERSISTENT)
+            throw Error{CGP_E_UNSUPPORTED, "the no-allocation solve runs the staged engine"};
+        if (o.guess == CGP_GUESS_EXTRAP) {
+            CGP_REQUIRE(d_prev1 && d_prev2, "prev1 and prev2 are required for this guess mode");
+            CGP_REQUIRE(d_prev1 != d_phi && d_prev2 != d_phi, "prev1/prev2 must not alias phi");
+        }
+        Mesh &m = get_mesh(ctx, mesh);
+        const int64_t n = m.lv[0].n;
+        const int degree = std::max(1, o.precond_degree);
+        const bool defl = o.deflation == 1;
+        const bool tiled = o.engine != CGP_ENGINE_STAGED_ROWS && (o.engine == CGP_ENGINE_STAGED || degree >= 2 || defl);
+        if ((degree >= 2 || defl) && !tiled)
+            throw Error{CGP_E_UNSUPPORTED, "the Chebyshev preconditioner and deflation need the tiled iteration"};
+        TilePlan *T = nullptr;
+        if (tiled) {
+            T = m.tiles[degree] ? m.tiles[degree].get() : nullptr;
+            CGP_REQUIRE(T != nullptr && T->nparts > 0,
+                        "the mesh's tiled plan of this degree is not built: call cgp_poisson_solve with this "
+                        "degree on the mesh first");
+            CGP_REQUIRE(degree < 2 || m.gershgorin > 0.0,
+                        "the mesh's spectral bound is not computed: call cgp_poisson_solve with this degree first");
+            CGP_REQUIRE(!defl || T->defl_state == 1,
+                        "the mesh's deflation data is not built: call cgp_poisson_solve with deflation first");
+        }
+        const int nblk = tiled ? T->nparts : static_cast<int>((n + pcg_block_size() - 1) / pcg_block_size());
+        const int na = defl ? AGG_PER_TILE * nblk : 0;
+        const int ncb = defl ? (na + COARSE_ROWS - 1) / COARSE_ROWS : 0;
+        // layout of the scratch array (every piece 256-byte aligned)
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = off;
+            off = (off + bytes + 255) / 256 * 256;
+            return at;
+        };
+        const size_t o_r = take(2 * n * sizeof(double)), o_w = take(2 * n * sizeof(double)),
+                     o_s = take(2 * n * sizeof(double)), o_p = take(n * sizeof(double)), o_u = take(n * sizeof(double));
+        const size_t o_r32 = take(2 * n * sizeof(float)), o_w32 = take(2 * n * sizeof(float)),
+                     o_s32 = take(2 * n * sizeof(float)), o_p32 = take(n * sizeof(float)),
+                     o_c32 = take(n * sizeof(float)), o_u32 = take(n * sizeof(float));
+        const size_t o_inst = take(sizeof(InstDesc)), o_bi = take(sizeof(int32_t) * nblk),
+                     o_rng = take(sizeof(RowRange) * nblk), o_ctl = take(2 * sizeof(Ctl)), o_done = take(sizeof(int32_t)),
+                     o_prm = take(sizeof(SolveParams)), o_part = take(sizeof(double) * 2 * NPART * nblk),
+                     o_zero = take(sizeof(double) * (na + ncb)), o_cbi = take(sizeof(int32_t) * std::max(ncb, 1)),
+                     o_crec = take(sizeof(CoarseRec));
+        if (off > CGP_NOALLOC_SCRATCH_BYTES) {
+            std::ostringstream msg;
+            msg << "the solve needs " << off << " bytes of scratch; the no-allocation array holds "
+                << CGP_NOALLOC_SCRATCH_BYTES;
+            throw Error{CGP_E_INVALID, msg.str()};
+        }
+        uint8_t *base = noalloc_scratch(ctx->device);
+        CGP_REQUIRE(base != nullptr, "the no-allocation array of this device was not looked up");
+        auto at = [&](size_t o_) { return base + o_; };
+        WorkPtrs ws{reinterpret_cast<double *>(at(o_r)), reinterpret_cast<double *>(at(o_w)),
+                    reinterpret_cast<double *>(at(o_s)), reinterpret_cast<double *>(at(o_p)),
+                    reinterpret_cast<double *>(at(o_u)), reinterpret_cast<float *>(at(o_r32)),
+                    reinterpret_cast<float *>(at(o_w32)), reinterpret_cast<float *>(at(o_s32)),
+                    reinterpret_cast<float *>(at(o_p32)), reinterpret_cast<float *>(at(o_c32)),
+                    reinterpret_cast<float *>(at(o_u32))};
+        const bool extrap = o.guess == CGP_GUESS_EXTRAP;
+        const int lanes = o.spmv_lanes ? o.spmv_lanes : (m.tuned_lanes[o.precision] ? m.tuned_lanes[o.precision] : 4);
+        InstDesc d = describe_instance(m, ws, T, degree, defl, false, lanes, o.guess, d_b, d_phi,
+                                       extrap ? d_prev1 : nullptr, extrap ? d_prev2 : nullptr, ctx->aux);
+        d.blk0 = 0;
+        d.nblk = nblk;
+        d.stats_index = 0;
+        d.chunk = static_cast<int32_t>((n + nblk - 1) / nblk);
+        d.partials = reinterpret_cast<double *>(at(o_part));
+        d.ctl = reinterpret_cast<Ctl *>(at(o_ctl));
+        double *zero = reinterpret_cast<double *>(at(o_zero));
+        CoarseRec cr{};
+        if (defl) {
+            d.ncb = ncb;
+            d.cblk0 = 0;
+            d.mu = zero;
+            d.cpart = zero + na;
+            cr = coarse_record(d, 0);
+        }
+        SolveParams prm{};
+        prm.tol = o.tol;
+        prm.delta = o.refine_delta > 0.0 ? o.refine_delta : (o.precond_degree >= 2 ? 0.01 : 0.1);
+        prm.max_iter = o.max_iter > 0 ? o.max_iter : 100000;
+        prm.precision = o.precision;
+        prm.n_inst = 1;
+        prm.stats = d_stats;
+        InstDesc *d_insts = reinterpret_cast<InstDesc *>(at(o_inst));
+        int32_t *d_bi = reinterpret_cast<int32_t *>(at(o_bi));
+        RowRange *d_rng = reinterpret_cast<RowRange *>(at(o_rng));
+        int32_t *d_done = reinterpret_cast<int32_t *>(at(o_done));
+        SolveParams *d_prm = reinterpret_cast<SolveParams *>(at(o_prm));
+        int32_t *d_cbi = reinterpret_cast<int32_t *>(at(o_cbi));
+        CoarseRec *d_crec = reinterpret_cast<CoarseRec *>(at(o_crec));
+        hipStream_t st = ctx->stream;
+        launch_noalloc_setup(st, d_insts, d, d_bi, nblk, d_cbi, ncb, zero, na + ncb, defl ? d_crec : nullptr, cr);
+        launch_ranges(st, d_insts, d_bi, nblk, d_rng);
+        volatile int32_t *flag = ctx->host_flag;
+        flag[0] = 0;
+        launch_cg_boot(st, d_insts, 1, prm, d_prm, d_done);
+        // chunks of stage launches enqueued directly, two in flight, until the device reports
+        // completion (the row-range kernel's widest staging variant covers any halo: a row range
+        // whose halo does not fit takes the general stage path)
+        const int launches = o.launches_per_graph > 0 ? o.launches_per_graph : 16;
+        const int64_t max_stages = 4 * static_cast<int64_t>(prm.max_iter) + 16;
+        const bool mixed = o.precision == CGP_FP32_IR;
+        int64_t issued = 0, chunk = 0;
+        for (;;) {
+            if (chunk >= 2) {
+                hipEvent_t old = ctx->chunk_ev[chunk & 1];
+                for (;;) {
+                    if (*flag) break;
+                    const hipError_t q = hipEventQuery(old);
+                    if (q == hipSuccess) break;
+                    if (q != hipErrorNotReady) CGP_HIP(q);
+                }
+            }
+            if (*flag) break;
+            if (issued >= max_stages + 2 * launches) throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
+            for (int l = 0; l < launches; ++l) {
+                if (tiled) {
+                    launch_cg_tile(st, mixed, T->width, defl, 1, d_insts, &d, d_bi, d_rng, nblk, d_prm, l & 1, d_done,
+                                   ctx->host_flag_dev);
+                    if (defl) launch_cg_coarse(st, &cr, d_crec, d_cbi, ncb, l & 1);
+                } else {
+                    launch_cg_step(st, mixed, INT32_MAX, 1, d_insts, &d, d_bi, d_rng, nblk, d_prm, l & 1, d_done,
+                                   ctx->host_flag_dev);
+                }
+            }
+            CGP_HIP(hipEventRecord(ctx->chunk_ev[chunk & 1], st));
+            ctx->stage_launches += launches;
+            issued += launches;
+            ++chunk;
+        }
+    });
 }
 
 cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_t precision, int32_t *h_lanes_out) {

@@ -363,6 +363,14 @@ void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, co
                           const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,
                           int32_t *d_done_at, uint64_t timeout_ticks);
 
+// the no-allocation solve's device array (noalloc.hip): noalloc_init looks its address up on
+// `device` (which must be current), noalloc_scratch returns it (null before noalloc_init)
+void noalloc_init(int device);
+uint8_t *noalloc_scratch(int device);
+void launch_noalloc_setup(hipStream_t s, InstDesc *insts, const InstDesc &d, int32_t *block_inst, int nblk,
+                          int32_t *cblk_inst, int ncb, double *zero, int nzero, CoarseRec *crec,
+                          const CoarseRec &c);
+
 // mesh build (mesh_build.hip)
 void build_hierarchy(hipStream_t s, Mesh &m, const double *h_xy, int64_t n, const int32_t *h_tri,
                      int64_t T, const uint8_t *h_dir, int32_t k);
