@@ -250,6 +250,7 @@ InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int d
             d.kzv32 = T->kzv32.p;
             d.kzv = T->kzv64.p;
             d.einv = T->einv.p;
+            d.einv32 = T->einv32.p;
             d.oagg = T->oagg.p;
         }
         cheb_coefficients(d.cheb, degree, degree >= 2 ? mesh_gershgorin(aux, m) : 0.0, defl);
@@ -257,10 +258,13 @@ InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int d
     return d;
 }
 
-// the coarse step's record of a deflated instance whose record d is complete
+// the coarse step's record of a deflated instance whose record d is complete (fp32 iterations
+// read E^-1 rounded to fp32: they round mu to fp32 anyway, and the coarse step reads all of
+// E^-1 every stage)
 CoarseRec coarse_record(const InstDesc &d, int cblk0) {
     CoarseRec cr{};
     cr.einv = d.einv;
+    cr.einv32 = d.einv32;
     cr.partials = d.partials;
     cr.mu = d.mu;
     cr.cpart = d.cpart;
@@ -802,8 +806,8 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                                        plan->d_done, ctx->host_flag_dev);
                         if (ev) CGP_HIP(hipEventRecord(ev[kps * l + 1], st));
                         if (defl) {
-                            launch_cg_coarse(st, gn == 1 ? plan->crecs.data() : nullptr, plan->d_crecs,
-                                             plan->d_cblk_inst, plan->cgrid, l & 1);
+                            launch_cg_coarse(st, o.precision == CGP_FP32_IR, gn == 1 ? plan->crecs.data() : nullptr,
+                                             plan->d_crecs, plan->d_cblk_inst, plan->cgrid, l & 1);
                             if (ev) CGP_HIP(hipEventRecord(ev[kps * l + 2], st));
                         }
                     } else {
@@ -1058,7 +1062,7 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
                 if (tiled) {
                     launch_cg_tile(st, mixed, T->width, defl, 1, d_insts, &d, d_bi, d_rng, nblk, d_prm, l & 1, d_done,
                                    ctx->host_flag_dev);
-                    if (defl) launch_cg_coarse(st, &cr, d_crec, d_cbi, ncb, l & 1);
+                    if (defl) launch_cg_coarse(st, mixed, &cr, d_crec, d_cbi, ncb, l & 1);
                 } else {
                     launch_cg_step(st, mixed, INT32_MAX, 1, d_insts, &d, d_bi, d_rng, nblk, d_prm, l & 1, d_done,
                                    ctx->host_flag_dev);

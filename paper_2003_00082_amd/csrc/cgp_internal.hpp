@@ -135,7 +135,8 @@ struct TilePlan {
     DBuf<int32_t> kzg;        // [4] per record: aggregates (tiles) the row couples to
     DBuf<float> kzv32;        // [4] per record: (K Z)_{row, aggregate}
     DBuf<double> kzv64;
-    DBuf<double> einv;        // [m x m] (Z^T K Z)^-1, row-major, m = AGG_PER_TILE * nparts
+    DBuf<double> einv;        // [m x einv_stride(m)] (Z^T K Z)^-1, row-major, m = AGG_PER_TILE * nparts
+    DBuf<float> einv32;       // the same rounded to fp32 (the coarse step of fp32 iterations)
 };
 
 constexpr int AGG_PER_TILE = 2;          // deflation aggregates per tile
@@ -304,7 +305,8 @@ struct InstDesc {
     const int32_t *kzg;
     const float *kzv32;
     const double *kzv;
-    const double *einv;                  // [m x m], m = AGG_PER_TILE * nblk
+    const double *einv;                  // [m x einv_stride(m)], m = AGG_PER_TILE * nblk
+    const float *einv32;                 // the same in fp32
     double *mu;                          // [m] E^-1 Z^T v of the last stage
     double *cpart;                       // [ncb] partial sums of mu . Z^T v
     const int8_t *oagg;                  // own rows (by region entry): 0 Dirichlet, 1 + half of the tile
@@ -343,9 +345,14 @@ void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst,
                     const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
                     const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag);
 // the coarse step of deflation after a tiled stage launch: mu = E^-1 (aggregate sums), c partials
-constexpr int COARSE_ROWS = 4;   // aggregates per coarse workgroup (one wavefront each)
+constexpr int COARSE_WAVES = 8;                  // wavefronts per coarse workgroup
+constexpr int COARSE_ROWS = 2 * COARSE_WAVES;    // aggregates (rows of E^-1) per coarse workgroup
+// row stride of both copies of E^-1: m rounded up to a multiple of 4 entries (zero padded), so
+// that every row starts 16-byte aligned
+constexpr int einv_stride(int m) { return (m + 3) & ~3; }
 struct CoarseRec {               // what the coarse step of one instance touches
-    const double *einv;          // [m x m]
+    const double *einv;          // [m x einv_stride(m)]
+    const float *einv32;         // the same in fp32 (read by the coarse step of fp32 iterations)
     const double *partials;      // the instance's [2][NPART][tiles] stage partials
     double *mu;                  // [m]
     double *cpart;               // [ceil(m / COARSE_ROWS)]
@@ -356,8 +363,9 @@ struct CoarseRec {               // what the coarse step of one instance touches
     const Ctl *ctl;              // the instance's control state, by stage parity
 };
 // h_single: the record of a single-instance solve (passed by value), else the device records
-void launch_cg_coarse(hipStream_t s, const CoarseRec *h_single, const CoarseRec *d_recs, const int32_t *d_cblk_inst,
-                      int grid, int par);
+// e32: read the fp32 copy of E^-1 (fp32 iterations)
+void launch_cg_coarse(hipStream_t s, bool e32, const CoarseRec *h_single, const CoarseRec *d_recs,
+                      const int32_t *d_cblk_inst, int grid, int par);
 int pcg_ell_max_width();
 void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
                           const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,

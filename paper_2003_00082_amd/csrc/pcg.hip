@@ -614,40 +614,28 @@ __device__ inline void write_stats(const Ctl &c, const SolveParams &prm, int idx
     prm.stats[idx] = o;
 }
 
-// sums of the first NRED of an instance's per-workgroup partials by one wavefront
-// (fixed order); loads are issued RED_ROWS rows of 64 at a time so they are in flight
-// together (two: their registers count against the tiled kernel's budget)
-constexpr int RED_ROWS = 2;
-__device__ inline void wave_reduce_partials(const double *part, int nblk, double (&S)[NPART]) {
-    const int lane = threadIdx.x & 63;
-    const CGP_GLOBAL double *pg = gld(part);
+// The previous stage's sums of an instance, by every thread of the workgroup: the first
+// NRED of its per-workgroup partials and (deflation) the coarse step's partials of
+// c = mu . q into S[NRED].  Each thread adds the slots t, t + BLOCK, ..., then block_sums
+// adds threads and wavefronts in a fixed order, so every workgroup of the instance gets the
+// same sums.  One round of loads for up to BLOCK workgroups, instead of a wavefront walking
+// the slots 64 at a time.
+__device__ inline void stage_sums(const InstDesc &D, int rd, double (*red)[NPART], double *out) {
+    const int nblk = D.nblk;
+    const CGP_GLOBAL double *pg = gld(D.partials + static_cast<size_t>(rd) * NPART * nblk);
+    double t[NPART] = {};
+    for (int j = threadIdx.x; j < nblk; j += BLOCK) {
+        double a[NRED];
 #pragma unroll
-    for (int s = 0; s < NPART; ++s) S[s] = 0.0;
-    for (int base = 0; base < nblk; base += 64 * RED_ROWS) {
-        double t[RED_ROWS][NRED];
+        for (int q = 0; q < NRED; ++q) a[q] = pg[q * nblk + j];
 #pragma unroll
-        for (int u = 0; u < RED_ROWS; ++u) {
-            const int j = base + lane + 64 * u;
-#pragma unroll
-            for (int s = 0; s < NRED; ++s) t[u][s] = j < nblk ? pg[s * nblk + j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < RED_ROWS; ++u) {
-#pragma unroll
-            for (int s = 0; s < NRED; ++s) S[s] += t[u][s];
-        }
+        for (int q = 0; q < NRED; ++q) t[q] += a[q];
     }
-#pragma unroll
-    for (int s = 0; s < NRED; ++s) S[s] = wave_sum(S[s]);
-}
-
-// the coarse term c = mu . Z^T v of deflation: the sum of the coarse kernel's partials
-__device__ inline double wave_coarse_term(const double *cpart, int ncb) {
-    const int lane = threadIdx.x & 63;
-    const CGP_GLOBAL double *pg = gld(cpart);
-    double t = 0.0;
-    for (int j = lane; j < ncb; j += 64) t += pg[j];
-    return wave_sum(t);
+    if (D.defl) {
+        const CGP_GLOBAL double *cg = gld(D.cpart);
+        for (int j = threadIdx.x; j < D.ncb; j += BLOCK) t[NRED] += cg[j];
+    }
+    block_sums(t, red, out);
 }
 
 // The common transition, an iteration followed by another one, kept short and
@@ -677,33 +665,30 @@ __device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolvePa
     return transition(prev, S, prm, guess);
 }
 
-// Decode the stage: wavefront 0 reduces the previous stage's partials and applies
-// the transition into sh.ctl (workgroup 0 of the instance also carries the state
-// forward and reports completion); the other wavefronts wait at the barrier.
+// Decode the stage: the workgroup sums the previous stage's partials, thread 0 applies
+// the transition into sh.ctl (workgroup 0 of the instance also carries the state forward
+// and reports completion); the other threads wait at the barrier.
 __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, const SolveParams *prm_dev,
                                     Shared &sh, int32_t *done_count, int32_t *host_flag) {
-    if (threadIdx.x < 64) {
-        const Ctl prev = D.ctl[rd];
-        double S[NPART];   // loaded whatever the state, so the loads overlap the control read
-        wave_reduce_partials(D.partials + static_cast<size_t>(rd) * NPART * D.nblk, D.nblk, S);
-        if (D.defl) S[NRED] = wave_coarse_term(D.cpart, D.ncb);
+    Ctl prev{};
+    if (threadIdx.x == 0) prev = D.ctl[rd];   // in flight while the sums are loaded
+    stage_sums(D, rd, sh.red, sh.sums);
+    if (threadIdx.x == 0) {
         const SolveParams prm = *prm_dev;
         Ctl c = prev;
-        if (prev.state != ST_DONE && threadIdx.x == 0) {
-            c = next_state(prev, S, prm, D.guess);
+        if (prev.state != ST_DONE) {
+            c = next_state(prev, sh.sums, prm, D.guess);
             c.stages = prev.stages + 1;
         }
-        if (threadIdx.x == 0) {
-            sh.ctl = c;
-            if (lb == 0) {
-                D.ctl[par] = c;   // carried forward every launch, DONE included
-                if (c.state == ST_DONE && prev.state != ST_DONE) {
-                    write_stats(c, prm, D.stats_index);
-                    // the last instance to finish reports the launches it needed, then completion
-                    if (atomicAdd(done_count, 1) == prm.n_inst - 1) {
-                        __hip_atomic_store(host_flag + 1, c.stages, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                        __hip_atomic_store(host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-                    }
+        sh.ctl = c;
+        if (lb == 0) {
+            D.ctl[par] = c;   // carried forward every launch, DONE included
+            if (c.state == ST_DONE && prev.state != ST_DONE) {
+                write_stats(c, prm, D.stats_index);
+                // the last instance to finish reports the launches it needed, then completion
+                if (atomicAdd(done_count, 1) == prm.n_inst - 1) {
+                    __hip_atomic_store(host_flag + 1, c.stages, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
             }
         }
@@ -1139,46 +1124,86 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
 }
 
 // Coarse step of deflation after a tiled stage: mu = E^-1 q with q the stage's aggregate
-// sums (the fifth partial of its workgroups), one wavefront per aggregate, and per
-// workgroup the partial sum of mu_a q_a (fixed order); the next stage reads both.  Every
-// stage gets one (only those after a residual, restart or iteration stage are read); the
-// record of a single instance arrives in the kernel arguments, so the products' loads are
+// sums (the fifth partial of its workgroups), one wavefront per row of E^-1 (two rows per
+// wavefront, COARSE_ROWS per workgroup), and per workgroup the partial sum of mu_a q_a
+// (fixed order); the next stage reads both.  A row is read with 16-byte loads (E^-1 rows
+// start 16-byte aligned: stride einv_stride(m), zero padded); fp32 iterations read the fp32
+// copy (both rows' loads in flight together), fp64 ones the fp64 copy (a row at a time).
+// Every stage gets one (only those after a residual, restart or iteration stage are read);
+// the record of a single instance arrives in the kernel arguments, so the row loads are
 // the first memory accesses.
+template <class E>
+__device__ inline const E *einv_of(const CoarseRec &C);
+template <>
+__device__ inline const double *einv_of<double>(const CoarseRec &C) { return C.einv; }
+template <>
+__device__ inline const float *einv_of<float>(const CoarseRec &C) { return C.einv32; }
+
+template <class E>
 __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
-    constexpr int PER_LANE = MAX_DEFL_AGGREGATES / 64;
+    constexpr int VE = 16 / static_cast<int>(sizeof(E));        // entries per 16-byte load
+    constexpr int CH = MAX_DEFL_AGGREGATES / (64 * VE);         // loads per lane and row, at most
+    constexpr bool BOTH = sizeof(E) == 4;                       // both rows' loads at once
     __shared__ double red[COARSE_ROWS];
-    __shared__ double qs[MAX_DEFL_AGGREGATES];
+    __shared__ __attribute__((aligned(16))) double qs[MAX_DEFL_AGGREGATES];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m = C.m, nt = C.tiles;
-    const int a = cb * COARSE_ROWS + wave;
-    // the wavefront's row of E^-1 (static) is loaded first, so that its loads and those of
-    // the stage's aggregate sums are in flight together
-    double e[PER_LANE];
-    const CGP_GLOBAL double *er = gld(C.einv) + static_cast<size_t>(a < m ? a : 0) * m;
+    const int m = C.m, ms = einv_stride(m), nt = C.tiles, nch = ms / VE;
+    const int a0 = cb * COARSE_ROWS + wave, a1 = a0 + COARSE_WAVES;
+    const E *einv = einv_of<E>(C);
+    u32x4 e0[CH], e1[BOTH ? CH : 1];
+    auto load_row = [&](int a, u32x4 *e) {
+        const CGP_GLOBAL u32x4 *er =
+            reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(einv) + static_cast<size_t>(a < m ? a : 0) * ms);
 #pragma unroll
-    for (int k = 0; k < PER_LANE; ++k) {
-        const int b = lane + 64 * k;
-        e[k] = (a < m && b < m) ? er[b] : 0.0;
-    }
+        for (int k = 0; k < CH; ++k) {
+            const int c = lane + 64 * k;
+            e[k] = (a < m && c < nch) ? er[c] : u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    load_row(a0, e0);
+    if constexpr (BOTH) load_row(a1, e1);
     // a stage that found the instance finished (launches past the end of the solve) has
     // nothing for the next one; its state was stored by the stage kernel before this launch
-    // (read with the row's loads in flight)
+    // (read with the row loads in flight)
     if (gld(C.ctl)[par].state == ST_DONE) return;
-    // q_a, the partial NRED + (a % 2) of tile a / 2, staged in LDS (coalesced)
+    // q_a, the partial NRED + (a % 2) of tile a / 2, staged in LDS (zero past m)
     static_assert(AGG_PER_TILE == 2, "aggregate a is half a % 2 of tile a / 2");
     const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * nt + static_cast<size_t>(NRED) * nt;
-    for (int i = threadIdx.x; i < m; i += 64 * COARSE_ROWS) qs[i] = q[static_cast<size_t>(i & 1) * nt + (i >> 1)];
+    for (int i = threadIdx.x; i < ms; i += 64 * COARSE_WAVES)
+        qs[i] = i < m ? q[static_cast<size_t>(i & 1) * nt + (i >> 1)] : 0.0;
     __syncthreads();
-    double acc = 0.0;
+    auto dot = [&](const u32x4 *e) {
+        double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < PER_LANE; ++k) {
-        const int b = lane + 64 * k;
-        if (b < m) acc += e[k] * qs[b];
+        for (int k = 0; k < CH; ++k) {
+            const int c = lane + 64 * k;
+            if (c < nch) {
+                if constexpr (sizeof(E) == 4) {
+                    acc += static_cast<double>(__uint_as_float(e[k].x)) * qs[4 * c] +
+                           static_cast<double>(__uint_as_float(e[k].y)) * qs[4 * c + 1] +
+                           static_cast<double>(__uint_as_float(e[k].z)) * qs[4 * c + 2] +
+                           static_cast<double>(__uint_as_float(e[k].w)) * qs[4 * c + 3];
+                } else {
+                    acc += __hiloint2double(static_cast<int>(e[k].y), static_cast<int>(e[k].x)) * qs[2 * c] +
+                           __hiloint2double(static_cast<int>(e[k].w), static_cast<int>(e[k].z)) * qs[2 * c + 1];
+                }
+            }
+        }
+        return wave_sum(acc);
+    };
+    const double mu0 = dot(e0);
+    double mu1;
+    if constexpr (BOTH) {
+        mu1 = dot(e1);
+    } else {
+        load_row(a1, e0);
+        mu1 = dot(e0);
     }
-    acc = wave_sum(acc);
     if (lane == 0) {
-        red[wave] = a < m ? acc * qs[a] : 0.0;
-        if (a < m) gst(C.mu)[a] = acc;
+        red[wave] = a0 < m ? mu0 * qs[a0] : 0.0;
+        red[wave + COARSE_WAVES] = a1 < m ? mu1 * qs[a1] : 0.0;
+        if (a0 < m) gst(C.mu)[a0] = mu0;
+        if (a1 < m) gst(C.mu)[a1] = mu1;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1188,14 +1213,16 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     }
 }
 
-__global__ __launch_bounds__(64 * COARSE_ROWS) void k_cg_coarse1(const CoarseRec C, int par) {
-    coarse_rows(C, blockIdx.x, par);
+template <class E>
+__global__ __launch_bounds__(64 * COARSE_WAVES) void k_cg_coarse1(const CoarseRec C, int par) {
+    coarse_rows<E>(C, blockIdx.x, par);
 }
 
-__global__ __launch_bounds__(64 * COARSE_ROWS) void k_cg_coarse(const CoarseRec *__restrict__ recs,
-                                                               const int32_t *__restrict__ cblk_inst, int par) {
+template <class E>
+__global__ __launch_bounds__(64 * COARSE_WAVES) void k_cg_coarse(const CoarseRec *__restrict__ recs,
+                                                                const int32_t *__restrict__ cblk_inst, int par) {
     const CoarseRec C = recs[cblk_inst[blockIdx.x]];
-    coarse_rows(C, blockIdx.x - C.cblk0, par);
+    coarse_rows<E>(C, blockIdx.x - C.cblk0, par);
 }
 
 __global__ void k_cg_boot(InstDesc *insts, int n_inst, const SolveParams prm, SolveParams *prm_dev,
@@ -1402,12 +1429,21 @@ void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst,
     CGP_HIP(hipGetLastError());
 }
 
-void launch_cg_coarse(hipStream_t s, const CoarseRec *h_single, const CoarseRec *d_recs, const int32_t *d_cblk_inst,
-                      int grid, int par) {
-    if (h_single)
-        hipLaunchKernelGGL(k_cg_coarse1, dim3(grid), dim3(64 * COARSE_ROWS), 0, s, *h_single, par);
+void launch_cg_coarse(hipStream_t s, bool e32, const CoarseRec *h_single, const CoarseRec *d_recs,
+                      const int32_t *d_cblk_inst, int grid, int par) {
+#define CGP_COARSE(E)                                                                                             \
+    do {                                                                                                          \
+        if (h_single)                                                                                             \
+            hipLaunchKernelGGL(k_cg_coarse1<E>, dim3(grid), dim3(64 * COARSE_WAVES), 0, s, *h_single, par);      \
+        else                                                                                                      \
+            hipLaunchKernelGGL(k_cg_coarse<E>, dim3(grid), dim3(64 * COARSE_WAVES), 0, s, d_recs, d_cblk_inst,    \
+                               par);                                                                              \
+    } while (0)
+    if (e32)
+        CGP_COARSE(float);
     else
-        hipLaunchKernelGGL(k_cg_coarse, dim3(grid), dim3(64 * COARSE_ROWS), 0, s, d_recs, d_cblk_inst, par);
+        CGP_COARSE(double);
+#undef CGP_COARSE
     CGP_HIP(hipGetLastError());
 }
 

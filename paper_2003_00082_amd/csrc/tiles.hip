@@ -368,7 +368,15 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
     h2d(s, P.kzv64, kzv);
     std::vector<float> kzv32(kzv.begin(), kzv.end());
     h2d(s, P.kzv32, kzv32);
-    h2d(s, P.einv, Ei);
+    // rows padded with zeros to einv_stride(na) entries (16-byte aligned rows for the coarse step)
+    const int ms = einv_stride(na);
+    std::vector<double> Ep(static_cast<size_t>(na) * ms, 0.0);
+    for (int a = 0; a < na; ++a)
+        std::copy(Ei.begin() + static_cast<size_t>(a) * na, Ei.begin() + static_cast<size_t>(a + 1) * na,
+                  Ep.begin() + static_cast<size_t>(a) * ms);
+    h2d(s, P.einv, Ep);
+    std::vector<float> ep32(Ep.begin(), Ep.end());
+    h2d(s, P.einv32, ep32);
     CGP_HIP(hipStreamSynchronize(s));
     P.defl_state = 1;
     return true;
