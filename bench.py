@@ -169,10 +169,10 @@ def batch_main(args):
     log-spaced over [0.1, 10]).  Each step solves phi for every instance in ONE batched
     call, then p in one.  Three variants on the same inputs: staged with the
     Chebyshev preconditioner of degree --degree (one graph-replayed launch per CG
-    stage for the whole batch, tiled), staged Jacobi (row ranges), and persistent
+    stage for the whole batch, tiled), the same with each instance's degree chosen by the
+    autotuner (cgp_autotune, per mesh shape), staged Jacobi (row ranges), and persistent
     Jacobi (one co-resident launch per batched solve with grid barriers, captured in
-    HIP graphs, SpMV lanes per instance from the autotuner).  fp32 CG with fp64
-    refinement from the extrapolated guess, to 1e-8."""
+    HIP graphs).  fp32 CG with fp64 refinement from the extrapolated guess, to 1e-8."""
     import numpy as np
     import torch
 
@@ -203,7 +203,7 @@ def batch_main(args):
             vel[i][n] = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in seq.at(n))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lanes = ctx.autotune(H, cgp.CGP_FP32_IR)
+    tuned, tune_ms = ctx.autotune(H, cgp.CGP_FP32_IR, deflation=args.deflation)
     tune_s = time.perf_counter() - t0
     rho_dt = 1.0 / ci.DT
     bphi = [torch.empty(n, **f64) for n in nc]
@@ -218,7 +218,8 @@ def batch_main(args):
     stats_all = torch.zeros(2 * nsteps * M * cgp.STATS_BYTES, dtype=torch.uint8, device=dev)
 
     def run(engine: str):
-        fdeg = args.degree if engine == "staged_chebyshev" else 0
+        fdeg = {"staged_chebyshev": args.degree, "staged_tuned": cgp.CGP_DEGREE_TUNED}.get(engine, 0)
+        cheb = engine in ("staged_chebyshev", "staged_tuned")
         bufs = {eq: [[torch.zeros(n, **f64) for n in nc] for _ in range(3)] for eq in ("phi", "p")}
         st = {eq: cgp.stats_buffer(M) for eq in ("phi", "p")}
         graphs = {}
@@ -226,9 +227,9 @@ def batch_main(args):
         def solve(eq, bvecs, n):
             cur, p1, p2 = (bufs[eq][(n - k) % 3] for k in range(3))
             kw = dict(prev1=p1, prev2=p2, guess=cgp.CGP_GUESS_EXTRAP, precision=cgp.CGP_FP32_IR, tol=TOL,
-                      precond_degree=fdeg, refine_delta=args.refine_delta if fdeg >= 2 else 0.0,
-                      deflation=args.deflation if engine == "staged_chebyshev" else 0)
-            if engine == "staged_chebyshev":
+                      precond_degree=fdeg, refine_delta=args.refine_delta if cheb else 0.0,
+                      deflation=args.deflation if cheb else 0)
+            if cheb:
                 ctx.poisson_solve(H, bvecs, cur, st[eq], engine=cgp.CGP_ENGINE_STAGED, **kw)
             elif engine == "staged_jacobi":
                 ctx.poisson_solve(H, bvecs, cur, st[eq], engine=cgp.CGP_ENGINE_STAGED_ROWS, **kw)
@@ -275,7 +276,7 @@ def batch_main(args):
         timed = host[2 * W * M:].reshape(K, 2, M)
         ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
         nbytes = sum(pcg_bytes(nc[i], nnz[i], int(timed["iters"][k, e, i]), int(timed["ref"][k, e, i]), True, True,
-                               fdeg)
+                               tuned[i] if fdeg == cgp.CGP_DEGREE_TUNED else fdeg)
                      for k in range(K) for e in range(2) for i in range(M))
         for g in graphs.values():
             ctx.graph_free(g)
@@ -285,7 +286,7 @@ def batch_main(args):
                 "bytes_per_step": nbytes / K, "stage_launches_per_step": launches / K,
                 "achieved_GBs_step": nbytes / elapsed / 1e9}
 
-    res = {e: run(e) for e in ("staged_chebyshev", "staged_jacobi", "persistent")}
+    res = {e: run(e) for e in ("staged_tuned", "staged_chebyshev", "staged_jacobi", "persistent")}
     best = max(res, key=lambda e: res[e]["solves_per_s"])
     R = res[best]
     out = {
@@ -308,7 +309,9 @@ def batch_main(args):
                                f"extrapolated guess to {TOL:g}",
                    "instances": M, "coarse_rows": int(sum(nc)), "nnz": int(sum(nnz)), "engine": best},
         "engines": res,
-        "autotune": {"lanes": lanes, "seconds": tune_s},
+        "autotune": {"degrees": tuned, "seconds": tune_s,
+                     "degree_histogram": {int(d): int(c) for d, c in zip(*np.unique(tuned, return_counts=True))},
+                     "tuned_vs_fixed_degree": res["staged_tuned"]["solves_per_s"] / res["staged_chebyshev"]["solves_per_s"]},
         "roofline": {"bound": "hbm", "achieved": R["achieved_GBs_step"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": R["achieved_GBs_step"] / HBM_PEAK_GBS, "traffic": None,
                      "note": "algorithmic PCG bytes of all solves / whole step time (restrict, prolong and "

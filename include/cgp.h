@@ -174,11 +174,14 @@ typedef struct {
                              0.01 with the Chebyshev preconditioner)                    */
     int32_t max_iter;     /* cap on CG iterations per instance (0 = default 100000)      */
     cgp_model model;      /* network for CGP_GUESS_LEARNED                               */
-    int32_t spmv_lanes;   /* lanes per matrix row: 0 = autotuned/default, else 1,2,4,8   */
+    int32_t spmv_lanes;   /* lanes per matrix row of the general row-range stages (residual,
+                             judge, persistent engine): 0 = default 4, else 1, 2, 4, 8        */
     int32_t blocks;       /* workgroups of the solve: 0 = one per compute unit           */
     int32_t engine;       /* CGP_ENGINE_*                                                */
     int32_t launches_per_graph; /* CGP_ENGINE_STAGED: stages per replayed graph (0 = 16; even) */
-    int32_t precond_degree; /* 0 or 1: Jacobi M = diag(K); 2..8: Chebyshev polynomial of this
+    int32_t precond_degree; /* CGP_DEGREE_TUNED (-1): per instance, the degree cgp_autotune chose
+                             for its mesh (this precision and deflation); otherwise
+                             0 or 1: Jacobi M = diag(K); 2..8: Chebyshev polynomial of this
                              degree in D^-1 K over [hi/1000, hi] ([hi/30, hi] with
                              deflation), hi = max_i sum_j |K_ij|/K_ii (Gershgorin),
                              applied as that many steps of Chebyshev iteration for
@@ -277,11 +280,25 @@ cgp_status cgp_stage_timing(cgp_ctx ctx, int32_t enable);
  * coarse-step launches and theirs.  Any output may be NULL. */
 cgp_status cgp_stage_timing_read(cgp_ctx ctx, int64_t *h_stage_launches, double *h_stage_us,
                                  int64_t *h_coarse_launches, double *h_coarse_us);
-/* Pick spmv_lanes per mesh by timing the solver's matrix-vector stage on the
- * device (one entry per mesh in h_lanes_out, also remembered by the mesh and
- * used when cgp_solve_opts.spmv_lanes == 0).  Synchronous. */
+/* Choose the preconditioner degree of each mesh by timing (an extension of the method:
+ * the paper fixes its solver).  For every candidate degree d in {1 (Jacobi), 2, ..., 8}
+ * the call solves, on the staged tiled engine with this precision and deflation, the
+ * mesh's system for a unit source on the free rows from zero to 1e-8 (building the tiled
+ * plan of d on its first solve, which is not timed) and keeps the best of two timed
+ * solves (HIP events on the context's stream); the fastest candidate becomes the mesh's
+ * degree for solves with precond_degree = CGP_DEGREE_TUNED (so that instances of one
+ * batched solve may run different degrees, and with them different tile partitions).
+ * Choices are cached by mesh shape (rows, nonzeros, widest row), precision and deflation:
+ * a mesh of a shape already tuned takes the cached choice without timing.
+ *   h_degree_out [n]  (may be NULL): the chosen degrees
+ *   h_ms_out     [n * 8] (may be NULL): per mesh, the time of each candidate in ms (-1
+ *                where the candidate could not solve: no tiled plan, no deflation data,
+ *                or no convergence)
+ * Synchronous; allocates the tuning problem's vectors. */
+#define CGP_DEGREE_TUNED (-1)
+#define CGP_AUTOTUNE_CANDIDATES 8
 cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_t precision,
-                        int32_t *h_lanes_out);
+                        int32_t deflation, int32_t *h_degree_out, double *h_ms_out);
 
 /* ------------------------------------------------------------------ CGP steps 3, 7 and 4 */
 

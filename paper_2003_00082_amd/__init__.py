@@ -40,6 +40,8 @@ CGP_ENGINE_AUTO = 0
 CGP_ENGINE_STAGED = 1
 CGP_ENGINE_PERSISTENT = 2
 CGP_ENGINE_STAGED_ROWS = 3
+CGP_DEGREE_TUNED = -1
+AUTOTUNE_CANDIDATES = 8
 SOLVE_STATUS = {0: "ok", 1: "noconv", 2: "breakdown", 3: "aborted"}
 
 
@@ -96,7 +98,7 @@ _SIGS = {
     "cgp_poisson_solve": ([_vp, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp], _i32),
     "cgp_solve_check": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_poisson_solve_noalloc": ([_vp, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp], _i32),
-    "cgp_autotune": ([_vp, _i32, _vp, _i32, _vp], _i32),
+    "cgp_autotune": ([_vp, _i32, _vp, _i32, _i32, _vp, _vp], _i32),
     "cgp_prolong": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_lorentz_force": ([_vp, _i32, _vp, _vp, _vp, _f64, _f64, _vp, _vp, _vp], _i32),
     "cgp_velocity_correct": ([_vp, _i32, _vp, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
@@ -327,12 +329,15 @@ class Context:
                  "guess_used": s.guess_used, "rel_res": s.rel_res, "rel_res_guess": s.rel_res_guess}
                 for s in host]
 
-    def autotune(self, meshes, precision: int) -> list[int]:
+    def autotune(self, meshes, precision: int, deflation: int = 1):
+        """Per mesh, the preconditioner degree chosen by timing and the time of each candidate
+        degree 1..8 (ms, -1 where it could not solve): (degrees, times [k, 8])."""
         k = len(meshes)
         arr_m = (_i32 * k)(*meshes)
         out = (_i32 * k)()
-        _check(load().cgp_autotune(self.handle, k, arr_m, precision, out))
-        return list(out)
+        ms = np.empty((k, AUTOTUNE_CANDIDATES), dtype=np.float64)
+        _check(load().cgp_autotune(self.handle, k, arr_m, precision, deflation, out, ms.ctypes.data))
+        return list(out), ms
 
     # ---------------------------------------------------------------- learned guess
     @staticmethod

@@ -53,6 +53,14 @@ struct Plan {
 
 constexpr int TAIL_LAUNCHES = 4;   // stage launches per graph near the predicted end of a solve
 
+// preconditioner degrees cgp_autotune times (1 = Jacobi in the tiled iteration)
+constexpr int AUTOTUNE_CANDIDATES = CGP_AUTOTUNE_CANDIDATES;
+constexpr int AUTOTUNE_DEGREES[AUTOTUNE_CANDIDATES] = {1, 2, 3, 4, 5, 6, 7, 8};
+struct TuneRec {
+    int32_t degree = 0;
+    double ms[AUTOTUNE_CANDIDATES] = {};   // best solve time of each candidate (-1: it did not solve)
+};
+
 struct GraphRec {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -71,6 +79,12 @@ struct cgp_ctx_s {
     int32_t next_mesh = 0, next_graph = 0;
     std::map<int32_t, std::unique_ptr<Mesh>> meshes;
     std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
+    // launches the last solve of a mesh set and option set needed, whatever its vectors: the
+    // prediction for a plan's first solve (plans differ by vector pointers, e.g. rotating
+    // previous-solution buffers, but solve alike)
+    std::unordered_map<std::string, int32_t> stage_hint;
+    // cgp_autotune's choices by mesh shape (rows, nonzeros, widest row), precision and deflation
+    std::unordered_map<std::string, TuneRec> tuned;
     std::map<int32_t, GraphRec> graphs;
     struct ModelDel {
         void operator()(Model *m) const { gnn_destroy(m); }
@@ -286,7 +300,8 @@ void check_opts(const cgp_solve_opts &o) {
                 "spmv_lanes must be 0, 1, 2, 4 or 8");
     CGP_REQUIRE(o.blocks >= 0, "blocks must be >= 0");
     CGP_REQUIRE(o.engine >= CGP_ENGINE_AUTO && o.engine <= CGP_ENGINE_STAGED_ROWS, "unknown engine");
-    CGP_REQUIRE(o.precond_degree >= 0 && o.precond_degree <= TILE_MAX_DEGREE, "precond_degree must be in [0, 8]");
+    CGP_REQUIRE(o.precond_degree == CGP_DEGREE_TUNED || (o.precond_degree >= 0 && o.precond_degree <= TILE_MAX_DEGREE),
+                "precond_degree must be in [0, 8] or CGP_DEGREE_TUNED");
     CGP_REQUIRE(o.deflation == 0 || o.deflation == 1, "deflation must be 0 or 1");
     CGP_REQUIRE(o.launches_per_graph >= 0 && o.launches_per_graph % 2 == 0 && o.launches_per_graph <= 4096,
                 "launches_per_graph must be even and <= 4096");
@@ -478,6 +493,7 @@ cgp_status cgp_mesh_free(cgp_ctx ctx, cgp_mesh mesh) {
         CGP_HIP(hipStreamSynchronize(ctx->stream));
         // launch plans that reference this mesh's buffers become stale
         ctx->plans.clear();
+        ctx->stage_hint.clear();
         for (auto &md : ctx->models) gnn_release_mesh(*md.second, ctx->meshes[mesh].get());
         ctx->meshes.erase(mesh);
     });
@@ -617,7 +633,17 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         }
         const bool persistent = o.engine == CGP_ENGINE_PERSISTENT || (o.engine == CGP_ENGINE_AUTO && ctx->capturing);
         CGP_REQUIRE(persistent || !ctx->capturing, "the staged engine cannot be captured; use CGP_ENGINE_PERSISTENT");
-        const int degree = std::max(1, o.precond_degree);
+        // preconditioner degree of each instance: the option's, or (CGP_DEGREE_TUNED) the one
+        // cgp_autotune chose for the instance's mesh
+        std::vector<int> degs(n_inst, std::max(1, o.precond_degree));
+        if (o.precond_degree == CGP_DEGREE_TUNED) {
+            for (int i = 0; i < n_inst; ++i) {
+                degs[i] = ms[i]->tuned_degree[o.precision][o.deflation];
+                CGP_REQUIRE(degs[i] >= 1, "CGP_DEGREE_TUNED: a mesh has no autotuned degree for this precision and "
+                                          "deflation (call cgp_autotune)");
+            }
+        }
+        const int degree = *std::max_element(degs.begin(), degs.end());
         if (degree >= 2 && (persistent || o.engine == CGP_ENGINE_STAGED_ROWS))
             throw Error{CGP_E_UNSUPPORTED, "the Chebyshev preconditioner needs CGP_ENGINE_STAGED"};
         // tiled iteration when every instance's mesh fits it with one matrix width (AUTO: only
@@ -626,7 +652,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         bool tiled = !persistent && o.engine != CGP_ENGINE_STAGED_ROWS &&
                      (o.engine == CGP_ENGINE_STAGED || degree >= 2 || o.deflation == 1);
         for (int i = 0; i < n_inst && tiled; ++i) {
-            tp[i] = tile_plan(ctx->aux, *ms[i], degree);
+            tp[i] = tile_plan(ctx->aux, *ms[i], degs[i]);
             tiled = tp[i] != nullptr && tp[i]->width == tp[0]->width;
         }
         if (degree >= 2 && !tiled)
@@ -641,7 +667,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         SolveParams prm{};
         prm.tol = o.tol;
         // fewer iterations between refinements with the Chebyshev preconditioner: longer fp32 runs
-        prm.delta = o.refine_delta > 0.0 ? o.refine_delta : (o.precond_degree >= 2 ? 0.01 : 0.1);
+        prm.delta = o.refine_delta > 0.0 ? o.refine_delta : (degree >= 2 ? 0.01 : 0.1);
         prm.max_iter = o.max_iter > 0 ? o.max_iter : 100000;
         prm.precision = o.precision;
         const int launches = o.launches_per_graph > 0 ? o.launches_per_graph : 16;
@@ -669,19 +695,26 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             int used = 0;
             for (int v : nb) used += v;
             auto lanes_of = [&](Mesh &m) {
-                return o.spmv_lanes ? o.spmv_lanes : (m.tuned_lanes[o.precision] ? m.tuned_lanes[o.precision] : 4);
+                (void)m;
+                return o.spmv_lanes ? o.spmv_lanes : 4;
             };
             // cache key: everything the launch records depend on
             std::ostringstream key;
             key << o.precision << ':' << o.guess << ':' << used << ':' << launches << ':' << persistent << ':'
-                << tiled << ':' << degree << ':' << defl << ':';
+                << tiled << ':' << defl << ':';
             for (int i = 0; i < gn; ++i) {
                 const int ii = g0 + i;
-                key << h_meshes[ii] << ',' << lanes_of(*ms[ii]) << ',' << nb[i] << ',' << (const void *)h_d_b[ii]
+                key << h_meshes[ii] << ',' << degs[ii] << ',' << lanes_of(*ms[ii]) << ',' << nb[i] << ','
+                    << (const void *)h_d_b[ii]
                     << ',' << (const void *)h_d_phi[ii] << ','
                     << (const void *)(need_prev ? h_d_prev1[ii] : nullptr) << ','
                     << (const void *)(need_prev ? h_d_prev2[ii] : nullptr) << ';';
             }
+            // the same key without the vectors, for the stage-count prediction
+            std::ostringstream hkey;
+            hkey << o.precision << ':' << o.guess << ':' << launches << ':' << tiled << ':' << defl << ':' << o.tol
+                 << ':';
+            for (int i = 0; i < gn; ++i) hkey << h_meshes[g0 + i] << ',' << degs[g0 + i] << ';';
             auto it = ctx->plans.find(key.str());
             Plan *plan = nullptr;
             if (it != ctx->plans.end()) {
@@ -722,7 +755,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 for (int i = 0; i < gn; ++i) {
                     const int ii = g0 + i;
                     Mesh &m = *ms[ii];
-                    InstDesc d = describe_instance(m, work_ptrs(m.work), tiled ? tp[ii] : nullptr, degree, defl,
+                    InstDesc d = describe_instance(m, work_ptrs(m.work), tiled ? tp[ii] : nullptr, degs[ii], defl,
                                                    persistent, lanes_of(m), o.guess, h_d_b[ii], h_d_phi[ii],
                                                    need_prev ? h_d_prev1[ii] : nullptr,
                                                    need_prev ? h_d_prev2[ii] : nullptr, ctx->aux);
@@ -839,7 +872,11 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             const int64_t max_stages = 4 * static_cast<int64_t>(prm.max_iter) + 16;
             // full graphs while they end before the launch count the previous solve of this plan
             // needed, then short ones, so that little runs past the end
-            const int64_t predicted = plan->last_stages;
+            int64_t predicted = plan->last_stages;
+            if (predicted == 0) {
+                auto h = ctx->stage_hint.find(hkey.str());
+                if (h != ctx->stage_hint.end()) predicted = h->second;
+            }
             int64_t issued = 0;
             int64_t chunk = 0;
             bool finished = false;
@@ -903,6 +940,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 ++chunk;
             }
             plan->last_stages = flag[1];
+            ctx->stage_hint[hkey.str()] = flag[1];
         }
     });
 }
@@ -943,6 +981,8 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
             throw Error{CGP_E_UNSUPPORTED, "the learned guess allocates the network's activations per mesh"};
         if (o.engine == CGP_ENGINE_PERSISTENT)
             throw Error{CGP_E_UNSUPPORTED, "the no-allocation solve runs the staged engine"};
+        if (o.precond_degree == CGP_DEGREE_TUNED)
+            throw Error{CGP_E_UNSUPPORTED, "the no-allocation solve takes an explicit preconditioner degree"};
         if (o.guess == CGP_GUESS_EXTRAP) {
             CGP_REQUIRE(d_prev1 && d_prev2, "prev1 and prev2 are required for this guess mode");
             CGP_REQUIRE(d_prev1 != d_phi && d_prev2 != d_phi, "prev1/prev2 must not alias phi");
@@ -1001,7 +1041,7 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
                     reinterpret_cast<float *>(at(o_p32)), reinterpret_cast<float *>(at(o_c32)),
                     reinterpret_cast<float *>(at(o_u32))};
         const bool extrap = o.guess == CGP_GUESS_EXTRAP;
-        const int lanes = o.spmv_lanes ? o.spmv_lanes : (m.tuned_lanes[o.precision] ? m.tuned_lanes[o.precision] : 4);
+        const int lanes = o.spmv_lanes ? o.spmv_lanes : 4;
         InstDesc d = describe_instance(m, ws, T, degree, defl, false, lanes, o.guess, d_b, d_phi,
                                        extrap ? d_prev1 : nullptr, extrap ? d_prev2 : nullptr, ctx->aux);
         d.blk0 = 0;
@@ -1076,61 +1116,100 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
     });
 }
 
-cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_t precision, int32_t *h_lanes_out) {
+cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_t precision, int32_t deflation,
+                        int32_t *h_degree_out, double *h_ms_out) {
     return guarded([&] {
         use_device(ctx);
         CGP_REQUIRE(n >= 1 && h_meshes != nullptr, "bad arguments");
         CGP_REQUIRE(precision == CGP_FP64 || precision == CGP_FP32_IR, "unknown precision");
+        CGP_REQUIRE(deflation == 0 || deflation == 1, "deflation must be 0 or 1");
         CGP_REQUIRE(!ctx->capturing, "cgp_autotune cannot be captured");
         hipEvent_t e0, e1;
         CGP_HIP(hipEventCreate(&e0));
         CGP_HIP(hipEventCreate(&e1));
+        struct EvGuard {
+            hipEvent_t a, b;
+            ~EvGuard() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } guard{e0, e1};
         for (int i = 0; i < n; ++i) {
             Mesh &m = get_mesh(ctx, h_meshes[i]);
             const int64_t nn = m.lv[0].n;
+            std::ostringstream shape;
+            shape << nn << ':' << m.nnz << ':' << m.max_row << ':' << precision << ':' << deflation;
+            auto hit = ctx->tuned.find(shape.str());
+            if (hit != ctx->tuned.end()) {
+                // a mesh of the same shape (rows, nonzeros, widest row) was tuned: same choice
+                m.tuned_degree[precision][deflation] = hit->second.degree;
+                if (h_degree_out) h_degree_out[i] = hit->second.degree;
+                if (h_ms_out)
+                    for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c) h_ms_out[i * AUTOTUNE_CANDIDATES + c] = hit->second.ms[c];
+                continue;
+            }
             DBuf<double> b, x;
             DBuf<cgp_solve_stats> st;
             b.alloc(nn);
             x.alloc(nn);
             st.alloc(1);
-            // right-hand side: the load of a unit source on the free nodes (row sums of K are
-            // not needed; any nonzero vector exercises the same kernels)
-            std::vector<double> hb(nn, 1.0);
+            // right-hand side: the load of a unit source (b_i = 1 on free rows), a smooth field
+            // like the sources of the time steps; every candidate solves it from zero to 1e-8
+            std::vector<uint8_t> dir(nn);
+            CGP_HIP(hipMemcpy(dir.data(), m.lv[0].dir.p, nn, hipMemcpyDeviceToHost));
+            std::vector<double> hb(nn);
+            for (int64_t j = 0; j < nn; ++j) hb[j] = dir[j] ? 0.0 : 1.0;
             CGP_HIP(hipMemcpy(b.p, hb.data(), nn * sizeof(double), hipMemcpyHostToDevice));
-            const int cand[4] = {1, 2, 4, 8};
+            TuneRec rec{};
             float best = 1e30f;
-            int best_l = 4;
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c) {
+                const int deg = AUTOTUNE_DEGREES[c];
                 cgp_solve_opts o{};
                 o.precision = precision;
                 o.guess = CGP_GUESS_ZERO;
-                o.tol = 1e-300;   // run exactly max_iter iterations
-                o.max_iter = 60;
-                o.spmv_lanes = cand[c];
+                o.tol = 1e-8;
+                o.precond_degree = deg;
+                o.deflation = deflation;
+                o.engine = CGP_ENGINE_STAGED;
                 const double *bp = b.p;
                 double *xp = x.p;
                 const cgp_mesh mh = h_meshes[i];
                 float ms_best = 1e30f;
-                for (int rep = 0; rep < 3; ++rep) {
+                bool ok = true;
+                for (int rep = 0; rep < 3 && ok; ++rep) {   // the first solve also builds the tiled plan
                     CGP_HIP(hipEventRecord(e0, ctx->stream));
-                    cgp_status rc = cgp_poisson_solve(ctx, 1, &mh, &bp, &xp, nullptr, nullptr, &o, st.p);
+                    const cgp_status rc = cgp_poisson_solve(ctx, 1, &mh, &bp, &xp, nullptr, nullptr, &o, st.p);
+                    if (rc == CGP_E_UNSUPPORTED) {   // the mesh does not fit the tiled plan of this degree
+                        ok = false;
+                        break;
+                    }
                     if (rc != CGP_OK) throw Error{rc, g_last_error};
                     CGP_HIP(hipEventRecord(e1, ctx->stream));
                     CGP_HIP(hipEventSynchronize(e1));
+                    cgp_solve_stats hs{};
+                    CGP_HIP(hipMemcpy(&hs, st.p, sizeof hs, hipMemcpyDeviceToHost));
+                    if (hs.status != CGP_SOLVE_OK) {
+                        ok = false;
+                        break;
+                    }
                     float msec = 0.f;
                     CGP_HIP(hipEventElapsedTime(&msec, e0, e1));
-                    ms_best = std::min(ms_best, msec);
+                    if (rep > 0) ms_best = std::min(ms_best, msec);
                 }
-                if (ms_best < best) {
+                rec.ms[c] = ok ? ms_best : -1.0;
+                if (ok && ms_best < best) {
                     best = ms_best;
-                    best_l = cand[c];
+                    rec.degree = deg;
                 }
             }
-            m.tuned_lanes[precision] = best_l;
-            if (h_lanes_out) h_lanes_out[i] = best_l;
+            CGP_REQUIRE(rec.degree > 0, "no preconditioner degree solved the tuning problem");
+            m.tuned_degree[precision][deflation] = rec.degree;
+            ctx->tuned[shape.str()] = rec;
+            if (h_degree_out) h_degree_out[i] = rec.degree;
+            if (h_ms_out)
+                for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c) h_ms_out[i * AUTOTUNE_CANDIDATES + c] = rec.ms[c];
         }
-        CGP_HIP(hipEventDestroy(e0));
-        CGP_HIP(hipEventDestroy(e1));
+        // the tuning solves' launch plans point at the buffers freed above
         ctx->plans.clear();
     });
 }

@@ -220,7 +220,7 @@ struct Mesh {
     DBuf<double> ell_val;
     DBuf<float> ell_val32;
     SolveWork work;
-    int32_t tuned_lanes[2] = {0, 0};   // autotuned SpMV lanes per precision (0 = not tuned)
+    int32_t tuned_degree[2][2] = {{0, 0}, {0, 0}};   // cgp_autotune's degree per precision and deflation (0: none)
     double gershgorin = 0.0;           // max_i sum_j |K_ij| / K_ii (0 = not computed)
     std::unique_ptr<TilePlan> tiles[TILE_MAX_DEGREE + 1];   // per preconditioner degree
     NodalGrad grad;                     // finest level, built on the first force or correction

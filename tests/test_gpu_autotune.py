@@ -1,0 +1,92 @@
+"""The preconditioner-degree autotuner (cgp_autotune) and solves with the tuned degrees.
+
+The choice is made by timing, so which degree wins is not fixed; what is checked is that
+it is the fastest of the candidates the call itself timed, that meshes of one shape share
+the cached choice, and that a batched solve with CGP_DEGREE_TUNED runs each instance at
+its mesh's degree (its iterations equal those of a solve with that degree given
+explicitly) and meets the mixed-precision parity bar against phi* = K^-1 b.
+"""
+import numpy as np
+import pytest
+
+import cgp_inputs as ci
+from oracle import fem, solve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def cgp():
+    import paper_2003_00082_amd as lib
+    lib.load()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def ctx(cgp):
+    c = cgp.Context(0)
+    yield c
+    c.close()
+
+
+def dt(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def test_autotune_choice_cache_and_tuned_solves(ctx, cgp):
+    meshes = [ci.jittered_rect(97, 49, 61), ci.jittered_rect(97, 49, 62), ci.jittered_rect(129, 65, 63)]
+    H = [ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 0) for m in meshes]
+    try:
+        deg, ms = ctx.autotune(H, cgp.CGP_FP32_IR, deflation=1)
+        print("degrees", deg, "\n", np.round(ms, 3), flush=True)
+        assert all(1 <= d <= 8 for d in deg)
+        for i in range(3):
+            ok = ms[i] >= 0
+            assert ok.any()
+            assert ms[i, deg[i] - 1] == ms[i][ok].min()          # the fastest timed candidate
+        # meshes 0 and 1 have one shape (rows, nonzeros, widest row): the cached choice
+        assert deg[1] == deg[0]
+        np.testing.assert_array_equal(ms[1], ms[0])
+        # a batched solve at the tuned degrees
+        b, xs = [], []
+        for i, m in enumerate(meshes):
+            a = fem.system_matrix(m.xy, m.tri, m.dirichlet)
+            u, v = ci.stream_velocity(m.xy, ci.fourier_modes(70 + i), 0.0)
+            bb = fem.source(m.xy, m.tri, m.dirichlet, u, v, fem.CURL, 1.0)
+            b.append(bb)
+            xs.append(solve.direct(a, bb))
+        phi = [torch.zeros(m.n_nodes, dtype=torch.float64, device=DEV) for m in meshes]
+        st = cgp.stats_buffer(3)
+        kw = dict(precision=cgp.CGP_FP32_IR, guess=cgp.CGP_GUESS_ZERO, tol=1e-8, deflation=1)
+        ctx.poisson_solve(H, [dt(x) for x in b], phi, st, precond_degree=cgp.CGP_DEGREE_TUNED, **kw)
+        res = ctx.solve_check(3, st)
+        for i in range(3):
+            assert res[i]["status"] == "ok" and res[i]["rel_res"] <= 1e-8
+            err = np.linalg.norm(phi[i].cpu().numpy() - xs[i]) / np.linalg.norm(xs[i])
+            assert err <= 1e-6, (i, err)
+            # the same instance alone at its degree given explicitly: the same iterations
+            one = torch.zeros(meshes[i].n_nodes, dtype=torch.float64, device=DEV)
+            st1 = cgp.stats_buffer(1)
+            ctx.poisson_solve([H[i]], [dt(b[i])], [one], st1, precond_degree=deg[i], **kw)
+            r1 = ctx.solve_check(1, st1)[0]
+            assert r1["iters"] == res[i]["iters"] and r1["refinements"] == res[i]["refinements"], (i, r1, res[i])
+    finally:
+        for h in H:
+            ctx.mesh_free(h)
+
+
+def test_tuned_degree_needs_a_tuned_mesh(ctx, cgp):
+    m = ci.jittered_rect(33, 17, 64)
+    h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 0)
+    try:
+        b = torch.ones(m.n_nodes, dtype=torch.float64, device=DEV)
+        x = torch.zeros_like(b)
+        with pytest.raises(cgp.CGPError) as e:
+            ctx.poisson_solve([h], [b], [x], cgp.stats_buffer(1), precision=cgp.CGP_FP32_IR,
+                              precond_degree=cgp.CGP_DEGREE_TUNED, deflation=0)
+        assert e.value.code == cgp.CGP_E_INVALID
+    finally:
+        ctx.mesh_free(h)
