@@ -203,7 +203,7 @@ def batch_main(args):
             vel[i][n] = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in seq.at(n))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tuned, tune_ms = ctx.autotune(H, cgp.CGP_FP32_IR, deflation=args.deflation)
+    tuned, tune_ms, _ = ctx.autotune(H, cgp.CGP_FP32_IR, deflation=args.deflation)
     tune_s = time.perf_counter() - t0
     rho_dt = 1.0 / ci.DT
     bphi = [torch.empty(n, **f64) for n in nc]
@@ -309,7 +309,7 @@ def batch_main(args):
                                f"extrapolated guess to {TOL:g}",
                    "instances": M, "coarse_rows": int(sum(nc)), "nnz": int(sum(nnz)), "engine": best},
         "engines": res,
-        "autotune": {"degrees": tuned, "seconds": tune_s,
+        "autotune": {"degrees": tuned, "seconds": tune_s, "batch_ms_per_candidate_degree": list(tune_ms),
                      "degree_histogram": {int(d): int(c) for d, c in zip(*np.unique(tuned, return_counts=True))},
                      "tuned_vs_fixed_degree": res["staged_tuned"]["solves_per_s"] / res["staged_chebyshev"]["solves_per_s"]},
         "roofline": {"bound": "hbm", "achieved": R["achieved_GBs_step"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -175,8 +175,10 @@ typedef struct {
     int32_t max_iter;     /* cap on CG iterations per instance (0 = default 100000)      */
     cgp_model model;      /* network for CGP_GUESS_LEARNED                               */
     int32_t spmv_lanes;   /* lanes per matrix row of the general row-range stages (residual,
-                             judge, persistent engine): 0 = default 4, else 1, 2, 4, 8        */
-    int32_t blocks;       /* workgroups of the solve: 0 = one per compute unit           */
+                             judge, persistent engine): 0 = default (4; 1 for the persistent
+                             engine, whose workgroups own thousands of rows), else 1, 2, 4, 8 */
+    int32_t blocks;       /* workgroups of the row-range and persistent engines: 0 = one per
+                             compute unit (persistent: every co-resident workgroup slot)     */
     int32_t engine;       /* CGP_ENGINE_*                                                */
     int32_t launches_per_graph; /* CGP_ENGINE_STAGED: stages per replayed graph (0 = 16; even) */
     int32_t precond_degree; /* CGP_DEGREE_TUNED (-1): per instance, the degree cgp_autotune chose
@@ -280,25 +282,30 @@ cgp_status cgp_stage_timing(cgp_ctx ctx, int32_t enable);
  * coarse-step launches and theirs.  Any output may be NULL. */
 cgp_status cgp_stage_timing_read(cgp_ctx ctx, int64_t *h_stage_launches, double *h_stage_us,
                                  int64_t *h_coarse_launches, double *h_coarse_us);
-/* Choose the preconditioner degree of each mesh by timing (an extension of the method:
- * the paper fixes its solver).  For every candidate degree d in {1 (Jacobi), 2, ..., 8}
- * the call solves, on the staged tiled engine with this precision and deflation, the
- * mesh's system for a unit source on the free rows from zero to 1e-8 (building the tiled
- * plan of d on its first solve, which is not timed) and keeps the best of two timed
- * solves (HIP events on the context's stream); the fastest candidate becomes the mesh's
- * degree for solves with precond_degree = CGP_DEGREE_TUNED (so that instances of one
- * batched solve may run different degrees, and with them different tile partitions).
- * Choices are cached by mesh shape (rows, nonzeros, widest row), precision and deflation:
- * a mesh of a shape already tuned takes the cached choice without timing.
- *   h_degree_out [n]  (may be NULL): the chosen degrees
- *   h_ms_out     [n * 8] (may be NULL): per mesh, the time of each candidate in ms (-1
- *                where the candidate could not solve: no tiled plan, no deflation data,
- *                or no convergence)
+/* Choose the preconditioner degree of each instance of a batch by timing (an extension of
+ * the method: the paper fixes its solver).  For every candidate degree d in {1 (Jacobi),
+ * 2, ..., 8} the call solves the whole batch at degree d, on the staged tiled engine with
+ * this precision and deflation, each mesh's system for a unit source on its free rows from
+ * zero to 1e-8 (the first solve of a candidate builds the tiled plans and is not timed;
+ * the best of two timed solves counts, HIP events on the context's stream).  The fastest
+ * candidate d* fixes the batch's length, the most iterations S* any instance needs at d*;
+ * each instance then gets the lowest candidate degree at which it needs at most S*
+ * iterations (a lower degree works on a smaller region per tile: fewer bytes per stage for
+ * the same number of stages).  The choices become the meshes' degrees for solves with
+ * precond_degree = CGP_DEGREE_TUNED (instances of one batched solve may run different
+ * degrees).  They are cached by the batch's shapes (rows, nonzeros and widest row of each
+ * mesh, in order), precision and deflation: a batch of the same shapes takes the cached
+ * choices without solving.
+ *   h_degree_out [n]      (may be NULL): the chosen degrees
+ *   h_ms_out     [8]      (may be NULL): the batch's time at each candidate in ms (-1 where
+ *                         a mesh did not fit the candidate's tiled plan or deflation, or an
+ *                         instance did not converge)
+ *   h_iters_out  [n * 8]  (may be NULL): each instance's iterations at each candidate (-1 as above)
  * Synchronous; allocates the tuning problem's vectors. */
 #define CGP_DEGREE_TUNED (-1)
 #define CGP_AUTOTUNE_CANDIDATES 8
 cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_t precision,
-                        int32_t deflation, int32_t *h_degree_out, double *h_ms_out);
+                        int32_t deflation, int32_t *h_degree_out, double *h_ms_out, int32_t *h_iters_out);
 
 /* ------------------------------------------------------------------ CGP steps 3, 7 and 4 */
 

@@ -98,7 +98,7 @@ _SIGS = {
     "cgp_poisson_solve": ([_vp, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp], _i32),
     "cgp_solve_check": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_poisson_solve_noalloc": ([_vp, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp], _i32),
-    "cgp_autotune": ([_vp, _i32, _vp, _i32, _i32, _vp, _vp], _i32),
+    "cgp_autotune": ([_vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp], _i32),
     "cgp_prolong": ([_vp, _i32, _vp, _vp], _i32),
     "cgp_lorentz_force": ([_vp, _i32, _vp, _vp, _vp, _f64, _f64, _vp, _vp, _vp], _i32),
     "cgp_velocity_correct": ([_vp, _i32, _vp, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
@@ -330,14 +330,16 @@ class Context:
                 for s in host]
 
     def autotune(self, meshes, precision: int, deflation: int = 1):
-        """Per mesh, the preconditioner degree chosen by timing and the time of each candidate
-        degree 1..8 (ms, -1 where it could not solve): (degrees, times [k, 8])."""
+        """Preconditioner degrees for a batch chosen by timing: (degree per mesh, the batch's
+        time at each candidate degree 1..8 in ms [8], iterations per mesh and candidate [k, 8];
+        -1 where a candidate could not solve)."""
         k = len(meshes)
         arr_m = (_i32 * k)(*meshes)
         out = (_i32 * k)()
-        ms = np.empty((k, AUTOTUNE_CANDIDATES), dtype=np.float64)
-        _check(load().cgp_autotune(self.handle, k, arr_m, precision, deflation, out, ms.ctypes.data))
-        return list(out), ms
+        ms = np.empty(AUTOTUNE_CANDIDATES, dtype=np.float64)
+        its = np.empty((k, AUTOTUNE_CANDIDATES), dtype=np.int32)
+        _check(load().cgp_autotune(self.handle, k, arr_m, precision, deflation, out, ms.ctypes.data, its.ctypes.data))
+        return list(out), ms, its
 
     # ---------------------------------------------------------------- learned guess
     @staticmethod

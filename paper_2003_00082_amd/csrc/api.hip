@@ -57,8 +57,9 @@ constexpr int TAIL_LAUNCHES = 4;   // stage launches per graph near the predicte
 constexpr int AUTOTUNE_CANDIDATES = CGP_AUTOTUNE_CANDIDATES;
 constexpr int AUTOTUNE_DEGREES[AUTOTUNE_CANDIDATES] = {1, 2, 3, 4, 5, 6, 7, 8};
 struct TuneRec {
-    int32_t degree = 0;
-    double ms[AUTOTUNE_CANDIDATES] = {};   // best solve time of each candidate (-1: it did not solve)
+    std::vector<int32_t> degree;           // per instance
+    double ms[AUTOTUNE_CANDIDATES] = {};   // the batch's best solve time at each candidate (-1: no solve)
+    std::vector<int32_t> iters;            // [instance][candidate] iterations (-1: no solve)
 };
 
 struct GraphRec {
@@ -673,7 +674,10 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         const int launches = o.launches_per_graph > 0 ? o.launches_per_graph : 16;
 
         const int max_grid = ctx->cus * ctx->max_blocks_per_cu;
-        int grid = o.blocks > 0 ? o.blocks : ctx->cus;
+        // the persistent engine takes every co-resident workgroup slot by default: each of its
+        // workgroups walks thousands of rows per stage, and more of them in flight hide the
+        // latency of the row gathers
+        int grid = o.blocks > 0 ? o.blocks : (persistent ? max_grid : ctx->cus);
         grid = std::min(grid, max_grid);
         for (int i = 0; i < n_inst; ++i) ensure_work(*ms[i]);
 
@@ -694,9 +698,13 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             }
             int used = 0;
             for (int v : nb) used += v;
+            // lanes per matrix row of the general row-range stages: 4 for the staged engines' row
+            // blocks of at most a few hundred rows; 1 for the persistent engine, whose workgroups
+            // own thousands of rows (one row per thread keeps BLOCK rows' gathers in flight per
+            // pass, where 8 lanes would take 8 times the passes)
             auto lanes_of = [&](Mesh &m) {
                 (void)m;
-                return o.spmv_lanes ? o.spmv_lanes : 4;
+                return o.spmv_lanes ? o.spmv_lanes : (persistent ? 1 : 4);
             };
             // cache key: everything the launch records depend on
             std::ostringstream key;
@@ -1117,13 +1125,37 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
 }
 
 cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_t precision, int32_t deflation,
-                        int32_t *h_degree_out, double *h_ms_out) {
+                        int32_t *h_degree_out, double *h_ms_out, int32_t *h_iters_out) {
     return guarded([&] {
         use_device(ctx);
         CGP_REQUIRE(n >= 1 && h_meshes != nullptr, "bad arguments");
         CGP_REQUIRE(precision == CGP_FP64 || precision == CGP_FP32_IR, "unknown precision");
         CGP_REQUIRE(deflation == 0 || deflation == 1, "deflation must be 0 or 1");
         CGP_REQUIRE(!ctx->capturing, "cgp_autotune cannot be captured");
+        std::vector<Mesh *> ms(n);
+        std::ostringstream shape;   // the batch's shapes (rows, nonzeros, widest row), precision, deflation
+        shape << precision << ':' << deflation << ':';
+        for (int i = 0; i < n; ++i) {
+            ms[i] = &get_mesh(ctx, h_meshes[i]);
+            for (int j = 0; j < i; ++j) CGP_REQUIRE(h_meshes[j] != h_meshes[i], "each instance needs its own mesh");
+            shape << ms[i]->lv[0].n << ',' << ms[i]->nnz << ',' << ms[i]->max_row << ';';
+        }
+        auto emit = [&](const TuneRec &rec) {
+            for (int i = 0; i < n; ++i) {
+                ms[i]->tuned_degree[precision][deflation] = rec.degree[i];
+                if (h_degree_out) h_degree_out[i] = rec.degree[i];
+                if (h_iters_out)
+                    for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c)
+                        h_iters_out[i * AUTOTUNE_CANDIDATES + c] = rec.iters[static_cast<size_t>(i) * AUTOTUNE_CANDIDATES + c];
+            }
+            if (h_ms_out)
+                for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c) h_ms_out[c] = rec.ms[c];
+        };
+        auto hit = ctx->tuned.find(shape.str());
+        if (hit != ctx->tuned.end()) {   // a batch of the same shapes was tuned: same choices
+            emit(hit->second);
+            return;
+        }
         hipEvent_t e0, e1;
         CGP_HIP(hipEventCreate(&e0));
         CGP_HIP(hipEventCreate(&e1));
@@ -1134,82 +1166,82 @@ cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_
                 (void)hipEventDestroy(b);
             }
         } guard{e0, e1};
+        // per instance: the load of a unit source (b_i = 1 on free rows), a smooth field like the
+        // sources of the time steps, solved from zero to 1e-8
+        std::vector<DBuf<double>> bs(n), xs(n);
+        std::vector<const double *> bp(n);
+        std::vector<double *> xp(n);
         for (int i = 0; i < n; ++i) {
-            Mesh &m = get_mesh(ctx, h_meshes[i]);
-            const int64_t nn = m.lv[0].n;
-            std::ostringstream shape;
-            shape << nn << ':' << m.nnz << ':' << m.max_row << ':' << precision << ':' << deflation;
-            auto hit = ctx->tuned.find(shape.str());
-            if (hit != ctx->tuned.end()) {
-                // a mesh of the same shape (rows, nonzeros, widest row) was tuned: same choice
-                m.tuned_degree[precision][deflation] = hit->second.degree;
-                if (h_degree_out) h_degree_out[i] = hit->second.degree;
-                if (h_ms_out)
-                    for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c) h_ms_out[i * AUTOTUNE_CANDIDATES + c] = hit->second.ms[c];
-                continue;
-            }
-            DBuf<double> b, x;
-            DBuf<cgp_solve_stats> st;
-            b.alloc(nn);
-            x.alloc(nn);
-            st.alloc(1);
-            // right-hand side: the load of a unit source (b_i = 1 on free rows), a smooth field
-            // like the sources of the time steps; every candidate solves it from zero to 1e-8
+            const int64_t nn = ms[i]->lv[0].n;
+            bs[i].alloc(nn);
+            xs[i].alloc(nn);
             std::vector<uint8_t> dir(nn);
-            CGP_HIP(hipMemcpy(dir.data(), m.lv[0].dir.p, nn, hipMemcpyDeviceToHost));
+            CGP_HIP(hipMemcpy(dir.data(), ms[i]->lv[0].dir.p, nn, hipMemcpyDeviceToHost));
             std::vector<double> hb(nn);
             for (int64_t j = 0; j < nn; ++j) hb[j] = dir[j] ? 0.0 : 1.0;
-            CGP_HIP(hipMemcpy(b.p, hb.data(), nn * sizeof(double), hipMemcpyHostToDevice));
-            TuneRec rec{};
-            float best = 1e30f;
-            for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c) {
-                const int deg = AUTOTUNE_DEGREES[c];
-                cgp_solve_opts o{};
-                o.precision = precision;
-                o.guess = CGP_GUESS_ZERO;
-                o.tol = 1e-8;
-                o.precond_degree = deg;
-                o.deflation = deflation;
-                o.engine = CGP_ENGINE_STAGED;
-                const double *bp = b.p;
-                double *xp = x.p;
-                const cgp_mesh mh = h_meshes[i];
-                float ms_best = 1e30f;
-                bool ok = true;
-                for (int rep = 0; rep < 3 && ok; ++rep) {   // the first solve also builds the tiled plan
-                    CGP_HIP(hipEventRecord(e0, ctx->stream));
-                    const cgp_status rc = cgp_poisson_solve(ctx, 1, &mh, &bp, &xp, nullptr, nullptr, &o, st.p);
-                    if (rc == CGP_E_UNSUPPORTED) {   // the mesh does not fit the tiled plan of this degree
-                        ok = false;
-                        break;
-                    }
-                    if (rc != CGP_OK) throw Error{rc, g_last_error};
-                    CGP_HIP(hipEventRecord(e1, ctx->stream));
-                    CGP_HIP(hipEventSynchronize(e1));
-                    cgp_solve_stats hs{};
-                    CGP_HIP(hipMemcpy(&hs, st.p, sizeof hs, hipMemcpyDeviceToHost));
-                    if (hs.status != CGP_SOLVE_OK) {
-                        ok = false;
-                        break;
-                    }
-                    float msec = 0.f;
-                    CGP_HIP(hipEventElapsedTime(&msec, e0, e1));
-                    if (rep > 0) ms_best = std::min(ms_best, msec);
+            CGP_HIP(hipMemcpy(bs[i].p, hb.data(), nn * sizeof(double), hipMemcpyHostToDevice));
+            bp[i] = bs[i].p;
+            xp[i] = xs[i].p;
+        }
+        DBuf<cgp_solve_stats> st;
+        st.alloc(n);
+        std::vector<cgp_solve_stats> hs(n);
+        TuneRec rec;
+        rec.degree.assign(n, 0);
+        rec.iters.assign(static_cast<size_t>(n) * AUTOTUNE_CANDIDATES, -1);
+        // every candidate degree on the whole batch at once (the regime the solves run in)
+        int best = -1;
+        for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c) {
+            cgp_solve_opts o{};
+            o.precision = precision;
+            o.guess = CGP_GUESS_ZERO;
+            o.tol = 1e-8;
+            o.precond_degree = AUTOTUNE_DEGREES[c];
+            o.deflation = deflation;
+            o.engine = CGP_ENGINE_STAGED;
+            float ms_best = 1e30f;
+            bool ok = true;
+            for (int rep = 0; rep < 3 && ok; ++rep) {   // the first solve also builds the tiled plans
+                CGP_HIP(hipEventRecord(e0, ctx->stream));
+                const cgp_status rc = cgp_poisson_solve(ctx, n, h_meshes, bp.data(), xp.data(), nullptr, nullptr, &o,
+                                                        st.p);
+                if (rc == CGP_E_UNSUPPORTED) {   // a mesh does not fit the tiled plan of this degree
+                    ok = false;
+                    break;
                 }
-                rec.ms[c] = ok ? ms_best : -1.0;
-                if (ok && ms_best < best) {
-                    best = ms_best;
-                    rec.degree = deg;
+                if (rc != CGP_OK) throw Error{rc, g_last_error};
+                CGP_HIP(hipEventRecord(e1, ctx->stream));
+                CGP_HIP(hipEventSynchronize(e1));
+                CGP_HIP(hipMemcpy(hs.data(), st.p, n * sizeof(cgp_solve_stats), hipMemcpyDeviceToHost));
+                for (int i = 0; i < n && ok; ++i) ok = hs[i].status == CGP_SOLVE_OK;
+                float msec = 0.f;
+                CGP_HIP(hipEventElapsedTime(&msec, e0, e1));
+                if (rep > 0) ms_best = std::min(ms_best, msec);
+            }
+            rec.ms[c] = ok ? ms_best : -1.0;
+            if (!ok) continue;
+            for (int i = 0; i < n; ++i) rec.iters[static_cast<size_t>(i) * AUTOTUNE_CANDIDATES + c] = hs[i].iters;
+            if (best < 0 || ms_best < rec.ms[best]) best = c;
+        }
+        CGP_REQUIRE(best >= 0, "no preconditioner degree solved the tuning problem");
+        // the batch takes as many stages as its slowest instance at the fastest degree; every
+        // instance then runs the lowest degree that needs no more iterations than that (a lower
+        // degree has a smaller region: fewer bytes per stage, the same number of stages)
+        int smax = 0;
+        for (int i = 0; i < n; ++i) smax = std::max(smax, rec.iters[static_cast<size_t>(i) * AUTOTUNE_CANDIDATES + best]);
+        for (int i = 0; i < n; ++i) {
+            rec.degree[i] = AUTOTUNE_DEGREES[best];
+            for (int c = 0; c < best; ++c) {
+                const int it = rec.iters[static_cast<size_t>(i) * AUTOTUNE_CANDIDATES + c];
+                if (it >= 0 && it <= smax) {
+                    rec.degree[i] = AUTOTUNE_DEGREES[c];
+                    break;
                 }
             }
-            CGP_REQUIRE(rec.degree > 0, "no preconditioner degree solved the tuning problem");
-            m.tuned_degree[precision][deflation] = rec.degree;
-            ctx->tuned[shape.str()] = rec;
-            if (h_degree_out) h_degree_out[i] = rec.degree;
-            if (h_ms_out)
-                for (int c = 0; c < AUTOTUNE_CANDIDATES; ++c) h_ms_out[i * AUTOTUNE_CANDIDATES + c] = rec.ms[c];
         }
-        // the tuning solves' launch plans point at the buffers freed above
+        ctx->tuned[shape.str()] = rec;
+        emit(rec);
+        // the tuning solves' launch plans point at the buffers freed on return
         ctx->plans.clear();
     });
 }

@@ -255,12 +255,50 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
 
 // ------------------------------------------------------------------ stage work
 
+// The matrix of a row-range product: CSR, and the column-major ELL copy (entry k of row i
+// at k * n + i, padded with the row itself and value 0; width ew, 0 when absent).
+template <class V>
+struct RowMat {
+    const int32_t *rowptr, *col;
+    const V *val;
+    const int32_t *ecol;
+    const V *eval;
+    int ew;
+    int64_t n;
+};
+
 // y_i = sum_k val[k] * g(col[k]) for the workgroup's rows, `lanes` threads per row;
-// emit(i, y_i) from each row's first lane.
+// emit(i, y_i) from each row's first lane.  With one lane per row and an ELL copy of at
+// most KMAX columns, a thread issues its row's loads together from the ELL copy (same
+// terms, same order) instead of walking the CSR row one dependent load at a time.
 template <class V, class Gather, class Emit>
-__device__ inline void spmv_rows(const RowRange &R, int lanes, const int32_t *__restrict__ rowptr,
-                                 const int32_t *__restrict__ col, const V *__restrict__ val, Gather g,
-                                 Emit emit) {
+__device__ inline void spmv_rows(const RowRange &R, int lanes, const RowMat<V> &A, Gather g, Emit emit) {
+    if (lanes == 1 && A.ecol && A.ew <= KMAX) {
+        const CGP_GLOBAL int32_t *ec = gld(A.ecol);
+        const CGP_GLOBAL V *ev = gld(A.eval);
+        for (int32_t base = R.r0; base < R.r1; base += BLOCK) {
+            const int32_t i = base + threadIdx.x;
+            if (i >= R.r1) continue;
+            int32_t c[KMAX];
+            V v[KMAX];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k < A.ew) {
+                    c[k] = ec[k * A.n + i];
+                    v[k] = ev[k * A.n + i];
+                }
+            }
+            V acc = V(0);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < A.ew) acc += v[k] * g(c[k]);
+            emit(i, acc);
+        }
+        return;
+    }
+    const int32_t *__restrict__ rowptr = A.rowptr;
+    const int32_t *__restrict__ col = A.col;
+    const V *__restrict__ val = A.val;
     const int per_pass = BLOCK / lanes;
     const int sub = threadIdx.x % lanes;
     for (int32_t base = R.r0; base < R.r1; base += per_pass) {
@@ -279,8 +317,8 @@ __device__ inline void spmv_rows(const RowRange &R, int lanes, const int32_t *__
 // workgroup's own rows) and multiply from LDS; without room in LDS, own(j, v)
 // runs over the own rows and the product gathers src(col) directly.
 template <class V, class Src, class Own, class Emit>
-__device__ inline void staged_product(const RowRange &R, bool staged, int lanes, const int32_t *rowptr,
-                                      const int32_t *col, const V *val, V *lds, Src src, Own own, Emit emit) {
+__device__ inline void staged_product(const RowRange &R, bool staged, int lanes, const RowMat<V> &A, V *lds,
+                                      Src src, Own own, Emit emit) {
     if (staged) {
         for (int32_t j = R.c0 + threadIdx.x; j <= R.c1; j += BLOCK) {
             const V v = src(j);
@@ -288,12 +326,12 @@ __device__ inline void staged_product(const RowRange &R, bool staged, int lanes,
             if (j >= R.r0 && j < R.r1) own(j, v);
         }
         __syncthreads();
-        spmv_rows<V>(R, lanes, rowptr, col, val, [&](int32_t j) { return lds[j - R.c0]; },
+        spmv_rows<V>(R, lanes, A, [&](int32_t j) { return lds[j - R.c0]; },
                      [&](int32_t i, V y) { emit(i, y, lds[i - R.c0]); });
         __syncthreads();
     } else {
         for (int32_t j = R.r0 + threadIdx.x; j < R.r1; j += BLOCK) own(j, src(j));
-        spmv_rows<V>(R, lanes, rowptr, col, val, src, [&](int32_t i, V y) { emit(i, y, src(i)); });
+        spmv_rows<V>(R, lanes, A, src, [&](int32_t i, V y) { emit(i, y, src(i)); });
     }
 }
 
@@ -318,6 +356,8 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
     const bool staged32 = R.c1 >= R.c0 && R.c1 - R.c0 + 1 <= LDS_FLOATS;
     double *lds64 = sh.lds;
     float *lds32 = reinterpret_cast<float *>(sh.lds);
+    const RowMat<double> A64{D.rowptr, D.col, D.val, D.ell_col, D.ell_val, D.ell_w, n};
+    const RowMat<float> A32{D.rowptr, D.col, D.val32, D.ell_col, D.ell_val32, D.ell_w, n};
     auto nop = [](int32_t, auto) {};
     // carry the recurrence vectors of untouched rows into the write buffers
     auto carry = [&](bool cr, bool cw, bool cs) {
@@ -356,14 +396,14 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
         // J(x) = x.Kx / 2 - b.x = -x.(b + r) / 2 differs from the energy-norm error
         // |x - x*|_K^2 / 2 by a constant, so v[3] = J(prev1) - J(guess) (times 2) > 0
         // says the network's guess is the closer one in the norm CG minimises
-        staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return x[j]; },
+        staged_product<double>(R, staged64, lanes, A64, lds64, [&](int32_t j) { return x[j]; },
                                nop, [&](int32_t i, double y, double) {
                                    const double r = b[i] - y;
                                    v[0] += r * r;
                                    v[2] += b[i] * b[i];
                                    v[3] += x[i] * (b[i] + r);
                                });
-        staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64, [&](int32_t j) { return p1[j]; },
+        staged_product<double>(R, staged64, lanes, A64, lds64, [&](int32_t j) { return p1[j]; },
                                nop, [&](int32_t i, double y, double) {
                                    const double r = b[i] - y;
                                    v[1] += r * r;
@@ -377,7 +417,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
             // after the first, the iterate is x + c (c: the fp32 correction since the last START)
             float *r32 = D.r32 + wr * n;
             float *c32 = D.c32;
-            staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
+            staged_product<double>(R, staged64, lanes, A64, lds64,
                                    [&](int32_t j) { return first ? x[j] : x[j] + static_cast<double>(c32[j]); },
                                    nop, [&](int32_t i, double y, double) {
                                        const double ri = b[i] - y;
@@ -388,7 +428,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
                                    });
         } else {
             double *r = D.r + wr * n;
-            staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
+            staged_product<double>(R, staged64, lanes, A64, lds64,
                                    [&](int32_t j) { return x[j]; }, nop, [&](int32_t i, double y, double) {
                                        const double ri = b[i] - y;
                                        r[i] = ri;
@@ -404,7 +444,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
         if (mixed) {
             const float *r = D.r32 + rd * n, *s = D.s32 + rd * n, *dv = D.dinv32;
             float *w = D.w32 + wr * n;
-            staged_product<float>(R, staged32, lanes, D.rowptr, D.col, D.val32, lds32,
+            staged_product<float>(R, staged32, lanes, A32, lds32,
                                   [&](int32_t j) { return dv[j] * r[j]; },
                                   [&](int32_t j, float u) {
                                       v[0] += static_cast<double>(r[j]) * static_cast<double>(u);
@@ -422,7 +462,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
         } else {
             const double *r = D.r + rd * n, *s = D.s + rd * n, *dv = D.dinv;
             double *w = D.w + wr * n;
-            staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
+            staged_product<double>(R, staged64, lanes, A64, lds64,
                                    [&](int32_t j) { return dv[j] * r[j]; },
                                    [&](int32_t j, double u) {
                                        v[0] += r[j] * u;
@@ -445,7 +485,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
             float *p = D.p32, *cc = D.c32;
             // u_{i+1} at row j from the stable r_i, w_i, s_{i-1}
             auto s_new = [&](int32_t j) { return rs ? w[j] : w[j] + be * so[j]; };
-            staged_product<float>(R, staged32, lanes, D.rowptr, D.col, D.val32, lds32,
+            staged_product<float>(R, staged32, lanes, A32, lds32,
                                   [&](int32_t j) { return dv[j] * (r[j] - al * s_new(j)); },
                                   [&](int32_t j, float u1) {
                                       const float sj = s_new(j);
@@ -470,7 +510,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
             double *rn = D.r + wr * n, *wn = D.w + wr * n, *sn = D.s + wr * n;
             double *p = D.p;
             auto s_new = [&](int32_t j) { return rs ? w[j] : w[j] + be * so[j]; };
-            staged_product<double>(R, staged64, lanes, D.rowptr, D.col, D.val, lds64,
+            staged_product<double>(R, staged64, lanes, A64, lds64,
                                    [&](int32_t j) { return dv[j] * (r[j] - al * s_new(j)); },
                                    [&](int32_t j, double u1) {
                                        const double sj = s_new(j);
