@@ -99,9 +99,10 @@ def parse():
     ap.add_argument("--epochs", type=int, default=None, help="training epochs (c5: 6, sequence: 8)")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workload", default="c5",
-                    choices=["c5", "sequence", "batch", "momentum", "interpolate", "channel"],
+                    choices=["c5", "c4", "sequence", "batch", "momentum", "interpolate", "channel"],
                     help="c5: two-level CGP on batches of 8 Stuart numbers, coarse 1025x513, fine k=2 "
-                         "(default); sequence: one 513x257 CGP sequence; batch: 64-instance Stuart sweep; "
+                         "(default); c4: the learned warm-start protocol (train on 2000 steps, time 1000 "
+                         "held-out ones); sequence: one 513x257 CGP sequence; batch: 64-instance Stuart sweep; "
                          "momentum: the fine-mesh momentum step of Eqs. 13-14; interpolate: the restriction "
                          "of a fine field onto the nodes of a non-nested coarse mesh by point location; channel: "
                          "whole CGP time steps of the flow past a cylinder (Section 3), with drag and lift")
@@ -112,9 +113,14 @@ def parse():
     ap.add_argument("--instances", type=int, default=64, help="batch: number of instances")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--c4-train", type=int, default=2000, help="c4: training steps")
+    ap.add_argument("--c4-eval", type=int, default=1000, help="c4: held-out timed steps")
+    ap.add_argument("--c4-forms", default="ABCGE", help="c4: forms to time")
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     c5 = args.workload == "c5"
+    if args.workload == "c4" and args.epochs is None:
+        args.epochs = 3          # 1998 samples per network
     for name, v5, vs in (("steps", 20, 200), ("warmup", 5, 10), ("forms", "ABCD", "ABCDEF"),
                          ("train_steps", 100, 200), ("epochs", 6, 8)):
         if getattr(args, name) is None:
@@ -520,83 +526,6 @@ def interpolate_main(args):
     ctx.close()
 
 
-class ChannelRun:
-    """The flow past a cylinder of Section 3 on the device: two hierarchies of one channel
-    mesh (the electric potential's Dirichlet set: the box sides; the pressure's: the
-    outflow), the fine level's per-component velocity mask (inflow and cylinder: both
-    components, slip walls: v, outflow: none), the cylinder's boundary edges, and the
-    buffers of one CGP time step (Section 2.3's steps 1-8, every one a library call)."""
-
-    def __init__(self, ctx, coarse, k: int, *, rho=1.0, mu=0.01, dt=0.05, sigma=0.01, b0=1.0,
-                 solve_kw=None, mom_tol=1e-8, mom_max_iter=5000):
-        import numpy as np
-        import torch
-
-        import cgp_inputs as ci
-        import paper_2003_00082_amd as cgp
-
-        self.ctx, self.cgp = ctx, cgp
-        self.rho, self.mu, self.dt, self.sigma, self.b0 = rho, mu, dt, sigma, b0
-        self.mom_tol, self.mom_max_iter = mom_tol, mom_max_iter
-        self.solve_kw = dict(solve_kw or {})
-        dev = torch.device("cuda:0")
-        f64 = dict(dtype=torch.float64, device=dev)
-        self.h_phi = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, k)
-        self.h_p = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.outflow, k)
-        self.k = k
-        xy, tri, _, _ = ctx.mesh_download(self.h_p, k)
-        self.fine_xy, self.fine_tri = xy, tri
-        bnd = ci.channel_boundary(xy, tri, coarse.geometry)
-        self.vmask_np = ((bnd["inflow"] | bnd["cylinder"]) * 3 | bnd["walls"] * 2).astype(np.uint8)
-        self.cyl_np = bnd["cylinder"].astype(bool)
-        self.edges_np = bnd["cyl_edges"]
-        nc, nf = coarse.n_nodes, xy.shape[0]
-        self.nc, self.nf = nc, nf
-        self.vmask = torch.from_numpy(self.vmask_np).to(dev)
-        self.edges = torch.from_numpy(np.ascontiguousarray(self.edges_np)).to(dev)
-        # impulsive start: the free stream everywhere but on the cylinder
-        u0 = np.where(self.cyl_np, 0.0, 1.0)
-        self.u = torch.from_numpy(u0).to(dev)
-        self.v = torch.zeros(nf, **f64)
-        self.ut, self.vt = torch.empty(nf, **f64), torch.empty(nf, **f64)
-        self.fx, self.fy = torch.empty(nf, **f64), torch.empty(nf, **f64)
-        self.phi_c, self.p_c = torch.zeros(nc, **f64), torch.zeros(nc, **f64)
-        self.phi_f, self.p_f = torch.empty(nf, **f64), torch.empty(nf, **f64)
-        self.b_phi, self.b_p = torch.empty(nc, **f64), torch.empty(nc, **f64)
-        self.force = torch.zeros(5, **f64)
-        self.stats = cgp.stats_buffer(2)
-        self.mom_iters = []
-
-    def step(self):
-        ctx, cgp = self.ctx, self.cgp
-        S = cgp.STATS_BYTES
-        ctx.restrict(self.h_phi, self.u, self.v, cgp.CGP_SRC_CURL, self.b0, self.b_phi)          # steps 1-2
-        ctx.poisson_solve([self.h_phi], [self.b_phi], [self.phi_c], self.stats[:S], guess=cgp.CGP_GUESS_GIVEN,
-                          **self.solve_kw)
-        ctx.prolong(self.h_phi, self.phi_c, self.phi_f)                                            # step 3
-        ctx.lorentz_force(self.h_phi, self.phi_f, self.u, self.v, self.sigma, self.b0, self.fx, self.fy)
-        self.ut.copy_(self.u)                                                                    # step 4
-        self.vt.copy_(self.v)
-        st = ctx.momentum_step(self.h_p, self.u, self.v, self.fx, self.fy, self.rho, self.mu, self.dt, self.ut,
-                               self.vt, tol=self.mom_tol, max_iter=self.mom_max_iter, mask=self.vmask)
-        self.mom_iters.append(max(st["iters"]))
-        ctx.restrict(self.h_p, self.ut, self.vt, cgp.CGP_SRC_DIV, self.rho / self.dt, self.b_p)   # steps 5-6
-        ctx.poisson_solve([self.h_p], [self.b_p], [self.p_c], self.stats[S:], guess=cgp.CGP_GUESS_GIVEN,
-                          **self.solve_kw)
-        ctx.prolong(self.h_p, self.p_c, self.p_f)                                                  # step 7
-        ctx.velocity_correct(self.h_p, self.p_f, self.ut, self.vt, self.dt / self.rho, self.u, self.v,
-                             mask=self.vmask)                                                    # step 8
-        ctx.surface_force(self.h_p, self.k, self.edges, self.p_f, self.u, self.v, self.mu, self.force)
-        return st
-
-    def check(self):
-        return self.ctx.solve_check(2, self.stats)
-
-    def close(self):
-        self.ctx.mesh_free(self.h_phi)
-        self.ctx.mesh_free(self.h_p)
-
-
 def channel_main(args):
     """Whole CGP time steps of the flow past a cylinder (Section 3: box 38 x 32, a cylinder of
     diameter 1 at (8, 16), Re = 100 with rho = d = u_inf = 1 and mu = 0.01, dt = 0.05, Stuart
@@ -615,7 +544,10 @@ def channel_main(args):
     ctx = cgp.Context(0)
     kw = dict(precision=cgp.CGP_FP32_IR, tol=TOL, precond_degree=args.degree, deflation=args.deflation,
               refine_delta=args.refine_delta)
-    run = ChannelRun(ctx, coarse, args.channel_k, sigma=args.channel_stuart, solve_kw=kw, mom_tol=args.mom_tol,
+    from paper_2003_00082_amd.channel import ChannelRun
+    run = ChannelRun(ctx, coarse.xy, coarse.tri, coarse.dirichlet, coarse.outflow, args.channel_k,
+                     lambda xy, tri: ci.channel_boundary(xy, tri, coarse.geometry),
+                     sigma=args.channel_stuart, solve_kw=kw, mom_tol=args.mom_tol,
                      mu=args.mu)
     W, K = args.warmup, args.steps
     for _ in range(W):
@@ -861,7 +793,7 @@ def c5_main(args):
         timing = None
         if fdeg >= 1 or form == "A":
             ctx.stage_timing(True)
-            for n in range(K):
+            for n in range(K if form == args.headline else min(K, 3)):   # fewer for the other forms
                 step(n, 2 * (W + K + n))
             torch.cuda.synchronize()
             timing = ctx.stage_timing_read()
@@ -920,6 +852,7 @@ def c5_main(args):
         return out
 
     res = {}
+    args.headline = "B" if "B" in args.forms else args.forms[0]
     for f in args.forms:
         res[f] = run(f)
         print(json.dumps({"form": f, "solves_per_s": res[f]["solves_per_s"], "mean_iters": res[f]["mean_iters"]}),
@@ -1008,6 +941,147 @@ def c5_main(args):
     }
     print(json.dumps(out))
     ctx.close()
+    if args.calibrate_copy:
+        calibrate_copy()
+
+
+def c4_main(args):
+    """The learned warm-start protocol: one coarse 513 x 257 mesh (refined once), a drifting
+    flow over 3000 steps; the networks (one per equation) are trained on the fp64 solutions of
+    steps 0..1999 and every form is timed over steps 2000..2999 (held out), phi and p to 1e-8.
+    Forms: A plain fp64 Jacobi-PCG from the previous solution; B learned guess + fp32 CG
+    refined in fp64, Chebyshev degree d, deflated; C as B from the extrapolation; G the learned
+    guess with plain fp32 Jacobi CG refined in fp64; E as G from the extrapolation."""
+    import numpy as np
+    import torch
+
+    import cgp_inputs as ci
+    import paper_2003_00082_amd as cgp
+
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    nx, ny = args.nx or 513, args.ny or 257
+    T_TRAIN, T_EVAL = args.c4_train, args.c4_eval
+    coarse = ci.jittered_rect(nx, ny, 4000)
+    ctx = cgp.Context(0)
+    stream = torch.cuda.current_stream()
+    h = ctx.mesh_upload(coarse.xy, coarse.tri, coarse.dirichlet, 1)
+    nc, nnz = ctx.mesh_info(h, 0)["n_nodes"], ctx.mesh_info(h, 0)["nnz"]
+    nf = ctx.mesh_info(h, 1)["n_nodes"]
+    seq = ci.DeviceFourierSequence(torch.from_numpy(ctx.mesh_download(h, 1)[0]).to(dev), ci.fourier_modes(4500),
+                                   ci.fourier_modes(4700))
+    rho_dt = 1.0 / ci.DT
+
+    def rhs(n, out_phi, out_p):
+        u, v, ut, vt = seq.at(n)
+        ctx.restrict(h, u, v, cgp.CGP_SRC_CURL, 1.0, out_phi)
+        ctx.restrict(h, ut, vt, cgp.CGP_SRC_DIV, rho_dt, out_p)
+
+    # ---- training data: the fp64 solutions of steps 0..T_TRAIN-1 (each from the previous one)
+    t0 = time.perf_counter()
+    B = {"phi": torch.empty(T_TRAIN, nc, **f64), "p": torch.empty(T_TRAIN, nc, **f64)}
+    X = {"phi": torch.empty(T_TRAIN, nc, **f64), "p": torch.empty(T_TRAIN, nc, **f64)}
+    st1 = cgp.stats_buffer(1)
+    x = {"phi": torch.zeros(nc, **f64), "p": torch.zeros(nc, **f64)}
+    for n in range(T_TRAIN):
+        rhs(n, B["phi"][n], B["p"][n])
+        for eq in ("phi", "p"):
+            ctx.poisson_solve([h], [B[eq][n]], [x[eq]], st1, guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64,
+                              tol=1e-10, precond_degree=args.degree, deflation=1)
+            X[eq][n].copy_(x[eq])
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    models, hist = {}, {}
+    for j, eq in enumerate(("phi", "p")):
+        md = ctx.model_create(seed=21 + j)
+        idx = range(2, T_TRAIN)
+        hist[eq] = ctx.model_train(md, h, [B[eq][q] for q in idx], [X[eq][q - 1] for q in idx],
+                                   [X[eq][q - 2] for q in idx], [X[eq][q] for q in idx], epochs=args.epochs,
+                                   lr=args.lr, seed=31 + j)
+        models[eq] = md
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    last = {eq: [X[eq][T_TRAIN - 3].clone(), X[eq][T_TRAIN - 2].clone(), X[eq][T_TRAIN - 1].clone()]
+            for eq in ("phi", "p")}
+    del B, X
+    # ---- held-out steps, inputs resident before timing
+    Eb = {"phi": torch.empty(T_EVAL, nc, **f64), "p": torch.empty(T_EVAL, nc, **f64)}
+    for q in range(T_EVAL):
+        rhs(T_TRAIN + q, Eb["phi"][q], Eb["p"][q])
+    torch.cuda.synchronize()
+    deg = args.degree
+    forms = {   # precision, guess, degree (0 = Jacobi, row-range kernel), deflation
+        "A": (cgp.CGP_FP64, cgp.CGP_GUESS_GIVEN, 0, 0),
+        "B": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, deg, 1),
+        "C": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, deg, 1),
+        "G": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_LEARNED, 0, 0),
+        "E": (cgp.CGP_FP32_IR, cgp.CGP_GUESS_EXTRAP, 0, 0),
+    }
+    dtype_st = np.dtype([("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"),
+                         ("rel0", "f8")])
+    res = {}
+    for form in args.c4_forms:
+        prec, guess, fdeg, fdefl = forms[form]
+        rot = guess != cgp.CGP_GUESS_GIVEN
+        bufs = {eq: [t.clone() for t in last[eq]] for eq in ("phi", "p")}   # steps T-3, T-2, T-1
+        stats = torch.zeros(2 * T_EVAL * cgp.STATS_BYTES, dtype=torch.uint8, device=dev)
+        kw = dict(precision=prec, guess=guess, precond_degree=fdeg, deflation=fdefl, tol=TOL,
+                  refine_delta=args.refine_delta if fdeg >= 2 else 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in range(T_EVAL):
+            for k, eq in enumerate(("phi", "p")):
+                Bq = bufs[eq]
+                slot = (2 * q + k) * cgp.STATS_BYTES
+                st = stats[slot:slot + cgp.STATS_BYTES]
+                if rot:
+                    cur, p1, p2 = Bq[q % 3], Bq[(q + 2) % 3], Bq[(q + 1) % 3]
+                    extra = dict(prev1=[p1], prev2=[p2])
+                    if guess == cgp.CGP_GUESS_LEARNED:
+                        extra["model"] = models[eq]
+                    ctx.poisson_solve([h], [Eb[eq][q]], [cur], st, **kw, **extra)
+                else:
+                    ctx.poisson_solve([h], [Eb[eq][q]], [Bq[2]], st, **kw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        hs = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=dtype_st)
+        res[form] = {"solves_per_s": 2 * T_EVAL / el, "mean_iters": float(hs["iters"].mean()),
+                     "max_iters": int(hs["iters"].max()), "mean_refinements": float(hs["ref"].mean()),
+                     "all_converged": bool(np.all(hs["status"] == 0) and np.all(hs["rel"] <= TOL)),
+                     "mean_guess_rel_res": float(hs["rel0"].mean()),
+                     "learned_guess_kept": (float(np.mean(hs["guess"] == cgp.CGP_GUESS_LEARNED))
+                                            if guess == cgp.CGP_GUESS_LEARNED else None),
+                     "precision": "fp32+fp64 refinement" if prec == cgp.CGP_FP32_IR else "fp64",
+                     "preconditioner": (f"Chebyshev degree {fdeg}" if fdeg >= 2 else "Jacobi") +
+                                       (", deflated" if fdefl else ""),
+                     "guess": {cgp.CGP_GUESS_GIVEN: "previous solution", cgp.CGP_GUESS_EXTRAP: "extrapolation",
+                               cgp.CGP_GUESS_LEARNED: "learned"}[guess]}
+        print(json.dumps({"form": form, **{k: res[form][k] for k in ("solves_per_s", "mean_iters")}}),
+              file=sys.stderr, flush=True)
+    main_form = "B" if "B" in res else args.c4_forms[0]
+    R = res[main_form]
+    out = {
+        "metric": METRIC, "value": R["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": T_EVAL,
+        "warmup": T_TRAIN, "ms_per_step": 2e3 / R["solves_per_s"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64 (network bf16)", "data": "synthetic",
+        "config": {"workload": f"learned warm start: coarse {nx}x{ny} jittered P1 ({nc} nodes, nnz {nnz}), fine "
+                               f"k=1 ({nf} nodes), {T_TRAIN + T_EVAL}-step drifting flow, networks trained on the "
+                               f"fp64 solutions of steps 0..{T_TRAIN - 1}, timed on the held-out steps "
+                               f"{T_TRAIN}..{T_TRAIN + T_EVAL - 1}, phi and p to {TOL:g}",
+                   "coarse_nodes": nc, "nnz": nnz, "train_steps": T_TRAIN, "eval_steps": T_EVAL, "tol": TOL},
+        "forms": res,
+        "speedup_over_A": ({f: res[f]["solves_per_s"] / res["A"]["solves_per_s"] for f in res} if "A" in res else None),
+        "iterations_vs_previous_solution_pcg": ({f: res[f]["mean_iters"] / res["A"]["mean_iters"] for f in res}
+                                               if "A" in res else None),
+        "training": {"samples_per_network": T_TRAIN - 2, "epochs": args.epochs, "lr": args.lr, "data_s": data_s,
+                     "train_s": train_s, "loss_first_epoch": {k: float(v[0]) for k, v in hist.items()},
+                     "loss_last_epoch": {k: float(v[-1]) for k, v in hist.items()}},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+    ctx.close()
 
 
 def cpu_model() -> str:
@@ -1068,6 +1142,8 @@ def main():
         return cpu_worker(args.cpu_worker)
     if args.workload == "c5":
         return c5_main(args)
+    if args.workload == "c4":
+        return c4_main(args)
     if args.workload == "batch":
         if args.steps == 200:
             args.steps = 6

@@ -296,13 +296,15 @@ class DeviceFourierSequence:
         t = n * DT
         s = self._sin(0, t)
         m = self.sets[0]
-        u = -(s @ (m["c"] * m["ky"]))
-        v = s @ (m["c"] * m["kx"])
+        # mode sums as row sums of broadcast products (a matrix-vector product with 8 columns
+        # runs as a slow library reduction on the device)
+        u = -(s * (m["c"] * m["ky"])[None, :]).sum(dim=1)
+        v = (s * (m["c"] * m["kx"])[None, :]).sum(dim=1)
         del s
         s2 = self._sin(1, t)
         c2 = self.sets[1]
-        ut = u - s2 @ (c2["c"] * c2["kx"])
-        vt = v - s2 @ (c2["c"] * c2["ky"])
+        ut = u - (s2 * (c2["c"] * c2["kx"])[None, :]).sum(dim=1)
+        vt = v - (s2 * (c2["c"] * c2["ky"])[None, :]).sum(dim=1)
         return u.contiguous(), v.contiguous(), ut.contiguous(), vt.contiguous()
 
 
