@@ -137,7 +137,7 @@ Mesh &get_mesh(cgp_ctx ctx, cgp_mesh h) {
     return *it->second;
 }
 
-void ensure_work(Mesh &m) {
+void ensure_work(Mesh &m, hipStream_t st) {
     const int64_t n = m.lv[0].n;
     SolveWork &w = m.work;
     if (w.n == n) return;
@@ -152,6 +152,11 @@ void ensure_work(Mesh &m) {
     w.c32.alloc(n);
     w.u.alloc(n);
     w.u32.alloc(n);
+    w.rwsd32.alloc(8 * n);
+    w.rwsd64.alloc(8 * n);
+    w.up32.alloc(2 * n);
+    w.up64.alloc(2 * n);
+    launch_fill_rwsd(st, n, m.dinv32.p, m.dinv.p, w.rwsd32.p, w.rwsd64.p);
     w.n = n;
 }
 
@@ -189,10 +194,13 @@ std::vector<int32_t> split_blocks(const std::vector<int64_t> &rows, int grid) {
 struct WorkPtrs {
     double *r, *w, *s, *p, *u;
     float *r32, *w32, *s32, *p32, *c32, *u32;
+    float *rwsd32, *up32;
+    double *rwsd64, *up64;
 };
 
 WorkPtrs work_ptrs(SolveWork &w) {
-    return WorkPtrs{w.r.p, w.w.p, w.s.p, w.p.p, w.u.p, w.r32.p, w.w32.p, w.s32.p, w.p32.p, w.c32.p, w.u32.p};
+    return WorkPtrs{w.r.p,   w.w.p,   w.s.p,   w.p.p,      w.u.p,    w.r32.p,    w.w32.p, w.s32.p,
+                    w.p32.p, w.c32.p, w.u32.p, w.rwsd32.p, w.up32.p, w.rwsd64.p, w.up64.p};
 }
 
 // Chebyshev iteration over [hi/1000, hi] ([hi/30, hi] with deflation, whose coarse space takes
@@ -251,6 +259,10 @@ InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int d
     d.p32 = ws.p32;
     d.c32 = ws.c32;
     d.u32 = ws.u32;
+    d.rwsd32 = ws.rwsd32;
+    d.up32 = ws.up32;
+    d.rwsd64 = ws.rwsd64;
+    d.up64 = ws.up64;
     if (T) {
         d.degree = degree;
         d.tblk = T->blk.p;
@@ -679,7 +691,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
         // latency of the row gathers
         int grid = o.blocks > 0 ? o.blocks : (persistent ? max_grid : ctx->cus);
         grid = std::min(grid, max_grid);
-        for (int i = 0; i < n_inst; ++i) ensure_work(*ms[i]);
+        for (int i = 0; i < n_inst; ++i) ensure_work(*ms[i], ctx->stream);
 
         // instances in groups of at most `grid` (one workgroup minimum each)
         for (int g0 = 0; g0 < n_inst; g0 += (persistent ? grid : n_inst)) {
@@ -1023,11 +1035,32 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
             off = (off + bytes + 255) / 256 * 256;
             return at;
         };
-        const size_t o_r = take(2 * n * sizeof(double)), o_w = take(2 * n * sizeof(double)),
-                     o_s = take(2 * n * sizeof(double)), o_p = take(n * sizeof(double)), o_u = take(n * sizeof(double));
-        const size_t o_r32 = take(2 * n * sizeof(float)), o_w32 = take(2 * n * sizeof(float)),
-                     o_s32 = take(2 * n * sizeof(float)), o_p32 = take(n * sizeof(float)),
-                     o_c32 = take(n * sizeof(float)), o_u32 = take(n * sizeof(float));
+        // the iteration's vectors: the row-range kernel's separate arrays, or the tiled
+        // iteration's row-interleaved (r, w, s, D^-1) and (u, p) in the solve's precision and c
+        const bool mixed = o.precision == CGP_FP32_IR;
+        size_t o_r = 0, o_w = 0, o_s = 0, o_p = 0, o_u = 0, o_r32 = 0, o_w32 = 0, o_s32 = 0, o_p32 = 0, o_c32 = 0,
+               o_u32 = 0, o_rwsd = 0, o_up = 0;
+        if (!tiled) {
+            o_r = take(2 * n * sizeof(double));
+            o_w = take(2 * n * sizeof(double));
+            o_s = take(2 * n * sizeof(double));
+            o_p = take(n * sizeof(double));
+            o_u = take(n * sizeof(double));
+            o_r32 = take(2 * n * sizeof(float));
+            o_w32 = take(2 * n * sizeof(float));
+            o_s32 = take(2 * n * sizeof(float));
+            o_p32 = take(n * sizeof(float));
+            o_c32 = take(n * sizeof(float));
+            o_u32 = take(n * sizeof(float));
+            o_rwsd = o_up = o_r;   // not read by the row-range kernel
+        } else {
+            const size_t e = mixed ? sizeof(float) : sizeof(double);
+            o_rwsd = take(8 * n * e);
+            o_up = take(2 * n * e);
+            o_c32 = take(n * sizeof(float));
+            // the row-range arrays are not read by the tiled kernel; they alias the interleaved buffer
+            o_r = o_w = o_s = o_p = o_u = o_r32 = o_w32 = o_s32 = o_p32 = o_u32 = o_rwsd;
+        }
         const size_t o_inst = take(sizeof(InstDesc)), o_bi = take(sizeof(int32_t) * nblk),
                      o_rng = take(sizeof(RowRange) * nblk), o_ctl = take(2 * sizeof(Ctl)), o_done = take(sizeof(int32_t)),
                      o_prm = take(sizeof(SolveParams)), o_part = take(sizeof(double) * 2 * NPART * nblk),
@@ -1042,12 +1075,14 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
         uint8_t *base = noalloc_scratch(ctx->device);
         CGP_REQUIRE(base != nullptr, "the no-allocation array of this device was not looked up");
         auto at = [&](size_t o_) { return base + o_; };
-        WorkPtrs ws{reinterpret_cast<double *>(at(o_r)), reinterpret_cast<double *>(at(o_w)),
-                    reinterpret_cast<double *>(at(o_s)), reinterpret_cast<double *>(at(o_p)),
-                    reinterpret_cast<double *>(at(o_u)), reinterpret_cast<float *>(at(o_r32)),
-                    reinterpret_cast<float *>(at(o_w32)), reinterpret_cast<float *>(at(o_s32)),
-                    reinterpret_cast<float *>(at(o_p32)), reinterpret_cast<float *>(at(o_c32)),
-                    reinterpret_cast<float *>(at(o_u32))};
+        WorkPtrs ws{reinterpret_cast<double *>(at(o_r)),   reinterpret_cast<double *>(at(o_w)),
+                    reinterpret_cast<double *>(at(o_s)),   reinterpret_cast<double *>(at(o_p)),
+                    reinterpret_cast<double *>(at(o_u)),   reinterpret_cast<float *>(at(o_r32)),
+                    reinterpret_cast<float *>(at(o_w32)),  reinterpret_cast<float *>(at(o_s32)),
+                    reinterpret_cast<float *>(at(o_p32)),  reinterpret_cast<float *>(at(o_c32)),
+                    reinterpret_cast<float *>(at(o_u32)),  reinterpret_cast<float *>(at(o_rwsd)),
+                    reinterpret_cast<float *>(at(o_up)),   reinterpret_cast<double *>(at(o_rwsd)),
+                    reinterpret_cast<double *>(at(o_up))};
         const bool extrap = o.guess == CGP_GUESS_EXTRAP;
         const int lanes = o.spmv_lanes ? o.spmv_lanes : 4;
         InstDesc d = describe_instance(m, ws, T, degree, defl, false, lanes, o.guess, d_b, d_phi,
@@ -1083,6 +1118,8 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
         CoarseRec *d_crec = reinterpret_cast<CoarseRec *>(at(o_crec));
         hipStream_t st = ctx->stream;
         launch_noalloc_setup(st, d_insts, d, d_bi, nblk, d_cbi, ncb, zero, na + ncb, defl ? d_crec : nullptr, cr);
+        if (tiled)   // D^-1 into the interleaved vectors (the array keeps whatever the last call left)
+            launch_fill_rwsd(st, n, m.dinv32.p, m.dinv.p, mixed ? ws.rwsd32 : nullptr, mixed ? nullptr : ws.rwsd64);
         launch_ranges(st, d_insts, d_bi, nblk, d_rng);
         volatile int32_t *flag = ctx->host_flag;
         flag[0] = 0;
@@ -1092,7 +1129,6 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
         // whose halo does not fit takes the general stage path)
         const int launches = o.launches_per_graph > 0 ? o.launches_per_graph : 16;
         const int64_t max_stages = 4 * static_cast<int64_t>(prm.max_iter) + 16;
-        const bool mixed = o.precision == CGP_FP32_IR;
         int64_t issued = 0, chunk = 0;
         for (;;) {
             if (chunk >= 2) {

@@ -80,11 +80,17 @@ struct Level {
 };
 
 // per-instance solver workspace, owned by the mesh (r, w, s double-buffered;
-// u = M^-1 r of the tiled iteration single-buffered: only its own row reads it)
+// u = M^-1 r of the tiled iteration single-buffered: only its own row reads it).  The
+// tiled iteration keeps its vectors row-interleaved instead: rwsd [2][n][4] = (r, w, s,
+// D^-1) of a row by stage parity (one 16-byte gather per region row in fp32; D^-1 written
+// once, when the buffers are made), and up [n][2] = (u, p) by own slot (a tile's own rows
+// are consecutive slots, TileBlk::own_off on), which only the owning tile reads.
 struct SolveWork {
     int64_t n = 0;
     DBuf<double> r, w, s, p, u;
     DBuf<float> r32, w32, s32, p32, c32, u32;
+    DBuf<float> rwsd32, up32;
+    DBuf<double> rwsd64, up64;
 };
 
 // ------------------------------------------------------------------ tiled iteration
@@ -109,6 +115,7 @@ struct TileBlk {
     int32_t nt[TILE_MAX_DEGREE + 2];  // nt[t]: region rows at distance <= t
     int32_t kz_off;                   // deflation: first coupling record of the tile
     int32_t nkz;                      // deflation: coupling records (<= TILE_ROWS)
+    int32_t own_off;                  // first own slot of the tile (own rows of tiles 0..t-1)
 };
 
 // 16-bit column entries per local matrix row record (a multiple of 8: 16-byte loads)
@@ -295,6 +302,10 @@ struct InstDesc {
     const double *tval;
     double *u;                           // M^-1 r (own rows)
     float *u32;
+    float *rwsd32;                       // tiled iteration: (r, w, s, D^-1) [2][n][4] and (u, p) [n][2]
+    float *up32;
+    double *rwsd64;
+    double *up64;
     double cheb[2 * TILE_MAX_DEGREE];    // [0]: scale of the first step; [2k-1], [2k]: step k coefficients
     // subdomain deflation (tiled iteration only; aggregates = the instance's tiles)
     int32_t defl;                        // 0 off, 1 on
@@ -337,6 +348,9 @@ void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_bloc
                    RowRange *d_ranges);
 void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
                     int32_t *d_done);
+// D^-1 into the fourth component of both parities of the row-interleaved vectors (either may be null)
+void launch_fill_rwsd(hipStream_t s, int64_t n, const float *dinv32, const double *dinv, float *rwsd32,
+                      double *rwsd64);
 // h_one: the record of a single-instance solve (passed by value to the kernel), else null
 void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts, const InstDesc *h_one,
                     const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm,

@@ -271,9 +271,9 @@ struct RowMat {
 // emit(i, y_i) from each row's first lane.  With one lane per row and an ELL copy of at
 // most KMAX columns, a thread issues its row's loads together from the ELL copy (same
 // terms, same order) instead of walking the CSR row one dependent load at a time.
-template <class V, class Gather, class Emit>
+template <bool ELL, class V, class Gather, class Emit>
 __device__ inline void spmv_rows(const RowRange &R, int lanes, const RowMat<V> &A, Gather g, Emit emit) {
-    if (lanes == 1 && A.ecol && A.ew <= KMAX) {
+    if (ELL && lanes == 1 && A.ecol && A.ew <= KMAX) {
         const CGP_GLOBAL int32_t *ec = gld(A.ecol);
         const CGP_GLOBAL V *ev = gld(A.eval);
         for (int32_t base = R.r0; base < R.r1; base += BLOCK) {
@@ -316,7 +316,7 @@ __device__ inline void spmv_rows(const RowRange &R, int lanes, const RowMat<V> &
 // Fill LDS with src(j) over the column range (calling own(j, v) for the
 // workgroup's own rows) and multiply from LDS; without room in LDS, own(j, v)
 // runs over the own rows and the product gathers src(col) directly.
-template <class V, class Src, class Own, class Emit>
+template <bool ELL, class V, class Src, class Own, class Emit>
 __device__ inline void staged_product(const RowRange &R, bool staged, int lanes, const RowMat<V> &A, V *lds,
                                       Src src, Own own, Emit emit) {
     if (staged) {
@@ -326,12 +326,12 @@ __device__ inline void staged_product(const RowRange &R, bool staged, int lanes,
             if (j >= R.r0 && j < R.r1) own(j, v);
         }
         __syncthreads();
-        spmv_rows<V>(R, lanes, A, [&](int32_t j) { return lds[j - R.c0]; },
+        spmv_rows<ELL, V>(R, lanes, A, [&](int32_t j) { return lds[j - R.c0]; },
                      [&](int32_t i, V y) { emit(i, y, lds[i - R.c0]); });
         __syncthreads();
     } else {
         for (int32_t j = R.r0 + threadIdx.x; j < R.r1; j += BLOCK) own(j, src(j));
-        spmv_rows<V>(R, lanes, A, src, [&](int32_t i, V y) { emit(i, y, src(i)); });
+        spmv_rows<ELL, V>(R, lanes, A, src, [&](int32_t i, V y) { emit(i, y, src(i)); });
     }
 }
 
@@ -344,6 +344,10 @@ struct Shared {
 
 // One stage of instance D over the workgroup's rows (any number of rows per
 // thread); reads buffers rd = par^1, writes buffers wr = par; partial sums into v[].
+// ELL: the one-lane products may read the rows from the ELL copy (the persistent engine's
+// workgroups own thousands of rows); the staged kernels leave it out, where its registers
+// would crowd the prefetched iteration
+template <bool ELL>
 __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRange &R,
                                         const SolveParams &prm, Shared &sh, int par, double (&v)[NPART]) {
     const bool mixed = prm.precision == CGP_FP32_IR;
@@ -396,14 +400,14 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
         // J(x) = x.Kx / 2 - b.x = -x.(b + r) / 2 differs from the energy-norm error
         // |x - x*|_K^2 / 2 by a constant, so v[3] = J(prev1) - J(guess) (times 2) > 0
         // says the network's guess is the closer one in the norm CG minimises
-        staged_product<double>(R, staged64, lanes, A64, lds64, [&](int32_t j) { return x[j]; },
+        staged_product<ELL, double>(R, staged64, lanes, A64, lds64, [&](int32_t j) { return x[j]; },
                                nop, [&](int32_t i, double y, double) {
                                    const double r = b[i] - y;
                                    v[0] += r * r;
                                    v[2] += b[i] * b[i];
                                    v[3] += x[i] * (b[i] + r);
                                });
-        staged_product<double>(R, staged64, lanes, A64, lds64, [&](int32_t j) { return p1[j]; },
+        staged_product<ELL, double>(R, staged64, lanes, A64, lds64, [&](int32_t j) { return p1[j]; },
                                nop, [&](int32_t i, double y, double) {
                                    const double r = b[i] - y;
                                    v[1] += r * r;
@@ -417,7 +421,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
             // after the first, the iterate is x + c (c: the fp32 correction since the last START)
             float *r32 = D.r32 + wr * n;
             float *c32 = D.c32;
-            staged_product<double>(R, staged64, lanes, A64, lds64,
+            staged_product<ELL, double>(R, staged64, lanes, A64, lds64,
                                    [&](int32_t j) { return first ? x[j] : x[j] + static_cast<double>(c32[j]); },
                                    nop, [&](int32_t i, double y, double) {
                                        const double ri = b[i] - y;
@@ -428,7 +432,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
                                    });
         } else {
             double *r = D.r + wr * n;
-            staged_product<double>(R, staged64, lanes, A64, lds64,
+            staged_product<ELL, double>(R, staged64, lanes, A64, lds64,
                                    [&](int32_t j) { return x[j]; }, nop, [&](int32_t i, double y, double) {
                                        const double ri = b[i] - y;
                                        r[i] = ri;
@@ -444,7 +448,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
         if (mixed) {
             const float *r = D.r32 + rd * n, *s = D.s32 + rd * n, *dv = D.dinv32;
             float *w = D.w32 + wr * n;
-            staged_product<float>(R, staged32, lanes, A32, lds32,
+            staged_product<ELL, float>(R, staged32, lanes, A32, lds32,
                                   [&](int32_t j) { return dv[j] * r[j]; },
                                   [&](int32_t j, float u) {
                                       v[0] += static_cast<double>(r[j]) * static_cast<double>(u);
@@ -462,7 +466,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
         } else {
             const double *r = D.r + rd * n, *s = D.s + rd * n, *dv = D.dinv;
             double *w = D.w + wr * n;
-            staged_product<double>(R, staged64, lanes, A64, lds64,
+            staged_product<ELL, double>(R, staged64, lanes, A64, lds64,
                                    [&](int32_t j) { return dv[j] * r[j]; },
                                    [&](int32_t j, double u) {
                                        v[0] += r[j] * u;
@@ -485,7 +489,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
             float *p = D.p32, *cc = D.c32;
             // u_{i+1} at row j from the stable r_i, w_i, s_{i-1}
             auto s_new = [&](int32_t j) { return rs ? w[j] : w[j] + be * so[j]; };
-            staged_product<float>(R, staged32, lanes, A32, lds32,
+            staged_product<ELL, float>(R, staged32, lanes, A32, lds32,
                                   [&](int32_t j) { return dv[j] * (r[j] - al * s_new(j)); },
                                   [&](int32_t j, float u1) {
                                       const float sj = s_new(j);
@@ -510,7 +514,7 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
             double *rn = D.r + wr * n, *wn = D.w + wr * n, *sn = D.s + wr * n;
             double *p = D.p;
             auto s_new = [&](int32_t j) { return rs ? w[j] : w[j] + be * so[j]; };
-            staged_product<double>(R, staged64, lanes, A64, lds64,
+            staged_product<ELL, double>(R, staged64, lanes, A64, lds64,
                                    [&](int32_t j) { return dv[j] * (r[j] - al * s_new(j)); },
                                    [&](int32_t j, double u1) {
                                        const double sj = s_new(j);
@@ -765,7 +769,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
         iter_fast<T, H>(f, c, D, R, par, reinterpret_cast<T *>(sh.lds), v);
     } else {
         const SolveParams prm = *prm_dev;
-        stage_work(c, D, R, prm, sh, par, v);
+        stage_work<false>(c, D, R, prm, sh, par, v);
     }
     block_sums(v, sh.red, sh.sums);
     if (threadIdx.x < NPART) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
@@ -789,6 +793,19 @@ static_assert(BLOCK == TILE_ROWS, "one own row per thread in a tile of TILE_ROWS
 static_assert(TILE_OWN * BLOCK == TILE_ROWS_MAX && TILE_OWN <= TS, "own rows are local matrix rows");
 static_assert(4 * TILE_REGION * sizeof(double) <= LDS_DOUBLES * sizeof(double),
               "three region vectors and the deflation term in LDS");
+
+template <class T>
+__device__ inline T *rwsd_of(const InstDesc &D);
+template <>
+__device__ inline double *rwsd_of<double>(const InstDesc &D) { return D.rwsd64; }
+template <>
+__device__ inline float *rwsd_of<float>(const InstDesc &D) { return D.rwsd32; }
+template <class T>
+__device__ inline T *up_of(const InstDesc &D);
+template <>
+__device__ inline double *up_of<double>(const InstDesc &D) { return D.up64; }
+template <>
+__device__ inline float *up_of<float>(const InstDesc &D) { return D.up32; }
 
 template <class T, int W>
 struct TilePrefetch {
@@ -856,32 +873,41 @@ __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, c
         const int t = threadIdx.x + h * BLOCK;
         f.g[h] = t < B.nreg ? reg[t] : -1;
     }
-    const CGP_GLOBAL T *r = gld(vec_of<T>(D, 0) + rd * n), *w = gld(vec_of<T>(D, 1) + rd * n);
-    const CGP_GLOBAL T *s = gld(vec_of<T>(D, 2) + rd * n), *dv = gld(vec_of<T>(D, 3));
+    // (r, w, s, D^-1) of a region row: one 16-byte load (fp32) or two (fp64)
+    const CGP_GLOBAL u32x4 *q = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(rwsd_of<T>(D)) + rd * n * 4);
 #pragma unroll
     for (int h = 0; h < TH; ++h) {
         const int32_t j = f.g[h];
         if (j >= 0) {
-            f.r[h] = r[j];
-            f.w[h] = w[j];
-            f.s[h] = s[j];
-            f.dv[h] = dv[j];
+            if constexpr (sizeof(T) == 4) {
+                const u32x4 a = q[j];
+                f.r[h] = __uint_as_float(a.x);
+                f.w[h] = __uint_as_float(a.y);
+                f.s[h] = __uint_as_float(a.z);
+                f.dv[h] = __uint_as_float(a.w);
+            } else {
+                const u32x4 a = q[2 * static_cast<int64_t>(j)], b = q[2 * static_cast<int64_t>(j) + 1];
+                f.r[h] = __hiloint2double(static_cast<int>(a.y), static_cast<int>(a.x));
+                f.w[h] = __hiloint2double(static_cast<int>(a.w), static_cast<int>(a.z));
+                f.s[h] = __hiloint2double(static_cast<int>(b.y), static_cast<int>(b.x));
+                f.dv[h] = __hiloint2double(static_cast<int>(b.w), static_cast<int>(b.z));
+            }
         }
     }
+    // own rows: (u, p) by own slot, consecutive over the tile; c (fp32) or x (fp64) by row
+    const CGP_GLOBAL T *up = gld(up_of<T>(D)) + 2 * static_cast<int64_t>(B.own_off);
 #pragma unroll
     for (int h = 0; h < TILE_OWN; ++h) {
         f.ou[h] = f.op[h] = f.ox[h] = T(0);
-        if (static_cast<int>(threadIdx.x) + h * BLOCK < B.nt[0]) {
+        const int t = static_cast<int>(threadIdx.x) + h * BLOCK;
+        if (t < B.nt[0]) {
             const int32_t j = f.g[h];
-            if constexpr (sizeof(T) == 4) {
-                f.ou[h] = gld(D.u32)[j];
-                f.op[h] = gld(D.p32)[j];
+            f.ou[h] = up[2 * t];
+            f.op[h] = up[2 * t + 1];
+            if constexpr (sizeof(T) == 4)
                 f.ox[h] = gld(D.c32)[j];
-            } else {
-                f.ou[h] = gld(D.u)[j];
-                f.op[h] = gld(D.p)[j];
+            else
                 f.ox[h] = gld(D.x)[j];
-            }
         }
     }
 }
@@ -1025,27 +1051,31 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
         const int32_t j = f.g[h];
         const T u1 = zz[h];
         const T wn = tile_row(f, h, Uz);
-        gst(const_cast<T *>(vec_of<T>(D, 0)) + wr * n)[j] = r_own[h];
-        gst(const_cast<T *>(vec_of<T>(D, 1)) + wr * n)[j] = wn;
-        gst(const_cast<T *>(vec_of<T>(D, 2)) + wr * n)[j] = s_own[h];
-        if constexpr (sizeof(T) == 4)
-            gst(D.u32)[j] = u1;
-        else
-            gst(D.u)[j] = u1;
+        // (r, w, s) of the row into the write parity (D^-1 stays in the fourth slot)
+        CGP_GLOBAL T *q = gst(rwsd_of<T>(D)) + (wr * n + j) * 4;
+        q[0] = r_own[h];
+        q[1] = wn;
+        q[2] = s_own[h];
+        CGP_GLOBAL T *up = gst(up_of<T>(D)) + 2 * (static_cast<int64_t>(B.own_off) + threadIdx.x + h * BLOCK);
         if (!start) {
             const T pj = (rs ? f.ou[h] : f.ou[h] + be * f.op[h]) - zm[h];
-            gst(const_cast<T *>(vec_of<T>(D, 4)))[j] = pj;
+            up[0] = u1;
+            up[1] = pj;
             if constexpr (sizeof(T) == 4)
                 gst(D.c32)[j] = f.ox[h] + al * pj;
             else
                 gst(D.x)[j] = f.ox[h] + al * pj;
-        } else if constexpr (sizeof(T) == 4) {
-            // mixed: fold the correction the residual stage saw (f.ox = c) into x; the next
-            // correction starts with the coarse step (deflation) or at zero
-            gst(D.x)[j] = gld(D.x)[j] + static_cast<double>(f.ox[h]);
-            gst(D.c32)[j] = zm[h];
-        } else if (defl) {
-            gst(D.x)[j] = f.ox[h] + zm[h];   // fp64: the coarse correction of x
+        } else {
+            up[0] = u1;
+            up[1] = f.op[h];   // the direction carried (a refinement that keeps it reads it next)
+            if constexpr (sizeof(T) == 4) {
+                // mixed: fold the correction the residual stage saw (f.ox = c) into x; the next
+                // correction starts with the coarse step (deflation) or at zero
+                gst(D.x)[j] = gld(D.x)[j] + static_cast<double>(f.ox[h]);
+                gst(D.c32)[j] = zm[h];
+            } else if (defl) {
+                gst(D.x)[j] = f.ox[h] + zm[h];   // fp64: the coarse correction of x
+            }
         }
         const double r64 = static_cast<double>(r_own[h]), u64 = static_cast<double>(u1);
         v[0] += r64 * u64;
@@ -1056,8 +1086,8 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
     }
 }
 
-// The residual stage of a deflated solve, over the tile's own rows (so that the fifth
-// partial is the tile's aggregate sum Z^T r): r = b - K x in fp64 from the CSR matrix.
+// The residual stage of a tiled solve, over the tile's own rows (so that, with deflation, the
+// aggregate partials are the tile's sums Z^T r): r = b - K x in fp64 from the CSR matrix.
 __device__ inline void tile_res_row(const Ctl &c, const InstDesc &D, int32_t own, int code, bool mixed, int par,
                                     double (&v)[NPART]) {
     const int64_t n = D.n;
@@ -1073,13 +1103,14 @@ __device__ inline void tile_res_row(const Ctl &c, const InstDesc &D, int32_t own
     }
     const double bi = gld(D.b)[own], ri = bi - kx;
     if (mixed) {
-        gst(D.r32)[wr * n + own] = static_cast<float>(ri);
+        CGP_GLOBAL float *q = gst(D.rwsd32);
+        q[(wr * n + own) * 4] = static_cast<float>(ri);
         if (c.first)
             gst(D.c32)[own] = 0.0f;
         else
-            gst(D.s32)[wr * n + own] = gld(D.s32)[rd * n + own];   // START keeps the direction: it needs s
+            q[(wr * n + own) * 4 + 2] = q[(rd * n + own) * 4 + 2];   // START keeps the direction: it needs s
     } else {
-        gst(D.r)[wr * n + own] = ri;
+        gst(D.rwsd64)[(wr * n + own) * 4] = ri;
     }
     v[0] += ri * ri;
     if (c.first) v[1] += bi * bi;
@@ -1151,12 +1182,13 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
 #pragma unroll
         for (int h = 0; h < TILE_OWN; ++h) zm[h] = df.code[h] == 1 ? df.mu0 : (df.code[h] == 2 ? df.mu1 : T(0));
         tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), kzm, defl, zm, df.code, v);
-    } else if (c.state == ST_RES && defl) {
+    } else if (c.state == ST_RES) {
+        // the residual over the tile's own rows (its vectors are the tiled iteration's own)
         tile_res<T, W>(c, D, B, f, df.code, sizeof(T) == 4, par, v);
     } else {
         const SolveParams prm = *prm_dev;
         const RowRange R = ranges[D.blk0 + lb];
-        stage_work(c, D, R, prm, sh, par, v);
+        stage_work<false>(c, D, R, prm, sh, par, v);
     }
     block_sums(v, sh.red, sh.sums);
     if (threadIdx.x < NPART) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
@@ -1265,6 +1297,14 @@ __global__ __launch_bounds__(64 * COARSE_WAVES) void k_cg_coarse(const CoarseRec
     coarse_rows<E>(C, blockIdx.x - C.cblk0, par);
 }
 
+__global__ void k_fill_rwsd(int64_t n, const float *dinv32, const double *dinv, float *rwsd32, double *rwsd64) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= 2 * n) return;
+    const int64_t row = i < n ? i : i - n;
+    if (rwsd32) rwsd32[i * 4 + 3] = dinv32[row];
+    if (rwsd64) rwsd64[i * 4 + 3] = dinv[row];
+}
+
 __global__ void k_cg_boot(InstDesc *insts, int n_inst, const SolveParams prm, SolveParams *prm_dev,
                           int32_t *done_count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1341,7 +1381,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_persistent(const InstDesc *__restr
         double *part = D.partials + static_cast<size_t>(par) * NPART * D.nblk;
         const Ctl c = sh.ctl;
         double v[NPART] = {};
-        if (c.state != ST_DONE) stage_work(c, D, R, prm, sh, par, v);
+        if (c.state != ST_DONE) stage_work<true>(c, D, R, prm, sh, par, v);
         block_sums(v, sh.red, sh.sums);
         if (threadIdx.x < NPART) part[threadIdx.x * D.nblk + lb] = sh.sums[threadIdx.x];
         if (!grid_barrier(gs, gridDim.x, my_gen, timeout, &s_ok)) {
@@ -1440,6 +1480,12 @@ void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_bloc
 void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
                     int32_t *d_done) {
     hipLaunchKernelGGL(k_cg_boot, dim3((n_inst + 255) / 256), dim3(256), 0, s, d_insts, n_inst, prm, d_prm, d_done);
+    CGP_HIP(hipGetLastError());
+}
+
+void launch_fill_rwsd(hipStream_t s, int64_t n, const float *dinv32, const double *dinv, float *rwsd32,
+                      double *rwsd64) {
+    hipLaunchKernelGGL(k_fill_rwsd, dim3(blocks_for(2 * n, 256)), dim3(256), 0, s, n, dinv32, dinv, rwsd32, rwsd64);
     CGP_HIP(hipGetLastError());
 }
 

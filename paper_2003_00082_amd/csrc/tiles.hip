@@ -109,6 +109,7 @@ bool build_tiles(int64_t n, int parts, int degree, int width, const std::vector<
         for (int t = degree + 1; t < TILE_MAX_DEGREE + 2; ++t) B.nt[t] = B.nt[degree];
         B.kz_off = 0;
         B.nkz = 0;
+        B.own_off = static_cast<int32_t>(b0);
         B.nreg = B.nt[degree];
         B.nspmv = B.nt[std::max(degree - 1, 0)];
         if (B.nreg > TILE_REGION || B.nspmv > TILE_SPMV) return false;
