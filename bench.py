@@ -52,6 +52,13 @@ MEASURED_TRAFFIC = {"fingerprint": "76f97e3fb1e5a8e5", "profile": "profiles/cg_t
                     "k_cg_tile<double, 8, true, true> degree 6 deflated": 42.61e6}
 
 
+# The same for the batched tiled stage of the two-level workload (8 instances of the 1025x513 coarse
+# mesh, Chebyshev degree 6, deflated, fp32 with fp64 refinement), mean over the launches of a short
+# form-B run (iterations, restarts, residual stages, launches past the end).
+MEASURED_TRAFFIC_C5 = {"fingerprint": "0efb250fd83bf34c", "profile": "profiles/cg_traffic_c5_batch8.md",
+                       "k_cg_tile<float, 8, true, false>": 798.9e6, "k_cg_coarse<float>": 69.1e6}
+
+
 # HBM bytes per launch of the momentum step's two BiCGStab kernels on the 1025x513 fine mesh
 # (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled as above), valid for the recorded source.
 MEASURED_MOM_TRAFFIC = {"fingerprint": "7d5fea3bf168dc22", "profile": "profiles/momentum_1025x513.md",
@@ -899,6 +906,10 @@ def c5_main(args):
     kname = (f"k_cg_tile<{tname}, 8, true, false>" if forms[main_form][2] >= 1
              else f"k_cg_step<{tname}, 4, false>")
     traffic = None
+    if (kernel_fingerprint() == MEASURED_TRAFFIC_C5["fingerprint"] and (nx, ny, M, deg) == (1025, 513, 8, 6)
+            and main_form == "B"):
+        traffic = MEASURED_TRAFFIC_C5.get(kname)
+    alg_per_launch = (kt["algorithmic_bytes"] / kt["stage_launches"]) if kt else None
     out = {
         "metric": METRIC,
         "value": R["solves_per_s"],
@@ -931,8 +942,12 @@ def c5_main(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (kt["achieved_GBs"] / HBM_PEAK_GBS) if kt else None,
                      "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": alg_per_launch,
+                     "traffic_over_algorithmic": (traffic / alg_per_launch) if (traffic and alg_per_launch) else None,
                      "kernel": kname,
                      "kernel_avg_us": kt.get("stage_avg_us"),
+                     "coarse_step_avg_us": kt.get("coarse_avg_us"),
                      "bytes_model": "per CG iteration and instance 8 nnz + 52 n (fp32) or 12 nnz + 100 n "
                                     "(fp64), per refinement 12 nnz + 28 n; achieved = these bytes of the "
                                     "re-timed steps / the summed HIP-event durations of the stage kernel",
