@@ -273,10 +273,11 @@ int64_t cgp_stage_launches(cgp_ctx ctx);
 /* Stage timing, for measuring the solver's kernels (not for production runs).  With
  * enable = 1 (which also zeroes the totals) the staged engine enqueues the stage kernels of
  * later solves one by one on the context's stream, in the same chunks it would replay as
- * graphs, with a HIP event before the first kernel of a chunk and after every kernel; the
- * call waits for each chunk and adds each kernel's event-to-event time to the totals (the
- * tiled or row-range stage kernel, and the deflation coarse step).  Results are the same as
- * without timing.  enable = 0 returns to graph replay.  Not during graph capture. */
+ * graphs, each dispatch carrying its own start and stop HIP events (hipExtLaunchKernelGGL:
+ * the interval is the kernel's execution, without the gaps between kernels); the call waits
+ * for each chunk and adds each kernel's interval to the totals (the tiled or row-range
+ * stage kernel, and the deflation coarse step).  Results are the same as without timing.
+ * enable = 0 returns to graph replay.  Not during graph capture. */
 cgp_status cgp_stage_timing(cgp_ctx ctx, int32_t enable);
 /* Totals since timing was enabled: stage-kernel launches and their summed duration (us),
  * coarse-step launches and theirs.  Any output may be NULL. */

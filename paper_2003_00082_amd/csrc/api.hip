@@ -847,28 +847,24 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             // staged: graphs of stage launches (an even count each, so that the buffer parity runs
             // on from one graph to the next), replayed until every instance is done
             // `count` stage launches (and with deflation the coarse step after each) on stream st;
-            // ev (optional, 1 + kernels events): recorded before the first kernel and after each
+            // ev (optional): a start and a stop event per kernel, recorded by the dispatches themselves
             const int kps = (tiled && defl) ? 2 : 1;
             auto enqueue = [&](int count, hipStream_t st, hipEvent_t *ev) {
-                if (ev) CGP_HIP(hipEventRecord(ev[0], st));
+                auto evs = [&](int k) { return ev ? KernelEvents{ev[2 * k], ev[2 * k + 1]} : KernelEvents{}; };
                 for (int l = 0; l < count; ++l) {
                     if (tiled) {
                         launch_cg_tile(st, o.precision == CGP_FP32_IR, tp[g0]->width, defl, gn, plan->d_insts,
                                        gn == 1 ? &plan->one : nullptr,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
-                                       plan->d_done, ctx->host_flag_dev);
-                        if (ev) CGP_HIP(hipEventRecord(ev[kps * l + 1], st));
-                        if (defl) {
+                                       plan->d_done, ctx->host_flag_dev, evs(kps * l));
+                        if (defl)
                             launch_cg_coarse(st, o.precision == CGP_FP32_IR, gn == 1 ? plan->crecs.data() : nullptr,
-                                             plan->d_crecs, plan->d_cblk_inst, plan->cgrid, l & 1);
-                            if (ev) CGP_HIP(hipEventRecord(ev[kps * l + 2], st));
-                        }
+                                             plan->d_crecs, plan->d_cblk_inst, plan->cgrid, l & 1, evs(kps * l + 1));
                     } else {
                         launch_cg_step(st, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
                                        gn == 1 ? &plan->one : nullptr,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
-                                       plan->d_done, ctx->host_flag_dev);
-                        if (ev) CGP_HIP(hipEventRecord(ev[l + 1], st));
+                                       plan->d_done, ctx->host_flag_dev, evs(l));
                     }
                 }
             };
@@ -908,18 +904,18 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                         throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
                     const bool tail = plan->tail_exec && predicted > 0 && issued + plan->launches > predicted;
                     const int count = tail ? TAIL_LAUNCHES : plan->launches;
-                    const size_t nev = static_cast<size_t>(kps) * count + 1;
-                    while (ctx->tev.size() < nev) {
+                    const size_t nk = static_cast<size_t>(kps) * count;   // kernels in the chunk
+                    while (ctx->tev.size() < 2 * nk) {
                         hipEvent_t e;
                         CGP_HIP(hipEventCreate(&e));
                         ctx->tev.push_back(e);
                     }
                     enqueue(count, ctx->stream, ctx->tev.data());
-                    CGP_HIP(hipEventSynchronize(ctx->tev[nev - 1]));
-                    for (size_t q = 1; q < nev; ++q) {
+                    CGP_HIP(hipEventSynchronize(ctx->tev[2 * nk - 1]));
+                    for (size_t q = 0; q < nk; ++q) {
                         float msec = 0.f;
-                        CGP_HIP(hipEventElapsedTime(&msec, ctx->tev[q - 1], ctx->tev[q]));
-                        const int kind = (kps == 2 && (q % 2) == 0) ? 1 : 0;
+                        CGP_HIP(hipEventElapsedTime(&msec, ctx->tev[2 * q], ctx->tev[2 * q + 1]));
+                        const int kind = (kps == 2 && (q % 2) == 1) ? 1 : 0;
                         ctx->timed_us[kind] += 1e3 * static_cast<double>(msec);
                         ++ctx->timed_launches[kind];
                     }

@@ -351,13 +351,18 @@ void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolvePar
 // D^-1 into the fourth component of both parities of the row-interleaved vectors (either may be null)
 void launch_fill_rwsd(hipStream_t s, int64_t n, const float *dinv32, const double *dinv, float *rwsd32,
                       double *rwsd64);
+// start and stop events of one kernel dispatch (stage timing): recorded by the dispatch itself
+// (hipExtLaunchKernelGGL), so their interval is the kernel's own execution; null: plain launch
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
 // h_one: the record of a single-instance solve (passed by value to the kernel), else null
 void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts, const InstDesc *h_one,
                     const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm,
-                    int par, int32_t *d_done, int32_t *d_host_flag);
+                    int par, int32_t *d_done, int32_t *d_host_flag, KernelEvents ev = {});
 void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst, const InstDesc *d_insts,
                     const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
-                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag);
+                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag, KernelEvents ev = {});
 // the coarse step of deflation after a tiled stage launch: mu = E^-1 (aggregate sums), c partials
 constexpr int COARSE_WAVES = 8;                  // wavefronts per coarse workgroup
 constexpr int COARSE_ROWS = 2 * COARSE_WAVES;    // aggregates (rows of E^-1) per coarse workgroup
@@ -379,7 +384,7 @@ struct CoarseRec {               // what the coarse step of one instance touches
 // h_single: the record of a single-instance solve (passed by value), else the device records
 // e32: read the fp32 copy of E^-1 (fp32 iterations)
 void launch_cg_coarse(hipStream_t s, bool e32, const CoarseRec *h_single, const CoarseRec *d_recs,
-                      const int32_t *d_cblk_inst, int grid, int par);
+                      const int32_t *d_cblk_inst, int grid, int par, KernelEvents ev = {});
 int pcg_ell_max_width();
 void launch_cg_persistent(hipStream_t s, const InstDesc *d_insts, int n_inst, const int32_t *d_block_inst,
                           const RowRange *d_ranges, int grid, const SolveParams &prm, GridSync *d_sync,

@@ -38,6 +38,8 @@
 //                   iteration costs about one memory round trip.
 //   k_cg_persistent all stages in one co-resident launch with a grid barrier
 //                   (fits inside a caller's graph capture of a whole step)
+#include <hip/hip_ext.h>
+
 #include "cgp_internal.hpp"
 
 namespace cgp {
@@ -1489,18 +1491,27 @@ void launch_fill_rwsd(hipStream_t s, int64_t n, const float *dinv32, const doubl
     CGP_HIP(hipGetLastError());
 }
 
+// a kernel launch, with the dispatch's own start and stop timestamps in ev when ev.start is set
+#define CGP_LAUNCH(K, G, B, S, EV, ...)                                                                  \
+    do {                                                                                                \
+        if ((EV).start)                                                                                 \
+            hipExtLaunchKernelGGL(K, G, B, 0, S, (EV).start, (EV).stop, 0, __VA_ARGS__);                \
+        else                                                                                            \
+            hipLaunchKernelGGL(K, G, B, 0, S, __VA_ARGS__);                                             \
+    } while (0)
+
 void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst, const InstDesc *d_insts,
                     const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
-                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag) {
+                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag, KernelEvents ev) {
     const InstDesc none{};
 #define CGP_TILE(T, W, F)                                                                                          \
     do {                                                                                                           \
         if (h_one)                                                                                                 \
-            hipLaunchKernelGGL((k_cg_tile<T, W, F, true>), dim3(grid), dim3(BLOCK), 0, s, d_insts, *h_one,        \
-                               d_block_inst, n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                  \
+            CGP_LAUNCH((k_cg_tile<T, W, F, true>), dim3(grid), dim3(BLOCK), s, ev, d_insts, *h_one, d_block_inst,  \
+                       n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                                        \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_cg_tile<T, W, F, false>), dim3(grid), dim3(BLOCK), 0, s, d_insts, none,         \
-                               d_block_inst, n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                  \
+            CGP_LAUNCH((k_cg_tile<T, W, F, false>), dim3(grid), dim3(BLOCK), s, ev, d_insts, none, d_block_inst,   \
+                       n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                                        \
     } while (0)
 #define CGP_TILE_W(T, F)                     \
     if (width <= 8) CGP_TILE(T, 8, F); \
@@ -1516,14 +1527,13 @@ void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst,
 }
 
 void launch_cg_coarse(hipStream_t s, bool e32, const CoarseRec *h_single, const CoarseRec *d_recs,
-                      const int32_t *d_cblk_inst, int grid, int par) {
+                      const int32_t *d_cblk_inst, int grid, int par, KernelEvents ev) {
 #define CGP_COARSE(E)                                                                                             \
     do {                                                                                                          \
         if (h_single)                                                                                             \
-            hipLaunchKernelGGL(k_cg_coarse1<E>, dim3(grid), dim3(64 * COARSE_WAVES), 0, s, *h_single, par);      \
+            CGP_LAUNCH(k_cg_coarse1<E>, dim3(grid), dim3(64 * COARSE_WAVES), s, ev, *h_single, par);             \
         else                                                                                                      \
-            hipLaunchKernelGGL(k_cg_coarse<E>, dim3(grid), dim3(64 * COARSE_WAVES), 0, s, d_recs, d_cblk_inst,    \
-                               par);                                                                              \
+            CGP_LAUNCH(k_cg_coarse<E>, dim3(grid), dim3(64 * COARSE_WAVES), s, ev, d_recs, d_cblk_inst, par);    \
     } while (0)
     if (e32)
         CGP_COARSE(float);
@@ -1535,18 +1545,18 @@ void launch_cg_coarse(hipStream_t s, bool e32, const CoarseRec *h_single, const 
 
 void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts,
                     const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
-                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag) {
+                    const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag, KernelEvents ev) {
     // staged entries per thread: 4 covers workgroups whose column range spans <= 2048 rows
     const bool small = halo <= 4 * BLOCK;
     const InstDesc none{};
 #define CGP_STEP(T, H)                                                                                            \
     do {                                                                                                          \
         if (h_one)                                                                                                \
-            hipLaunchKernelGGL((k_cg_step<T, H, true>), dim3(grid), dim3(BLOCK), 0, s, d_insts, *h_one,          \
-                               d_block_inst, n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                 \
+            CGP_LAUNCH((k_cg_step<T, H, true>), dim3(grid), dim3(BLOCK), s, ev, d_insts, *h_one, d_block_inst,   \
+                       n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                                       \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_cg_step<T, H, false>), dim3(grid), dim3(BLOCK), 0, s, d_insts, none,           \
-                               d_block_inst, n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                 \
+            CGP_LAUNCH((k_cg_step<T, H, false>), dim3(grid), dim3(BLOCK), s, ev, d_insts, none, d_block_inst,    \
+                       n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                                       \
     } while (0)
     if (mixed) {
         if (small) CGP_STEP(float, 4);
