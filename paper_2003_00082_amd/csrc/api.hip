@@ -270,6 +270,7 @@ InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int d
         d.tcol = T->ecol.p;
         d.tval32 = T->eval32.p;
         d.tval = T->eval64.p;
+        d.agg = T->agg;
         if (defl) {
             d.defl = 1;
             d.kzr = T->kzr.p;
@@ -295,7 +296,8 @@ CoarseRec coarse_record(const InstDesc &d, int cblk0) {
     cr.partials = d.partials;
     cr.mu = d.mu;
     cr.cpart = d.cpart;
-    cr.m = AGG_PER_TILE * d.nblk;
+    cr.m = d.agg * d.nblk;
+    cr.agg = d.agg;
     cr.tiles = d.nblk;
     cr.cblk0 = cblk0;
     cr.ctl = d.ctl;
@@ -742,10 +744,11 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             } else {
                 auto p = std::make_unique<Plan>();
                 size_t npart = 0, nmu = 0, ncb_total = 0;
-                for (int v : nb) {
+                for (int i = 0; i < gn; ++i) {
+                    const int v = nb[i], A = tiled ? tp[g0 + i]->agg : 0;
                     npart += static_cast<size_t>(2) * NPART * v;
-                    nmu += AGG_PER_TILE * v;
-                    ncb_total += (AGG_PER_TILE * v + COARSE_ROWS - 1) / COARSE_ROWS;
+                    nmu += A * v;
+                    ncb_total += (A * v + COARSE_ROWS - 1) / COARSE_ROWS;
                 }
                 if (!defl) nmu = ncb_total = 0;
                 auto align = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -786,11 +789,11 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                     d.partials = dpart + poff;
                     d.ctl = dctl + 2 * i;
                     if (defl) {
-                        d.ncb = (AGG_PER_TILE * nb[i] + COARSE_ROWS - 1) / COARSE_ROWS;
+                        d.ncb = (d.agg * nb[i] + COARSE_ROWS - 1) / COARSE_ROWS;
                         d.cblk0 = cblk;
                         d.mu = dmu;
                         d.cpart = dcpart;
-                        dmu += AGG_PER_TILE * nb[i];
+                        dmu += d.agg * nb[i];
                         dcpart += d.ncb;
                         for (int v = 0; v < d.ncb; ++v) hcbi.push_back(i);
                         p->crecs.push_back(coarse_record(d, cblk));
@@ -1022,7 +1025,7 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
                         "the mesh's deflation data is not built: call cgp_poisson_solve with deflation first");
         }
         const int nblk = tiled ? T->nparts : static_cast<int>((n + pcg_block_size() - 1) / pcg_block_size());
-        const int na = defl ? AGG_PER_TILE * nblk : 0;
+        const int na = defl ? T->agg * nblk : 0;
         const int ncb = defl ? (na + COARSE_ROWS - 1) / COARSE_ROWS : 0;
         // layout of the scratch array (every piece 256-byte aligned)
         size_t off = 0;

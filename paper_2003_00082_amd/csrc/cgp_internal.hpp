@@ -126,6 +126,7 @@ constexpr int tile_col_stride(int width) { return width <= 8 ? 8 : 16; }
 // values at (ell_off + t) * width.
 struct TilePlan {
     int32_t degree = 0, width = 0, nparts = 0;
+    int32_t agg = 0;          // deflation aggregates per tile (each tile's own rows bisected into agg parts)
     std::vector<TileBlk> hblk;
     std::vector<int32_t> hreg;
     DBuf<TileBlk> blk;
@@ -133,20 +134,23 @@ struct TilePlan {
     DBuf<uint16_t> ecol;
     DBuf<float> eval32;
     DBuf<double> eval64;
-    // subdomain deflation, each tile cut in two aggregates (2t, 2t + 1) by one more
-    // bisection (built on first use; defl_state 0 = not built, 1 = built, -1 = not
+    // subdomain deflation, each tile's own rows cut into agg aggregates (agg t .. agg t +
+    // agg - 1) by bisection (built on first use; defl_state 0 = not built, 1 = built, -1 = not
     // supported for this mesh)
     int32_t defl_state = 0;
-    DBuf<int8_t> oagg;        // per region entry, own rows only: 0 Dirichlet, 1 + half of the tile
+    DBuf<int8_t> oagg;        // per region entry, own rows only: 0 Dirichlet, 1 + aggregate within the tile
     DBuf<int32_t> kzr;        // coupling record: region index of the row
     DBuf<int32_t> kzg;        // [4] per record: aggregates (tiles) the row couples to
     DBuf<float> kzv32;        // [4] per record: (K Z)_{row, aggregate}
     DBuf<double> kzv64;
-    DBuf<double> einv;        // [m x einv_stride(m)] (Z^T K Z)^-1, row-major, m = AGG_PER_TILE * nparts
+    DBuf<double> einv;        // [m x einv_stride(m)] (Z^T K Z)^-1, row-major, m = agg * nparts
     DBuf<float> einv32;       // the same rounded to fp32 (the coarse step of fp32 iterations)
 };
 
-constexpr int AGG_PER_TILE = 2;          // deflation aggregates per tile
+constexpr int AGG_TILE = 2;              // deflation aggregates per tile of TILE_ROWS-row tiles
+constexpr int AGG_MAX = 8;               // aggregates a tile may carry
+constexpr int NRED = 4;                  // reduced sums of a stage: gamma, delta, sigma, r.r
+constexpr int NPART = NRED + AGG_MAX;    // partial-sum slots per workgroup (NRED + aggregate sums)
 constexpr int KZ_PER_ROW = 4;            // aggregates one row may couple to
 constexpr int MAX_DEFL_AGGREGATES = 2048;   // the coarse step holds a row of E^-1 in 32 registers per lane
 
@@ -257,11 +261,10 @@ struct RowRange {
     int32_t r0, r1, c0, c1;
 };
 
-// per-workgroup partial sums of a stage: gamma, delta, sigma, r.r and (deflation) the
-// sums of w or r over the free rows of the tile's two aggregates; the first NRED are
-// reduced over the instance by the next stage, which puts the coarse term c in S[NRED]
-constexpr int NPART = 6;
-constexpr int NRED = 4;
+// per-workgroup partial sums of a stage (NPART slots, defined with the tile constants):
+// gamma, delta, sigma, r.r (NRED, reduced over the instance by the next stage, which puts
+// the coarse term c in S[NRED]) and (deflation) the sums of w or r over the free rows of
+// each of the tile's aggregates (slots NRED + a)
 
 // device-side description of one instance of a (batched) solve
 struct InstDesc {
@@ -307,20 +310,20 @@ struct InstDesc {
     double *rwsd64;
     double *up64;
     double cheb[2 * TILE_MAX_DEGREE];    // [0]: scale of the first step; [2k-1], [2k]: step k coefficients
-    // subdomain deflation (tiled iteration only; aggregates = the instance's tiles)
+    // subdomain deflation (tiled iteration only; agg aggregates in each of the instance's tiles)
     int32_t defl;                        // 0 off, 1 on
     int32_t ncb;                         // workgroups of the coarse kernel for this instance
     int32_t cblk0;                       // first of them
-    int32_t pad4_;
+    int32_t agg;                         // deflation aggregates per tile
     const int32_t *kzr;
     const int32_t *kzg;
     const float *kzv32;
     const double *kzv;
-    const double *einv;                  // [m x einv_stride(m)], m = AGG_PER_TILE * nblk
+    const double *einv;                  // [m x einv_stride(m)], m = agg * nblk
     const float *einv32;                 // the same in fp32
     double *mu;                          // [m] E^-1 Z^T v of the last stage
     double *cpart;                       // [ncb] partial sums of mu . Z^T v
-    const int8_t *oagg;                  // own rows (by region entry): 0 Dirichlet, 1 + half of the tile
+    const int8_t *oagg;                  // own rows (by region entry): 0 Dirichlet, 1 + aggregate within the tile
 };
 
 struct SolveParams {
@@ -375,10 +378,10 @@ struct CoarseRec {               // what the coarse step of one instance touches
     const double *partials;      // the instance's [2][NPART][tiles] stage partials
     double *mu;                  // [m]
     double *cpart;               // [ceil(m / COARSE_ROWS)]
-    int32_t m;                   // aggregates (AGG_PER_TILE per tile)
+    int32_t m;                   // aggregates (agg per tile)
     int32_t tiles;               // workgroups of the tiled stage
     int32_t cblk0;               // first coarse workgroup of the instance
-    int32_t pad_;
+    int32_t agg;                 // aggregates per tile: aggregate a is part a % agg of tile a / agg
     const Ctl *ctl;              // the instance's control state, by stage parity
 };
 // h_single: the record of a single-instance solve (passed by value), else the device records

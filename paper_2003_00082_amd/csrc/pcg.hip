@@ -83,17 +83,19 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// block-wide sums of NPART values into out[] (valid for every thread after return)
-__device__ inline void block_sums(double (&v)[NPART], double (*red)[NPART], double *out) {
+// block-wide sums of NS values into out[] (valid for every thread after return)
+template <int NS>
+__device__ inline void block_sums(double (&v)[NS], double (*red)[NPART], double *out) {
+    static_assert(NS <= NPART, "the reduction rows hold NPART values");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int s = 0; s < NPART; ++s) v[s] = wave_sum(v[s]);
+    for (int s = 0; s < NS; ++s) v[s] = wave_sum(v[s]);
     if (lane == 0) {
 #pragma unroll
-        for (int s = 0; s < NPART; ++s) red[wave][s] = v[s];
+        for (int s = 0; s < NS; ++s) red[wave][s] = v[s];
     }
     __syncthreads();
-    if (threadIdx.x < NPART) {
+    if (threadIdx.x < NS) {
         double t = 0.0;
         for (int w = 0; w < NWAVE; ++w) t += red[w][threadIdx.x];
         out[threadIdx.x] = t;
@@ -101,12 +103,13 @@ __device__ inline void block_sums(double (&v)[NPART], double (*red)[NPART], doub
     __syncthreads();
 }
 
-// sum of an instance's per-workgroup partials (same order in every workgroup)
+// sum of an instance's per-workgroup partials (same order in every workgroup); out[NRED],
+// the deflation term of the transitions, is zero (the persistent engine does not deflate)
 __device__ inline void reduce_partials(const double *part, int nblk, double (*red)[NPART], double *out) {
-    double t[NPART] = {};
+    double t[NRED + 1] = {};
     for (int j = threadIdx.x; j < nblk; j += BLOCK) {
 #pragma unroll
-        for (int s = 0; s < NPART; ++s) t[s] += part[s * nblk + j];
+        for (int s = 0; s < NRED; ++s) t[s] += part[s * nblk + j];
     }
     block_sums(t, red, out);
 }
@@ -351,7 +354,7 @@ struct Shared {
 // would crowd the prefetched iteration
 template <bool ELL>
 __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRange &R,
-                                        const SolveParams &prm, Shared &sh, int par, double (&v)[NPART]) {
+                                        const SolveParams &prm, Shared &sh, int par, double (&v)[NRED]) {
     const bool mixed = prm.precision == CGP_FP32_IR;
     const int lanes = D.lanes;
     const double *__restrict__ b = D.b;
@@ -609,7 +612,7 @@ __device__ inline void iter_prefetch(IterPrefetch<T, H> &f, const InstDesc &D, c
 // one CG iteration for the workgroup's rows (at most BLOCK of them) from prefetched values
 template <class T, int H>
 __device__ inline void iter_fast(const IterPrefetch<T, H> &f, const Ctl &c, const InstDesc &D, const RowRange &R,
-                                 int wr, T *lds, double (&v)[NPART]) {
+                                 int wr, T *lds, double (&v)[NRED]) {
     const int64_t n = D.n;
     const T al = static_cast<T>(c.alpha), be = static_cast<T>(c.beta);
     const bool rs = c.restart;
@@ -669,7 +672,7 @@ __device__ inline void write_stats(const Ctl &c, const SolveParams &prm, int idx
 __device__ inline void stage_sums(const InstDesc &D, int rd, double (*red)[NPART], double *out) {
     const int nblk = D.nblk;
     const CGP_GLOBAL double *pg = gld(D.partials + static_cast<size_t>(rd) * NPART * nblk);
-    double t[NPART] = {};
+    double t[NRED + 1] = {};
     for (int j = threadIdx.x; j < nblk; j += BLOCK) {
         double a[NRED];
 #pragma unroll
@@ -766,7 +769,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
     decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
     const Ctl c = sh.ctl;
     if (c.state == ST_DONE) return;
-    double v[NPART] = {};
+    double v[NRED] = {};
     if (fast && c.state == ST_ITER) {
         iter_fast<T, H>(f, c, D, R, par, reinterpret_cast<T *>(sh.lds), v);
     } else {
@@ -774,7 +777,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
         stage_work<false>(c, D, R, prm, sh, par, v);
     }
     block_sums(v, sh.red, sh.sums);
-    if (threadIdx.x < NPART) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
+    if (threadIdx.x < NRED) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
         sh.sums[threadIdx.x];
 }
 
@@ -914,17 +917,16 @@ __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, c
     }
 }
 
-// Deflation (aggregates: the two halves of every tile, Z their free-row indicators): the
-// coarse coefficients mu = E^-1 Z^T v written by the coarse kernel after the previous
-// stage, the thread's coupling record (a region row and its (K Z) entries) with the mu of
-// the aggregates it names, and the own row's aggregate code with the mu of both halves.
+// Deflation (aggregates: every tile's own rows cut into D.agg parts by bisection, Z their
+// free-row indicators): the coarse coefficients mu = E^-1 Z^T v written by the coarse
+// kernel after the previous stage, the thread's coupling record (a region row and its
+// (K Z) entries) with the mu of the aggregates it names, and the own row's aggregate code.
 template <class T>
 struct DeflPrefetch {
     int32_t kr;                // region index of the record, -1 for none
     T kv[KZ_PER_ROW];          // (K Z)_{row, a}
     T km[KZ_PER_ROW];          // mu_a (rounded to the iteration's precision)
-    T mu0, mu1;                // mu of the tile's two aggregates
-    int32_t code[TILE_OWN];    // own rows: 0 Dirichlet (or none), 1 + half of the tile
+    int32_t code[TILE_OWN];    // own rows: 0 Dirichlet (or none), 1 + part of the tile
 };
 
 template <class T>
@@ -934,12 +936,12 @@ __device__ inline const double *kz_val<double>(const InstDesc &D) { return D.kzv
 template <>
 __device__ inline const float *kz_val<float>(const InstDesc &D) { return D.kzv32; }
 
+// s_mu (LDS, D.agg entries): mu of the tile's own aggregates, loaded by the first threads
 template <class T>
-__device__ inline void defl_prefetch(DeflPrefetch<T> &f, const InstDesc &D, const TileBlk &B, int lb) {
+__device__ inline void defl_prefetch(DeflPrefetch<T> &f, const InstDesc &D, const TileBlk &B, int lb, double *s_mu) {
     const CGP_GLOBAL double *mu = gld(D.mu);
     f.kr = -1;
-    f.mu0 = static_cast<T>(mu[AGG_PER_TILE * lb]);
-    f.mu1 = static_cast<T>(mu[AGG_PER_TILE * lb + 1]);
+    if (static_cast<int>(threadIdx.x) < D.agg) s_mu[threadIdx.x] = mu[D.agg * lb + threadIdx.x];
 #pragma unroll
     for (int h = 0; h < TILE_OWN; ++h) {
         const int t = static_cast<int>(threadIdx.x) + h * BLOCK;
@@ -983,11 +985,12 @@ __device__ inline T tile_row(const TilePrefetch<T, W> &f, int h, const T *x) {
 // (their aggregate's mu), code their aggregate: ITER takes p = u + beta p - Z mu,
 // s = w + beta s - K Z mu (mu = E^-1 Z^T w of the previous stage); START applies the
 // coarse correction x += Z mu, r -= K Z mu (mu = E^-1 Z^T r of the residual stage before
-// it).  Both emit Z^T w' (the sums over the tile's two aggregates) as partials 4 and 5.
+// it).  Both emit Z^T w' (the sums over the tile's aggregates) as the partials after the
+// NRED sums.
 template <class T, int W>
 __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, const InstDesc &D, const TileBlk &B,
                                  const int32_t *nt, const double *cheb, int wr, T *lds, const T *kzm, bool defl,
-                                 const T (&zm)[TILE_OWN], const int32_t (&code)[TILE_OWN], double (&v)[NPART]) {
+                                 const T (&zm)[TILE_OWN], double (&v)[NRED], double (&av)[TILE_OWN]) {
     const int64_t n = D.n;
     const bool start = c.state == ST_START;
     const bool rs = c.restart;
@@ -1084,14 +1087,15 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
         v[1] += static_cast<double>(wn) * u64;
         v[2] += u64 * static_cast<double>(s_own[h]);
         v[3] += r64 * r64;
-        if (defl && code[h] > 0) v[NRED + code[h] - 1] += static_cast<double>(wn);
+        av[h] = static_cast<double>(wn);   // the row's term of its aggregate's sum Z^T w'
+
     }
 }
 
 // The residual stage of a tiled solve, over the tile's own rows (so that, with deflation, the
 // aggregate partials are the tile's sums Z^T r): r = b - K x in fp64 from the CSR matrix.
-__device__ inline void tile_res_row(const Ctl &c, const InstDesc &D, int32_t own, int code, bool mixed, int par,
-                                    double (&v)[NPART]) {
+__device__ inline void tile_res_row(const Ctl &c, const InstDesc &D, int32_t own, bool mixed, int par,
+                                    double (&v)[NRED], double &av) {
     const int64_t n = D.n;
     const int wr = par, rd = par ^ 1;
     const CGP_GLOBAL int32_t *rowptr = gld(D.rowptr), *col = gld(D.col);
@@ -1116,15 +1120,15 @@ __device__ inline void tile_res_row(const Ctl &c, const InstDesc &D, int32_t own
     }
     v[0] += ri * ri;
     if (c.first) v[1] += bi * bi;
-    if (code > 0) v[NRED + code - 1] += ri;
+    av = ri;   // the row's term of its aggregate's sum Z^T r
 }
 
 template <class T, int W>
 __device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &B, const TilePrefetch<T, W> &f,
-                                const int32_t (&code)[TILE_OWN], bool mixed, int par, double (&v)[NPART]) {
+                                bool mixed, int par, double (&v)[NRED], double (&av)[TILE_OWN]) {
 #pragma unroll
     for (int h = 0; h < TILE_OWN; ++h)
-        if (static_cast<int>(threadIdx.x) + h * BLOCK < B.nt[0]) tile_res_row(c, D, f.g[h], code[h], mixed, par, v);
+        if (static_cast<int>(threadIdx.x) + h * BLOCK < B.nt[0]) tile_res_row(c, D, f.g[h], mixed, par, v, av[h]);
 }
 
 // fp32: at most 128 VGPRs, so that two workgroups share a compute unit and a grid of
@@ -1152,13 +1156,14 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     tile_prefetch<T, W>(f, D, B, rd);
     constexpr bool defl = DEFL;
     DeflPrefetch<T> df;
+    __shared__ double s_mu[AGG_MAX];
+    static_assert(AGG_TILE <= AGG_MAX, "the partial slots hold the tile's aggregates");
     T *kzm = reinterpret_cast<T *>(sh.lds) + 3 * TILE_REGION;
     df.kr = -1;
-    df.mu0 = df.mu1 = T(0);
 #pragma unroll
     for (int h = 0; h < TILE_OWN; ++h) df.code[h] = 0;
     if (defl) {
-        defl_prefetch<T>(df, D, B, lb);
+        defl_prefetch<T>(df, D, B, lb, s_mu);
 #pragma unroll
         for (int h = 0; h < TH; ++h) {
             const int t = threadIdx.x + h * BLOCK;
@@ -1168,7 +1173,8 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
     const Ctl c = sh.ctl;
     if (c.state == ST_DONE) return;
-    double v[NPART] = {};
+    double v[NRED] = {};
+    double av[TILE_OWN] = {};   // per own row: its term of its aggregate's sum (deflation)
     if (c.state == ST_ITER || c.state == ST_START) {
         if (defl) {
             // K Z mu over the region: one coupling record per thread, zero elsewhere
@@ -1180,21 +1186,35 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
             }
             __syncthreads();
         }
-        T zm[TILE_OWN];
+        T zm[TILE_OWN];   // Z mu at the own rows: the mu of the row's aggregate
 #pragma unroll
-        for (int h = 0; h < TILE_OWN; ++h) zm[h] = df.code[h] == 1 ? df.mu0 : (df.code[h] == 2 ? df.mu1 : T(0));
-        tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), kzm, defl, zm, df.code, v);
+        for (int h = 0; h < TILE_OWN; ++h) zm[h] = df.code[h] > 0 ? static_cast<T>(s_mu[df.code[h] - 1]) : T(0);
+        tile_iter<T, W>(f, c, D, B, s_nt, s_cheb, par, reinterpret_cast<T *>(sh.lds), kzm, defl, zm, v, av);
     } else if (c.state == ST_RES) {
         // the residual over the tile's own rows (its vectors are the tiled iteration's own)
-        tile_res<T, W>(c, D, B, f, df.code, sizeof(T) == 4, par, v);
+        tile_res<T, W>(c, D, B, f, sizeof(T) == 4, par, v, av);
     } else {
         const SolveParams prm = *prm_dev;
         const RowRange R = ranges[D.blk0 + lb];
         stage_work<false>(c, D, R, prm, sh, par, v);
     }
-    block_sums(v, sh.red, sh.sums);
-    if (threadIdx.x < NPART) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
-        sh.sums[threadIdx.x];
+    // the partials: NRED sums and (deflation) the tile's aggregate sums, each own row's term
+    // added to its aggregate's slot
+    constexpr int NS = DEFL ? NRED + AGG_TILE : NRED;
+    double vs[NS];
+#pragma unroll
+    for (int q = 0; q < NRED; ++q) vs[q] = v[q];
+#pragma unroll
+    for (int a = 0; a < NS - NRED; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int h = 0; h < TILE_OWN; ++h)
+            if (df.code[h] == a + 1) t += av[h];
+        vs[NRED + a] = t;
+    }
+    block_sums(vs, sh.red, sh.sums);
+    double *part = D.partials + static_cast<size_t>(par) * NPART * D.nblk;
+    if (threadIdx.x < NS) part[threadIdx.x * D.nblk + lb] = sh.sums[threadIdx.x];
 }
 
 // Coarse step of deflation after a tiled stage: mu = E^-1 q with q the stage's aggregate
@@ -1240,11 +1260,11 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     // nothing for the next one; its state was stored by the stage kernel before this launch
     // (read with the row loads in flight)
     if (gld(C.ctl)[par].state == ST_DONE) return;
-    // q_a, the partial NRED + (a % 2) of tile a / 2, staged in LDS (zero past m)
-    static_assert(AGG_PER_TILE == 2, "aggregate a is half a % 2 of tile a / 2");
+    // q_a, the partial NRED + (a % agg) of tile a / agg, staged in LDS (zero past m)
     const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * nt + static_cast<size_t>(NRED) * nt;
+    const int A = C.agg;
     for (int i = threadIdx.x; i < ms; i += 64 * COARSE_WAVES)
-        qs[i] = i < m ? q[static_cast<size_t>(i & 1) * nt + (i >> 1)] : 0.0;
+        qs[i] = i < m ? q[static_cast<size_t>(i % A) * nt + i / A] : 0.0;
     __syncthreads();
     auto dot = [&](const u32x4 *e) {
         double acc = 0.0;
@@ -1382,10 +1402,10 @@ __global__ __launch_bounds__(BLOCK) void k_cg_persistent(const InstDesc *__restr
         const int par = stage & 1;
         double *part = D.partials + static_cast<size_t>(par) * NPART * D.nblk;
         const Ctl c = sh.ctl;
-        double v[NPART] = {};
+        double v[NRED] = {};
         if (c.state != ST_DONE) stage_work<true>(c, D, R, prm, sh, par, v);
         block_sums(v, sh.red, sh.sums);
-        if (threadIdx.x < NPART) part[threadIdx.x * D.nblk + lb] = sh.sums[threadIdx.x];
+        if (threadIdx.x < NRED) part[threadIdx.x * D.nblk + lb] = sh.sums[threadIdx.x];
         if (!grid_barrier(gs, gridDim.x, my_gen, timeout, &s_ok)) {
             if (lb == 0 && threadIdx.x == 0 && c.state != ST_DONE) {
                 Ctl a = c;

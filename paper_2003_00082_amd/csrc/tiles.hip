@@ -209,6 +209,7 @@ TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
             plan->degree = degree;
             plan->width = width;
             plan->nparts = parts;
+            plan->agg = AGG_TILE;
             plan->hblk = blk;
             plan->hreg = reg;
             h2d(s, plan->blk, blk);
@@ -225,8 +226,8 @@ TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
     return out;
 }
 
-// Deflation data of the tiled iteration.  Aggregates: every tile's own rows cut in two
-// by one more bisection (aggregates 2t and 2t + 1; Z: their free-row indicators).  For
+// Deflation data of the tiled iteration.  Aggregates: every tile's own rows cut into
+// P.agg parts by bisection (aggregates agg t .. agg t + agg - 1; Z: their free-row indicators).  For
 // every region row that couples to an aggregate through K, a record (region index, up to
 // KZ_PER_ROW aggregates, (K Z)_{row, a}); a row whose couplings cancel (an interior row:
 // zero row sum) gets none.  E = Z^T K Z is inverted on the host (Cholesky), an aggregate
@@ -234,7 +235,7 @@ TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
 bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
     if (P.defl_state != 0) return P.defl_state > 0;
     P.defl_state = -1;
-    const int nt = P.nparts, na = AGG_PER_TILE * nt;
+    const int nt = P.nparts, A = P.agg, na = A * nt;
     if (na > MAX_DEFL_AGGREGATES) return false;
     const int64_t n = m.lv[0].n;
     const auto rowptr = d2h(s, m.rowptr.p, n + 1);
@@ -248,16 +249,16 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
         const TileBlk &B = P.hblk[t];
         std::vector<int32_t> ids(P.hreg.begin() + B.reg_off, P.hreg.begin() + B.reg_off + B.nt[0]);
         std::vector<size_t> cuts;
-        bisect(ids, 0, ids.size(), AGG_PER_TILE, xy, cuts);
+        bisect(ids, 0, ids.size(), A, xy, cuts);
         size_t lo = 0;
-        for (int h = 0; h < AGG_PER_TILE; ++h) {
+        for (int h = 0; h < A; ++h) {
             for (size_t q = lo; q < cuts[h]; ++q)
-                if (!dir[ids[q]]) agg[ids[q]] = AGG_PER_TILE * t + h;
+                if (!dir[ids[q]]) agg[ids[q]] = A * t + h;
             lo = cuts[h];
         }
         for (int32_t q = 0; q < B.nt[0]; ++q) {
             const int32_t j = P.hreg[static_cast<size_t>(B.reg_off) + q];
-            oagg[static_cast<size_t>(B.reg_off) + q] = agg[j] < 0 ? 0 : static_cast<int8_t>(1 + agg[j] - AGG_PER_TILE * t);
+            oagg[static_cast<size_t>(B.reg_off) + q] = agg[j] < 0 ? 0 : static_cast<int8_t>(1 + agg[j] - A * t);
         }
     }
     // coupling records
@@ -299,7 +300,7 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
             if (keep > KZ_PER_ROW) return false;
             kzr.push_back(q);
             for (int e = 0; e < KZ_PER_ROW; ++e) {
-                kzg.push_back(e < keep ? ids[e] : AGG_PER_TILE * t);
+                kzg.push_back(e < keep ? ids[e] : A * t);
                 kzv.push_back(e < keep ? sums[e] : 0.0);
             }
         }
