@@ -73,6 +73,11 @@ enum { CGP_GUESS_ZERO = 0, CGP_GUESS_GIVEN = 1, CGP_GUESS_EXTRAP = 2, CGP_GUESS_
  *   STAGED      one kernel launch per stage (one per CG iteration), launched from
  *               replayed HIP graphs; the call returns once the host has seen every
  *               instance finish (it waits on the device, it does not enqueue only).
+ *               Under graph capture (cgp_graph_begin) the call waits for nothing: it
+ *               records the boot, a fixed number of stage launches (the stage budget,
+ *               cgp_solve_opts.stage_budget) and a closing kernel into the graph; it
+ *               needs an earlier uncaptured solve of the same meshes, vectors and
+ *               options (CGP_E_INVALID otherwise), which built the launch records.
  *               Each workgroup owns a compact tile of at most 512 rows (recursive
  *               coordinate bisection; when that takes more than 256 tiles, 256 tiles
  *               of up to 1024 rows) and works on the rows within graph distance
@@ -82,9 +87,9 @@ enum { CGP_GUESS_ZERO = 0, CGP_GUESS_GIVEN = 1, CGP_GUESS_EXTRAP = 2, CGP_GUESS_
  *   PERSISTENT  one co-resident launch with a grid-wide barrier between stages;
  *               fully asynchronous, so it can be captured in a caller's graph
  *               (Jacobi only)
- *   AUTO        PERSISTENT while the context's stream is being captured; otherwise
- *               STAGED for the Chebyshev preconditioner or deflation and
- *               STAGED_ROWS for plain Jacobi */
+ *   AUTO        STAGED for the Chebyshev preconditioner or deflation; plain Jacobi:
+ *               PERSISTENT while the context's stream is being captured, otherwise
+ *               STAGED_ROWS */
 enum { CGP_ENGINE_AUTO = 0, CGP_ENGINE_STAGED = 1, CGP_ENGINE_PERSISTENT = 2, CGP_ENGINE_STAGED_ROWS = 3 };
 /* per-instance solve status (cgp_solve_stats.status) */
 enum { CGP_SOLVE_OK = 0, CGP_SOLVE_NOCONV = 1, CGP_SOLVE_BREAKDOWN = 2, CGP_SOLVE_ABORTED = 3 };
@@ -199,6 +204,13 @@ typedef struct {
                              rows coupled to at most 4 aggregates: CGP_E_UNSUPPORTED
                              otherwise.  E = Z^T K Z is inverted on the host on first use
                              per mesh. */
+    int32_t stage_budget; /* staged engines under graph capture: the stage launches recorded
+                             (each deflated stage with its coarse step).  0 = 5/4 of the
+                             launches the last uncaptured solve of the same launch records
+                             needed, plus 8; at most 65536.  Launches past an instance's end
+                             return at once; an instance not finished by the last one ends
+                             with status CGP_SOLVE_ABORTED and its phi is not a solution.
+                             Ignored outside capture. */
 } cgp_solve_opts;
 
 typedef struct {
@@ -465,7 +477,13 @@ cgp_status cgp_model_load(cgp_ctx ctx, const char *path, cgp_model *out);
 
 /* Begin capturing the context's stream; library calls made until
  * cgp_graph_end are recorded instead of executed (they must be the
- * asynchronous calls above).  The stream must not be the null stream. */
+ * asynchronous calls above, or cgp_poisson_solve on the staged engines as its
+ * engine comment says).  The stream must not be the null stream.  A graph holds
+ * the launch records of the solves it recorded until it is freed; it reads and
+ * writes the vectors named at capture, and must not be launched after a mesh it
+ * uses was freed.  A solve graph can be captured as a whole CGP step (restrict,
+ * solve, prolong, Lorentz force, solve, prolong, velocity correction): one
+ * graph launch per time step. */
 cgp_status cgp_graph_begin(cgp_ctx ctx);
 /* End the capture and instantiate it. */
 cgp_status cgp_graph_end(cgp_ctx ctx, cgp_graph *out);

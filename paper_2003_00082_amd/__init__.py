@@ -56,7 +56,7 @@ class SolveOpts(ctypes.Structure):
                 ("refine_delta", ctypes.c_double), ("max_iter", ctypes.c_int32), ("model", ctypes.c_int32),
                 ("spmv_lanes", ctypes.c_int32), ("blocks", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("launches_per_graph", ctypes.c_int32), ("precond_degree", ctypes.c_int32),
-                ("deflation", ctypes.c_int32)]
+                ("deflation", ctypes.c_int32), ("stage_budget", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -296,7 +296,8 @@ class Context:
 
     def poisson_solve(self, meshes, b, phi, stats, *, prev1=None, prev2=None, precision=CGP_FP64,
                       guess=CGP_GUESS_GIVEN, tol=1e-8, refine_delta=0.0, max_iter=0, model=-1, spmv_lanes=0,
-                      blocks=0, engine=CGP_ENGINE_AUTO, launches_per_graph=0, precond_degree=0, deflation=0):
+                      blocks=0, engine=CGP_ENGINE_AUTO, launches_per_graph=0, precond_degree=0, deflation=0,
+                      stage_budget=0):
         """Enqueue one (batched) solve.  ``meshes``/``b``/``phi``/``prev*`` are sequences (one per
         instance); ``stats`` is a device uint8 tensor of n_inst * 32 bytes."""
         k = len(meshes)
@@ -306,7 +307,7 @@ class Context:
         arr_p1 = (_vp * k)(*[_ptr(t) for t in prev1]) if prev1 is not None else None
         arr_p2 = (_vp * k)(*[_ptr(t) for t in prev2]) if prev2 is not None else None
         opts = SolveOpts(precision, guess, tol, refine_delta, max_iter, model, spmv_lanes, blocks, engine,
-                         launches_per_graph, precond_degree, deflation)
+                         launches_per_graph, precond_degree, deflation, stage_budget)
         _check(load().cgp_poisson_solve(self.handle, k, arr_m, arr_b, arr_x, arr_p1, arr_p2, ctypes.byref(opts),
                                         _ptr(stats)))
 
@@ -316,7 +317,7 @@ class Context:
         """One solve that allocates no device memory (the library's fixed scratch array);
         ``stats`` is a device uint8 tensor of 32 bytes."""
         opts = SolveOpts(precision, guess, tol, refine_delta, max_iter, -1, spmv_lanes, 0, engine,
-                         launches_per_graph, precond_degree, deflation)
+                         launches_per_graph, precond_degree, deflation, 0)
         _check(load().cgp_poisson_solve_noalloc(self.handle, mesh, _ptr(b), _ptr(phi), _ptr(prev1), _ptr(prev2),
                                                 ctypes.byref(opts), _ptr(stats)))
 

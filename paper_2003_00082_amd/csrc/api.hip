@@ -65,6 +65,7 @@ struct TuneRec {
 struct GraphRec {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<std::shared_ptr<Plan>> plans;   // launch plans the recorded solves use
 };
 
 }  // namespace cgp
@@ -79,7 +80,8 @@ struct cgp_ctx_s {
     int max_blocks_per_cu = 1;
     int32_t next_mesh = 0, next_graph = 0;
     std::map<int32_t, std::unique_ptr<Mesh>> meshes;
-    std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
+    // (shared with the graphs that recorded solves on them, which keep them alive)
+    std::unordered_map<std::string, std::shared_ptr<Plan>> plans;
     // launches the last solve of a mesh set and option set needed, whatever its vectors: the
     // prediction for a plan's first solve (plans differ by vector pointers, e.g. rotating
     // previous-solution buffers, but solve alike)
@@ -96,10 +98,12 @@ struct cgp_ctx_s {
     int32_t *host_flag = nullptr;     // pinned, mapped: [0] set by the device when a staged solve is
                                       // done, [1] the launches its last instance needed
     int32_t *host_flag_dev = nullptr;
+    DBuf<int32_t> sink_flag;          // [2] the completion flag of solves recorded in graphs
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     uint64_t timeout_ticks = 0;
     int64_t stage_launches = 0;
     bool capturing = false;
+    std::vector<std::shared_ptr<Plan>> capture_plans;   // plans used by the capture in progress
     // stage timing (cgp_stage_timing): stage kernels launched one by one between HIP events
     bool time_stages = false;
     std::vector<hipEvent_t> tev;
@@ -320,6 +324,7 @@ void check_opts(const cgp_solve_opts &o) {
     CGP_REQUIRE(o.deflation == 0 || o.deflation == 1, "deflation must be 0 or 1");
     CGP_REQUIRE(o.launches_per_graph >= 0 && o.launches_per_graph % 2 == 0 && o.launches_per_graph <= 4096,
                 "launches_per_graph must be even and <= 4096");
+    CGP_REQUIRE(o.stage_budget >= 0 && o.stage_budget <= MAX_STAGE_BUDGET, "stage_budget must be in [0, 65536]");
 }
 
 Model &get_model(cgp_ctx ctx, cgp_model h) {
@@ -350,6 +355,7 @@ cgp_status cgp_create(cgp_ctx *out, int32_t device, void *hip_stream) {
         ctx->max_blocks_per_cu = std::max(1, pcg_max_blocks_per_cu());
         noalloc_init(device);   // the no-allocation solve's array on this device (once per device)
         ctx->sync.alloc(1);
+        ctx->sink_flag.alloc(2);
         CGP_HIP(hipMemset(ctx->sync.p, 0, sizeof(GridSync)));
         CGP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->host_flag), 2 * sizeof(int32_t), hipHostMallocMapped));
         ctx->host_flag[0] = ctx->host_flag[1] = 0;
@@ -646,8 +652,6 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                             "prev1/prev2 must not alias phi");
             }
         }
-        const bool persistent = o.engine == CGP_ENGINE_PERSISTENT || (o.engine == CGP_ENGINE_AUTO && ctx->capturing);
-        CGP_REQUIRE(persistent || !ctx->capturing, "the staged engine cannot be captured; use CGP_ENGINE_PERSISTENT");
         // preconditioner degree of each instance: the option's, or (CGP_DEGREE_TUNED) the one
         // cgp_autotune chose for the instance's mesh
         std::vector<int> degs(n_inst, std::max(1, o.precond_degree));
@@ -659,6 +663,10 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             }
         }
         const int degree = *std::max_element(degs.begin(), degs.end());
+        // AUTO under graph capture: the persistent engine for plain Jacobi, the staged engine's
+        // recorded launches for the Chebyshev preconditioner or deflation
+        const bool persistent = o.engine == CGP_ENGINE_PERSISTENT ||
+                                (o.engine == CGP_ENGINE_AUTO && ctx->capturing && degree < 2 && o.deflation != 1);
         if (degree >= 2 && (persistent || o.engine == CGP_ENGINE_STAGED_ROWS))
             throw Error{CGP_E_UNSUPPORTED, "the Chebyshev preconditioner needs CGP_ENGINE_STAGED"};
         // tiled iteration when every instance's mesh fits it with one matrix width (AUTO: only
@@ -738,11 +746,15 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                  << ':';
             for (int i = 0; i < gn; ++i) hkey << h_meshes[g0 + i] << ',' << degs[g0 + i] << ';';
             auto it = ctx->plans.find(key.str());
-            Plan *plan = nullptr;
+            std::shared_ptr<Plan> plan_sp;
             if (it != ctx->plans.end()) {
-                plan = it->second.get();
+                plan_sp = it->second;
             } else {
-                auto p = std::make_unique<Plan>();
+                if (ctx->capturing && !persistent)
+                    throw Error{CGP_E_INVALID, "a staged solve recorded in a graph needs an uncaptured solve of the "
+                                               "same meshes, vectors and options first (its launch records and "
+                                               "stage count)"};
+                auto p = std::make_shared<Plan>();
                 size_t npart = 0, nmu = 0, ncb_total = 0;
                 for (int i = 0; i < gn; ++i) {
                     const int v = nb[i], A = tiled ? tp[g0 + i]->agg : 0;
@@ -832,9 +844,11 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                                        ctx->aux));
                 CGP_HIP(hipStreamSynchronize(ctx->aux));
                 for (const RowRange &r : hr) p->halo = std::max(p->halo, r.c1 - r.c0 + 1);
-                plan = p.get();
+                plan_sp = p;
                 ctx->plans[key.str()] = std::move(p);
             }
+            Plan *plan = plan_sp.get();
+            if (ctx->capturing) ctx->capture_plans.push_back(plan_sp);
             SolveParams gp = prm;
             gp.n_inst = gn;
             gp.stats = d_stats + g0;
@@ -852,22 +866,26 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             // `count` stage launches (and with deflation the coarse step after each) on stream st;
             // ev (optional): a start and a stop event per kernel, recorded by the dispatches themselves
             const int kps = (tiled && defl) ? 2 : 1;
-            auto enqueue = [&](int count, hipStream_t st, hipEvent_t *ev) {
+            // completion flag: the host's, or under capture a device word nobody reads (a replay
+            // still running must not signal the end of a later uncaptured solve)
+            int32_t *done_flag = ctx->capturing ? ctx->sink_flag.p : ctx->host_flag_dev;
+            auto enqueue = [&](int64_t count, hipStream_t st, hipEvent_t *ev) {
                 auto evs = [&](int k) { return ev ? KernelEvents{ev[2 * k], ev[2 * k + 1]} : KernelEvents{}; };
-                for (int l = 0; l < count; ++l) {
+                for (int64_t l = 0; l < count; ++l) {
                     if (tiled) {
                         launch_cg_tile(st, o.precision == CGP_FP32_IR, tp[g0]->width, defl, gn, plan->d_insts,
                                        gn == 1 ? &plan->one : nullptr,
-                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
-                                       plan->d_done, ctx->host_flag_dev, evs(kps * l));
+                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm,
+                                       static_cast<int>(l & 1), plan->d_done, done_flag, evs(kps * l));
                         if (defl)
                             launch_cg_coarse(st, o.precision == CGP_FP32_IR, gn == 1 ? plan->crecs.data() : nullptr,
-                                             plan->d_crecs, plan->d_cblk_inst, plan->cgrid, l & 1, evs(kps * l + 1));
+                                             plan->d_crecs, plan->d_cblk_inst, plan->cgrid, static_cast<int>(l & 1),
+                                             evs(kps * l + 1));
                     } else {
                         launch_cg_step(st, o.precision == CGP_FP32_IR, plan->halo, gn, plan->d_insts,
                                        gn == 1 ? &plan->one : nullptr,
-                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm, l & 1,
-                                       plan->d_done, ctx->host_flag_dev, evs(l));
+                                       plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm,
+                                       static_cast<int>(l & 1), plan->d_done, done_flag, evs(l));
                     }
                 }
             };
@@ -878,6 +896,21 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 CGP_HIP(hipStreamEndCapture(ctx->aux, &graph));
                 CGP_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             };
+            if (ctx->capturing) {
+                // recorded in the caller's graph: the boot, a fixed number of stage launches (stages
+                // past an instance's end find it done and return) and the closing kernel, which
+                // marks instances still running after the last launch as aborted
+                CGP_REQUIRE(o.stage_budget > 0 || plan->last_stages > 0,
+                            "no stage count to size the recorded solve (stage_budget = 0 and no finished "
+                            "uncaptured solve of this launch plan)");
+                const int64_t budget = o.stage_budget > 0 ? o.stage_budget
+                                                          : (static_cast<int64_t>(plan->last_stages) * 5) / 4 + 8;
+                CGP_REQUIRE(budget <= MAX_STAGE_BUDGET, "stage budget above the limit of a recorded solve");
+                launch_cg_boot(ctx->stream, plan->d_insts, gn, gp, plan->d_prm, plan->d_done);
+                enqueue(budget, ctx->stream, nullptr);
+                launch_cg_close(ctx->stream, plan->d_insts, gn, plan->d_prm, static_cast<int>((budget - 1) & 1));
+                continue;
+            }
             if (!plan->exec) {
                 capture(launches, plan->graph, plan->exec);
                 plan->launches = launches;
@@ -1408,6 +1441,7 @@ cgp_status cgp_graph_begin(cgp_ctx ctx) {
         CGP_REQUIRE(!ctx->capturing, "capture already in progress");
         CGP_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
         ctx->capturing = true;
+        ctx->capture_plans.clear();
     });
 }
 
@@ -1418,6 +1452,8 @@ cgp_status cgp_graph_end(cgp_ctx ctx, cgp_graph *out) {
         CGP_REQUIRE(ctx->capturing, "no capture in progress");
         ctx->capturing = false;
         GraphRec g;
+        g.plans = std::move(ctx->capture_plans);
+        ctx->capture_plans.clear();
         CGP_HIP(hipStreamEndCapture(ctx->stream, &g.graph));
         CGP_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
         const int32_t h = ctx->next_graph++;

@@ -147,6 +147,7 @@ struct TilePlan {
     DBuf<float> einv32;       // the same rounded to fp32 (the coarse step of fp32 iterations)
 };
 
+constexpr int MAX_STAGE_BUDGET = 65536;    // stage launches a solve recorded in a graph may take
 constexpr int AGG_TILE = 2;              // deflation aggregates per tile of TILE_ROWS-row tiles
 constexpr int AGG_MAX = 8;               // aggregates a tile may carry
 constexpr int NRED = 4;                  // reduced sums of a stage: gamma, delta, sigma, r.r
@@ -351,6 +352,8 @@ void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_bloc
                    RowRange *d_ranges);
 void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
                     int32_t *d_done);
+// after the recorded launches of a captured staged solve (par: parity of the last launch)
+void launch_cg_close(hipStream_t s, const InstDesc *d_insts, int n_inst, const SolveParams *d_prm, int par);
 // D^-1 into the fourth component of both parities of the row-interleaved vectors (either may be null)
 void launch_fill_rwsd(hipStream_t s, int64_t n, const float *dinv32, const double *dinv, float *rwsd32,
                       double *rwsd64);

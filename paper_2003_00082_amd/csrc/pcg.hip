@@ -1341,6 +1341,19 @@ __global__ void k_cg_boot(InstDesc *insts, int n_inst, const SolveParams prm, So
     }
 }
 
+// After the recorded launches of a captured staged solve: an instance whose last decoded
+// stage (carried in ctl[par] by its first workgroup) is not the end was cut off by the
+// stage budget, and its statistics say so (status aborted, counters as far as it got).
+__global__ void k_cg_close(const InstDesc *insts, int n_inst, const SolveParams *prm_dev, int par) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    Ctl c = insts[i].ctl[par];
+    if (c.state != ST_DONE) {
+        c.status = CGP_SOLVE_ABORTED;
+        write_stats(c, *prm_dev, insts[i].stats_index);
+    }
+}
+
 // ------------------------------------------------------------------ driver 2: persistent launch
 
 // Grid barrier (arrive counter + generation) with a bounded wait: past `timeout`
@@ -1502,6 +1515,11 @@ void launch_ranges(hipStream_t s, const InstDesc *d_insts, const int32_t *d_bloc
 void launch_cg_boot(hipStream_t s, InstDesc *d_insts, int n_inst, const SolveParams &prm, SolveParams *d_prm,
                     int32_t *d_done) {
     hipLaunchKernelGGL(k_cg_boot, dim3((n_inst + 255) / 256), dim3(256), 0, s, d_insts, n_inst, prm, d_prm, d_done);
+    CGP_HIP(hipGetLastError());
+}
+
+void launch_cg_close(hipStream_t s, const InstDesc *d_insts, int n_inst, const SolveParams *d_prm, int par) {
+    hipLaunchKernelGGL(k_cg_close, dim3((n_inst + 255) / 256), dim3(256), 0, s, d_insts, n_inst, d_prm, par);
     CGP_HIP(hipGetLastError());
 }
 

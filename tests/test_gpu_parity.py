@@ -390,7 +390,7 @@ def test_graph_replay_matches_eager(ctx, cgp, c1):
             np.testing.assert_array_equal(t.cpu().numpy(), e)
         assert gctx.solve_check(1, stats)[0]["status"] == "ok"
     gctx.graph_free(g)
-    # the staged engine refuses capture instead of recording a host-driven loop
+    # the staged engine records a solve only after an uncaptured one of the same launch records
     gctx.graph_begin()
     with pytest.raises(cgp.CGPError):
         gctx.poisson_solve([h], [b], [phi], stats, precision=cgp.CGP_FP32_IR, guess=cgp.CGP_GUESS_ZERO, tol=1e-8,
