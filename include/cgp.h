@@ -106,8 +106,9 @@ cgp_status cgp_destroy(cgp_ctx ctx);
 cgp_status cgp_set_stream(cgp_ctx ctx, void *hip_stream);
 /* Wait for the context's stream; reports asynchronous HIP errors. */
 cgp_status cgp_sync(cgp_ctx ctx);
-/* Message of the last failing call made by this thread ("" if none). */
-const char *cgp_last_error(void);
+/* Message of the last failing call made by this thread ("" if none); the message is kept
+ * per host thread, so ctx may be any context or NULL. */
+const char *cgp_last_error(cgp_ctx ctx);
 /* Number of compute units of the context's device (for sizing launches). */
 int32_t cgp_device_cus(cgp_ctx ctx);
 
@@ -446,8 +447,12 @@ cgp_status cgp_momentum_step(cgp_ctx ctx, cgp_mesh mesh, const double *d_un, con
  * Training minimises the energy norm (delta^T K delta) / N_free of delta =
  * (y - (target - e) / s_d) on free nodes with Adam (beta 0.9 / 0.999, eps 1e-8). */
 int64_t cgp_model_param_count(void);
-/* New model with seeded He-normal weights (splitmix64 stream) and zero biases. */
-cgp_status cgp_model_create(cgp_ctx ctx, uint64_t seed, cgp_model *out);
+/* New model with seeded He-normal weights (splitmix64 stream) and zero biases.  The
+ * network's shape is fixed: hidden must be 64 and layers 3 (message layers), else
+ * CGP_E_UNSUPPORTED. */
+#define CGP_MODEL_HIDDEN 64
+#define CGP_MODEL_LAYERS 3
+cgp_status cgp_model_create(cgp_ctx ctx, int32_t hidden, int32_t layers, uint64_t seed, cgp_model *out);
 cgp_status cgp_model_free(cgp_ctx ctx, cgp_model model);
 /* Copy the fp32 parameters out / in (h_params: cgp_model_param_count() floats).
  * Setting parameters resets the optimiser state.  Synchronous. */

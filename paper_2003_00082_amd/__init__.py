@@ -81,7 +81,7 @@ _SIGS = {
     "cgp_destroy": ([_vp], _i32),
     "cgp_set_stream": ([_vp, _vp], _i32),
     "cgp_sync": ([_vp], _i32),
-    "cgp_last_error": ([], ctypes.c_char_p),
+    "cgp_last_error": ([_vp], ctypes.c_char_p),
     "cgp_device_cus": ([_vp], _i32),
     "cgp_stage_launches": ([_vp], _i64),
     "cgp_stage_timing": ([_vp, _i32], _i32),
@@ -107,7 +107,7 @@ _SIGS = {
                           _i32),
     "cgp_interpolate": ([_vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp], _i32),
     "cgp_model_param_count": ([], _i64),
-    "cgp_model_create": ([_vp, ctypes.c_uint64, ctypes.POINTER(_i32)], _i32),
+    "cgp_model_create": ([_vp, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_i32)], _i32),
     "cgp_model_free": ([_vp, _i32], _i32),
     "cgp_model_get_params": ([_vp, _i32, _vp], _i32),
     "cgp_model_set_params": ([_vp, _i32, _vp], _i32),
@@ -146,7 +146,7 @@ def load(path: str | None = None):
 
 def _check(rc: int):
     if rc != CGP_OK:
-        raise CGPError(rc, load().cgp_last_error().decode())
+        raise CGPError(rc, load().cgp_last_error(None).decode())
 
 
 def _ptr(t) -> int | None:
@@ -347,9 +347,9 @@ class Context:
     def model_param_count() -> int:
         return int(load().cgp_model_param_count())
 
-    def model_create(self, seed: int = 0) -> int:
+    def model_create(self, seed: int = 0, hidden: int = 64, layers: int = 3) -> int:
         out = _i32()
-        _check(load().cgp_model_create(self.handle, int(seed), ctypes.byref(out)))
+        _check(load().cgp_model_create(self.handle, int(hidden), int(layers), int(seed), ctypes.byref(out)))
         return int(out.value)
 
     def model_free(self, model: int):

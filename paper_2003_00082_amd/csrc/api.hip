@@ -337,7 +337,10 @@ Model &get_model(cgp_ctx ctx, cgp_model h) {
 
 extern "C" {
 
-const char *cgp_last_error(void) { return g_last_error.c_str(); }
+const char *cgp_last_error(cgp_ctx ctx) {
+    (void)ctx;   // the message is kept per host thread
+    return g_last_error.c_str();
+}
 
 cgp_status cgp_create(cgp_ctx *out, int32_t device, void *hip_stream) {
     return guarded([&] {
@@ -1318,11 +1321,13 @@ cgp_status cgp_autotune(cgp_ctx ctx, int32_t n, const cgp_mesh *h_meshes, int32_
 
 int64_t cgp_model_param_count(void) { return gnn_param_count(); }
 
-cgp_status cgp_model_create(cgp_ctx ctx, uint64_t seed, cgp_model *out) {
+cgp_status cgp_model_create(cgp_ctx ctx, int32_t hidden, int32_t layers, uint64_t seed, cgp_model *out) {
     return guarded([&] {
         use_device(ctx);
         CGP_REQUIRE(out != nullptr, "null output pointer");
         CGP_REQUIRE(!ctx->capturing, "cgp_model_create cannot be captured");
+        if (hidden != CGP_MODEL_HIDDEN || layers != CGP_MODEL_LAYERS)
+            throw Error{CGP_E_UNSUPPORTED, "the network has 64 hidden features and 3 message layers"};
         std::unique_ptr<Model, cgp_ctx_s::ModelDel> md(gnn_create(ctx->stream, seed));
         const int32_t h = ctx->next_model++;
         ctx->models[h] = std::move(md);

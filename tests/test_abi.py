@@ -2,6 +2,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -42,10 +43,21 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
         cgp._lib = saved
 
 
-def test_struct_layouts_match_the_header():
+def test_struct_layouts_match_the_header(tmp_path):
     import paper_2003_00082_amd as cgp
     assert ctypes.sizeof(cgp.SolveStats) == 32
-    assert ctypes.sizeof(cgp.SolveOpts) == 56
+    # every field offset of cgp_solve_opts as the C compiler lays it out from the header
+    fields = [f for f, _ in cgp.SolveOpts._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "cgp.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(cgp_solve_opts));\n' +
+                   "".join(f'  printf("%zu\\n", offsetof(cgp_solve_opts, {f}));\n' for f in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(cgp.SolveOpts)
+    assert got[1:] == [getattr(cgp.SolveOpts, f).offset for f in fields]
     # cgp_momentum_stats: int32 iters[2], int32 status[2], double rel_res[2]
     assert ctypes.sizeof(cgp.MomentumStats) == 32
     assert cgp.MomentumStats.rel_res.offset == 16

@@ -251,6 +251,15 @@ def test_learned_guess_beats_extrapolation_on_held_out_steps(ctx, cgp, seq):
         ctx.model_free(md)
 
 
+def test_network_shape_is_fixed(ctx, cgp):
+    with pytest.raises(cgp.CGPError) as e:
+        ctx.model_create(seed=1, hidden=32)
+    assert e.value.code == cgp.CGP_E_UNSUPPORTED
+    with pytest.raises(cgp.CGPError):
+        ctx.model_create(seed=1, layers=2)
+    ctx.model_free(ctx.model_create(seed=1, hidden=64, layers=3))
+
+
 @pytest.mark.parametrize("engine,deflation", [(1, 0), (2, 0), (1, 1)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_learned_solve(ctx, cgp, seq, engine, deflation, precision):
