@@ -230,9 +230,9 @@ void cheb_coefficients(double *cheb, int degree, double hi, bool defl) {
 // The record of one instance from its mesh, workspace vectors and the caller's vectors; the
 // launch-specific fields (workgroups, partial sums, control state, coarse-step buffers) are
 // the caller's to fill.  T: the tiled plan (null for the row-range and persistent kernels).
-InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int degree, bool defl, bool persistent,
-                           int lanes, int guess, const double *b, double *x, const double *prev1,
-                           const double *prev2, hipStream_t aux) {
+InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int kwidth, int degree, bool defl,
+                           bool persistent, int lanes, int guess, const double *b, double *x,
+                           const double *prev1, const double *prev2, hipStream_t aux) {
     InstDesc d{};
     d.n = static_cast<int32_t>(m.lv[0].n);
     d.lanes = lanes;
@@ -271,9 +271,15 @@ InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int d
         d.degree = degree;
         d.tblk = T->blk.p;
         d.treg = T->reg.p;
-        d.tcol = T->ecol.p;
-        d.tval32 = T->eval32.p;
-        d.tval = T->eval64.p;
+        if (kwidth == SPLIT_WIDTH) {
+            d.tcol = reinterpret_cast<const uint16_t *>(T->scol.p);
+            d.tval32 = T->sval32.p;
+            d.tval = T->sval64.p;
+        } else {
+            d.tcol = T->ecol.p;
+            d.tval32 = T->eval32.p;
+            d.tval = T->eval64.p;
+        }
         d.agg = T->agg;
         if (defl) {
             d.defl = 1;
@@ -681,6 +687,14 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
             tp[i] = tile_plan(ctx->aux, *ms[i], degs[i]);
             tiled = tp[i] != nullptr && tp[i]->width == tp[0]->width;
         }
+        // the records the stage kernel reads: split (off-diagonal) records when every instance
+        // has them, else the plans' common width
+        int kwidth = 0;
+        if (tiled) {
+            kwidth = SPLIT_WIDTH;
+            for (int i = 0; i < n_inst; ++i)
+                if (tp[i]->kwidth != SPLIT_WIDTH) kwidth = tp[0]->width;
+        }
         if (degree >= 2 && !tiled)
             throw Error{CGP_E_UNSUPPORTED, "a mesh does not fit the tiled iteration the Chebyshev preconditioner needs"};
         const bool defl = o.deflation == 1;
@@ -793,7 +807,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 for (int i = 0; i < gn; ++i) {
                     const int ii = g0 + i;
                     Mesh &m = *ms[ii];
-                    InstDesc d = describe_instance(m, work_ptrs(m.work), tiled ? tp[ii] : nullptr, degs[ii], defl,
+                    InstDesc d = describe_instance(m, work_ptrs(m.work), tiled ? tp[ii] : nullptr, kwidth, degs[ii], defl,
                                                    persistent, lanes_of(m), o.guess, h_d_b[ii], h_d_phi[ii],
                                                    need_prev ? h_d_prev1[ii] : nullptr,
                                                    need_prev ? h_d_prev2[ii] : nullptr, ctx->aux);
@@ -876,7 +890,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 auto evs = [&](int k) { return ev ? KernelEvents{ev[2 * k], ev[2 * k + 1]} : KernelEvents{}; };
                 for (int64_t l = 0; l < count; ++l) {
                     if (tiled) {
-                        launch_cg_tile(st, o.precision == CGP_FP32_IR, tp[g0]->width, defl, gn, plan->d_insts,
+                        launch_cg_tile(st, o.precision == CGP_FP32_IR, kwidth, defl, gn, plan->d_insts,
                                        gn == 1 ? &plan->one : nullptr,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm,
                                        static_cast<int>(l & 1), plan->d_done, done_flag, evs(kps * l));
@@ -1120,7 +1134,7 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
                     reinterpret_cast<double *>(at(o_up))};
         const bool extrap = o.guess == CGP_GUESS_EXTRAP;
         const int lanes = o.spmv_lanes ? o.spmv_lanes : 4;
-        InstDesc d = describe_instance(m, ws, T, degree, defl, false, lanes, o.guess, d_b, d_phi,
+        InstDesc d = describe_instance(m, ws, T, T ? T->kwidth : 0, degree, defl, false, lanes, o.guess, d_b, d_phi,
                                        extrap ? d_prev1 : nullptr, extrap ? d_prev2 : nullptr, ctx->aux);
         d.blk0 = 0;
         d.nblk = nblk;
@@ -1179,7 +1193,7 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
             if (issued >= max_stages + 2 * launches) throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
             for (int l = 0; l < launches; ++l) {
                 if (tiled) {
-                    launch_cg_tile(st, mixed, T->width, defl, 1, d_insts, &d, d_bi, d_rng, nblk, d_prm, l & 1, d_done,
+                    launch_cg_tile(st, mixed, T->kwidth, defl, 1, d_insts, &d, d_bi, d_rng, nblk, d_prm, l & 1, d_done,
                                    ctx->host_flag_dev);
                     if (defl) launch_cg_coarse(st, mixed, &cr, d_crec, d_cbi, ncb, l & 1);
                 } else {

@@ -126,6 +126,9 @@ constexpr int tile_col_stride(int width) { return width <= 8 ? 8 : 16; }
 // values at (ell_off + t) * width.
 struct TilePlan {
     int32_t degree = 0, width = 0, nparts = 0;
+    // records the CG stage kernel reads: SPLIT_WIDTH (rows of at most SPLIT_WIDTH off-diagonal
+    // entries: the split records below) or width (the records above)
+    int32_t kwidth = 0;
     int32_t agg = 0;          // deflation aggregates per tile (each tile's own rows bisected into agg parts)
     std::vector<TileBlk> hblk;
     std::vector<int32_t> hreg;
@@ -134,6 +137,14 @@ struct TilePlan {
     DBuf<uint16_t> ecol;
     DBuf<float> eval32;
     DBuf<double> eval64;
+    // split records: the off-diagonal entries only (the kernel forms the diagonal as 1 / D^-1
+    // from the row's vector record), padded with the row's own region index and value 0; per
+    // tile column-major, so that one load instruction of a wavefront reads consecutive rows:
+    // value pair q (entries 2q, 2q + 1) of local row t at SPLIT_WIDTH ell_off + 2 (q nspmv + t),
+    // column pair q (two 16-bit region indices) at (SPLIT_WIDTH / 2) ell_off + q nspmv + t
+    DBuf<uint32_t> scol;
+    DBuf<float> sval32;
+    DBuf<double> sval64;
     // subdomain deflation, each tile's own rows cut into agg aggregates (agg t .. agg t +
     // agg - 1) by bisection (built on first use; defl_state 0 = not built, 1 = built, -1 = not
     // supported for this mesh)
@@ -147,6 +158,7 @@ struct TilePlan {
     DBuf<float> einv32;       // the same rounded to fp32 (the coarse step of fp32 iterations)
 };
 
+constexpr int SPLIT_WIDTH = 6;             // off-diagonal entries of a split record
 constexpr int MAX_STAGE_BUDGET = 65536;    // stage launches a solve recorded in a graph may take
 constexpr int AGG_TILE = 2;              // deflation aggregates per tile of TILE_ROWS-row tiles
 constexpr int AGG_MAX = 8;               // aggregates a tile may carry

@@ -829,13 +829,14 @@ template <>
 __device__ inline const float *tile_val<float>(const InstDesc &D) { return D.tval32; }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 template <class T, int W>
 __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, const TileBlk &B, int rd) {
     const int64_t n = D.n;
     constexpr int CW = tile_col_stride(W);   // 16-bit columns per record
     constexpr int VP = 16 / sizeof(T);        // values per 16-byte load
-    static_assert(W % VP == 0, "value records are whole 16-byte loads");
+    static_assert(W == SPLIT_WIDTH || W % VP == 0, "value records are whole 16-byte loads");
 #pragma unroll
     for (int h = 0; h < TS; ++h) {
         const int t = threadIdx.x + h * BLOCK;
@@ -843,7 +844,28 @@ __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, c
         for (int k = 0; k < W / 2; ++k) f.ec[h][k] = 0u;   // rows past nspmv gather entry 0 times 0
 #pragma unroll
         for (int k = 0; k < W; ++k) f.ev[h][k] = T(0);
-        if (t < B.nspmv) {
+        if constexpr (W == SPLIT_WIDTH) {
+            if (t < B.nspmv) {
+                // split records, column-major over the tile's rows: pair q of every row in turn
+                const size_t ns = static_cast<size_t>(B.nspmv);
+                const CGP_GLOBAL uint32_t *sc = reinterpret_cast<const CGP_GLOBAL uint32_t *>(gld(D.tcol)) +
+                                                (SPLIT_WIDTH / 2) * static_cast<size_t>(B.ell_off) + t;
+                const CGP_GLOBAL T *sv = gld(tile_val<T>(D)) + SPLIT_WIDTH * static_cast<size_t>(B.ell_off) + 2 * t;
+#pragma unroll
+                for (int q = 0; q < SPLIT_WIDTH / 2; ++q) {
+                    f.ec[h][q] = sc[q * ns];
+                    if constexpr (sizeof(T) == 4) {
+                        const u32x2 u = *reinterpret_cast<const CGP_GLOBAL u32x2 *>(sv + 2 * q * ns);
+                        f.ev[h][2 * q] = __uint_as_float(u.x);
+                        f.ev[h][2 * q + 1] = __uint_as_float(u.y);
+                    } else {
+                        const u32x4 u = *reinterpret_cast<const CGP_GLOBAL u32x4 *>(sv + 2 * q * ns);
+                        f.ev[h][2 * q] = __hiloint2double(static_cast<int>(u.y), static_cast<int>(u.x));
+                        f.ev[h][2 * q + 1] = __hiloint2double(static_cast<int>(u.w), static_cast<int>(u.z));
+                    }
+                }
+            }
+        } else if (t < B.nspmv) {
             const size_t row = static_cast<size_t>(B.ell_off) + t;
             const CGP_GLOBAL u32x4 *ec = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(D.tcol) + row * CW);
             const u32x4 c0 = ec[0];
@@ -966,10 +988,11 @@ __device__ inline void defl_prefetch(DeflPrefetch<T> &f, const InstDesc &D, cons
     }
 }
 
-// y_t = sum_k ev[h][k] * x[ec[h][k]] for the thread's local matrix row h
+// y_t = sum_k ev[h][k] * x[ec[h][k]] for the thread's local matrix row h; with split records
+// (W = SPLIT_WIDTH) the diagonal term dg x_t comes first (own = x_t, held by the thread)
 template <class T, int W>
-__device__ inline T tile_row(const TilePrefetch<T, W> &f, int h, const T *x) {
-    T acc = T(0);
+__device__ inline T tile_row(const TilePrefetch<T, W> &f, int h, const T *x, T own, T dg) {
+    T acc = W == SPLIT_WIDTH ? dg * own : T(0);
 #pragma unroll
     for (int k = 0; k < W; ++k) acc += f.ev[h][k] * x[(f.ec[h][k / 2] >> (16 * (k & 1))) & 0xffffu];
     return acc;
@@ -1000,6 +1023,11 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
     const T c0 = static_cast<T>(cheb[0]);
     T s_own[TILE_OWN] = {}, r_own[TILE_OWN] = {};
     T rr[TS], zz[TS], qq[TS], dd[TS];
+    // split records: the diagonal of a local matrix row, 1 / D^-1 (rounded to T)
+    T dg[TS];
+#pragma unroll
+    for (int h = 0; h < TS; ++h)
+        dg[h] = (W == SPLIT_WIDTH && static_cast<int>(threadIdx.x) + h * BLOCK < B.nspmv) ? T(1) / f.dv[h] : T(0);
     // r' = r - alpha (w + beta s) over the region; first Chebyshev step z = c0 D^-1 r'
 #pragma unroll
     for (int h = 0; h < TH; ++h) {
@@ -1034,7 +1062,7 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
         // the gathers of all of the thread's rows first (in flight together), then the updates
         T kx[TS];
 #pragma unroll
-        for (int h = 0; h < TS; ++h) kx[h] = tile_row(f, h, src);
+        for (int h = 0; h < TS; ++h) kx[h] = tile_row(f, h, src, dd[h], dg[h]);
 #pragma unroll
         for (int h = 0; h < TS; ++h) {
             const int t = threadIdx.x + h * BLOCK;
@@ -1055,7 +1083,7 @@ __device__ inline void tile_iter(const TilePrefetch<T, W> &f, const Ctl &c, cons
         if (static_cast<int>(threadIdx.x) + h * BLOCK >= nt[0]) continue;
         const int32_t j = f.g[h];
         const T u1 = zz[h];
-        const T wn = tile_row(f, h, Uz);
+        const T wn = tile_row(f, h, Uz, zz[h], dg[h]);
         // (r, w, s) of the row into the write parity (D^-1 stays in the fourth slot)
         CGP_GLOBAL T *q = gst(rwsd_of<T>(D)) + (wr * n + j) * 4;
         q[0] = r_own[h];
@@ -1552,7 +1580,8 @@ void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst,
                        n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                                        \
     } while (0)
 #define CGP_TILE_W(T, F)                     \
-    if (width <= 8) CGP_TILE(T, 8, F); \
+    if (width == SPLIT_WIDTH) CGP_TILE(T, SPLIT_WIDTH, F); \
+    else if (width <= 8) CGP_TILE(T, 8, F); \
     else CGP_TILE(T, 12, F)
     if (mixed) {
         if (defl) { CGP_TILE_W(float, true); } else { CGP_TILE_W(float, false); }

@@ -155,6 +155,52 @@ bool build_tiles(int64_t n, int parts, int degree, int width, const std::vector<
     return true;
 }
 
+// The split records of a plan built with width-8 records (tile_col_stride 8): every local row's
+// entries other than its own column (the diagonal, and the padding, which names the row itself),
+// in the same order.  False if a row has more than SPLIT_WIDTH of them.
+bool split_records(const std::vector<TileBlk> &blk, const std::vector<uint16_t> &ecol,
+                   const std::vector<double> &eval, TilePlan &plan, hipStream_t s) {
+    constexpr int W = 8, SW = SPLIT_WIDTH;
+    static_assert(SW % 2 == 0 && SW <= W, "split records hold pairs of entries");
+    const size_t rows = eval.size() / W;
+    std::vector<double> sv(rows * SW, 0.0);
+    std::vector<uint32_t> sc(rows * (SW / 2), 0u);
+    for (const TileBlk &B : blk) {
+        const size_t ns = static_cast<size_t>(B.nspmv);
+        for (size_t t = 0; t < ns; ++t) {
+            const size_t r = static_cast<size_t>(B.ell_off) + t;
+            uint16_t c[SW];
+            double v[SW];
+            int cnt = 0;
+            for (int k = 0; k < W; ++k) {
+                const uint16_t lc = ecol[r * tile_col_stride(W) + k];
+                if (lc == t) continue;
+                if (cnt == SW) return false;
+                c[cnt] = lc;
+                v[cnt] = eval[r * W + k];
+                ++cnt;
+            }
+            for (; cnt < SW; ++cnt) {
+                c[cnt] = static_cast<uint16_t>(t);
+                v[cnt] = 0.0;
+            }
+            for (int q = 0; q < SW / 2; ++q) {
+                const size_t vo = static_cast<size_t>(SW) * B.ell_off + 2 * (q * ns + t);
+                sv[vo] = v[2 * q];
+                sv[vo + 1] = v[2 * q + 1];
+                sc[static_cast<size_t>(SW / 2) * B.ell_off + q * ns + t] =
+                    static_cast<uint32_t>(c[2 * q]) | (static_cast<uint32_t>(c[2 * q + 1]) << 16);
+            }
+        }
+    }
+    h2d(s, plan.scol, sc);
+    h2d(s, plan.sval64, sv);
+    std::vector<float> s32(sv.begin(), sv.end());
+    h2d(s, plan.sval32, s32);
+    CGP_HIP(hipStreamSynchronize(s));
+    return true;
+}
+
 }  // namespace
 
 double mesh_gershgorin(hipStream_t s, Mesh &m) {
@@ -208,6 +254,8 @@ TilePlan *tile_plan(hipStream_t s, Mesh &m, int degree) {
         if (ok) {
             plan->degree = degree;
             plan->width = width;
+            plan->kwidth = width;
+            if (m.max_row <= SPLIT_WIDTH + 1 && split_records(blk, ecol, eval, *plan, s)) plan->kwidth = SPLIT_WIDTH;
             plan->nparts = parts;
             plan->agg = AGG_TILE;
             plan->hblk = blk;

@@ -409,6 +409,10 @@ def cheb_meshes():
         "hole_41x21": ci.rect_with_hole(41, 21, (12, 28, 6, 14), seed=5),
         "permuted_40x21": ci.permuted(ci.jittered_rect(40, 21, 6), seed=7),
         "ragged_7x4": ci.jittered_rect(7, 4, 5),
+        # rows of 7 and 11 off-diagonal entries at the centre: the tiled iteration's width-8 and
+        # width-12 records (the meshes above have at most 6 and take the split records)
+        "wheel_7": ci.wheel(30, 7, 21),
+        "wheel_11": ci.wheel(30, 11, 22),
     }
 
 
@@ -437,7 +441,7 @@ def test_chebyshev_fp64_matches_direct_and_oracle(ctx, cgp, cheb_cases, name, de
     assert abs(st["iters"] - info["iters"]) <= 2, (st, info)
 
 
-@pytest.mark.parametrize("name", ["rect_129x65", "hole_41x21", "permuted_40x21"])
+@pytest.mark.parametrize("name", ["rect_129x65", "hole_41x21", "permuted_40x21", "wheel_7", "wheel_11"])
 @pytest.mark.parametrize("degree", [2, 4, 8])
 def test_chebyshev_mixed_matches_direct_and_oracle(ctx, cgp, cheb_cases, name, degree):
     m, a, b, h = cheb_cases[name]
@@ -449,8 +453,9 @@ def test_chebyshev_mixed_matches_direct_and_oracle(ctx, cgp, cheb_cases, name, d
     assert abs(st["iters"] - info["iters"]) <= max(3, info["iters"] // 10), (st, info)
 
 
-def test_chebyshev_guess_modes_and_batches(ctx, cgp, cheb_cases):
-    names = ["rect_33x17", "rect_129x65", "hole_41x21"]
+@pytest.mark.parametrize("names", [["rect_33x17", "rect_129x65", "hole_41x21"],
+                                   ["rect_33x17", "wheel_7", "rect_129x65"]])   # split records with width 8
+def test_chebyshev_guess_modes_and_batches(ctx, cgp, cheb_cases, names):
     hs = [cheb_cases[k][3] for k in names]
     bs = [dt(cheb_cases[k][2]) for k in names]
     refs = [solve.direct(cheb_cases[k][1], cheb_cases[k][2]) for k in names]
