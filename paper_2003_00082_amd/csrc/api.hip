@@ -311,6 +311,7 @@ CoarseRec coarse_record(const InstDesc &d, int cblk0) {
     cr.tiles = d.nblk;
     cr.cblk0 = cblk0;
     cr.ctl = d.ctl;
+    cr.ncb = d.ncb;
     return cr;
 }
 
@@ -790,7 +791,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 const size_t off_part = align(off_prm + sizeof(SolveParams));
                 const size_t off_mu = align(off_part + sizeof(double) * npart);
                 const size_t off_cpart = align(off_mu + sizeof(double) * nmu);
-                const size_t off_cbi = align(off_cpart + sizeof(double) * ncb_total);
+                const size_t off_cbi = align(off_cpart + sizeof(double) * (NRED + 1) * ncb_total);
                 const size_t off_crec = align(off_cbi + sizeof(int32_t) * ncb_total);
                 const size_t total = off_crec + (defl ? sizeof(CoarseRec) * gn : 0);
                 p->buf.alloc(total);
@@ -823,7 +824,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                         d.mu = dmu;
                         d.cpart = dcpart;
                         dmu += d.agg * nb[i];
-                        dcpart += d.ncb;
+                        dcpart += static_cast<size_t>(NRED + 1) * d.ncb;
                         for (int v = 0; v < d.ncb; ++v) hcbi.push_back(i);
                         p->crecs.push_back(coarse_record(d, cblk));
                         cblk += d.ncb;
@@ -836,7 +837,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 CGP_HIP(hipMemcpyAsync(p->buf.p, host.data(), off_rng, hipMemcpyHostToDevice, ctx->aux));
                 p->one = hd[0];
                 if (defl) {
-                    // mu and the coarse partials start at zero: the first stages read them before
+                    // mu and the coarse records start at zero: the first stages read them before
                     // any coarse step has produced values for them
                     CGP_HIP(hipMemsetAsync(p->buf.p + off_mu, 0, off_cbi - off_mu, ctx->aux));
                     CGP_HIP(hipMemcpyAsync(p->buf.p + off_cbi, hcbi.data(), sizeof(int32_t) * hcbi.size(),
@@ -1113,7 +1114,8 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
         const size_t o_inst = take(sizeof(InstDesc)), o_bi = take(sizeof(int32_t) * nblk),
                      o_rng = take(sizeof(RowRange) * nblk), o_ctl = take(2 * sizeof(Ctl)), o_done = take(sizeof(int32_t)),
                      o_prm = take(sizeof(SolveParams)), o_part = take(sizeof(double) * 2 * NPART * nblk),
-                     o_zero = take(sizeof(double) * (na + ncb)), o_cbi = take(sizeof(int32_t) * std::max(ncb, 1)),
+                     o_zero = take(sizeof(double) * (na + (NRED + 1) * ncb)),
+                     o_cbi = take(sizeof(int32_t) * std::max(ncb, 1)),
                      o_crec = take(sizeof(CoarseRec));
         if (off > CGP_NOALLOC_SCRATCH_BYTES) {
             std::ostringstream msg;
@@ -1166,7 +1168,8 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
         int32_t *d_cbi = reinterpret_cast<int32_t *>(at(o_cbi));
         CoarseRec *d_crec = reinterpret_cast<CoarseRec *>(at(o_crec));
         hipStream_t st = ctx->stream;
-        launch_noalloc_setup(st, d_insts, d, d_bi, nblk, d_cbi, ncb, zero, na + ncb, defl ? d_crec : nullptr, cr);
+        launch_noalloc_setup(st, d_insts, d, d_bi, nblk, d_cbi, ncb, zero, na + (NRED + 1) * ncb,
+                             defl ? d_crec : nullptr, cr);
         if (tiled)   // D^-1 into the interleaved vectors (the array keeps whatever the last call left)
             launch_fill_rwsd(st, n, m.dinv32.p, m.dinv.p, mixed ? ws.rwsd32 : nullptr, mixed ? nullptr : ws.rwsd64);
         launch_ranges(st, d_insts, d_bi, nblk, d_rng);

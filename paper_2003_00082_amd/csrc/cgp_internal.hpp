@@ -335,7 +335,8 @@ struct InstDesc {
     const double *einv;                  // [m x einv_stride(m)], m = agg * nblk
     const float *einv32;                 // the same in fp32
     double *mu;                          // [m] E^-1 Z^T v of the last stage
-    double *cpart;                       // [ncb] partial sums of mu . Z^T v
+    double *cpart;                       // [ncb][NRED + 1] coarse step records: a slice of the tiles' NRED
+                                         // sums and a partial of mu . Z^T v
     const int8_t *oagg;                  // own rows (by region entry): 0 Dirichlet, 1 + aggregate within the tile
 };
 
@@ -392,12 +393,14 @@ struct CoarseRec {               // what the coarse step of one instance touches
     const float *einv32;         // the same in fp32 (read by the coarse step of fp32 iterations)
     const double *partials;      // the instance's [2][NPART][tiles] stage partials
     double *mu;                  // [m]
-    double *cpart;               // [ceil(m / COARSE_ROWS)]
+    double *cpart;               // [ncb][NRED + 1]
     int32_t m;                   // aggregates (agg per tile)
     int32_t tiles;               // workgroups of the tiled stage
     int32_t cblk0;               // first coarse workgroup of the instance
     int32_t agg;                 // aggregates per tile: aggregate a is part a % agg of tile a / agg
     const Ctl *ctl;              // the instance's control state, by stage parity
+    int32_t ncb;                 // coarse workgroups of the instance (ceil(m / COARSE_ROWS))
+    int32_t pad_;
 };
 // h_single: the record of a single-instance solve (passed by value), else the device records
 // e32: read the fp32 copy of E^-1 (fp32 iterations)

@@ -63,6 +63,26 @@ template <class T>
 __device__ __forceinline__ CGP_GLOBAL T *gst(T *p) {
     return (CGP_GLOBAL T *)p;
 }
+// Memory that no thread writes while the kernel runs, read at a uniform address: through the
+// constant address space the compiler loads it with scalar loads, which complete apart from
+// the vector loads in flight.
+#define CGP_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const CGP_CONST T *cld(const T *p) {
+    return (const CGP_CONST T *)p;
+}
+// a whole record that way (word by word: structs do not copy across address spaces)
+template <class T>
+__device__ __forceinline__ T cld_record(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "records of whole 32-bit words");
+    const CGP_CONST uint32_t *src = (const CGP_CONST uint32_t *)p;
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; ++i) w[i] = src[i];
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
 
 enum State : int32_t {
     ST_BOOT = 0,  // before the first stage
@@ -664,10 +684,10 @@ __device__ inline void write_stats(const Ctl &c, const SolveParams &prm, int idx
 }
 
 // The previous stage's sums of an instance, by every thread of the workgroup: the first
-// NRED of its per-workgroup partials and (deflation) the coarse step's partials of
-// c = mu . q into S[NRED].  Each thread adds the slots t, t + BLOCK, ..., then block_sums
-// adds threads and wavefronts in a fixed order, so every workgroup of the instance gets the
-// same sums.  One round of loads for up to BLOCK workgroups, instead of a wavefront walking
+// NRED of its per-workgroup partials, and S[NRED] = 0 (the stages of a deflated solve
+// decode from the coarse step's records instead: reduced_decode).  Each thread adds the
+// slots t, t + BLOCK, ..., then block_sums adds threads and wavefronts in a fixed order, so
+// every workgroup of the instance gets the same sums.  One round of loads for up to BLOCK workgroups, instead of a wavefront walking
 // the slots 64 at a time.
 __device__ inline void stage_sums(const InstDesc &D, int rd, double (*red)[NPART], double *out) {
     const int nblk = D.nblk;
@@ -680,11 +700,7 @@ __device__ inline void stage_sums(const InstDesc &D, int rd, double (*red)[NPART
 #pragma unroll
         for (int q = 0; q < NRED; ++q) t[q] += a[q];
     }
-    if (D.defl) {
-        const CGP_GLOBAL double *cg = gld(D.cpart);
-        for (int j = threadIdx.x; j < D.ncb; j += BLOCK) t[NRED] += cg[j];
-    }
-    block_sums(t, red, out);
+    block_sums(t, red, out);   // t[NRED] = 0: deflated stages decode from the coarse step's sums
 }
 
 // The common transition, an iteration followed by another one, kept short and
@@ -714,6 +730,21 @@ __device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolvePa
     return transition(prev, S, prm, guess);
 }
 
+// What workgroup 0 of an instance does after a transition (one thread): carry the state
+// forward and, when the instance finished, write its stats and report completion.
+__device__ inline void stage_bookkeeping(const InstDesc &D, int par, const Ctl &prev, const Ctl &c,
+                                         const SolveParams &prm, int32_t *done_count, int32_t *host_flag) {
+    D.ctl[par] = c;   // carried forward every launch, DONE included
+    if (c.state == ST_DONE && prev.state != ST_DONE) {
+        write_stats(c, prm, D.stats_index);
+        // the last instance to finish reports the launches it needed, then completion
+        if (atomicAdd(done_count, 1) == prm.n_inst - 1) {
+            __hip_atomic_store(host_flag + 1, c.stages, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
 // Decode the stage: the workgroup sums the previous stage's partials, thread 0 applies
 // the transition into sh.ctl (workgroup 0 of the instance also carries the state forward
 // and reports completion); the other threads wait at the barrier.
@@ -730,19 +761,42 @@ __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, 
             c.stages = prev.stages + 1;
         }
         sh.ctl = c;
-        if (lb == 0) {
-            D.ctl[par] = c;   // carried forward every launch, DONE included
-            if (c.state == ST_DONE && prev.state != ST_DONE) {
-                write_stats(c, prm, D.stats_index);
-                // the last instance to finish reports the launches it needed, then completion
-                if (atomicAdd(done_count, 1) == prm.n_inst - 1) {
-                    __hip_atomic_store(host_flag + 1, c.stages, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    __hip_atomic_store(host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-                }
+        if (lb == 0) stage_bookkeeping(D, par, prev, c, prm, done_count, host_flag);
+    }
+    __syncthreads();
+}
+
+// A deflated tiled stage finds the previous stage's sums in the records of that stage's
+// coarse step (ncb records per instance, each a slice of the tiles' NRED sums and a partial
+// of c): wavefront 0 adds them (lanes over the records, then across the wavefront: a fixed
+// order) instead of the whole workgroup reducing every tile's partials, and thread 0 applies
+// the transition.  The control state and the parameters come through scalar loads (the
+// stage writes ctl[par], never ctl[rd], and no parameter).
+__device__ inline Ctl reduced_decode(const InstDesc &D, int lb, int rd, int par, const SolveParams *prm_dev,
+                                     Shared &sh, int32_t *done_count, int32_t *host_flag) {
+    const Ctl prev = cld_record(D.ctl + rd);
+    const SolveParams prm = cld_record(prm_dev);
+    if (threadIdx.x < 64) {
+        const CGP_GLOBAL double *cp = gld(D.cpart);
+        double S[NRED + 1] = {};
+        for (int j = static_cast<int>(threadIdx.x); j < D.ncb; j += 64) {
+#pragma unroll
+            for (int q = 0; q <= NRED; ++q) S[q] += cp[j * (NRED + 1) + q];
+        }
+#pragma unroll
+        for (int q = 0; q <= NRED; ++q) S[q] = wave_sum(S[q]);
+        if (threadIdx.x == 0) {
+            Ctl c = prev;
+            if (prev.state != ST_DONE) {
+                c = next_state(prev, S, prm, D.guess);
+                c.stages = prev.stages + 1;
             }
+            sh.ctl = c;
+            if (lb == 0) stage_bookkeeping(D, par, prev, c, prm, done_count, host_flag);
         }
     }
     __syncthreads();
+    return sh.ctl;
 }
 
 // ------------------------------------------------------------------ driver 1: one stage per launch
@@ -833,109 +887,122 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 template <class T, int W>
 __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, const TileBlk &B, int rd) {
+    // Every load is issued by every thread, at a clamped index where the thread has no row
+    // (its values are then replaced by zeros): with no branch around the loads the compiler
+    // can wait for exactly the loads a step needs, so the gathers that follow the region's
+    // row list go out as soon as that list has arrived, while the matrix records are in flight.
     const int64_t n = D.n;
     constexpr int CW = tile_col_stride(W);   // 16-bit columns per record
     constexpr int VP = 16 / sizeof(T);        // values per 16-byte load
     static_assert(W == SPLIT_WIDTH || W % VP == 0, "value records are whole 16-byte loads");
+    const int tid = static_cast<int>(threadIdx.x);
+    // the region's global rows first (the gathers below wait for them, not for the records)
+    const CGP_GLOBAL int32_t *reg = gld(D.treg + B.reg_off);
+#pragma unroll
+    for (int h = 0; h < TH; ++h) {
+        const int t = tid + h * BLOCK;
+        const int32_t g = reg[min(t, B.nreg - 1)];
+        f.g[h] = t < B.nreg ? g : -1;
+    }
+    // local matrix rows (rows past nspmv gather entry 0 times 0)
 #pragma unroll
     for (int h = 0; h < TS; ++h) {
-        const int t = threadIdx.x + h * BLOCK;
-#pragma unroll
-        for (int k = 0; k < W / 2; ++k) f.ec[h][k] = 0u;   // rows past nspmv gather entry 0 times 0
-#pragma unroll
-        for (int k = 0; k < W; ++k) f.ev[h][k] = T(0);
+        const int t = tid + h * BLOCK;
+        const bool live = t < B.nspmv;
+        const size_t tc = static_cast<size_t>(min(t, B.nspmv - 1));
         if constexpr (W == SPLIT_WIDTH) {
-            if (t < B.nspmv) {
-                // split records, column-major over the tile's rows: pair q of every row in turn
-                const size_t ns = static_cast<size_t>(B.nspmv);
-                const CGP_GLOBAL uint32_t *sc = reinterpret_cast<const CGP_GLOBAL uint32_t *>(gld(D.tcol)) +
-                                                (SPLIT_WIDTH / 2) * static_cast<size_t>(B.ell_off) + t;
-                const CGP_GLOBAL T *sv = gld(tile_val<T>(D)) + SPLIT_WIDTH * static_cast<size_t>(B.ell_off) + 2 * t;
+            // split records, column-major over the tile's rows: pair q of every row in turn
+            const size_t ns = static_cast<size_t>(B.nspmv);
+            const CGP_GLOBAL uint32_t *sc = reinterpret_cast<const CGP_GLOBAL uint32_t *>(gld(D.tcol)) +
+                                            (SPLIT_WIDTH / 2) * static_cast<size_t>(B.ell_off) + tc;
+            const CGP_GLOBAL T *sv = gld(tile_val<T>(D)) + SPLIT_WIDTH * static_cast<size_t>(B.ell_off) + 2 * tc;
 #pragma unroll
-                for (int q = 0; q < SPLIT_WIDTH / 2; ++q) {
-                    f.ec[h][q] = sc[q * ns];
-                    if constexpr (sizeof(T) == 4) {
-                        const u32x2 u = *reinterpret_cast<const CGP_GLOBAL u32x2 *>(sv + 2 * q * ns);
-                        f.ev[h][2 * q] = __uint_as_float(u.x);
-                        f.ev[h][2 * q + 1] = __uint_as_float(u.y);
-                    } else {
-                        const u32x4 u = *reinterpret_cast<const CGP_GLOBAL u32x4 *>(sv + 2 * q * ns);
-                        f.ev[h][2 * q] = __hiloint2double(static_cast<int>(u.y), static_cast<int>(u.x));
-                        f.ev[h][2 * q + 1] = __hiloint2double(static_cast<int>(u.w), static_cast<int>(u.z));
-                    }
+            for (int q = 0; q < SPLIT_WIDTH / 2; ++q) {
+                const uint32_t c = sc[q * ns];
+                f.ec[h][q] = live ? c : 0u;
+                if constexpr (sizeof(T) == 4) {
+                    const u32x2 u = *reinterpret_cast<const CGP_GLOBAL u32x2 *>(sv + 2 * q * ns);
+                    f.ev[h][2 * q] = live ? __uint_as_float(u.x) : 0.0f;
+                    f.ev[h][2 * q + 1] = live ? __uint_as_float(u.y) : 0.0f;
+                } else {
+                    const u32x4 u = *reinterpret_cast<const CGP_GLOBAL u32x4 *>(sv + 2 * q * ns);
+                    f.ev[h][2 * q] = live ? __hiloint2double(static_cast<int>(u.y), static_cast<int>(u.x)) : 0.0;
+                    f.ev[h][2 * q + 1] = live ? __hiloint2double(static_cast<int>(u.w), static_cast<int>(u.z)) : 0.0;
                 }
             }
-        } else if (t < B.nspmv) {
-            const size_t row = static_cast<size_t>(B.ell_off) + t;
+        } else {
+            const size_t row = static_cast<size_t>(B.ell_off) + tc;
             const CGP_GLOBAL u32x4 *ec = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(D.tcol) + row * CW);
             const u32x4 c0 = ec[0];
-            f.ec[h][0] = c0.x;
-            f.ec[h][1] = c0.y;
-            f.ec[h][2] = c0.z;
-            f.ec[h][3] = c0.w;
+            f.ec[h][0] = live ? c0.x : 0u;
+            f.ec[h][1] = live ? c0.y : 0u;
+            f.ec[h][2] = live ? c0.z : 0u;
+            f.ec[h][3] = live ? c0.w : 0u;
             if constexpr (W > 8) {
                 const u32x4 c1 = ec[1];
-                f.ec[h][4] = c1.x;
-                f.ec[h][5] = c1.y;
+                f.ec[h][4] = live ? c1.x : 0u;
+                f.ec[h][5] = live ? c1.y : 0u;
             }
             const CGP_GLOBAL u32x4 *ev = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(tile_val<T>(D)) + row * W);
 #pragma unroll
             for (int q = 0; q < W / VP; ++q) {
                 const u32x4 u = ev[q];
                 if constexpr (sizeof(T) == 4) {
-                    f.ev[h][4 * q] = __uint_as_float(u.x);
-                    f.ev[h][4 * q + 1] = __uint_as_float(u.y);
-                    f.ev[h][4 * q + 2] = __uint_as_float(u.z);
-                    f.ev[h][4 * q + 3] = __uint_as_float(u.w);
+                    f.ev[h][4 * q] = live ? __uint_as_float(u.x) : 0.0f;
+                    f.ev[h][4 * q + 1] = live ? __uint_as_float(u.y) : 0.0f;
+                    f.ev[h][4 * q + 2] = live ? __uint_as_float(u.z) : 0.0f;
+                    f.ev[h][4 * q + 3] = live ? __uint_as_float(u.w) : 0.0f;
                 } else {
-                    f.ev[h][2 * q] = __hiloint2double(static_cast<int>(u.y), static_cast<int>(u.x));
-                    f.ev[h][2 * q + 1] = __hiloint2double(static_cast<int>(u.w), static_cast<int>(u.z));
+                    f.ev[h][2 * q] = live ? __hiloint2double(static_cast<int>(u.y), static_cast<int>(u.x)) : 0.0;
+                    f.ev[h][2 * q + 1] = live ? __hiloint2double(static_cast<int>(u.w), static_cast<int>(u.z)) : 0.0;
                 }
             }
         }
     }
-    const CGP_GLOBAL int32_t *reg = gld(D.treg + B.reg_off);
+    // own rows: (u, p) by own slot, consecutive over the tile
+    const CGP_GLOBAL T *up = gld(up_of<T>(D)) + 2 * static_cast<int64_t>(B.own_off);
 #pragma unroll
-    for (int h = 0; h < TH; ++h) {
-        const int t = threadIdx.x + h * BLOCK;
-        f.g[h] = t < B.nreg ? reg[t] : -1;
+    for (int h = 0; h < TILE_OWN; ++h) {
+        const int t = tid + h * BLOCK;
+        const bool live = t < B.nt[0];
+        const int tc = min(t, B.nt[0] - 1);
+        const T u = up[2 * tc], p = up[2 * tc + 1];
+        f.ou[h] = live ? u : T(0);
+        f.op[h] = live ? p : T(0);
     }
     // (r, w, s, D^-1) of a region row: one 16-byte load (fp32) or two (fp64)
     const CGP_GLOBAL u32x4 *q = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(rwsd_of<T>(D)) + rd * n * 4);
 #pragma unroll
     for (int h = 0; h < TH; ++h) {
         const int32_t j = f.g[h];
-        if (j >= 0) {
-            if constexpr (sizeof(T) == 4) {
-                const u32x4 a = q[j];
-                f.r[h] = __uint_as_float(a.x);
-                f.w[h] = __uint_as_float(a.y);
-                f.s[h] = __uint_as_float(a.z);
-                f.dv[h] = __uint_as_float(a.w);
-            } else {
-                const u32x4 a = q[2 * static_cast<int64_t>(j)], b = q[2 * static_cast<int64_t>(j) + 1];
-                f.r[h] = __hiloint2double(static_cast<int>(a.y), static_cast<int>(a.x));
-                f.w[h] = __hiloint2double(static_cast<int>(a.w), static_cast<int>(a.z));
-                f.s[h] = __hiloint2double(static_cast<int>(b.y), static_cast<int>(b.x));
-                f.dv[h] = __hiloint2double(static_cast<int>(b.w), static_cast<int>(b.z));
-            }
+        const int64_t jc = j >= 0 ? j : 0;
+        const bool live = j >= 0;
+        if constexpr (sizeof(T) == 4) {
+            const u32x4 a = q[jc];
+            f.r[h] = live ? __uint_as_float(a.x) : 0.0f;
+            f.w[h] = live ? __uint_as_float(a.y) : 0.0f;
+            f.s[h] = live ? __uint_as_float(a.z) : 0.0f;
+            f.dv[h] = live ? __uint_as_float(a.w) : 1.0f;
+        } else {
+            const u32x4 a = q[2 * jc], b = q[2 * jc + 1];
+            f.r[h] = live ? __hiloint2double(static_cast<int>(a.y), static_cast<int>(a.x)) : 0.0;
+            f.w[h] = live ? __hiloint2double(static_cast<int>(a.w), static_cast<int>(a.z)) : 0.0;
+            f.s[h] = live ? __hiloint2double(static_cast<int>(b.y), static_cast<int>(b.x)) : 0.0;
+            f.dv[h] = live ? __hiloint2double(static_cast<int>(b.w), static_cast<int>(b.z)) : 1.0;
         }
     }
-    // own rows: (u, p) by own slot, consecutive over the tile; c (fp32) or x (fp64) by row
-    const CGP_GLOBAL T *up = gld(up_of<T>(D)) + 2 * static_cast<int64_t>(B.own_off);
+    // own rows: c (fp32) or x (fp64) by row
 #pragma unroll
     for (int h = 0; h < TILE_OWN; ++h) {
-        f.ou[h] = f.op[h] = f.ox[h] = T(0);
-        const int t = static_cast<int>(threadIdx.x) + h * BLOCK;
-        if (t < B.nt[0]) {
-            const int32_t j = f.g[h];
-            f.ou[h] = up[2 * t];
-            f.op[h] = up[2 * t + 1];
-            if constexpr (sizeof(T) == 4)
-                f.ox[h] = gld(D.c32)[j];
-            else
-                f.ox[h] = gld(D.x)[j];
-        }
+        const int32_t j = f.g[h];
+        const int64_t jc = j >= 0 ? j : 0;
+        const bool live = tid + h * BLOCK < B.nt[0];
+        T x;
+        if constexpr (sizeof(T) == 4)
+            x = gld(D.c32)[jc];
+        else
+            x = gld(D.x)[jc];
+        f.ox[h] = live ? x : T(0);
     }
 }
 
@@ -946,6 +1013,8 @@ __device__ inline void tile_prefetch(TilePrefetch<T, W> &f, const InstDesc &D, c
 template <class T>
 struct DeflPrefetch {
     int32_t kr;                // region index of the record, -1 for none
+    uint32_t kg[KZ_PER_ROW];   // the aggregates it names
+    double mu_own;             // thread a < agg: mu of the tile's aggregate a
     T kv[KZ_PER_ROW];          // (K Z)_{row, a}
     T km[KZ_PER_ROW];          // mu_a (rounded to the iteration's precision)
     int32_t code[TILE_OWN];    // own rows: 0 Dirichlet (or none), 1 + part of the tile
@@ -958,34 +1027,40 @@ __device__ inline const double *kz_val<double>(const InstDesc &D) { return D.kzv
 template <>
 __device__ inline const float *kz_val<float>(const InstDesc &D) { return D.kzv32; }
 
-// s_mu (LDS, D.agg entries): mu of the tile's own aggregates, loaded by the first threads
+// (1) the loads that depend on nothing: coupling record, aggregate codes, own-aggregate mu;
+// issued ahead of the tile's loads, so that (2), the gathers of the named aggregates' mu,
+// waits for them alone
 template <class T>
-__device__ inline void defl_prefetch(DeflPrefetch<T> &f, const InstDesc &D, const TileBlk &B, int lb, double *s_mu) {
-    const CGP_GLOBAL double *mu = gld(D.mu);
-    f.kr = -1;
-    if (static_cast<int>(threadIdx.x) < D.agg) s_mu[threadIdx.x] = mu[D.agg * lb + threadIdx.x];
+__device__ inline void defl_records(DeflPrefetch<T> &f, const InstDesc &D, const TileBlk &B, int lb) {
+    const int tid = static_cast<int>(threadIdx.x);
+    const double m = gld(D.mu)[D.agg * lb + min(tid, D.agg - 1)];
+    f.mu_own = tid < D.agg ? m : 0.0;
 #pragma unroll
     for (int h = 0; h < TILE_OWN; ++h) {
-        const int t = static_cast<int>(threadIdx.x) + h * BLOCK;
-        f.code[h] = t < B.nt[0] ? gld(D.oagg)[static_cast<size_t>(B.reg_off) + t] : 0;
+        const int t = tid + h * BLOCK;
+        const int32_t code = gld(D.oagg)[static_cast<size_t>(B.reg_off) + min(t, B.nt[0] - 1)];
+        f.code[h] = t < B.nt[0] ? code : 0;
     }
+    // record kz_off + min(t, nkz): the records of the next tile, or the one past the last
+    // tile's, where the thread has none (kg, kv and km are read only where kr >= 0)
+    const size_t q = static_cast<size_t>(B.kz_off) + min(tid, B.nkz);
+    const int32_t kr = gld(D.kzr)[q];
+    f.kr = tid < B.nkz ? kr : -1;
+    const u32x4 g = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(D.kzg))[q];
+    f.kg[0] = g.x;
+    f.kg[1] = g.y;
+    f.kg[2] = g.z;
+    f.kg[3] = g.w;
+    const CGP_GLOBAL T *kv = gld(kz_val<T>(D)) + q * KZ_PER_ROW;
 #pragma unroll
-    for (int e = 0; e < KZ_PER_ROW; ++e) {
-        f.kv[e] = T(0);
-        f.km[e] = T(0);
-    }
-    if (static_cast<int>(threadIdx.x) < B.nkz) {
-        const size_t q = static_cast<size_t>(B.kz_off) + threadIdx.x;
-        f.kr = gld(D.kzr)[q];
-        const u32x4 g = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(D.kzg))[q];
-        const CGP_GLOBAL T *kv = gld(kz_val<T>(D)) + q * KZ_PER_ROW;
+    for (int e = 0; e < KZ_PER_ROW; ++e) f.kv[e] = kv[e];
+}
+
+template <class T>
+__device__ inline void defl_mu(DeflPrefetch<T> &f, const InstDesc &D) {
+    const CGP_GLOBAL double *mu = gld(D.mu);
 #pragma unroll
-        for (int e = 0; e < KZ_PER_ROW; ++e) f.kv[e] = kv[e];
-        f.km[0] = static_cast<T>(mu[g.x]);
-        f.km[1] = static_cast<T>(mu[g.y]);
-        f.km[2] = static_cast<T>(mu[g.z]);
-        f.km[3] = static_cast<T>(mu[g.w]);
-    }
+    for (int e = 0; e < KZ_PER_ROW; ++e) f.km[e] = static_cast<T>(mu[f.kg[e]]);
 }
 
 // y_t = sum_k ev[h][k] * x[ec[h][k]] for the thread's local matrix row h; with split records
@@ -1176,36 +1251,49 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     const int lb = xcd_block(blockIdx.x - D.blk0, D.nblk);
     const TileBlk B = D.tblk[lb];
     const int rd = par ^ 1;
-    // per-distance row counts and coefficients, indexed by a run-time degree: LDS
-    if (threadIdx.x < TILE_MAX_DEGREE + 2) s_nt[threadIdx.x] = D.tblk[lb].nt[threadIdx.x];
-    if (threadIdx.x < 2 * TILE_MAX_DEGREE) s_cheb[threadIdx.x] = D.cheb[threadIdx.x];
     // speculative loads for an iteration, in flight while the state is decoded
-    TilePrefetch<T, W> f;
-    tile_prefetch<T, W>(f, D, B, rd);
     constexpr bool defl = DEFL;
     DeflPrefetch<T> df;
-    __shared__ double s_mu[AGG_MAX];
-    static_assert(AGG_TILE <= AGG_MAX, "the partial slots hold the tile's aggregates");
-    T *kzm = reinterpret_cast<T *>(sh.lds) + 3 * TILE_REGION;
     df.kr = -1;
 #pragma unroll
     for (int h = 0; h < TILE_OWN; ++h) df.code[h] = 0;
+    if (defl) defl_records<T>(df, D, B, lb);
+    TilePrefetch<T, W> f;
+    tile_prefetch<T, W>(f, D, B, rd);
+    __shared__ double s_mu[AGG_MAX];
+    static_assert(AGG_TILE <= AGG_MAX, "the partial slots hold the tile's aggregates");
+    T *kzm = reinterpret_cast<T *>(sh.lds) + 3 * TILE_REGION;
     if (defl) {
-        defl_prefetch<T>(df, D, B, lb, s_mu);
+        defl_mu<T>(df, D);
 #pragma unroll
         for (int h = 0; h < TH; ++h) {
             const int t = threadIdx.x + h * BLOCK;
             if (t < B.nreg) kzm[t] = T(0);
         }
     }
-    decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
-    const Ctl c = sh.ctl;
+    // per-distance row counts and coefficients, indexed by a run-time degree: LDS (from the
+    // records already loaded, read after the barriers below)
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < TILE_MAX_DEGREE + 2; ++k) s_nt[k] = B.nt[k];
+#pragma unroll
+        for (int k = 0; k < 2 * TILE_MAX_DEGREE; ++k) s_cheb[k] = D.cheb[k];
+    }
+    Ctl c;
+    if constexpr (DEFL) {
+        c = reduced_decode(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
+    } else {
+        decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
+        c = sh.ctl;
+    }
     if (c.state == ST_DONE) return;
     double v[NRED] = {};
     double av[TILE_OWN] = {};   // per own row: its term of its aggregate's sum (deflation)
     if (c.state == ST_ITER || c.state == ST_START) {
         if (defl) {
-            // K Z mu over the region: one coupling record per thread, zero elsewhere
+            // K Z mu over the region: one coupling record per thread, zero elsewhere (the
+            // decode's barrier put every thread's zeros in place first); the tile's own mu
+            if (static_cast<int>(threadIdx.x) < D.agg) s_mu[threadIdx.x] = df.mu_own;
             if (df.kr >= 0) {
                 T a = T(0);
 #pragma unroll
@@ -1328,10 +1416,29 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
         if (a1 < m) gst(C.mu)[a1] = mu1;
     }
     __syncthreads();
+    // the workgroup's record for the next stage's decode: its partial of c = mu . q, and its
+    // slice of the tiles' NRED partials (tiles [cb nt / ncb, (cb + 1) nt / ncb), lanes over
+    // the slice, then across the wavefront), so that the next stage adds ncb records
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < COARSE_ROWS; ++w) t += red[w];
-        gst(C.cpart)[cb] = t;
+        gst(C.cpart)[cb * (NRED + 1) + NRED] = t;
+    }
+    if (wave == 1) {
+        const int j0 = static_cast<int>(static_cast<int64_t>(cb) * nt / C.ncb);
+        const int j1 = static_cast<int>(static_cast<int64_t>(cb + 1) * nt / C.ncb);
+        const CGP_GLOBAL double *pg = gld(C.partials) + static_cast<size_t>(par) * NPART * nt;
+        double t[NRED] = {};
+        for (int j = j0 + lane; j < j1; j += 64) {
+#pragma unroll
+            for (int q = 0; q < NRED; ++q) t[q] += pg[q * nt + j];
+        }
+#pragma unroll
+        for (int q = 0; q < NRED; ++q) t[q] = wave_sum(t[q]);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < NRED; ++q) gst(C.cpart)[cb * (NRED + 1) + q] = t[q];
+        }
     }
 }
 

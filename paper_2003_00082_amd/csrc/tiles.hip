@@ -355,6 +355,13 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
         blk[t].nkz = static_cast<int32_t>(kzr.size()) - blk[t].kz_off;
         if (blk[t].nkz > TILE_ROWS) return false;   // one record per thread
     }
+    // one record past the last tile's: every thread of the stage kernel loads record
+    // kz_off + min(t, nkz) (no branch around the loads) and ignores it unless t < nkz
+    kzr.push_back(0);
+    for (int e = 0; e < KZ_PER_ROW; ++e) {
+        kzg.push_back(0);
+        kzv.push_back(0.0);
+    }
     // E = Z^T K Z and its inverse
     std::vector<double> E(static_cast<size_t>(na) * na, 0.0);
     std::vector<int32_t> nfree(na, 0);
