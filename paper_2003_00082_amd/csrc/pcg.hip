@@ -1360,6 +1360,20 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     const int m = C.m, ms = einv_stride(m), nt = C.tiles, nch = ms / VE;
     const int a0 = cb * COARSE_ROWS + wave, a1 = a0 + COARSE_WAVES;
     const E *einv = einv_of<E>(C);
+    // Loads without branches around them (clamped indices, zeros selected afterwards), q
+    // first: its LDS copy then waits for q alone while the rows of E^-1 are in flight.
+    // q_a, the partial NRED + (a % agg) of tile a / agg (zero past m)
+    constexpr int QT = MAX_DEFL_AGGREGATES / (64 * COARSE_WAVES);   // q entries per thread, at most
+    const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * nt + static_cast<size_t>(NRED) * nt;
+    const int A = C.agg;
+    double qv[QT];
+#pragma unroll
+    for (int k = 0; k < QT; ++k) {
+        const int i = static_cast<int>(threadIdx.x) + k * 64 * COARSE_WAVES;
+        const int ic = min(i, m - 1);
+        const double v = q[static_cast<size_t>(ic % A) * nt + ic / A];
+        qv[k] = i < m ? v : 0.0;
+    }
     u32x4 e0[CH], e1[BOTH ? CH : 1];
     auto load_row = [&](int a, u32x4 *e) {
         const CGP_GLOBAL u32x4 *er =
@@ -1367,20 +1381,21 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
             const int c = lane + 64 * k;
-            e[k] = (a < m && c < nch) ? er[c] : u32x4{0u, 0u, 0u, 0u};
+            const u32x4 v = er[min(c, nch - 1)];
+            e[k] = (a < m && c < nch) ? v : u32x4{0u, 0u, 0u, 0u};
         }
     };
     load_row(a0, e0);
     if constexpr (BOTH) load_row(a1, e1);
     // a stage that found the instance finished (launches past the end of the solve) has
     // nothing for the next one; its state was stored by the stage kernel before this launch
-    // (read with the row loads in flight)
-    if (gld(C.ctl)[par].state == ST_DONE) return;
-    // q_a, the partial NRED + (a % agg) of tile a / agg, staged in LDS (zero past m)
-    const CGP_GLOBAL double *q = gld(C.partials) + static_cast<size_t>(par) * NPART * nt + static_cast<size_t>(NRED) * nt;
-    const int A = C.agg;
-    for (int i = threadIdx.x; i < ms; i += 64 * COARSE_WAVES)
-        qs[i] = i < m ? q[static_cast<size_t>(i % A) * nt + i / A] : 0.0;
+    // (a scalar load: no wait for the loads in flight)
+    if ((cld(C.ctl) + par)->state == ST_DONE) return;
+#pragma unroll
+    for (int k = 0; k < QT; ++k) {
+        const int i = static_cast<int>(threadIdx.x) + k * 64 * COARSE_WAVES;
+        if (i < ms) qs[i] = qv[k];
+    }
     __syncthreads();
     auto dot = [&](const u32x4 *e) {
         double acc = 0.0;
