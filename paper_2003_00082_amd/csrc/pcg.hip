@@ -123,6 +123,26 @@ __device__ inline void block_sums(double (&v)[NS], double (*red)[NPART], double 
     __syncthreads();
 }
 
+// the workgroup's NS sums written to part[s * stride], s < NS, in block_sums' order; one
+// barrier (no thread reads the sums afterwards)
+template <int NS>
+__device__ inline void block_partials(double (&v)[NS], double (*red)[NPART], double *part, int stride) {
+    static_assert(NS <= NPART, "the reduction rows hold NPART values");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = wave_sum(v[s]);
+    if (lane == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) red[wave][s] = v[s];
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        double t = 0.0;
+        for (int w = 0; w < NWAVE; ++w) t += red[w][threadIdx.x];
+        part[static_cast<size_t>(threadIdx.x) * stride] = t;
+    }
+}
+
 // sum of an instance's per-workgroup partials (same order in every workgroup); out[NRED],
 // the deflation term of the transitions, is zero (the persistent engine does not deflate)
 __device__ inline void reduce_partials(const double *part, int nblk, double (*red)[NPART], double *out) {
@@ -830,9 +850,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
         const SolveParams prm = *prm_dev;
         stage_work<false>(c, D, R, prm, sh, par, v);
     }
-    block_sums(v, sh.red, sh.sums);
-    if (threadIdx.x < NRED) D.partials[static_cast<size_t>(par) * NPART * D.nblk + threadIdx.x * D.nblk + lb] =
-        sh.sums[threadIdx.x];
+    block_partials(v, sh.red, D.partials + static_cast<size_t>(par) * NPART * D.nblk + lb, D.nblk);
 }
 
 // ------------------------------------------------------------------ tiled iteration
@@ -1328,9 +1346,7 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
             if (df.code[h] == a + 1) t += av[h];
         vs[NRED + a] = t;
     }
-    block_sums(vs, sh.red, sh.sums);
-    double *part = D.partials + static_cast<size_t>(par) * NPART * D.nblk;
-    if (threadIdx.x < NS) part[threadIdx.x * D.nblk + lb] = sh.sums[threadIdx.x];
+    block_partials(vs, sh.red, D.partials + static_cast<size_t>(par) * NPART * D.nblk + lb, D.nblk);
 }
 
 // Coarse step of deflation after a tiled stage: mu = E^-1 q with q the stage's aggregate
