@@ -74,6 +74,16 @@ def momentum_fingerprint() -> str:
     return h.hexdigest()[:16]
 
 
+def tile_width(tri) -> int:
+    """Record width of the tiled stage kernel for a mesh: 6 (split records: rows of at most six
+    off-diagonal entries), else 8 or 12 (the widest row of the stiffness matrix, diagonal included)."""
+    import numpy as np
+    e = np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]]), axis=1)
+    e = np.unique(e, axis=0)
+    widest = int(np.bincount(e.ravel()).max()) + 1
+    return 6 if widest <= 7 else (8 if widest <= 8 else 12)
+
+
 def kernel_fingerprint() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -934,7 +944,7 @@ def c5_main(args):
 
     tname = "float" if forms[main_form][0] == cgp.CGP_FP32_IR else "double"
     kt = R.get("kernel_timing") or {}
-    kname = (f"k_cg_tile<{tname}, 8, true, false>" if forms[main_form][2] >= 1
+    kname = (f"k_cg_tile<{tname}, {tile_width(coarse0.tri)}, true, false>" if forms[main_form][2] >= 1
              else f"k_cg_step<{tname}, 4, false>")
     traffic = None
     if (kernel_fingerprint() == MEASURED_TRAFFIC_C5["fingerprint"] and (nx, ny, M, deg) == (1025, 513, 8, 6)
@@ -1434,7 +1444,7 @@ def main():
     mixed_main = mprec == cgp.CGP_FP32_IR
     tname = "float" if mixed_main else "double"
     if mdeg >= 1:
-        kname = f"k_cg_tile<{tname}, 8, {'true' if mdefl else 'false'}, true>"   # deflation, one instance
+        kname = f"k_cg_tile<{tname}, {tile_width(coarse.tri)}, {'true' if mdefl else 'false'}, true>"   # one instance
         bpi = pcg_bytes(nc, nnz, 1, 0, mixed_main, False, mdeg, aggs if mdefl else 0) - \
             pcg_bytes(nc, nnz, 0, 0, mixed_main, False, mdeg, aggs if mdefl else 0)
     else:
