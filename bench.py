@@ -145,47 +145,6 @@ def parse():
     return args
 
 
-def pcg_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool, extrap: bool,
-              degree: int = 0, aggregates: int = 0) -> float:
-    """Algorithmic HBM bytes of one solve: every matrix entry (value + int32 column) each
-    product with K reads and every vector element each stage reads or writes, counted
-    once per stage (halo re-reads, region copies and padding are not counted).
-
-    Jacobi (degree 0, row-range kernel): fp32 iteration 8 nnz + 44 n (matrix; reads r, w,
-    s, D^-1, p, c, writes p, s, r, w, c); fp64 iteration 12 nnz + 88 n.  A refinement
-    (mixed) is FOLD (32 n) + true residual in fp64 (12 nnz + 32 n) + restart of the
-    recurrences in fp32 (8 nnz + 28 n).
-    Chebyshev degree d >= 1 (tiled kernel): an iteration or restart performs d products
-    with K, d (8 nnz + 8 n) in fp32, plus the recurrences of the own rows (reads r, w, s,
-    u, p, c, D^-1, writes r, w, s, u, p, c: 52 n); fp64 doubles the vector and value
-    bytes (12 nnz + 16 n per product, 104 n).  The initial guess adds 24 n (extrapolation).
-    Deflation with m aggregates adds the coarse step of every stage, 8 m^2 (E^-1) + 16 m
-    (aggregate sums in, coefficients out); its per-row coupling records (a few percent) are
-    not counted."""
-    if degree >= 1:
-        if mixed:
-            it = degree * (8 * nnz + 8 * n) + 52 * n + 8 * aggregates * aggregates + 16 * aggregates
-            res = 12 * nnz + 32 * n
-            total = res + it + iters * it + refinements * (32 * n + res + it)
-        else:
-            it = degree * (12 * nnz + 16 * n) + 104 * n + 8 * aggregates * aggregates + 16 * aggregates
-            res = 12 * nnz + 28 * n
-            total = res + it + iters * it + refinements * (res + it)
-    elif mixed:
-        it = 8 * nnz + 44 * n
-        res = 12 * nnz + 32 * n
-        start = 8 * nnz + 28 * n
-        total = res + start + iters * it + refinements * (32 * n + res + start)
-    else:
-        it = 12 * nnz + 88 * n
-        res = 12 * nnz + 28 * n
-        start = 12 * nnz + 36 * n
-        total = res + start + iters * it + refinements * res
-    if extrap:
-        total += 24 * n
-    return float(total)
-
-
 def batch_main(args):
     """Batched Stuart sweep: `instances` independent CGP instances (coarse nx = 2m+1,
     ny = m+1, m ~ U{32..256}, each refined once; own Fourier flow; Stuart numbers
@@ -298,8 +257,7 @@ def batch_main(args):
             [("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"), ("rel0", "f8")]))
         timed = host[2 * W * M:].reshape(K, 2, M)
         ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
-        nbytes = sum(pcg_bytes(nc[i], nnz[i], int(timed["iters"][k, e, i]), int(timed["ref"][k, e, i]), True, True,
-                               tuned[i] if fdeg == cgp.CGP_DEGREE_TUNED else fdeg)
+        nbytes = sum(solve_bytes(nc[i], nnz[i], int(timed["iters"][k, e, i]), int(timed["ref"][k, e, i]), True)
                      for k in range(K) for e in range(2) for i in range(M))
         for g in graphs.values():
             ctx.graph_free(g)
@@ -656,7 +614,7 @@ def channel_main(args):
     ctx.close()
 
 
-def c5_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool) -> float:
+def solve_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool) -> float:
     """Algorithmic HBM bytes of one solve by the per-iteration figures: a CG iteration reads
     the matrix once (value + int32 column per entry) and the recurrence vectors of its rows,
     8 nnz + 52 n in fp32 (values 4 B; r, w, s, D^-1, u, p, c read and r, w, s, u, p, c
@@ -883,7 +841,7 @@ def c5_main(args):
             "step0": {k: v.cpu().numpy() for k, v in keep.items()},
         }
         if timing is not None and timing["stage_launches"] > 0:
-            alg = sum(c5_bytes(nc[i], nnz[i], int(rerun["iters"][s, i]), int(rerun["ref"][s, i]), mixed)
+            alg = sum(solve_bytes(nc[i], nnz[i], int(rerun["iters"][s, i]), int(rerun["ref"][s, i]), mixed)
                       for s in range(2 * K) for i in range(M))
             iters = int(rerun["iters"].sum())
             out["kernel_timing"] = {
@@ -1373,8 +1331,7 @@ def main():
         ok = bool(np.all(timed["status"] == 0) and np.all(timed["rel"] <= TOL))
         solve_ms = np.array([a.elapsed_time(b) for a, b in ev])
         pcg_ms = solve_ms.sum() - 1e-3 * gnn_us * len(solve_ms)
-        nbytes = np.array([pcg_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed, rotating, fdeg,
-                                     aggs if fdefl else 0) for r in timed])
+        nbytes = np.array([solve_bytes(nc, nnz, int(r["iters"]), int(r["ref"]), mixed) for r in timed])
         return {
             "solves_per_s": 2 * K / elapsed,
             "ms_per_step": 1e3 * elapsed / K,
@@ -1445,11 +1402,9 @@ def main():
     tname = "float" if mixed_main else "double"
     if mdeg >= 1:
         kname = f"k_cg_tile<{tname}, {tile_width(coarse.tri)}, {'true' if mdefl else 'false'}, true>"   # one instance
-        bpi = pcg_bytes(nc, nnz, 1, 0, mixed_main, False, mdeg, aggs if mdefl else 0) - \
-            pcg_bytes(nc, nnz, 0, 0, mixed_main, False, mdeg, aggs if mdefl else 0)
     else:
         kname = f"k_cg_step<{tname}, 4, true>"
-        bpi = (8 * nnz + 44 * nc) if mixed_main else (12 * nnz + 88 * nc)
+    bpi = solve_bytes(nc, nnz, 1, 0, mixed_main)
     traffic = None
     if kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"] and (nx, ny) == (513, 257):
         traffic = MEASURED_TRAFFIC.get(f"{kname} degree {mdeg}" + (" deflated" if mdefl else ""))
@@ -1483,10 +1438,11 @@ def main():
                      "kernel": f"{kname} (one CG stage per launch" +
                                (", followed by the coarse kernel k_cg_coarse)" if mdefl else ")"),
                      "algorithmic_bytes_per_iter": bpi,
-                     "bytes_model": "d products with K (matrix read once each) + own-row recurrence vectors; "
-                                    "see pcg_bytes",
-                     "algorithmic_bytes_per_launch": R["achieved_GBs"] * 1e3 * R["kernel_avg_us"],
-                     "kernel_avg_us": R["kernel_avg_us"]},
+                     "bytes_model": "per CG iteration 8 nnz + 52 n (fp32) or 12 nnz + 100 n (fp64), per "
+                                    "refinement 12 nnz + 28 n; achieved = these bytes / the solves' HIP-event "
+                                    "time on the stream less the network's (wall time of the solves, not "
+                                    "kernel durations)",
+                     "solve_us_per_launch": R["kernel_avg_us"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -17,7 +17,7 @@ def test_algorithmic_bytes_of_a_solve():
     sys.path.insert(0, ROOT)
     import bench
     n, nnz = 1000, 6000
-    # fp32 iteration 8 nnz + 44 n; fp64 iteration 12 nnz + 88 n
-    assert bench.pcg_bytes(n, nnz, 2, 0, True, False) - bench.pcg_bytes(n, nnz, 1, 0, True, False) == 8 * nnz + 44 * n
-    assert bench.pcg_bytes(n, nnz, 2, 0, False, False) - bench.pcg_bytes(n, nnz, 1, 0, False, False) == 12 * nnz + 88 * n
-    assert bench.pcg_bytes(n, nnz, 1, 0, True, True) - bench.pcg_bytes(n, nnz, 1, 0, True, False) == 24 * n
+    # per iteration: fp32 8 nnz + 52 n, fp64 12 nnz + 100 n; per refinement 12 nnz + 28 n
+    assert bench.solve_bytes(n, nnz, 2, 0, True) - bench.solve_bytes(n, nnz, 1, 0, True) == 8 * nnz + 52 * n
+    assert bench.solve_bytes(n, nnz, 2, 0, False) - bench.solve_bytes(n, nnz, 1, 0, False) == 12 * nnz + 100 * n
+    assert bench.solve_bytes(n, nnz, 1, 1, True) - bench.solve_bytes(n, nnz, 1, 0, True) == 12 * nnz + 28 * n
