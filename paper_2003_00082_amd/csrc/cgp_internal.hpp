@@ -172,7 +172,8 @@ constexpr int MAX_DEFL_AGGREGATES = 2048;   // the coarse step holds a row of E^
 // width W (entry k of node i at k * n + i; padding: the node itself with zero weights).
 constexpr int GRAD_MAX_W = 32;
 struct NodalGrad {
-    int32_t W = 0;        // 0: not built; -1: a node has more than GRAD_MAX_W neighbours
+    int32_t W = 0;        // entries per node (its other vertices, padded to 6 or 8); 0: not built; -1: a
+                          // node has more than GRAD_MAX_W - 1 neighbours
     DBuf<int32_t> col;
     DBuf<double> cx, cy;
 };

@@ -181,28 +181,62 @@ __global__ __launch_bounds__(TPB) void k_grad_fill(int64_t n, int W, const int32
         }
         area += 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
     }
-    for (int p = 0; p < W; ++p) {
-        const bool live = p < cnt;
-        col[static_cast<int64_t>(p) * n + i] = live ? ids[p] : static_cast<int32_t>(i);
-        cx[static_cast<int64_t>(p) * n + i] = live ? wx[p] / area : 0.0;
-        cy[static_cast<int64_t>(p) * n + i] = live ? wy[p] / area : 0.0;
+    // the node's own entry is left out: every row of the operator sums to zero (a constant has
+    // no gradient), so G_i q = sum_j c_ij (q_j - q_i) over the other vertices
+    int q = 0;
+    for (int p = 0; p < cnt; ++p) {
+        if (ids[p] == i) continue;
+        col[static_cast<int64_t>(q) * n + i] = ids[p];
+        cx[static_cast<int64_t>(q) * n + i] = wx[p] / area;
+        cy[static_cast<int64_t>(q) * n + i] = wy[p] / area;
+        ++q;
+    }
+    for (; q < W; ++q) {   // padding: the node itself, coefficient 0
+        col[static_cast<int64_t>(q) * n + i] = static_cast<int32_t>(i);
+        cx[static_cast<int64_t>(q) * n + i] = 0.0;
+        cy[static_cast<int64_t>(q) * n + i] = 0.0;
     }
 }
 
-// G_i from the operator (coalesced column-major entries, gathered q)
+// G_i from the operator (coalesced column-major entries of the other vertices, gathered q):
+// sum_j c_ij (q_j - q_i).  WT > 0: the operator's width, every load of the row issued before
+// the first is used; 0: the width W at run time.
+template <int WT>
 __device__ inline void grad_apply(int64_t i, int64_t n, int W, const int32_t *__restrict__ col,
                                   const double *__restrict__ cx, const double *__restrict__ cy,
                                   const double *__restrict__ q, double &gx, double &gy) {
+    const double qi = q[i];
     gx = 0.0;
     gy = 0.0;
-    for (int p = 0; p < W; ++p) {
-        const int64_t o = static_cast<int64_t>(p) * n + i;
-        const double qj = q[col[o]];
-        gx += cx[o] * qj;
-        gy += cy[o] * qj;
+    if constexpr (WT > 0) {
+        int32_t c[WT];
+        double a[WT], b[WT], qj[WT];
+#pragma unroll
+        for (int p = 0; p < WT; ++p) {
+            const int64_t o = static_cast<int64_t>(p) * n + i;
+            c[p] = col[o];
+            a[p] = cx[o];
+            b[p] = cy[o];
+        }
+#pragma unroll
+        for (int p = 0; p < WT; ++p) qj[p] = q[c[p]];
+#pragma unroll
+        for (int p = 0; p < WT; ++p) {
+            const double d = qj[p] - qi;
+            gx += a[p] * d;
+            gy += b[p] * d;
+        }
+    } else {
+        for (int p = 0; p < W; ++p) {
+            const int64_t o = static_cast<int64_t>(p) * n + i;
+            const double d = q[col[o]] - qi;
+            gx += cx[o] * d;
+            gy += cy[o] * d;
+        }
     }
 }
 
+template <int WT>
 __global__ __launch_bounds__(TPB) void k_lorentz_op(int64_t n, int W, const int32_t *__restrict__ col,
                                                     const double *__restrict__ cx, const double *__restrict__ cy,
                                                     const double *__restrict__ phi, const double *__restrict__ u,
@@ -211,12 +245,13 @@ __global__ __launch_bounds__(TPB) void k_lorentz_op(int64_t n, int W, const int3
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double gx, gy;
-    grad_apply(i, n, W, col, cx, cy, phi, gx, gy);
+    grad_apply<WT>(i, n, W, col, cx, cy, phi, gx, gy);
     fx[i] = sigma * b0 * (-gy - b0 * u[i]);
     fy[i] = sigma * b0 * (gx - b0 * v[i]);
 }
 
 // u may alias ut and v vt (thread i reads and writes only entry i of them)
+template <int WT>
 __global__ __launch_bounds__(TPB) void k_velocity_op(int64_t n, int W, const int32_t *__restrict__ col,
                                                      const double *__restrict__ cx, const double *__restrict__ cy,
                                                      const double *__restrict__ p, const double *ut,
@@ -225,7 +260,7 @@ __global__ __launch_bounds__(TPB) void k_velocity_op(int64_t n, int W, const int
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double gx, gy;
-    grad_apply(i, n, W, col, cx, cy, p, gx, gy);
+    grad_apply<WT>(i, n, W, col, cx, cy, p, gx, gy);
     const double a = ut[i], b = vt[i];
     const int m = mask ? mask[i] : 0;
     u[i] = (m & 1) ? a : a - scale * gx;
@@ -355,6 +390,11 @@ bool nodal_grad(hipStream_t s, Mesh &m, bool build) {
         int32_t W = 0;
         CGP_HIP(hipMemcpyAsync(&W, w.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         CGP_HIP(hipStreamSynchronize(s));
+        // W counts the node itself, which the operator leaves out; widths up to 6 and 8 are padded
+        // to those (the unrolled kernels)
+        W -= 1;
+        if (W > 0 && W <= 6) W = 6;
+        else if (W > 6 && W <= 8) W = 8;
         if (W > GRAD_MAX_W || W < 1) {
             G.W = -1;
         } else {
@@ -373,10 +413,18 @@ bool nodal_grad(hipStream_t s, Mesh &m, bool build) {
 void launch_lorentz(hipStream_t s, Mesh &m, const double *phif, const double *uf, const double *vf,
                     double sigma, double b0, double *fx, double *fy, double *grad_elem, bool build) {
     const Level &L = m.lv[m.k];
-    if (nodal_grad(s, m, build))
-        hipLaunchKernelGGL(k_lorentz_op, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.grad.W, m.grad.col.p,
-                           m.grad.cx.p, m.grad.cy.p, phif, uf, vf, sigma, b0, fx, fy);
-    else
+    if (nodal_grad(s, m, build)) {
+#define CGP_LORENTZ(WT)                                                                                     \
+    hipLaunchKernelGGL(k_lorentz_op<WT>, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.grad.W,      \
+                       m.grad.col.p, m.grad.cx.p, m.grad.cy.p, phif, uf, vf, sigma, b0, fx, fy)
+        if (m.grad.W == 6)
+            CGP_LORENTZ(6);
+        else if (m.grad.W == 8)
+            CGP_LORENTZ(8);
+        else
+            CGP_LORENTZ(0);
+#undef CGP_LORENTZ
+    } else
         hipLaunchKernelGGL(k_lorentz, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
                            L.tri.p, L.xy.p, phif, uf, vf, sigma, b0, fx, fy);
     CGP_HIP(hipGetLastError());
@@ -390,10 +438,18 @@ void launch_lorentz(hipStream_t s, Mesh &m, const double *phif, const double *uf
 void launch_velocity(hipStream_t s, Mesh &m, const double *pf, const double *ut, const double *vt,
                      const uint8_t *mask, double scale, double *u, double *v, bool build) {
     const Level &L = m.lv[m.k];
-    if (nodal_grad(s, m, build))
-        hipLaunchKernelGGL(k_velocity_op, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.grad.W, m.grad.col.p,
-                           m.grad.cx.p, m.grad.cy.p, pf, ut, vt, mask, scale, u, v);
-    else
+    if (nodal_grad(s, m, build)) {
+#define CGP_VELOCITY(WT)                                                                                    \
+    hipLaunchKernelGGL(k_velocity_op<WT>, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, m.grad.W,     \
+                       m.grad.col.p, m.grad.cx.p, m.grad.cy.p, pf, ut, vt, mask, scale, u, v)
+        if (m.grad.W == 6)
+            CGP_VELOCITY(6);
+        else if (m.grad.W == 8)
+            CGP_VELOCITY(8);
+        else
+            CGP_VELOCITY(0);
+#undef CGP_VELOCITY
+    } else
         hipLaunchKernelGGL(k_velocity, dim3(blocks_for(L.n, TPB)), dim3(TPB), 0, s, L.n, L.ne_ptr.p, L.ne_idx.p,
                            L.tri.p, L.xy.p, pf, ut, vt, mask, scale, u, v);
     CGP_HIP(hipGetLastError());
