@@ -55,7 +55,7 @@ MEASURED_TRAFFIC = {"fingerprint": "76f97e3fb1e5a8e5", "profile": "profiles/cg_t
 # The same for the batched tiled stage of the two-level workload (8 instances of the 1025x513 coarse
 # mesh, Chebyshev degree 6, deflated, fp32 with fp64 refinement), mean over the launches of a short
 # form-B run (iterations, restarts, residual stages, launches past the end).
-MEASURED_TRAFFIC_C5 = {"fingerprint": "c23888e855530f28", "profile": "profiles/cg_traffic_c5_batch8.md",
+MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "c23888e855530f28", "profile": "profiles/cg_traffic_twolevel_batch8.md",
                        "k_cg_tile<float, 6, true, false>": 634.16e6, "k_cg_coarse<float>": 42.23e6}
 
 
@@ -96,29 +96,29 @@ def kernel_fingerprint() -> str:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed CGP time steps (c5: 20, sequence: 200)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed steps before the timed ones (c5: 5, "
+    ap.add_argument("--steps", type=int, default=None, help="timed CGP time steps (twolevel: 20, sequence: 200)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps before the timed ones (twolevel: 5, "
                                                              "sequence: 10)")
-    ap.add_argument("--nx", type=int, default=None, help="coarse grid nodes along x (c5: 1025, sequence: 513)")
-    ap.add_argument("--ny", type=int, default=None, help="coarse grid nodes along y (c5: 513, sequence: 257)")
-    ap.add_argument("--batch", type=int, default=8, help="c5: instances per batched solve")
+    ap.add_argument("--nx", type=int, default=None, help="coarse grid nodes along x (twolevel: 1025, sequence: 513)")
+    ap.add_argument("--ny", type=int, default=None, help="coarse grid nodes along y (twolevel: 513, sequence: 257)")
+    ap.add_argument("--batch", type=int, default=8, help="twolevel: instances per batched solve")
     ap.add_argument("--stuart", type=float, default=1.0, help="Stuart number N (sigma of the Lorentz force)")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle sample: steps (2 solves each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default=None, help="forms to run (c5: ABCD, sequence: ABCDEF)")
+    ap.add_argument("--forms", default=None, help="forms to run (twolevel: ABCD, sequence: ABCDEF)")
     ap.add_argument("--deflation", type=int, default=1, choices=[0, 1], help="deflation in forms B, C, D")
     ap.add_argument("--degree", type=int, default=6, help="Chebyshev preconditioner degree of forms B, C, D, F")
     ap.add_argument("--refine-delta", type=float, default=1e-3,
                     help="fp32 Chebyshev forms: refine when the fp32 residual fell by this factor since the last "
                          "refinement (the Jacobi forms keep the library's default, 0.1)")
     ap.add_argument("--train-steps", type=int, default=None,
-                    help="steps solved (fp64) to train the networks (c5: 100, sequence: 200)")
-    ap.add_argument("--epochs", type=int, default=None, help="training epochs (c5: 6, sequence: 8)")
+                    help="steps solved (fp64) to train the networks (twolevel: 100, sequence: 200)")
+    ap.add_argument("--epochs", type=int, default=None, help="training epochs (twolevel: 6, sequence: 8)")
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--workload", default="c5",
-                    choices=["c5", "c4", "sequence", "batch", "momentum", "interpolate", "channel"],
-                    help="c5: two-level CGP on batches of 8 Stuart numbers, coarse 1025x513, fine k=2 "
-                         "(default); c4: the learned warm-start protocol (train on 2000 steps, time 1000 "
+    ap.add_argument("--workload", default="twolevel",
+                    choices=["twolevel", "warmstart", "sequence", "batch", "momentum", "interpolate", "channel"],
+                    help="twolevel: two-level CGP on batches of 8 Stuart numbers, coarse 1025x513, fine k=2 "
+                         "(default); warmstart: the learned warm-start protocol (train on 2000 steps, time 1000 "
                          "held-out ones); sequence: one 513x257 CGP sequence; batch: 64-instance Stuart sweep; "
                          "momentum: the fine-mesh momentum step of Eqs. 13-14; interpolate: the restriction "
                          "of a fine field onto the nodes of a non-nested coarse mesh by point location; channel: "
@@ -130,18 +130,18 @@ def parse():
     ap.add_argument("--instances", type=int, default=64, help="batch: number of instances")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one plain 1 GiB device-to-device copy (reference for HBM byte counters)")
-    ap.add_argument("--c4-train", type=int, default=2000, help="c4: training steps")
-    ap.add_argument("--c4-eval", type=int, default=1000, help="c4: held-out timed steps")
-    ap.add_argument("--c4-forms", default="ABCGE", help="c4: forms to time")
+    ap.add_argument("--warmstart-train", type=int, default=2000, help="warmstart: training steps")
+    ap.add_argument("--warmstart-eval", type=int, default=1000, help="warmstart: held-out timed steps")
+    ap.add_argument("--warmstart-forms", default="ABCGE", help="warmstart: forms to time")
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
-    c5 = args.workload == "c5"
-    if args.workload == "c4" and args.epochs is None:
+    twolevel = args.workload == "twolevel"
+    if args.workload == "warmstart" and args.epochs is None:
         args.epochs = 3          # 1998 samples per network
     for name, v5, vs in (("steps", 20, 200), ("warmup", 5, 10), ("forms", "ABCD", "ABCDEF"),
                          ("train_steps", 100, 200), ("epochs", 6, 8)):
         if getattr(args, name) is None:
-            setattr(args, name, v5 if c5 else vs)
+            setattr(args, name, v5 if twolevel else vs)
     return args
 
 
@@ -624,7 +624,7 @@ def solve_bytes(n: int, nnz: int, iters: int, refinements: int, mixed: bool) -> 
     return float(iters * it + refinements * (12 * nnz + 28 * n))
 
 
-def c5_main(args):
+def twolevel_main(args):
     """Two-level CGP on batches of Stuart numbers (the default workload).
 
     ``--batch`` (8) instances, each a coarse 1025 x 513 jittered P1 mesh of [0,2]x[0,1]
@@ -905,9 +905,9 @@ def c5_main(args):
     kname = (f"k_cg_tile<{tname}, {tile_width(coarse0.tri)}, true, false>" if forms[main_form][2] >= 1
              else f"k_cg_step<{tname}, 4, false>")
     traffic = None
-    if (kernel_fingerprint() == MEASURED_TRAFFIC_C5["fingerprint"] and (nx, ny, M, deg) == (1025, 513, 8, 6)
+    if (kernel_fingerprint() == MEASURED_TRAFFIC_TWOLEVEL["fingerprint"] and (nx, ny, M, deg) == (1025, 513, 8, 6)
             and main_form == "B"):
-        traffic = MEASURED_TRAFFIC_C5.get(kname)
+        traffic = MEASURED_TRAFFIC_TWOLEVEL.get(kname)
     alg_per_launch = (kt["algorithmic_bytes"] / kt["stage_launches"]) if kt else None
     out = {
         "metric": METRIC,
@@ -959,7 +959,7 @@ def c5_main(args):
         calibrate_copy()
 
 
-def c4_main(args):
+def warmstart_main(args):
     """The learned warm-start protocol: one coarse 513 x 257 mesh (refined once), a drifting
     flow over 3000 steps; the networks (one per equation) are trained on the fp64 solutions of
     steps 0..1999 and every form is timed over steps 2000..2999 (held out), phi and p to 1e-8.
@@ -975,7 +975,7 @@ def c4_main(args):
     dev = torch.device("cuda:0")
     f64 = dict(dtype=torch.float64, device=dev)
     nx, ny = args.nx or 513, args.ny or 257
-    T_TRAIN, T_EVAL = args.c4_train, args.c4_eval
+    T_TRAIN, T_EVAL = args.warmstart_train, args.warmstart_eval
     coarse = ci.jittered_rect(nx, ny, 4000)
     ctx = cgp.Context(0)
     stream = torch.cuda.current_stream()
@@ -1035,7 +1035,7 @@ def c4_main(args):
     dtype_st = np.dtype([("iters", "i4"), ("ref", "i4"), ("status", "i4"), ("guess", "i4"), ("rel", "f8"),
                          ("rel0", "f8")])
     res = {}
-    for form in args.c4_forms:
+    for form in args.warmstart_forms:
         prec, guess, fdeg, fdefl = forms[form]
         rot = guess != cgp.CGP_GUESS_GIVEN
         bufs = {eq: [t.clone() for t in last[eq]] for eq in ("phi", "p")}   # steps T-3, T-2, T-1
@@ -1073,7 +1073,7 @@ def c4_main(args):
                                cgp.CGP_GUESS_LEARNED: "learned"}[guess]}
         print(json.dumps({"form": form, **{k: res[form][k] for k in ("solves_per_s", "mean_iters")}}),
               file=sys.stderr, flush=True)
-    main_form = "B" if "B" in res else args.c4_forms[0]
+    main_form = "B" if "B" in res else args.warmstart_forms[0]
     R = res[main_form]
     out = {
         "metric": METRIC, "value": R["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": T_EVAL,
@@ -1154,10 +1154,10 @@ def main():
         sys.exit(2)
     if args.cpu_worker:
         return cpu_worker(args.cpu_worker)
-    if args.workload == "c5":
-        return c5_main(args)
-    if args.workload == "c4":
-        return c4_main(args)
+    if args.workload == "twolevel":
+        return twolevel_main(args)
+    if args.workload == "warmstart":
+        return warmstart_main(args)
     if args.workload == "batch":
         if args.steps == 200:
             args.steps = 6

@@ -129,7 +129,7 @@ def test_two_level_batch_at_1025x513(ctx, cgp):
         ctx.poisson_solve([H[0]], [b[2][0]], [phi], st, precision=cgp.CGP_FP64, guess=cgp.CGP_GUESS_ZERO,
                           tol=1e-10)
         s = ctx.solve_check(1, st)[0]
-        print("c5 fp64 Jacobi", s, flush=True)
+        print("1025x513 fp64 Jacobi", s, flush=True)
         assert s["status"] == "ok" and s["rel_res"] <= 1e-10
         assert rel(phi.cpu().numpy(), xs[2]) <= 1e-8
         # the learned fp32-refined Chebyshev deflated solve of instance 0 (form B) against phi*
@@ -139,7 +139,7 @@ def test_two_level_batch_at_1025x513(ctx, cgp):
                           precision=cgp.CGP_FP32_IR, guess=cgp.CGP_GUESS_LEARNED, model=md, tol=1e-8,
                           precond_degree=6, deflation=1, refine_delta=1e-3)
         s = ctx.solve_check(1, st)[0]
-        print("c5 learned", s, flush=True)
+        print("1025x513 learned", s, flush=True)
         assert s["status"] == "ok" and s["rel_res"] <= 1e-8
         assert rel(phi.cpu().numpy(), xs[2]) <= 1e-6
         # the batch of eight from the extrapolation of the two previous sources' solutions
