@@ -79,8 +79,9 @@ enum { CGP_GUESS_ZERO = 0, CGP_GUESS_GIVEN = 1, CGP_GUESS_EXTRAP = 2, CGP_GUESS_
  *               needs an earlier uncaptured solve of the same meshes, vectors and
  *               options (CGP_E_INVALID otherwise), which built the launch records.
  *               Each workgroup owns a compact tile of at most 512 rows (recursive
- *               coordinate bisection; when that takes more than 256 tiles, 256 tiles
- *               of up to 1024 rows) and works on the rows within graph distance
+ *               coordinate bisection; when that takes more than 256 tiles, the larger
+ *               of 256 and n/1024 tiles of up to 1024 rows; more while a region does not
+ *               fit a workgroup) and works on the rows within graph distance
  *               d of it; meshes whose rows are wider than 12 entries or whose
  *               regions do not fit use STAGED_ROWS instead (Jacobi only)
  *   STAGED_ROWS as STAGED with workgroups owning consecutive row ranges (Jacobi only)
