@@ -55,7 +55,7 @@ MEASURED_TRAFFIC = {"fingerprint": "76f97e3fb1e5a8e5", "profile": "profiles/cg_t
 # The same for the batched tiled stage of the two-level workload (8 instances of the 1025x513 coarse
 # mesh, Chebyshev degree 6, deflated, fp32 with fp64 refinement), mean over the launches of a short
 # form-B run (iterations, restarts, residual stages, launches past the end).
-MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "c23888e855530f28", "profile": "profiles/cg_traffic_twolevel_batch8.md",
+MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "75264a3cba144464", "profile": "profiles/cg_traffic_twolevel_batch8.md",
                        "k_cg_tile<float, 6, true, false>": 634.16e6, "k_cg_coarse<float>": 42.23e6}
 
 
