@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
 """Benchmark of the CGP hot path on one MI355X.
 
-Workload (default): coarse 513x257 jittered P1 mesh of [0,2]x[0,1] (131841
-nodes, 262144 triangles), refined once to the 1025x513 fine mesh (525825
-nodes); a drifting 8-mode Fourier flow gives the fine velocity of each time
-step.  One *step* is one pass of the whole hot path:
+Workload (default, ``--workload twolevel``): a batch of 8 instances, each a
+coarse 1025x513 jittered P1 mesh of [0,2]x[0,1] (525825 nodes, 1048576
+triangles) refined twice to 4097x2049 (8394753 fine nodes), with its own
+drifting 8-mode Fourier flow and a Stuart number of a log-spaced sweep over
+[0.1, 10].  ``--workload sequence`` runs one coarse 513x257 mesh refined once
+(1025x513 fine) instead; the other workloads are described under --workload.
+One *step* is one pass of the whole hot path for every instance of the batch:
 
     restrict (Eq. 19) + curl source (Eq. 12) -> solve phi -> prolong phi (Eq. 20)
     -> Lorentz force (Eqs. 13-14) -> restrict + divergence source (Eq. 15)
@@ -25,8 +28,9 @@ unless --deflation 0):
     E  fp32 Jacobi-PCG with fp64 refinement from the extrapolation
     F  as B without deflation
 
-``value`` is form B's whole-job Poisson solves per second (2 solves per step)
-over the timed steps, inputs resident in HBM.  Training is a one-off set-up
+``value`` is form B's whole-job Poisson solves per second (2 solves per step
+and instance; the instances' solves batched) over the timed steps, inputs
+resident in HBM.  Training is a one-off set-up
 cost, reported beside it.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -47,9 +51,9 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "76f97e3fb1e5a8e5", "profile": "profiles/cg_traffic_513x257.md",
-                    "k_cg_tile<float, 8, true, true> degree 6 deflated": 25.69e6,
-                    "k_cg_tile<double, 8, true, true> degree 6 deflated": 42.61e6}
+MEASURED_TRAFFIC = {"fingerprint": "75264a3cba144464", "profile": "profiles/cg_traffic_513x257.md",
+                    "k_cg_tile<float, 6, true, true> degree 6 deflated": 22.95e6,
+                    "k_cg_tile<double, 6, true, true> degree 6 deflated": 37.81e6}
 
 
 # The same for the batched tiled stage of the two-level workload (8 instances of the 1025x513 coarse
@@ -61,8 +65,8 @@ MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "75264a3cba144464", "profile": "prof
 
 # HBM bytes per launch of the momentum step's two BiCGStab kernels on the 1025x513 fine mesh
 # (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled as above), valid for the recorded source.
-MEASURED_MOM_TRAFFIC = {"fingerprint": "7d5fea3bf168dc22", "profile": "profiles/momentum_1025x513.md",
-                        "k_mom_ha<7>": 159.30e6, "k_mom_hb<7>": 103.94e6}
+MEASURED_MOM_TRAFFIC = {"fingerprint": "8fed993f44ca515e", "profile": "profiles/momentum_1025x513.md",
+                        "k_mom_ha<7>": 156.87e6, "k_mom_hb<7>": 102.52e6}
 
 
 def momentum_fingerprint() -> str:
