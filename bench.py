@@ -60,7 +60,7 @@ MEASURED_TRAFFIC = {"fingerprint": "75264a3cba144464", "profile": "profiles/cg_t
 # mesh, Chebyshev degree 6, deflated, fp32 with fp64 refinement), mean over the launches of a short
 # form-B run (iterations, restarts, residual stages, launches past the end).
 MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "75264a3cba144464", "profile": "profiles/cg_traffic_twolevel_batch8.md",
-                       "k_cg_tile<float, 6, true, false>": 634.16e6, "k_cg_coarse<float>": 42.23e6}
+                       "k_cg_tile<float, 6, true, false>": 692.89e6, "k_cg_coarse<float>": 62.50e6}
 
 
 # HBM bytes per launch of the momentum step's two BiCGStab kernels on the 1025x513 fine mesh
@@ -112,9 +112,10 @@ def parse():
     ap.add_argument("--forms", default=None, help="forms to run (twolevel: ABCD, sequence: ABCDEF)")
     ap.add_argument("--deflation", type=int, default=1, choices=[0, 1], help="deflation in forms B, C, D")
     ap.add_argument("--degree", type=int, default=6, help="Chebyshev preconditioner degree of forms B, C, D, F")
-    ap.add_argument("--refine-delta", type=float, default=1e-3,
+    ap.add_argument("--refine-delta", type=float, default=0.0,
                     help="fp32 Chebyshev forms: refine when the fp32 residual fell by this factor since the last "
-                         "refinement (the Jacobi forms keep the library's default, 0.1)")
+                         "refinement (0: the library's default, 0.01 with the Chebyshev preconditioner; the Jacobi "
+                         "forms keep the library's 0.1)")
     ap.add_argument("--train-steps", type=int, default=None,
                     help="steps solved (fp64) to train the networks (twolevel: 100, sequence: 200)")
     ap.add_argument("--epochs", type=int, default=None, help="training epochs (twolevel: 6, sequence: 8)")
