@@ -283,8 +283,7 @@ InstDesc describe_instance(Mesh &m, const WorkPtrs &ws, const TilePlan *T, int k
         d.agg = T->agg;
         if (defl) {
             d.defl = 1;
-            d.kzr = T->kzr.p;
-            d.kzg = T->kzg.p;
+            d.kzk = T->kzk.p;
             d.kzv32 = T->kzv32.p;
             d.kzv = T->kzv64.p;
             d.einv = T->einv.p;

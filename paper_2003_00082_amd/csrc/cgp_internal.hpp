@@ -150,8 +150,8 @@ struct TilePlan {
     // supported for this mesh)
     int32_t defl_state = 0;
     DBuf<int8_t> oagg;        // per region entry, own rows only: 0 Dirichlet, 1 + aggregate within the tile
-    DBuf<int32_t> kzr;        // coupling record: region index of the row
-    DBuf<int32_t> kzg;        // [4] per record: aggregates (tiles) the row couples to
+    DBuf<uint64_t> kzk;       // coupling record: the region index of the row (bits 0..11) and the
+                              // KZ_PER_ROW aggregates it couples to (12 bits each from bit 12 on)
     DBuf<float> kzv32;        // [4] per record: (K Z)_{row, aggregate}
     DBuf<double> kzv64;
     DBuf<double> einv;        // [m x einv_stride(m)] (Z^T K Z)^-1, row-major, m = agg * nparts
@@ -165,7 +165,10 @@ constexpr int AGG_MAX = 8;               // aggregates a tile may carry
 constexpr int NRED = 4;                  // reduced sums of a stage: gamma, delta, sigma, r.r
 constexpr int NPART = NRED + AGG_MAX;    // partial-sum slots per workgroup (NRED + aggregate sums)
 constexpr int KZ_PER_ROW = 4;            // aggregates one row may couple to
+constexpr int KZ_BITS = 12;              // bits of a region index or aggregate in a coupling record
 constexpr int MAX_DEFL_AGGREGATES = 2048;   // the coarse step holds a row of E^-1 in 32 registers per lane
+static_assert(TILE_REGION <= (1 << KZ_BITS) && MAX_DEFL_AGGREGATES <= (1 << KZ_BITS) &&
+                  KZ_BITS * (1 + KZ_PER_ROW) <= 64, "a coupling record packs into 64 bits");
 
 // The nodal gradient of the finest level as a sparse operator: G_i = sum_j (cx_ij, cy_ij) q_j
 // (the area-weighted mean of the element gradients around node i), column-major ELL of
@@ -329,8 +332,7 @@ struct InstDesc {
     int32_t ncb;                         // workgroups of the coarse kernel for this instance
     int32_t cblk0;                       // first of them
     int32_t agg;                         // deflation aggregates per tile
-    const int32_t *kzr;
-    const int32_t *kzg;
+    const uint64_t *kzk;
     const float *kzv32;
     const double *kzv;
     const double *einv;                  // [m x einv_stride(m)], m = agg * nblk

@@ -1062,13 +1062,11 @@ __device__ inline void defl_records(DeflPrefetch<T> &f, const InstDesc &D, const
     // record kz_off + min(t, nkz): the records of the next tile, or the one past the last
     // tile's, where the thread has none (kg, kv and km are read only where kr >= 0)
     const size_t q = static_cast<size_t>(B.kz_off) + min(tid, B.nkz);
-    const int32_t kr = gld(D.kzr)[q];
-    f.kr = tid < B.nkz ? kr : -1;
-    const u32x4 g = reinterpret_cast<const CGP_GLOBAL u32x4 *>(gld(D.kzg))[q];
-    f.kg[0] = g.x;
-    f.kg[1] = g.y;
-    f.kg[2] = g.z;
-    f.kg[3] = g.w;
+    const uint64_t k = gld(D.kzk)[q];
+    constexpr uint64_t MASK = (uint64_t(1) << KZ_BITS) - 1;
+    f.kr = tid < B.nkz ? static_cast<int32_t>(k & MASK) : -1;
+#pragma unroll
+    for (int e = 0; e < KZ_PER_ROW; ++e) f.kg[e] = static_cast<uint32_t>((k >> (KZ_BITS * (1 + e))) & MASK);
     const CGP_GLOBAL T *kv = gld(kz_val<T>(D)) + q * KZ_PER_ROW;
 #pragma unroll
     for (int e = 0; e < KZ_PER_ROW; ++e) f.kv[e] = kv[e];

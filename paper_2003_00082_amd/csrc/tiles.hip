@@ -311,11 +311,11 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
     }
     // coupling records
     std::vector<TileBlk> blk = P.hblk;
-    std::vector<int32_t> kzr, kzg;
+    std::vector<uint64_t> kzk;
     std::vector<double> kzv;
     for (int t = 0; t < nt; ++t) {
         const TileBlk &B = P.hblk[t];
-        blk[t].kz_off = static_cast<int32_t>(kzr.size());
+        blk[t].kz_off = static_cast<int32_t>(kzk.size());
         for (int32_t q = 0; q < B.nreg; ++q) {
             const int32_t j = P.hreg[static_cast<size_t>(B.reg_off) + q];
             int32_t ids[16];
@@ -346,22 +346,20 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
                 }
             if (keep == 0) continue;
             if (keep > KZ_PER_ROW) return false;
-            kzr.push_back(q);
+            uint64_t rec = static_cast<uint64_t>(q);
             for (int e = 0; e < KZ_PER_ROW; ++e) {
-                kzg.push_back(e < keep ? ids[e] : A * t);
+                rec |= static_cast<uint64_t>(e < keep ? ids[e] : A * t) << (KZ_BITS * (1 + e));
                 kzv.push_back(e < keep ? sums[e] : 0.0);
             }
+            kzk.push_back(rec);
         }
-        blk[t].nkz = static_cast<int32_t>(kzr.size()) - blk[t].kz_off;
+        blk[t].nkz = static_cast<int32_t>(kzk.size()) - blk[t].kz_off;
         if (blk[t].nkz > TILE_ROWS) return false;   // one record per thread
     }
     // one record past the last tile's: every thread of the stage kernel loads record
     // kz_off + min(t, nkz) (no branch around the loads) and ignores it unless t < nkz
-    kzr.push_back(0);
-    for (int e = 0; e < KZ_PER_ROW; ++e) {
-        kzg.push_back(0);
-        kzv.push_back(0.0);
-    }
+    kzk.push_back(0);
+    for (int e = 0; e < KZ_PER_ROW; ++e) kzv.push_back(0.0);
     // E = Z^T K Z and its inverse
     std::vector<double> E(static_cast<size_t>(na) * na, 0.0);
     std::vector<int32_t> nfree(na, 0);
@@ -420,8 +418,7 @@ bool tile_deflation(hipStream_t s, Mesh &m, TilePlan &P) {
     P.hblk = blk;
     CGP_HIP(hipMemcpyAsync(P.blk.p, blk.data(), blk.size() * sizeof(TileBlk), hipMemcpyHostToDevice, s));
     h2d(s, P.oagg, oagg);
-    h2d(s, P.kzr, kzr);
-    h2d(s, P.kzg, kzg);
+    h2d(s, P.kzk, kzk);
     h2d(s, P.kzv64, kzv);
     std::vector<float> kzv32(kzv.begin(), kzv.end());
     h2d(s, P.kzv32, kzv32);
