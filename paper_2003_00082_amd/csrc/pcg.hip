@@ -1401,6 +1401,21 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     };
     load_row(a0, e0);
     if constexpr (BOTH) load_row(a1, e1);
+    // wave 1: the first 64 tiles of the workgroup's slice of the tiles' NRED partials (tiles
+    // [cb nt / ncb, (cb + 1) nt / ncb): about COARSE_ROWS / agg of them), requested behind the
+    // rows of E^-1 and summed at the end
+    const int j0 = static_cast<int>(static_cast<int64_t>(cb) * nt / C.ncb);
+    const int j1 = static_cast<int>(static_cast<int64_t>(cb + 1) * nt / C.ncb);
+    const CGP_GLOBAL double *pg = gld(C.partials) + static_cast<size_t>(par) * NPART * nt;
+    double tp[NRED] = {};
+    if (wave == 1) {
+        const int j = min(j0 + lane, j1 - 1);
+#pragma unroll
+        for (int q = 0; q < NRED; ++q) {
+            const double v = pg[q * nt + max(j, 0)];
+            tp[q] = j0 + lane < j1 ? v : 0.0;
+        }
+    }
     // a stage that found the instance finished (launches past the end of the solve) has
     // nothing for the next one; its state was stored by the stage kernel before this launch
     // (a scalar load: no wait for the loads in flight)
@@ -1454,11 +1469,10 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
         gst(C.cpart)[cb * (NRED + 1) + NRED] = t;
     }
     if (wave == 1) {
-        const int j0 = static_cast<int>(static_cast<int64_t>(cb) * nt / C.ncb);
-        const int j1 = static_cast<int>(static_cast<int64_t>(cb + 1) * nt / C.ncb);
-        const CGP_GLOBAL double *pg = gld(C.partials) + static_cast<size_t>(par) * NPART * nt;
-        double t[NRED] = {};
-        for (int j = j0 + lane; j < j1; j += 64) {
+        double t[NRED];
+#pragma unroll
+        for (int q = 0; q < NRED; ++q) t[q] = tp[q];
+        for (int j = j0 + 64 + lane; j < j1; j += 64) {   // (slices past 64 tiles)
 #pragma unroll
             for (int q = 0; q < NRED; ++q) t[q] += pg[q * nt + j];
         }
