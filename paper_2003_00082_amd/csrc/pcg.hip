@@ -1363,11 +1363,14 @@ __device__ inline const double *einv_of<double>(const CoarseRec &C) { return C.e
 template <>
 __device__ inline const float *einv_of<float>(const CoarseRec &C) { return C.einv32; }
 
-template <class E>
+// BOTH: the two rows' loads of E^-1 at once (fp32 only: registers), for the single-instance
+// step, whose few workgroups leave the compute units' wave slots free; the batched step loads a
+// row at a time, so that all of its workgroups fit the chip at once (80 registers, six
+// wavefronts per SIMD) instead of running a second, partly filled round
+template <class E, bool BOTH>
 __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
     constexpr int VE = 16 / static_cast<int>(sizeof(E));        // entries per 16-byte load
     constexpr int CH = MAX_DEFL_AGGREGATES / (64 * VE);         // loads per lane and row, at most
-    constexpr bool BOTH = sizeof(E) == 4;                       // both rows' loads at once
     __shared__ double red[COARSE_ROWS];
     __shared__ __attribute__((aligned(16))) double qs[MAX_DEFL_AGGREGATES];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1487,14 +1490,15 @@ __device__ inline void coarse_rows(const CoarseRec &C, int cb, int par) {
 
 template <class E>
 __global__ __launch_bounds__(64 * COARSE_WAVES) void k_cg_coarse1(const CoarseRec C, int par) {
-    coarse_rows<E>(C, blockIdx.x, par);
+    coarse_rows<E, sizeof(E) == 4>(C, blockIdx.x, par);
 }
 
 template <class E>
-__global__ __launch_bounds__(64 * COARSE_WAVES) void k_cg_coarse(const CoarseRec *__restrict__ recs,
+__global__ __launch_bounds__(64 * COARSE_WAVES) __attribute__((amdgpu_waves_per_eu(sizeof(E) == 4 ? 6 : 1))) void
+k_cg_coarse(const CoarseRec *__restrict__ recs,
                                                                 const int32_t *__restrict__ cblk_inst, int par) {
     const CoarseRec C = recs[cblk_inst[blockIdx.x]];
-    coarse_rows<E>(C, blockIdx.x - C.cblk0, par);
+    coarse_rows<E, false>(C, blockIdx.x - C.cblk0, par);
 }
 
 __global__ void k_fill_rwsd(int64_t n, const float *dinv32, const double *dinv, float *rwsd32, double *rwsd64) {
