@@ -258,13 +258,35 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-// v = hi + lo with hi = bf16(v), lo = bf16(v - hi)
+// v = hi + lo with hi = bf16(v), lo = bf16(v - hi), by pairs (one conversion instruction per
+// two values; the hi pair back in fp32 by a shift and a mask)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ inline void split8(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        hi[q] = to_bf16(v[q]);
-        lo[q] = to_bf16(v[q] - from_bf16(hi[q]));
+    for (int q = 0; q < 8; q += 2) {
+        const f32x2 x = {v[q], v[q + 1]};
+        const bf16x2 h = __builtin_convertvector(x, bf16x2);
+        const bf16x2 l = __builtin_convertvector(x - __builtin_convertvector(h, f32x2), bf16x2);
+        hi[q] = h[0];
+        hi[q + 1] = h[1];
+        lo[q] = l[0];
+        lo[q + 1] = l[1];
     }
+}
+
+// column c of activation row r, addressed as the buffer's base plus a 32-bit unsigned byte
+// offset (activation buffers are smaller than 4 GiB, checked on the host), so that a load or
+// store takes the kernel argument's base and one 32-bit register instead of a 64-bit pointer
+// per lane
+__device__ inline uint32_t row_off(int64_t r, int c) {
+    return (static_cast<uint32_t>(r) * GH + static_cast<uint32_t>(c)) * static_cast<uint32_t>(sizeof(float));
+}
+__device__ inline float4 ld4o(const float *base, uint32_t off) {
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
+}
+__device__ inline void st4o(float *base, uint32_t off, float4 v) {
+    *reinterpret_cast<float4 *>(reinterpret_cast<char *>(base) + off) = v;
 }
 
 template <int MODE, int NB>
@@ -340,7 +362,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int64_t ir = row0 + rg + 4 * k;
-                st4(Z + (rg + 4 * k) * ZS + c4, ld4(h + (ir < n ? ir : n) * GH + c4));
+                st4(Z + (rg + 4 * k) * ZS + c4, ld4o(h, row_off(ir < n ? ir : n, c4)));
             }
             wave_lds_sync();
             {
@@ -363,19 +385,19 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
                     nb[u] = valid ? v : static_cast<int32_t>(n);
                     deg += nb[u] != n ? 1 : 0;
                 }
+                const float inv_row = deg > 0 ? 1.0f / static_cast<float>(deg) : 0.0f;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     float4 v[NB];
 #pragma unroll
                     for (int u = 0; u < NB; ++u) {
                         const int32_t j = __shfl(nb[u], rg + 4 * k, 64);
-                        v[u] = ld4(h + static_cast<int64_t>(j) * GH + c4);
+                        v[u] = ld4o(h, row_off(j, c4));
                     }
                     float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
                     for (int u = 0; u < NB; ++u) acc = add4(acc, v[u]);
-                    const int dg = __shfl(deg, rg + 4 * k, 64);
-                    const float inv = dg > 0 ? 1.0f / static_cast<float>(dg) : 0.0f;
+                    const float inv = __shfl(inv_row, rg + 4 * k, 64);
                     st4(Z + (rg + 4 * k) * ZS + c4, make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv));
                     if (k & 1) __builtin_amdgcn_sched_barrier(0);
                 }
@@ -419,7 +441,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int64_t ir = row0 + rg + 4 * k;
-            res[k] = MODE != 0 ? ld4(A.hin + (ir < n ? ir : n) * GH + c4) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            res[k] = MODE != 0 ? ld4o(A.hin, row_off(ir < n ? ir : n, c4)) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -430,8 +452,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k
             float4 hv = make_float4(fmaxf(pre.x, 0.0f), fmaxf(pre.y, 0.0f), fmaxf(pre.z, 0.0f), fmaxf(pre.w, 0.0f));
             if constexpr (MODE != 0) hv = add4(hv, res[k]);
             if (ok) {
-                st4(A.hout + ir * GH + c4, hv);
-                if (A.aout) st4(A.aout + ir * GH + c4, pre);
+                st4o(A.hout, row_off(ir, c4), hv);
+                if (A.aout) st4o(A.aout, row_off(ir, c4), pre);
             }
             if constexpr (MODE == 2) {
                 float y = hv.x * wd.x + hv.y * wd.y + hv.z * wd.z + hv.w * wd.w;
@@ -829,6 +851,8 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     hipLaunchKernelGGL(k_gnn_prep, dim3(nb), dim3(TPB), 0, s, n, m.max_row, m.ell_col.p, m.ell_val.p, b, p1, p2,
                        w.e.p, w.d.p, w.re.p, w.kd.p, w.part.p);
     hipLaunchKernelGGL(k_gnn_scales, dim3(1), dim3(TPB), 0, s, n, w.part.p, static_cast<int>(nb), w.scales.p);
+    CGP_REQUIRE((n + 1) * GH * static_cast<int64_t>(sizeof(float)) <= static_cast<int64_t>(UINT32_MAX),
+                "mesh too large for the network's activations");
     const int64_t ngroups = ((n + 31) / 32 + FWD_WAVES - 1) / FWD_WAVES;
     const unsigned nf = static_cast<unsigned>(std::min<int64_t>(ngroups, FWD_MAX_BLOCKS));
     const float *th = md.theta.p;
