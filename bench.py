@@ -51,22 +51,22 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "75264a3cba144464", "profile": "profiles/cg_traffic_513x257.md",
-                    "k_cg_tile<float, 6, true, true> degree 6 deflated": 22.95e6,
-                    "k_cg_tile<double, 6, true, true> degree 6 deflated": 37.81e6}
+MEASURED_TRAFFIC = {"fingerprint": "b9a771f2b2644879", "profile": "profiles/cg_traffic_513x257.md",
+                    "k_cg_tile<float, 6, true, true> degree 6 deflated": 22.15e6,
+                    "k_cg_tile<double, 6, true, true> degree 6 deflated": 36.73e6}
 
 
 # The same for the batched tiled stage of the two-level workload (8 instances of the 1025x513 coarse
 # mesh, Chebyshev degree 6, deflated, fp32 with fp64 refinement), mean over the launches of a short
 # form-B run (iterations, restarts, residual stages, launches past the end).
-MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "75264a3cba144464", "profile": "profiles/cg_traffic_twolevel_batch8.md",
-                       "k_cg_tile<float, 6, true, false>": 692.89e6, "k_cg_coarse<float>": 62.50e6}
+MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "b9a771f2b2644879", "profile": "profiles/cg_traffic_twolevel_batch8.md",
+                       "k_cg_tile<float, 6, true, false>": 664.51e6, "k_cg_coarse<float>": 66.44e6}
 
 
 # HBM bytes per launch of the momentum step's two BiCGStab kernels on the 1025x513 fine mesh
 # (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled as above), valid for the recorded source.
-MEASURED_MOM_TRAFFIC = {"fingerprint": "8fed993f44ca515e", "profile": "profiles/momentum_1025x513.md",
-                        "k_mom_ha<7>": 156.87e6, "k_mom_hb<7>": 102.52e6}
+MEASURED_MOM_TRAFFIC = {"fingerprint": "4714e03e6455b16f", "profile": "profiles/momentum_1025x513.md",
+                        "k_mom_ha<7>": 155.14e6, "k_mom_hb<7>": 98.96e6}
 
 
 def momentum_fingerprint() -> str:
