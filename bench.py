@@ -51,7 +51,7 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "b9a771f2b2644879", "profile": "profiles/cg_traffic_513x257.md",
+MEASURED_TRAFFIC = {"fingerprint": "c9c368293c0704e0", "profile": "profiles/cg_traffic_513x257.md",
                     "k_cg_tile<float, 6, true, true> degree 6 deflated": 22.15e6,
                     "k_cg_tile<double, 6, true, true> degree 6 deflated": 36.73e6}
 
@@ -59,7 +59,7 @@ MEASURED_TRAFFIC = {"fingerprint": "b9a771f2b2644879", "profile": "profiles/cg_t
 # The same for the batched tiled stage of the two-level workload (8 instances of the 1025x513 coarse
 # mesh, Chebyshev degree 6, deflated, fp32 with fp64 refinement), mean over the launches of a short
 # form-B run (iterations, restarts, residual stages, launches past the end).
-MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "b9a771f2b2644879", "profile": "profiles/cg_traffic_twolevel_batch8.md",
+MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "c9c368293c0704e0", "profile": "profiles/cg_traffic_twolevel_batch8.md",
                        "k_cg_tile<float, 6, true, false>": 664.51e6, "k_cg_coarse<float>": 66.44e6}
 
 
@@ -89,9 +89,11 @@ def tile_width(tri) -> int:
 
 
 def kernel_fingerprint() -> str:
+    """Fingerprint of the sources the stage kernels' traffic depends on: the kernels, their shared
+    declarations and the tile planner that lays out the records they read."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("pcg.hip", "cgp_internal.hpp"):
+    for f in ("pcg.hip", "cgp_internal.hpp", "tiles.hip"):
         with open(os.path.join(ROOT, "paper_2003_00082_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
