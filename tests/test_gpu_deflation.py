@@ -171,3 +171,29 @@ def test_deflation_needs_the_tiled_engine(ctx, cgp, cases):
     with pytest.raises(cgp.CGPError) as ei:
         ctx.poisson_solve([c.h], [dt(c.b)], [phi], stats, tol=1e-8, deflation=2)
     assert ei.value.code == cgp.CGP_E_INVALID
+
+
+def test_more_aggregates_than_the_coarse_step_holds(ctx, cgp):
+    """A 1449x725 mesh (1050525 rows) takes more than 1024 tiles at degree 6, so more than the
+    2048 aggregates the coarse step holds: a deflated solve is refused with CGP_E_UNSUPPORTED and
+    leaves the mesh usable; the undeflated fp32-refined solve meets the tolerance on the true
+    residual, checked on the host with the oracle's matrix."""
+    m = ci.jittered_rect(1449, 725, 31)
+    a = fem.system_matrix(m.xy, m.tri, m.dirichlet)
+    u, v = ci.stream_velocity(m.xy, ci.fourier_modes(31))
+    b = fem.source(m.xy, m.tri, m.dirichlet, u, v, fem.CURL, 1.0)
+    h = ctx.mesh_upload(m.xy, m.tri, m.dirichlet, 0)
+    try:
+        phi = torch.zeros(m.n_nodes, dtype=torch.float64, device=DEV)
+        stats = cgp.stats_buffer(1)
+        kw = dict(precision=cgp.CGP_FP32_IR, guess=cgp.CGP_GUESS_ZERO, tol=1e-8, precond_degree=6)
+        with pytest.raises(cgp.CGPError) as ei:
+            ctx.poisson_solve([h], [dt(b)], [phi], stats, deflation=1, **kw)
+        assert ei.value.code == cgp.CGP_E_UNSUPPORTED
+        ctx.poisson_solve([h], [dt(b)], [phi], stats, deflation=0, **kw)
+        st = ctx.solve_check(1, stats)[0]
+        assert st["status"] == "ok" and st["rel_res"] <= 1e-8
+        x = phi.cpu().numpy()
+        assert np.linalg.norm(b - a @ x) <= 1.01e-8 * np.linalg.norm(b)
+    finally:
+        ctx.mesh_free(h)
