@@ -907,6 +907,38 @@ def twolevel_main(args):
         if one is not None:
             cpu["one_thread"] = one
 
+    # the fine-level transfer kernels (one launch per instance and call) timed between HIP events on
+    # the library's stream: the force and the velocity correction read the gradient operator (W
+    # entries of a 4-byte column and two 8-byte coefficients), the node's own potential and velocity
+    # and write two values: 20 W + 40 bytes per fine node (the neighbours' potentials counted as
+    # cache hits)
+    edges = np.unique(np.sort(np.concatenate([coarse0.tri[:, [0, 1]], coarse0.tri[:, [1, 2]],
+                                              coarse0.tri[:, [2, 0]]]), axis=1), axis=0)
+    gw = max(6, int(np.bincount(edges.ravel()).max()))   # refinement adds nodes of six neighbours
+    tr_us = {}
+    for name, call in (("lorentz_force", lambda i: ctx.lorentz_force(H[i], qf[i], vel[0][i][0], vel[0][i][1],
+                                                                     float(sig[i]), 1.0, fx[i], fy[i])),
+                       ("velocity_correct", lambda i: ctx.velocity_correct(H[i], qf[i], vel[0][i][2], vel[0][i][3],
+                                                                           1.0 / rho_dt, un[i], vn[i]))):
+        for i in range(M):
+            call(i)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            for i in range(M):
+                call(i)
+        e1.record()
+        torch.cuda.synchronize()
+        tr_us[name] = 1e3 * e0.elapsed_time(e1) / (reps * M)
+    tr_bytes = (20 * gw + 40) * nf[0]
+    tr_gbs = tr_bytes / (1e-6 * max(tr_us.values())) / 1e9
+    transfer = {"kernels": f"k_lorentz_op<{gw}>, k_velocity_op<{gw}> (one {nf[0]}-node instance per launch)",
+                "us_per_launch": tr_us, "algorithmic_bytes_per_launch": tr_bytes,
+                "bytes_model": f"20 W + 40 per fine node, W = {gw}",
+                "achieved": tr_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": tr_gbs / HBM_PEAK_GBS,
+                "timing": "HIP events around the calls on the library's stream (launch overhead included)"}
+
     tname = "float" if forms[main_form][0] == cgp.CGP_FP32_IR else "double"
     kt = R.get("kernel_timing") or {}
     kname = (f"k_cg_tile<{tname}, {tile_width(coarse0.tri)}, true, false>" if forms[main_form][2] >= 1
@@ -958,6 +990,7 @@ def twolevel_main(args):
                                     "(fp64), per refinement 12 nnz + 28 n; achieved = these bytes of the "
                                     "re-timed steps / the summed HIP-event durations of the stage kernel",
                      "iterations_per_launch": kt.get("iterations_per_launch")},
+        "transfer_roofline": transfer,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
