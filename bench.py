@@ -21,8 +21,9 @@ unless --deflation 0):
     A  plain fp64 Jacobi-PCG from the previous solution (the baseline)
     B  fp32 PCG with fp64 residual refinement, Chebyshev degree d, deflated, from
        the learned guess (one network per equation, trained on the GPU beforehand
-       on the solutions of the steps that precede the warm-up; each guess is
-       judged against the previous solution by the solver)
+       on the solutions of the steps that precede the warm-up, of every instance
+       of the batch; each guess is judged against the previous solution by the
+       solver)
     C  as B from the extrapolation 2 phi^{n-1} - phi^{n-2} instead of the network
     D  fp64 PCG, Chebyshev degree d, deflated, from the previous solution
     E  fp32 Jacobi-PCG with fp64 refinement from the extrapolation
@@ -60,7 +61,7 @@ MEASURED_TRAFFIC = {"fingerprint": "c9c368293c0704e0", "profile": "profiles/cg_t
 # mesh, Chebyshev degree 6, deflated, fp32 with fp64 refinement), mean over the launches of a short
 # form-B run (iterations, restarts, residual stages, launches past the end).
 MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "c9c368293c0704e0", "profile": "profiles/cg_traffic_twolevel_batch8.md",
-                       "k_cg_tile<float, 6, true, false>": 664.51e6, "k_cg_coarse<float>": 66.44e6}
+                       "k_cg_tile<float, 6, true, false>": 666.54e6, "k_cg_coarse<float>": 66.47e6}
 
 
 # HBM bytes per launch of the momentum step's two BiCGStab kernels on the 1025x513 fine mesh
@@ -121,6 +122,9 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=None,
                     help="steps solved (fp64) to train the networks (twolevel: 100, sequence: 200)")
     ap.add_argument("--epochs", type=int, default=None, help="training epochs (twolevel: 6, sequence: 8)")
+    ap.add_argument("--train-instances", type=int, default=8,
+                    help="twolevel: instances whose solutions train the networks (the first ones of the batch; "
+                         "default: all eight)")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workload", default="twolevel",
                     choices=["twolevel", "warmstart", "sequence", "batch", "momentum", "interpolate", "channel"],
@@ -693,43 +697,56 @@ def twolevel_main(args):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
 
-    # ---- networks for form B: fp64 solutions of instance 0 over the TR steps before the warm-up
+    # ---- networks for form B: fp64 solutions of the first TI instances over the TR steps before the
+    # warm-up (the instances' solves batched); each epoch passes over every instance's samples in
+    # turn, the optimiser's state carried from one to the next
     models, train_info = {}, None
+    TI = max(1, min(args.train_instances, M))
     if TR > 0:
         t0 = time.perf_counter()
-        sols = {"phi": [], "p": []}
-        rhs_t = {"phi": [], "p": []}
-        x = {"phi": torch.zeros(nc[0], **f64), "p": torch.zeros(nc[0], **f64)}
-        st1 = cgp.stats_buffer(1)
+        sols = {eq: [[] for _ in range(TI)] for eq in ("phi", "p")}
+        rhs_t = {eq: [[] for _ in range(TI)] for eq in ("phi", "p")}
+        x = {eq: [torch.zeros(nc[i], **f64) for i in range(TI)] for eq in ("phi", "p")}
+        stT = cgp.stats_buffer(TI)
         for n in range(-W - TR, -W):
-            u, v, ut, vt = seqs[0].at(n)
-            for eq, kind, uu, vv, sc in (("phi", cgp.CGP_SRC_CURL, u, v, 1.0),
-                                         ("p", cgp.CGP_SRC_DIV, ut, vt, rho_dt)):
-                bb = torch.empty(nc[0], **f64)
-                ctx.restrict(H[0], uu, vv, kind, sc, bb)
-                ctx.poisson_solve([H[0]], [bb], [x[eq]], st1, guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64,
+            vs = [seqs[i].at(n) for i in range(TI)]
+            for eq, kind, cu, cv, sc in (("phi", cgp.CGP_SRC_CURL, 0, 1, 1.0), ("p", cgp.CGP_SRC_DIV, 2, 3, rho_dt)):
+                bbs = [torch.empty(nc[i], **f64) for i in range(TI)]
+                for i in range(TI):
+                    ctx.restrict(H[i], vs[i][cu], vs[i][cv], kind, sc, bbs[i])
+                ctx.poisson_solve(H[:TI], bbs, x[eq], stT, guess=cgp.CGP_GUESS_GIVEN, precision=cgp.CGP_FP64,
                                   tol=1e-10, precond_degree=args.degree, deflation=1)
-                rhs_t[eq].append(bb)
-                sols[eq].append(x[eq].clone())
-            del u, v, ut, vt
+                for i in range(TI):
+                    rhs_t[eq][i].append(bbs[i])
+                    sols[eq][i].append(x[eq][i].clone())
+            del vs
         torch.cuda.synchronize()
         t_data = time.perf_counter() - t0
         t0 = time.perf_counter()
         hist = {}
         for j, eq in enumerate(("phi", "p")):
             md = ctx.model_create(seed=11 + j)
-            S, Bv = sols[eq], rhs_t[eq]
-            idx = range(2, len(S))
-            hist[eq] = ctx.model_train(md, H[0], [Bv[q] for q in idx], [S[q - 1] for q in idx],
-                                       [S[q - 2] for q in idx], [S[q] for q in idx], epochs=args.epochs,
-                                       lr=args.lr, seed=5 + j)
+
+            def train(i, epochs, seed):
+                S, Bv = sols[eq][i], rhs_t[eq][i]
+                idx = range(2, len(S))
+                return ctx.model_train(md, H[i], [Bv[q] for q in idx], [S[q - 1] for q in idx],
+                                       [S[q - 2] for q in idx], [S[q] for q in idx], epochs=epochs,
+                                       lr=args.lr, seed=seed)
+
+            if TI == 1:
+                hist[eq] = [float(h) for h in train(0, args.epochs, 5 + j)]
+            else:
+                hist[eq] = [float(np.mean([train(i, 1, 5 + j + 1000 * ep + 17 * i)[0] for i in range(TI)]))
+                            for ep in range(args.epochs)]
             models[eq] = md
         torch.cuda.synchronize()
-        train_info = {"train_steps": TR, "samples_per_network": TR - 2, "trained_on": "instance 0",
+        train_info = {"train_steps": TR, "samples_per_network": TI * (TR - 2),
+                      "trained_on": f"instances 0..{TI - 1}" if TI > 1 else "instance 0",
                       "epochs": args.epochs, "lr": args.lr, "data_s": t_data,
                       "train_s": time.perf_counter() - t0,
-                      "loss_first_epoch": {k: float(v[0]) for k, v in hist.items()},
-                      "loss_last_epoch": {k: float(v[-1]) for k, v in hist.items()}}
+                      "loss_first_epoch": {k: v[0] for k, v in hist.items()},
+                      "loss_last_epoch": {k: v[-1] for k, v in hist.items()}}
         del sols, rhs_t
 
     deg = args.degree
