@@ -54,6 +54,7 @@ struct GnnWork {
     DBuf<float> y;                // [n]
     DBuf<float> dy, dh, dhp, dm;  // training
     DBuf<float> gpart;            // per-workgroup gradient partials
+    DBuf<float> gred;             // their sums over RED_CHUNKS ranges of workgroups
     DBuf<float> grad;             // [P_COUNT]
     DBuf<double> lpart;
 };
@@ -774,6 +775,21 @@ __global__ __launch_bounds__(TPB) void k_gnn_reduce(const float *gpart, int nblk
     grad[off + p] = t;
 }
 
+// the same sum in two passes when there are many blocks: range c of the blocks ([c nblk / RED_CHUNKS,
+// (c + 1) nblk / RED_CHUNKS), in order) by workgroup row c, then the RED_CHUNKS range sums in order
+// by k_gnn_reduce; a fixed order either way, with RED_CHUNKS times the workgroups streaming the partials
+constexpr int RED_CHUNKS = 32;
+__global__ __launch_bounds__(TPB) void k_gnn_reduce_chunks(const float *gpart, int nblk, int stride, int count,
+                                                           float *part) {
+    const int p = blockIdx.x * TPB + threadIdx.x, c = blockIdx.y;
+    if (p >= count) return;
+    const int b0 = static_cast<int>(static_cast<int64_t>(c) * nblk / RED_CHUNKS);
+    const int b1 = static_cast<int>(static_cast<int64_t>(c + 1) * nblk / RED_CHUNKS);
+    float t = 0.0f;
+    for (int b = b0; b < b1; ++b) t += gpart[static_cast<int64_t>(b) * stride + p];
+    part[static_cast<int64_t>(c) * count + p] = t;
+}
+
 // Adam on the fp32 master weights, then the bf16 copies of the matrices
 __global__ __launch_bounds__(TPB) void k_gnn_adam(float *theta, float *m1, float *m2, const float *grad, float lr,
                                                   float b1, float b2, float c1, float c2, float eps) {
@@ -838,6 +854,7 @@ GnnWork &work_for(hipStream_t s, Model &md, const Mesh &m, bool training) {
         const int64_t nbw = (n + BW_SUB * TM - 1) / (BW_SUB * TM);
         w.gpart.alloc(std::max<int64_t>(nbw * (2 * GH * GH + GH), blocks_for(n, TPB) * (GH + 1)));
         w.grad.alloc(P_COUNT);
+        w.gred.alloc(static_cast<size_t>(RED_CHUNKS) * (2 * GH * GH + GH));
         w.lpart.alloc(blocks_for(n, TPB));
     }
     return w;
@@ -936,6 +953,19 @@ double count_free(hipStream_t s, const Mesh &m) {
     return f > 0.0 ? f : 1.0;
 }
 
+// w.grad[off + p] = the fixed-order sum of the nblk partials of gradient entry p
+void reduce_grad(hipStream_t s, GnnWork &w, int nblk, int stride, int count, int off) {
+    if (nblk <= 2 * RED_CHUNKS) {
+        hipLaunchKernelGGL(k_gnn_reduce, dim3(blocks_for(count, TPB)), dim3(TPB), 0, s, w.gpart.p, nblk, stride, count,
+                           w.grad.p, off);
+        return;
+    }
+    hipLaunchKernelGGL(k_gnn_reduce_chunks, dim3(blocks_for(count, TPB), RED_CHUNKS), dim3(TPB), 0, s, w.gpart.p, nblk,
+                       stride, count, w.gred.p);
+    hipLaunchKernelGGL(k_gnn_reduce, dim3(blocks_for(count, TPB)), dim3(TPB), 0, s, w.gred.p, RED_CHUNKS, count, count,
+                       w.grad.p, off);
+}
+
 // one sample: forward, loss (added to *loss_dev), gradient into w.grad
 void loss_grad(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *b, const double *p1,
                const double *p2, const double *target, double nfree, double *loss_dev) {
@@ -950,22 +980,19 @@ void loss_grad(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double
     // decoder
     hipLaunchKernelGGL(k_gnn_dec_bwd, dim3(nb), dim3(TPB), 0, s, n, w.dy.p, w.h[GL].p, md.theta.p, w.dh.p,
                        w.gpart.p);
-    hipLaunchKernelGGL(k_gnn_reduce, dim3(1), dim3(TPB), 0, s, w.gpart.p, static_cast<int>(nb), GH + 1, GH + 1,
-                       w.grad.p, P_WD);
+    reduce_grad(s, w, static_cast<int>(nb), GH + 1, GH + 1, P_WD);
     const unsigned nbw = static_cast<unsigned>((n + BW_SUB * TM - 1) / (BW_SUB * TM));
     const int lstride = 2 * GH * GH + GH;
     for (int l = GL; l >= 1; --l) {
         hipLaunchKernelGGL(k_gnn_layer_bwd, dim3(nbw), dim3(TPB), 0, s, n, w.h[l - 1].p, m.adj_ptr.p, m.adj_col.p,
                            md.wq.p + GFP * GH + (l - 1) * 2 * GH * GH, w.a[l].p, w.dh.p, w.dhp.p, w.dm.p,
                            w.gpart.p);
-        hipLaunchKernelGGL(k_gnn_reduce, dim3(blocks_for(lstride, TPB)), dim3(TPB), 0, s, w.gpart.p,
-                           static_cast<int>(nbw), lstride, lstride, w.grad.p, P_L0 + (l - 1) * P_LSTRIDE);
+        reduce_grad(s, w, static_cast<int>(nbw), lstride, lstride, P_L0 + (l - 1) * P_LSTRIDE);
         hipLaunchKernelGGL(k_gnn_agg_bwd, dim3(blocks_for(n * (GH / 8), TPB)), dim3(TPB), 0, s, n, m.adj_ptr.p,
                            m.adj_col.p, w.dhp.p, w.dm.p, w.dh.p);
     }
     hipLaunchKernelGGL(k_gnn_enc_bwd, dim3(nbw), dim3(TPB), 0, s, n, w.x.p, w.a[0].p, w.dh.p, w.gpart.p);
-    hipLaunchKernelGGL(k_gnn_reduce, dim3(blocks_for(GFP * GH + GH, TPB)), dim3(TPB), 0, s, w.gpart.p,
-                       static_cast<int>(nbw), GFP * GH + GH, GFP * GH + GH, w.grad.p, P_W0);
+    reduce_grad(s, w, static_cast<int>(nbw), GFP * GH + GH, GFP * GH + GH, P_W0);
     CGP_HIP(hipGetLastError());
 }
 
