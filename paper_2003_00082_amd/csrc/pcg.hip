@@ -86,10 +86,8 @@ __device__ __forceinline__ T cld_record(const T *p) {
 
 enum State : int32_t {
     ST_BOOT = 0,  // before the first stage
-    ST_PREP,      // x = initial guess (ZERO / EXTRAP)
     ST_JUDGE,     // LEARNED: energy-norm comparison of the network guess with prev1
-    ST_PICK,      // LEARNED rejected: x = prev1
-    ST_RES,       // r = b - K x (fp64)
+    ST_RES,       // r = b - K x (fp64); the first one also stores the initial x
     ST_START,     // u = M^-1 r, w = K u, reductions gamma, delta, sigma
     ST_ITER,      // one CG iteration
     ST_FOLD,      // mixed, last stage: x += c, c = 0 (refinements fold c at START)
@@ -170,11 +168,7 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
         c.first = 1;
         c.gamma = c.alpha = c.beta = c.pap = 0.0;
         c.bnorm = c.rmax = c.rel_res = c.rel_res_guess = 0.0;
-        c.state = guess == CGP_GUESS_LEARNED ? ST_JUDGE : (guess == CGP_GUESS_GIVEN ? ST_RES : ST_PREP);
-        break;
-    case ST_PREP:
-    case ST_PICK:
-        c.state = ST_RES;
+        c.state = guess == CGP_GUESS_LEARNED ? ST_JUDGE : ST_RES;
         break;
     case ST_JUDGE: {
         const double rl = S[0], rp = S[1], gain = S[3];
@@ -183,10 +177,10 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
             c.guess_used = CGP_GUESS_LEARNED;
             c.rel_res_guess = sqrt(rl) / bn;
             c.state = ST_RES;
-        } else {
+        } else {   // the first residual stage starts from prev1 instead
             c.guess_used = CGP_GUESS_GIVEN;
             c.rel_res_guess = sqrt(rp) / bn;
-            c.state = ST_PICK;
+            c.state = ST_RES;
         }
         break;
     }
@@ -296,6 +290,23 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
         break;
     }
     return c;
+}
+
+// The iterate a solve's first residual stage starts from, which that stage also stores in x
+// for its rows: zero, the extrapolation 2 prev1 - prev2, prev1 (a network guess the judge
+// rejected), or x as the caller or the network left it.  The stage reads it from its source,
+// never from x, so the rows of other workgroups are never read while they are written.
+enum FirstIterate : int { X0_AS_IS = 0, X0_ZERO, X0_EXTRAP, X0_PREV1 };
+__device__ inline int first_iterate(const Ctl &c, int guess) {
+    if (!c.first) return X0_AS_IS;
+    if (guess == CGP_GUESS_ZERO) return X0_ZERO;
+    if (guess == CGP_GUESS_EXTRAP) return X0_EXTRAP;
+    if (guess == CGP_GUESS_LEARNED && c.guess_used != CGP_GUESS_LEARNED) return X0_PREV1;
+    return X0_AS_IS;
+}
+template <class PX, class PP>
+__device__ inline double first_x(int src, PX x, PP p1, PP p2, int64_t j) {
+    return src == X0_ZERO ? 0.0 : src == X0_EXTRAP ? 2.0 * p1[j] - p2[j] : src == X0_PREV1 ? p1[j] : x[j];
 }
 
 // ------------------------------------------------------------------ stage work
@@ -424,13 +435,6 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
     };
 
     switch (c.state) {
-    case ST_PREP:
-        for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK)
-            x[i] = (D.guess == CGP_GUESS_EXTRAP) ? 2.0 * D.prev1[i] - D.prev2[i] : 0.0;
-        break;
-    case ST_PICK:
-        for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) x[i] = D.prev1[i];
-        break;
     case ST_ZEROX:
         for (int32_t i = R.r0 + threadIdx.x; i < R.r1; i += BLOCK) x[i] = 0.0;
         break;
@@ -462,25 +466,32 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
     }
     case ST_RES: {
         const bool first = c.first;
+        const int src = first_iterate(c, D.guess);
+        const double *p1 = D.prev1, *p2 = D.prev2;
         if (mixed) {
             // after the first, the iterate is x + c (c: the fp32 correction since the last START)
             float *r32 = D.r32 + wr * n;
             float *c32 = D.c32;
             staged_product<ELL, double>(R, staged64, lanes, A64, lds64,
-                                   [&](int32_t j) { return first ? x[j] : x[j] + static_cast<double>(c32[j]); },
-                                   nop, [&](int32_t i, double y, double) {
+                                   [&](int32_t j) {
+                                       return first ? first_x(src, x, p1, p2, j) : x[j] + static_cast<double>(c32[j]);
+                                   },
+                                   nop, [&](int32_t i, double y, double xi) {
                                        const double ri = b[i] - y;
                                        r32[i] = static_cast<float>(ri);
                                        if (first) c32[i] = 0.0f;
+                                       if (src != X0_AS_IS) x[i] = xi;
                                        v[0] += ri * ri;
                                        if (first) v[1] += b[i] * b[i];
                                    });
         } else {
             double *r = D.r + wr * n;
             staged_product<ELL, double>(R, staged64, lanes, A64, lds64,
-                                   [&](int32_t j) { return x[j]; }, nop, [&](int32_t i, double y, double) {
+                                   [&](int32_t j) { return first_x(src, x, p1, p2, j); },
+                                   nop, [&](int32_t i, double y, double xi) {
                                        const double ri = b[i] - y;
                                        r[i] = ri;
+                                       if (src != X0_AS_IS) x[i] = xi;
                                        v[0] += ri * ri;
                                        if (first) v[1] += b[i] * b[i];
                                    });
@@ -751,15 +762,20 @@ __device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolvePa
 }
 
 // What workgroup 0 of an instance does after a transition (one thread): carry the state
-// forward and, when the instance finished, write its stats and report completion.
+// forward and, when the instance finished, write its stats and report completion.  A stage
+// whose successor is the end whatever it sums (the fold of a mixed solve, x = 0 for b = 0)
+// is the instance's last: this launch does its work and carries the end forward, so no
+// further launch is needed to find it.
 __device__ inline void stage_bookkeeping(const InstDesc &D, int par, const Ctl &prev, const Ctl &c,
                                          const SolveParams &prm, int32_t *done_count, int32_t *host_flag) {
-    D.ctl[par] = c;   // carried forward every launch, DONE included
-    if (c.state == ST_DONE && prev.state != ST_DONE) {
-        write_stats(c, prm, D.stats_index);
+    const double none[NRED + 1] = {};
+    const Ctl out = (c.state == ST_FOLD || c.state == ST_ZEROX) ? transition(c, none, prm, D.guess) : c;
+    D.ctl[par] = out;   // carried forward every launch, DONE included
+    if (out.state == ST_DONE && prev.state != ST_DONE) {
+        write_stats(out, prm, D.stats_index);
         // the last instance to finish reports the launches it needed, then completion
         if (atomicAdd(done_count, 1) == prm.n_inst - 1) {
-            __hip_atomic_store(host_flag + 1, c.stages, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(host_flag + 1, out.stages, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             __hip_atomic_store(host_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
@@ -1221,11 +1237,14 @@ __device__ inline void tile_res_row(const Ctl &c, const InstDesc &D, int32_t own
     const CGP_GLOBAL double *val = gld(D.val), *x = gld(D.x);
     const CGP_GLOBAL float *cc = gld(D.c32);
     const bool with_c = mixed && !c.first;   // the iterate is x + c after the first residual
+    const int src = first_iterate(c, D.guess);
+    const CGP_GLOBAL double *p1 = gld(D.prev1), *p2 = gld(D.prev2);
     double kx = 0.0;
     for (int32_t k = rowptr[own]; k < rowptr[own + 1]; ++k) {
         const int32_t j = col[k];
-        kx += val[k] * (with_c ? x[j] + static_cast<double>(cc[j]) : x[j]);
+        kx += val[k] * (with_c ? x[j] + static_cast<double>(cc[j]) : first_x(src, x, p1, p2, j));
     }
+    if (src != X0_AS_IS) gst(D.x)[own] = first_x(src, x, p1, p2, own);
     const double bi = gld(D.b)[own], ri = bi - kx;
     if (mixed) {
         CGP_GLOBAL float *q = gst(D.rwsd32);
@@ -1267,6 +1286,14 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     const int lb = xcd_block(blockIdx.x - D.blk0, D.nblk);
     const TileBlk B = D.tblk[lb];
     const int rd = par ^ 1;
+    // an instance that finished before this launch (the launches that run past the end of a
+    // batch's slowest instance): workgroup 0 carries its state forward, and nothing is
+    // prefetched.  The state arrives through a scalar load beside the tile's record, which the
+    // prefetch waits for anyway.
+    if (cld(&D.ctl[rd].state)[0] == ST_DONE) {
+        if (lb == 0 && threadIdx.x == 0) D.ctl[par] = cld_record(D.ctl + rd);
+        return;
+    }
     // speculative loads for an iteration, in flight while the state is decoded
     constexpr bool defl = DEFL;
     DeflPrefetch<T> df;
