@@ -473,6 +473,72 @@ def test_chebyshev_guess_modes_and_batches(ctx, cgp, cheb_cases, names):
         assert all(st["iters"] == 0 for st in ctx.solve_check(len(hs), stats))
 
 
+EARLY_END_CONFIGS = ["fp64_jacobi_rows", "fp64_jacobi_persistent", "fp64_cheb6", "fp32ir_cheb6",
+                     "fp32ir_cheb6_deflated"]
+
+
+def _early_end_kw(cgp, cfg):
+    return {"fp64_jacobi_rows": dict(precision=cgp.CGP_FP64, tol=1e-10, engine=cgp.CGP_ENGINE_STAGED_ROWS),
+            "fp64_jacobi_persistent": dict(precision=cgp.CGP_FP64, tol=1e-10, engine=cgp.CGP_ENGINE_PERSISTENT),
+            "fp64_cheb6": dict(precision=cgp.CGP_FP64, tol=1e-10, precond_degree=6),
+            "fp32ir_cheb6": dict(precision=cgp.CGP_FP32_IR, tol=1e-8, precond_degree=6),
+            "fp32ir_cheb6_deflated": dict(precision=cgp.CGP_FP32_IR, tol=1e-8, precond_degree=6,
+                                          deflation=1)}[cfg]
+
+
+@pytest.mark.parametrize("cfg", EARLY_END_CONFIGS)
+def test_batch_members_that_end_at_their_first_residual(ctx, cgp, cheb_cases, cfg):
+    """A batch with a member whose b = 0 (started from ones, x must come back zero) and one
+    started from its exact solution (nothing to iterate), beside a member that iterates: the first
+    two end at their first residual stage and the launches after it find them finished, while the
+    third solves to the tolerance in the iterations it takes alone."""
+    kw = _early_end_kw(cgp, cfg)
+    bound = 1e-8 if kw["precision"] == cgp.CGP_FP64 else 1e-6
+    names = ["rect_33x17", "rect_129x65", "hole_41x21"]
+    hs = [cheb_cases[k][3] for k in names]
+    _, a1, b1, _ = cheb_cases[names[1]]
+    _, a2, b2, _ = cheb_cases[names[2]]
+    ref1, ref2 = solve.direct(a1, b1), solve.direct(a2, b2)
+    n0 = cheb_cases[names[0]][0].n_nodes
+    bs = [dt(np.zeros(n0)), dt(b1), dt(b2)]
+    xs = [dt(np.ones(n0)), torch.zeros_like(bs[1]), dt(ref2)]
+    stats = cgp.stats_buffer(3)
+    ctx.poisson_solve(hs, bs, xs, stats, guess=cgp.CGP_GUESS_GIVEN, **kw)
+    s0, s1, s2 = ctx.solve_check(3, stats)
+    assert s0["status"] == "ok" and s0["iters"] == 0 and not xs[0].cpu().numpy().any(), s0
+    assert s2["status"] == "ok" and s2["iters"] == 0, s2
+    np.testing.assert_array_equal(xs[2].cpu().numpy(), ref2)
+    x1 = xs[1].cpu().numpy()
+    assert s1["status"] == "ok" and s1["iters"] > 0, s1
+    assert np.linalg.norm(x1 - ref1) / np.linalg.norm(ref1) <= bound
+    _, solo = _solve(ctx, cgp, hs[1], b1, x0=np.zeros_like(b1), **kw)
+    assert abs(s1["iters"] - solo["iters"]) <= 1, (s1, solo)
+
+
+@pytest.mark.parametrize("cfg", EARLY_END_CONFIGS)
+def test_initial_iterate_ignores_what_x_holds(ctx, cgp, cheb_cases, cfg):
+    """With a zero or extrapolated start the solve takes its initial iterate from the guess's
+    source, not from x: the same batch started with x full of ones or of zeros gives the same bits
+    and the same statistics."""
+    kw = _early_end_kw(cgp, cfg)
+    names = ["rect_33x17", "rect_129x65", "hole_41x21"]
+    hs = [cheb_cases[k][3] for k in names]
+    bs = [dt(cheb_cases[k][2]) for k in names]
+    prev = [dt(0.5 * solve.direct(cheb_cases[k][1], cheb_cases[k][2])) for k in names]
+    for guess, extra in ((cgp.CGP_GUESS_ZERO, {}), (cgp.CGP_GUESS_EXTRAP, dict(prev1=prev, prev2=prev))):
+        runs = []
+        for fill in (1.0, 0.0):
+            xs = [torch.full_like(b, fill) for b in bs]
+            stats = cgp.stats_buffer(3)
+            ctx.poisson_solve(hs, bs, xs, stats, guess=guess, **extra, **kw)
+            runs.append(([x.cpu().numpy() for x in xs], ctx.solve_check(3, stats)))
+        (xa, sa), (xb, sb) = runs
+        assert all(s["status"] == "ok" for s in sa), sa
+        assert sa == sb
+        for p, q in zip(xa, xb):
+            np.testing.assert_array_equal(p, q)
+
+
 def test_chebyshev_edge_cases(ctx, cgp, c1):
     n = c1.m.n_nodes
     x, st = _solve(ctx, cgp, c1.handle, np.zeros(n), x0=np.ones(n), precond_degree=5)
