@@ -233,7 +233,6 @@ struct FwdArgs {
 };
 
 constexpr int FWD_WAVES = TPB / 64;
-constexpr int FWD_MAX_BLOCKS = 2048;
 constexpr int ZS = GH + 4;   // padded row of a wavefront's 32 x 64 LDS tile (floats)
 
 __device__ inline bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
@@ -871,7 +870,9 @@ void forward(hipStream_t s, Model &md, const Mesh &m, GnnWork &w, const double *
     CGP_REQUIRE((n + 1) * GH * static_cast<int64_t>(sizeof(float)) <= static_cast<int64_t>(UINT32_MAX),
                 "mesh too large for the network's activations");
     const int64_t ngroups = ((n + 31) / 32 + FWD_WAVES - 1) / FWD_WAVES;
-    const unsigned nf = static_cast<unsigned>(std::min<int64_t>(ngroups, FWD_MAX_BLOCKS));
+    // one workgroup per group of tiles (capping the grid at 2048 workgroups of about two groups
+    // each, to load the weights into LDS fewer times, measured 3 % slower at 525825 rows)
+    const unsigned nf = static_cast<unsigned>(ngroups);
     const float *th = md.theta.p;
     FwdArgs A{};
     A.n = n;
