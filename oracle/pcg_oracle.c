@@ -199,12 +199,22 @@ done:
  * fp32 loop accumulates a correction c.  The fp32 recurrence residual r32 is
  * replaced by fl32(b - K x) (computed in fp64 after x += c) whenever ||r32||
  * has dropped below delta times its value at the previous refinement step, or
- * below the final tolerance.  The search direction p is kept across a
+ * below the final tolerance.  A phase whose refinement point delta * s would
+ * leave a short last phase (the tolerance within a factor delta^(1/4) of that
+ * point) runs to the tolerance instead: refining there would cost a true
+ * residual and a restart for a fraction of a phase.  The search direction p is kept across a
  * refinement step, so the Krylov information is not lost.  Convergence is
  * decided only on the true fp64 residual ||b - K x|| <= tol ||b||.  The inner
  * matrix (fl32 of K) and vectors are fp32; every dot product accumulates the
  * fp32 products in fp64.
  */
+/* The value a refinement phase starting at true residual s measures its fall
+ * against: s, or 0 (no refinement point, only the tolerance) when the point
+ * delta * s is within a factor delta^(1/4) of the tolerance. */
+static double phase_start(double s, double delta, double tol, double bnorm) {
+    return delta * sqrt(sqrt(delta)) * s <= tol * bnorm ? 0.0 : s;
+}
+
 int oracle_pcg_mixed(int n, const int *rowptr, const int *col, const double *val,
                      const double *dinv, int deg, double lo, double hi, const double *b, double *x,
                      double tol, double delta, int max_iter, int *iters_out, int *updates_out,
@@ -228,7 +238,7 @@ int oracle_pcg_mixed(int n, const int *rowptr, const int *col, const double *val
     s = residual64(n, rowptr, col, val, b, x, r);
     if (!isfinite(s)) { status = ORACLE_BREAKDOWN; goto done; }
     if (s <= tol * bnorm) { status = ORACLE_OK; goto done; }
-    double rho = 0.0, rmax = s;
+    double rho = 0.0, rmax = phase_start(s, delta, tol, bnorm);
     for (int i = 0; i < n; ++i) {
         r32[i] = (float)r[i];
         c[i] = 0.0f;
@@ -269,7 +279,7 @@ int oracle_pcg_mixed(int n, const int *rowptr, const int *col, const double *val
             if (!isfinite(s)) { status = ORACLE_BREAKDOWN; goto done; }
             if (s <= tol * bnorm) { status = ORACLE_OK; goto done; }
             for (int i = 0; i < n; ++i) r32[i] = (float)r[i];
-            rmax = s;
+            rmax = phase_start(s, delta, tol, bnorm);
         }
         double rho_new = 0.0;
         precond32(n, rowptr, col, v32, di32, deg, lo, hi, r32, z, w1, w2, w3);

@@ -222,7 +222,10 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
         // fp64: a failed verification restarts CG; mixed: a replaced residual keeps p and s
         c.restart = (c.first || !mixed) ? 1 : 0;
         c.first = 0;
-        c.rmax = rn;
+        // the phase's refinement point delta rn, unless the phase after it would be short (the
+        // tolerance within a factor delta^(1/4) of that point: half a decade at delta = 0.01):
+        // then this phase runs to the tolerance (rmax = 0 leaves only the stopping test)
+        c.rmax = (mixed && prm.delta * sqrt(sqrt(prm.delta)) * rn <= tol * c.bnorm) ? 0.0 : rn;
         c.state = ST_START;
         break;
     }

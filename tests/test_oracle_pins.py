@@ -247,6 +247,32 @@ def test_pcg_matches_a_dense_factorisation_on_the_small_mesh():
     assert np.linalg.norm(xm - x_direct) / np.linalg.norm(x_direct) <= 1e-7
 
 
+def _start_at_relative_residual(a, b, free, rel, seed):
+    """x* plus a random free-node perturbation scaled so that ||b - K x0|| = rel ||b||."""
+    xs = np.linalg.solve(a.toarray(), b)
+    y = np.random.default_rng(seed).standard_normal(b.shape[0]) * free
+    return xs + y * (rel * np.linalg.norm(b) / np.linalg.norm(a @ y)), xs
+
+
+@pytest.mark.parametrize("rel, phases", [(1.66e-2, 3), (2.0e-3, 3), (6.0e-2, 4)])
+def test_mixed_refinement_runs_a_short_last_phase_into_the_previous_one(rel, phases):
+    """fp32 PCG refined every two decades (delta = 0.01) to 1e-8 from a start at relative residual
+    rel.  From 1.66e-2 the phases end near 1.66e-4 and 1.66e-6; the third one's refinement point
+    1.66e-8 is within half a decade of the tolerance, so that phase runs to it: three true
+    residuals after the start (where refining at every point would take four).  From 2e-3 the third
+    phase reaches the tolerance before its point 2e-9 anyway (three); from 6e-2 the third point
+    6e-8 is more than half a decade above it, so a fourth, short phase follows (four).  Each start
+    solves to the tolerance."""
+    m, a = _c1_system()
+    free = ~m.dirichlet.astype(bool)
+    b = np.random.default_rng(11).standard_normal(m.n_nodes) * free
+    x0, xs = _start_at_relative_residual(a, b, free, rel, seed=12)
+    x, info = solve.pcg_mixed(a, b, x0=x0, tol=1e-8, delta=0.01)
+    assert info["status"] == "ok" and info["rel_res"] <= 1e-8
+    assert info["updates"] == phases, info
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-6
+
+
 def test_pcg_recovers_discrete_sine_modes_in_as_many_steps_as_modes():
     """Unjittered grid: K v_pq = lambda_pq v_pq with lambda = 4 - 2cos(p pi/(nx-1)) - 2cos(q pi/(ny-1))."""
     nx, ny = 33, 17
