@@ -36,6 +36,7 @@ struct Plan {
     int cgrid = 0;                   // deflation: coarse-kernel workgroups
     int grid = 0;
     int n_inst = 0;
+    int unb = 0;                     // workgroups per instance when all instances have as many, else 0
     int halo = 0;                    // widest column range of a workgroup
     hipGraph_t graph = nullptr;      // staged driver: `launches` stage launches
     hipGraphExec_t exec = nullptr;
@@ -855,6 +856,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 p->d_prm = reinterpret_cast<SolveParams *>(p->buf.p + off_prm);
                 p->grid = used;
                 p->n_inst = gn;
+                p->unb = std::all_of(nb.begin(), nb.end(), [&](int32_t v) { return v == nb[0]; }) ? nb[0] : 0;
                 launch_ranges(ctx->aux, p->d_insts, p->d_block_inst, used, p->d_ranges);
                 std::vector<RowRange> hr(used);
                 CGP_HIP(hipMemcpyAsync(hr.data(), p->d_ranges, sizeof(RowRange) * used, hipMemcpyDeviceToHost,
@@ -890,7 +892,7 @@ cgp_status cgp_poisson_solve(cgp_ctx ctx, int32_t n_inst, const cgp_mesh *h_mesh
                 auto evs = [&](int k) { return ev ? KernelEvents{ev[2 * k], ev[2 * k + 1]} : KernelEvents{}; };
                 for (int64_t l = 0; l < count; ++l) {
                     if (tiled) {
-                        launch_cg_tile(st, o.precision == CGP_FP32_IR, kwidth, defl, gn, plan->d_insts,
+                        launch_cg_tile(st, o.precision == CGP_FP32_IR, kwidth, defl, plan->unb, plan->d_insts,
                                        gn == 1 ? &plan->one : nullptr,
                                        plan->d_block_inst, plan->d_ranges, plan->grid, plan->d_prm,
                                        static_cast<int>(l & 1), plan->d_done, done_flag, evs(kps * l));
@@ -1195,7 +1197,7 @@ cgp_status cgp_poisson_solve_noalloc(cgp_ctx ctx, cgp_mesh mesh, const double *d
             if (issued >= max_stages + 2 * launches) throw Error{CGP_E_ABORTED, "staged solve did not terminate"};
             for (int l = 0; l < launches; ++l) {
                 if (tiled) {
-                    launch_cg_tile(st, mixed, T->kwidth, defl, 1, d_insts, &d, d_bi, d_rng, nblk, d_prm, l & 1, d_done,
+                    launch_cg_tile(st, mixed, T->kwidth, defl, 0, d_insts, &d, d_bi, d_rng, nblk, d_prm, l & 1, d_done,
                                    ctx->host_flag_dev);
                     if (defl) launch_cg_coarse(st, mixed, &cr, d_crec, d_cbi, ncb, l & 1);
                 } else {

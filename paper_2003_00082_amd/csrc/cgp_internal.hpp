@@ -382,7 +382,9 @@ struct KernelEvents {
 void launch_cg_step(hipStream_t s, bool mixed, int halo, int n_inst, const InstDesc *d_insts, const InstDesc *h_one,
                     const int32_t *d_block_inst, const RowRange *d_ranges, int grid, const SolveParams *d_prm,
                     int par, int32_t *d_done, int32_t *d_host_flag, KernelEvents ev = {});
-void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst, const InstDesc *d_insts,
+// unb: the workgroups of each instance when all instances have that many (the stage kernel then
+// finds its instance without reading d_block_inst), else 0
+void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int unb, const InstDesc *d_insts,
                     const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
                     const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag, KernelEvents ev = {});
 // the coarse step of deflation after a tiled stage launch: mu = E^-1 (aggregate sums), c partials

@@ -1279,13 +1279,15 @@ __device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &
 template <class T, int W, bool DEFL, bool ONE>
 __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const InstDesc *__restrict__ insts,
                                                    const InstDesc one, const int32_t *__restrict__ block_inst,
-                                                   int n_inst, const RowRange *__restrict__ ranges,
+                                                   int unb, const RowRange *__restrict__ ranges,
                                                    const SolveParams *__restrict__ prm_dev, int par,
                                                    int32_t *done_count, int32_t *host_flag) {
     __shared__ Shared sh;
     __shared__ int32_t s_nt[TILE_MAX_DEGREE + 2];
     __shared__ double s_cheb[2 * TILE_MAX_DEGREE];
-    const InstDesc &D = ONE ? one : insts[block_inst[blockIdx.x]];
+    // unb > 0: every instance has unb workgroups, and the instance follows from the workgroup
+    // index (one dependent load less before the tile's record and its prefetch)
+    const InstDesc &D = ONE ? one : insts[unb > 0 ? static_cast<int>(blockIdx.x) / unb : block_inst[blockIdx.x]];
     const int lb = xcd_block(blockIdx.x - D.blk0, D.nblk);
     const TileBlk B = D.tblk[lb];
     const int rd = par ^ 1;
@@ -1750,7 +1752,7 @@ void launch_fill_rwsd(hipStream_t s, int64_t n, const float *dinv32, const doubl
             hipLaunchKernelGGL(K, G, B, 0, S, __VA_ARGS__);                                             \
     } while (0)
 
-void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst, const InstDesc *d_insts,
+void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int unb, const InstDesc *d_insts,
                     const InstDesc *h_one, const int32_t *d_block_inst, const RowRange *d_ranges, int grid,
                     const SolveParams *d_prm, int par, int32_t *d_done, int32_t *d_host_flag, KernelEvents ev) {
     const InstDesc none{};
@@ -1758,10 +1760,10 @@ void launch_cg_tile(hipStream_t s, bool mixed, int width, bool defl, int n_inst,
     do {                                                                                                           \
         if (h_one)                                                                                                 \
             CGP_LAUNCH((k_cg_tile<T, W, F, true>), dim3(grid), dim3(BLOCK), s, ev, d_insts, *h_one, d_block_inst,  \
-                       n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                                        \
+                       0, d_ranges, d_prm, par, d_done, d_host_flag);                                             \
         else                                                                                                       \
             CGP_LAUNCH((k_cg_tile<T, W, F, false>), dim3(grid), dim3(BLOCK), s, ev, d_insts, none, d_block_inst,   \
-                       n_inst, d_ranges, d_prm, par, d_done, d_host_flag);                                        \
+                       unb, d_ranges, d_prm, par, d_done, d_host_flag);                                           \
     } while (0)
 #define CGP_TILE_W(T, F)                     \
     if (width == SPLIT_WIDTH) CGP_TILE(T, SPLIT_WIDTH, F); \
