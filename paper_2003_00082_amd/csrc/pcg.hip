@@ -154,9 +154,59 @@ __device__ inline void reduce_partials(const double *part, int nblk, double (*re
 
 // ------------------------------------------------------------------ state transitions
 
-// Decide the next stage from the stage just executed and its reductions S.
+// After a true residual ||r||^2 = rr of the iterate (on the first, also ||b||^2 = bb): the end,
+// a stop, or the restart of the recurrences.  Executed by one thread.
+__device__ inline Ctl after_residual(Ctl c, double rr, double bb, const SolveParams &prm, int guess) {
+    const bool mixed = prm.precision == CGP_FP32_IR;
+    const double tol = prm.tol;
+    if (c.first) {
+        c.bnorm = sqrt(bb);
+        if (bb == 0.0) {
+            c.state = ST_ZEROX;
+            return c;
+        }
+        if (!isfinite(bb)) {
+            c.status = CGP_SOLVE_BREAKDOWN;
+            c.state = ST_DONE;
+            return c;
+        }
+    }
+    if (!isfinite(rr)) {
+        c.status = CGP_SOLVE_BREAKDOWN;
+        c.state = ST_DONE;
+        return c;
+    }
+    const double rn = sqrt(rr);
+    c.rel_res = rn / c.bnorm;
+    if (c.first && guess != CGP_GUESS_LEARNED) c.rel_res_guess = c.rel_res;
+    if (!c.first) ++c.refinements;
+    // mixed: the residual was of x + c, and c is folded into x before the end
+    const int32_t end = (mixed && !c.first) ? ST_FOLD : ST_DONE;
+    if (rn <= tol * c.bnorm) {
+        c.status = CGP_SOLVE_OK;
+        c.state = end;
+        return c;
+    }
+    if (c.it >= prm.max_iter) {
+        c.status = CGP_SOLVE_NOCONV;
+        c.state = end;
+        return c;
+    }
+    // fp64: a failed verification restarts CG; mixed: a replaced residual keeps p and s
+    c.restart = (c.first || !mixed) ? 1 : 0;
+    c.first = 0;
+    // the phase's refinement point delta rn, unless the phase after it would be short (the
+    // tolerance within a factor delta^(1/4) of that point: half a decade at delta = 0.01):
+    // then this phase runs to the tolerance (rmax = 0 leaves only the stopping test)
+    c.rmax = (mixed && prm.delta * sqrt(sqrt(prm.delta)) * rn <= tol * c.bnorm) ? 0.0 : rn;
+    c.state = ST_START;
+    return c;
+}
+
+// Decide the next stage from the stage just executed and its reductions S.  judge_res: the
+// kernel's judge stage also leaves the guess's residual as the first residual stage does.
 // Executed by one thread; every workgroup of the instance computes the same result.
-__device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm, int guess) {
+__device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm, int guess, bool judge_res = true) {
     const bool mixed = prm.precision == CGP_FP32_IR;
     const double tol = prm.tol;
     switch (c.state) {
@@ -176,7 +226,10 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
         if (gain >= 0.0 && isfinite(rl) && isfinite(gain)) {   // a non-finite network output is rejected
             c.guess_used = CGP_GUESS_LEARNED;
             c.rel_res_guess = sqrt(rl) / bn;
-            c.state = ST_RES;
+            if (judge_res)
+                c = after_residual(c, rl, S[2], prm, guess);
+            else
+                c.state = ST_RES;
         } else {   // the first residual stage starts from prev1 instead
             c.guess_used = CGP_GUESS_GIVEN;
             c.rel_res_guess = sqrt(rp) / bn;
@@ -184,51 +237,9 @@ __device__ inline Ctl transition(Ctl c, const double *S, const SolveParams &prm,
         }
         break;
     }
-    case ST_RES: {
-        const double rr = S[0];
-        if (c.first) {
-            c.bnorm = sqrt(S[1]);
-            if (S[1] == 0.0) {
-                c.state = ST_ZEROX;
-                break;
-            }
-            if (!isfinite(S[1])) {
-                c.status = CGP_SOLVE_BREAKDOWN;
-                c.state = ST_DONE;
-                break;
-            }
-        }
-        if (!isfinite(rr)) {
-            c.status = CGP_SOLVE_BREAKDOWN;
-            c.state = ST_DONE;
-            break;
-        }
-        const double rn = sqrt(rr);
-        c.rel_res = rn / c.bnorm;
-        if (c.first && guess != CGP_GUESS_LEARNED) c.rel_res_guess = c.rel_res;
-        if (!c.first) ++c.refinements;
-        // mixed: the residual was of x + c, and c is folded into x before the end
-        const int32_t end = (mixed && !c.first) ? ST_FOLD : ST_DONE;
-        if (rn <= tol * c.bnorm) {
-            c.status = CGP_SOLVE_OK;
-            c.state = end;
-            break;
-        }
-        if (c.it >= prm.max_iter) {
-            c.status = CGP_SOLVE_NOCONV;
-            c.state = end;
-            break;
-        }
-        // fp64: a failed verification restarts CG; mixed: a replaced residual keeps p and s
-        c.restart = (c.first || !mixed) ? 1 : 0;
-        c.first = 0;
-        // the phase's refinement point delta rn, unless the phase after it would be short (the
-        // tolerance within a factor delta^(1/4) of that point: half a decade at delta = 0.01):
-        // then this phase runs to the tolerance (rmax = 0 leaves only the stopping test)
-        c.rmax = (mixed && prm.delta * sqrt(sqrt(prm.delta)) * rn <= tol * c.bnorm) ? 0.0 : rn;
-        c.state = ST_START;
+    case ST_RES:
+        c = after_residual(c, S[0], S[1], prm, guess);
         break;
-    }
     case ST_START: {
         const double g = S[0], dl = S[1], sg = S[2];
         double denom;
@@ -452,9 +463,17 @@ __device__ inline void stage_work(const Ctl &c, const InstDesc &D, const RowRang
         // J(x) = x.Kx / 2 - b.x = -x.(b + r) / 2 differs from the energy-norm error
         // |x - x*|_K^2 / 2 by a constant, so v[3] = J(prev1) - J(guess) (times 2) > 0
         // says the network's guess is the closer one in the norm CG minimises
+        // the guess's residual is also left as the first residual stage would leave it (r, and
+        // c = 0 when mixed): an accepted guess goes on to the restart directly
         staged_product<ELL, double>(R, staged64, lanes, A64, lds64, [&](int32_t j) { return x[j]; },
                                nop, [&](int32_t i, double y, double) {
                                    const double r = b[i] - y;
+                                   if (mixed) {
+                                       D.r32[wr * n + i] = static_cast<float>(r);
+                                       D.c32[i] = 0.0f;
+                                   } else {
+                                       D.r[wr * n + i] = r;
+                                   }
                                    v[0] += r * r;
                                    v[2] += b[i] * b[i];
                                    v[3] += x[i] * (b[i] + r);
@@ -739,7 +758,8 @@ __device__ inline void stage_sums(const InstDesc &D, int rd, double (*red)[NPART
 
 // The common transition, an iteration followed by another one, kept short and
 // inline; every other case goes through transition().  Same arithmetic.
-__device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolveParams &prm, int guess) {
+__device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolveParams &prm, int guess,
+                                 bool judge_res = true) {
     if (prev.state == ST_ITER) {
         const double g = S[0], dl = S[1], sg = S[2], rr = S[3];
         // the stopping tests of transition() on squares: rn <= t  <=>  rr <= t^2 (t >= 0)
@@ -761,7 +781,7 @@ __device__ inline Ctl next_state(const Ctl &prev, const double *S, const SolvePa
             }
         }
     }
-    return transition(prev, S, prm, guess);
+    return transition(prev, S, prm, guess, judge_res);
 }
 
 // What workgroup 0 of an instance does after a transition (one thread): carry the state
@@ -787,7 +807,7 @@ __device__ inline void stage_bookkeeping(const InstDesc &D, int par, const Ctl &
 // Decode the stage: the workgroup sums the previous stage's partials, thread 0 applies
 // the transition into sh.ctl (workgroup 0 of the instance also carries the state forward
 // and reports completion); the other threads wait at the barrier.
-__device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, const SolveParams *prm_dev,
+__device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, bool judge_res, const SolveParams *prm_dev,
                                     Shared &sh, int32_t *done_count, int32_t *host_flag) {
     Ctl prev{};
     if (threadIdx.x == 0) prev = D.ctl[rd];   // in flight while the sums are loaded
@@ -796,7 +816,7 @@ __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, 
         const SolveParams prm = *prm_dev;
         Ctl c = prev;
         if (prev.state != ST_DONE) {
-            c = next_state(prev, sh.sums, prm, D.guess);
+            c = next_state(prev, sh.sums, prm, D.guess, judge_res);
             c.stages = prev.stages + 1;
         }
         sh.ctl = c;
@@ -811,7 +831,7 @@ __device__ inline void decode_stage(const InstDesc &D, int lb, int rd, int par, 
 // order) instead of the whole workgroup reducing every tile's partials, and thread 0 applies
 // the transition.  The control state and the parameters come through scalar loads (the
 // stage writes ctl[par], never ctl[rd], and no parameter).
-__device__ inline Ctl reduced_decode(const InstDesc &D, int lb, int rd, int par, const SolveParams *prm_dev,
+__device__ inline Ctl reduced_decode(const InstDesc &D, int lb, int rd, int par, bool judge_res, const SolveParams *prm_dev,
                                      Shared &sh, int32_t *done_count, int32_t *host_flag) {
     const Ctl prev = cld_record(D.ctl + rd);
     const SolveParams prm = cld_record(prm_dev);
@@ -827,7 +847,7 @@ __device__ inline Ctl reduced_decode(const InstDesc &D, int lb, int rd, int par,
         if (threadIdx.x == 0) {
             Ctl c = prev;
             if (prev.state != ST_DONE) {
-                c = next_state(prev, S, prm, D.guess);
+                c = next_state(prev, S, prm, D.guess, judge_res);
                 c.stages = prev.stages + 1;
             }
             sh.ctl = c;
@@ -859,7 +879,7 @@ __global__ __launch_bounds__(BLOCK) void k_cg_step(const InstDesc *__restrict__ 
     // speculative loads for an iteration, in flight while the state is decoded
     IterPrefetch<T, H> f;
     if (fast) iter_prefetch<T, H>(f, D, R, rd);
-    decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
+    decode_stage(D, lb, rd, par, true, prm_dev, sh, done_count, host_flag);
     const Ctl c = sh.ctl;
     if (c.state == ST_DONE) return;
     double v[NRED] = {};
@@ -1264,6 +1284,38 @@ __device__ inline void tile_res_row(const Ctl &c, const InstDesc &D, int32_t own
     av = ri;   // the row's term of its aggregate's sum Z^T r
 }
 
+// The judge of a learned guess over the tile's own rows: the fp64 residuals of the guess (in x)
+// and of prev1, b.b and the energy-norm comparison x.(b + r_x) - prev1.(b + r_prev1), and for the
+// guess what the first residual stage leaves (r with the same arithmetic, c = 0 when mixed, the
+// row's term of its aggregate's sum Z^T r), so that an accepted guess goes on to the restart.
+__device__ inline void tile_judge_row(const InstDesc &D, int32_t own, bool mixed, int par, double (&v)[NRED],
+                                      double &av) {
+    const int64_t n = D.n;
+    const CGP_GLOBAL int32_t *rowptr = gld(D.rowptr), *col = gld(D.col);
+    const CGP_GLOBAL double *val = gld(D.val), *x = gld(D.x), *p1 = gld(D.prev1);
+    const int32_t k0 = rowptr[own], k1 = rowptr[own + 1];
+    const double bi = gld(D.b)[own];
+    // the guess first (its residual is kept), then prev1: one product in flight at a time
+    double kx = 0.0;
+    for (int32_t k = k0; k < k1; ++k) kx += val[k] * x[col[k]];
+    const double rg = bi - kx;
+    if (mixed) {
+        gst(D.rwsd32)[(par * n + own) * 4] = static_cast<float>(rg);
+        gst(D.c32)[own] = 0.0f;
+    } else {
+        gst(D.rwsd64)[(par * n + own) * 4] = rg;
+    }
+    v[0] += rg * rg;
+    v[2] += bi * bi;
+    v[3] += x[own] * (bi + rg);
+    av = rg;
+    double kp = 0.0;
+    for (int32_t k = k0; k < k1; ++k) kp += val[k] * p1[col[k]];
+    const double rp = bi - kp;
+    v[1] += rp * rp;
+    v[3] -= p1[own] * (bi + rp);
+}
+
 template <class T, int W>
 __device__ inline void tile_res(const Ctl &c, const InstDesc &D, const TileBlk &B, const TilePrefetch<T, W> &f,
                                 bool mixed, int par, double (&v)[NRED], double (&av)[TILE_OWN]) {
@@ -1301,6 +1353,10 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     }
     // speculative loads for an iteration, in flight while the state is decoded
     constexpr bool defl = DEFL;
+    // the split-record kernel judges a learned guess over the tile's own rows and leaves its
+    // residual (the first residual stage's work) on the way; the wider ones, whose registers
+    // are fuller, judge over row ranges and run the residual stage after it
+    constexpr bool JUDGE_RES = W == SPLIT_WIDTH;
     DeflPrefetch<T> df;
     df.kr = -1;
 #pragma unroll
@@ -1329,9 +1385,9 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     }
     Ctl c;
     if constexpr (DEFL) {
-        c = reduced_decode(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
+        c = reduced_decode(D, lb, rd, par, JUDGE_RES, prm_dev, sh, done_count, host_flag);
     } else {
-        decode_stage(D, lb, rd, par, prm_dev, sh, done_count, host_flag);
+        decode_stage(D, lb, rd, par, JUDGE_RES, prm_dev, sh, done_count, host_flag);
         c = sh.ctl;
     }
     if (c.state == ST_DONE) return;
@@ -1357,6 +1413,10 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     } else if (c.state == ST_RES) {
         // the residual over the tile's own rows (its vectors are the tiled iteration's own)
         tile_res<T, W>(c, D, B, f, sizeof(T) == 4, par, v, av);
+    } else if (JUDGE_RES && c.state == ST_JUDGE) {
+#pragma unroll
+        for (int h = 0; h < TILE_OWN; ++h)
+            if (static_cast<int>(threadIdx.x) + h * BLOCK < B.nt[0]) tile_judge_row(D, f.g[h], sizeof(T) == 4, par, v, av[h]);
     } else {
         const SolveParams prm = *prm_dev;
         const RowRange R = ranges[D.blk0 + lb];
