@@ -52,16 +52,16 @@ TOL = 1e-8
 # HBM bytes per k_cg_step launch from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, each
 # scaled by what the counter reads for a plain 1 GiB copy), valid for the kernel source whose
 # fingerprint is recorded with them; reported as null for any other source.
-MEASURED_TRAFFIC = {"fingerprint": "6dfec6e917aa9123", "profile": "profiles/cg_traffic_513x257.md",
+MEASURED_TRAFFIC = {"fingerprint": "97bfd4b3d1dc9ca7", "profile": "profiles/cg_traffic_513x257.md",
                     "k_cg_tile<float, 6, true, true> degree 6 deflated": 19.81e6,
-                    "k_cg_tile<double, 6, true, true> degree 6 deflated": 34.13e6}
+                    "k_cg_tile<double, 6, true, true> degree 6 deflated": 34.16e6}
 
 
 # The same for the batched tiled stage of the two-level workload (8 instances of the 1025x513 coarse
 # mesh, Chebyshev degree 6, deflated, fp32 with fp64 refinement), mean over the launches of a short
 # form-B run (iterations, restarts, residual stages, launches past the end).
-MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "6dfec6e917aa9123", "profile": "profiles/cg_traffic_twolevel_batch8.md",
-                       "k_cg_tile<float, 6, true, false>": 621.14e6, "k_cg_coarse<float>": 66.74e6}
+MEASURED_TRAFFIC_TWOLEVEL = {"fingerprint": "97bfd4b3d1dc9ca7", "profile": "profiles/cg_traffic_twolevel_batch8.md",
+                       "k_cg_tile<float, 6, true, false>": 621.04e6, "k_cg_coarse<float>": 66.74e6}
 
 
 # HBM bytes per launch of the momentum step's two BiCGStab kernels on the 1025x513 fine mesh

@@ -1353,10 +1353,10 @@ __global__ __launch_bounds__(BLOCK, sizeof(T) == 4 ? 4 : 1) void k_cg_tile(const
     }
     // speculative loads for an iteration, in flight while the state is decoded
     constexpr bool defl = DEFL;
-    // the split-record kernel judges a learned guess over the tile's own rows and leaves its
-    // residual (the first residual stage's work) on the way; the wider ones, whose registers
-    // are fuller, judge over row ranges and run the residual stage after it
-    constexpr bool JUDGE_RES = W == SPLIT_WIDTH;
+    // the fp32 split-record kernel judges a learned guess over the tile's own rows and leaves its
+    // residual (the first residual stage's work) on the way; the others, whose registers are
+    // fuller, judge over row ranges and run the residual stage after it
+    constexpr bool JUDGE_RES = W == SPLIT_WIDTH && sizeof(T) == 4;
     DeflPrefetch<T> df;
     df.kr = -1;
 #pragma unroll
